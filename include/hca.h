@@ -1,0 +1,175 @@
+/*
+ * hca.h -- exact hypercube-grid DBSCAN on AMD MI355X (gfx950).
+ *
+ * C ABI of libhca.so.  The operation is the clustering problem of the paper's
+ * appendix ("The DBSCAN Algorithm", Definitions 1-5: inputs are the data set
+ * D, eps and MINPTS), computed with the hypercube method of the methodology
+ * section and Algorithms 1-4 (cubes of space diagonal at most eps, the cube
+ * dictionary, representative points, merging of neighbouring cubes).  The
+ * library returns the exact DBSCAN result, not the approximation that merging
+ * on representative points alone can give:
+ *
+ *   eps2    = floor(eps^2), computed exactly from the binary value of eps;
+ *             dist2(p, q) = sum_k (p_k - q_k)^2 over int32 coordinates, exact.
+ *   N(p)    = { q : dist2(p, q) <= eps2 }, p included (closed ball).
+ *   core    = |N(p)| >= min_pts.
+ *   cluster = connected component of the core points under dist2 <= eps2.
+ *   border  = a non-core point with a core point within eps; it joins the
+ *             cluster of its nearest core point, ties to the smaller point
+ *             index (the paper leaves this choice open).
+ *   noise   = every other point, label -1.
+ *   labels  = clusters numbered 0, 1, 2, ... in order of their smallest
+ *             member index (core and assigned border points).
+ * Exactly one labelling satisfies these rules, so results are reproducible
+ * bit for bit across runs, launch orders and devices.
+ *
+ * Coordinates are fixed point: the caller scales real data by 2^q and rounds
+ * to int32, and passes eps in the same units.
+ *
+ * Threading: a context is used by one host thread at a time.  Calls are
+ * blocking (the context's stream is synchronised before return).
+ */
+#ifndef HCA_H
+#define HCA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hca_ctx hca_ctx;
+
+typedef enum {
+    HCA_OK = 0,
+    HCA_E_INVAL = 1,   /* bad argument: NULL pointer, n < 0, n > 2^31-1, d not in [1,8],
+                          eps not finite or <= 0, min_pts < 1 */
+    HCA_E_RANGE = 2,   /* a per-dimension coordinate span (max - min) >= 2^30, or the
+                          packed cube key needs more than 63 bits */
+    HCA_E_NOMEM = 3,   /* device or pinned host allocation failed */
+    HCA_E_DEVICE = 4   /* HIP runtime error (no device, launch or sync failure) */
+} hca_status;
+
+/* Grid geometry for (eps, d), computed on the host (no device needed).
+ * side:   cube side s = max(1, floor(sqrt(floor(eps2 / d)))), so d*s^2 <= eps2
+ *         ("Overlaying Hypercubes": space diagonal at most eps; Algorithm 1
+ *         band width eps/sqrt(d)).
+ * radius: largest offset R along one axis at which two cubes can still hold
+ *         points within eps: ((R-1)*s + 1)^2 <= eps2.
+ * stencil: number of cube offsets D != 0 with sum over D_k != 0 of
+ *         ((|D_k|-1)*s + 1)^2 <= eps2 (the neighbour hypercubes of the Depth
+ *         First Search and Layering paragraphs; 20 in 2-D), or -1 if more than
+ *         2^24.
+ * group:  cubes per side of a neighbour-search group (1 = search cube by cube
+ *         over the stencil; >1 = groups of side >= sqrt(eps2), searched over
+ *         the 3^d surrounding groups).
+ * group_stencil: number of group offsets searched, self included.
+ * reps:   representative points per cube, 3^d - 1 ("Choosing Representative
+ *         Points"), or 0 when they are not used (group > 1 or d > 4). */
+typedef struct {
+    int64_t eps2;
+    int64_t side;
+    int32_t radius;
+    int32_t group;
+    int64_t stencil;
+    int64_t group_stencil;
+    int32_t reps;
+    int32_t reserved;
+} hca_geometry;
+
+/* Counters of one call, filled by hca_cluster_ex when asked for. */
+typedef struct {
+    int64_t n_cells;          /* non-empty cubes */
+    int64_t n_groups;         /* non-empty search groups */
+    int64_t n_core_points;
+    int64_t n_clusters;
+    int64_t n_noise;
+    int64_t exact_pairs;      /* cube pairs whose representatives were not within eps */
+    int32_t key_bits;         /* bits of the packed cube key */
+    int32_t sort_passes;      /* radix passes of the cube-key sort */
+    int32_t group;            /* cubes per group side used */
+    int32_t wide;             /* 1 if squared distances were computed in 64 bits */
+    int32_t dense_table;      /* 1 if the group lookup was a direct-indexed table */
+    int32_t reserved;
+} hca_stats;
+
+/* Exact floor(eps^2) of a double (no device needed).  HCA_E_INVAL if eps is
+ * not finite or <= 0.  Values above 2^63-1 saturate. */
+hca_status hca_exact_eps2(double eps, int64_t *eps2);
+
+/* Geometry of the cube grid for eps and d (no device needed). */
+hca_status hca_get_geometry(double eps, int32_t d, hca_geometry *out);
+
+/* Create a context on HIP device `device`.  *out receives the context (owned
+ * by the caller, released by hca_destroy).  HCA_E_DEVICE if the device cannot
+ * be used; HCA_E_NOMEM if pinned staging memory cannot be allocated. */
+hca_status hca_create(hca_ctx **out, int32_t device);
+
+/* Release a context and its device workspace.  NULL is ignored. */
+void hca_destroy(hca_ctx *ctx);
+
+/* Text describing the last non-OK status of this context ("" if none). */
+const char *hca_last_error(const hca_ctx *ctx);
+
+/* Set the HIP stream (hipStream_t) that later calls run on; NULL selects the
+ * default stream.  The caller keeps ownership of the stream. */
+hca_status hca_set_stream(hca_ctx *ctx, void *stream);
+
+/* Cluster n points of dimension d.
+ * points: DEVICE pointer to n*d int32, row-major [n][d], fixed-point units;
+ *         read only, owned by the caller.  Aligned to 8 bytes for d = 2 and
+ *         to 16 bytes for d = 4 or 8 (HCA_E_INVAL otherwise); the start of
+ *         any device allocation qualifies.
+ * eps:    radius in the same units (e.g. 0.02 * 2^12).
+ * min_pts: >= 1; |N(p)| counts p itself (Definition 2).
+ * labels: DEVICE pointer to n int32, owned by the caller: -1 for noise, else
+ *         the canonical cluster number.  Left untouched on argument and
+ *         range errors.
+ * n == 0 returns HCA_OK without touching the device.  The context's device
+ * workspace grows as needed and is reused across calls. */
+hca_status hca_cluster(hca_ctx *ctx, const int32_t *points, int64_t n, int32_t d,
+                       double eps, int32_t min_pts, int32_t *labels);
+
+/* As hca_cluster, and optionally: core (DEVICE pointer, n uint8 in input
+ * order: 1 for core points) and stats (HOST pointer).  Either may be NULL. */
+hca_status hca_cluster_ex(hca_ctx *ctx, const int32_t *points, int64_t n, int32_t d,
+                          double eps, int32_t min_pts, int32_t *labels, uint8_t *core,
+                          hca_stats *stats);
+
+/* As hca_cluster with HOST pointers for points and labels: copies in, runs,
+ * copies out (staging through the context's device workspace). */
+hca_status hca_cluster_host(hca_ctx *ctx, const int32_t *points, int64_t n, int32_t d,
+                            double eps, int32_t min_pts, int32_t *labels);
+
+/* Phases of one call, in launch order, for hca_set_profiling / hca_phase_times:
+ * origin shift (bounding box), cube keys and their radix sort with the gather
+ * of points into cube order (methodology, pre-processing sort), cube and group
+ * tables with the lookup table (Algorithm 1's dictionary), core points
+ * (Definition 2), representative points (Algorithm 2), merging of neighbouring
+ * cubes with union-find (Algorithm 3), border points, canonical labels. */
+enum {
+    HCA_PHASE_BBOX = 0,
+    HCA_PHASE_SORT = 1,
+    HCA_PHASE_CELLS = 2,
+    HCA_PHASE_CORE = 3,
+    HCA_PHASE_REPS = 4,
+    HCA_PHASE_MERGE = 5,
+    HCA_PHASE_BORDER = 6,
+    HCA_PHASE_LABELS = 7,
+    HCA_PHASES = 8
+};
+
+/* Time phases of later calls with HIP events on the context's stream:
+ * phase = -1 off (default), -2 every phase, k in [0, HCA_PHASES) phase k only.
+ * HCA_E_INVAL for other values or a NULL context. */
+hca_status hca_set_profiling(hca_ctx *ctx, int32_t phase);
+
+/* Milliseconds spent in each phase by the last call (0 for phases not timed):
+ * ms[0 .. count-1], HOST pointer owned by the caller. */
+hca_status hca_phase_times(const hca_ctx *ctx, float *ms, int32_t count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HCA_H */

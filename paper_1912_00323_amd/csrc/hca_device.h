@@ -1,0 +1,339 @@
+// Device helpers for the gfx950 kernels: wave64 primitives, block scans, the
+// group lookup, lock-free union-find and exact squared distances.
+#pragma once
+
+#include "hca_plan.h"
+
+namespace hca {
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+__device__ __forceinline__ uint32_t wave_in_block() { return threadIdx.x / kWave; }
+
+// ---- relaxed / agent-scope memory helpers --------------------------------
+// Locations that atomics update are initialised with agent-scope stores and
+// read back with agent-scope loads, never with plain accesses: each XCD has
+// its own L2, and a plain access can be served by (or write back) a stale
+// copy of a line that an atomic changed at the device coherence point.
+__device__ __forceinline__ uint32_t ld_agent32(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent32(uint32_t *p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_agent(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t cas_agent(uint32_t *p, uint32_t expect, uint32_t desired)
+{
+    __hip_atomic_compare_exchange_strong(p, &expect, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    return expect;   // the value found: equal to the expected one on success
+}
+
+// ---- wave64 reductions and scans ------------------------------------------
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_min(T v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        T w = __shfl_xor(v, o);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        T w = __shfl_xor(v, o);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T v)
+{
+    const uint32_t l = lane_id();
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        T w = __shfl_up(v, o);
+        if (l >= (uint32_t)o) v += w;
+    }
+    return v;
+}
+
+// Exclusive scan over the 256 threads of a block.  `smem` holds 4 values.
+// Returns the exclusive prefix; *total receives the block sum.
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T *smem, T *total)
+{
+    T inc = wave_inclusive_scan(v);
+    const uint32_t w = wave_in_block();
+    if (lane_id() == kWave - 1) smem[w] = inc;
+    __syncthreads();
+    T base = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < kBlock / kWave; i++) {
+        T s = smem[i];
+        if ((uint32_t)i < w) base += s;
+        all += s;
+    }
+    __syncthreads();
+    *total = all;
+    return base + inc - v;
+}
+
+// ---- XCD-aware assignment of work units to waves -------------------------
+// Workgroups are dispatched round-robin over the 8 XCDs.  Each XCD gets one
+// contiguous eighth of the units (neighbouring cubes, so its L2 holds their
+// data) and its waves stride over that range.
+struct WaveRange {
+    uint32_t first, step, end;
+};
+
+__device__ __forceinline__ WaveRange wave_range(uint32_t units)
+{
+    const uint32_t nb = gridDim.x, b = blockIdx.x;
+    const uint32_t xcd = b & 7u, bx = b >> 3;
+    const uint32_t nbx = (nb - xcd + 7u) >> 3;
+    const uint64_t lo = (uint64_t)units * xcd / 8u, hi = (uint64_t)units * (xcd + 1u) / 8u;
+    WaveRange r;
+    r.first = (uint32_t)lo + bx * (kBlock / kWave) + wave_in_block();
+    r.step = nbx * (kBlock / kWave);
+    r.end = (uint32_t)hi;
+    return r;
+}
+
+// ---- points ----------------------------------------------------------------
+template <int D>
+struct Pt {
+    int32_t x[D];
+};
+
+template <int D>
+__device__ __forceinline__ Pt<D> load_pt(const int32_t *base, uint64_t i)
+{
+    Pt<D> p;
+    const int32_t *s = base + i * D;
+    if constexpr (D == 2) {
+        int2 v = *reinterpret_cast<const int2 *>(s);
+        p.x[0] = v.x; p.x[1] = v.y;
+    } else if constexpr (D == 4) {
+        int4 v = *reinterpret_cast<const int4 *>(s);
+        p.x[0] = v.x; p.x[1] = v.y; p.x[2] = v.z; p.x[3] = v.w;
+    } else if constexpr (D == 8) {
+        int4 v = reinterpret_cast<const int4 *>(s)[0];
+        int4 u = reinterpret_cast<const int4 *>(s)[1];
+        p.x[0] = v.x; p.x[1] = v.y; p.x[2] = v.z; p.x[3] = v.w;
+        p.x[4] = u.x; p.x[5] = u.y; p.x[6] = u.z; p.x[7] = u.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < D; k++) p.x[k] = s[k];
+    }
+    return p;
+}
+
+template <int D>
+__device__ __forceinline__ void store_pt(int32_t *base, uint64_t i, const Pt<D> &p)
+{
+    int32_t *s = base + i * D;
+    if constexpr (D == 2) {
+        *reinterpret_cast<int2 *>(s) = make_int2(p.x[0], p.x[1]);
+    } else if constexpr (D == 4) {
+        *reinterpret_cast<int4 *>(s) = make_int4(p.x[0], p.x[1], p.x[2], p.x[3]);
+    } else if constexpr (D == 8) {
+        reinterpret_cast<int4 *>(s)[0] = make_int4(p.x[0], p.x[1], p.x[2], p.x[3]);
+        reinterpret_cast<int4 *>(s)[1] = make_int4(p.x[4], p.x[5], p.x[6], p.x[7]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < D; k++) s[k] = p.x[k];
+    }
+}
+
+// Exact "dist2(a, b) <= eps2".  Narrow form: the host has proved
+// d * (largest coordinate difference of any tested pair)^2 < 2^31, so every
+// term fits a 24-bit multiply and the sum fits int32.
+template <int D, bool WIDE>
+__device__ __forceinline__ bool within(const Pt<D> &a, const Pt<D> &b, int64_t eps2)
+{
+    if constexpr (WIDE) {
+        int64_t s = 0;
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+            int64_t t = (int64_t)a.x[k] - (int64_t)b.x[k];
+            s += t * t;
+        }
+        return s <= eps2;
+    } else {
+        int32_t s = 0;
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+            int32_t t = a.x[k] - b.x[k];
+            s += __mul24(t, t);
+        }
+        return s <= (int32_t)eps2;
+    }
+}
+
+template <int D, bool WIDE>
+__device__ __forceinline__ int64_t dist2(const Pt<D> &a, const Pt<D> &b)
+{
+    if constexpr (WIDE) {
+        int64_t s = 0;
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+            int64_t t = (int64_t)a.x[k] - (int64_t)b.x[k];
+            s += t * t;
+        }
+        return s;
+    } else {
+        int32_t s = 0;
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+            int32_t t = a.x[k] - b.x[k];
+            s += __mul24(t, t);
+        }
+        return s;
+    }
+}
+
+// ---- group lookup ----------------------------------------------------------
+__device__ __forceinline__ uint64_t mix64(uint64_t x)
+{
+    x ^= x >> 33;
+    x *= 0xff51afd7ed558ccdull;
+    x ^= x >> 33;
+    x *= 0xc4ceb9fe1a85ec53ull;
+    x ^= x >> 33;
+    return x;
+}
+
+__device__ __forceinline__ uint32_t group_lookup(const Plan &P, uint64_t gkey)
+{
+    if (P.dense) return P.table[gkey];
+    uint64_t h = mix64(gkey) & P.hash_mask;
+    while (true) {
+        const uint64_t k = ld_agent(P.hkeys + h);
+        if (k == gkey) return P.table[h];
+        if (k == ~0ull) return kNone;
+        h = (h + 1) & P.hash_mask;
+    }
+}
+
+// Group key of the group at offset `o` from group key g, or ~0 if the target
+// lies outside the occupied range of some axis.  Group coordinate k occupies
+// bits [goff[k], goff[k] + gw[k]) of the group key.
+template <int D>
+__device__ __forceinline__ uint64_t group_neighbour(const Plan &P, uint64_t g, const int8_t *o)
+{
+    uint64_t key = g;
+#pragma unroll
+    for (int k = 0; k < D; k++) {
+        const int32_t ok = o[k];
+        if (ok == 0) continue;
+        const int32_t c = (int32_t)((g >> P.goff[k]) & ((1ull << P.gw[k]) - 1ull));
+        const int32_t nc = c + ok;
+        if (nc < 0 || nc > (int32_t)P.gmax[k]) return ~0ull;
+        key += (uint64_t)(int64_t)ok << P.goff[k];
+    }
+    return key;
+}
+
+// ---- lock-free union-find over cubes ----------------------------------------
+// Parent pointers only ever point to a smaller index; hooking is a
+// compare-and-swap on a root (larger root under smaller root), and a failed
+// swap returns the newer parent to follow.  Every access to the parent array
+// while other workgroups may change it is an agent-scope atomic: the XCDs'
+// L2 caches are not coherent with each other for plain loads and stores, so
+// a plain access could read or write back a stale parent.
+__device__ __forceinline__ uint32_t ld_parent(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_parent(uint32_t *p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t uf_find(uint32_t *parent, uint32_t x)
+{
+    uint32_t p = ld_parent(parent + x);
+    while (p != x) {
+        const uint32_t gp = ld_parent(parent + p);
+        if (gp != p) st_parent(parent + x, gp);   // path splitting; gp is an ancestor of x
+        x = p;
+        p = gp;
+    }
+    return x;
+}
+
+// Root of x without writing anything.  Used once no more unions can happen:
+// a concurrent path-splitting write could otherwise replace a root that
+// another thread has just stored with an older ancestor.
+__device__ __forceinline__ uint32_t uf_root(const uint32_t *parent, uint32_t x)
+{
+    uint32_t p = ld_parent(parent + x);
+    while (p != x) {
+        x = p;
+        p = ld_parent(parent + x);
+    }
+    return x;
+}
+
+__device__ __forceinline__ void uf_union(uint32_t *parent, uint32_t a, uint32_t b)
+{
+    a = uf_find(parent, a);
+    b = uf_find(parent, b);
+    while (a != b) {
+        if (a < b) { uint32_t t = a; a = b; b = t; }     // hook larger root a under b
+        uint32_t seen = cas_agent(parent + a, a, b);
+        if (seen == a) return;
+        a = uf_find(parent, seen);
+        b = uf_find(parent, b);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Look-back for single-value device scans: one thread publishes the tile's
+// aggregate and returns the exclusive prefix of all earlier tiles.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t scan_lookback(uint64_t *status, uint32_t tile, uint64_t agg)
+{
+    if (tile == 0) {
+        st_agent(status, kFlagInc | agg);
+        return 0;
+    }
+    st_agent(status + tile, kFlagAgg | agg);
+    uint64_t excl = 0;
+    int64_t k = (int64_t)tile - 1;
+    while (true) {
+        const uint64_t v = ld_agent(status + k);
+        const uint64_t f = v & ~kValMask;
+        if (f == 0) { __builtin_amdgcn_s_sleep(1); continue; }
+        excl += v & kValMask;
+        if (f == kFlagInc) break;
+        k--;
+    }
+    st_agent(status + tile, kFlagInc | (excl + agg));
+    return excl;
+}
+
+}  // namespace hca

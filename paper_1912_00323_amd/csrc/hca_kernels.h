@@ -1,0 +1,34 @@
+// Host-side launchers of the gfx950 kernels (internal to libhca.so).
+#pragma once
+
+#include "hca_plan.h"
+
+namespace hca {
+
+struct SortBuffers {
+    void *keys_a, *keys_b;
+    uint32_t *vals_a, *vals_b;
+    uint32_t *hist;          // [passes][256], zeroed
+    uint64_t *status;        // [passes][tiles][256], zeroed
+    uint32_t *tickets;       // [passes], zeroed
+    void *result_keys;       // set by launch_sort
+    uint32_t *result_vals;
+};
+
+void launch_bbox(int d, const int32_t *pts, uint32_t n, int32_t *partial, int blocks,
+                 hipStream_t s);
+void launch_sort(const Plan &P, SortBuffers &B, bool wide_keys, hipStream_t s);
+void launch_cells(const Plan &P, bool wide_keys, uint64_t *status, uint32_t *ticket,
+                  hipStream_t s);
+
+void launch_init(uint32_t *zero, uint64_t zero_words, uint64_t *hkeys, uint64_t hcap, uint32_t *table,
+                 uint64_t tsize, hipStream_t s);
+void launch_table(const Plan &P, int blocks, hipStream_t s);
+void launch_core(const Plan &P, int blocks, hipStream_t s);
+void launch_reps(const Plan &P, int blocks, hipStream_t s);
+void launch_merge(const Plan &P, int blocks, hipStream_t s);
+void launch_compress(const Plan &P, int blocks, hipStream_t s);
+void launch_border(const Plan &P, int blocks, hipStream_t s);
+void launch_labels(const Plan &P, uint64_t *status, uint32_t *ticket, hipStream_t s);
+
+}  // namespace hca

@@ -1,0 +1,104 @@
+// Internal launch plan shared by the host driver and the gfx950 kernels.
+// Plain data only: the host fills it once per call and passes it by value.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hca {
+
+constexpr int kMaxDim = 8;
+constexpr int kWave = 64;
+constexpr int kBlock = 256;                    // 4 waves per workgroup
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+// Radix sort of cube keys: 8-bit digits, 2048-key tiles (256 threads x 8 keys).
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kSortItems = 8;
+constexpr int kSortTile = kBlock * kSortItems;
+
+// Device-wide scans: 256 threads x 16 items.
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kBlock * kScanItems;
+
+// Look-back status words: two flag bits over a 62-bit value.
+constexpr uint64_t kFlagAgg = 1ull << 62;
+constexpr uint64_t kFlagInc = 2ull << 62;
+constexpr uint64_t kValMask = (1ull << 62) - 1;
+
+// Counters kept on the device for one call (zeroed before each call).
+struct Counters {
+    uint32_t n_cells;
+    uint32_t n_groups;
+    uint32_t worklist;          // cube pairs waiting for an exact test
+    uint32_t bbox_done;         // blocks of the bounding-box kernel finished
+    uint32_t sort_tickets[8];   // tile tickets, one per radix pass
+    uint32_t scan_tickets[4];   // tile tickets of the device-wide scans
+    uint32_t n_core;
+    uint32_t n_noise;
+    uint32_t n_clusters;
+    uint32_t pad[13];
+};
+
+struct Plan {
+    // problem
+    uint32_t n;
+    int32_t d;
+    int32_t min_pts;
+    int32_t wide;               // 64-bit squared distances
+    int64_t eps2;
+    // grid: cube side s; a group is m x ... x m cubes; the cube key packs the
+    // group coordinates (dimension 0 most significant) above the in-group
+    // offsets (bm bits each)
+    int32_t origin[kMaxDim];
+    uint32_t side;
+    uint32_t m;
+    uint32_t bm;
+    uint32_t fine_bits;         // d * bm
+    uint32_t goff[kMaxDim];     // bit offset of group coordinate k in the group key
+    uint32_t gw[kMaxDim];       // bit width of group coordinate k
+    uint32_t gmax[kMaxDim];     // largest group coordinate per axis
+    uint32_t key_bits;
+    uint32_t passes;
+    // neighbour search over groups: offsets in [-R, R]^d, self first
+    uint32_t n_off;
+    const int8_t *off;          // [n_off][d]
+    // representative points (m == 1 only): directions per cube, and for each
+    // offset the direction index of sign(offset) and of -sign(offset)
+    uint32_t n_dir;
+    const uint16_t *dir_fwd;    // [n_off]
+    const uint16_t *dir_bwd;    // [n_off]
+    // group lookup: direct table over the packed group key, or hash
+    uint32_t dense;
+    uint64_t hash_mask;
+
+    // buffers
+    const int32_t *pts;         // [n][d] input order
+    int32_t *spts;              // [n][d] sorted by cube key
+    const uint32_t *sidx;       // sorted position -> input index
+    const void *skeys;          // sorted keys (uint32 or uint64)
+    uint32_t *cell_of;          // sorted position -> cube id
+    uint32_t *cell_start;       // [n + 1] cube -> first sorted position
+    uint32_t *group_start;      // [n + 1] group -> first sorted position
+    uint32_t *group_cell;       // [n + 1] group -> first cube id
+    uint64_t *group_key;        // [n]
+    uint32_t *table;            // dense: [2^gbits] ; hash: values [cap]
+    uint64_t *hkeys;            // hash: keys [cap]
+    uint8_t *core;              // [n] sorted order
+    uint32_t *ncore;            // [n] cube -> core points
+    uint32_t *rep;              // [cells][n_dir] sorted positions
+    uint32_t *parent;           // [n] union-find over cubes
+    uint32_t *work;             // [2 * work_cap] cube pairs for exact tests
+    uint32_t work_cap;
+    uint32_t *owner;            // [n] sorted position -> root cube (border), kNone
+    uint32_t *minmem;           // [n] root cube -> smallest member input index
+    uint32_t *root_in;          // [n] input index -> root cube or kNone
+    uint32_t *rank;             // [n] input index -> exclusive count of first members
+    uint64_t *scan_status;      // look-back words for the device-wide scans
+    Counters *ctr;
+    uint8_t *core_out;          // optional [n] input order
+    int32_t *labels;            // [n] input order
+};
+
+}  // namespace hca

@@ -1,0 +1,367 @@
+// Binning: bounding box (origin shift), cube keys, stable LSD radix sort of the
+// keys, and the cube / group tables.
+//
+// Methodology section: the data set is sorted on the leading dimension with
+// ties broken by the following ones, and every point falls into the hypercube
+// given by its band along each axis after an origin shift.  Here the band of
+// coordinate x_k is floor((x_k - min_k) / s); the packed key orders cubes with
+// dimension 0 most significant, and the sort is stable, so points of one cube
+// keep their input order.
+#include <algorithm>
+
+#include "hca_device.h"
+#include "hca_kernels.h"
+
+namespace hca {
+
+// ---------------------------------------------------------------------------
+// Bounding box: per-block minima and maxima; the host reduces the partials.
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_bbox(const int32_t *__restrict__ pts, uint32_t n,
+                                                 int32_t *__restrict__ partial)
+{
+    __shared__ int32_t s_mn[kBlock / kWave][D], s_mx[kBlock / kWave][D];
+    int32_t mn[D], mx[D];
+#pragma unroll
+    for (int k = 0; k < D; k++) { mn[k] = INT32_MAX; mx[k] = INT32_MIN; }
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        Pt<D> p = load_pt<D>(pts, i);
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+            mn[k] = min(mn[k], p.x[k]);
+            mx[k] = max(mx[k], p.x[k]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < D; k++) {
+        mn[k] = wave_min(mn[k]);
+        mx[k] = wave_max(mx[k]);
+    }
+    const uint32_t w = wave_in_block();
+    if (lane_id() == 0) {
+#pragma unroll
+        for (int k = 0; k < D; k++) { s_mn[w][k] = mn[k]; s_mx[w][k] = mx[k]; }
+    }
+    __syncthreads();
+    if (threadIdx.x < D) {
+        const int k = threadIdx.x;
+        int32_t a = s_mn[0][k], b = s_mx[0][k];
+        for (int i = 1; i < kBlock / kWave; i++) { a = min(a, s_mn[i][k]); b = max(b, s_mx[i][k]); }
+        partial[blockIdx.x * 2 * D + k] = a;
+        partial[blockIdx.x * 2 * D + D + k] = b;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Cube keys and the digit histograms of every radix pass, in one read.
+// ---------------------------------------------------------------------------
+template <int D, typename K>
+__device__ __forceinline__ K cube_key(const Plan &P, const Pt<D> &p)
+{
+    uint64_t key = 0;
+#pragma unroll
+    for (int k = 0; k < D; k++) {
+        const uint32_t u = (uint32_t)(p.x[k] - P.origin[k]);     // < 2^30 (host checked)
+        const uint32_t c = u / P.side;
+        const uint32_t g = c / P.m;
+        const uint32_t f = c - g * P.m;
+        key |= (uint64_t)g << (P.goff[k] + P.fine_bits);
+        key |= (uint64_t)f << (P.bm * (uint32_t)(D - 1 - k));
+    }
+    return (K)key;
+}
+
+template <int D, typename K>
+__global__ __launch_bounds__(kBlock) void k_keys_hist(Plan P, K *__restrict__ keys,
+                                                      uint32_t *__restrict__ vals,
+                                                      uint32_t *__restrict__ hist)
+{
+    __shared__ uint32_t s_hist[8 * kRadix];
+    const uint32_t passes = P.passes;
+    for (uint32_t e = threadIdx.x; e < passes * kRadix; e += kBlock) s_hist[e] = 0;
+    __syncthreads();
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < P.n; i += gridDim.x * kBlock) {
+        const K key = cube_key<D, K>(P, load_pt<D>(P.pts, i));
+        keys[i] = key;
+        vals[i] = i;
+        for (uint32_t q = 0; q < passes; q++)
+            atomicAdd(&s_hist[q * kRadix + (uint32_t)((key >> (q * kRadixBits)) & (kRadix - 1))], 1u);
+    }
+    __syncthreads();
+    for (uint32_t e = threadIdx.x; e < passes * kRadix; e += kBlock)
+        if (s_hist[e]) atomicAdd(&hist[e], s_hist[e]);
+}
+
+// ---------------------------------------------------------------------------
+// One stable LSD pass with decoupled look-back (one launch per digit).
+//
+// A workgroup takes the next 2048-key tile by ticket.  Each wave owns 512
+// consecutive keys and ranks them in eight rounds of 64: lanes with equal
+// digits find each other with eight ballots, and a per-wave digit counter in
+// LDS gives each key its rank.  The tile's digit counts are published at once
+// and turned into global offsets by looking back over earlier tiles; keys
+// are then staged in LDS in digit order and written out in runs.
+// ---------------------------------------------------------------------------
+template <typename K, int D, bool GATHER>
+__global__ __launch_bounds__(kBlock) void k_onesweep(Plan P, const K *__restrict__ kin,
+                                                     const uint32_t *__restrict__ vin,
+                                                     K *__restrict__ kout, uint32_t *__restrict__ vout,
+                                                     uint32_t shift, const uint32_t *hist,
+                                                     uint64_t *__restrict__ status, uint32_t *ticket)
+{
+    constexpr int W = kBlock / kWave;
+    constexpr int PER_WAVE = kWave * kSortItems;
+    __shared__ K s_keys[kSortTile];
+    __shared__ uint32_t s_vals[kSortTile];
+    __shared__ uint32_t s_wcnt[W][kRadix];      // per-wave digit counts, then offsets
+    __shared__ uint32_t s_tstart[kRadix];       // tile-local start of each digit
+    __shared__ uint32_t s_gbase[kRadix];        // global position of tile-local 0 per digit
+    __shared__ uint32_t s_red[W];
+    __shared__ uint32_t s_tile;
+
+    const uint32_t t = threadIdx.x, w = wave_in_block(), l = lane_id();
+    if (t == 0) s_tile = atomicAdd(ticket, 1u);
+    for (uint32_t e = t; e < W * kRadix; e += kBlock) (&s_wcnt[0][0])[e] = 0;
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint32_t n = P.n;
+    const uint32_t base = tile * kSortTile + w * PER_WAVE;
+    const uint64_t lt_mask = __lanemask_lt();
+
+    K key[kSortItems];
+    uint32_t val[kSortItems], rank[kSortItems], dig[kSortItems];
+#pragma unroll
+    for (int j = 0; j < kSortItems; j++) {
+        const uint32_t idx = base + j * kWave + l;
+        const bool ok = idx < n;
+        key[j] = ok ? kin[idx] : (K)0;
+        val[j] = ok ? vin[idx] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kSortItems; j++) {
+        const uint32_t idx = base + j * kWave + l;
+        const bool ok = idx < n;
+        const uint32_t dg = (uint32_t)(key[j] >> shift) & (kRadix - 1);
+        uint64_t peers = __ballot(ok);
+#pragma unroll
+        for (int b = 0; b < kRadixBits; b++) {
+            const bool bit = (dg >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t before = ok ? s_wcnt[w][dg] : 0u;
+        const uint32_t below = __popcll(peers & lt_mask);
+        __builtin_amdgcn_wave_barrier();
+        if (ok && below == 0) s_wcnt[w][dg] = before + __popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+        rank[j] = before + below;
+        dig[j] = ok ? dg : kRadix;
+    }
+    __syncthreads();
+
+    // thread t owns digit t: tile count, per-wave offsets, look-back
+    uint32_t cnt = 0;
+    {
+        uint32_t c[W];
+#pragma unroll
+        for (int i = 0; i < W; i++) c[i] = s_wcnt[i][t];
+        uint32_t run = 0;
+#pragma unroll
+        for (int i = 0; i < W; i++) { s_wcnt[i][t] = run; run += c[i]; }
+        cnt = run;
+    }
+    uint64_t *my = status + (uint64_t)tile * kRadix + t;
+    st_agent(my, (tile == 0 ? kFlagInc : kFlagAgg) | cnt);
+    uint32_t total;
+    const uint32_t tstart = block_exclusive_scan<uint32_t>(cnt, s_red, &total);
+    const uint32_t gstart = block_exclusive_scan<uint32_t>(ld_agent32(hist + t), s_red, &total);
+    uint64_t excl = 0;
+    if (tile > 0) {
+        int64_t k = (int64_t)tile - 1;
+        while (true) {
+            const uint64_t v = ld_agent(status + (uint64_t)k * kRadix + t);
+            const uint64_t f = v & ~kValMask;
+            if (f == 0) { __builtin_amdgcn_s_sleep(1); continue; }
+            excl += v & kValMask;
+            if (f == kFlagInc) break;
+            k--;
+        }
+        st_agent(my, kFlagInc | (excl + cnt));
+    }
+    s_tstart[t] = tstart;
+    s_gbase[t] = gstart + (uint32_t)excl - tstart;
+    __syncthreads();
+
+#pragma unroll
+    for (int j = 0; j < kSortItems; j++) {
+        if (dig[j] < kRadix) {
+            const uint32_t lp = s_tstart[dig[j]] + s_wcnt[w][dig[j]] + rank[j];
+            s_keys[lp] = key[j];
+            s_vals[lp] = val[j];
+        }
+    }
+    __syncthreads();
+    const uint32_t tile_base = tile * kSortTile;
+    const uint32_t tile_n = min((uint32_t)kSortTile, n - tile_base);
+    for (uint32_t i = t; i < tile_n; i += kBlock) {
+        const K kk = s_keys[i];
+        const uint32_t vv = s_vals[i];
+        const uint32_t pos = s_gbase[(uint32_t)(kk >> shift) & (kRadix - 1)] + i;
+        kout[pos] = kk;
+        vout[pos] = vv;
+        if constexpr (GATHER) store_pt<D>(P.spts, pos, load_pt<D>(P.pts, vv));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Cube and group tables from the sorted keys (Algorithm 1's dictionary, for
+// non-empty cubes only).  One scan counts cube starts (bits 0..30) and group
+// starts (bits 31..61) together.
+// ---------------------------------------------------------------------------
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_cells(Plan P, uint64_t *__restrict__ status,
+                                                  uint32_t *ticket)
+{
+    __shared__ uint64_t s_red[kBlock / kWave];
+    __shared__ uint32_t s_tile;
+    __shared__ uint64_t s_excl;
+    const K *skeys = (const K *)P.skeys;
+    const uint32_t t = threadIdx.x, n = P.n;
+    if (t == 0) s_tile = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint32_t base = tile * kScanTile;
+    const uint32_t fb = P.fine_bits;
+
+    uint64_t v[kScanItems];
+    uint64_t local = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; j++) {
+        const uint32_t idx = base + j * kBlock + t;
+        uint64_t fc = 0, fg = 0;
+        if (idx < n) {
+            if (idx == 0) {
+                fc = fg = 1;
+            } else {
+                const uint64_t a = (uint64_t)skeys[idx], b = (uint64_t)skeys[idx - 1];
+                fc = a != b;
+                fg = (a >> fb) != (b >> fb);
+            }
+        }
+        v[j] = fc | (fg << 31);
+        local += v[j];
+    }
+    uint64_t agg;
+    block_exclusive_scan<uint64_t>(local, s_red, &agg);
+    if (t == 0) s_excl = scan_lookback(status, tile, agg);
+    __syncthreads();
+    uint64_t run = s_excl;
+    const uint64_t lo_mask = (1ull << 31) - 1;
+#pragma unroll
+    for (int j = 0; j < kScanItems; j++) {
+        uint64_t tot;
+        const uint64_t e = block_exclusive_scan<uint64_t>(v[j], s_red, &tot);
+        const uint32_t idx = base + j * kBlock + t;
+        if (idx < n) {
+            const uint64_t inc = run + e + v[j];
+            const uint32_t cell = (uint32_t)(inc & lo_mask) - 1u;
+            P.cell_of[idx] = cell;
+            if (v[j] & 1u) {
+                P.cell_start[cell] = idx;
+                st_parent(P.parent + cell, cell);
+            }
+            if (v[j] >> 31) {
+                const uint32_t g = (uint32_t)(inc >> 31) - 1u;
+                P.group_start[g] = idx;
+                P.group_key[g] = (uint64_t)skeys[idx] >> fb;
+                P.group_cell[g] = cell;
+            }
+            if (idx == n - 1) {
+                const uint32_t nc = (uint32_t)(inc & lo_mask), ng = (uint32_t)(inc >> 31);
+                P.cell_start[nc] = n;
+                P.group_start[ng] = n;
+                P.group_cell[ng] = nc;
+                st_agent32(&P.ctr->n_cells, nc);
+                st_agent32(&P.ctr->n_groups, ng);
+            }
+        }
+        run += tot;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+// ---------------------------------------------------------------------------
+template <int D>
+static void launch_bbox_d(const int32_t *pts, uint32_t n, int32_t *partial, int blocks,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bbox<D>, dim3(blocks), dim3(kBlock), 0, s, pts, n, partial);
+}
+
+void launch_bbox(int d, const int32_t *pts, uint32_t n, int32_t *partial, int blocks,
+                 hipStream_t s)
+{
+    switch (d) {
+    case 1: launch_bbox_d<1>(pts, n, partial, blocks, s); break;
+    case 2: launch_bbox_d<2>(pts, n, partial, blocks, s); break;
+    case 3: launch_bbox_d<3>(pts, n, partial, blocks, s); break;
+    case 4: launch_bbox_d<4>(pts, n, partial, blocks, s); break;
+    case 5: launch_bbox_d<5>(pts, n, partial, blocks, s); break;
+    case 6: launch_bbox_d<6>(pts, n, partial, blocks, s); break;
+    case 7: launch_bbox_d<7>(pts, n, partial, blocks, s); break;
+    case 8: launch_bbox_d<8>(pts, n, partial, blocks, s); break;
+    }
+}
+
+template <int D, typename K>
+static void sort_d(const Plan &P, const SortBuffers &B, hipStream_t s)
+{
+    const int hb = (int)std::min<uint64_t>((P.n + kBlock - 1) / kBlock, 2048);
+    K *ka = (K *)B.keys_a, *kb = (K *)B.keys_b;
+    uint32_t *va = B.vals_a, *vb = B.vals_b;
+    hipLaunchKernelGGL((k_keys_hist<D, K>), dim3(hb), dim3(kBlock), 0, s, P, ka, va, B.hist);
+    const uint32_t tiles = (P.n + kSortTile - 1) / kSortTile;
+    for (uint32_t q = 0; q < P.passes; q++) {
+        uint64_t *st = B.status + (uint64_t)q * tiles * kRadix;
+        const bool last = q + 1 == P.passes;
+        if (last)
+            hipLaunchKernelGGL((k_onesweep<K, D, true>), dim3(tiles), dim3(kBlock), 0, s, P, ka, va,
+                               kb, vb, q * kRadixBits, B.hist + q * kRadix, st, B.tickets + q);
+        else
+            hipLaunchKernelGGL((k_onesweep<K, D, false>), dim3(tiles), dim3(kBlock), 0, s, P, ka,
+                               va, kb, vb, q * kRadixBits, B.hist + q * kRadix, st, B.tickets + q);
+        K *tk = ka; ka = kb; kb = tk;
+        uint32_t *tv = va; va = vb; vb = tv;
+    }
+}
+
+// Returns via B.result_keys / result_vals which buffers hold the sorted data.
+void launch_sort(const Plan &P, SortBuffers &B, bool wide_keys, hipStream_t s)
+{
+#define HCA_SORT_CASE(DD)                                                     \
+    case DD:                                                                  \
+        if (wide_keys) sort_d<DD, uint64_t>(P, B, s);                         \
+        else sort_d<DD, uint32_t>(P, B, s);                                   \
+        break;
+    switch (P.d) {
+        HCA_SORT_CASE(1) HCA_SORT_CASE(2) HCA_SORT_CASE(3) HCA_SORT_CASE(4)
+        HCA_SORT_CASE(5) HCA_SORT_CASE(6) HCA_SORT_CASE(7) HCA_SORT_CASE(8)
+    }
+#undef HCA_SORT_CASE
+    const bool odd = P.passes & 1u;
+    B.result_keys = odd ? B.keys_b : B.keys_a;
+    B.result_vals = odd ? B.vals_b : B.vals_a;
+}
+
+void launch_cells(const Plan &P, bool wide_keys, uint64_t *status, uint32_t *ticket, hipStream_t s)
+{
+    const uint32_t tiles = (P.n + kScanTile - 1) / kScanTile;
+    if (wide_keys)
+        hipLaunchKernelGGL(k_cells<uint64_t>, dim3(tiles), dim3(kBlock), 0, s, P, status, ticket);
+    else
+        hipLaunchKernelGGL(k_cells<uint32_t>, dim3(tiles), dim3(kBlock), 0, s, P, status, ticket);
+}
+
+}  // namespace hca

@@ -1,0 +1,209 @@
+"""Python binding of libhca.so (ctypes).  Argument marshalling only: every step
+of the clustering runs in the library's HIP kernels.  There is no CPU path; if
+the library is missing or no GPU is usable, calls raise.
+
+Names follow the C ABI in ``include/hca.h``.
+"""
+from __future__ import annotations
+
+import ctypes
+from pathlib import Path
+
+import numpy as np
+
+_HERE = Path(__file__).resolve().parent
+LIB_PATH = _HERE / "libhca.so"
+
+HCA_OK, HCA_E_INVAL, HCA_E_RANGE, HCA_E_NOMEM, HCA_E_DEVICE = 0, 1, 2, 3, 4
+PHASES = ["bbox", "sort", "cells", "core", "reps", "merge", "border", "labels"]
+STATUS_NAMES = {0: "HCA_OK", 1: "HCA_E_INVAL", 2: "HCA_E_RANGE", 3: "HCA_E_NOMEM",
+                4: "HCA_E_DEVICE"}
+
+
+class HcaError(RuntimeError):
+    def __init__(self, status: int, message: str = ""):
+        self.status = status
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("eps2", ctypes.c_int64), ("side", ctypes.c_int64), ("radius", ctypes.c_int32),
+                ("group", ctypes.c_int32), ("stencil", ctypes.c_int64),
+                ("group_stencil", ctypes.c_int64), ("reps", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_cells", ctypes.c_int64), ("n_groups", ctypes.c_int64),
+                ("n_core_points", ctypes.c_int64), ("n_clusters", ctypes.c_int64),
+                ("n_noise", ctypes.c_int64), ("exact_pairs", ctypes.c_int64),
+                ("key_bits", ctypes.c_int32), ("sort_passes", ctypes.c_int32),
+                ("group", ctypes.c_int32), ("wide", ctypes.c_int32),
+                ("dense_table", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+_lib = None
+
+
+def load_library(path: str | Path | None = None) -> ctypes.CDLL:
+    """Load libhca.so (built in-tree by ``paper_1912_00323_amd.build``)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = Path(path) if path is not None else LIB_PATH
+    if not p.exists():
+        raise RuntimeError(f"{p} is missing: build it with `python -m paper_1912_00323_amd.build`")
+    lib = ctypes.CDLL(str(p))
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.hca_exact_eps2.argtypes = [dbl, ctypes.POINTER(i64)]
+    lib.hca_exact_eps2.restype = ctypes.c_int
+    lib.hca_get_geometry.argtypes = [dbl, i32, ctypes.POINTER(Geometry)]
+    lib.hca_get_geometry.restype = ctypes.c_int
+    lib.hca_create.argtypes = [ctypes.POINTER(vp), i32]
+    lib.hca_create.restype = ctypes.c_int
+    lib.hca_destroy.argtypes = [vp]
+    lib.hca_destroy.restype = None
+    lib.hca_last_error.argtypes = [vp]
+    lib.hca_last_error.restype = ctypes.c_char_p
+    lib.hca_set_stream.argtypes = [vp, vp]
+    lib.hca_set_stream.restype = ctypes.c_int
+    lib.hca_cluster.argtypes = [vp, vp, i64, i32, dbl, i32, vp]
+    lib.hca_cluster.restype = ctypes.c_int
+    lib.hca_cluster_ex.argtypes = [vp, vp, i64, i32, dbl, i32, vp, vp, ctypes.POINTER(Stats)]
+    lib.hca_cluster_ex.restype = ctypes.c_int
+    lib.hca_cluster_host.argtypes = [vp, vp, i64, i32, dbl, i32, vp]
+    lib.hca_cluster_host.restype = ctypes.c_int
+    lib.hca_set_profiling.argtypes = [vp, i32]
+    lib.hca_set_profiling.restype = ctypes.c_int
+    lib.hca_phase_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32]
+    lib.hca_phase_times.restype = ctypes.c_int
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def exact_eps2(eps: float) -> int:
+    out = ctypes.c_int64()
+    st = load_library().hca_exact_eps2(float(eps), ctypes.byref(out))
+    if st != HCA_OK:
+        raise HcaError(st, "eps must be finite and > 0")
+    return int(out.value)
+
+
+def geometry(eps: float, d: int) -> dict:
+    g = Geometry()
+    st = load_library().hca_get_geometry(float(eps), int(d), ctypes.byref(g))
+    if st != HCA_OK:
+        raise HcaError(st, "bad eps or d")
+    return g.as_dict()
+
+
+class Context:
+    """One hca_ctx on a HIP device (owns the device workspace)."""
+
+    def __init__(self, device: int = 0):
+        self._lib = load_library()
+        self._ctx = ctypes.c_void_p()
+        st = self._lib.hca_create(ctypes.byref(self._ctx), int(device))
+        if st != HCA_OK:
+            raise HcaError(st, f"hca_create(device={device}) failed")
+        self.device = device
+
+    def close(self):
+        if self._ctx:
+            self._lib.hca_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != HCA_OK:
+            msg = self._lib.hca_last_error(self._ctx)
+            raise HcaError(st, msg.decode() if msg else "")
+
+    def set_stream(self, stream_handle: int | None):
+        self._check(self._lib.hca_set_stream(self._ctx, ctypes.c_void_p(stream_handle or 0)))
+
+    def set_profiling(self, phase: int | str | None):
+        """Time later calls with HIP events: None = off, "all", or one phase."""
+        code = -1 if phase is None else -2 if phase == "all" else (
+            PHASES.index(phase) if isinstance(phase, str) else int(phase))
+        self._check(self._lib.hca_set_profiling(self._ctx, code))
+
+    def phase_times(self) -> dict:
+        """Milliseconds per phase of the last call (timed phases only)."""
+        buf = (ctypes.c_float * len(PHASES))()
+        self._check(self._lib.hca_phase_times(self._ctx, buf, len(PHASES)))
+        return {name: float(buf[i]) for i, name in enumerate(PHASES)}
+
+    def cluster(self, points, eps: float, min_pts: int, core: bool = False, stats: bool = False,
+                out=None):
+        """Cluster a CUDA int32 tensor [n, d].  Returns an int32 tensor of labels
+        (and, if asked, a uint8 core-flag tensor and a stats dict).  Runs on the
+        current torch stream and blocks until done."""
+        import torch
+        if not (isinstance(points, torch.Tensor) and points.is_cuda):
+            raise TypeError("points must be a CUDA (HIP) torch tensor")
+        if points.dtype != torch.int32 or points.dim() != 2:
+            raise TypeError("points must be int32 with shape [n, d]")
+        pts = points.contiguous()
+        n, d = pts.shape
+        labels = out if out is not None else torch.empty(n, dtype=torch.int32, device=pts.device)
+        core_t = torch.empty(n, dtype=torch.uint8, device=pts.device) if core else None
+        st_obj = Stats() if stats else None
+        self.set_stream(torch.cuda.current_stream(pts.device).cuda_stream)
+        st = self._lib.hca_cluster_ex(self._ctx, ctypes.c_void_p(pts.data_ptr()), n, d, float(eps),
+                                      int(min_pts), ctypes.c_void_p(labels.data_ptr()),
+                                      ctypes.c_void_p(core_t.data_ptr()) if core else None,
+                                      ctypes.byref(st_obj) if stats else None)
+        self._check(st)
+        res = [labels]
+        if core:
+            res.append(core_t)
+        if stats:
+            res.append(st_obj.as_dict())
+        return res[0] if len(res) == 1 else tuple(res)
+
+    def cluster_ptr(self, points_ptr: int, n: int, d: int, eps: float, min_pts: int,
+                    labels_ptr: int):
+        """hca_cluster on raw device pointers (no tensor checks)."""
+        self._check(self._lib.hca_cluster(self._ctx, ctypes.c_void_p(points_ptr), int(n), int(d),
+                                          float(eps), int(min_pts), ctypes.c_void_p(labels_ptr)))
+
+    def cluster_host(self, points: np.ndarray, eps: float, min_pts: int) -> np.ndarray:
+        """Cluster a host int32 array [n, d] (copied in and out by the library)."""
+        p = np.ascontiguousarray(points, dtype=np.int32)
+        if p.ndim != 2:
+            raise TypeError("points must have shape [n, d]")
+        labels = np.empty(p.shape[0], np.int32)
+        st = self._lib.hca_cluster_host(self._ctx, p.ctypes.data_as(ctypes.c_void_p), p.shape[0],
+                                        p.shape[1], float(eps), int(min_pts),
+                                        labels.ctypes.data_as(ctypes.c_void_p))
+        self._check(st)
+        return labels
+
+
+_contexts: dict[int, Context] = {}
+
+
+def context(device: int = 0) -> Context:
+    """A cached context per device."""
+    if device not in _contexts:
+        _contexts[device] = Context(device)
+    return _contexts[device]
+
+
+def cluster(points, eps: float, min_pts: int, **kw):
+    """Cluster a CUDA int32 tensor [n, d] on its device; see Context.cluster."""
+    dev = points.device.index or 0
+    return context(dev).cluster(points, eps, min_pts, **kw)

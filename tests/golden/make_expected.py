@@ -1,0 +1,62 @@
+"""Write tests/golden/full_size_expected.json: the oracle's labels for the fixed
+workloads, stored as SHA-256 digests of the little-endian int32 label arrays
+plus summary counts.  Calls only the CPU oracle (definition part) and the
+seeded input generator.
+
+    python tests/golden/make_expected.py [--threads N]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import sys
+import time
+from pathlib import Path
+
+import numpy as np
+
+ROOT = Path(__file__).resolve().parents[2]
+sys.path.insert(0, str(ROOT))
+
+import oracle  # noqa: E402
+from paper_1912_00323_amd.datagen import make_config  # noqa: E402
+
+OUT = Path(__file__).resolve().parent / "full_size_expected.json"
+
+
+def digest(a: np.ndarray) -> str:
+    return hashlib.sha256(np.ascontiguousarray(a).astype("<i4").tobytes()).hexdigest()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--threads", type=int, default=0)
+    args = ap.parse_args()
+    out = {"note": "labels of the CPU oracle (DBSCAN definition) on the seeded workloads; "
+                   "points_sha256 guards against generator drift",
+           "workloads": {}}
+    for k in (1, 2, 3):
+        w = make_config(k)
+        t0 = time.time()
+        labels, counts, _ = oracle.dbscan(w.points, w.eps, w.min_pts, threads=args.threads,
+                                          details=True)
+        dt = time.time() - t0
+        core = counts >= w.min_pts
+        out["workloads"][w.name] = {
+            "config": k, "seed": k, "n": w.n, "d": w.d, "eps": w.eps, "min_pts": w.min_pts,
+            "eps2": oracle.exact_eps2(w.eps),
+            "points_sha256": digest(w.points.reshape(-1)),
+            "labels_sha256": digest(labels),
+            "core_sha256": digest(core.astype(np.int32)),
+            "n_clusters": int(labels.max() + 1) if len(labels) else 0,
+            "n_noise": int((labels < 0).sum()),
+            "n_core": int(core.sum()),
+            "oracle_seconds": round(dt, 2),
+        }
+        print(w.name, out["workloads"][w.name], flush=True)
+    OUT.write_text(json.dumps(out, indent=1) + "\n")
+
+
+if __name__ == "__main__":
+    main()

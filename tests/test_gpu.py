@@ -1,0 +1,240 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Labels must be bit-identical: exact DBSCAN with the fixed border rule and
+canonical numbering has exactly one correct labelling.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1912_00323_amd.datagen import make_blobs, make_config, make_mixed, quantise
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = Path(__file__).resolve().parent / "golden"
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "no HIP device visible"
+    from paper_1912_00323_amd import hca
+    c = hca.Context(0)
+    yield c
+    c.close()
+
+
+def gpu_labels(ctx, pts, eps, min_pts, core=False, stats=False):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(pts, np.int32)).cuda()
+    out = ctx.cluster(t, eps, min_pts, core=core, stats=stats)
+    if isinstance(out, tuple):
+        return tuple(o.cpu().numpy() if hasattr(o, "cpu") else o for o in out)
+    return out.cpu().numpy()
+
+
+def digest(a):
+    return hashlib.sha256(np.ascontiguousarray(a).astype("<i4").tobytes()).hexdigest()
+
+
+def check(ctx, pts, eps, mp, tag=""):
+    print(f"[case] {tag} n={len(pts)} d={pts.shape[1]} eps={eps} minPts={mp}", flush=True)
+    want = oracle.dbscan(pts, eps, mp)
+    got = gpu_labels(ctx, pts, eps, mp)
+    if not np.array_equal(got, want):
+        bad = np.flatnonzero(got != want)
+        raise AssertionError(f"{tag}: {len(bad)} labels differ, first at {bad[:10]} "
+                             f"got {got[bad[:10]]} want {want[bad[:10]]}")
+
+
+def test_small_workload(ctx):
+    w = make_config(1)
+    want, counts, _ = oracle.dbscan(w.points, w.eps, w.min_pts, details=True)
+    got, core, stats = gpu_labels(ctx, w.points, w.eps, w.min_pts, core=True, stats=True)
+    assert np.array_equal(core.astype(bool), counts >= w.min_pts)
+    assert np.array_equal(got, want)
+    assert stats["n_clusters"] == want.max() + 1
+    assert stats["n_noise"] == (want < 0).sum()
+    assert stats["n_core_points"] == (counts >= w.min_pts).sum()
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_blobs_every_dimension(ctx, d):
+    rng = np.random.default_rng(100 + d)
+    for n in (1, 2, 63, 64, 65, 2047, 2049, 5000):
+        x = make_blobs(rng, n, d, 4, 0.04, 0.1)
+        pts = quantise(x, 10)
+        eps = (0.06 + 0.01 * d) * 2 ** 10
+        for mp in (1, 4, 9):
+            check(ctx, pts, eps, mp, f"blobs d={d}")
+
+
+@pytest.mark.parametrize("mode", ["cube", "group"])
+@pytest.mark.parametrize("reps", ["1", "0"])
+def test_search_modes_agree(ctx, mode, reps, monkeypatch):
+    monkeypatch.setenv("HCA_SEARCH", mode)
+    monkeypatch.setenv("HCA_REPS", reps)
+    for d in (2, 3, 4, 5):
+        rng = np.random.default_rng(7 * d)
+        x = make_blobs(rng, 4000, d, 5, 0.03, 0.1)
+        pts = quantise(x, 12)
+        check(ctx, pts, 0.05 * 2 ** 12, 5, f"mode={mode} reps={reps} d={d}")
+
+
+def test_mixed_family(ctx):
+    for seed in range(6):
+        d = (2, 3, 4)[seed % 3]
+        n = int(np.exp(np.random.default_rng(seed).uniform(np.log(1000), np.log(20000))))
+        w = make_mixed(1000 + seed, n, d)
+        check(ctx, w.points, w.eps, w.min_pts, f"mixed seed={seed}")
+
+
+def test_degenerate_cases(ctx):
+    same = np.full((300, 3), 77, np.int32)
+    check(ctx, same, 0.5, 300, "identical, minPts=n")
+    check(ctx, same, 0.5, 301, "identical, minPts>n")
+    check(ctx, np.array([[5, -7]], np.int32), 3.0, 1, "single point")
+    check(ctx, np.array([[5, -7]], np.int32), 3.0, 2, "single point noise")
+    rng = np.random.default_rng(3)
+    pts = rng.integers(-5000, 5000, size=(3000, 2)).astype(np.int32)
+    check(ctx, pts, 0.3, 1, "eps < 1: only duplicates connect")
+    check(ctx, pts, 1e6, 5, "eps beyond the diameter")
+    k = 9
+    lat = np.array([(i * k, j * k) for i in range(40) for j in range(40)], np.int32)
+    check(ctx, lat, float(k), 5, "lattice on the eps boundary")
+    check(ctx, lat, k - 1e-9, 2, "lattice just outside eps")
+    line = np.stack([np.arange(5000) * 3, np.zeros(5000)], 1).astype(np.int32)
+    check(ctx, line, 3.0, 3, "collinear chain")
+    neg = quantise(make_blobs(rng, 3000, 4, 3, 0.05, 0.1), 10) - 100_000
+    check(ctx, neg, 70.0, 4, "negative coordinates")
+    # golden fixtures
+    for name in ("closed_ball_core", "representative_split", "border_ties"):
+        g = json.loads((GOLDEN / f"{name}.json").read_text())
+        for case in g["cases"]:
+            pts = np.array(case.get("points", g.get("points")), np.int32)
+            got = gpu_labels(ctx, pts, case["eps"], case["min_pts"])
+            assert got.tolist() == case["labels"], (name, case)
+
+
+def test_chains(ctx):
+    """Chains whose only links are consecutive points exactly eps apart: no
+    redundant edge, so a single lost union-find link changes the labels."""
+    rng = np.random.default_rng(5)
+    for n in (5000, 60000):
+        i = np.arange(n)
+        line = np.stack([i * 3, np.zeros(n)], 1).astype(np.int32)
+        diag = np.stack([i, i], 1).astype(np.int32)
+        cube8 = np.zeros((n, 8), np.int32)
+        cube8[:, 0] = cube8[:, 1] = i * 2                # steps of dist^2 = 8 in 8-D
+        for name, pts, eps in (("line", line, 3.0), ("diagonal", diag, 2 ** 0.5),
+                               ("8-D diagonal", cube8, 8 ** 0.5)):
+            for order in ("sorted", "reversed", "shuffled"):
+                p = pts[::-1] if order == "reversed" else (
+                    pts[rng.permutation(n)] if order == "shuffled" else pts)
+                p = np.ascontiguousarray(p)
+                check(ctx, p, eps, 3, f"chain {name} {order}")
+                check(ctx, p, eps, 1, f"chain {name} {order} minPts=1")
+
+
+def test_wide_distances(ctx):
+    """Coordinates and eps large enough that squared distances need 64 bits."""
+    rng = np.random.default_rng(11)
+    x = make_blobs(rng, 4000, 3, 4, 0.03, 0.1)
+    pts = quantise(x, 26)                          # spans ~2^26
+    eps = 0.05 * 2 ** 26
+    got, stats = gpu_labels(ctx, pts, eps, 5, stats=True)
+    assert stats["wide"] == 1
+    assert np.array_equal(got, oracle.dbscan(pts, eps, 5))
+
+
+def test_errors(ctx):
+    from paper_1912_00323_amd import hca
+    import torch
+    big = torch.tensor([[0, 0], [1 << 30, 0]], dtype=torch.int32, device="cuda")
+    with pytest.raises(hca.HcaError) as e:
+        ctx.cluster(big, 1.0, 1)
+    assert e.value.status == hca.HCA_E_RANGE
+    wide = torch.tensor([[0] * 8, [(1 << 29)] * 8], dtype=torch.int32, device="cuda")
+    with pytest.raises(hca.HcaError) as e:
+        ctx.cluster(wide, 1.0, 1)
+    assert e.value.status == hca.HCA_E_RANGE
+    ok = torch.zeros((4, 2), dtype=torch.int32, device="cuda")
+    for eps, mp in ((0.0, 1), (float("nan"), 1), (1.0, 0)):
+        with pytest.raises(hca.HcaError) as e:
+            ctx.cluster(ok, eps, mp)
+        assert e.value.status == hca.HCA_E_INVAL
+    # the context stays usable after errors
+    assert ctx.cluster(ok, 1.0, 1).cpu().tolist() == [0, 0, 0, 0]
+    empty = torch.zeros((0, 3), dtype=torch.int32, device="cuda")
+    assert ctx.cluster(empty, 1.0, 1).numel() == 0
+
+
+def test_host_pointer_entry(ctx):
+    w = make_config(1)
+    assert np.array_equal(ctx.cluster_host(w.points, w.eps, w.min_pts),
+                          oracle.dbscan(w.points, w.eps, w.min_pts))
+
+
+def test_side_stream(ctx):
+    import torch
+    w = make_config(1)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        t = torch.from_numpy(w.points).to("cuda", non_blocking=False)
+        lab = ctx.cluster(t, w.eps, w.min_pts)
+    s.synchronize()
+    assert np.array_equal(lab.cpu().numpy(), oracle.dbscan(w.points, w.eps, w.min_pts))
+
+
+def _sampled_checks(w, got, core, samples=300):
+    """One-by-one oracle checks on sampled points: |N(i)| by brute force over
+    all points decides core; a sampled non-core point with a core neighbour
+    must carry the label of its nearest core point (ties: smaller index)."""
+    rng = np.random.default_rng(99)
+    p = w.points.astype(np.int64)
+    e2 = oracle.exact_eps2(w.eps)
+    for i in rng.choice(w.n, size=min(samples, w.n), replace=False):
+        d2 = ((p - p[i]) ** 2).sum(1)
+        nb = d2 <= e2
+        assert core[i] == (nb.sum() >= w.min_pts), i
+        if not core[i]:
+            cand = np.flatnonzero(nb & core)
+            if len(cand) == 0:
+                assert got[i] == -1, i
+            else:
+                j = cand[np.lexsort((cand, d2[cand]))[0]]
+                assert got[i] == got[j] and got[i] >= 0, i
+        else:
+            cn = np.flatnonzero(nb & core)
+            assert (got[cn] == got[i]).all(), i
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_full_size_workloads(ctx, k):
+    exp = json.loads((GOLDEN / "full_size_expected.json").read_text())
+    w = make_config(k)
+    e = exp["workloads"][w.name]
+    assert digest(w.points.reshape(-1)) == e["points_sha256"], "input generator drifted"
+    print(f"[case] full-size {w.name}", flush=True)
+    got, core, stats = gpu_labels(ctx, w.points, w.eps, w.min_pts, core=True, stats=True)
+    core = core.astype(bool)
+    assert int(core.sum()) == e["n_core"]
+    assert digest(core.astype(np.int32)) == e["core_sha256"]
+    assert stats["n_clusters"] == e["n_clusters"] and stats["n_noise"] == e["n_noise"]
+    assert digest(got) == e["labels_sha256"]
+    _sampled_checks(w, got, core)
+
+
+def test_repeatable(ctx):
+    w = make_config(2, n=200_000)
+    first = gpu_labels(ctx, w.points, w.eps, w.min_pts)
+    for _ in range(5):
+        assert np.array_equal(gpu_labels(ctx, w.points, w.eps, w.min_pts), first)
+    assert np.array_equal(first, oracle.dbscan(w.points, w.eps, w.min_pts))
