@@ -185,6 +185,28 @@ bool plan_geometry(double eps, int d, Geometry *g, bool with_offsets)
     g->off.assign(d, 0);                          // self first
     int64_t cnt;
     enumerate_offsets(d, g->gradius, g->gside, g->eps2, 1ull << 24, &g->off, &cnt);
+    {
+        // nearest offsets first (smallest possible squared gap), self stays
+        // first: searches that stop early (core counting) stop sooner
+        const size_t m = g->off.size() / d;
+        std::vector<std::pair<unsigned __int128, uint32_t>> order;
+        for (size_t j = 1; j < m; j++) {
+            unsigned __int128 acc = 0;
+            for (int k = 0; k < d; k++) {
+                const int64_t a = std::abs((int)g->off[j * d + k]);
+                const unsigned __int128 gap = a ? (unsigned __int128)(a - 1) * (uint64_t)g->gside + 1 : 0;
+                acc += gap * gap;
+            }
+            order.push_back({acc, (uint32_t)j});
+        }
+        std::stable_sort(order.begin(), order.end(),
+                         [](const auto &x, const auto &y) { return x.first < y.first; });
+        std::vector<int8_t> sorted(g->off.begin(), g->off.begin() + d);
+        for (const auto &e : order)
+            sorted.insert(sorted.end(), g->off.begin() + (size_t)e.second * d,
+                          g->off.begin() + (size_t)(e.second + 1) * d);
+        g->off.swap(sorted);
+    }
     const uint32_t n_off = (uint32_t)(g->off.size() / d);
     g->n_dir = 0;
     if (g->m == 1 && d <= 4 && env_reps()) {
@@ -403,6 +425,7 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
     P.eps2 = G.eps2;
     P.side = (uint32_t)std::min<int64_t>(G.side, 1ll << 31);
     P.m = G.m;
+    P.gside = G.gside;
     P.bm = bit_length(G.m - 1);
     P.fine_bits = P.bm * d;
     uint32_t gbits = 0;
@@ -439,7 +462,8 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
     P.hash_mask = hcap - 1;
     const uint32_t sort_tiles = (n + kSortTile - 1) / kSortTile;
     const uint32_t scan_tiles = (n + kScanTile - 1) / kScanTile;
-    P.work_cap = (uint32_t)std::min<uint64_t>(4ull * n + 1024, 1ull << 30);
+    P.work_cap = (uint32_t)std::min<uint64_t>(4ull * n + 1024, 1ull << 30) / kWorkRegions * kWorkRegions;
+    P.want_stats = stats != nullptr;
 
     // 3. workspace
     auto carve = [&](Carver &cv, SortBuffers &B, uint32_t **zero_begin, size_t *zero_bytes) {
@@ -457,19 +481,23 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
         P.group_key = cv.take<uint64_t>(n);
         P.core = cv.take<uint8_t>(n);
         P.ncore = cv.take<uint32_t>(n);
-        P.rep = P.n_dir ? cv.take<uint32_t>((size_t)n * P.n_dir) : nullptr;
+        P.rep = P.n_dir ? cv.take<uint64_t>((size_t)n * P.n_dir) : nullptr;
         P.parent = cv.take<uint32_t>(n);
+        P.gcube = cv.take<uint32_t>(n);
+        P.unified = cv.take<uint8_t>(n);
         P.work = cv.take<uint32_t>((size_t)2 * P.work_cap);
         P.owner = cv.take<uint32_t>(n);
+        P.cmin = cv.take<uint32_t>(n);
         P.minmem = cv.take<uint32_t>(n);
-        P.root_in = cv.take<uint32_t>(n);
-        P.rank = cv.take<uint32_t>(n);
+        P.wrank = cv.take<uint32_t>(((size_t)n + 31) / 32);
+        P.label_of = cv.take<int32_t>(n);
         // zeroed before every call: counters, histograms, look-back words
         const size_t zstart = cv.off;
         P.ctr = cv.take<Counters>(1);
         B.hist = cv.take<uint32_t>((size_t)P.passes * kRadix);
         B.status = cv.take<uint64_t>((size_t)P.passes * sort_tiles * kRadix);
         P.scan_status = cv.take<uint64_t>((size_t)2 * scan_tiles + 64);
+        P.first = cv.take<uint32_t>(((size_t)n + 31) / 32);
         *zero_bytes = cv.off - zstart;
         *zero_begin = (uint32_t *)(cv.base ? cv.base + zstart : nullptr);
         // lookup table, filled with all-ones
@@ -515,7 +543,9 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
     launch_table(P, tb, s);
     mark(ctx, HCA_PHASE_CELLS, true);
     // 6. core points, representatives, merging, border points, labels
-    const int pb = (int)std::min<uint64_t>(kPersistBlocks, ((uint64_t)n + kBlock - 1) / kBlock * 4 + 8) & ~7;
+    int persist = kPersistBlocks;
+    if (const char *e = std::getenv("HCA_WAVE_BLOCKS")) persist = std::max(8, std::atoi(e));
+    const int pb = (int)std::min<uint64_t>(persist, ((uint64_t)n + kBlock - 1) / kBlock * 4 + 8) & ~7;
     const int wb = std::max(8, pb);
     mark(ctx, HCA_PHASE_CORE, false);
     launch_core(P, wb, s);
@@ -547,7 +577,9 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
         const Counters *hc = (const Counters *)ctx->pinned;
         stats->n_cells = hc->n_cells;
         stats->n_groups = hc->n_groups;
-        stats->exact_pairs = hc->worklist;
+        int64_t pairs = 0;
+        for (int r = 0; r < kWorkRegions; r++) pairs += hc->work_count[r * kCounterStride];
+        stats->exact_pairs = pairs;
         stats->n_core_points = hc->n_core;
         stats->n_noise = hc->n_noise;
         stats->n_clusters = hc->n_clusters;

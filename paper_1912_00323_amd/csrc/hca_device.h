@@ -102,25 +102,37 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T *smem, T *total)
 }
 
 // ---- XCD-aware assignment of work units to waves -------------------------
-// Workgroups are dispatched round-robin over the 8 XCDs.  Each XCD gets one
-// contiguous eighth of the units (neighbouring cubes, so its L2 holds their
-// data) and its waves stride over that range.
+// Workgroups are dispatched round-robin over the 8 XCDs.  Units (cubes or
+// groups, in key order) are dealt to the XCDs in runs of 32, so each XCD's L2
+// sees runs of neighbouring cubes while dense regions are spread over all
+// XCDs; within an XCD the waves take its units in turn.
+constexpr uint32_t kXcdRun = 32;
+
 struct WaveRange {
-    uint32_t first, step, end;
+    uint32_t first, step, xcd;
+    __device__ __forceinline__ uint32_t unit(uint32_t k) const
+    {
+        return ((k / kXcdRun) * 8u + xcd) * kXcdRun + (k % kXcdRun);
+    }
 };
 
-__device__ __forceinline__ WaveRange wave_range(uint32_t units)
+__device__ __forceinline__ WaveRange wave_range()
 {
     const uint32_t nb = gridDim.x, b = blockIdx.x;
     const uint32_t xcd = b & 7u, bx = b >> 3;
     const uint32_t nbx = (nb - xcd + 7u) >> 3;
-    const uint64_t lo = (uint64_t)units * xcd / 8u, hi = (uint64_t)units * (xcd + 1u) / 8u;
     WaveRange r;
-    r.first = (uint32_t)lo + bx * (kBlock / kWave) + wave_in_block();
+    r.first = bx * (kBlock / kWave) + wave_in_block();
     r.step = nbx * (kBlock / kWave);
-    r.end = (uint32_t)hi;
+    r.xcd = xcd;
     return r;
 }
+
+// for (unit u of this wave) { ... }: units grow with k, so the first one past
+// the end closes the loop.
+#define HCA_FOR_UNITS(u, units)                                                         \
+    for (uint32_t k_ = hca_wr_.first, u = hca_wr_.unit(k_); u < (units);                \
+         k_ += hca_wr_.step, u = hca_wr_.unit(k_))
 
 // ---- points ----------------------------------------------------------------
 template <int D>
@@ -273,11 +285,19 @@ __device__ __forceinline__ void st_parent(uint32_t *p, uint32_t v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// While unions are in progress a cached (possibly stale) read is enough: it
+// still names an ancestor, indices fall along every path, and the union's
+// compare-and-swap works on the coherent value and returns it on failure.
+__device__ __forceinline__ uint32_t ld_parent_cached(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 __device__ __forceinline__ uint32_t uf_find(uint32_t *parent, uint32_t x)
 {
-    uint32_t p = ld_parent(parent + x);
+    uint32_t p = ld_parent_cached(parent + x);
     while (p != x) {
-        const uint32_t gp = ld_parent(parent + p);
+        const uint32_t gp = ld_parent_cached(parent + p);
         if (gp != p) st_parent(parent + x, gp);   // path splitting; gp is an ancestor of x
         x = p;
         p = gp;
@@ -315,6 +335,35 @@ __device__ __forceinline__ void uf_union(uint32_t *parent, uint32_t a, uint32_t 
 // Look-back for single-value device scans: one thread publishes the tile's
 // aggregate and returns the exclusive prefix of all earlier tiles.
 // ---------------------------------------------------------------------------
+// Wave-parallel form: the 64 lanes of one wave read 64 predecessors at once
+// and stop at the nearest one holding an inclusive prefix.  All lanes return
+// the same exclusive prefix.
+__device__ __forceinline__ uint64_t scan_lookback_wave(uint64_t *status, uint32_t tile, uint64_t agg)
+{
+    const uint32_t l = lane_id();
+    if (l == 0) st_agent(status + tile, (tile == 0 ? kFlagInc : kFlagAgg) | agg);
+    if (tile == 0) return 0;
+    uint64_t excl = 0;
+    int64_t top = (int64_t)tile - 1;             // predecessor read by lane 0
+    while (true) {
+        const int64_t k = top - (int64_t)l;
+        uint64_t v = k >= 0 ? ld_agent(status + k) : kFlagInc;   // before tile 0: empty prefix
+        uint64_t f = v & ~kValMask;
+        const uint64_t pending = __ballot(f == 0);
+        const uint64_t inc = __ballot(f == kFlagInc);
+        // the nearest inclusive word; every lane before it must be ready
+        const uint32_t stop = inc ? (uint32_t)__ffsll((unsigned long long)inc) - 1 : 64u;
+        const uint64_t before = stop >= 64 ? ~0ull : ((2ull << stop) - 1ull);
+        if (pending & before) { __builtin_amdgcn_s_sleep(1); continue; }
+        uint64_t mine = (l <= stop) ? (v & kValMask) : 0ull;
+        excl += wave_sum(mine);
+        if (inc) break;
+        top -= 64;
+    }
+    if (l == 0) st_agent(status + tile, kFlagInc | (excl + agg));
+    return excl;
+}
+
 __device__ __forceinline__ uint64_t scan_lookback(uint64_t *status, uint32_t tile, uint64_t agg)
 {
     if (tile == 0) {

@@ -14,36 +14,77 @@ namespace hca {
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kPch = 8;           // points of the own group handled per sweep
 
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int32_t uniform_i(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Bounding box of the chunk points whose bit is set in `mask` (wave-uniform).
+template <int D>
+struct QBox {
+    int32_t lo[D], hi[D];
+};
+
+template <int D>
+__device__ __forceinline__ QBox<D> chunk_box(const Pt<D> *pp, uint32_t mask)
+{
+    QBox<D> b;
+#pragma unroll
+    for (int e = 0; e < D; e++) { b.lo[e] = INT32_MAX; b.hi[e] = INT32_MIN; }
+#pragma unroll
+    for (int k = 0; k < kPch; k++) {
+        if (!(mask & (1u << k))) continue;
+#pragma unroll
+        for (int e = 0; e < D; e++) {
+            b.lo[e] = min(b.lo[e], pp[k].x[e]);
+            b.hi[e] = max(b.hi[e], pp[k].x[e]);
+        }
+    }
+    return b;
+}
+
 // ---------------------------------------------------------------------------
 // Candidate lists: the points of the neighbour groups at offsets
 // [first, first + 64), laid out one after the other.  Lane l resolves offset
 // first + l; its point range starts at s_beg[l] and its first candidate index
-// is s_pre[l].  Returns the number of candidates in the chunk.
+// is s_pre[l].  A group is dropped when its id is below `lowest`, when its box
+// is farther than eps from the query box q, or (need_core, m == 1) when its
+// cube has no core point.  Returns the number of candidates in the chunk.
 // ---------------------------------------------------------------------------
 template <int D>
 __device__ __forceinline__ uint32_t load_neighbours(const Plan &P, uint64_t gkey, uint32_t first,
-                                                    uint32_t lowest, uint32_t *s_beg,
-                                                    uint32_t *s_pre, uint32_t *s_grp)
+                                                    uint32_t lowest, bool need_core,
+                                                    const QBox<D> &q, uint32_t *s_beg,
+                                                    uint32_t *s_pre)
 {
     const uint32_t l = lane_id();
     const uint32_t j = first + l;
-    uint32_t a = 0, size = 0, G = kNone;
+    uint32_t a = 0, size = 0;
     if (j < P.n_off) {
         const uint64_t nk = group_neighbour<D>(P, gkey, P.off + (uint64_t)j * D);
         if (nk != ~0ull) {
-            G = group_lookup(P, nk);
-            if (G != kNone && G >= lowest) {
-                a = P.group_start[G];
-                size = P.group_start[G + 1] - a;
-            } else {
-                G = kNone;
+            const uint32_t G = group_lookup(P, nk);
+            if (G != kNone && G >= lowest && !(need_core && P.m == 1 && P.ncore[G] == 0)) {
+                // closest approach of the group's box to the query box
+                int64_t acc = 0;
+#pragma unroll
+                for (int e = 0; e < D; e++) {
+                    const int64_t gc = (int64_t)((nk >> P.goff[e]) & ((1ull << P.gw[e]) - 1ull));
+                    const int64_t glo = (int64_t)P.origin[e] + gc * P.gside;
+                    const int64_t ghi = glo + P.gside - 1;
+                    int64_t gap = 0;
+                    if (glo > q.hi[e]) gap = glo - q.hi[e];
+                    else if ((int64_t)q.lo[e] > ghi) gap = (int64_t)q.lo[e] - ghi;
+                    acc += gap * gap;
+                }
+                if (acc <= P.eps2) {
+                    a = P.group_start[G];
+                    size = P.group_start[G + 1] - a;
+                }
             }
         }
     }
     const uint32_t inc = wave_inclusive_scan(size);
     s_beg[l] = a;
     s_pre[l] = inc - size;
-    if (s_grp) s_grp[l] = G;
     __builtin_amdgcn_wave_barrier();
     return __shfl(inc, kWave - 1);
 }
@@ -60,12 +101,24 @@ __device__ __forceinline__ uint32_t candidate_lane(uint32_t ci, const uint32_t *
     return lo;
 }
 
-__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+// The chunk's own points [pc, pc + np) as wave-uniform registers.
+template <int D>
+__device__ __forceinline__ void load_chunk(const Plan &P, uint32_t pc, uint32_t np, Pt<D> *pp)
+{
+#pragma unroll
+    for (int k = 0; k < kPch; k++) {
+        const uint32_t q = pc + (k < (int)np ? k : 0);
+        pp[k] = load_pt<D>(P.spts, q);
+#pragma unroll
+        for (int e = 0; e < D; e++) pp[k].x[e] = uniform_i(pp[k].x[e]);
+    }
+}
 
 // ---------------------------------------------------------------------------
-// Per-call initialisation: counters, histograms and look-back words (zero)
-// and hash keys (all ones) with agent-scope stores, since atomics update them
-// later; the direct lookup table (all ones) with plain stores.
+// Per-call initialisation: counters, histograms, look-back words and the
+// first-member bitmap (zero) and hash keys (all ones) with agent-scope
+// stores, since atomics update them later; the direct lookup table (all
+// ones) with plain stores.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_init(uint32_t *zero, uint64_t zero_words, uint64_t *hkeys,
                                                  uint64_t hcap, uint32_t *table, uint64_t tsize)
@@ -106,7 +159,10 @@ __global__ __launch_bounds__(kBlock) void k_table(Plan P)
 // Core marking (appendix, Definition 2).  A cube holding at least minPts
 // points makes them all core, since every pair in a cube is within eps.  A
 // point of a sparser cube counts the candidates within eps, own group
-// included, and stops as soon as it reaches minPts.
+// included, and stops as soon as it reaches minPts.  The wave owning a group
+// also records, per cube, its number of core points and the smallest input
+// index among them (the first core point: the sort keeps input order inside
+// a cube).
 // ---------------------------------------------------------------------------
 template <int D, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_core(Plan P)
@@ -115,12 +171,11 @@ __global__ __launch_bounds__(kBlock) void k_core(Plan P)
     const uint32_t w = wave_in_block(), l = lane_id();
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
     const uint32_t minpts = (uint32_t)P.min_pts;
-    const WaveRange r = wave_range(ng);
-    for (uint32_t g = r.first; g < r.end; g += r.step) {
+    const WaveRange hca_wr_ = wave_range();
+    HCA_FOR_UNITS(g, ng) {
         const uint32_t p0 = P.group_start[g], p1 = P.group_start[g + 1];
         const uint32_t c0 = P.group_cell[g], c1 = P.group_cell[g + 1];
         const uint64_t gkey = P.group_key[g];
-        // dense cubes first
         bool any_sparse = false;
         for (uint32_t c = c0; c < c1; c++) {
             const uint32_t a = P.cell_start[c], b = P.cell_start[c + 1];
@@ -130,49 +185,51 @@ __global__ __launch_bounds__(kBlock) void k_core(Plan P)
                 for (uint32_t q = a + l; q < b; q += kWave) P.core[q] = 1;
         }
         if (!any_sparse) {
-            for (uint32_t c = c0 + l; c < c1; c += kWave) P.ncore[c] = P.cell_start[c + 1] - P.cell_start[c];
+            for (uint32_t c = c0 + l; c < c1; c += kWave) {
+                P.ncore[c] = P.cell_start[c + 1] - P.cell_start[c];
+                P.cmin[c] = P.sidx[P.cell_start[c]];
+            }
             continue;
         }
-        // core points per cube, tallied in point order (cubes are contiguous)
-        uint32_t tally_cell = kNone, tally = 0;
+        uint32_t tally_cell = kNone, tally = 0, tally_min = kNone;
         for (uint32_t pc = p0; pc < p1; pc += kPch) {
-            // the chunk's own points: uniform registers
             Pt<D> pp[kPch];
             uint32_t cnt[kPch];
             uint32_t done = 0;
             const uint32_t np = min((uint32_t)kPch, p1 - pc);
+            load_chunk<D>(P, pc, np, pp);
 #pragma unroll
             for (int k = 0; k < kPch; k++) {
                 cnt[k] = 0;
-                const uint32_t q = pc + (k < (int)np ? k : 0);
-                pp[k] = load_pt<D>(P.spts, q);
-#pragma unroll
-                for (int e = 0; e < D; e++) pp[k].x[e] = __builtin_amdgcn_readfirstlane(pp[k].x[e]);
-                const uint32_t c = P.cell_of[q];
+                const uint32_t c = P.cell_of[pc + (k < (int)np ? k : 0)];
                 const bool dense = P.cell_start[c + 1] - P.cell_start[c] >= minpts;
                 if (k >= (int)np || dense) done |= 1u << k;
             }
             done = uniform(done);
             const uint32_t all = (1u << kPch) - 1u;
-            for (uint32_t oc = 0; oc < P.n_off && done != all; oc += kWave) {
-                const uint32_t total = load_neighbours<D>(P, gkey, oc, 0, s_beg[w], s_pre[w], nullptr);
-                for (uint32_t ci = 0; ci < total && done != all; ci += kWave) {
-                    const uint32_t c = ci + l;
-                    const bool ok = c < total;
-                    uint32_t pos = 0;
-                    if (ok) {
-                        const uint32_t ln = candidate_lane(c, s_pre[w]);
-                        pos = s_beg[w][ln] + (c - s_pre[w][ln]);
-                    }
-                    const Pt<D> q = load_pt<D>(P.spts, pos);
+            if (done != all) {
+                const QBox<D> qb = chunk_box<D>(pp, ~done);
+                for (uint32_t oc = 0; oc < P.n_off && done != all; oc += kWave) {
+                    const uint32_t total =
+                        load_neighbours<D>(P, gkey, oc, 0, false, qb, s_beg[w], s_pre[w]);
+                    for (uint32_t ci = 0; ci < total && done != all; ci += kWave) {
+                        const uint32_t c = ci + l;
+                        const bool ok = c < total;
+                        uint32_t pos = 0;
+                        if (ok) {
+                            const uint32_t ln = candidate_lane(c, s_pre[w]);
+                            pos = s_beg[w][ln] + (c - s_pre[w][ln]);
+                        }
+                        const Pt<D> q = load_pt<D>(P.spts, pos);
 #pragma unroll
-                    for (int k = 0; k < kPch; k++) {
-                        if (done & (1u << k)) continue;
-                        const bool hit = ok && within<D, WIDE>(pp[k], q, P.eps2);
-                        cnt[k] += __popcll(__ballot(hit));
-                        if (cnt[k] >= minpts) done |= 1u << k;
+                        for (int k = 0; k < kPch; k++) {
+                            if (done & (1u << k)) continue;
+                            const bool hit = ok && within<D, WIDE>(pp[k], q, P.eps2);
+                            cnt[k] += __popcll(__ballot(hit));
+                            if (cnt[k] >= minpts) done |= 1u << k;
+                        }
+                        done = uniform(done);
                     }
-                    done = uniform(done);
                 }
             }
             // lane k < np writes the result of point pc + k
@@ -186,6 +243,7 @@ __global__ __launch_bounds__(kBlock) void k_core(Plan P)
                 const bool dense = P.cell_start[c + 1] - P.cell_start[c] >= minpts;
                 if (!dense) P.core[q] = mine >= minpts;
             }
+            // per-cube tallies in point order
 #pragma unroll
             for (int k = 0; k < kPch; k++) {
                 if ((uint32_t)k >= np) break;
@@ -193,14 +251,24 @@ __global__ __launch_bounds__(kBlock) void k_core(Plan P)
                 const uint32_t c = uniform(P.cell_of[q]);
                 const bool dense = P.cell_start[c + 1] - P.cell_start[c] >= minpts;
                 if (c != tally_cell) {
-                    if (tally_cell != kNone && l == 0) P.ncore[tally_cell] = tally;
+                    if (tally_cell != kNone && l == 0) {
+                        P.ncore[tally_cell] = tally;
+                        P.cmin[tally_cell] = tally_min;
+                    }
                     tally_cell = c;
                     tally = 0;
+                    tally_min = kNone;
                 }
-                tally += (dense || cnt[k] >= minpts) ? 1u : 0u;
+                if (dense || cnt[k] >= minpts) {
+                    tally++;
+                    if (tally_min == kNone) tally_min = uniform(P.sidx[q]);
+                }
             }
         }
-        if (l == 0) P.ncore[tally_cell] = tally;
+        if (l == 0) {
+            P.ncore[tally_cell] = tally;
+            P.cmin[tally_cell] = tally_min;
+        }
     }
 }
 
@@ -210,55 +278,65 @@ __global__ __launch_bounds__(kBlock) void k_core(Plan P)
 // cube closest to the ideal position on the boundary in that direction,
 // ties to the first point in sorted order.  The ideal coordinate is the upper
 // face (c+1)*s for +1 and the lower face c*s for -1; axes with 0 are free.
+//
+// Cubes range from one point to thousands, so the work is cut into equal
+// chunks of 64 sorted points, one per wave.  Each lane scores its point in
+// every direction; a segmented minimum over the lanes of each cube (cubes are
+// contiguous runs) leaves the chunk's best in the cube's first lane, which
+// folds it into the cube's representative with a 64-bit atomic minimum of
+// (score, position).
 // ---------------------------------------------------------------------------
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_reps(Plan P)
 {
     const uint32_t l = lane_id();
-    const uint32_t nc = ld_agent32(&P.ctr->n_cells);
-    const WaveRange r = wave_range(nc);
     const int64_t s = P.side;
-    for (uint32_t c = r.first; c < r.end; c += r.step) {
-        if (P.ncore[c] == 0) continue;
-        const uint32_t a = P.cell_start[c], b = P.cell_start[c + 1];
-        const uint64_t gkey = P.group_key[c];
-        int64_t lo[D];
+    uint32_t zero = 0, mul = 1;
 #pragma unroll
-        for (int k = 0; k < D; k++) {
-            const int64_t gc = (int64_t)((gkey >> P.goff[k]) & ((1ull << P.gw[k]) - 1ull));
-            lo[k] = (int64_t)P.origin[k] + gc * s;
+    for (int k = 0; k < D; k++) { zero += mul; mul *= 3; }
+    const uint32_t chunks = (P.n + kWave - 1) / kWave;
+    const WaveRange hca_wr_ = wave_range();
+    HCA_FOR_UNITS(ch, chunks) {
+        const uint32_t q = ch * kWave + l;
+        const bool in = q < P.n;
+        const uint32_t c = in ? P.cell_of[q] : kNone;
+        const bool core = in && P.core[q];
+        if (!__ballot(core)) continue;
+        const uint32_t cprev = __shfl_up(c, 1);
+        const bool head = l == 0 || cprev != c;
+        uint64_t up[D], dn[D];                  // squared gaps to the upper and lower faces
+        {
+            const Pt<D> p = load_pt<D>(P.spts, in ? q : 0);
+            const uint64_t gkey = in ? P.group_key[c] : 0;
+#pragma unroll
+            for (int k = 0; k < D; k++) {
+                const int64_t gc = (int64_t)((gkey >> P.goff[k]) & ((1ull << P.gw[k]) - 1ull));
+                const int64_t u = (int64_t)p.x[k] - ((int64_t)P.origin[k] + gc * s);
+                up[k] = (uint64_t)((s - u) * (s - u));
+                dn[k] = (uint64_t)(u * u);
+            }
         }
         for (uint32_t t = 0; t < P.n_dir; t++) {
-            int dir[D];
-            {
-                uint32_t zero = 0, mul = 1;
+            uint32_t v = t >= zero ? t + 1 : t;
+            uint64_t sc = 0;
 #pragma unroll
-                for (int k = 0; k < D; k++) { zero += mul; mul *= 3; }
-                uint32_t v = t >= zero ? t + 1 : t;
-#pragma unroll
-                for (int k = 0; k < D; k++) { dir[k] = (int)(v % 3) - 1; v /= 3; }
+            for (int k = 0; k < D; k++) {
+                const uint32_t digit = v % 3;
+                v /= 3;
+                sc += digit == 2 ? up[k] : (digit == 0 ? dn[k] : 0);
             }
-            int64_t best = INT64_MAX;
-            uint32_t bpos = kNone;
-            for (uint32_t q = a + l; q < b; q += kWave) {
-                if (!P.core[q]) continue;
-                const Pt<D> p = load_pt<D>(P.spts, q);
-                int64_t sc = 0;
+            // scores past 32 bits only blur the choice between
+            // representatives, which affects speed, never labels
+            uint64_t key = core ? (min(sc, (uint64_t)0xFFFFFFFFull) << 32) | q : ~0ull;
 #pragma unroll
-                for (int k = 0; k < D; k++) {
-                    const int64_t u = (int64_t)p.x[k] - lo[k];
-                    const int64_t e = dir[k] > 0 ? s - u : u;
-                    sc += dir[k] ? e * e : 0;
-                }
-                if (sc < best || (sc == best && q < bpos)) { best = sc; bpos = q; }
+            for (int o = 1; o < kWave; o <<= 1) {
+                const uint64_t other = __shfl_down(key, o);
+                const uint32_t oc = __shfl_down(c, o);
+                if (l + o < (uint32_t)kWave && oc == c && other < key) key = other;
             }
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                const int64_t ob = __shfl_xor(best, o);
-                const uint32_t op = __shfl_xor(bpos, o);
-                if (ob < best || (ob == best && op < bpos)) { best = ob; bpos = op; }
-            }
-            if (l == 0) P.rep[(uint64_t)c * P.n_dir + t] = bpos;
+            if (head && key != ~0ull)
+                atomicMin((unsigned long long *)(P.rep + ((uint64_t)c * P.n_dir + t)),
+                          (unsigned long long)key);
         }
     }
 }
@@ -278,8 +356,8 @@ __global__ __launch_bounds__(kBlock) void k_merge_rep(Plan P)
 {
     const uint32_t l = lane_id();
     const uint32_t nc = ld_agent32(&P.ctr->n_cells);
-    const WaveRange r = wave_range(nc);
-    for (uint32_t A = r.first; A < r.end; A += r.step) {
+    const WaveRange hca_wr_ = wave_range();
+    HCA_FOR_UNITS(A, nc) {
         if (P.ncore[A] == 0) continue;
         const uint64_t gkey = P.group_key[A];
         for (uint32_t oc = 1; oc < P.n_off; oc += kWave) {
@@ -293,22 +371,27 @@ __global__ __launch_bounds__(kBlock) void k_merge_rep(Plan P)
             if (todo) todo = uf_find(P.parent, A) != uf_find(P.parent, B);
             bool joined = false;
             if (todo && P.n_dir) {
-                const uint32_t qa = P.rep[(uint64_t)A * P.n_dir + P.dir_fwd[j]];
-                const uint32_t qb = P.rep[(uint64_t)B * P.n_dir + P.dir_bwd[j]];
+                const uint32_t qa = (uint32_t)ld_agent(P.rep + (uint64_t)A * P.n_dir + P.dir_fwd[j]);
+                const uint32_t qb = (uint32_t)ld_agent(P.rep + (uint64_t)B * P.n_dir + P.dir_bwd[j]);
                 joined = within<D, WIDE>(load_pt<D>(P.spts, qa), load_pt<D>(P.spts, qb), P.eps2);
                 if (joined) uf_union(P.parent, A, B);
             }
             const bool exact = todo && !joined;
             const uint64_t m = __ballot(exact);
             if (m) {
+                // region of this wave; slots of region r are [r * cap, (r + 1) * cap)
+                const uint32_t region = (blockIdx.x * kWavesPerBlock + wave_in_block()) % kWorkRegions;
+                const uint32_t cap = P.work_cap / kWorkRegions;
                 uint32_t base = 0;
-                if (l == 0) base = atomicAdd(&P.ctr->worklist, (uint32_t)__popcll(m));
+                if (l == 0)
+                    base = atomicAdd(P.ctr->work_count + region * kCounterStride, (uint32_t)__popcll(m));
                 base = __shfl(base, 0);
                 const uint32_t slot = base + __popcll(m & __lanemask_lt());
-                const bool spill = exact && slot >= P.work_cap;
+                const bool spill = exact && slot >= cap;
                 if (exact && !spill) {
-                    P.work[2ull * slot] = A;
-                    P.work[2ull * slot + 1] = B;
+                    const uint64_t at = (uint64_t)region * cap + slot;
+                    P.work[2ull * at] = A;
+                    P.work[2ull * at + 1] = B;
                 }
                 // worklist full: test here, one spilled pair at a time
                 uint64_t sm = __ballot(spill);
@@ -353,65 +436,198 @@ __device__ void exact_pair(const Plan &P, uint32_t A, uint32_t B)
 template <int D, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_merge_exact(Plan P)
 {
-    const uint32_t items = min(ld_agent32(&P.ctr->worklist), P.work_cap);
-    const WaveRange r = wave_range(items);
-    for (uint32_t it = r.first; it < r.end; it += r.step)
-        exact_pair<D, WIDE>(P, P.work[2ull * it], P.work[2ull * it + 1]);
+    __shared__ uint32_t s_pre[kWavesPerBlock][kWorkRegions];
+    const uint32_t w = wave_in_block(), l = lane_id();
+    // items per region (lane = region), laid out one region after the other
+    const uint32_t cap = P.work_cap / kWorkRegions;
+    const uint32_t cnt = min(ld_agent32(P.ctr->work_count + l * kCounterStride), cap);
+    const uint32_t inc = wave_inclusive_scan(cnt);
+    s_pre[w][l] = inc - cnt;
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t items = __shfl(inc, kWave - 1);
+    const WaveRange hca_wr_ = wave_range();
+    HCA_FOR_UNITS(it, items) {
+        const uint32_t r = candidate_lane(it, s_pre[w]);
+        const uint64_t at = (uint64_t)r * cap + (it - s_pre[w][r]);
+        exact_pair<D, WIDE>(P, P.work[2ull * at], P.work[2ull * at + 1]);
+    }
 }
 
 // ---------------------------------------------------------------------------
-// Merging, m > 1: one wave per group GA, against every group GB >= GA at the
-// search offsets; each core pair within eps links its two cubes.
+// Merging, m > 1, in two passes.
+//
+// Intra: each group links the cubes of its own core pairs within eps, then
+// records its first core cube and whether all its core cubes now share one
+// root ("unified"; unions only ever join sets, so a unified group stays so).
+//
+// Inter: for each group GA and neighbour group GB > GA, when both are unified
+// one root per group decides: equal roots mean nothing to do; otherwise the
+// core pairs of the two groups are tested in tiles of 64 lanes until the
+// first pair within eps (wavefront ballot), which joins the two sets.  A pair
+// involving a group that is not unified falls back to linking every core
+// pair within eps.
 // ---------------------------------------------------------------------------
 template <int D, bool WIDE>
-__global__ __launch_bounds__(kBlock) void k_merge_group(Plan P)
+__global__ __launch_bounds__(kBlock) void k_merge_intra(Plan P)
 {
-    __shared__ uint32_t s_beg[kWavesPerBlock][kWave], s_pre[kWavesPerBlock][kWave];
-    const uint32_t w = wave_in_block(), l = lane_id();
+    const uint32_t l = lane_id();
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
-    const WaveRange r = wave_range(ng);
-    for (uint32_t g = r.first; g < r.end; g += r.step) {
+    const WaveRange hca_wr_ = wave_range();
+    HCA_FOR_UNITS(g, ng) {
         const uint32_t p0 = P.group_start[g], p1 = P.group_start[g + 1];
-        const uint64_t gkey = P.group_key[g];
-        for (uint32_t pc = p0; pc < p1; pc += kPch) {
-            Pt<D> pp[kPch];
-            uint32_t cell[kPch];
-            uint32_t live = 0;
-            const uint32_t np = min((uint32_t)kPch, p1 - pc);
+        const uint32_t c0 = P.group_cell[g], c1 = P.group_cell[g + 1];
+        if (c1 - c0 > 1) {
+            for (uint32_t pc = p0; pc < p1; pc += kPch) {
+                Pt<D> pp[kPch];
+                uint32_t cell[kPch];
+                uint32_t live = 0;
+                const uint32_t np = min((uint32_t)kPch, p1 - pc);
+                load_chunk<D>(P, pc, np, pp);
 #pragma unroll
-            for (int k = 0; k < kPch; k++) {
-                const uint32_t q = pc + (k < (int)np ? k : 0);
-                pp[k] = load_pt<D>(P.spts, q);
-#pragma unroll
-                for (int e = 0; e < D; e++) pp[k].x[e] = __builtin_amdgcn_readfirstlane(pp[k].x[e]);
-                cell[k] = uniform(P.cell_of[q]);
-                if (k < (int)np && P.core[q]) live |= 1u << k;
-            }
-            live = uniform(live);
-            if (!live) continue;
-            for (uint32_t oc = 0; oc < P.n_off; oc += kWave) {
-                const uint32_t total = load_neighbours<D>(P, gkey, oc, g, s_beg[w], s_pre[w], nullptr);
-                for (uint32_t ci = 0; ci < total; ci += kWave) {
-                    const uint32_t c = ci + l;
-                    bool ok = c < total;
-                    uint32_t pos = 0;
-                    if (ok) {
-                        const uint32_t ln = candidate_lane(c, s_pre[w]);
-                        pos = s_beg[w][ln] + (c - s_pre[w][ln]);
-                        ok = P.core[pos] != 0;
-                    }
-                    const Pt<D> q = load_pt<D>(P.spts, pos);
-                    const uint32_t cq = P.cell_of[pos];
+                for (int k = 0; k < kPch; k++) {
+                    const uint32_t q = pc + (k < (int)np ? k : 0);
+                    cell[k] = uniform(P.cell_of[q]);
+                    if (k < (int)np && P.core[q]) live |= 1u << k;
+                }
+                live = uniform(live);
+                if (!live) continue;
+                for (uint32_t base = pc; base < p1; base += kWave) {
+                    const uint32_t q = base + l;
+                    const bool ok = q < p1 && P.core[q];
+                    const Pt<D> pq = load_pt<D>(P.spts, ok ? q : pc);
+                    const uint32_t cq = ok ? P.cell_of[q] : 0;
 #pragma unroll
                     for (int k = 0; k < kPch; k++) {
                         if (!(live & (1u << k))) continue;
-                        // each unordered cube pair once: other groups are > g,
-                        // and inside g only cubes above the point's own
-                        const bool hit = ok && cq > cell[k] && within<D, WIDE>(pp[k], q, P.eps2);
+                        const bool hit = ok && cq > cell[k] && within<D, WIDE>(pp[k], pq, P.eps2);
                         if (hit && uf_find(P.parent, cell[k]) != uf_find(P.parent, cq))
                             uf_union(P.parent, cell[k], cq);
                     }
                 }
+            }
+        }
+        // first core cube, and whether every core cube shares its root
+        uint32_t first = kNone;
+        for (uint32_t cb = c0; cb < c1 && first == kNone; cb += kWave) {
+            const uint32_t c = cb + l;
+            const uint64_t m = __ballot(c < c1 && P.ncore[c] > 0);
+            if (m) first = cb + __ffsll((unsigned long long)m) - 1;
+        }
+        bool unified = true;
+        if (first != kNone) {
+            const uint32_t r0 = uf_find(P.parent, first);
+            for (uint32_t cb = first; cb < c1 && unified; cb += kWave) {
+                const uint32_t c = cb + l;
+                const bool other = c < c1 && P.ncore[c] > 0 && uf_find(P.parent, c) != r0;
+                unified = __ballot(other) == 0;
+            }
+        }
+        if (l == 0) {
+            P.gcube[g] = first;
+            P.unified[g] = unified;
+        }
+    }
+}
+
+template <int D, bool WIDE>
+__device__ void link_groups(const Plan &P, uint32_t GA, uint32_t GB, bool both_unified)
+{
+    const uint32_t l = lane_id();
+    const uint32_t a0 = P.group_start[GA], na = P.group_start[GA + 1] - a0;
+    const uint32_t b0 = P.group_start[GB], nb = P.group_start[GB + 1] - b0;
+    const uint64_t total = (uint64_t)na * nb;
+    if (both_unified) {
+        const uint32_t ca = P.gcube[GA], cb = P.gcube[GB];
+        if (uf_find(P.parent, ca) == uf_find(P.parent, cb)) return;
+        for (uint64_t base = 0; base < total; base += kWave) {
+            const uint64_t k = base + l;
+            bool hit = false;
+            if (k < total) {
+                const uint32_t i = (uint32_t)(k / nb), j = (uint32_t)(k - (uint64_t)i * nb);
+                const uint32_t pa = a0 + i, pb = b0 + j;
+                if (P.core[pa] && P.core[pb])
+                    hit = within<D, WIDE>(load_pt<D>(P.spts, pa), load_pt<D>(P.spts, pb), P.eps2);
+            }
+            if (__ballot(hit)) {
+                if (l == 0) uf_union(P.parent, ca, cb);
+                return;
+            }
+        }
+        return;
+    }
+    for (uint64_t base = 0; base < total; base += kWave) {
+        const uint64_t k = base + l;
+        if (k < total) {
+            const uint32_t i = (uint32_t)(k / nb), j = (uint32_t)(k - (uint64_t)i * nb);
+            const uint32_t pa = a0 + i, pb = b0 + j;
+            if (P.core[pa] && P.core[pb] &&
+                within<D, WIDE>(load_pt<D>(P.spts, pa), load_pt<D>(P.spts, pb), P.eps2)) {
+                const uint32_t x = P.cell_of[pa], y = P.cell_of[pb];
+                if (uf_find(P.parent, x) != uf_find(P.parent, y)) uf_union(P.parent, x, y);
+            }
+        }
+    }
+}
+
+template <int D, bool WIDE>
+__global__ __launch_bounds__(kBlock) void k_merge_inter(Plan P)
+{
+    const uint32_t l = lane_id();
+    const uint32_t ng = ld_agent32(&P.ctr->n_groups);
+    const WaveRange hca_wr_ = wave_range();
+    HCA_FOR_UNITS(GA, ng) {
+        const uint32_t ga = P.gcube[GA];
+        if (ga == kNone) continue;                        // no core point
+        const bool ua = P.unified[GA];
+        const uint64_t gkey = P.group_key[GA];
+        // bounding box of GA's core points
+        const uint32_t a0 = P.group_start[GA], a1 = P.group_start[GA + 1];
+        QBox<D> qb;
+#pragma unroll
+        for (int e = 0; e < D; e++) { qb.lo[e] = INT32_MAX; qb.hi[e] = INT32_MIN; }
+        for (uint32_t q = a0 + l; q < a1 + l; q += kWave) {
+            if (q < a1 && P.core[q]) {
+                const Pt<D> p = load_pt<D>(P.spts, q);
+#pragma unroll
+                for (int e = 0; e < D; e++) { qb.lo[e] = min(qb.lo[e], p.x[e]); qb.hi[e] = max(qb.hi[e], p.x[e]); }
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < D; e++) { qb.lo[e] = wave_min(qb.lo[e]); qb.hi[e] = wave_max(qb.hi[e]); }
+        for (uint32_t oc = 1; oc < P.n_off; oc += kWave) {
+            const uint32_t j = oc + l;
+            uint32_t GB = kNone;
+            bool need = false, both = false;
+            if (j < P.n_off) {
+                const uint64_t nk = group_neighbour<D>(P, gkey, P.off + (uint64_t)j * D);
+                if (nk != ~0ull) {
+                    GB = group_lookup(P, nk);
+                    if (GB != kNone && GB > GA && P.gcube[GB] != kNone) {
+                        int64_t acc = 0;
+#pragma unroll
+                        for (int e = 0; e < D; e++) {
+                            const int64_t gc = (int64_t)((nk >> P.goff[e]) & ((1ull << P.gw[e]) - 1ull));
+                            const int64_t glo = (int64_t)P.origin[e] + gc * P.gside;
+                            const int64_t ghi = glo + P.gside - 1;
+                            int64_t gap = 0;
+                            if (glo > qb.hi[e]) gap = glo - qb.hi[e];
+                            else if ((int64_t)qb.lo[e] > ghi) gap = (int64_t)qb.lo[e] - ghi;
+                            acc += gap * gap;
+                        }
+                        if (acc <= P.eps2) {
+                            both = ua && P.unified[GB];
+                            need = !both || uf_find(P.parent, ga) != uf_find(P.parent, P.gcube[GB]);
+                        }
+                    }
+                }
+            }
+            uint64_t m = __ballot(need);
+            while (m) {
+                const uint32_t src = __ffsll((unsigned long long)m) - 1;
+                const uint32_t gb = __shfl(GB, src);
+                const bool bu = __shfl((int)both, src) != 0;
+                link_groups<D, WIDE>(P, GA, gb, bu);
+                m &= m - 1;
             }
         }
     }
@@ -419,15 +635,32 @@ __global__ __launch_bounds__(kBlock) void k_merge_group(Plan P)
 
 // ---------------------------------------------------------------------------
 // Flatten the union-find forest (every cube then points at its root; the
-// walk writes nothing, so the only stores are final roots) and reset the
-// per-root minimum member.
+// walk writes nothing, so the only stores are final roots) and fold each
+// cube's smallest core input index into its root's minimum, one atomic per
+// distinct root among a wave's 64 cubes.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_compress(Plan P)
 {
     const uint32_t nc = ld_agent32(&P.ctr->n_cells);
-    for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < nc; c += gridDim.x * kBlock) {
-        st_parent(P.parent + c, uf_root(P.parent, c));
-        st_agent32(P.minmem + c, kNone);
+    const uint32_t stride = gridDim.x * kBlock;
+    for (uint32_t base = blockIdx.x * kBlock; base < nc; base += stride) {
+        const uint32_t c = base + threadIdx.x;
+        uint32_t root = kNone, m = kNone;
+        if (c < nc) {
+            root = uf_root(P.parent, c);
+            st_parent(P.parent + c, root);
+            m = P.cmin[c];
+        }
+        uint64_t pending = __ballot(m != kNone);
+        while (pending) {
+            const uint32_t src = __ffsll((unsigned long long)pending) - 1;
+            const uint32_t rr = __shfl(root, src);
+            const bool mine = m != kNone && root == rr;
+            const uint64_t same = __ballot(mine);
+            const uint32_t mm = wave_min(mine ? m : kNone);
+            if (lane_id() == src) atomicMin(P.minmem + rr, mm);
+            pending &= ~same;
+        }
     }
 }
 
@@ -441,30 +674,28 @@ __global__ __launch_bounds__(kBlock) void k_border(Plan P)
     __shared__ uint32_t s_beg[kWavesPerBlock][kWave], s_pre[kWavesPerBlock][kWave];
     const uint32_t w = wave_in_block(), l = lane_id();
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
-    const WaveRange r = wave_range(ng);
-    for (uint32_t g = r.first; g < r.end; g += r.step) {
+    const WaveRange hca_wr_ = wave_range();
+    HCA_FOR_UNITS(g, ng) {
         const uint32_t p0 = P.group_start[g], p1 = P.group_start[g + 1];
         const uint64_t gkey = P.group_key[g];
+        if (P.m == 1 && P.ncore[g] == p1 - p0) continue;     // a cube of core points only
         for (uint32_t pc = p0; pc < p1; pc += kPch) {
             Pt<D> pp[kPch];
             uint32_t todo = 0;
             const uint32_t np = min((uint32_t)kPch, p1 - pc);
+            load_chunk<D>(P, pc, np, pp);
 #pragma unroll
-            for (int k = 0; k < kPch; k++) {
-                const uint32_t q = pc + (k < (int)np ? k : 0);
-                pp[k] = load_pt<D>(P.spts, q);
-#pragma unroll
-                for (int e = 0; e < D; e++) pp[k].x[e] = __builtin_amdgcn_readfirstlane(pp[k].x[e]);
-                if (k < (int)np && !P.core[q]) todo |= 1u << k;
-            }
+            for (int k = 0; k < kPch; k++)
+                if (k < (int)np && !P.core[pc + k]) todo |= 1u << k;
             todo = uniform(todo);
             if (!todo) continue;
+            const QBox<D> qb = chunk_box<D>(pp, todo);
             int64_t bd[kPch];
             uint32_t bi[kPch], bp[kPch];
 #pragma unroll
             for (int k = 0; k < kPch; k++) { bd[k] = INT64_MAX; bi[k] = kNone; bp[k] = kNone; }
             for (uint32_t oc = 0; oc < P.n_off; oc += kWave) {
-                const uint32_t total = load_neighbours<D>(P, gkey, oc, 0, s_beg[w], s_pre[w], nullptr);
+                const uint32_t total = load_neighbours<D>(P, gkey, oc, 0, true, qb, s_beg[w], s_pre[w]);
                 for (uint32_t ci = 0; ci < total; ci += kWave) {
                     const uint32_t c = ci + l;
                     bool ok = c < total;
@@ -476,13 +707,20 @@ __global__ __launch_bounds__(kBlock) void k_border(Plan P)
                     }
                     if (!__ballot(ok)) continue;
                     const Pt<D> q = load_pt<D>(P.spts, pos);
-                    const uint32_t qi = ok ? P.sidx[pos] : kNone;
+                    int64_t dd[kPch];
+                    bool near = false;
+#pragma unroll
+                    for (int k = 0; k < kPch; k++) {
+                        dd[k] = dist2<D, WIDE>(pp[k], q);
+                        near |= (todo & (1u << k)) && ok && dd[k] <= P.eps2 && dd[k] <= bd[k];
+                    }
+                    if (!near) continue;
+                    const uint32_t qi = P.sidx[pos];
 #pragma unroll
                     for (int k = 0; k < kPch; k++) {
                         if (!(todo & (1u << k))) continue;
-                        const int64_t dd = dist2<D, WIDE>(pp[k], q);
-                        if (ok && dd <= P.eps2 && (dd < bd[k] || (dd == bd[k] && qi < bi[k]))) {
-                            bd[k] = dd; bi[k] = qi; bp[k] = pos;
+                        if (ok && dd[k] <= P.eps2 && (dd[k] < bd[k] || (dd[k] == bd[k] && qi < bi[k]))) {
+                            bd[k] = dd[k]; bi[k] = qi; bp[k] = pos;
                         }
                     }
                 }
@@ -498,7 +736,14 @@ __global__ __launch_bounds__(kBlock) void k_border(Plan P)
                     const uint32_t i1 = __shfl_xor(i0, o), q1 = __shfl_xor(q0, o);
                     if (d1 < d0 || (d1 == d0 && i1 < i0)) { d0 = d1; i0 = i1; q0 = q1; }
                 }
-                if (l == 0) P.owner[pc + k] = q0 == kNone ? kNone : ld_parent(P.parent + P.cell_of[q0]);
+                if (l == 0) {
+                    const uint32_t root = q0 == kNone ? kNone : ld_parent(P.parent + P.cell_of[q0]);
+                    P.owner[pc + k] = root;
+                    if (root != kNone) {
+                        const uint32_t me = P.sidx[pc + k];
+                        if (me < ld_agent32(P.minmem + root)) atomicMin(P.minmem + root, me);
+                    }
+                }
             }
         }
     }
@@ -506,18 +751,17 @@ __global__ __launch_bounds__(kBlock) void k_border(Plan P)
 
 // ---------------------------------------------------------------------------
 // Canonical labels: clusters numbered by their smallest member input index.
+// Each root marks its smallest member in a bitmap over input indices; a scan
+// of the bitmap's popcounts ranks the marks; every point then takes the rank
+// of its root's mark.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_label_roots(Plan P)
+__global__ __launch_bounds__(kBlock) void k_label_marks(Plan P)
 {
-    for (uint32_t a = blockIdx.x * kBlock + threadIdx.x; a < P.n; a += gridDim.x * kBlock) {
-        const bool core = P.core[a];
-        const uint32_t root = core ? ld_parent(P.parent + P.cell_of[a]) : P.owner[a];
-        const uint32_t i = P.sidx[a];
-        P.root_in[i] = root;
-        if (root != kNone) atomicMin(P.minmem + root, i);
-        if (P.core_out) P.core_out[i] = core;
-        const uint64_t m = __ballot(core);
-        if (lane_id() == 0 && m) atomicAdd(&P.ctr->n_core, (uint32_t)__popcll(m));
+    const uint32_t nc = ld_agent32(&P.ctr->n_cells);
+    for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < nc; c += gridDim.x * kBlock) {
+        if (ld_parent(P.parent + c) != c) continue;
+        const uint32_t m = ld_agent32(P.minmem + c);
+        if (m != kNone) atomicOr(P.first + (m >> 5), 1u << (m & 31u));
     }
 }
 
@@ -525,7 +769,8 @@ __global__ __launch_bounds__(kBlock) void k_label_scan(Plan P, uint64_t *status,
 {
     __shared__ uint32_t s_red[kBlock / kWave];
     __shared__ uint32_t s_tile, s_excl;
-    const uint32_t t = threadIdx.x, n = P.n;
+    const uint32_t t = threadIdx.x;
+    const uint32_t nw = (P.n + 31u) >> 5;
     if (t == 0) s_tile = atomicAdd(ticket, 1u);
     __syncthreads();
     const uint32_t tile = s_tile, base = tile * kScanTile;
@@ -534,17 +779,15 @@ __global__ __launch_bounds__(kBlock) void k_label_scan(Plan P, uint64_t *status,
 #pragma unroll
     for (int j = 0; j < kScanItems; j++) {
         const uint32_t i = base + j * kBlock + t;
-        uint32_t v = 0;
-        if (i < n) {
-            const uint32_t root = P.root_in[i];
-            v = root != kNone && ld_agent32(P.minmem + root) == i;
-        }
-        f[j] = v;
-        local += v;
+        f[j] = i < nw ? __popc(ld_agent32(P.first + i)) : 0u;
+        local += f[j];
     }
     uint32_t agg;
     block_exclusive_scan<uint32_t>(local, s_red, &agg);
-    if (t == 0) s_excl = (uint32_t)scan_lookback(status, tile, agg);
+    if (t < kWave) {
+        const uint32_t e = (uint32_t)scan_lookback_wave(status, tile, agg);
+        if (t == 0) s_excl = e;
+    }
     __syncthreads();
     uint32_t run = s_excl;
 #pragma unroll
@@ -552,19 +795,58 @@ __global__ __launch_bounds__(kBlock) void k_label_scan(Plan P, uint64_t *status,
         uint32_t tot;
         const uint32_t e = block_exclusive_scan<uint32_t>(f[j], s_red, &tot);
         const uint32_t i = base + j * kBlock + t;
-        if (i < n && f[j]) P.rank[i] = run + e;
+        if (i < nw) P.wrank[i] = run + e;
         run += tot;
     }
-    if (t == 0 && base + kScanTile >= n) P.ctr->n_clusters = run;
+    if (t == 0 && base + kScanTile >= nw) P.ctr->n_clusters = run;
 }
 
+// Label of every cube's cluster (-1 for a cube without core points).
+__global__ __launch_bounds__(kBlock) void k_label_cubes(Plan P)
+{
+    const uint32_t nc = ld_agent32(&P.ctr->n_cells);
+    for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < nc; c += gridDim.x * kBlock) {
+        const uint32_t root = ld_parent(P.parent + c);
+        const uint32_t m = ld_agent32(P.minmem + root);
+        int32_t label = -1;
+        if (m != kNone) {
+            const uint32_t wd = m >> 5;
+            label = (int32_t)(P.wrank[wd] +
+                              __popc(ld_agent32(P.first + wd) & ((1u << (m & 31u)) - 1u)));
+        }
+        P.label_of[c] = label;
+    }
+}
+
+// Every point takes its cube's label (core) or its owner root's label (border).
 __global__ __launch_bounds__(kBlock) void k_label_write(Plan P)
 {
-    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < P.n; i += gridDim.x * kBlock) {
-        const uint32_t root = P.root_in[i];
-        P.labels[i] = root == kNone ? -1 : (int32_t)P.rank[ld_agent32(P.minmem + root)];
-        const uint64_t m = __ballot(root == kNone);
-        if (lane_id() == 0 && m) atomicAdd(&P.ctr->n_noise, (uint32_t)__popcll(m));
+    __shared__ uint32_t s_cnt[2][kWavesPerBlock];
+    uint32_t n_core = 0, n_noise = 0;
+    for (uint32_t a = blockIdx.x * kBlock + threadIdx.x; a < P.n; a += gridDim.x * kBlock) {
+        const bool core = P.core[a];
+        const uint32_t cube = core ? P.cell_of[a] : P.owner[a];
+        const uint32_t i = P.sidx[a];
+        const int32_t label = cube == kNone ? -1 : P.label_of[cube];
+        P.labels[i] = label;
+        if (P.core_out) P.core_out[i] = core;
+        n_core += core;
+        n_noise += label < 0;
+    }
+    if (!P.want_stats) return;
+    // one atomic per block and counter
+    n_core = wave_sum(n_core);
+    n_noise = wave_sum(n_noise);
+    if (lane_id() == 0) {
+        s_cnt[0][wave_in_block()] = n_core;
+        s_cnt[1][wave_in_block()] = n_noise;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t c = 0, z = 0;
+        for (int i = 0; i < kWavesPerBlock; i++) { c += s_cnt[0][i]; z += s_cnt[1][i]; }
+        if (c) atomicAdd(&P.ctr->n_core, c);
+        if (z) atomicAdd(&P.ctr->n_noise, z);
     }
 }
 
@@ -627,7 +909,8 @@ void launch_merge(const Plan &P, int blocks, hipStream_t s)
         HCA_DISPATCH_DW(k_merge_rep, P, blocks, s);
         HCA_DISPATCH_DW(k_merge_exact, P, blocks, s);
     } else {
-        HCA_DISPATCH_DW(k_merge_group, P, blocks, s);
+        HCA_DISPATCH_DW(k_merge_intra, P, blocks, s);
+        HCA_DISPATCH_DW(k_merge_inter, P, blocks, s);
     }
 }
 
@@ -643,10 +926,13 @@ void launch_border(const Plan &P, int blocks, hipStream_t s)
 
 void launch_labels(const Plan &P, uint64_t *status, uint32_t *ticket, hipStream_t s)
 {
-    const int blocks = (int)std::min<uint64_t>((P.n + kBlock - 1) / kBlock, 4096);
-    hipLaunchKernelGGL(k_label_roots, dim3(blocks), dim3(kBlock), 0, s, P);
-    const uint32_t tiles = (P.n + kScanTile - 1) / kScanTile;
+    const int cb = (int)std::min<uint64_t>((P.n + kBlock - 1) / kBlock, 1024);
+    hipLaunchKernelGGL(k_label_marks, dim3(cb), dim3(kBlock), 0, s, P);
+    const uint32_t nw = (P.n + 31u) >> 5;
+    const uint32_t tiles = (nw + kScanTile - 1) / kScanTile;
     hipLaunchKernelGGL(k_label_scan, dim3(tiles), dim3(kBlock), 0, s, P, status, ticket);
+    hipLaunchKernelGGL(k_label_cubes, dim3(cb), dim3(kBlock), 0, s, P);
+    const int blocks = (int)std::min<uint64_t>((P.n + kBlock - 1) / kBlock, 4096);
     hipLaunchKernelGGL(k_label_write, dim3(blocks), dim3(kBlock), 0, s, P);
 }
 

@@ -27,11 +27,17 @@ constexpr uint64_t kFlagAgg = 1ull << 62;
 constexpr uint64_t kFlagInc = 2ull << 62;
 constexpr uint64_t kValMask = (1ull << 62) - 1;
 
+// The exact-test worklist is split into kWorkRegions regions, each with its
+// own counter on its own 64-byte line, so that appends from many waves do not
+// all contend for one address.
+constexpr int kWorkRegions = 64;
+constexpr int kCounterStride = 16;   // uint32 words per 64-byte line
+
 // Counters kept on the device for one call (zeroed before each call).
 struct Counters {
     uint32_t n_cells;
     uint32_t n_groups;
-    uint32_t worklist;          // cube pairs waiting for an exact test
+    uint32_t worklist;          // unused (see work_count)
     uint32_t bbox_done;         // blocks of the bounding-box kernel finished
     uint32_t sort_tickets[8];   // tile tickets, one per radix pass
     uint32_t scan_tickets[4];   // tile tickets of the device-wide scans
@@ -39,6 +45,7 @@ struct Counters {
     uint32_t n_noise;
     uint32_t n_clusters;
     uint32_t pad[13];
+    uint32_t work_count[kWorkRegions * kCounterStride];   // region r at [r * kCounterStride]
 };
 
 struct Plan {
@@ -54,6 +61,7 @@ struct Plan {
     int32_t origin[kMaxDim];
     uint32_t side;
     uint32_t m;
+    int64_t gside;              // group side m * s
     uint32_t bm;
     uint32_t fine_bits;         // d * bm
     uint32_t goff[kMaxDim];     // bit offset of group coordinate k in the group key
@@ -87,14 +95,19 @@ struct Plan {
     uint64_t *hkeys;            // hash: keys [cap]
     uint8_t *core;              // [n] sorted order
     uint32_t *ncore;            // [n] cube -> core points
-    uint32_t *rep;              // [cells][n_dir] sorted positions
+    uint64_t *rep;              // [cells][n_dir] (score << 32 | sorted position), min wins
     uint32_t *parent;           // [n] union-find over cubes
+    uint32_t *gcube;            // [n] group -> first cube with a core point, kNone if none
+    uint8_t *unified;           // [n] group -> its core cubes share one union-find root
     uint32_t *work;             // [2 * work_cap] cube pairs for exact tests
-    uint32_t work_cap;
+    uint32_t work_cap;          // multiple of kWorkRegions
+    uint32_t want_stats;        // count core and noise points
     uint32_t *owner;            // [n] sorted position -> root cube (border), kNone
+    uint32_t *cmin;             // [n] cube -> smallest input index of its core points, kNone
     uint32_t *minmem;           // [n] root cube -> smallest member input index
-    uint32_t *root_in;          // [n] input index -> root cube or kNone
-    uint32_t *rank;             // [n] input index -> exclusive count of first members
+    uint32_t *first;            // [ceil(n/32)] bitmap: input index is its cluster's smallest member
+    uint32_t *wrank;            // [ceil(n/32)] first members before each bitmap word
+    int32_t *label_of;          // [n] cube -> canonical label of its cluster, -1 if none
     uint64_t *scan_status;      // look-back words for the device-wide scans
     Counters *ctr;
     uint8_t *core_out;          // optional [n] input order

@@ -254,7 +254,10 @@ __global__ __launch_bounds__(kBlock) void k_cells(Plan P, uint64_t *__restrict__
     }
     uint64_t agg;
     block_exclusive_scan<uint64_t>(local, s_red, &agg);
-    if (t == 0) s_excl = scan_lookback(status, tile, agg);
+    if (t < kWave) {
+        const uint64_t e = scan_lookback_wave(status, tile, agg);
+        if (t == 0) s_excl = e;
+    }
     __syncthreads();
     uint64_t run = s_excl;
     const uint64_t lo_mask = (1ull << 31) - 1;
@@ -270,6 +273,8 @@ __global__ __launch_bounds__(kBlock) void k_cells(Plan P, uint64_t *__restrict__
             if (v[j] & 1u) {
                 P.cell_start[cell] = idx;
                 st_parent(P.parent + cell, cell);
+                st_agent32(P.minmem + cell, kNone);
+                for (uint32_t t = 0; t < P.n_dir; t++) st_agent(P.rep + (uint64_t)cell * P.n_dir + t, ~0ull);
             }
             if (v[j] >> 31) {
                 const uint32_t g = (uint32_t)(inc >> 31) - 1u;
@@ -318,7 +323,8 @@ void launch_bbox(int d, const int32_t *pts, uint32_t n, int32_t *partial, int bl
 template <int D, typename K>
 static void sort_d(const Plan &P, const SortBuffers &B, hipStream_t s)
 {
-    const int hb = (int)std::min<uint64_t>((P.n + kBlock - 1) / kBlock, 2048);
+    // few blocks: each flushes its LDS histogram with one global atomic per bin
+    const int hb = (int)std::min<uint64_t>((P.n + kBlock * 16 - 1) / (kBlock * 16), 256);
     K *ka = (K *)B.keys_a, *kb = (K *)B.keys_b;
     uint32_t *va = B.vals_a, *vb = B.vals_b;
     hipLaunchKernelGGL((k_keys_hist<D, K>), dim3(hb), dim3(kBlock), 0, s, P, ka, va, B.hist);
