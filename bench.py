@@ -10,6 +10,7 @@ timed beside it as a reported baseline.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import statistics
@@ -22,28 +23,56 @@ sys.path.insert(0, str(ROOT))
 
 METRIC = "points clustered/s (2-D 1M, 8-D 500k) vs HBM roofline; served p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-ALU_PEAK_TOPS = 39.3          # 256 CUs x 64 lanes x 2.4 GHz, int32 lane-ops per second
+# int32 VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 lane-ops/s
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 WORKLOADS = {"2d": 2, "8d": 3, "small": 1}
+HBM_PHASES = ("bbox", "sort", "cells", "labels")
+ALU_PHASES = {"core": "tests_core", "merge": "tests_merge", "border": "tests_border"}
 
 
 def algorithmic_bytes(phase: str, n: int, d: int, key_bytes: int, passes: int, cells: int) -> float:
-    """Bytes the method must move in a phase (per call), independent of how
-    the kernels happen to move them."""
+    """Bytes the method must move in a phase per call, independent of how the
+    kernels happen to move them (per-point figures x n)."""
     if phase == "bbox":
-        return 4.0 * d * n
+        return 4.0 * d * n                                   # read the points
     if phase == "sort":
         kv = key_bytes + 4
-        # keys: read points, write (key, index); P passes read and write
-        # (key, index); last pass gathers the points into cube order
+        # keys: read points, write (key, index); each pass reads and writes
+        # (key, index); the last pass gathers the points into cube order
         return n * (4.0 * d + kv + 2.0 * passes * kv + 8.0 * d)
     if phase == "cells":
-        return n * (key_bytes + 4.0) + cells * 16.0
+        return n * (key_bytes + 4.0) + cells * 16.0           # read keys, write cube ids + tables
     if phase == "labels":
-        return n * 45.0
+        # core flag, cube or owner, sorted index read; label written; + per cube
+        return n * (1.0 + 4.0 + 4.0 + 4.0) + cells * 16.0
     return 0.0
 
 
-def cpu_baseline(w, budget_s: float = 20.0) -> dict:
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for f in sorted((ROOT / "paper_1912_00323_amd" / "csrc").glob("*.*")):
+        if f.suffix in (".hip", ".h", ".cpp"):
+            h.update(f.read_bytes())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from a committed rocprofv3 PMC summary, if it was
+    taken on the current kernel sources; else None."""
+    f = ROOT / "profiles" / "pmc_traffic.json"
+    if not f.exists():
+        return None
+    try:
+        data = json.loads(f.read_text())
+    except ValueError:
+        return None
+    e = data.get("entries", {}).get(f"{workload}:{kernel}")
+    if not e or e.get("source_digest") != kernel_source_digest():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(w, budget_s: float = 25.0) -> dict:
     import oracle
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     times = []
@@ -54,9 +83,9 @@ def cpu_baseline(w, budget_s: float = 20.0) -> dict:
         times.append(time.perf_counter() - t0)
     t = statistics.median(times)
     return {"value": w.n / t, "unit": "points/s", "cores": threads, "kind": "oracle",
-            "sample": f"whole {w.name} workload, paper's hypercube method on the CPU "
-                      f"(oracle/hca_grid.c, OpenMP over points, sequential merge), "
-                      f"median of {len(times)} runs"}
+            "sample": f"the whole {w.name} workload (n={w.n}), the paper's hypercube method on "
+                      f"the CPU (oracle/hca_grid.c: OpenMP over points for core marking and "
+                      f"borders, sequential depth-first merge), median of {len(times)} run(s)"}
 
 
 def main() -> int:
@@ -69,7 +98,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU form of "
-              f"this path is a design in DESIGN.md, not a measured mode", file=sys.stderr)
+              f"this path is a design, not a measured mode", file=sys.stderr)
         return 2
 
     import torch
@@ -88,7 +117,7 @@ def main() -> int:
         ctx.cluster(pts, w.eps, w.min_pts, out=labels)
     _, stats = ctx.cluster(pts, w.eps, w.min_pts, out=labels, stats=True)
 
-    # timed region: K whole clustering calls
+    # timed region: K whole clustering calls, inputs resident in HBM
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -97,23 +126,42 @@ def main() -> int:
     dt = time.perf_counter() - t0
     ms_per_step = dt * 1e3 / args.steps
 
-    # per-phase durations: HIP events on the library's stream around each phase
+    # per-phase durations from HIP events the library records on its own
+    # stream around each phase, and pair-test counts, over K more calls
     ctx.set_profiling("all")
     acc = {p: [] for p in hca.PHASES}
+    tests = {k: [] for k in ALU_PHASES.values()}
     for _ in range(args.steps):
-        ctx.cluster(pts, w.eps, w.min_pts, out=labels)
+        _, st = ctx.cluster(pts, w.eps, w.min_pts, out=labels, stats=True)
         for p, v in ctx.phase_times().items():
             acc[p].append(v)
+        for k in tests:
+            tests[k].append(st[k])
     ctx.set_profiling(None)
     phase_ms = {p: statistics.mean(v) for p, v in acc.items()}
     key_bytes = 8 if stats["key_bits"] > 32 else 4
+
+    def hbm_roofline(phase):
+        ab = algorithmic_bytes(phase, w.n, w.d, key_bytes, stats["sort_passes"], stats["n_cells"])
+        achieved = ab / (phase_ms[phase] * 1e-3) / 1e9
+        return {"bound": "hbm", "phase": phase, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(phase, w.name), "algorithmic_bytes": ab}
+
+    def alu_roofline(phase):
+        n_tests = statistics.mean(tests[ALU_PHASES[phase]])
+        ops = 3.0 * w.d * n_tests                        # d sub + d mul + d-1 add + compare
+        achieved = ops / (phase_ms[phase] * 1e-3) / 1e12
+        return {"bound": "alu", "phase": phase, "achieved": round(achieved, 4), "peak": round(ALU_PEAK_TOPS, 2),
+                "unit": "Tops/s (int32 lane-ops)", "frac": round(achieved / ALU_PEAK_TOPS, 5),
+                "traffic": measured_traffic(phase, w.name), "pair_tests": n_tests,
+                "ops_per_test": 3 * w.d}
+
     dominant = max(phase_ms, key=phase_ms.get)
-    hbm_phase = max((p for p in ("sort", "cells", "labels", "bbox")), key=phase_ms.get)
-    ab = algorithmic_bytes(hbm_phase, w.n, w.d, key_bytes, stats["sort_passes"], stats["n_cells"])
-    achieved = ab / (phase_ms[hbm_phase] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": hbm_phase, "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None}
+    roofline = alu_roofline(dominant) if dominant in ALU_PHASES else (
+        hbm_roofline(dominant) if dominant in HBM_PHASES else
+        {"bound": "alu", "phase": dominant, "achieved": None, "peak": round(ALU_PEAK_TOPS, 2),
+         "unit": "Tops/s (int32 lane-ops)", "frac": None, "traffic": None})
 
     line = {
         "metric": METRIC,
@@ -131,8 +179,8 @@ def main() -> int:
         "config": {"workload": w.name, "n": w.n, "d": w.d, "eps": w.eps, "min_pts": w.min_pts,
                    "fixed_point_bits": w.q, "parallelism": "single-gpu"},
         "roofline": roofline,
+        "roofline_binning_sort": hbm_roofline("sort"),
         "phase_ms": {p: round(v, 4) for p, v in phase_ms.items()},
-        "dominant_phase": dominant,
         "stats": stats,
     }
     if not args.no_cpu_baseline:

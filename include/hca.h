@@ -91,6 +91,12 @@ typedef struct {
     int32_t wide;             /* 1 if squared distances were computed in 64 bits */
     int32_t dense_table;      /* 1 if the group lookup was a direct-indexed table */
     int32_t reserved;
+    /* point-pair distance tests executed by core marking, merging and border
+     * assignment; counted only while phase profiling is on (hca_set_profiling),
+     * else 0 */
+    int64_t tests_core;
+    int64_t tests_merge;
+    int64_t tests_border;
 } hca_stats;
 
 /* Exact floor(eps^2) of a double (no device needed).  HCA_E_INVAL if eps is

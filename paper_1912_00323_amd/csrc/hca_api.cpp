@@ -464,6 +464,9 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
     const uint32_t scan_tiles = (n + kScanTile - 1) / kScanTile;
     P.work_cap = (uint32_t)std::min<uint64_t>(4ull * n + 1024, 1ull << 30) / kWorkRegions * kWorkRegions;
     P.want_stats = stats != nullptr;
+    // neighbour-group lists in group mode: room for 64 entries per point
+    P.nbr_cap = P.m > 1 ? (uint32_t)std::min<uint64_t>(64ull * n, 1ull << 31) : 0;
+    P.count_work = stats != nullptr && ctx->prof != -1;
 
     // 3. workspace
     auto carve = [&](Carver &cv, SortBuffers &B, uint32_t **zero_begin, size_t *zero_bytes) {
@@ -485,6 +488,12 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
         P.parent = cv.take<uint32_t>(n);
         P.gcube = cv.take<uint32_t>(n);
         P.unified = cv.take<uint8_t>(n);
+        P.tile_start = cv.take<uint32_t>(n);
+        if (P.nbr_cap) {
+            P.nbr_count = cv.take<uint32_t>(n);
+            P.nbr_start = cv.take<uint32_t>(n);
+            P.nbr = cv.take<uint32_t>(P.nbr_cap);
+        }
         P.work = cv.take<uint32_t>((size_t)2 * P.work_cap);
         P.owner = cv.take<uint32_t>(n);
         P.cmin = cv.take<uint32_t>(n);
@@ -498,15 +507,19 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
         B.status = cv.take<uint64_t>((size_t)P.passes * sort_tiles * kRadix);
         P.scan_status = cv.take<uint64_t>((size_t)2 * scan_tiles + 64);
         P.first = cv.take<uint32_t>(((size_t)n + 31) / 32);
+        P.tile_status = cv.take<uint64_t>((size_t)scan_tiles + 64);
+        P.nbr_status = cv.take<uint64_t>((size_t)scan_tiles + 64);
         *zero_bytes = cv.off - zstart;
         *zero_begin = (uint32_t *)(cv.base ? cv.base + zstart : nullptr);
         // lookup table, filled with all-ones
         if (P.dense) {
             P.table = cv.take<uint32_t>((size_t)1 << gbits);
             P.hkeys = nullptr;
+            P.hkeys_read = nullptr;
         } else {
             P.table = cv.take<uint32_t>(hcap);
             P.hkeys = cv.take<uint64_t>(hcap);
+            P.hkeys_read = cv.take<uint64_t>(hcap);
         }
     };
     SortBuffers B;
@@ -527,8 +540,9 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
     P.labels = labels;
     P.core_out = core_out;
 
-    launch_init(zbeg, zbytes / sizeof(uint32_t), P.dense ? nullptr : P.hkeys, P.dense ? 0 : hcap,
-                P.dense ? P.table : nullptr, P.dense ? (1ull << gbits) : 0, s);
+    launch_init(zbeg, zbytes / sizeof(uint32_t), P.dense ? nullptr : P.hkeys,
+                P.dense ? nullptr : P.hkeys_read, P.dense ? 0 : hcap, P.dense ? P.table : nullptr,
+                P.dense ? (1ull << gbits) : 0, s);
 
     // 4. cube keys and stable radix sort (points gathered in the last pass)
     mark(ctx, HCA_PHASE_SORT, false);
@@ -542,12 +556,13 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
     const int tb = (int)std::min<uint64_t>((n + kBlock - 1) / kBlock, 1024);
     launch_table(P, tb, s);
     mark(ctx, HCA_PHASE_CELLS, true);
+    mark(ctx, HCA_PHASE_CORE, false);
     // 6. core points, representatives, merging, border points, labels
     int persist = kPersistBlocks;
     if (const char *e = std::getenv("HCA_WAVE_BLOCKS")) persist = std::max(8, std::atoi(e));
     const int pb = (int)std::min<uint64_t>(persist, ((uint64_t)n + kBlock - 1) / kBlock * 4 + 8) & ~7;
     const int wb = std::max(8, pb);
-    mark(ctx, HCA_PHASE_CORE, false);
+    launch_lists(P, wb, s);
     launch_core(P, wb, s);
     mark(ctx, HCA_PHASE_CORE, true);
     mark(ctx, HCA_PHASE_REPS, false);
@@ -583,6 +598,11 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
         stats->n_core_points = hc->n_core;
         stats->n_noise = hc->n_noise;
         stats->n_clusters = hc->n_clusters;
+        for (int ph = 0; ph < 3; ph++) {
+            int64_t t = 0;
+            for (int r = 0; r < kWorkRegions; r++) t += (int64_t)hc->tests[ph][r * 8];
+            (ph == 0 ? stats->tests_core : ph == 1 ? stats->tests_merge : stats->tests_border) = t;
+        }
         stats->key_bits = (int32_t)P.key_bits;
         stats->sort_passes = (int32_t)P.passes;
         stats->group = (int32_t)P.m;

@@ -134,6 +134,16 @@ __device__ __forceinline__ WaveRange wave_range()
     for (uint32_t k_ = hca_wr_.first, u = hca_wr_.unit(k_); u < (units);                \
          k_ += hca_wr_.step, u = hca_wr_.unit(k_))
 
+// ---- work counters ----------------------------------------------------------
+// Pair tests a lane executed; one atomic per wave, spread over many lines.
+__device__ __forceinline__ void flush_tests(const Plan &P, int which, uint32_t lane_tests)
+{
+    if (!P.count_work) return;
+    const uint64_t t = wave_sum((uint64_t)lane_tests);
+    const uint32_t region = (blockIdx.x * (kBlock / kWave) + wave_in_block()) % kWorkRegions;
+    if (lane_id() == 0 && t) atomicAdd(&P.ctr->tests[which][region * 8], (unsigned long long)t);
+}
+
 // ---- points ----------------------------------------------------------------
 template <int D>
 struct Pt {
@@ -243,7 +253,7 @@ __device__ __forceinline__ uint32_t group_lookup(const Plan &P, uint64_t gkey)
     if (P.dense) return P.table[gkey];
     uint64_t h = mix64(gkey) & P.hash_mask;
     while (true) {
-        const uint64_t k = ld_agent(P.hkeys + h);
+        const uint64_t k = P.hkeys_read[h];
         if (k == gkey) return P.table[h];
         if (k == ~0ull) return kNone;
         h = (h + 1) & P.hash_mask;

@@ -41,16 +41,74 @@ __device__ __forceinline__ QBox<D> chunk_box(const Pt<D> *pp, uint32_t mask)
     return b;
 }
 
+// Can the group with key nk hold a point within eps of the query box q?
+// (closest approach of the group's box to q, from the key alone)
+template <int D>
+__device__ __forceinline__ bool group_box_within(const Plan &P, uint64_t nk, const QBox<D> &q)
+{
+    int64_t acc = 0;
+#pragma unroll
+    for (int e = 0; e < D; e++) {
+        const int64_t gc = (int64_t)((nk >> P.goff[e]) & ((1ull << P.gw[e]) - 1ull));
+        const int64_t glo = (int64_t)P.origin[e] + gc * P.gside;
+        const int64_t ghi = glo + P.gside - 1;
+        int64_t gap = 0;
+        if (glo > q.hi[e]) gap = glo - q.hi[e];
+        else if ((int64_t)q.lo[e] > ghi) gap = (int64_t)q.lo[e] - ghi;
+        acc += gap * gap;
+    }
+    return acc <= P.eps2;
+}
+
 // ---------------------------------------------------------------------------
-// Candidate lists: the points of the neighbour groups at offsets
-// [first, first + 64), laid out one after the other.  Lane l resolves offset
+// Where a group's neighbour groups come from: the precomputed list (group
+// mode, when it fit) or the offset stencil.  Slot 0 is always the group
+// itself.
+// ---------------------------------------------------------------------------
+struct NbrSrc {
+    uint32_t lists, start, slots;
+};
+
+__device__ __forceinline__ bool lists_ready(const Plan &P)
+{
+    return P.nbr_cap && ld_agent32(&P.ctr->n_nbr) <= P.nbr_cap;
+}
+
+__device__ __forceinline__ NbrSrc nbr_source(const Plan &P, uint32_t g, bool lists)
+{
+    NbrSrc src;
+    src.lists = lists;
+    src.start = lists ? P.nbr_start[g] : 0;
+    src.slots = lists ? P.nbr_count[g] + 1 : P.n_off;
+    return src;
+}
+
+// Group at slot j (or kNone), with its key in *nk.
+template <int D>
+__device__ __forceinline__ uint32_t slot_group(const Plan &P, uint32_t g, uint64_t gkey, const NbrSrc &src,
+                                               uint32_t j, uint64_t *nk)
+{
+    if (src.lists) {
+        const uint32_t G = j == 0 ? g : P.nbr[src.start + j - 1];
+        *nk = P.group_key[G];
+        return G;
+    }
+    *nk = group_neighbour<D>(P, gkey, P.off + (uint64_t)j * D);
+    return *nk == ~0ull ? kNone : group_lookup(P, *nk);
+}
+
+// ---------------------------------------------------------------------------
+// Candidate lists: the points of the neighbour groups in slots
+// [first, first + 64), laid out one after the other.  Lane l resolves slot
 // first + l; its point range starts at s_beg[l] and its first candidate index
 // is s_pre[l].  A group is dropped when its id is below `lowest`, when its box
-// is farther than eps from the query box q, or (need_core, m == 1) when its
-// cube has no core point.  Returns the number of candidates in the chunk.
+// is farther than eps from the query box q (tested before the lookup on the
+// stencil path), or (need_core, m == 1) when its cube has no core point.
+// Returns the number of candidates in the chunk.
 // ---------------------------------------------------------------------------
 template <int D>
-__device__ __forceinline__ uint32_t load_neighbours(const Plan &P, uint64_t gkey, uint32_t first,
+__device__ __forceinline__ uint32_t load_neighbours(const Plan &P, uint32_t g, uint64_t gkey,
+                                                    const NbrSrc &src, uint32_t first,
                                                     uint32_t lowest, bool need_core,
                                                     const QBox<D> &q, uint32_t *s_beg,
                                                     uint32_t *s_pre)
@@ -58,28 +116,19 @@ __device__ __forceinline__ uint32_t load_neighbours(const Plan &P, uint64_t gkey
     const uint32_t l = lane_id();
     const uint32_t j = first + l;
     uint32_t a = 0, size = 0;
-    if (j < P.n_off) {
-        const uint64_t nk = group_neighbour<D>(P, gkey, P.off + (uint64_t)j * D);
-        if (nk != ~0ull) {
-            const uint32_t G = group_lookup(P, nk);
-            if (G != kNone && G >= lowest && !(need_core && P.m == 1 && P.ncore[G] == 0)) {
-                // closest approach of the group's box to the query box
-                int64_t acc = 0;
-#pragma unroll
-                for (int e = 0; e < D; e++) {
-                    const int64_t gc = (int64_t)((nk >> P.goff[e]) & ((1ull << P.gw[e]) - 1ull));
-                    const int64_t glo = (int64_t)P.origin[e] + gc * P.gside;
-                    const int64_t ghi = glo + P.gside - 1;
-                    int64_t gap = 0;
-                    if (glo > q.hi[e]) gap = glo - q.hi[e];
-                    else if ((int64_t)q.lo[e] > ghi) gap = (int64_t)q.lo[e] - ghi;
-                    acc += gap * gap;
-                }
-                if (acc <= P.eps2) {
-                    a = P.group_start[G];
-                    size = P.group_start[G + 1] - a;
-                }
-            }
+    if (j < src.slots) {
+        uint32_t G = kNone;
+        if (src.lists) {
+            uint64_t nk;
+            G = slot_group<D>(P, g, gkey, src, j, &nk);
+            if (!group_box_within<D>(P, nk, q)) G = kNone;
+        } else {
+            const uint64_t nk = group_neighbour<D>(P, gkey, P.off + (uint64_t)j * D);
+            if (nk != ~0ull && group_box_within<D>(P, nk, q)) G = group_lookup(P, nk);
+        }
+        if (G != kNone && G >= lowest && !(need_core && P.m == 1 && P.ncore[G] == 0)) {
+            a = P.group_start[G];
+            size = P.group_start[G + 1] - a;
         }
     }
     const uint32_t inc = wave_inclusive_scan(size);
@@ -121,12 +170,16 @@ __device__ __forceinline__ void load_chunk(const Plan &P, uint32_t pc, uint32_t 
 // ones) with plain stores.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_init(uint32_t *zero, uint64_t zero_words, uint64_t *hkeys,
-                                                 uint64_t hcap, uint32_t *table, uint64_t tsize)
+                                                 uint64_t *hkeys_read, uint64_t hcap, uint32_t *table,
+                                                 uint64_t tsize)
 {
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     const uint64_t i0 = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     for (uint64_t i = i0; i < zero_words; i += stride) st_agent32(zero + i, 0u);
-    for (uint64_t i = i0; i < hcap; i += stride) st_agent(hkeys + i, ~0ull);
+    for (uint64_t i = i0; i < hcap; i += stride) {
+        st_agent(hkeys + i, ~0ull);
+        hkeys_read[i] = ~0ull;
+    }
     for (uint64_t i = i0; i < tsize; i += stride) table[i] = kNone;
 }
 
@@ -148,11 +201,101 @@ __global__ __launch_bounds__(kBlock) void k_table(Plan P)
             const uint64_t prev = atomicCAS((unsigned long long *)(P.hkeys + h), ~0ull, key);
             if (prev == ~0ull || prev == key) {
                 P.table[h] = g;
+                P.hkeys_read[h] = key;      // the slot's only writer
                 break;
             }
             h = (h + 1) & P.hash_mask;
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Neighbour-group lists (group mode): every group at a stencil offset that
+// exists and whose box comes within eps of the group's own points, nearest
+// offsets first.  Built once per call by a counting pass, a scan and a fill
+// pass, then walked by core marking, merging and border assignment.
+// ---------------------------------------------------------------------------
+template <int D>
+__device__ __forceinline__ QBox<D> group_points_box(const Plan &P, uint32_t p0, uint32_t p1)
+{
+    const uint32_t l = lane_id();
+    QBox<D> b;
+#pragma unroll
+    for (int e = 0; e < D; e++) { b.lo[e] = INT32_MAX; b.hi[e] = INT32_MIN; }
+    for (uint32_t q = p0 + l; q < p1 + l; q += kWave) {
+        if (q < p1) {
+            const Pt<D> p = load_pt<D>(P.spts, q);
+#pragma unroll
+            for (int e = 0; e < D; e++) { b.lo[e] = min(b.lo[e], p.x[e]); b.hi[e] = max(b.hi[e], p.x[e]); }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < D; e++) { b.lo[e] = wave_min(b.lo[e]); b.hi[e] = wave_max(b.hi[e]); }
+    return b;
+}
+
+template <int D, bool FILL>
+__global__ __launch_bounds__(kBlock) void k_nbr_lists(Plan P)
+{
+    const uint32_t l = lane_id();
+    const uint32_t ng = ld_agent32(&P.ctr->n_groups);
+    if (FILL && ld_agent32(&P.ctr->n_nbr) > P.nbr_cap) return;     // lists do not fit
+    const WaveRange hca_wr_ = wave_range();
+    HCA_FOR_UNITS(g, ng) {
+        const uint64_t gkey = P.group_key[g];
+        const QBox<D> qb = group_points_box<D>(P, P.group_start[g], P.group_start[g + 1]);
+        uint32_t at = FILL ? P.nbr_start[g] : 0, count = 0;
+        for (uint32_t oc = 1; oc < P.n_off; oc += kWave) {
+            const uint32_t j = oc + l;
+            uint32_t G = kNone;
+            if (j < P.n_off) {
+                const uint64_t nk = group_neighbour<D>(P, gkey, P.off + (uint64_t)j * D);
+                if (nk != ~0ull && group_box_within<D>(P, nk, qb)) G = group_lookup(P, nk);
+            }
+            const uint64_t m = __ballot(G != kNone);
+            if (FILL && G != kNone) P.nbr[at + __popcll(m & __lanemask_lt())] = G;
+            at += __popcll(m);
+            count += __popcll(m);
+        }
+        if (!FILL && l == 0) P.nbr_count[g] = count;
+    }
+}
+
+// Exclusive prefix of nbr_count over the groups; the total goes to n_nbr.
+__global__ __launch_bounds__(kBlock) void k_nbr_scan(Plan P, uint64_t *status, uint32_t *ticket)
+{
+    __shared__ uint32_t s_red[kBlock / kWave];
+    __shared__ uint32_t s_tile, s_excl;
+    const uint32_t t = threadIdx.x;
+    const uint32_t ng = ld_agent32(&P.ctr->n_groups);
+    if (t == 0) s_tile = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile, base = tile * kScanTile;
+    uint32_t f[kScanItems];
+    uint32_t local = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; j++) {
+        const uint32_t g = base + j * kBlock + t;
+        f[j] = g < ng ? P.nbr_count[g] : 0u;
+        local += f[j];
+    }
+    uint32_t agg;
+    block_exclusive_scan<uint32_t>(local, s_red, &agg);
+    if (t < kWave) {
+        const uint32_t e = (uint32_t)scan_lookback_wave(status, tile, agg);
+        if (t == 0) s_excl = e;
+    }
+    __syncthreads();
+    uint32_t run = s_excl;
+#pragma unroll
+    for (int j = 0; j < kScanItems; j++) {
+        uint32_t tot;
+        const uint32_t e = block_exclusive_scan<uint32_t>(f[j], s_red, &tot);
+        const uint32_t g = base + j * kBlock + t;
+        if (g < ng) P.nbr_start[g] = run + e;
+        run += tot;
+    }
+    if (t == 0 && base + kScanTile >= ng) st_agent32(&P.ctr->n_nbr, run);
 }
 
 // ---------------------------------------------------------------------------
@@ -171,6 +314,8 @@ __global__ __launch_bounds__(kBlock) void k_core(Plan P)
     const uint32_t w = wave_in_block(), l = lane_id();
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
     const uint32_t minpts = (uint32_t)P.min_pts;
+    const bool lists = lists_ready(P);
+    uint32_t lt = 0;
     const WaveRange hca_wr_ = wave_range();
     HCA_FOR_UNITS(g, ng) {
         const uint32_t p0 = P.group_start[g], p1 = P.group_start[g + 1];
@@ -209,9 +354,10 @@ __global__ __launch_bounds__(kBlock) void k_core(Plan P)
             const uint32_t all = (1u << kPch) - 1u;
             if (done != all) {
                 const QBox<D> qb = chunk_box<D>(pp, ~done);
-                for (uint32_t oc = 0; oc < P.n_off && done != all; oc += kWave) {
+                const NbrSrc src = nbr_source(P, g, lists);
+                for (uint32_t oc = 0; oc < src.slots && done != all; oc += kWave) {
                     const uint32_t total =
-                        load_neighbours<D>(P, gkey, oc, 0, false, qb, s_beg[w], s_pre[w]);
+                        load_neighbours<D>(P, g, gkey, src, oc, 0, false, qb, s_beg[w], s_pre[w]);
                     for (uint32_t ci = 0; ci < total && done != all; ci += kWave) {
                         const uint32_t c = ci + l;
                         const bool ok = c < total;
@@ -224,6 +370,7 @@ __global__ __launch_bounds__(kBlock) void k_core(Plan P)
 #pragma unroll
                         for (int k = 0; k < kPch; k++) {
                             if (done & (1u << k)) continue;
+                            lt += ok;
                             const bool hit = ok && within<D, WIDE>(pp[k], q, P.eps2);
                             cnt[k] += __popcll(__ballot(hit));
                             if (cnt[k] >= minpts) done |= 1u << k;
@@ -270,6 +417,7 @@ __global__ __launch_bounds__(kBlock) void k_core(Plan P)
             P.cmin[tally_cell] = tally_min;
         }
     }
+    flush_tests(P, kTestsCore, lt);
 }
 
 // ---------------------------------------------------------------------------
@@ -349,12 +497,13 @@ __global__ __launch_bounds__(kBlock) void k_reps(Plan P)
 // core pairs (merging on representatives alone can miss a pair within eps).
 // ---------------------------------------------------------------------------
 template <int D, bool WIDE>
-__device__ void exact_pair(const Plan &P, uint32_t A, uint32_t B);
+__device__ void exact_pair(const Plan &P, uint32_t A, uint32_t B, uint32_t &lt);
 
 template <int D, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_merge_rep(Plan P)
 {
     const uint32_t l = lane_id();
+    uint32_t lt = 0;
     const uint32_t nc = ld_agent32(&P.ctr->n_cells);
     const WaveRange hca_wr_ = wave_range();
     HCA_FOR_UNITS(A, nc) {
@@ -373,6 +522,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_rep(Plan P)
             if (todo && P.n_dir) {
                 const uint32_t qa = (uint32_t)ld_agent(P.rep + (uint64_t)A * P.n_dir + P.dir_fwd[j]);
                 const uint32_t qb = (uint32_t)ld_agent(P.rep + (uint64_t)B * P.n_dir + P.dir_bwd[j]);
+                lt++;
                 joined = within<D, WIDE>(load_pt<D>(P.spts, qa), load_pt<D>(P.spts, qb), P.eps2);
                 if (joined) uf_union(P.parent, A, B);
             }
@@ -397,19 +547,20 @@ __global__ __launch_bounds__(kBlock) void k_merge_rep(Plan P)
                 uint64_t sm = __ballot(spill);
                 while (sm) {
                     const uint32_t src = __ffsll((unsigned long long)sm) - 1;
-                    exact_pair<D, WIDE>(P, A, __shfl(B, src));
+                    exact_pair<D, WIDE>(P, A, __shfl(B, src), lt);
                     sm &= sm - 1;
                 }
             }
         }
     }
+    flush_tests(P, kTestsMerge, lt);
 }
 
 // Exact test of cube pair (A, B) by one wave: all core pairs in tiles of 64
 // lanes, stopping at the first pair within eps (wavefront ballot) or when
 // the two cubes have meanwhile been merged through other pairs.
 template <int D, bool WIDE>
-__device__ void exact_pair(const Plan &P, uint32_t A, uint32_t B)
+__device__ void exact_pair(const Plan &P, uint32_t A, uint32_t B, uint32_t &lt)
 {
     const uint32_t l = lane_id();
     if (uf_find(P.parent, A) == uf_find(P.parent, B)) return;
@@ -424,8 +575,10 @@ __device__ void exact_pair(const Plan &P, uint32_t A, uint32_t B)
         if (k < total) {
             const uint32_t i = (uint32_t)(k / nb), j = (uint32_t)(k - (uint64_t)i * nb);
             const uint32_t pa = a0 + i, pb = b0 + j;
-            if (P.core[pa] && P.core[pb])
+            if (P.core[pa] && P.core[pb]) {
+                lt++;
                 hit = within<D, WIDE>(load_pt<D>(P.spts, pa), load_pt<D>(P.spts, pb), P.eps2);
+            }
         }
         if (__ballot(hit)) { found = true; break; }
         if ((it & 63u) == 63u && uf_find(P.parent, A) == uf_find(P.parent, B)) return;
@@ -445,12 +598,14 @@ __global__ __launch_bounds__(kBlock) void k_merge_exact(Plan P)
     s_pre[w][l] = inc - cnt;
     __builtin_amdgcn_wave_barrier();
     const uint32_t items = __shfl(inc, kWave - 1);
+    uint32_t lt = 0;
     const WaveRange hca_wr_ = wave_range();
     HCA_FOR_UNITS(it, items) {
         const uint32_t r = candidate_lane(it, s_pre[w]);
         const uint64_t at = (uint64_t)r * cap + (it - s_pre[w][r]);
-        exact_pair<D, WIDE>(P, P.work[2ull * at], P.work[2ull * at + 1]);
+        exact_pair<D, WIDE>(P, P.work[2ull * at], P.work[2ull * at + 1], lt);
     }
+    flush_tests(P, kTestsMerge, lt);
 }
 
 // ---------------------------------------------------------------------------
@@ -467,8 +622,128 @@ __global__ __launch_bounds__(kBlock) void k_merge_exact(Plan P)
 // involving a group that is not unified falls back to linking every core
 // pair within eps.
 // ---------------------------------------------------------------------------
+// Intra-group pairs are cut into 64 x 64 tiles of points, dealt to all waves
+// so that a group of thousands of points does not rest on one wave.  Groups
+// of one cube need none (a cube is one union-find node); groups beyond
+// kTileMaxChunks chunks are linked point by point in k_merge_unify.
+constexpr uint32_t kTileMaxChunks = 1024;
+
+__device__ __forceinline__ uint32_t group_tiles(const Plan &P, uint32_t g)
+{
+    if (P.group_cell[g + 1] - P.group_cell[g] < 2) return 0;
+    const uint32_t nc = (P.group_start[g + 1] - P.group_start[g] + kWave - 1) / kWave;
+    return nc > kTileMaxChunks ? 0 : nc * (nc + 1) / 2;
+}
+
+// Exclusive prefix of the tile counts over groups; the total goes to the
+// counters.
+__global__ __launch_bounds__(kBlock) void k_tile_scan(Plan P, uint64_t *status, uint32_t *ticket)
+{
+    __shared__ uint32_t s_red[kBlock / kWave];
+    __shared__ uint32_t s_tile, s_excl;
+    const uint32_t t = threadIdx.x;
+    const uint32_t ng = ld_agent32(&P.ctr->n_groups);
+    if (t == 0) s_tile = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile, base = tile * kScanTile;
+    uint32_t f[kScanItems];
+    uint32_t local = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; j++) {
+        const uint32_t g = base + j * kBlock + t;
+        f[j] = g < ng ? group_tiles(P, g) : 0u;
+        local += f[j];
+    }
+    uint32_t agg;
+    block_exclusive_scan<uint32_t>(local, s_red, &agg);
+    if (t < kWave) {
+        const uint32_t e = (uint32_t)scan_lookback_wave(status, tile, agg);
+        if (t == 0) s_excl = e;
+    }
+    __syncthreads();
+    uint32_t run = s_excl;
+#pragma unroll
+    for (int j = 0; j < kScanItems; j++) {
+        uint32_t tot;
+        const uint32_t e = block_exclusive_scan<uint32_t>(f[j], s_red, &tot);
+        const uint32_t g = base + j * kBlock + t;
+        if (g < ng) P.tile_start[g] = run + e;
+        run += tot;
+    }
+    if (t == 0 && base + kScanTile >= ng) st_agent32(&P.ctr->n_tiles, run);
+}
+
+// One 64 x 64 tile of a group's point pairs per wave.  Lane l holds point l of
+// the column chunk and its cube's root; the row chunk's points sit in LDS and
+// are visited one at a time.  A pair within eps links its two cubes only when
+// the cached roots differ; roots are refreshed after any link.
 template <int D, bool WIDE>
-__global__ __launch_bounds__(kBlock) void k_merge_intra(Plan P)
+__global__ __launch_bounds__(kBlock) void k_merge_tiles(Plan P)
+{
+    __shared__ int32_t s_pt[kWavesPerBlock][kWave][D];
+    const uint32_t w = wave_in_block(), l = lane_id();
+    const uint32_t ng = ld_agent32(&P.ctr->n_groups);
+    const uint32_t total = ld_agent32(&P.ctr->n_tiles);
+    uint32_t lt = 0;
+    const WaveRange hca_wr_ = wave_range();
+    HCA_FOR_UNITS(u, total) {
+        // group: last g with tile_start[g] <= u
+        uint32_t lo = 0, hi = ng;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (P.tile_start[mid] <= u) lo = mid; else hi = mid;
+        }
+        const uint32_t g = lo;
+        const uint32_t a0 = P.group_start[g], a1 = P.group_start[g + 1];
+        const uint32_t nc = (a1 - a0 + kWave - 1) / kWave;
+        // row ci, column cj >= ci of the upper triangle
+        const uint32_t t = u - P.tile_start[g];
+        uint32_t ci = (uint32_t)((2.0f * nc + 1.0f - sqrtf((2.0f * nc + 1.0f) * (2.0f * nc + 1.0f) - 8.0f * t)) * 0.5f);
+        while (ci > 0 && ci * nc - ci * (ci - 1) / 2 > t) ci--;
+        while ((ci + 1) * nc - (ci + 1) * ci / 2 <= t) ci++;
+        const uint32_t cj = ci + (t - (ci * nc - ci * (ci - 1) / 2));
+        const uint32_t i0 = a0 + ci * kWave, j0 = a0 + cj * kWave;
+        const uint32_t qi = i0 + l, qj = j0 + l;
+        const bool core_i = qi < a1 && P.core[qi];
+        const bool core_j = qj < a1 && P.core[qj];
+        const uint64_t mi = __ballot(core_i);
+        if (!mi || !__ballot(core_j)) continue;
+        const uint32_t cube_i = core_i ? P.cell_of[qi] : kNone;
+        const uint32_t cube_j = core_j ? P.cell_of[qj] : kNone;
+        const Pt<D> pi = load_pt<D>(P.spts, core_i ? qi : a0);
+        const Pt<D> pj = load_pt<D>(P.spts, core_j ? qj : a0);
+#pragma unroll
+        for (int e = 0; e < D; e++) s_pt[w][l][e] = pi.x[e];
+        __builtin_amdgcn_wave_barrier();
+        uint32_t root_i = core_i ? uf_find(P.parent, cube_i) : kNone;
+        uint32_t root_j = core_j ? uf_find(P.parent, cube_j) : kNone;
+        uint64_t rows = mi;
+        while (rows) {
+            const uint32_t r = __ffsll((unsigned long long)rows) - 1;
+            rows &= rows - 1;
+            const uint32_t cr = __shfl(cube_i, r);
+            const uint32_t rr = __shfl(root_i, r);
+            Pt<D> pr;
+#pragma unroll
+            for (int e = 0; e < D; e++) pr.x[e] = s_pt[w][r][e];
+            lt += core_j;
+            const bool hit = core_j && cube_j > cr && within<D, WIDE>(pr, pj, P.eps2);
+            const bool need = hit && root_j != rr;
+            if (__ballot(need)) {
+                if (need) uf_union(P.parent, cr, cube_j);
+                root_j = core_j ? uf_find(P.parent, cube_j) : kNone;
+                root_i = core_i ? uf_find(P.parent, cube_i) : kNone;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    flush_tests(P, kTestsMerge, lt);
+}
+
+// First core cube of each group and whether all its core cubes share one
+// root.  Groups too large for tiles are linked point by point here first.
+template <int D, bool WIDE>
+__global__ __launch_bounds__(kBlock) void k_merge_unify(Plan P)
 {
     const uint32_t l = lane_id();
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
@@ -476,7 +751,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_intra(Plan P)
     HCA_FOR_UNITS(g, ng) {
         const uint32_t p0 = P.group_start[g], p1 = P.group_start[g + 1];
         const uint32_t c0 = P.group_cell[g], c1 = P.group_cell[g + 1];
-        if (c1 - c0 > 1) {
+        if (c1 - c0 > 1 && (p1 - p0 + kWave - 1) / kWave > kTileMaxChunks) {
             for (uint32_t pc = p0; pc < p1; pc += kPch) {
                 Pt<D> pp[kPch];
                 uint32_t cell[kPch];
@@ -506,7 +781,6 @@ __global__ __launch_bounds__(kBlock) void k_merge_intra(Plan P)
                 }
             }
         }
-        // first core cube, and whether every core cube shares its root
         uint32_t first = kNone;
         for (uint32_t cb = c0; cb < c1 && first == kNone; cb += kWave) {
             const uint32_t c = cb + l;
@@ -530,7 +804,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_intra(Plan P)
 }
 
 template <int D, bool WIDE>
-__device__ void link_groups(const Plan &P, uint32_t GA, uint32_t GB, bool both_unified)
+__device__ void link_groups(const Plan &P, uint32_t GA, uint32_t GB, bool both_unified, uint32_t &lt)
 {
     const uint32_t l = lane_id();
     const uint32_t a0 = P.group_start[GA], na = P.group_start[GA + 1] - a0;
@@ -545,8 +819,10 @@ __device__ void link_groups(const Plan &P, uint32_t GA, uint32_t GB, bool both_u
             if (k < total) {
                 const uint32_t i = (uint32_t)(k / nb), j = (uint32_t)(k - (uint64_t)i * nb);
                 const uint32_t pa = a0 + i, pb = b0 + j;
-                if (P.core[pa] && P.core[pb])
+                if (P.core[pa] && P.core[pb]) {
+                    lt++;
                     hit = within<D, WIDE>(load_pt<D>(P.spts, pa), load_pt<D>(P.spts, pb), P.eps2);
+                }
             }
             if (__ballot(hit)) {
                 if (l == 0) uf_union(P.parent, ca, cb);
@@ -560,7 +836,7 @@ __device__ void link_groups(const Plan &P, uint32_t GA, uint32_t GB, bool both_u
         if (k < total) {
             const uint32_t i = (uint32_t)(k / nb), j = (uint32_t)(k - (uint64_t)i * nb);
             const uint32_t pa = a0 + i, pb = b0 + j;
-            if (P.core[pa] && P.core[pb] &&
+            if (P.core[pa] && P.core[pb] && (++lt, true) &&
                 within<D, WIDE>(load_pt<D>(P.spts, pa), load_pt<D>(P.spts, pb), P.eps2)) {
                 const uint32_t x = P.cell_of[pa], y = P.cell_of[pb];
                 if (uf_find(P.parent, x) != uf_find(P.parent, y)) uf_union(P.parent, x, y);
@@ -573,6 +849,8 @@ template <int D, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_merge_inter(Plan P)
 {
     const uint32_t l = lane_id();
+    const bool lists = lists_ready(P);
+    uint32_t lt = 0;
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
     const WaveRange hca_wr_ = wave_range();
     HCA_FOR_UNITS(GA, ng) {
@@ -594,31 +872,34 @@ __global__ __launch_bounds__(kBlock) void k_merge_inter(Plan P)
         }
 #pragma unroll
         for (int e = 0; e < D; e++) { qb.lo[e] = wave_min(qb.lo[e]); qb.hi[e] = wave_max(qb.hi[e]); }
-        for (uint32_t oc = 1; oc < P.n_off; oc += kWave) {
+        const NbrSrc src = nbr_source(P, GA, lists);
+        for (uint32_t oc = 1; oc < src.slots; oc += kWave) {
             const uint32_t j = oc + l;
             uint32_t GB = kNone;
             bool need = false, both = false;
-            if (j < P.n_off) {
-                const uint64_t nk = group_neighbour<D>(P, gkey, P.off + (uint64_t)j * D);
-                if (nk != ~0ull) {
-                    GB = group_lookup(P, nk);
-                    if (GB != kNone && GB > GA && P.gcube[GB] != kNone) {
-                        int64_t acc = 0;
+            if (j < src.slots) {
+                uint64_t nk = ~0ull;
+                if (src.lists) {
+                    GB = P.nbr[src.start + j - 1];
+                    if (GB > GA) nk = P.group_key[GB]; else GB = kNone;
+                } else {
+                    // groups are numbered in key order: GB > GA exactly when
+                    // the first non-zero component of the offset is positive
+                    const int8_t *o = P.off + (uint64_t)j * D;
+                    int lead = 0;
 #pragma unroll
-                        for (int e = 0; e < D; e++) {
-                            const int64_t gc = (int64_t)((nk >> P.goff[e]) & ((1ull << P.gw[e]) - 1ull));
-                            const int64_t glo = (int64_t)P.origin[e] + gc * P.gside;
-                            const int64_t ghi = glo + P.gside - 1;
-                            int64_t gap = 0;
-                            if (glo > qb.hi[e]) gap = glo - qb.hi[e];
-                            else if ((int64_t)qb.lo[e] > ghi) gap = (int64_t)qb.lo[e] - ghi;
-                            acc += gap * gap;
-                        }
-                        if (acc <= P.eps2) {
-                            both = ua && P.unified[GB];
-                            need = !both || uf_find(P.parent, ga) != uf_find(P.parent, P.gcube[GB]);
-                        }
+                    for (int e = 0; e < D; e++)
+                        if (lead == 0) lead = o[e];
+                    nk = lead > 0 ? group_neighbour<D>(P, gkey, o) : ~0ull;
+                }
+                if (nk != ~0ull && group_box_within<D>(P, nk, qb)) {
+                    if (!src.lists) GB = group_lookup(P, nk);
+                    if (GB != kNone && P.gcube[GB] != kNone) {
+                        both = ua && P.unified[GB];
+                        need = !both || uf_find(P.parent, ga) != uf_find(P.parent, P.gcube[GB]);
                     }
+                } else {
+                    GB = kNone;
                 }
             }
             uint64_t m = __ballot(need);
@@ -626,11 +907,12 @@ __global__ __launch_bounds__(kBlock) void k_merge_inter(Plan P)
                 const uint32_t src = __ffsll((unsigned long long)m) - 1;
                 const uint32_t gb = __shfl(GB, src);
                 const bool bu = __shfl((int)both, src) != 0;
-                link_groups<D, WIDE>(P, GA, gb, bu);
+                link_groups<D, WIDE>(P, GA, gb, bu, lt);
                 m &= m - 1;
             }
         }
     }
+    flush_tests(P, kTestsMerge, lt);
 }
 
 // ---------------------------------------------------------------------------
@@ -673,6 +955,8 @@ __global__ __launch_bounds__(kBlock) void k_border(Plan P)
 {
     __shared__ uint32_t s_beg[kWavesPerBlock][kWave], s_pre[kWavesPerBlock][kWave];
     const uint32_t w = wave_in_block(), l = lane_id();
+    const bool lists = lists_ready(P);
+    uint32_t lt = 0;
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
     const WaveRange hca_wr_ = wave_range();
     HCA_FOR_UNITS(g, ng) {
@@ -694,8 +978,10 @@ __global__ __launch_bounds__(kBlock) void k_border(Plan P)
             uint32_t bi[kPch], bp[kPch];
 #pragma unroll
             for (int k = 0; k < kPch; k++) { bd[k] = INT64_MAX; bi[k] = kNone; bp[k] = kNone; }
-            for (uint32_t oc = 0; oc < P.n_off; oc += kWave) {
-                const uint32_t total = load_neighbours<D>(P, gkey, oc, 0, true, qb, s_beg[w], s_pre[w]);
+            const NbrSrc src = nbr_source(P, g, lists);
+            for (uint32_t oc = 0; oc < src.slots; oc += kWave) {
+                const uint32_t total =
+                    load_neighbours<D>(P, g, gkey, src, oc, 0, true, qb, s_beg[w], s_pre[w]);
                 for (uint32_t ci = 0; ci < total; ci += kWave) {
                     const uint32_t c = ci + l;
                     bool ok = c < total;
@@ -711,6 +997,7 @@ __global__ __launch_bounds__(kBlock) void k_border(Plan P)
                     bool near = false;
 #pragma unroll
                     for (int k = 0; k < kPch; k++) {
+                        if (todo & (1u << k)) lt += ok;
                         dd[k] = dist2<D, WIDE>(pp[k], q);
                         near |= (todo & (1u << k)) && ok && dd[k] <= P.eps2 && dd[k] <= bd[k];
                     }
@@ -747,6 +1034,7 @@ __global__ __launch_bounds__(kBlock) void k_border(Plan P)
             }
         }
     }
+    flush_tests(P, kTestsBorder, lt);
 }
 
 // ---------------------------------------------------------------------------
@@ -875,17 +1163,41 @@ __global__ __launch_bounds__(kBlock) void k_label_write(Plan P)
         }                                                                                 \
     } while (0)
 
-void launch_init(uint32_t *zero, uint64_t zero_words, uint64_t *hkeys, uint64_t hcap, uint32_t *table,
-                 uint64_t tsize, hipStream_t s)
+void launch_init(uint32_t *zero, uint64_t zero_words, uint64_t *hkeys, uint64_t *hkeys_read,
+                 uint64_t hcap, uint32_t *table, uint64_t tsize, hipStream_t s)
 {
     const uint64_t work = std::max(zero_words, std::max(hcap, tsize));
     const int blocks = (int)std::max<uint64_t>(1, std::min<uint64_t>((work + kBlock - 1) / kBlock, 2048));
-    hipLaunchKernelGGL(k_init, dim3(blocks), dim3(kBlock), 0, s, zero, zero_words, hkeys, hcap, table, tsize);
+    hipLaunchKernelGGL(k_init, dim3(blocks), dim3(kBlock), 0, s, zero, zero_words, hkeys, hkeys_read, hcap,
+                       table, tsize);
 }
 
 void launch_table(const Plan &P, int blocks, hipStream_t s)
 {
     hipLaunchKernelGGL(k_table, dim3(blocks), dim3(kBlock), 0, s, P);
+}
+
+#define HCA_DISPATCH_D_FILL(FILL, P, blocks, s)                                                      \
+    do {                                                                                             \
+        switch ((P).d) {                                                                             \
+        case 1: hipLaunchKernelGGL((k_nbr_lists<1, FILL>), dim3(blocks), dim3(kBlock), 0, s, P); break; \
+        case 2: hipLaunchKernelGGL((k_nbr_lists<2, FILL>), dim3(blocks), dim3(kBlock), 0, s, P); break; \
+        case 3: hipLaunchKernelGGL((k_nbr_lists<3, FILL>), dim3(blocks), dim3(kBlock), 0, s, P); break; \
+        case 4: hipLaunchKernelGGL((k_nbr_lists<4, FILL>), dim3(blocks), dim3(kBlock), 0, s, P); break; \
+        case 5: hipLaunchKernelGGL((k_nbr_lists<5, FILL>), dim3(blocks), dim3(kBlock), 0, s, P); break; \
+        case 6: hipLaunchKernelGGL((k_nbr_lists<6, FILL>), dim3(blocks), dim3(kBlock), 0, s, P); break; \
+        case 7: hipLaunchKernelGGL((k_nbr_lists<7, FILL>), dim3(blocks), dim3(kBlock), 0, s, P); break; \
+        case 8: hipLaunchKernelGGL((k_nbr_lists<8, FILL>), dim3(blocks), dim3(kBlock), 0, s, P); break; \
+        }                                                                                            \
+    } while (0)
+
+void launch_lists(const Plan &P, int blocks, hipStream_t s)
+{
+    if (!P.nbr_cap) return;
+    HCA_DISPATCH_D_FILL(false, P, blocks, s);
+    const uint32_t tiles = (P.n + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(k_nbr_scan, dim3(tiles), dim3(kBlock), 0, s, P, P.nbr_status, &P.ctr->nbr_ticket);
+    HCA_DISPATCH_D_FILL(true, P, blocks, s);
 }
 
 void launch_core(const Plan &P, int blocks, hipStream_t s)
@@ -909,7 +1221,10 @@ void launch_merge(const Plan &P, int blocks, hipStream_t s)
         HCA_DISPATCH_DW(k_merge_rep, P, blocks, s);
         HCA_DISPATCH_DW(k_merge_exact, P, blocks, s);
     } else {
-        HCA_DISPATCH_DW(k_merge_intra, P, blocks, s);
+        const uint32_t tiles = (P.n + kScanTile - 1) / kScanTile;
+        hipLaunchKernelGGL(k_tile_scan, dim3(tiles), dim3(kBlock), 0, s, P, P.tile_status, &P.ctr->tile_ticket);
+        HCA_DISPATCH_DW(k_merge_tiles, P, blocks, s);
+        HCA_DISPATCH_DW(k_merge_unify, P, blocks, s);
         HCA_DISPATCH_DW(k_merge_inter, P, blocks, s);
     }
 }

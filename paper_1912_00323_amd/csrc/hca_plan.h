@@ -44,9 +44,18 @@ struct Counters {
     uint32_t n_core;
     uint32_t n_noise;
     uint32_t n_clusters;
-    uint32_t pad[13];
+    uint32_t n_tiles;           // intra-group point tiles
+    uint32_t tile_ticket;
+    uint32_t n_nbr;             // entries of the neighbour-group lists
+    uint32_t nbr_ticket;
+    uint32_t pad[9];
     uint32_t work_count[kWorkRegions * kCounterStride];   // region r at [r * kCounterStride]
+    // pair tests executed, per phase (core, merge, border), spread over
+    // kWorkRegions lines of eight 64-bit words; counted only on request
+    unsigned long long tests[3][kWorkRegions * 8];
 };
+
+enum { kTestsCore = 0, kTestsMerge = 1, kTestsBorder = 2 };
 
 struct Plan {
     // problem
@@ -92,16 +101,27 @@ struct Plan {
     uint32_t *group_cell;       // [n + 1] group -> first cube id
     uint64_t *group_key;        // [n]
     uint32_t *table;            // dense: [2^gbits] ; hash: values [cap]
-    uint64_t *hkeys;            // hash: keys [cap]
+    uint64_t *hkeys;            // hash: keys [cap], claimed by compare-and-swap
+    uint64_t *hkeys_read;       // hash: plain copy of the claimed keys [cap], read by lookups
     uint8_t *core;              // [n] sorted order
     uint32_t *ncore;            // [n] cube -> core points
     uint64_t *rep;              // [cells][n_dir] (score << 32 | sorted position), min wins
     uint32_t *parent;           // [n] union-find over cubes
     uint32_t *gcube;            // [n] group -> first cube with a core point, kNone if none
     uint8_t *unified;           // [n] group -> its core cubes share one union-find root
+    uint32_t *tile_start;       // [n] group -> first intra-group tile
+    // group mode: non-empty neighbour groups of each group (self excluded),
+    // nearest offsets first; used when they fit in nbr_cap entries
+    uint32_t nbr_cap;
+    uint32_t *nbr_count;        // [n]
+    uint32_t *nbr_start;        // [n]
+    uint32_t *nbr;              // [nbr_cap]
+    uint64_t *nbr_status;       // look-back words of the list scan
+    uint64_t *tile_status;      // look-back words of the tile scan
     uint32_t *work;             // [2 * work_cap] cube pairs for exact tests
     uint32_t work_cap;          // multiple of kWorkRegions
     uint32_t want_stats;        // count core and noise points
+    uint32_t count_work;        // count pair tests per phase
     uint32_t *owner;            // [n] sorted position -> root cube (border), kNone
     uint32_t *cmin;             // [n] cube -> smallest input index of its core points, kNone
     uint32_t *minmem;           // [n] root cube -> smallest member input index

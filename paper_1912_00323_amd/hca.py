@@ -42,7 +42,9 @@ class Stats(ctypes.Structure):
                 ("n_noise", ctypes.c_int64), ("exact_pairs", ctypes.c_int64),
                 ("key_bits", ctypes.c_int32), ("sort_passes", ctypes.c_int32),
                 ("group", ctypes.c_int32), ("wide", ctypes.c_int32),
-                ("dense_table", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("dense_table", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tests_core", ctypes.c_int64), ("tests_merge", ctypes.c_int64),
+                ("tests_border", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
