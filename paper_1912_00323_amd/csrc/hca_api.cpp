@@ -464,8 +464,16 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
     const uint32_t scan_tiles = (n + kScanTile - 1) / kScanTile;
     P.work_cap = (uint32_t)std::min<uint64_t>(4ull * n + 1024, 1ull << 30) / kWorkRegions * kWorkRegions;
     P.want_stats = stats != nullptr;
-    // neighbour-group lists in group mode: room for 64 entries per point
-    P.nbr_cap = P.m > 1 ? (uint32_t)std::min<uint64_t>(64ull * n, 1ull << 31) : 0;
+    // persistent grids of the neighbour phases: enough waves to fill the chip
+    int persist = kPersistBlocks;
+    if (const char *e = std::getenv("HCA_WAVE_BLOCKS")) persist = std::max(8, std::atoi(e));
+    const int pb = (int)std::min<uint64_t>(persist, ((uint64_t)n + kBlock - 1) / kBlock * 4 + 8) & ~7;
+    const int wb = std::max(8, pb);
+    // neighbour-group lists in group mode: 64 entries per point, at least
+    // 4096 per wave, at most 2^29 in all
+    P.nbr_cap = P.m > 1 ? (uint32_t)std::min<uint64_t>(std::max<uint64_t>(64ull * n, 4096ull * wb * (kBlock / kWave)),
+                                                       1ull << 29)
+                        : 0;
     P.count_work = stats != nullptr && ctx->prof != -1;
 
     // 3. workspace
@@ -489,6 +497,7 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
         P.gcube = cv.take<uint32_t>(n);
         P.unified = cv.take<uint8_t>(n);
         P.tile_start = cv.take<uint32_t>(n);
+        P.group_of = cv.take<uint32_t>(n);
         if (P.nbr_cap) {
             P.nbr_count = cv.take<uint32_t>(n);
             P.nbr_start = cv.take<uint32_t>(n);
@@ -508,7 +517,6 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
         P.scan_status = cv.take<uint64_t>((size_t)2 * scan_tiles + 64);
         P.first = cv.take<uint32_t>(((size_t)n + 31) / 32);
         P.tile_status = cv.take<uint64_t>((size_t)scan_tiles + 64);
-        P.nbr_status = cv.take<uint64_t>((size_t)scan_tiles + 64);
         *zero_bytes = cv.off - zstart;
         *zero_begin = (uint32_t *)(cv.base ? cv.base + zstart : nullptr);
         // lookup table, filled with all-ones
@@ -558,10 +566,6 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
     mark(ctx, HCA_PHASE_CELLS, true);
     mark(ctx, HCA_PHASE_CORE, false);
     // 6. core points, representatives, merging, border points, labels
-    int persist = kPersistBlocks;
-    if (const char *e = std::getenv("HCA_WAVE_BLOCKS")) persist = std::max(8, std::atoi(e));
-    const int pb = (int)std::min<uint64_t>(persist, ((uint64_t)n + kBlock - 1) / kBlock * 4 + 8) & ~7;
-    const int wb = std::max(8, pb);
     launch_lists(P, wb, s);
     launch_core(P, wb, s);
     mark(ctx, HCA_PHASE_CORE, true);

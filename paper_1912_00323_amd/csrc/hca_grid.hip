@@ -69,17 +69,13 @@ struct NbrSrc {
     uint32_t lists, start, slots;
 };
 
-__device__ __forceinline__ bool lists_ready(const Plan &P)
-{
-    return P.nbr_cap && ld_agent32(&P.ctr->n_nbr) <= P.nbr_cap;
-}
-
-__device__ __forceinline__ NbrSrc nbr_source(const Plan &P, uint32_t g, bool lists)
+__device__ __forceinline__ NbrSrc nbr_source(const Plan &P, uint32_t g)
 {
     NbrSrc src;
-    src.lists = lists;
-    src.start = lists ? P.nbr_start[g] : 0;
-    src.slots = lists ? P.nbr_count[g] + 1 : P.n_off;
+    const uint32_t c = P.nbr_cap ? P.nbr_count[g] : kNone;
+    src.lists = c != kNone;
+    src.start = src.lists ? P.nbr_start[g] : 0;
+    src.slots = src.lists ? c + 1 : P.n_off;
     return src;
 }
 
@@ -103,7 +99,7 @@ __device__ __forceinline__ uint32_t slot_group(const Plan &P, uint32_t g, uint64
 // first + l; its point range starts at s_beg[l] and its first candidate index
 // is s_pre[l].  A group is dropped when its id is below `lowest`, when its box
 // is farther than eps from the query box q (tested before the lookup on the
-// stencil path), or (need_core, m == 1) when its cube has no core point.
+// stencil path), or (need_core) when it has no core point.
 // Returns the number of candidates in the chunk.
 // ---------------------------------------------------------------------------
 template <int D>
@@ -126,7 +122,8 @@ __device__ __forceinline__ uint32_t load_neighbours(const Plan &P, uint32_t g, u
             const uint64_t nk = group_neighbour<D>(P, gkey, P.off + (uint64_t)j * D);
             if (nk != ~0ull && group_box_within<D>(P, nk, q)) G = group_lookup(P, nk);
         }
-        if (G != kNone && G >= lowest && !(need_core && P.m == 1 && P.ncore[G] == 0)) {
+        if (G != kNone && G >= lowest &&
+            !(need_core && (P.m == 1 ? P.ncore[G] == 0 : P.gcube[G] == kNone))) {
             a = P.group_start[G];
             size = P.group_start[G + 1] - a;
         }
@@ -210,11 +207,11 @@ __global__ __launch_bounds__(kBlock) void k_table(Plan P)
 }
 
 // ---------------------------------------------------------------------------
-// Neighbour-group lists (group mode): every group at a stencil offset that
-// exists and whose box comes within eps of the group's own points, nearest
-// offsets first.  Built once per call by a counting pass, a scan and a fill
-// pass, then walked by core marking, merging and border assignment.
+// Neighbour-group lists (group mode): every non-empty group at an offset in
+// {-1, 0, 1}^d whose box comes within eps of the group's own points.  Built
+// once per call, then walked by core marking, merging and border assignment.
 // ---------------------------------------------------------------------------
+// Bounding box of the points [p0, p1) (wave-uniform result).
 template <int D>
 __device__ __forceinline__ QBox<D> group_points_box(const Plan &P, uint32_t p0, uint32_t p1)
 {
@@ -234,68 +231,196 @@ __device__ __forceinline__ QBox<D> group_points_box(const Plan &P, uint32_t p0, 
     return b;
 }
 
-template <int D, bool FILL>
-__global__ __launch_bounds__(kBlock) void k_nbr_lists(Plan P)
+constexpr int pow3(int k) { return k == 0 ? 1 : 3 * pow3(k - 1); }
+
+// Squared gap along axis e between the query box [lo, hi] and the group at
+// coordinate c + o (o in {-1, 0, 1}), or -1 when that group lies outside the
+// grid.
+__device__ __forceinline__ int64_t axis_gap2(const Plan &P, uint64_t gkey, int e, int o, int32_t lo, int32_t hi)
+{
+    const int64_t c = (int64_t)((gkey >> P.goff[e]) & ((1ull << P.gw[e]) - 1ull)) + o;
+    if (c < 0 || c > (int64_t)P.gmax[e]) return -1;
+    const int64_t glo = (int64_t)P.origin[e] + c * P.gside, ghi = glo + P.gside - 1;
+    const int64_t gap = glo > hi ? glo - hi : (lo > ghi ? lo - ghi : 0);
+    return gap * gap;
+}
+
+// Half of the axes (first, first + K): the sum of squared gaps of the offset
+// combination `idx` (base-3 digits, axis `first` lowest), or INT64_MAX when
+// it leaves the grid or already exceeds eps.
+template <int D, int K>
+__device__ __forceinline__ int64_t half_gap2(const Plan &P, uint64_t gkey, int first, uint32_t idx,
+                                             const QBox<D> &q)
+{
+    int64_t acc = 0;
+#pragma unroll
+    for (int e = 0; e < K; e++) {
+        const int o = (int)(idx % 3u) - 1;
+        idx /= 3u;
+        const int64_t g2 = axis_gap2(P, gkey, first + e, o, q.lo[first + e], q.hi[first + e]);
+        if (g2 < 0) return INT64_MAX;
+        acc += g2;
+    }
+    return acc <= P.eps2 ? acc : INT64_MAX;
+}
+
+template <int K>
+__device__ __forceinline__ int64_t half_key_delta(const Plan &P, int first, uint32_t idx)
+{
+    int64_t kd = 0;
+#pragma unroll
+    for (int e = 0; e < K; e++) {
+        const int o = (int)(idx % 3u) - 1;
+        idx /= 3u;
+        kd += (int64_t)o * (int64_t)(1ull << P.goff[first + e]);
+    }
+    return kd;
+}
+
+// Sort the n <= 128 gap sums of one half ascending (ties by index) into
+// s_sum / s_idx, by counting ranks; input in s_in.
+__device__ __forceinline__ void rank_sort(const int64_t *s_in, int n, int64_t *s_sum, uint8_t *s_idx)
 {
     const uint32_t l = lane_id();
+    for (int i = l; i < n; i += kWave) {
+        const int64_t v = s_in[i];
+        int r = 0;
+        for (int j = 0; j < n; j++) {
+            const int64_t u = s_in[j];
+            r += u < v || (u == v && j < i);
+        }
+        s_sum[r] = v;
+        s_idx[r] = (uint8_t)i;
+    }
+}
+
+// Neighbour-group lists (group mode), one wave per group.  The offsets in
+// {-1, 0, 1}^d split into two halves of the axes; the squared gaps between
+// the group's point box and the neighbour boxes add over axes, so the
+// offsets that can hold a point within eps are the pairs (i, j) of the two
+// halves with sum_a[i] + sum_b[j] <= eps^2.  Both halves are sorted, so for
+// each i the valid j form a prefix; only those offsets are looked up.  Each
+// wave appends to its own slab; a group that does not fit is flagged and
+// searched over the stencil instead.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_nbr_lists(Plan P)
+{
+    constexpr int DA = D / 2, DB = D - DA, NA = pow3(DA), NB = pow3(DB);
+    __shared__ int64_t s_in[kWavesPerBlock][NA > NB ? NA : NB];
+    __shared__ int64_t s_sa[kWavesPerBlock][NA], s_sb[kWavesPerBlock][NB];
+    __shared__ uint8_t s_ia[kWavesPerBlock][NA], s_ib[kWavesPerBlock][NB];
+    __shared__ uint32_t s_pre[kWavesPerBlock][NA + 1];
+    const uint32_t w = wave_in_block(), l = lane_id();
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
-    if (FILL && ld_agent32(&P.ctr->n_nbr) > P.nbr_cap) return;     // lists do not fit
+    const uint32_t waves = gridDim.x * kWavesPerBlock;
+    const uint32_t slab = P.nbr_cap / waves;
+    uint32_t at = (blockIdx.x * kWavesPerBlock + w) * slab;
+    const uint32_t end = at + slab;
+    uint32_t overflow = 0;
     const WaveRange hca_wr_ = wave_range();
     HCA_FOR_UNITS(g, ng) {
         const uint64_t gkey = P.group_key[g];
         const QBox<D> qb = group_points_box<D>(P, P.group_start[g], P.group_start[g + 1]);
-        uint32_t at = FILL ? P.nbr_start[g] : 0, count = 0;
-        for (uint32_t oc = 1; oc < P.n_off; oc += kWave) {
-            const uint32_t j = oc + l;
+        // both halves' gap sums, sorted ascending
+        for (int i = l; i < NA; i += kWave) s_in[w][i] = half_gap2<D, DA>(P, gkey, 0, i, qb);
+        __builtin_amdgcn_wave_barrier();
+        rank_sort(s_in[w], NA, s_sa[w], s_ia[w]);
+        __builtin_amdgcn_wave_barrier();
+        for (int j = l; j < NB; j += kWave) s_in[w][j] = half_gap2<D, DB>(P, gkey, DA, j, qb);
+        __builtin_amdgcn_wave_barrier();
+        rank_sort(s_in[w], NB, s_sb[w], s_ib[w]);
+        __builtin_amdgcn_wave_barrier();
+        // valid j per i (a prefix of the sorted second half), then their prefix
+        uint32_t tot = 0;
+        for (int i0 = 0; i0 < NA; i0 += kWave) {
+            const int i = i0 + (int)l;
+            uint32_t c = 0;
+            if (i < NA && s_sa[w][i] != INT64_MAX) {
+                const int64_t lim = P.eps2 - s_sa[w][i];
+                int lo = 0, hi = NB;                      // first j with s_sb > lim
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_sb[w][mid] <= lim) lo = mid + 1; else hi = mid;
+                }
+                c = (uint32_t)lo;
+            }
+            const uint32_t inc = wave_inclusive_scan(c);
+            if (i < NA) s_pre[w][i] = tot + inc - c;
+            tot += __shfl(inc, kWave - 1);
+        }
+        if (l == 0) s_pre[w][NA] = tot;
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t start = at;
+        bool fits = true;
+        for (uint32_t t0 = 0; t0 < tot; t0 += kWave) {
+            const uint32_t t = t0 + l;
             uint32_t G = kNone;
-            if (j < P.n_off) {
-                const uint64_t nk = group_neighbour<D>(P, gkey, P.off + (uint64_t)j * D);
-                if (nk != ~0ull && group_box_within<D>(P, nk, qb)) G = group_lookup(P, nk);
+            if (t < tot) {
+                int lo = 0, hi = NA;                      // last i with s_pre[i] <= t
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_pre[w][mid] <= t) lo = mid; else hi = mid;
+                }
+                const uint32_t j = t - s_pre[w][lo];
+                const uint64_t nk = gkey + (uint64_t)(half_key_delta<DA>(P, 0, s_ia[w][lo]) +
+                                                      half_key_delta<DB>(P, DA, s_ib[w][j]));
+                if (nk != gkey) G = group_lookup(P, nk);
             }
             const uint64_t m = __ballot(G != kNone);
-            if (FILL && G != kNone) P.nbr[at + __popcll(m & __lanemask_lt())] = G;
-            at += __popcll(m);
-            count += __popcll(m);
+            const uint32_t k = (uint32_t)__popcll(m);
+            if (at + k > end) fits = false;
+            if (fits && G != kNone) P.nbr[at + __popcll(m & __lanemask_lt())] = G;
+            if (fits) at += k;
         }
-        if (!FILL && l == 0) P.nbr_count[g] = count;
+        __builtin_amdgcn_wave_barrier();
+        if (l == 0) {
+            P.nbr_start[g] = start;
+            P.nbr_count[g] = fits ? at - start : kNone;
+        }
+        if (!fits) {
+            at = start;
+            overflow++;
+        }
     }
+    if (l == 0 && overflow) atomicAdd(&P.ctr->nbr_overflow, overflow);
 }
 
-// Exclusive prefix of nbr_count over the groups; the total goes to n_nbr.
-__global__ __launch_bounds__(kBlock) void k_nbr_scan(Plan P, uint64_t *status, uint32_t *ticket)
+// Neighbour counts of the chunk points not yet flagged in `done`, over group
+// g and its neighbour groups, until each reaches minPts (then its bit is
+// set).  Returns the updated mask.
+template <int D, bool WIDE>
+__device__ __forceinline__ uint32_t count_walk(const Plan &P, uint32_t g, uint64_t gkey, const Pt<D> *pp,
+                                               uint32_t done, uint32_t *cnt, uint32_t *s_beg,
+                                               uint32_t *s_pre, uint32_t &lt)
 {
-    __shared__ uint32_t s_red[kBlock / kWave];
-    __shared__ uint32_t s_tile, s_excl;
-    const uint32_t t = threadIdx.x;
-    const uint32_t ng = ld_agent32(&P.ctr->n_groups);
-    if (t == 0) s_tile = atomicAdd(ticket, 1u);
-    __syncthreads();
-    const uint32_t tile = s_tile, base = tile * kScanTile;
-    uint32_t f[kScanItems];
-    uint32_t local = 0;
+    const uint32_t l = lane_id();
+    const uint32_t minpts = (uint32_t)P.min_pts;
+    const uint32_t all = (1u << kPch) - 1u;
+    const QBox<D> qb = chunk_box<D>(pp, ~done);
+    const NbrSrc src = nbr_source(P, g);
+    for (uint32_t oc = 0; oc < src.slots && done != all; oc += kWave) {
+        const uint32_t total = load_neighbours<D>(P, g, gkey, src, oc, 0, false, qb, s_beg, s_pre);
+        for (uint32_t ci = 0; ci < total && done != all; ci += kWave) {
+            const uint32_t c = ci + l;
+            const bool ok = c < total;
+            uint32_t pos = 0;
+            if (ok) {
+                const uint32_t ln = candidate_lane(c, s_pre);
+                pos = s_beg[ln] + (c - s_pre[ln]);
+            }
+            const Pt<D> q = load_pt<D>(P.spts, pos);
 #pragma unroll
-    for (int j = 0; j < kScanItems; j++) {
-        const uint32_t g = base + j * kBlock + t;
-        f[j] = g < ng ? P.nbr_count[g] : 0u;
-        local += f[j];
+            for (int k = 0; k < kPch; k++) {
+                if (done & (1u << k)) continue;
+                lt += ok;
+                const bool hit = ok && within<D, WIDE>(pp[k], q, P.eps2);
+                cnt[k] += __popcll(__ballot(hit));
+                if (cnt[k] >= minpts) done |= 1u << k;
+            }
+            done = uniform(done);
+        }
     }
-    uint32_t agg;
-    block_exclusive_scan<uint32_t>(local, s_red, &agg);
-    if (t < kWave) {
-        const uint32_t e = (uint32_t)scan_lookback_wave(status, tile, agg);
-        if (t == 0) s_excl = e;
-    }
-    __syncthreads();
-    uint32_t run = s_excl;
-#pragma unroll
-    for (int j = 0; j < kScanItems; j++) {
-        uint32_t tot;
-        const uint32_t e = block_exclusive_scan<uint32_t>(f[j], s_red, &tot);
-        const uint32_t g = base + j * kBlock + t;
-        if (g < ng) P.nbr_start[g] = run + e;
-        run += tot;
-    }
-    if (t == 0 && base + kScanTile >= ng) st_agent32(&P.ctr->n_nbr, run);
+    return done;
 }
 
 // ---------------------------------------------------------------------------
@@ -314,7 +439,6 @@ __global__ __launch_bounds__(kBlock) void k_core(Plan P)
     const uint32_t w = wave_in_block(), l = lane_id();
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
     const uint32_t minpts = (uint32_t)P.min_pts;
-    const bool lists = lists_ready(P);
     uint32_t lt = 0;
     const WaveRange hca_wr_ = wave_range();
     HCA_FOR_UNITS(g, ng) {
@@ -352,33 +476,7 @@ __global__ __launch_bounds__(kBlock) void k_core(Plan P)
             }
             done = uniform(done);
             const uint32_t all = (1u << kPch) - 1u;
-            if (done != all) {
-                const QBox<D> qb = chunk_box<D>(pp, ~done);
-                const NbrSrc src = nbr_source(P, g, lists);
-                for (uint32_t oc = 0; oc < src.slots && done != all; oc += kWave) {
-                    const uint32_t total =
-                        load_neighbours<D>(P, g, gkey, src, oc, 0, false, qb, s_beg[w], s_pre[w]);
-                    for (uint32_t ci = 0; ci < total && done != all; ci += kWave) {
-                        const uint32_t c = ci + l;
-                        const bool ok = c < total;
-                        uint32_t pos = 0;
-                        if (ok) {
-                            const uint32_t ln = candidate_lane(c, s_pre[w]);
-                            pos = s_beg[w][ln] + (c - s_pre[w][ln]);
-                        }
-                        const Pt<D> q = load_pt<D>(P.spts, pos);
-#pragma unroll
-                        for (int k = 0; k < kPch; k++) {
-                            if (done & (1u << k)) continue;
-                            lt += ok;
-                            const bool hit = ok && within<D, WIDE>(pp[k], q, P.eps2);
-                            cnt[k] += __popcll(__ballot(hit));
-                            if (cnt[k] >= minpts) done |= 1u << k;
-                        }
-                        done = uniform(done);
-                    }
-                }
-            }
+            if (done != all) done = count_walk<D, WIDE>(P, g, gkey, pp, done, cnt, s_beg[w], s_pre[w], lt);
             // lane k < np writes the result of point pc + k
             uint32_t mine = 0;
 #pragma unroll
@@ -415,6 +513,72 @@ __global__ __launch_bounds__(kBlock) void k_core(Plan P)
         if (l == 0) {
             P.ncore[tally_cell] = tally;
             P.cmin[tally_cell] = tally_min;
+        }
+    }
+    flush_tests(P, kTestsCore, lt);
+}
+
+// Group mode: the units are chunks of kPch consecutive sorted points, so the
+// thousands of points of a dense group are spread over many waves.  A chunk
+// may straddle groups; its points are walked group by group.  The per-cube
+// tallies (core points, smallest core input index) are accumulated with one
+// atomic per cube run of the chunk.
+template <int D, bool WIDE>
+__global__ __launch_bounds__(kBlock) void k_core_chunks(Plan P)
+{
+    __shared__ uint32_t s_beg[kWavesPerBlock][kWave], s_pre[kWavesPerBlock][kWave];
+    const uint32_t w = wave_in_block(), l = lane_id();
+    const uint32_t n = P.n, minpts = (uint32_t)P.min_pts;
+    const uint32_t all = (1u << kPch) - 1u;
+    uint32_t lt = 0;
+    const WaveRange hca_wr_ = wave_range();
+    HCA_FOR_UNITS(u, (n + kPch - 1) / kPch) {
+        const uint32_t pc = u * kPch, np = min((uint32_t)kPch, n - pc);
+        // lane k < np: cube, group and density of point pc + k
+        uint32_t cell = kNone, grp = kNone;
+        bool dense = true;
+        if (l < np) {
+            cell = P.cell_of[pc + l];
+            grp = P.group_of[cell];
+            dense = P.cell_start[cell + 1] - P.cell_start[cell] >= minpts;
+        }
+        uint32_t done = (uint32_t)__ballot(dense) & all;
+        uint32_t cnt[kPch];
+#pragma unroll
+        for (int k = 0; k < kPch; k++) cnt[k] = 0;
+        if (done != all) {
+            Pt<D> pp[kPch];
+            load_chunk<D>(P, pc, np, pp);
+            uint32_t left = ~done & all;
+            while (left) {
+                const uint32_t g = __shfl(grp, __ffs(left) - 1);
+                const uint32_t run = (uint32_t)__ballot(grp == g) & left;
+                left &= ~run;
+                const uint32_t got = count_walk<D, WIDE>(P, g, P.group_key[g], pp, ~run & all, cnt, s_beg[w],
+                                                         s_pre[w], lt);
+                done |= got & run;
+            }
+        }
+        uint32_t mine = 0;
+#pragma unroll
+        for (int k = 0; k < kPch; k++)
+            if ((uint32_t)k == l) mine = cnt[k];
+        const bool core = l < np && (dense || mine >= minpts);
+        if (l < np) P.core[pc + l] = core;
+        const uint32_t me = core ? P.sidx[pc + l] : kNone;
+        // one atomic per cube of the chunk (cubes are runs of lanes)
+        uint64_t pend = __ballot(l < np);
+        while (pend) {
+            const uint32_t k0 = __ffsll((unsigned long long)pend) - 1;
+            const uint32_t c = __shfl(cell, k0);
+            const uint64_t same = __ballot(l < np && cell == c);
+            const uint32_t cores = (uint32_t)__popcll(__ballot(l < np && cell == c && core));
+            const uint32_t mn = wave_min(cell == c ? me : kNone);
+            if (l == k0 && cores) {
+                atomicAdd(P.ncore + c, cores);
+                atomicMin(P.cmin + c, mn);
+            }
+            pend &= ~same;
         }
     }
     flush_tests(P, kTestsCore, lt);
@@ -615,12 +779,13 @@ __global__ __launch_bounds__(kBlock) void k_merge_exact(Plan P)
 // records its first core cube and whether all its core cubes now share one
 // root ("unified"; unions only ever join sets, so a unified group stays so).
 //
-// Inter: for each group GA and neighbour group GB > GA, when both are unified
-// one root per group decides: equal roots mean nothing to do; otherwise the
-// core pairs of the two groups are tested in tiles of 64 lanes until the
-// first pair within eps (wavefront ballot), which joins the two sets.  A pair
-// involving a group that is not unified falls back to linking every core
-// pair within eps.
+// Inter: for each pair of neighbour groups GA < GB with core points near
+// enough, when each group's core cubes share one root the two roots decide:
+// equal roots mean nothing to do; otherwise the core pairs are tested in
+// tiles of 64 lanes until the first pair within eps (wavefront ballot),
+// which joins the two sets.  Otherwise every core pair within eps links its
+// two cubes.  Pairs of unified groups are handled as they are found; the
+// others are queued and spread over all waves.
 // ---------------------------------------------------------------------------
 // Intra-group pairs are cut into 64 x 64 tiles of points, dealt to all waves
 // so that a group of thousands of points does not rest on one wave.  Groups
@@ -717,6 +882,14 @@ __global__ __launch_bounds__(kBlock) void k_merge_tiles(Plan P)
         __builtin_amdgcn_wave_barrier();
         uint32_t root_i = core_i ? uf_find(P.parent, cube_i) : kNone;
         uint32_t root_j = core_j ? uf_find(P.parent, cube_j) : kNone;
+        {
+            // nothing to link when every cube of the tile already has one root
+            const uint32_t r0 = __shfl(root_i, __ffsll((unsigned long long)mi) - 1);
+            if (!__ballot((core_i && root_i != r0) || (core_j && root_j != r0))) {
+                __builtin_amdgcn_wave_barrier();
+                continue;
+            }
+        }
         uint64_t rows = mi;
         while (rows) {
             const uint32_t r = __ffsll((unsigned long long)rows) - 1;
@@ -803,59 +976,109 @@ __global__ __launch_bounds__(kBlock) void k_merge_unify(Plan P)
     }
 }
 
-template <int D, bool WIDE>
-__device__ void link_groups(const Plan &P, uint32_t GA, uint32_t GB, bool both_unified, uint32_t &lt)
+// Root shared by all core cubes of group G, or kNone when they have several
+// (read-only walks).  Two roots that agree prove their cubes joined even
+// when read at different moments, since sets only ever grow.
+__device__ uint32_t group_root(const Plan &P, uint32_t G)
 {
     const uint32_t l = lane_id();
-    const uint32_t a0 = P.group_start[GA], na = P.group_start[GA + 1] - a0;
-    const uint32_t b0 = P.group_start[GB], nb = P.group_start[GB + 1] - b0;
-    const uint64_t total = (uint64_t)na * nb;
-    if (both_unified) {
-        const uint32_t ca = P.gcube[GA], cb = P.gcube[GB];
-        if (uf_find(P.parent, ca) == uf_find(P.parent, cb)) return;
-        for (uint64_t base = 0; base < total; base += kWave) {
-            const uint64_t k = base + l;
-            bool hit = false;
-            if (k < total) {
-                const uint32_t i = (uint32_t)(k / nb), j = (uint32_t)(k - (uint64_t)i * nb);
-                const uint32_t pa = a0 + i, pb = b0 + j;
-                if (P.core[pa] && P.core[pb]) {
-                    lt++;
-                    hit = within<D, WIDE>(load_pt<D>(P.spts, pa), load_pt<D>(P.spts, pb), P.eps2);
-                }
-            }
-            if (__ballot(hit)) {
-                if (l == 0) uf_union(P.parent, ca, cb);
-                return;
-            }
-        }
-        return;
+    const uint32_t c0 = P.group_cell[G], c1 = P.group_cell[G + 1];
+    uint32_t r0 = kNone;
+    for (uint32_t cb = c0; cb < c1; cb += kWave) {
+        const uint32_t c = cb + l;
+        const uint32_t r = c < c1 && P.ncore[c] > 0 ? uf_root(P.parent, c) : kNone;
+        const uint64_t v = __ballot(r != kNone);
+        if (!v) continue;
+        if (r0 == kNone) r0 = __shfl(r, __ffsll((unsigned long long)v) - 1);
+        if (__ballot(r != kNone && r != r0)) return kNone;
     }
-    for (uint64_t base = 0; base < total; base += kWave) {
-        const uint64_t k = base + l;
-        if (k < total) {
-            const uint32_t i = (uint32_t)(k / nb), j = (uint32_t)(k - (uint64_t)i * nb);
-            const uint32_t pa = a0 + i, pb = b0 + j;
-            if (P.core[pa] && P.core[pb] && (++lt, true) &&
-                within<D, WIDE>(load_pt<D>(P.spts, pa), load_pt<D>(P.spts, pb), P.eps2)) {
-                const uint32_t x = P.cell_of[pa], y = P.cell_of[pb];
-                if (uf_find(P.parent, x) != uf_find(P.parent, y)) uf_union(P.parent, x, y);
+    return r0;
+}
+
+// Core pairs of groups GA x GB in 64 x 64 tiles: 64 points of GA staged in
+// LDS are visited one at a time against 64 points of GB in the lanes.  When
+// each group's core cubes already share one root, the two roots decide:
+// equal means nothing to do, otherwise the first pair within eps joins them
+// and ends the search.  Otherwise every pair within eps links its two cubes
+// unless their cached roots already agree.
+// ra and rb are cubes that stand for all core cubes of GA and GB, or kNone
+// when not known; those are then looked up.
+template <int D, bool WIDE>
+__device__ void link_pair(const Plan &P, uint32_t GA, uint32_t GB, uint32_t ra, uint32_t rb,
+                          int32_t (*s_pt)[D], uint32_t &lt)
+{
+    const uint32_t l = lane_id();
+    if (ra == kNone) ra = group_root(P, GA);
+    if (ra != kNone && rb == kNone) rb = group_root(P, GB);
+    const bool single = ra != kNone && rb != kNone;
+    if (single && uf_find(P.parent, ra) == uf_find(P.parent, rb)) return;
+    const uint32_t a0 = P.group_start[GA], a1 = P.group_start[GA + 1];
+    const uint32_t b0 = P.group_start[GB], b1 = P.group_start[GB + 1];
+    for (uint32_t ia = a0; ia < a1; ia += kWave) {
+        const uint32_t qi = ia + l;
+        const bool core_i = qi < a1 && P.core[qi];
+        const uint64_t mi = __ballot(core_i);
+        if (!mi) continue;
+        const Pt<D> pi = load_pt<D>(P.spts, core_i ? qi : a0);
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int e = 0; e < D; e++) s_pt[l][e] = pi.x[e];
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t cube_i = !single && core_i ? P.cell_of[qi] : kNone;
+        uint32_t root_i = !single && core_i ? uf_find(P.parent, cube_i) : kNone;
+        for (uint32_t jb = b0; jb < b1; jb += kWave) {
+            const uint32_t qj = jb + l;
+            const bool core_j = qj < b1 && P.core[qj];
+            if (!__ballot(core_j)) continue;
+            const Pt<D> pj = load_pt<D>(P.spts, core_j ? qj : b0);
+            const uint32_t cube_j = !single && core_j ? P.cell_of[qj] : kNone;
+            uint32_t root_j = !single && core_j ? uf_find(P.parent, cube_j) : kNone;
+            uint64_t rows = mi;
+            while (rows) {
+                const uint32_t r = __ffsll((unsigned long long)rows) - 1;
+                rows &= rows - 1;
+                Pt<D> pr;
+#pragma unroll
+                for (int e = 0; e < D; e++) pr.x[e] = s_pt[r][e];
+                lt += core_j;
+                const bool hit = core_j && within<D, WIDE>(pr, pj, P.eps2);
+                if (single) {
+                    if (__ballot(hit)) {
+                        if (l == 0) uf_union(P.parent, ra, rb);
+                        return;
+                    }
+                    continue;
+                }
+                const uint32_t cr = __shfl(cube_i, r), rr = __shfl(root_i, r);
+                const bool need = hit && root_j != rr;
+                if (__ballot(need)) {
+                    if (need) uf_union(P.parent, cr, cube_j);
+                    root_j = core_j ? uf_find(P.parent, cube_j) : kNone;
+                    root_i = core_i ? uf_find(P.parent, cube_i) : kNone;
+                }
             }
         }
     }
 }
 
+// Inter: each group GA with core points walks its neighbour groups GB > GA
+// that have core points and whose box comes within eps of GA's core points.
+// When both groups are unified, their roots are compared on the spot and a
+// pair with different roots is searched right away; the other pairs go to
+// the worklist (a full region links its pairs on the spot).
 template <int D, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_merge_inter(Plan P)
 {
-    const uint32_t l = lane_id();
-    const bool lists = lists_ready(P);
+    __shared__ int32_t s_pt[kWavesPerBlock][kWave][D];
+    const uint32_t w = wave_in_block(), l = lane_id();
+    const uint32_t region = (blockIdx.x * kWavesPerBlock + w) % kWorkRegions;
+    const uint32_t cap = P.work_cap / kWorkRegions;
     uint32_t lt = 0;
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
     const WaveRange hca_wr_ = wave_range();
     HCA_FOR_UNITS(GA, ng) {
         const uint32_t ga = P.gcube[GA];
-        if (ga == kNone) continue;                        // no core point
+        if (ga == kNone) continue;                                 // no core point
         const bool ua = P.unified[GA];
         const uint64_t gkey = P.group_key[GA];
         // bounding box of GA's core points
@@ -872,16 +1095,16 @@ __global__ __launch_bounds__(kBlock) void k_merge_inter(Plan P)
         }
 #pragma unroll
         for (int e = 0; e < D; e++) { qb.lo[e] = wave_min(qb.lo[e]); qb.hi[e] = wave_max(qb.hi[e]); }
-        const NbrSrc src = nbr_source(P, GA, lists);
+        const NbrSrc src = nbr_source(P, GA);
         for (uint32_t oc = 1; oc < src.slots; oc += kWave) {
             const uint32_t j = oc + l;
             uint32_t GB = kNone;
-            bool need = false, both = false;
+            bool both = false, differ = false;
             if (j < src.slots) {
                 uint64_t nk = ~0ull;
                 if (src.lists) {
-                    GB = P.nbr[src.start + j - 1];
-                    if (GB > GA) nk = P.group_key[GB]; else GB = kNone;
+                    const uint32_t G = P.nbr[src.start + j - 1];
+                    if (G > GA) { GB = G; nk = P.group_key[G]; }
                 } else {
                     // groups are numbered in key order: GB > GA exactly when
                     // the first non-zero component of the offset is positive
@@ -894,23 +1117,65 @@ __global__ __launch_bounds__(kBlock) void k_merge_inter(Plan P)
                 }
                 if (nk != ~0ull && group_box_within<D>(P, nk, qb)) {
                     if (!src.lists) GB = group_lookup(P, nk);
-                    if (GB != kNone && P.gcube[GB] != kNone) {
-                        both = ua && P.unified[GB];
-                        need = !both || uf_find(P.parent, ga) != uf_find(P.parent, P.gcube[GB]);
-                    }
+                    if (GB != kNone && P.gcube[GB] == kNone) GB = kNone;
                 } else {
                     GB = kNone;
                 }
+                if (GB != kNone && ua && P.unified[GB]) {
+                    both = true;
+                    differ = uf_find(P.parent, ga) != uf_find(P.parent, P.gcube[GB]);
+                }
             }
-            uint64_t m = __ballot(need);
-            while (m) {
-                const uint32_t src = __ffsll((unsigned long long)m) - 1;
-                const uint32_t gb = __shfl(GB, src);
-                const bool bu = __shfl((int)both, src) != 0;
-                link_groups<D, WIDE>(P, GA, gb, bu, lt);
-                m &= m - 1;
+            uint64_t now = __ballot(both && differ);
+            while (now) {
+                const uint32_t src_lane = __ffsll((unsigned long long)now) - 1;
+                const uint32_t gb = __shfl(GB, src_lane);
+                link_pair<D, WIDE>(P, GA, gb, ga, P.gcube[gb], s_pt[w], lt);
+                now &= now - 1;
+            }
+            if (both) GB = kNone;
+            const uint64_t m = __ballot(GB != kNone);
+            if (!m) continue;
+            uint32_t base = 0;
+            if (l == 0) base = atomicAdd(P.ctr->work_count + region * kCounterStride, (uint32_t)__popcll(m));
+            base = __shfl(base, 0);
+            const uint32_t slot = base + __popcll(m & __lanemask_lt());
+            const bool spill = GB != kNone && slot >= cap;
+            if (GB != kNone && !spill) {
+                const uint64_t at = (uint64_t)region * cap + slot;
+                P.work[2ull * at] = GA;
+                P.work[2ull * at + 1] = GB;
+            }
+            uint64_t sm = __ballot(spill);
+            while (sm) {
+                const uint32_t src_lane = __ffsll((unsigned long long)sm) - 1;
+                link_pair<D, WIDE>(P, GA, __shfl(GB, src_lane), kNone, kNone, s_pt[w], lt);
+                sm &= sm - 1;
             }
         }
+    }
+    flush_tests(P, kTestsMerge, lt);
+}
+
+// The queued group pairs, one per wave at a time over all waves.
+template <int D, bool WIDE>
+__global__ __launch_bounds__(kBlock) void k_merge_pairs(Plan P)
+{
+    __shared__ uint32_t s_pre[kWavesPerBlock][kWorkRegions];
+    __shared__ int32_t s_pt[kWavesPerBlock][kWave][D];
+    const uint32_t w = wave_in_block(), l = lane_id();
+    const uint32_t cap = P.work_cap / kWorkRegions;
+    const uint32_t cnt = min(ld_agent32(P.ctr->work_count + l * kCounterStride), cap);
+    const uint32_t inc = wave_inclusive_scan(cnt);
+    s_pre[w][l] = inc - cnt;
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t items = __shfl(inc, kWave - 1);
+    uint32_t lt = 0;
+    const WaveRange hca_wr_ = wave_range();
+    HCA_FOR_UNITS(it, items) {
+        const uint32_t r = candidate_lane(it, s_pre[w]);
+        const uint64_t at = (uint64_t)r * cap + (it - s_pre[w][r]);
+        link_pair<D, WIDE>(P, P.work[2ull * at], P.work[2ull * at + 1], kNone, kNone, s_pt[w], lt);
     }
     flush_tests(P, kTestsMerge, lt);
 }
@@ -947,6 +1212,81 @@ __global__ __launch_bounds__(kBlock) void k_compress(Plan P)
 }
 
 // ---------------------------------------------------------------------------
+// Nearest core point within eps (ties: smaller input index) of each chunk
+// point flagged in `todo`, over group g and its neighbour groups; per lane
+// partial bests in bd (squared distance), bi (input index), bp (position).
+template <int D, bool WIDE>
+__device__ __forceinline__ void border_walk(const Plan &P, uint32_t g, uint64_t gkey, const Pt<D> *pp,
+                                            uint32_t todo, int64_t *bd, uint32_t *bi, uint32_t *bp,
+                                            uint32_t *s_beg, uint32_t *s_pre, uint32_t &lt)
+{
+    const uint32_t l = lane_id();
+    const QBox<D> qb = chunk_box<D>(pp, todo);
+    const NbrSrc src = nbr_source(P, g);
+    for (uint32_t oc = 0; oc < src.slots; oc += kWave) {
+        const uint32_t total = load_neighbours<D>(P, g, gkey, src, oc, 0, true, qb, s_beg, s_pre);
+        for (uint32_t ci = 0; ci < total; ci += kWave) {
+            const uint32_t c = ci + l;
+            bool ok = c < total;
+            uint32_t pos = 0;
+            if (ok) {
+                const uint32_t ln = candidate_lane(c, s_pre);
+                pos = s_beg[ln] + (c - s_pre[ln]);
+                ok = P.core[pos] != 0;
+            }
+            if (!__ballot(ok)) continue;
+            const Pt<D> q = load_pt<D>(P.spts, pos);
+            int64_t dd[kPch];
+            bool near = false;
+#pragma unroll
+            for (int k = 0; k < kPch; k++) {
+                if (todo & (1u << k)) lt += ok;
+                dd[k] = dist2<D, WIDE>(pp[k], q);
+                near |= (todo & (1u << k)) && ok && dd[k] <= P.eps2 && dd[k] <= bd[k];
+            }
+            if (!near) continue;
+            const uint32_t qi = P.sidx[pos];
+#pragma unroll
+            for (int k = 0; k < kPch; k++) {
+                if (!(todo & (1u << k))) continue;
+                if (ok && dd[k] <= P.eps2 && (dd[k] < bd[k] || (dd[k] == bd[k] && qi < bi[k]))) {
+                    bd[k] = dd[k]; bi[k] = qi; bp[k] = pos;
+                }
+            }
+        }
+    }
+}
+
+// Reduce the per-lane bests over the wave; each point flagged in `todo`
+// takes the root of its nearest core point (kNone: noise) and, when it has
+// one, offers its input index to that cluster's smallest member.
+__device__ __forceinline__ void border_finish(const Plan &P, uint32_t pc, uint32_t todo, const int64_t *bd,
+                                              const uint32_t *bi, const uint32_t *bp)
+{
+    const uint32_t l = lane_id();
+#pragma unroll
+    for (int k = 0; k < kPch; k++) {
+        if (!(todo & (1u << k))) continue;
+        int64_t d0 = bd[k];
+        uint32_t i0 = bi[k], q0 = bp[k];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const int64_t d1 = __shfl_xor(d0, o);
+            const uint32_t i1 = __shfl_xor(i0, o), q1 = __shfl_xor(q0, o);
+            if (d1 < d0 || (d1 == d0 && i1 < i0)) { d0 = d1; i0 = i1; q0 = q1; }
+        }
+        if (l == 0) {
+            const uint32_t root = q0 == kNone ? kNone : ld_parent(P.parent + P.cell_of[q0]);
+            P.owner[pc + k] = root;
+            if (root != kNone) {
+                const uint32_t me = P.sidx[pc + k];
+                if (me < ld_agent32(P.minmem + root)) atomicMin(P.minmem + root, me);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Border points: each non-core point takes the root of its nearest core
 // point within eps, ties to the smaller input index; none -> noise.
 // ---------------------------------------------------------------------------
@@ -955,7 +1295,6 @@ __global__ __launch_bounds__(kBlock) void k_border(Plan P)
 {
     __shared__ uint32_t s_beg[kWavesPerBlock][kWave], s_pre[kWavesPerBlock][kWave];
     const uint32_t w = wave_in_block(), l = lane_id();
-    const bool lists = lists_ready(P);
     uint32_t lt = 0;
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
     const WaveRange hca_wr_ = wave_range();
@@ -973,66 +1312,47 @@ __global__ __launch_bounds__(kBlock) void k_border(Plan P)
                 if (k < (int)np && !P.core[pc + k]) todo |= 1u << k;
             todo = uniform(todo);
             if (!todo) continue;
-            const QBox<D> qb = chunk_box<D>(pp, todo);
             int64_t bd[kPch];
             uint32_t bi[kPch], bp[kPch];
 #pragma unroll
             for (int k = 0; k < kPch; k++) { bd[k] = INT64_MAX; bi[k] = kNone; bp[k] = kNone; }
-            const NbrSrc src = nbr_source(P, g, lists);
-            for (uint32_t oc = 0; oc < src.slots; oc += kWave) {
-                const uint32_t total =
-                    load_neighbours<D>(P, g, gkey, src, oc, 0, true, qb, s_beg[w], s_pre[w]);
-                for (uint32_t ci = 0; ci < total; ci += kWave) {
-                    const uint32_t c = ci + l;
-                    bool ok = c < total;
-                    uint32_t pos = 0;
-                    if (ok) {
-                        const uint32_t ln = candidate_lane(c, s_pre[w]);
-                        pos = s_beg[w][ln] + (c - s_pre[w][ln]);
-                        ok = P.core[pos] != 0;
-                    }
-                    if (!__ballot(ok)) continue;
-                    const Pt<D> q = load_pt<D>(P.spts, pos);
-                    int64_t dd[kPch];
-                    bool near = false;
-#pragma unroll
-                    for (int k = 0; k < kPch; k++) {
-                        if (todo & (1u << k)) lt += ok;
-                        dd[k] = dist2<D, WIDE>(pp[k], q);
-                        near |= (todo & (1u << k)) && ok && dd[k] <= P.eps2 && dd[k] <= bd[k];
-                    }
-                    if (!near) continue;
-                    const uint32_t qi = P.sidx[pos];
-#pragma unroll
-                    for (int k = 0; k < kPch; k++) {
-                        if (!(todo & (1u << k))) continue;
-                        if (ok && dd[k] <= P.eps2 && (dd[k] < bd[k] || (dd[k] == bd[k] && qi < bi[k]))) {
-                            bd[k] = dd[k]; bi[k] = qi; bp[k] = pos;
-                        }
-                    }
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < kPch; k++) {
-                if (!(todo & (1u << k))) continue;
-                int64_t d0 = bd[k];
-                uint32_t i0 = bi[k], q0 = bp[k];
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) {
-                    const int64_t d1 = __shfl_xor(d0, o);
-                    const uint32_t i1 = __shfl_xor(i0, o), q1 = __shfl_xor(q0, o);
-                    if (d1 < d0 || (d1 == d0 && i1 < i0)) { d0 = d1; i0 = i1; q0 = q1; }
-                }
-                if (l == 0) {
-                    const uint32_t root = q0 == kNone ? kNone : ld_parent(P.parent + P.cell_of[q0]);
-                    P.owner[pc + k] = root;
-                    if (root != kNone) {
-                        const uint32_t me = P.sidx[pc + k];
-                        if (me < ld_agent32(P.minmem + root)) atomicMin(P.minmem + root, me);
-                    }
-                }
-            }
+            border_walk<D, WIDE>(P, g, gkey, pp, todo, bd, bi, bp, s_beg[w], s_pre[w], lt);
+            border_finish(P, pc, todo, bd, bi, bp);
         }
+    }
+    flush_tests(P, kTestsBorder, lt);
+}
+
+// Group mode: chunks of kPch consecutive sorted points, walked group by
+// group, as in core marking.
+template <int D, bool WIDE>
+__global__ __launch_bounds__(kBlock) void k_border_chunks(Plan P)
+{
+    __shared__ uint32_t s_beg[kWavesPerBlock][kWave], s_pre[kWavesPerBlock][kWave];
+    const uint32_t w = wave_in_block(), l = lane_id();
+    const uint32_t n = P.n;
+    uint32_t lt = 0;
+    const WaveRange hca_wr_ = wave_range();
+    HCA_FOR_UNITS(u, (n + kPch - 1) / kPch) {
+        const uint32_t pc = u * kPch, np = min((uint32_t)kPch, n - pc);
+        const bool mine = l < np && !P.core[pc + l];
+        const uint32_t todo = (uint32_t)__ballot(mine) & ((1u << kPch) - 1u);
+        if (!todo) continue;
+        const uint32_t grp = mine ? P.group_of[P.cell_of[pc + l]] : kNone;
+        Pt<D> pp[kPch];
+        load_chunk<D>(P, pc, np, pp);
+        int64_t bd[kPch];
+        uint32_t bi[kPch], bp[kPch];
+#pragma unroll
+        for (int k = 0; k < kPch; k++) { bd[k] = INT64_MAX; bi[k] = kNone; bp[k] = kNone; }
+        uint32_t left = todo;
+        while (left) {
+            const uint32_t g = __shfl(grp, __ffs(left) - 1);
+            const uint32_t run = (uint32_t)__ballot(grp == g) & left;
+            left &= ~run;
+            border_walk<D, WIDE>(P, g, P.group_key[g], pp, run, bd, bi, bp, s_beg[w], s_pre[w], lt);
+        }
+        border_finish(P, pc, todo, bd, bi, bp);
     }
     flush_tests(P, kTestsBorder, lt);
 }
@@ -1177,32 +1497,25 @@ void launch_table(const Plan &P, int blocks, hipStream_t s)
     hipLaunchKernelGGL(k_table, dim3(blocks), dim3(kBlock), 0, s, P);
 }
 
-#define HCA_DISPATCH_D_FILL(FILL, P, blocks, s)                                                      \
-    do {                                                                                             \
-        switch ((P).d) {                                                                             \
-        case 1: hipLaunchKernelGGL((k_nbr_lists<1, FILL>), dim3(blocks), dim3(kBlock), 0, s, P); break; \
-        case 2: hipLaunchKernelGGL((k_nbr_lists<2, FILL>), dim3(blocks), dim3(kBlock), 0, s, P); break; \
-        case 3: hipLaunchKernelGGL((k_nbr_lists<3, FILL>), dim3(blocks), dim3(kBlock), 0, s, P); break; \
-        case 4: hipLaunchKernelGGL((k_nbr_lists<4, FILL>), dim3(blocks), dim3(kBlock), 0, s, P); break; \
-        case 5: hipLaunchKernelGGL((k_nbr_lists<5, FILL>), dim3(blocks), dim3(kBlock), 0, s, P); break; \
-        case 6: hipLaunchKernelGGL((k_nbr_lists<6, FILL>), dim3(blocks), dim3(kBlock), 0, s, P); break; \
-        case 7: hipLaunchKernelGGL((k_nbr_lists<7, FILL>), dim3(blocks), dim3(kBlock), 0, s, P); break; \
-        case 8: hipLaunchKernelGGL((k_nbr_lists<8, FILL>), dim3(blocks), dim3(kBlock), 0, s, P); break; \
-        }                                                                                            \
-    } while (0)
-
 void launch_lists(const Plan &P, int blocks, hipStream_t s)
 {
     if (!P.nbr_cap) return;
-    HCA_DISPATCH_D_FILL(false, P, blocks, s);
-    const uint32_t tiles = (P.n + kScanTile - 1) / kScanTile;
-    hipLaunchKernelGGL(k_nbr_scan, dim3(tiles), dim3(kBlock), 0, s, P, P.nbr_status, &P.ctr->nbr_ticket);
-    HCA_DISPATCH_D_FILL(true, P, blocks, s);
+    switch (P.d) {
+    case 1: hipLaunchKernelGGL(k_nbr_lists<1>, dim3(blocks), dim3(kBlock), 0, s, P); break;
+    case 2: hipLaunchKernelGGL(k_nbr_lists<2>, dim3(blocks), dim3(kBlock), 0, s, P); break;
+    case 3: hipLaunchKernelGGL(k_nbr_lists<3>, dim3(blocks), dim3(kBlock), 0, s, P); break;
+    case 4: hipLaunchKernelGGL(k_nbr_lists<4>, dim3(blocks), dim3(kBlock), 0, s, P); break;
+    case 5: hipLaunchKernelGGL(k_nbr_lists<5>, dim3(blocks), dim3(kBlock), 0, s, P); break;
+    case 6: hipLaunchKernelGGL(k_nbr_lists<6>, dim3(blocks), dim3(kBlock), 0, s, P); break;
+    case 7: hipLaunchKernelGGL(k_nbr_lists<7>, dim3(blocks), dim3(kBlock), 0, s, P); break;
+    case 8: hipLaunchKernelGGL(k_nbr_lists<8>, dim3(blocks), dim3(kBlock), 0, s, P); break;
+    }
 }
 
 void launch_core(const Plan &P, int blocks, hipStream_t s)
 {
-    HCA_DISPATCH_DW(k_core, P, blocks, s);
+    if (P.m > 1) HCA_DISPATCH_DW(k_core_chunks, P, blocks, s);
+    else HCA_DISPATCH_DW(k_core, P, blocks, s);
 }
 
 void launch_reps(const Plan &P, int blocks, hipStream_t s)
@@ -1226,6 +1539,7 @@ void launch_merge(const Plan &P, int blocks, hipStream_t s)
         HCA_DISPATCH_DW(k_merge_tiles, P, blocks, s);
         HCA_DISPATCH_DW(k_merge_unify, P, blocks, s);
         HCA_DISPATCH_DW(k_merge_inter, P, blocks, s);
+        HCA_DISPATCH_DW(k_merge_pairs, P, blocks, s);
     }
 }
 
@@ -1236,7 +1550,8 @@ void launch_compress(const Plan &P, int blocks, hipStream_t s)
 
 void launch_border(const Plan &P, int blocks, hipStream_t s)
 {
-    HCA_DISPATCH_DW(k_border, P, blocks, s);
+    if (P.m > 1) HCA_DISPATCH_DW(k_border_chunks, P, blocks, s);
+    else HCA_DISPATCH_DW(k_border, P, blocks, s);
 }
 
 void launch_labels(const Plan &P, uint64_t *status, uint32_t *ticket, hipStream_t s)

@@ -46,9 +46,8 @@ struct Counters {
     uint32_t n_clusters;
     uint32_t n_tiles;           // intra-group point tiles
     uint32_t tile_ticket;
-    uint32_t n_nbr;             // entries of the neighbour-group lists
-    uint32_t nbr_ticket;
-    uint32_t pad[9];
+    uint32_t nbr_overflow;      // groups whose neighbour list did not fit
+    uint32_t pad[10];
     uint32_t work_count[kWorkRegions * kCounterStride];   // region r at [r * kCounterStride]
     // pair tests executed, per phase (core, merge, border), spread over
     // kWorkRegions lines of eight 64-bit words; counted only on request
@@ -110,13 +109,15 @@ struct Plan {
     uint32_t *gcube;            // [n] group -> first cube with a core point, kNone if none
     uint8_t *unified;           // [n] group -> its core cubes share one union-find root
     uint32_t *tile_start;       // [n] group -> first intra-group tile
-    // group mode: non-empty neighbour groups of each group (self excluded),
-    // nearest offsets first; used when they fit in nbr_cap entries
+    // group mode: the non-empty neighbour groups of each group (self
+    // excluded) that can hold a point within eps of one of its points.  Each
+    // wave fills its own slab of nbr_cap / waves entries; a group whose list
+    // does not fit gets nbr_count = kNone and is searched over the stencil.
     uint32_t nbr_cap;
     uint32_t *nbr_count;        // [n]
     uint32_t *nbr_start;        // [n]
     uint32_t *nbr;              // [nbr_cap]
-    uint64_t *nbr_status;       // look-back words of the list scan
+    uint32_t *group_of;         // [n] cube -> its group
     uint64_t *tile_status;      // look-back words of the tile scan
     uint32_t *work;             // [2 * work_cap] cube pairs for exact tests
     uint32_t work_cap;          // multiple of kWorkRegions
