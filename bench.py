@@ -2,10 +2,11 @@
 """Throughput of exact hypercube-grid DBSCAN on one MI355X.
 
 One step = one full clustering call (bounding box, cube keys and radix sort,
-cube tables, core points, representatives, merging, border points, canonical
-labels) over the 2-D 1M-point workload, points already resident in HBM.
-Prints one JSON line.  The CPU oracle (the paper's method run on the host) is
-timed beside it as a reported baseline.
+cube tables, neighbour-group lists, core points, representatives, merging,
+border points, canonical labels) over one synthetic workload whose points are
+already resident in HBM.  Default workload: 2-D, 1M points.  Prints one JSON
+line.  The CPU oracle (the paper's grid method run on the host) is timed on a
+bounded sample beside it as a reported baseline.
 """
 from __future__ import annotations
 
@@ -23,16 +24,25 @@ sys.path.insert(0, str(ROOT))
 
 METRIC = "points clustered/s (2-D 1M, 8-D 500k) vs HBM roofline; served p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-# int32 VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 lane-ops/s
+# int32 VALU lane-ops: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 /s
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 WORKLOADS = {"2d": 2, "8d": 3, "small": 1}
 HBM_PHASES = ("bbox", "sort", "cells", "labels")
-ALU_PHASES = {"core": "tests_core", "merge": "tests_merge", "border": "tests_border"}
+ALU_PHASES = {"core": "tests_core", "intra": "tests_intra", "merge": "tests_merge",
+              "border": "tests_border"}
+PHASE_KERNELS = {
+    "bbox": ["k_bbox"], "sort": ["k_keys_hist", "k_onesweep"], "cells": ["k_cells", "k_table"],
+    "lists": ["k_nbr_lists"], "core": ["k_core", "k_core_chunks"], "reps": ["k_reps"],
+    "intra": ["k_tile_scan", "k_merge_tiles", "k_merge_unify"],
+    "merge": ["k_merge_rep", "k_merge_exact", "k_merge_inter", "k_merge_pairs", "k_compress"],
+    "border": ["k_border", "k_border_chunks"],
+    "labels": ["k_label_marks", "k_label_scan", "k_label_cubes", "k_label_write"],
+}
 
 
 def algorithmic_bytes(phase: str, n: int, d: int, key_bytes: int, passes: int, cells: int) -> float:
-    """Bytes the method must move in a phase per call, independent of how the
-    kernels happen to move them (per-point figures x n)."""
+    """Bytes a phase must move per call whatever the kernels do (per point and
+    per cube figures times the counts)."""
     if phase == "bbox":
         return 4.0 * d * n                                   # read the points
     if phase == "sort":
@@ -43,7 +53,7 @@ def algorithmic_bytes(phase: str, n: int, d: int, key_bytes: int, passes: int, c
     if phase == "cells":
         return n * (key_bytes + 4.0) + cells * 16.0           # read keys, write cube ids + tables
     if phase == "labels":
-        # core flag, cube or owner, sorted index read; label written; + per cube
+        # core flag, cube or owner, input index read; label written; + per cube
         return n * (1.0 + 4.0 + 4.0 + 4.0) + cells * 16.0
     return 0.0
 
@@ -56,9 +66,9 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, workload: str):
-    """HBM bytes per launch from a committed rocprofv3 PMC summary, if it was
-    taken on the current kernel sources; else None."""
+def measured_traffic(phase: str, workload: str):
+    """HBM bytes per call of a phase from the committed rocprofv3 PMC summary,
+    if it was taken on the current kernel sources; else None."""
     f = ROOT / "profiles" / "pmc_traffic.json"
     if not f.exists():
         return None
@@ -66,26 +76,41 @@ def measured_traffic(kernel: str, workload: str):
         data = json.loads(f.read_text())
     except ValueError:
         return None
-    e = data.get("entries", {}).get(f"{workload}:{kernel}")
+    e = data.get("entries", {}).get(f"{workload}:{phase}")
     if not e or e.get("source_digest") != kernel_source_digest():
         return None
-    return e.get("bytes_per_launch")
+    return e.get("bytes_per_call")
 
 
 def cpu_baseline(w, budget_s: float = 25.0) -> dict:
+    """The oracle's grid method on the host cores, on the whole workload when
+    it finishes within the budget, else on the first m points of the input
+    (which is in random order), m doubling from 20k while runs stay short."""
     import oracle
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    times = []
     t_all = time.perf_counter()
-    while len(times) < 3 and time.perf_counter() - t_all < budget_s:
+    m = min(w.n, 20_000)
+    while True:
         t0 = time.perf_counter()
-        oracle.hca_grid(w.points, w.eps, w.min_pts, threads=threads)
+        oracle.hca_grid(w.points[:m], w.eps, w.min_pts, threads=threads)
+        t = time.perf_counter() - t0
+        # the cost grows at least linearly in m: stop before overrunning
+        if m == w.n or t * 4 > budget_s - (time.perf_counter() - t_all):
+            break
+        m = min(w.n, 2 * m)
+    times = [t]
+    while len(times) < 3 and time.perf_counter() - t_all + t < budget_s:
+        t0 = time.perf_counter()
+        oracle.hca_grid(w.points[:m], w.eps, w.min_pts, threads=threads)
         times.append(time.perf_counter() - t0)
     t = statistics.median(times)
-    return {"value": w.n / t, "unit": "points/s", "cores": threads, "kind": "oracle",
-            "sample": f"the whole {w.name} workload (n={w.n}), the paper's hypercube method on "
-                      f"the CPU (oracle/hca_grid.c: OpenMP over points for core marking and "
-                      f"borders, sequential depth-first merge), median of {len(times)} run(s)"}
+    what = (f"the whole {w.name} workload (n={w.n})" if m == w.n else
+            f"the first {m} of the {w.n} points of {w.name} (same eps and minPts; lower density "
+            f"than the whole set, so the per-point rate flatters the CPU)")
+    return {"value": m / t, "unit": "points/s", "cores": threads, "kind": "oracle",
+            "sample": f"{what}; the paper's hypercube method in plain C (oracle/hca_grid.c: OpenMP "
+                      f"over points for core marking and borders, sequential depth-first merge), "
+                      f"median of {len(times)} run(s)"}
 
 
 def main() -> int:
@@ -115,53 +140,64 @@ def main() -> int:
 
     for _ in range(args.warmup):
         ctx.cluster(pts, w.eps, w.min_pts, out=labels)
-    _, stats = ctx.cluster(pts, w.eps, w.min_pts, out=labels, stats=True)
 
-    # timed region: K whole clustering calls, inputs resident in HBM
+    # per-phase breakdown and pair-test counts (HIP events on the library's
+    # stream around every phase), outside the timed region
+    ctx.set_profiling("all")
+    acc = {p: [] for p in hca.PHASES}
+    tests = {k: [] for k in ALU_PHASES.values()}
+    stats = None
+    for _ in range(max(3, min(args.steps, 10))):
+        _, stats = ctx.cluster(pts, w.eps, w.min_pts, out=labels, stats=True)
+        for p, v in ctx.phase_times().items():
+            acc[p].append(v)
+        for k in tests:
+            tests[k].append(stats[k])
+    phase_ms = {p: statistics.mean(v) for p, v in acc.items()}
+    dominant = max(phase_ms, key=phase_ms.get)
+
+    # timed region: K whole clustering calls, inputs resident in HBM; only the
+    # dominant phase is bracketed by HIP events (two per call)
+    ctx.set_profiling(dominant)
+    dom_ms = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ctx.cluster(pts, w.eps, w.min_pts, out=labels)
+        dom_ms.append(ctx.phase_times()[dominant])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    ms_per_step = dt * 1e3 / args.steps
-
-    # per-phase durations from HIP events the library records on its own
-    # stream around each phase, and pair-test counts, over K more calls
-    ctx.set_profiling("all")
-    acc = {p: [] for p in hca.PHASES}
-    tests = {k: [] for k in ALU_PHASES.values()}
-    for _ in range(args.steps):
-        _, st = ctx.cluster(pts, w.eps, w.min_pts, out=labels, stats=True)
-        for p, v in ctx.phase_times().items():
-            acc[p].append(v)
-        for k in tests:
-            tests[k].append(st[k])
     ctx.set_profiling(None)
-    phase_ms = {p: statistics.mean(v) for p, v in acc.items()}
+    ms_per_step = dt * 1e3 / args.steps
+    dom = statistics.mean(dom_ms)
     key_bytes = 8 if stats["key_bits"] > 32 else 4
 
-    def hbm_roofline(phase):
+    def hbm_roofline(phase, ms):
         ab = algorithmic_bytes(phase, w.n, w.d, key_bytes, stats["sort_passes"], stats["n_cells"])
-        achieved = ab / (phase_ms[phase] * 1e-3) / 1e9
-        return {"bound": "hbm", "phase": phase, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(phase, w.name), "algorithmic_bytes": ab}
+        achieved = ab / (ms * 1e-3) / 1e9
+        return {"bound": "hbm", "phase": phase, "kernels": PHASE_KERNELS[phase],
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(phase, w.name),
+                "algorithmic_bytes": ab, "phase_ms": round(ms, 4)}
 
-    def alu_roofline(phase):
+    def alu_roofline(phase, ms):
         n_tests = statistics.mean(tests[ALU_PHASES[phase]])
-        ops = 3.0 * w.d * n_tests                        # d sub + d mul + d-1 add + compare
-        achieved = ops / (phase_ms[phase] * 1e-3) / 1e12
-        return {"bound": "alu", "phase": phase, "achieved": round(achieved, 4), "peak": round(ALU_PEAK_TOPS, 2),
+        ops = 3.0 * w.d * n_tests                        # d sub + d mul + (d-1) add + compare
+        achieved = ops / (ms * 1e-3) / 1e12
+        return {"bound": "alu", "phase": phase, "kernels": PHASE_KERNELS[phase],
+                "achieved": round(achieved, 4), "peak": round(ALU_PEAK_TOPS, 2),
                 "unit": "Tops/s (int32 lane-ops)", "frac": round(achieved / ALU_PEAK_TOPS, 5),
                 "traffic": measured_traffic(phase, w.name), "pair_tests": n_tests,
-                "ops_per_test": 3 * w.d}
+                "ops_per_test": 3 * w.d, "phase_ms": round(ms, 4)}
 
-    dominant = max(phase_ms, key=phase_ms.get)
-    roofline = alu_roofline(dominant) if dominant in ALU_PHASES else (
-        hbm_roofline(dominant) if dominant in HBM_PHASES else
-        {"bound": "alu", "phase": dominant, "achieved": None, "peak": round(ALU_PEAK_TOPS, 2),
-         "unit": "Tops/s (int32 lane-ops)", "frac": None, "traffic": None})
+    if dominant in ALU_PHASES:
+        roofline = alu_roofline(dominant, dom)
+    elif dominant in HBM_PHASES:
+        roofline = hbm_roofline(dominant, dom)
+    else:
+        roofline = {"bound": "alu", "phase": dominant, "kernels": PHASE_KERNELS[dominant],
+                    "achieved": None, "peak": round(ALU_PEAK_TOPS, 2), "unit": "Tops/s (int32 lane-ops)",
+                    "frac": None, "traffic": measured_traffic(dominant, w.name), "phase_ms": round(dom, 4)}
 
     line = {
         "metric": METRIC,
@@ -179,8 +215,8 @@ def main() -> int:
         "config": {"workload": w.name, "n": w.n, "d": w.d, "eps": w.eps, "min_pts": w.min_pts,
                    "fixed_point_bits": w.q, "parallelism": "single-gpu"},
         "roofline": roofline,
-        "roofline_binning_sort": hbm_roofline("sort"),
-        "phase_ms": {p: round(v, 4) for p, v in phase_ms.items()},
+        "roofline_binning_sort": hbm_roofline("sort", phase_ms["sort"]),
+        "phase_ms": {p: round(v, 4) for p, v in phase_ms.items() if v > 0},
         "stats": stats,
     }
     if not args.no_cpu_baseline:

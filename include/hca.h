@@ -84,19 +84,22 @@ typedef struct {
     int64_t n_core_points;
     int64_t n_clusters;
     int64_t n_noise;
-    int64_t exact_pairs;      /* cube pairs whose representatives were not within eps */
+    int64_t exact_pairs;      /* cube pairs (one cube per group) or pairs of not yet unified
+                               * groups (m > 1) queued for the exact all-pairs test */
     int32_t key_bits;         /* bits of the packed cube key */
     int32_t sort_passes;      /* radix passes of the cube-key sort */
     int32_t group;            /* cubes per group side used */
     int32_t wide;             /* 1 if squared distances were computed in 64 bits */
     int32_t dense_table;      /* 1 if the group lookup was a direct-indexed table */
-    int32_t reserved;
+    int32_t list_overflow;    /* groups searched over the whole stencil because their
+                               * neighbour list did not fit its slab (m > 1) */
     /* point-pair distance tests executed by core marking, merging and border
      * assignment; counted only while phase profiling is on (hca_set_profiling),
      * else 0 */
     int64_t tests_core;
-    int64_t tests_merge;
+    int64_t tests_merge;      /* between neighbouring cubes or groups */
     int64_t tests_border;
+    int64_t tests_intra;      /* inside search groups (m > 1) */
 } hca_stats;
 
 /* Exact floor(eps^2) of a double (no device needed).  HCA_E_INVAL if eps is
@@ -148,21 +151,25 @@ hca_status hca_cluster_host(hca_ctx *ctx, const int32_t *points, int64_t n, int3
                             double eps, int32_t min_pts, int32_t *labels);
 
 /* Phases of one call, in launch order, for hca_set_profiling / hca_phase_times:
- * origin shift (bounding box), cube keys and their radix sort with the gather
- * of points into cube order (methodology, pre-processing sort), cube and group
- * tables with the lookup table (Algorithm 1's dictionary), core points
- * (Definition 2), representative points (Algorithm 2), merging of neighbouring
- * cubes with union-find (Algorithm 3), border points, canonical labels. */
+ * origin shift (bounding box); cube keys and their radix sort with the gather
+ * of points into cube order (methodology, pre-processing sort); cube and group
+ * tables with the lookup table (Algorithm 1's dictionary); the neighbour-group
+ * lists (search groups of m > 1 cubes only); core points (Definition 2);
+ * representative points (Algorithm 2); linking inside each search group
+ * (m > 1 only); merging of neighbouring cubes or groups with union-find
+ * (Algorithm 3), with the final flattening; border points; canonical labels. */
 enum {
     HCA_PHASE_BBOX = 0,
     HCA_PHASE_SORT = 1,
     HCA_PHASE_CELLS = 2,
-    HCA_PHASE_CORE = 3,
-    HCA_PHASE_REPS = 4,
-    HCA_PHASE_MERGE = 5,
-    HCA_PHASE_BORDER = 6,
-    HCA_PHASE_LABELS = 7,
-    HCA_PHASES = 8
+    HCA_PHASE_LISTS = 3,
+    HCA_PHASE_CORE = 4,
+    HCA_PHASE_REPS = 5,
+    HCA_PHASE_INTRA = 6,
+    HCA_PHASE_MERGE = 7,
+    HCA_PHASE_BORDER = 8,
+    HCA_PHASE_LABELS = 9,
+    HCA_PHASES = 10
 };
 
 /* Time phases of later calls with HIP events on the context's stream:

@@ -470,10 +470,13 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
     const int pb = (int)std::min<uint64_t>(persist, ((uint64_t)n + kBlock - 1) / kBlock * 4 + 8) & ~7;
     const int wb = std::max(8, pb);
     // neighbour-group lists in group mode: 64 entries per point, at least
-    // 4096 per wave, at most 2^29 in all
-    P.nbr_cap = P.m > 1 ? (uint32_t)std::min<uint64_t>(std::max<uint64_t>(64ull * n, 4096ull * wb * (kBlock / kWave)),
-                                                       1ull << 29)
-                        : 0;
+    // 4096 per wave, at most 2^29 in all (HCA_LIST_SLAB: entries per wave,
+    // 0 = no lists)
+    const uint64_t waves = (uint64_t)wb * (kBlock / kWave);
+    uint64_t list_cap = std::min<uint64_t>(std::max<uint64_t>(64ull * n, 4096ull * waves), 1ull << 29);
+    if (const char *e = std::getenv("HCA_LIST_SLAB"))
+        list_cap = std::min<uint64_t>((uint64_t)std::max(0, std::atoi(e)) * waves, 1ull << 29);
+    P.nbr_cap = P.m > 1 ? (uint32_t)list_cap : 0;
     P.count_work = stats != nullptr && ctx->prof != -1;
 
     // 3. workspace
@@ -564,14 +567,26 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
     const int tb = (int)std::min<uint64_t>((n + kBlock - 1) / kBlock, 1024);
     launch_table(P, tb, s);
     mark(ctx, HCA_PHASE_CELLS, true);
+    // 6. neighbour-group lists, core points, representatives, merging,
+    // border points, labels
+    if (P.nbr_cap) {
+        mark(ctx, HCA_PHASE_LISTS, false);
+        launch_lists(P, wb, s);
+        mark(ctx, HCA_PHASE_LISTS, true);
+    }
     mark(ctx, HCA_PHASE_CORE, false);
-    // 6. core points, representatives, merging, border points, labels
-    launch_lists(P, wb, s);
     launch_core(P, wb, s);
     mark(ctx, HCA_PHASE_CORE, true);
-    mark(ctx, HCA_PHASE_REPS, false);
-    if (P.n_dir) launch_reps(P, wb, s);
-    mark(ctx, HCA_PHASE_REPS, true);
+    if (P.n_dir) {
+        mark(ctx, HCA_PHASE_REPS, false);
+        launch_reps(P, wb, s);
+        mark(ctx, HCA_PHASE_REPS, true);
+    }
+    if (P.m > 1) {
+        mark(ctx, HCA_PHASE_INTRA, false);
+        launch_merge_intra(P, wb, s);
+        mark(ctx, HCA_PHASE_INTRA, true);
+    }
     mark(ctx, HCA_PHASE_MERGE, false);
     launch_merge(P, wb, s);
     launch_compress(P, tb, s);
@@ -602,16 +617,19 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
         stats->n_core_points = hc->n_core;
         stats->n_noise = hc->n_noise;
         stats->n_clusters = hc->n_clusters;
-        for (int ph = 0; ph < 3; ph++) {
+        int64_t *const dst[4] = {&stats->tests_core, &stats->tests_merge, &stats->tests_border,
+                                 &stats->tests_intra};
+        for (int ph = 0; ph < 4; ph++) {
             int64_t t = 0;
             for (int r = 0; r < kWorkRegions; r++) t += (int64_t)hc->tests[ph][r * 8];
-            (ph == 0 ? stats->tests_core : ph == 1 ? stats->tests_merge : stats->tests_border) = t;
+            *dst[ph] = t;
         }
         stats->key_bits = (int32_t)P.key_bits;
         stats->sort_passes = (int32_t)P.passes;
         stats->group = (int32_t)P.m;
         stats->wide = P.wide;
         stats->dense_table = (int32_t)P.dense;
+        stats->list_overflow = (int32_t)hc->nbr_overflow;
     }
     return HCA_OK;
 }

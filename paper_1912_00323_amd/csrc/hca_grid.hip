@@ -910,7 +910,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_tiles(Plan P)
         }
         __builtin_amdgcn_wave_barrier();
     }
-    flush_tests(P, kTestsMerge, lt);
+    flush_tests(P, kTestsIntra, lt);
 }
 
 // First core cube of each group and whether all its core cubes share one
@@ -1528,16 +1528,21 @@ void launch_reps(const Plan &P, int blocks, hipStream_t s)
     }
 }
 
+void launch_merge_intra(const Plan &P, int blocks, hipStream_t s)
+{
+    if (P.m == 1) return;
+    const uint32_t tiles = (P.n + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(k_tile_scan, dim3(tiles), dim3(kBlock), 0, s, P, P.tile_status, &P.ctr->tile_ticket);
+    HCA_DISPATCH_DW(k_merge_tiles, P, blocks, s);
+    HCA_DISPATCH_DW(k_merge_unify, P, blocks, s);
+}
+
 void launch_merge(const Plan &P, int blocks, hipStream_t s)
 {
     if (P.m == 1) {
         HCA_DISPATCH_DW(k_merge_rep, P, blocks, s);
         HCA_DISPATCH_DW(k_merge_exact, P, blocks, s);
     } else {
-        const uint32_t tiles = (P.n + kScanTile - 1) / kScanTile;
-        hipLaunchKernelGGL(k_tile_scan, dim3(tiles), dim3(kBlock), 0, s, P, P.tile_status, &P.ctr->tile_ticket);
-        HCA_DISPATCH_DW(k_merge_tiles, P, blocks, s);
-        HCA_DISPATCH_DW(k_merge_unify, P, blocks, s);
         HCA_DISPATCH_DW(k_merge_inter, P, blocks, s);
         HCA_DISPATCH_DW(k_merge_pairs, P, blocks, s);
     }

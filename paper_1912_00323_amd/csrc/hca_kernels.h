@@ -27,6 +27,7 @@ void launch_table(const Plan &P, int blocks, hipStream_t s);
 void launch_lists(const Plan &P, int blocks, hipStream_t s);
 void launch_core(const Plan &P, int blocks, hipStream_t s);
 void launch_reps(const Plan &P, int blocks, hipStream_t s);
+void launch_merge_intra(const Plan &P, int blocks, hipStream_t s);
 void launch_merge(const Plan &P, int blocks, hipStream_t s);
 void launch_compress(const Plan &P, int blocks, hipStream_t s);
 void launch_border(const Plan &P, int blocks, hipStream_t s);

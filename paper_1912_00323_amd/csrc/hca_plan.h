@@ -51,10 +51,10 @@ struct Counters {
     uint32_t work_count[kWorkRegions * kCounterStride];   // region r at [r * kCounterStride]
     // pair tests executed, per phase (core, merge, border), spread over
     // kWorkRegions lines of eight 64-bit words; counted only on request
-    unsigned long long tests[3][kWorkRegions * 8];
+    unsigned long long tests[4][kWorkRegions * 8];
 };
 
-enum { kTestsCore = 0, kTestsMerge = 1, kTestsBorder = 2 };
+enum { kTestsCore = 0, kTestsMerge = 1, kTestsBorder = 2, kTestsIntra = 3 };
 
 struct Plan {
     // problem

@@ -15,7 +15,7 @@ _HERE = Path(__file__).resolve().parent
 LIB_PATH = _HERE / "libhca.so"
 
 HCA_OK, HCA_E_INVAL, HCA_E_RANGE, HCA_E_NOMEM, HCA_E_DEVICE = 0, 1, 2, 3, 4
-PHASES = ["bbox", "sort", "cells", "core", "reps", "merge", "border", "labels"]
+PHASES = ["bbox", "sort", "cells", "lists", "core", "reps", "intra", "merge", "border", "labels"]
 STATUS_NAMES = {0: "HCA_OK", 1: "HCA_E_INVAL", 2: "HCA_E_RANGE", 3: "HCA_E_NOMEM",
                 4: "HCA_E_DEVICE"}
 
@@ -42,12 +42,12 @@ class Stats(ctypes.Structure):
                 ("n_noise", ctypes.c_int64), ("exact_pairs", ctypes.c_int64),
                 ("key_bits", ctypes.c_int32), ("sort_passes", ctypes.c_int32),
                 ("group", ctypes.c_int32), ("wide", ctypes.c_int32),
-                ("dense_table", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("dense_table", ctypes.c_int32), ("list_overflow", ctypes.c_int32),
                 ("tests_core", ctypes.c_int64), ("tests_merge", ctypes.c_int64),
-                ("tests_border", ctypes.c_int64)]
+                ("tests_border", ctypes.c_int64), ("tests_intra", ctypes.c_int64)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _lib = None

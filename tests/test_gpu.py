@@ -88,6 +88,27 @@ def test_search_modes_agree(ctx, mode, reps, monkeypatch):
         check(ctx, pts, 0.05 * 2 ** 12, 5, f"mode={mode} reps={reps} d={d}")
 
 
+@pytest.mark.parametrize("slab", ["0", "16", "64"])
+def test_group_lists_fallback(ctx, slab, monkeypatch):
+    """Group mode with no neighbour lists (stencil walk) and with slabs so small
+    that most groups fall back to the stencil while the rest use their lists."""
+    monkeypatch.setenv("HCA_SEARCH", "group")
+    monkeypatch.setenv("HCA_LIST_SLAB", slab)
+    for d in (3, 5, 6):
+        rng = np.random.default_rng(70 + d)
+        x = make_blobs(rng, 6000, d, 6, 0.04, 0.1)
+        pts = quantise(x, 12)
+        eps, mp = 0.08 * 2 ** 12, 5
+        print(f"[case] lists slab={slab} d={d}", flush=True)
+        want = oracle.dbscan(pts, eps, mp)
+        got, stats = gpu_labels(ctx, pts, eps, mp, stats=True)
+        assert np.array_equal(got, want), f"slab={slab} d={d}"
+        if slab == "16" and d >= 5:
+            assert stats["list_overflow"] > 0
+        if slab == "0":
+            assert stats["list_overflow"] == 0
+
+
 def test_mixed_family(ctx):
     for seed in range(6):
         d = (2, 3, 4)[seed % 3]
