@@ -976,63 +976,48 @@ __global__ __launch_bounds__(kBlock) void k_merge_unify(Plan P)
     }
 }
 
-// Root shared by all core cubes of group G, or kNone when they have several
-// (read-only walks).  Two roots that agree prove their cubes joined even
-// when read at different moments, since sets only ever grow.
-__device__ uint32_t group_root(const Plan &P, uint32_t G)
-{
-    const uint32_t l = lane_id();
-    const uint32_t c0 = P.group_cell[G], c1 = P.group_cell[G + 1];
-    uint32_t r0 = kNone;
-    for (uint32_t cb = c0; cb < c1; cb += kWave) {
-        const uint32_t c = cb + l;
-        const uint32_t r = c < c1 && P.ncore[c] > 0 ? uf_root(P.parent, c) : kNone;
-        const uint64_t v = __ballot(r != kNone);
-        if (!v) continue;
-        if (r0 == kNone) r0 = __shfl(r, __ffsll((unsigned long long)v) - 1);
-        if (__ballot(r != kNone && r != r0)) return kNone;
-    }
-    return r0;
-}
-
-// Core pairs of groups GA x GB in 64 x 64 tiles: 64 points of GA staged in
-// LDS are visited one at a time against 64 points of GB in the lanes.  When
-// each group's core cubes already share one root, the two roots decide:
-// equal means nothing to do, otherwise the first pair within eps joins them
-// and ends the search.  Otherwise every pair within eps links its two cubes
-// unless their cached roots already agree.
-// ra and rb are cubes that stand for all core cubes of GA and GB, or kNone
-// when not known; those are then looked up.
+// Core pairs of groups GA x GB, rows [ra0, ra1) of GA against columns
+// [rb0, rb1) of GB (sorted positions), in 64 x 64 tiles: 64 row points staged
+// in LDS are visited one at a time against 64 column points in the lanes.  A
+// unified group stands as one node (its first core cube).  When both groups
+// are unified, their two roots decide: equal means nothing to do, otherwise
+// the first pair within eps joins them and ends the search.  Otherwise every
+// pair within eps links its two nodes unless their cached roots already
+// agree; a tile whose nodes all share one root is skipped.
 template <int D, bool WIDE>
-__device__ void link_pair(const Plan &P, uint32_t GA, uint32_t GB, uint32_t ra, uint32_t rb,
-                          int32_t (*s_pt)[D], uint32_t &lt)
+__device__ void link_pair(const Plan &P, uint32_t GA, uint32_t GB, bool ua, bool ub, uint32_t ra0,
+                          uint32_t ra1, uint32_t rb0, uint32_t rb1, int32_t (*s_pt)[D], uint32_t &lt)
 {
     const uint32_t l = lane_id();
-    if (ra == kNone) ra = group_root(P, GA);
-    if (ra != kNone && rb == kNone) rb = group_root(P, GB);
-    const bool single = ra != kNone && rb != kNone;
-    if (single && uf_find(P.parent, ra) == uf_find(P.parent, rb)) return;
-    const uint32_t a0 = P.group_start[GA], a1 = P.group_start[GA + 1];
-    const uint32_t b0 = P.group_start[GB], b1 = P.group_start[GB + 1];
-    for (uint32_t ia = a0; ia < a1; ia += kWave) {
+    const uint32_t ga = P.gcube[GA], gb = P.gcube[GB];
+    const bool single = ua && ub;
+    if (single && uf_find(P.parent, ga) == uf_find(P.parent, gb)) return;
+    for (uint32_t ia = ra0; ia < ra1; ia += kWave) {
         const uint32_t qi = ia + l;
-        const bool core_i = qi < a1 && P.core[qi];
+        const bool core_i = qi < ra1 && P.core[qi];
         const uint64_t mi = __ballot(core_i);
         if (!mi) continue;
-        const Pt<D> pi = load_pt<D>(P.spts, core_i ? qi : a0);
+        const Pt<D> pi = load_pt<D>(P.spts, core_i ? qi : ra0);
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int e = 0; e < D; e++) s_pt[l][e] = pi.x[e];
         __builtin_amdgcn_wave_barrier();
-        const uint32_t cube_i = !single && core_i ? P.cell_of[qi] : kNone;
-        uint32_t root_i = !single && core_i ? uf_find(P.parent, cube_i) : kNone;
-        for (uint32_t jb = b0; jb < b1; jb += kWave) {
+        // node of each row point and its root (one lookup for a unified group)
+        const uint32_t node_i = single || !core_i ? kNone : (ua ? ga : P.cell_of[qi]);
+        uint32_t root_i = kNone;
+        if (!single) root_i = ua ? uf_find(P.parent, ga) : (core_i ? uf_find(P.parent, node_i) : kNone);
+        for (uint32_t jb = rb0; jb < rb1; jb += kWave) {
             const uint32_t qj = jb + l;
-            const bool core_j = qj < b1 && P.core[qj];
+            const bool core_j = qj < rb1 && P.core[qj];
             if (!__ballot(core_j)) continue;
-            const Pt<D> pj = load_pt<D>(P.spts, core_j ? qj : b0);
-            const uint32_t cube_j = !single && core_j ? P.cell_of[qj] : kNone;
-            uint32_t root_j = !single && core_j ? uf_find(P.parent, cube_j) : kNone;
+            const uint32_t node_j = single || !core_j ? kNone : (ub ? gb : P.cell_of[qj]);
+            uint32_t root_j = kNone;
+            if (!single) {
+                root_j = ub ? uf_find(P.parent, gb) : (core_j ? uf_find(P.parent, node_j) : kNone);
+                const uint32_t r0 = __shfl(root_i, __ffsll((unsigned long long)mi) - 1);
+                if (!__ballot((core_i && root_i != r0) || (core_j && root_j != r0))) continue;
+            }
+            const Pt<D> pj = load_pt<D>(P.spts, core_j ? qj : rb0);
             uint64_t rows = mi;
             while (rows) {
                 const uint32_t r = __ffsll((unsigned long long)rows) - 1;
@@ -1044,35 +1029,65 @@ __device__ void link_pair(const Plan &P, uint32_t GA, uint32_t GB, uint32_t ra, 
                 const bool hit = core_j && within<D, WIDE>(pr, pj, P.eps2);
                 if (single) {
                     if (__ballot(hit)) {
-                        if (l == 0) uf_union(P.parent, ra, rb);
+                        if (l == 0) uf_union(P.parent, ga, gb);
                         return;
                     }
                     continue;
                 }
-                const uint32_t cr = __shfl(cube_i, r), rr = __shfl(root_i, r);
+                const uint32_t nr = __shfl(node_i, r), rr = __shfl(root_i, r);
                 const bool need = hit && root_j != rr;
-                if (__ballot(need)) {
-                    if (need) uf_union(P.parent, cr, cube_j);
-                    root_j = core_j ? uf_find(P.parent, cube_j) : kNone;
-                    root_i = core_i ? uf_find(P.parent, cube_i) : kNone;
+                const uint64_t nm = __ballot(need);
+                if (nm) {
+                    if (ub) {
+                        // one node on the GB side: a single union suffices
+                        if (l == __ffsll((unsigned long long)nm) - 1) uf_union(P.parent, nr, gb);
+                    } else if (need) {
+                        uf_union(P.parent, nr, node_j);
+                    }
+                    root_j = ub ? uf_find(P.parent, gb) : (core_j ? uf_find(P.parent, node_j) : kNone);
+                    root_i = ua ? uf_find(P.parent, ga) : (core_i ? uf_find(P.parent, node_i) : kNone);
                 }
             }
         }
     }
 }
 
+// Group-pair work in the worklist: 4 words each (GA, GB, row tile, column
+// tile), row tile kNone for a whole pair of unified groups; region r owns
+// entries [r * cap, (r + 1) * cap).
+__device__ __forceinline__ uint32_t pair_tile_cap(const Plan &P) { return P.work_cap / 2 / kWorkRegions; }
+
+template <int D, bool WIDE>
+__device__ __forceinline__ void link_tile(const Plan &P, uint32_t GA, uint32_t GB, uint32_t ti, uint32_t tj,
+                                          int32_t (*s_pt)[D], uint32_t &lt)
+{
+    const uint32_t a0 = P.group_start[GA], a1 = P.group_start[GA + 1];
+    const uint32_t b0 = P.group_start[GB], b1 = P.group_start[GB + 1];
+    if (ti == kNone) {                                   // a whole pair of unified groups
+        link_pair<D, WIDE>(P, GA, GB, true, true, a0, a1, b0, b1, s_pt, lt);
+        return;
+    }
+    const uint32_t ra0 = a0 + ti * kWave, rb0 = b0 + tj * kWave;
+    link_pair<D, WIDE>(P, GA, GB, P.unified[GA], P.unified[GB], ra0, min(a1, ra0 + kWave), rb0,
+                       min(b1, rb0 + kWave), s_pt, lt);
+}
+
 // Inter: each group GA with core points walks its neighbour groups GB > GA
 // that have core points and whose box comes within eps of GA's core points.
-// When both groups are unified, their roots are compared on the spot and a
-// pair with different roots is searched right away; the other pairs go to
-// the worklist (a full region links its pairs on the spot).
+// When both groups are unified, their roots are compared on the spot; a
+// small pair with different roots is searched right away.  The other pairs
+// go to the worklist cut into 64 x 64 tiles, so that a pair of large groups
+// is spread over many waves (tiles past a full region are linked on the
+// spot).
+constexpr uint32_t kInlineTiles = 4;
+
 template <int D, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_merge_inter(Plan P)
 {
     __shared__ int32_t s_pt[kWavesPerBlock][kWave][D];
     const uint32_t w = wave_in_block(), l = lane_id();
     const uint32_t region = (blockIdx.x * kWavesPerBlock + w) % kWorkRegions;
-    const uint32_t cap = P.work_cap / kWorkRegions;
+    const uint32_t cap = pair_tile_cap(P);
     uint32_t lt = 0;
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
     const WaveRange hca_wr_ = wave_range();
@@ -1083,6 +1098,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_inter(Plan P)
         const uint64_t gkey = P.group_key[GA];
         // bounding box of GA's core points
         const uint32_t a0 = P.group_start[GA], a1 = P.group_start[GA + 1];
+        const uint32_t nta = (a1 - a0 + kWave - 1) / kWave;
         QBox<D> qb;
 #pragma unroll
         for (int e = 0; e < D; e++) { qb.lo[e] = INT32_MAX; qb.hi[e] = INT32_MIN; }
@@ -1098,8 +1114,8 @@ __global__ __launch_bounds__(kBlock) void k_merge_inter(Plan P)
         const NbrSrc src = nbr_source(P, GA);
         for (uint32_t oc = 1; oc < src.slots; oc += kWave) {
             const uint32_t j = oc + l;
-            uint32_t GB = kNone;
-            bool both = false, differ = false;
+            uint32_t GB = kNone, tiles = 0, ntb = 1;
+            bool both = false;
             if (j < src.slots) {
                 uint64_t nk = ~0ull;
                 if (src.lists) {
@@ -1121,50 +1137,76 @@ __global__ __launch_bounds__(kBlock) void k_merge_inter(Plan P)
                 } else {
                     GB = kNone;
                 }
-                if (GB != kNone && ua && P.unified[GB]) {
-                    both = true;
-                    differ = uf_find(P.parent, ga) != uf_find(P.parent, P.gcube[GB]);
+                if (GB != kNone) {
+                    ntb = (P.group_start[GB + 1] - P.group_start[GB] + kWave - 1) / kWave;
+                    tiles = nta * ntb;
+                    if (ua && P.unified[GB]) {
+                        both = true;
+                        if (uf_find(P.parent, ga) == uf_find(P.parent, P.gcube[GB])) GB = kNone;
+                    }
                 }
             }
-            uint64_t now = __ballot(both && differ);
+            // small pairs of unified groups: searched right away
+            uint64_t now = __ballot(GB != kNone && both && tiles <= kInlineTiles);
             while (now) {
                 const uint32_t src_lane = __ffsll((unsigned long long)now) - 1;
                 const uint32_t gb = __shfl(GB, src_lane);
-                link_pair<D, WIDE>(P, GA, gb, ga, P.gcube[gb], s_pt[w], lt);
+                link_pair<D, WIDE>(P, GA, gb, true, true, a0, a1, P.group_start[gb], P.group_start[gb + 1],
+                                   s_pt[w], lt);
                 now &= now - 1;
             }
-            if (both) GB = kNone;
-            const uint64_t m = __ballot(GB != kNone);
-            if (!m) continue;
+            if (both && tiles <= kInlineTiles) GB = kNone;
+            // the rest: one worklist entry per 64 x 64 tile, or one for a whole
+            // pair of unified groups (its search ends at the first hit)
+            const uint32_t want = GB == kNone ? 0u : both ? 1u : tiles;
+            const uint32_t inc = wave_inclusive_scan(want);
+            const uint32_t total = __shfl(inc, kWave - 1);
+            if (!total) continue;
             uint32_t base = 0;
-            if (l == 0) base = atomicAdd(P.ctr->work_count + region * kCounterStride, (uint32_t)__popcll(m));
+            if (l == 0) base = atomicAdd(P.ctr->work_count + region * kCounterStride, total);
             base = __shfl(base, 0);
-            const uint32_t slot = base + __popcll(m & __lanemask_lt());
-            const bool spill = GB != kNone && slot >= cap;
-            if (GB != kNone && !spill) {
-                const uint64_t at = (uint64_t)region * cap + slot;
-                P.work[2ull * at] = GA;
-                P.work[2ull * at + 1] = GB;
-            }
-            uint64_t sm = __ballot(spill);
-            while (sm) {
-                const uint32_t src_lane = __ffsll((unsigned long long)sm) - 1;
-                link_pair<D, WIDE>(P, GA, __shfl(GB, src_lane), kNone, kNone, s_pt[w], lt);
-                sm &= sm - 1;
+            uint64_t m = __ballot(want != 0);
+            while (m) {
+                const uint32_t src_lane = __ffsll((unsigned long long)m) - 1;
+                m &= m - 1;
+                const uint32_t gb = __shfl(GB, src_lane), nt = __shfl(want, src_lane);
+                const uint32_t nb_t = __shfl(ntb, src_lane);
+                const uint32_t first = base + __shfl(inc, src_lane) - nt;
+                const bool whole = __shfl((uint32_t)both, src_lane) != 0;
+                for (uint32_t t0 = 0; t0 < nt; t0 += kWave) {
+                    const uint32_t t = t0 + l;
+                    const uint32_t ti = t / nb_t, tj = t - ti * nb_t;
+                    const bool mine = t < nt;
+                    const uint32_t slot = first + t;
+                    if (mine && slot < cap) {
+                        uint32_t *e = P.work + 4ull * ((uint64_t)region * cap + slot);
+                        e[0] = GA;
+                        e[1] = gb;
+                        e[2] = whole ? kNone : ti;
+                        e[3] = tj;
+                    }
+                    // region full: link those tiles here
+                    uint64_t sp = __ballot(mine && slot >= cap);
+                    while (sp) {
+                        const uint32_t sl = __ffsll((unsigned long long)sp) - 1;
+                        sp &= sp - 1;
+                        link_tile<D, WIDE>(P, GA, gb, whole ? kNone : __shfl(ti, sl), __shfl(tj, sl), s_pt[w], lt);
+                    }
+                }
             }
         }
     }
     flush_tests(P, kTestsMerge, lt);
 }
 
-// The queued group pairs, one per wave at a time over all waves.
+// The queued tiles, one per wave at a time over all waves.
 template <int D, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_merge_pairs(Plan P)
 {
     __shared__ uint32_t s_pre[kWavesPerBlock][kWorkRegions];
     __shared__ int32_t s_pt[kWavesPerBlock][kWave][D];
     const uint32_t w = wave_in_block(), l = lane_id();
-    const uint32_t cap = P.work_cap / kWorkRegions;
+    const uint32_t cap = pair_tile_cap(P);
     const uint32_t cnt = min(ld_agent32(P.ctr->work_count + l * kCounterStride), cap);
     const uint32_t inc = wave_inclusive_scan(cnt);
     s_pre[w][l] = inc - cnt;
@@ -1174,10 +1216,24 @@ __global__ __launch_bounds__(kBlock) void k_merge_pairs(Plan P)
     const WaveRange hca_wr_ = wave_range();
     HCA_FOR_UNITS(it, items) {
         const uint32_t r = candidate_lane(it, s_pre[w]);
-        const uint64_t at = (uint64_t)r * cap + (it - s_pre[w][r]);
-        link_pair<D, WIDE>(P, P.work[2ull * at], P.work[2ull * at + 1], kNone, kNone, s_pt[w], lt);
+        const uint32_t *e = P.work + 4ull * ((uint64_t)r * cap + (it - s_pre[w][r]));
+        link_tile<D, WIDE>(P, e[0], e[1], e[2], e[3], s_pt[w], lt);
     }
     flush_tests(P, kTestsMerge, lt);
+}
+
+// Between linking passes: point every cube straight at its root, so later
+// finds start from depth one (hooking larger roots under smaller ones can
+// build long chains).  No union runs concurrently.
+__global__ __launch_bounds__(kBlock) void k_flatten(Plan P)
+{
+    const uint32_t nc = ld_agent32(&P.ctr->n_cells);
+    for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < nc; c += gridDim.x * kBlock) {
+        const uint32_t p = ld_parent(P.parent + c);
+        if (p == c) continue;
+        const uint32_t r = uf_root(P.parent, p);
+        if (r != p) st_parent(P.parent + c, r);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1535,6 +1591,7 @@ void launch_merge_intra(const Plan &P, int blocks, hipStream_t s)
     hipLaunchKernelGGL(k_tile_scan, dim3(tiles), dim3(kBlock), 0, s, P, P.tile_status, &P.ctr->tile_ticket);
     HCA_DISPATCH_DW(k_merge_tiles, P, blocks, s);
     HCA_DISPATCH_DW(k_merge_unify, P, blocks, s);
+    hipLaunchKernelGGL(k_flatten, dim3(1024), dim3(kBlock), 0, s, P);
 }
 
 void launch_merge(const Plan &P, int blocks, hipStream_t s)
@@ -1544,6 +1601,7 @@ void launch_merge(const Plan &P, int blocks, hipStream_t s)
         HCA_DISPATCH_DW(k_merge_exact, P, blocks, s);
     } else {
         HCA_DISPATCH_DW(k_merge_inter, P, blocks, s);
+        hipLaunchKernelGGL(k_flatten, dim3(1024), dim3(kBlock), 0, s, P);
         HCA_DISPATCH_DW(k_merge_pairs, P, blocks, s);
     }
 }
