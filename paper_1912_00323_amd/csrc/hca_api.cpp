@@ -526,11 +526,11 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
         if (P.dense) {
             P.table = cv.take<uint32_t>((size_t)1 << gbits);
             P.hkeys = nullptr;
-            P.hkeys_read = nullptr;
+            P.hslot = nullptr;
         } else {
-            P.table = cv.take<uint32_t>(hcap);
+            P.table = nullptr;
             P.hkeys = cv.take<uint64_t>(hcap);
-            P.hkeys_read = cv.take<uint64_t>(hcap);
+            P.hslot = cv.take<uint64_t>(2 * hcap);
         }
     };
     SortBuffers B;
@@ -551,9 +551,7 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
     P.labels = labels;
     P.core_out = core_out;
 
-    launch_init(zbeg, zbytes / sizeof(uint32_t), P.dense ? nullptr : P.hkeys,
-                P.dense ? nullptr : P.hkeys_read, P.dense ? 0 : hcap, P.dense ? P.table : nullptr,
-                P.dense ? (1ull << gbits) : 0, s);
+    launch_init(zbeg, zbytes / sizeof(uint32_t), P.dense ? P.table : nullptr, P.dense ? (1ull << gbits) : 0, s);
 
     // 4. cube keys and stable radix sort (points gathered in the last pass)
     mark(ctx, HCA_PHASE_SORT, false);

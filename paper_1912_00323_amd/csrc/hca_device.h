@@ -251,12 +251,41 @@ __device__ __forceinline__ uint64_t mix64(uint64_t x)
 __device__ __forceinline__ uint32_t group_lookup(const Plan &P, uint64_t gkey)
 {
     if (P.dense) return P.table[gkey];
-    uint64_t h = mix64(gkey) & P.hash_mask;
+    const uint64_t mask = P.ctr->hmask;
+    uint64_t h = mix64(gkey) & mask;
     while (true) {
-        const uint64_t k = P.hkeys_read[h];
-        if (k == gkey) return P.table[h];
-        if (k == ~0ull) return kNone;
-        h = (h + 1) & P.hash_mask;
+        const ulonglong2 slot = *(const ulonglong2 *)(P.hslot + 2 * h);
+        if (slot.x == gkey) return (uint32_t)slot.y;
+        if (slot.x == ~0ull) return kNone;
+        h = (h + 1) & mask;
+    }
+}
+
+// B lookups at once (keys ~0 stand for none): the first probes are all in
+// flight together, the rare longer chains are followed afterwards.
+template <int B>
+__device__ __forceinline__ void group_lookup_n(const Plan &P, const uint64_t *keys, uint32_t *out)
+{
+    if (P.dense) {
+#pragma unroll
+        for (int b = 0; b < B; b++) out[b] = keys[b] != ~0ull ? P.table[keys[b]] : kNone;
+        return;
+    }
+    const uint64_t mask = P.ctr->hmask;
+    uint64_t h[B];
+    ulonglong2 slot[B];
+#pragma unroll
+    for (int b = 0; b < B; b++) {
+        h[b] = mix64(keys[b]) & mask;
+        slot[b] = keys[b] != ~0ull ? *(const ulonglong2 *)(P.hslot + 2 * h[b]) : make_ulonglong2(~0ull, 0ull);
+    }
+#pragma unroll
+    for (int b = 0; b < B; b++) {
+        while (slot[b].x != keys[b] && slot[b].x != ~0ull) {
+            h[b] = (h[b] + 1) & mask;
+            slot[b] = *(const ulonglong2 *)(P.hslot + 2 * h[b]);
+        }
+        out[b] = keys[b] != ~0ull && slot[b].x == keys[b] ? (uint32_t)slot[b].y : kNone;
     }
 }
 

@@ -166,42 +166,53 @@ __device__ __forceinline__ void load_chunk(const Plan &P, uint32_t pc, uint32_t 
 // stores, since atomics update them later; the direct lookup table (all
 // ones) with plain stores.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_init(uint32_t *zero, uint64_t zero_words, uint64_t *hkeys,
-                                                 uint64_t *hkeys_read, uint64_t hcap, uint32_t *table,
+__global__ __launch_bounds__(kBlock) void k_init(uint32_t *zero, uint64_t zero_words, uint32_t *table,
                                                  uint64_t tsize)
 {
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     const uint64_t i0 = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     for (uint64_t i = i0; i < zero_words; i += stride) st_agent32(zero + i, 0u);
-    for (uint64_t i = i0; i < hcap; i += stride) {
-        st_agent(hkeys + i, ~0ull);
-        hkeys_read[i] = ~0ull;
-    }
     for (uint64_t i = i0; i < tsize; i += stride) table[i] = kNone;
 }
 
 // ---------------------------------------------------------------------------
 // Group lookup table: direct index over the packed group key, or open
-// addressing with linear probing (64-bit keys, all-ones = empty).
+// addressing with linear probing (64-bit keys, all-ones = empty).  The hash
+// uses a power of two >= 2x the groups of this call (at least 1024 slots), so
+// that the slots probed stay few and cache-resident; only those start empty.
 // ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_table_clear(Plan P)
+{
+    const uint32_t ng = ld_agent32(&P.ctr->n_groups);
+    uint64_t cap = 1024;
+    while (cap < 2ull * ng) cap <<= 1;
+    cap = min(cap, P.hash_mask + 1);
+    if (blockIdx.x == 0 && threadIdx.x == 0) st_agent32(&P.ctr->hmask, (uint32_t)(cap - 1));
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < cap; i += (uint64_t)gridDim.x * kBlock) {
+        st_agent(P.hkeys + i, ~0ull);
+        P.hslot[2 * i] = ~0ull;
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_table(Plan P)
 {
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
+    const uint64_t mask = P.ctr->hmask;
     for (uint32_t g = blockIdx.x * kBlock + threadIdx.x; g < ng; g += gridDim.x * kBlock) {
         const uint64_t key = P.group_key[g];
         if (P.dense) {
             P.table[key] = g;
             continue;
         }
-        uint64_t h = mix64(key) & P.hash_mask;
+        uint64_t h = mix64(key) & mask;
         while (true) {
             const uint64_t prev = atomicCAS((unsigned long long *)(P.hkeys + h), ~0ull, key);
             if (prev == ~0ull || prev == key) {
-                P.table[h] = g;
-                P.hkeys_read[h] = key;      // the slot's only writer
+                // the slot's only writer
+                *(ulonglong2 *)(P.hslot + 2 * h) = make_ulonglong2(key, (unsigned long long)g);
                 break;
             }
-            h = (h + 1) & P.hash_mask;
+            h = (h + 1) & mask;
         }
     }
 }
@@ -302,6 +313,8 @@ __device__ __forceinline__ void rank_sort(const int64_t *s_in, int n, int64_t *s
 // each i the valid j form a prefix; only those offsets are looked up.  Each
 // wave appends to its own slab; a group that does not fit is flagged and
 // searched over the stencil instead.
+constexpr int kListBatch = 4;        // lookups in flight per lane
+
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_nbr_lists(Plan P)
 {
@@ -309,6 +322,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr_lists(Plan P)
     __shared__ int64_t s_in[kWavesPerBlock][NA > NB ? NA : NB];
     __shared__ int64_t s_sa[kWavesPerBlock][NA], s_sb[kWavesPerBlock][NB];
     __shared__ uint8_t s_ia[kWavesPerBlock][NA], s_ib[kWavesPerBlock][NB];
+    __shared__ int64_t s_ka[kWavesPerBlock][NA], s_kb[kWavesPerBlock][NB];
     __shared__ uint32_t s_pre[kWavesPerBlock][NA + 1];
     const uint32_t w = wave_in_block(), l = lane_id();
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
@@ -349,28 +363,39 @@ __global__ __launch_bounds__(kBlock) void k_nbr_lists(Plan P)
             tot += __shfl(inc, kWave - 1);
         }
         if (l == 0) s_pre[w][NA] = tot;
+        // key offsets of both halves in sorted order
+        for (int i = l; i < NA; i += kWave) s_ka[w][i] = half_key_delta<DA>(P, 0, s_ia[w][i]);
+        for (int j = l; j < NB; j += kWave) s_kb[w][j] = half_key_delta<DB>(P, DA, s_ib[w][j]);
         __builtin_amdgcn_wave_barrier();
         const uint32_t start = at;
         bool fits = true;
-        for (uint32_t t0 = 0; t0 < tot; t0 += kWave) {
-            const uint32_t t = t0 + l;
-            uint32_t G = kNone;
-            if (t < tot) {
-                int lo = 0, hi = NA;                      // last i with s_pre[i] <= t
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (s_pre[w][mid] <= t) lo = mid; else hi = mid;
+        for (uint32_t t0 = 0; t0 < tot; t0 += kWave * kListBatch) {
+            uint64_t nk[kListBatch];
+            uint32_t G[kListBatch];
+#pragma unroll
+            for (int b = 0; b < kListBatch; b++) {
+                const uint32_t t = t0 + b * kWave + l;
+                nk[b] = ~0ull;
+                if (t < tot) {
+                    int lo = 0, hi = NA;                  // last i with s_pre[i] <= t
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (s_pre[w][mid] <= t) lo = mid; else hi = mid;
+                    }
+                    const uint32_t j = t - s_pre[w][lo];
+                    nk[b] = gkey + (uint64_t)(s_ka[w][lo] + s_kb[w][j]);
+                    if (nk[b] == gkey) nk[b] = ~0ull;     // the group itself
                 }
-                const uint32_t j = t - s_pre[w][lo];
-                const uint64_t nk = gkey + (uint64_t)(half_key_delta<DA>(P, 0, s_ia[w][lo]) +
-                                                      half_key_delta<DB>(P, DA, s_ib[w][j]));
-                if (nk != gkey) G = group_lookup(P, nk);
             }
-            const uint64_t m = __ballot(G != kNone);
-            const uint32_t k = (uint32_t)__popcll(m);
-            if (at + k > end) fits = false;
-            if (fits && G != kNone) P.nbr[at + __popcll(m & __lanemask_lt())] = G;
-            if (fits) at += k;
+            group_lookup_n<kListBatch>(P, nk, G);
+#pragma unroll
+            for (int b = 0; b < kListBatch; b++) {
+                const uint64_t m = __ballot(G[b] != kNone);
+                const uint32_t k = (uint32_t)__popcll(m);
+                if (at + k > end) fits = false;
+                if (fits && G[b] != kNone) P.nbr[at + __popcll(m & __lanemask_lt())] = G[b];
+                if (fits) at += k;
+            }
         }
         __builtin_amdgcn_wave_barrier();
         if (l == 0) {
@@ -1539,17 +1564,19 @@ __global__ __launch_bounds__(kBlock) void k_label_write(Plan P)
         }                                                                                 \
     } while (0)
 
-void launch_init(uint32_t *zero, uint64_t zero_words, uint64_t *hkeys, uint64_t *hkeys_read,
-                 uint64_t hcap, uint32_t *table, uint64_t tsize, hipStream_t s)
+void launch_init(uint32_t *zero, uint64_t zero_words, uint32_t *table, uint64_t tsize, hipStream_t s)
 {
-    const uint64_t work = std::max(zero_words, std::max(hcap, tsize));
+    const uint64_t work = std::max(zero_words, tsize);
     const int blocks = (int)std::max<uint64_t>(1, std::min<uint64_t>((work + kBlock - 1) / kBlock, 2048));
-    hipLaunchKernelGGL(k_init, dim3(blocks), dim3(kBlock), 0, s, zero, zero_words, hkeys, hkeys_read, hcap,
-                       table, tsize);
+    hipLaunchKernelGGL(k_init, dim3(blocks), dim3(kBlock), 0, s, zero, zero_words, table, tsize);
 }
 
 void launch_table(const Plan &P, int blocks, hipStream_t s)
 {
+    if (!P.dense) {
+        const int cb = (int)std::min<uint64_t>((P.hash_mask + kBlock) / kBlock, 1024);
+        hipLaunchKernelGGL(k_table_clear, dim3(cb), dim3(kBlock), 0, s, P);
+    }
     hipLaunchKernelGGL(k_table, dim3(blocks), dim3(kBlock), 0, s, P);
 }
 

@@ -21,8 +21,7 @@ void launch_sort(const Plan &P, SortBuffers &B, bool wide_keys, hipStream_t s);
 void launch_cells(const Plan &P, bool wide_keys, uint64_t *status, uint32_t *ticket,
                   hipStream_t s);
 
-void launch_init(uint32_t *zero, uint64_t zero_words, uint64_t *hkeys, uint64_t *hkeys_read,
-                 uint64_t hcap, uint32_t *table, uint64_t tsize, hipStream_t s);
+void launch_init(uint32_t *zero, uint64_t zero_words, uint32_t *table, uint64_t tsize, hipStream_t s);
 void launch_table(const Plan &P, int blocks, hipStream_t s);
 void launch_lists(const Plan &P, int blocks, hipStream_t s);
 void launch_core(const Plan &P, int blocks, hipStream_t s);

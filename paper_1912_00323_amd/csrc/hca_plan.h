@@ -47,7 +47,8 @@ struct Counters {
     uint32_t n_tiles;           // intra-group point tiles
     uint32_t tile_ticket;
     uint32_t nbr_overflow;      // groups whose neighbour list did not fit
-    uint32_t pad[10];
+    uint32_t hmask;             // hash slots in use - 1 (a power of two - 1)
+    uint32_t pad[9];
     uint32_t work_count[kWorkRegions * kCounterStride];   // region r at [r * kCounterStride]
     // pair tests executed, per phase (core, merge, border), spread over
     // kWorkRegions lines of eight 64-bit words; counted only on request
@@ -87,7 +88,7 @@ struct Plan {
     const uint16_t *dir_bwd;    // [n_off]
     // group lookup: direct table over the packed group key, or hash
     uint32_t dense;
-    uint64_t hash_mask;
+    uint64_t hash_mask;         // allocated capacity - 1; the call uses Counters::hmask
 
     // buffers
     const int32_t *pts;         // [n][d] input order
@@ -99,9 +100,9 @@ struct Plan {
     uint32_t *group_start;      // [n + 1] group -> first sorted position
     uint32_t *group_cell;       // [n + 1] group -> first cube id
     uint64_t *group_key;        // [n]
-    uint32_t *table;            // dense: [2^gbits] ; hash: values [cap]
+    uint32_t *table;            // dense: [2^gbits] group ids
     uint64_t *hkeys;            // hash: keys [cap], claimed by compare-and-swap
-    uint64_t *hkeys_read;       // hash: plain copy of the claimed keys [cap], read by lookups
+    uint64_t *hslot;            // hash: [cap][2] (key, group id), read by lookups
     uint8_t *core;              // [n] sorted order
     uint32_t *ncore;            // [n] cube -> core points
     uint64_t *rep;              // [cells][n_dir] (score << 32 | sorted position), min wins
