@@ -150,6 +150,28 @@ hca_status hca_cluster_ex(hca_ctx *ctx, const int32_t *points, int64_t n, int32_
 hca_status hca_cluster_host(hca_ctx *ctx, const int32_t *points, int64_t n, int32_t d,
                             double eps, int32_t min_pts, int32_t *labels);
 
+/* Batched form: cluster many independent data sets with one launch sequence
+ * per dimension (the data sets of equal d share the sort, the cube tables,
+ * the lookup and the union-find, each with its own eps, minPts, cube side and
+ * origin, its index kept above the cube coordinates in the packed key).
+ *   points  DEVICE, the data sets one after the other, data set i row-major
+ *           int32[rows[i]][dims[i]]; 4-byte aligned; never written.
+ *   nseg    number of data sets (0: nothing to do).
+ *   rows, dims, eps, min_pts  HOST arrays of nseg entries: rows >= 0,
+ *           dims in [1, 4], eps finite and > 0 (same units as the points),
+ *           min_pts >= 1.
+ *   labels  DEVICE int32[sum of rows], data set i's labels at its own rows'
+ *           place, clusters numbered from 0 within each data set, -1 noise:
+ *           exactly what hca_cluster returns for the data set alone.
+ * Blocking like hca_cluster.  HCA_E_INVAL for bad arguments, d > 4, more than
+ * 2^31-1 rows in all or more than 8192 data sets of one dimension;
+ * HCA_E_RANGE when a data set spans 2^30 or more along an axis or the packed
+ * keys of one dimension need more than 63 bits.  Phase profiling does not
+ * apply to batches. */
+hca_status hca_cluster_batch(hca_ctx *ctx, const int32_t *points, int32_t nseg, const int64_t *rows,
+                             const int32_t *dims, const double *eps, const int32_t *min_pts,
+                             int32_t *labels);
+
 /* Phases of one call, in launch order, for hca_set_profiling / hca_phase_times:
  * origin shift (bounding box); cube keys and their radix sort with the gather
  * of points into cube order (methodology, pre-processing sort); cube and group

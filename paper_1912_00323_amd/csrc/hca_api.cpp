@@ -20,6 +20,8 @@ namespace {
 
 constexpr int kBboxBlocks = 256;
 constexpr int kPersistBlocks = 2048;       // multiple of the 8 XCDs
+constexpr int kMaxBatchDim = 4;            // batches: search groups of one cube, d <= 4
+constexpr size_t kMaxBatchSegs = 8192;     // data sets of one dimension per batch
 
 // ---- exact integer helpers --------------------------------------------------
 
@@ -240,6 +242,8 @@ struct hca_ctx {
     size_t io_size = 0;
     void *geo_dev = nullptr;          // offsets and direction tables
     size_t geo_dev_size = 0;
+    void *bws = nullptr;              // batches: staged rows, data-set tables, offsets
+    size_t bws_size = 0;
     // cached geometry
     bool geo_valid = false;
     int64_t geo_eps2 = -1;
@@ -333,6 +337,176 @@ struct Carver {
         return p;
     }
 };
+
+// Sizes of one launch sequence, fixed before the workspace is carved.
+struct Sizes {
+    bool wide_keys = false;
+    uint32_t gbits = 0;              // bits of the group key (direct table: 2^gbits slots)
+    uint64_t hcap = 0;               // hash slots allocated
+    uint32_t sort_tiles = 0, scan_tiles = 0;
+    int wb = 8;                      // persistent blocks of the neighbour phases
+    int tb = 1;                      // blocks of the flat per-cube kernels
+};
+
+// Lookup form, worklist and list capacities, grid sizes.
+void plan_sizes(Plan &P, uint32_t gbits, bool count_work, bool want_stats, Sizes *Z)
+{
+    const uint32_t n = P.n;
+    Z->gbits = gbits;
+    Z->wide_keys = P.key_bits > 32;
+    P.dense = gbits <= 24 && (1ull << gbits) <= std::max<uint64_t>(16ull * n, 1ull << 20);
+    Z->hcap = 1024;
+    while (Z->hcap < 2ull * n) Z->hcap <<= 1;
+    P.hash_mask = Z->hcap - 1;
+    Z->sort_tiles = (n + kSortTile - 1) / kSortTile;
+    Z->scan_tiles = (n + kScanTile - 1) / kScanTile;
+    P.work_cap = (uint32_t)std::min<uint64_t>(4ull * n + 1024, 1ull << 30) / kWorkRegions * kWorkRegions;
+    P.want_stats = want_stats;
+    P.count_work = count_work;
+    // persistent grids of the neighbour phases: enough waves to fill the chip
+    int persist = kPersistBlocks;
+    if (const char *e = std::getenv("HCA_WAVE_BLOCKS")) persist = std::max(8, std::atoi(e));
+    const int pb = (int)std::min<uint64_t>(persist, ((uint64_t)n + kBlock - 1) / kBlock * 4 + 8) & ~7;
+    Z->wb = std::max(8, pb);
+    Z->tb = (int)std::min<uint64_t>((n + kBlock - 1) / kBlock, 1024);
+    // neighbour-group lists in group mode: 64 entries per point, at least
+    // 4096 per wave, at most 2^29 in all (HCA_LIST_SLAB: entries per wave,
+    // 0 = no lists)
+    const uint64_t waves = (uint64_t)Z->wb * (kBlock / kWave);
+    uint64_t list_cap = std::min<uint64_t>(std::max<uint64_t>(64ull * n, 4096ull * waves), 1ull << 29);
+    if (const char *e = std::getenv("HCA_LIST_SLAB"))
+        list_cap = std::min<uint64_t>((uint64_t)std::max(0, std::atoi(e)) * waves, 1ull << 29);
+    P.nbr_cap = P.m > 1 ? (uint32_t)list_cap : 0;
+}
+
+// The device workspace of one launch sequence (the first bytes hold the
+// bounding-box partials).
+void carve_ws(Carver &cv, Plan &P, SortBuffers &B, const Sizes &Z, uint32_t **zero_begin, size_t *zero_bytes)
+{
+    const uint32_t n = P.n;
+    cv.take<int32_t>((size_t)kBboxBlocks * 2 * kMaxDim);
+    const size_t ksz = Z.wide_keys ? 8 : 4;
+    B.keys_a = cv.take<char>((size_t)n * ksz);
+    B.keys_b = cv.take<char>((size_t)n * ksz);
+    B.vals_a = cv.take<uint32_t>(n);
+    B.vals_b = cv.take<uint32_t>(n);
+    P.spts = cv.take<int32_t>((size_t)n * P.d);
+    P.cell_of = cv.take<uint32_t>(n);
+    P.cell_start = cv.take<uint32_t>((size_t)n + 1);
+    P.group_start = cv.take<uint32_t>((size_t)n + 1);
+    P.group_cell = cv.take<uint32_t>((size_t)n + 1);
+    P.group_key = cv.take<uint64_t>(n);
+    P.core = cv.take<uint8_t>(n);
+    P.ncore = cv.take<uint32_t>(n);
+    P.rep = P.n_dir ? cv.take<uint64_t>((size_t)n * P.n_dir) : nullptr;
+    P.parent = cv.take<uint32_t>(n);
+    P.gcube = cv.take<uint32_t>(n);
+    P.unified = cv.take<uint8_t>(n);
+    P.tile_start = cv.take<uint32_t>(n);
+    P.group_of = cv.take<uint32_t>(n);
+    if (P.nbr_cap) {
+        P.nbr_count = cv.take<uint32_t>(n);
+        P.nbr_start = cv.take<uint32_t>(n);
+        P.nbr = cv.take<uint32_t>(P.nbr_cap);
+    }
+    P.work = cv.take<uint32_t>((size_t)2 * P.work_cap);
+    P.owner = cv.take<uint32_t>(n);
+    P.cmin = cv.take<uint32_t>(n);
+    P.minmem = cv.take<uint32_t>(n);
+    P.wrank = cv.take<uint32_t>(((size_t)n + 31) / 32);
+    P.label_of = cv.take<int32_t>(n);
+    // zeroed before every call: counters, histograms, look-back words
+    const size_t zstart = cv.off;
+    P.ctr = cv.take<Counters>(1);
+    B.hist = cv.take<uint32_t>((size_t)P.passes * kRadix);
+    B.status = cv.take<uint64_t>((size_t)P.passes * Z.sort_tiles * kRadix);
+    P.scan_status = cv.take<uint64_t>((size_t)2 * Z.scan_tiles + 64);
+    P.first = cv.take<uint32_t>(((size_t)n + 31) / 32);
+    P.tile_status = cv.take<uint64_t>((size_t)Z.scan_tiles + 64);
+    *zero_bytes = cv.off - zstart;
+    *zero_begin = (uint32_t *)(cv.base ? cv.base + zstart : nullptr);
+    // lookup table, filled with all-ones
+    if (P.dense) {
+        P.table = cv.take<uint32_t>((size_t)1 << Z.gbits);
+        P.hkeys = nullptr;
+        P.hslot = nullptr;
+    } else {
+        P.table = nullptr;
+        P.hkeys = cv.take<uint64_t>(Z.hcap);
+        P.hslot = cv.take<uint64_t>(2 * Z.hcap);
+    }
+}
+
+size_t ws_bytes(Plan P, const Sizes &Z)
+{
+    Carver probe{nullptr};
+    SortBuffers B;
+    std::memset(&B, 0, sizeof B);
+    uint32_t *zb;
+    size_t zz;
+    carve_ws(probe, P, B, Z, &zb, &zz);
+    return probe.off;
+}
+
+// Steps 3-12 of a call on the context's stream (the workspace is large
+// enough): initialisation, sort, cube tables and lookup, lists, core points,
+// representatives, merging, border points, labels.  No synchronisation.
+void launch_sequence(hca_ctx *ctx, Plan &P, const Sizes &Z)
+{
+    hipStream_t s = ctx->stream;
+    SortBuffers B;
+    std::memset(&B, 0, sizeof B);
+    uint32_t *zbeg;
+    size_t zbytes;
+    Carver cv{(char *)ctx->ws};
+    carve_ws(cv, P, B, Z, &zbeg, &zbytes);
+    B.tickets = P.ctr->sort_tickets;
+    const int wb = Z.wb, tb = Z.tb;
+
+    launch_init(zbeg, zbytes / sizeof(uint32_t), P.dense ? P.table : nullptr, P.dense ? (1ull << Z.gbits) : 0, s);
+
+    // cube keys and stable radix sort (points gathered in the last pass)
+    mark(ctx, HCA_PHASE_SORT, false);
+    launch_sort(P, B, Z.wide_keys, s);
+    mark(ctx, HCA_PHASE_SORT, true);
+    P.skeys = B.result_keys;
+    P.sidx = B.result_vals;
+    // cube and group tables, lookup
+    mark(ctx, HCA_PHASE_CELLS, false);
+    launch_cells(P, Z.wide_keys, P.scan_status, P.ctr->scan_tickets + 0, s);
+    launch_table(P, tb, s);
+    mark(ctx, HCA_PHASE_CELLS, true);
+    // neighbour-group lists, core points, representatives, merging, border
+    // points, labels
+    if (P.nbr_cap) {
+        mark(ctx, HCA_PHASE_LISTS, false);
+        launch_lists(P, wb, s);
+        mark(ctx, HCA_PHASE_LISTS, true);
+    }
+    mark(ctx, HCA_PHASE_CORE, false);
+    launch_core(P, wb, s);
+    mark(ctx, HCA_PHASE_CORE, true);
+    if (P.n_dir) {
+        mark(ctx, HCA_PHASE_REPS, false);
+        launch_reps(P, wb, s);
+        mark(ctx, HCA_PHASE_REPS, true);
+    }
+    if (P.m > 1) {
+        mark(ctx, HCA_PHASE_INTRA, false);
+        launch_merge_intra(P, wb, s);
+        mark(ctx, HCA_PHASE_INTRA, true);
+    }
+    mark(ctx, HCA_PHASE_MERGE, false);
+    launch_merge(P, wb, s);
+    launch_compress(P, tb, s);
+    mark(ctx, HCA_PHASE_MERGE, true);
+    mark(ctx, HCA_PHASE_BORDER, false);
+    launch_border(P, wb, s);
+    mark(ctx, HCA_PHASE_BORDER, true);
+    mark(ctx, HCA_PHASE_LABELS, false);
+    launch_labels(P, P.scan_status + Z.scan_tiles + 32, P.ctr->scan_tickets + 1, s);
+    mark(ctx, HCA_PHASE_LABELS, true);
+}
 
 hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, double eps,
                int32_t min_pts, int32_t *labels, uint8_t *core_out, hca_stats *stats)
@@ -443,7 +617,6 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
     P.key_bits = gbits + P.fine_bits;
     if (P.key_bits > 63) return fail(ctx, HCA_E_RANGE, "packed cube key needs more than 63 bits");
     P.passes = std::max<uint32_t>(1, (P.key_bits + kRadixBits - 1) / kRadixBits);
-    const bool wide_keys = P.key_bits > 32;
     // largest coordinate difference of any pair the kernels test
     const unsigned __int128 reach = (unsigned __int128)(G.gradius + 1) * (uint64_t)G.gside - 1;
     const uint64_t dmax = (uint64_t)std::min<unsigned __int128>(reach, (unsigned __int128)span_max);
@@ -456,145 +629,14 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
         P.dir_fwd = (const uint16_t *)(gd + align256(G.off.size()));
         P.dir_bwd = (const uint16_t *)(gd + align256(G.off.size()) + align256((size_t)n_off * 2));
     }
-    P.dense = gbits <= 24 && (1ull << gbits) <= std::max<uint64_t>(16ull * n, 1ull << 20);
-    uint64_t hcap = 1024;
-    while (hcap < 2ull * n) hcap <<= 1;
-    P.hash_mask = hcap - 1;
-    const uint32_t sort_tiles = (n + kSortTile - 1) / kSortTile;
-    const uint32_t scan_tiles = (n + kScanTile - 1) / kScanTile;
-    P.work_cap = (uint32_t)std::min<uint64_t>(4ull * n + 1024, 1ull << 30) / kWorkRegions * kWorkRegions;
-    P.want_stats = stats != nullptr;
-    // persistent grids of the neighbour phases: enough waves to fill the chip
-    int persist = kPersistBlocks;
-    if (const char *e = std::getenv("HCA_WAVE_BLOCKS")) persist = std::max(8, std::atoi(e));
-    const int pb = (int)std::min<uint64_t>(persist, ((uint64_t)n + kBlock - 1) / kBlock * 4 + 8) & ~7;
-    const int wb = std::max(8, pb);
-    // neighbour-group lists in group mode: 64 entries per point, at least
-    // 4096 per wave, at most 2^29 in all (HCA_LIST_SLAB: entries per wave,
-    // 0 = no lists)
-    const uint64_t waves = (uint64_t)wb * (kBlock / kWave);
-    uint64_t list_cap = std::min<uint64_t>(std::max<uint64_t>(64ull * n, 4096ull * waves), 1ull << 29);
-    if (const char *e = std::getenv("HCA_LIST_SLAB"))
-        list_cap = std::min<uint64_t>((uint64_t)std::max(0, std::atoi(e)) * waves, 1ull << 29);
-    P.nbr_cap = P.m > 1 ? (uint32_t)list_cap : 0;
-    P.count_work = stats != nullptr && ctx->prof != -1;
-
-    // 3. workspace
-    auto carve = [&](Carver &cv, SortBuffers &B, uint32_t **zero_begin, size_t *zero_bytes) {
-        cv.take<int32_t>((size_t)kBboxBlocks * 2 * kMaxDim);
-        const size_t ksz = wide_keys ? 8 : 4;
-        B.keys_a = cv.take<char>((size_t)n * ksz);
-        B.keys_b = cv.take<char>((size_t)n * ksz);
-        B.vals_a = cv.take<uint32_t>(n);
-        B.vals_b = cv.take<uint32_t>(n);
-        P.spts = cv.take<int32_t>((size_t)n * d);
-        P.cell_of = cv.take<uint32_t>(n);
-        P.cell_start = cv.take<uint32_t>((size_t)n + 1);
-        P.group_start = cv.take<uint32_t>((size_t)n + 1);
-        P.group_cell = cv.take<uint32_t>((size_t)n + 1);
-        P.group_key = cv.take<uint64_t>(n);
-        P.core = cv.take<uint8_t>(n);
-        P.ncore = cv.take<uint32_t>(n);
-        P.rep = P.n_dir ? cv.take<uint64_t>((size_t)n * P.n_dir) : nullptr;
-        P.parent = cv.take<uint32_t>(n);
-        P.gcube = cv.take<uint32_t>(n);
-        P.unified = cv.take<uint8_t>(n);
-        P.tile_start = cv.take<uint32_t>(n);
-        P.group_of = cv.take<uint32_t>(n);
-        if (P.nbr_cap) {
-            P.nbr_count = cv.take<uint32_t>(n);
-            P.nbr_start = cv.take<uint32_t>(n);
-            P.nbr = cv.take<uint32_t>(P.nbr_cap);
-        }
-        P.work = cv.take<uint32_t>((size_t)2 * P.work_cap);
-        P.owner = cv.take<uint32_t>(n);
-        P.cmin = cv.take<uint32_t>(n);
-        P.minmem = cv.take<uint32_t>(n);
-        P.wrank = cv.take<uint32_t>(((size_t)n + 31) / 32);
-        P.label_of = cv.take<int32_t>(n);
-        // zeroed before every call: counters, histograms, look-back words
-        const size_t zstart = cv.off;
-        P.ctr = cv.take<Counters>(1);
-        B.hist = cv.take<uint32_t>((size_t)P.passes * kRadix);
-        B.status = cv.take<uint64_t>((size_t)P.passes * sort_tiles * kRadix);
-        P.scan_status = cv.take<uint64_t>((size_t)2 * scan_tiles + 64);
-        P.first = cv.take<uint32_t>(((size_t)n + 31) / 32);
-        P.tile_status = cv.take<uint64_t>((size_t)scan_tiles + 64);
-        *zero_bytes = cv.off - zstart;
-        *zero_begin = (uint32_t *)(cv.base ? cv.base + zstart : nullptr);
-        // lookup table, filled with all-ones
-        if (P.dense) {
-            P.table = cv.take<uint32_t>((size_t)1 << gbits);
-            P.hkeys = nullptr;
-            P.hslot = nullptr;
-        } else {
-            P.table = nullptr;
-            P.hkeys = cv.take<uint64_t>(hcap);
-            P.hslot = cv.take<uint64_t>(2 * hcap);
-        }
-    };
-    SortBuffers B;
-    std::memset(&B, 0, sizeof B);
-    uint32_t *zbeg;
-    size_t zbytes;
-    {
-        Carver probe{nullptr};
-        carve(probe, B, &zbeg, &zbytes);
-        st = ensure(ctx, &ctx->ws, &ctx->ws_size, probe.off, "workspace");
-        if (st) return st;
-    }
-    Carver cv{(char *)ctx->ws};
-    carve(cv, B, &zbeg, &zbytes);
-    B.tickets = P.ctr->sort_tickets;
-    partial = (int32_t *)ctx->ws;
+    Sizes Z;
+    plan_sizes(P, gbits, stats != nullptr && ctx->prof != -1, stats != nullptr, &Z);
     P.pts = points;
     P.labels = labels;
     P.core_out = core_out;
-
-    launch_init(zbeg, zbytes / sizeof(uint32_t), P.dense ? P.table : nullptr, P.dense ? (1ull << gbits) : 0, s);
-
-    // 4. cube keys and stable radix sort (points gathered in the last pass)
-    mark(ctx, HCA_PHASE_SORT, false);
-    launch_sort(P, B, wide_keys, s);
-    mark(ctx, HCA_PHASE_SORT, true);
-    P.skeys = B.result_keys;
-    P.sidx = B.result_vals;
-    // 5. cube and group tables, lookup
-    mark(ctx, HCA_PHASE_CELLS, false);
-    launch_cells(P, wide_keys, P.scan_status, P.ctr->scan_tickets + 0, s);
-    const int tb = (int)std::min<uint64_t>((n + kBlock - 1) / kBlock, 1024);
-    launch_table(P, tb, s);
-    mark(ctx, HCA_PHASE_CELLS, true);
-    // 6. neighbour-group lists, core points, representatives, merging,
-    // border points, labels
-    if (P.nbr_cap) {
-        mark(ctx, HCA_PHASE_LISTS, false);
-        launch_lists(P, wb, s);
-        mark(ctx, HCA_PHASE_LISTS, true);
-    }
-    mark(ctx, HCA_PHASE_CORE, false);
-    launch_core(P, wb, s);
-    mark(ctx, HCA_PHASE_CORE, true);
-    if (P.n_dir) {
-        mark(ctx, HCA_PHASE_REPS, false);
-        launch_reps(P, wb, s);
-        mark(ctx, HCA_PHASE_REPS, true);
-    }
-    if (P.m > 1) {
-        mark(ctx, HCA_PHASE_INTRA, false);
-        launch_merge_intra(P, wb, s);
-        mark(ctx, HCA_PHASE_INTRA, true);
-    }
-    mark(ctx, HCA_PHASE_MERGE, false);
-    launch_merge(P, wb, s);
-    launch_compress(P, tb, s);
-    mark(ctx, HCA_PHASE_MERGE, true);
-    mark(ctx, HCA_PHASE_BORDER, false);
-    launch_border(P, wb, s);
-    mark(ctx, HCA_PHASE_BORDER, true);
-    mark(ctx, HCA_PHASE_LABELS, false);
-    launch_labels(P, P.scan_status + scan_tiles + 32, P.ctr->scan_tickets + 1, s);
-    mark(ctx, HCA_PHASE_LABELS, true);
+    st = ensure(ctx, &ctx->ws, &ctx->ws_size, ws_bytes(P, Z), "workspace");
+    if (st) return st;
+    launch_sequence(ctx, P, Z);
     HCA_HIP(hipGetLastError(), "kernel launch");
     if (stats) {
         HCA_HIP(hipMemcpyAsync((char *)ctx->pinned, P.ctr, sizeof(Counters), hipMemcpyDeviceToHost, s),
@@ -629,6 +671,259 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
         stats->dense_table = (int32_t)P.dense;
         stats->list_overflow = (int32_t)hc->nbr_overflow;
     }
+    return HCA_OK;
+}
+
+// ---- batches -------------------------------------------------------------------
+// The data sets of one dimension, staged contiguously and clustered by one
+// launch sequence.
+struct BatchGroup {
+    int d = 0;
+    std::vector<int32_t> segs;          // caller indices
+    uint32_t n = 0;                     // rows
+    std::vector<SegParam> par;
+    std::vector<int32_t> radius;
+    std::vector<int8_t> off;            // union of the data sets' stencils, self first
+    std::vector<uint16_t> dir_fwd, dir_bwd;
+    uint32_t n_dir = 0;
+    // device / pinned placement (byte offsets)
+    size_t d_seg = 0, d_pts = 0, d_segof = 0, d_lab = 0, d_box = 0, d_off = 0, d_dirf = 0, d_dirb = 0;
+    size_t h_seg = 0, h_off = 0, h_box = 0;
+    Plan P;
+    Sizes Z;
+};
+
+// Offsets that some data set of the group can need: for a data set with side
+// s and eps^2 e, sum over D_k != 0 of ((|D_k| - 1) s + 1)^2 <= e.  Self
+// first, then nearest (smallest gap relative to eps) first.
+void batch_stencil(BatchGroup &g)
+{
+    const int d = g.d;
+    int32_t r = 0;
+    for (int32_t v : g.radius) r = std::max(r, v);
+    int64_t total = 1;
+    for (int k = 0; k < d; k++) total *= 2 * r + 1;
+    std::vector<std::pair<double, std::vector<int8_t>>> keep;
+    std::vector<int32_t> o(d, -r);
+    for (int64_t code = 0; code < total; code++) {
+        bool zero = true;
+        for (int k = 0; k < d; k++) zero &= o[k] == 0;
+        if (!zero) {
+            double best = 2.0;
+            for (size_t i = 0; i < g.par.size(); i++) {
+                const SegParam &sp = g.par[i];
+                unsigned __int128 acc = 0;
+                for (int k = 0; k < d; k++) {
+                    const int64_t a = std::abs(o[k]);
+                    const unsigned __int128 gap = a ? (unsigned __int128)(a - 1) * (uint64_t)sp.side + 1 : 0;
+                    acc += gap * gap;
+                }
+                if (acc <= (unsigned __int128)sp.eps2) best = std::min(best, (double)acc / (double)sp.eps2);
+            }
+            if (best <= 1.0) keep.push_back({best, std::vector<int8_t>(o.begin(), o.end())});
+        }
+        for (int k = d - 1; k >= 0; k--) {
+            if (++o[k] <= r) break;
+            o[k] = -r;
+        }
+    }
+    std::stable_sort(keep.begin(), keep.end(), [](const auto &a, const auto &b) { return a.first < b.first; });
+    g.off.assign(d, 0);
+    for (const auto &e : keep) g.off.insert(g.off.end(), e.second.begin(), e.second.end());
+    const uint32_t n_off = (uint32_t)(g.off.size() / d);
+    g.n_dir = 0;
+    if (d <= 4 && env_reps()) {
+        uint32_t v = 1;
+        for (int k = 0; k < d; k++) v *= 3;
+        g.n_dir = v - 1;
+    }
+    g.dir_fwd.assign(n_off, 0);
+    g.dir_bwd.assign(n_off, 0);
+    if (g.n_dir)
+        for (uint32_t j = 1; j < n_off; j++) {
+            g.dir_fwd[j] = direction_index(&g.off[(size_t)j * d], d, 1);
+            g.dir_bwd[j] = direction_index(&g.off[(size_t)j * d], d, -1);
+        }
+}
+
+hca_status run_batch(hca_ctx *ctx, const int32_t *points, int32_t nseg, const int64_t *rows, const int32_t *dims,
+                     const double *eps, const int32_t *min_pts, int32_t *labels)
+{
+    if (!ctx) return HCA_E_INVAL;
+    ctx->err.clear();
+    if (nseg < 0) return fail(ctx, HCA_E_INVAL, "nseg must be >= 0");
+    if (nseg == 0) return HCA_OK;
+    if (!rows || !dims || !eps || !min_pts) return fail(ctx, HCA_E_INVAL, "per-data-set arrays must not be NULL");
+    uint64_t total_rows = 0, total_elems = 0;
+    for (int32_t i = 0; i < nseg; i++) {
+        if (rows[i] < 0) return fail(ctx, HCA_E_INVAL, "rows must be >= 0");
+        if (dims[i] < 1 || dims[i] > kMaxBatchDim) return fail(ctx, HCA_E_INVAL, "batch data sets need d in [1, 4]");
+        if (!(eps[i] > 0.0) || !std::isfinite(eps[i])) return fail(ctx, HCA_E_INVAL, "eps must be finite and > 0");
+        if (min_pts[i] < 1) return fail(ctx, HCA_E_INVAL, "min_pts must be >= 1");
+        total_rows += (uint64_t)rows[i];
+        total_elems += (uint64_t)rows[i] * (uint64_t)dims[i];
+        if (total_rows > (uint64_t)INT32_MAX) return fail(ctx, HCA_E_INVAL, "more than 2^31 - 1 rows in all");
+    }
+    if (total_rows == 0) return HCA_OK;
+    if (!points || !labels) return fail(ctx, HCA_E_INVAL, "points and labels must not be NULL");
+    if ((uintptr_t)points % 4 || (uintptr_t)labels % 4) return fail(ctx, HCA_E_INVAL, "misaligned arrays");
+    hipStream_t s = ctx->stream;
+    HCA_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+
+    // 1. data sets by dimension, with their exact eps^2, cube side, places
+    std::vector<BatchGroup> groups;
+    {
+        BatchGroup by_d[kMaxBatchDim + 1];
+        uint64_t elem = 0, row = 0;
+        for (int32_t i = 0; i < nseg; i++) {
+            BatchGroup &g = by_d[dims[i]];
+            g.d = dims[i];
+            SegParam sp;
+            std::memset(&sp, 0, sizeof sp);
+            exact_eps2(eps[i], &sp.eps2);
+            sp.side = std::max<int64_t>(1, (int64_t)isqrt_u64((uint64_t)sp.eps2 / (uint64_t)dims[i]));
+            sp.side = std::min<int64_t>(sp.side, 1ll << 31);
+            sp.src_elem = elem;
+            sp.min_pts = (uint32_t)min_pts[i];
+            sp.vstart = g.n;
+            sp.dst_row = (uint32_t)row;
+            g.segs.push_back(i);
+            g.par.push_back(sp);
+            g.radius.push_back(offset_radius(sp.side, sp.eps2));
+            g.n += (uint32_t)rows[i];
+            elem += (uint64_t)rows[i] * (uint64_t)dims[i];
+            row += (uint64_t)rows[i];
+        }
+        for (int dd = 1; dd <= kMaxBatchDim; dd++)
+            if (by_d[dd].n > 0) groups.push_back(std::move(by_d[dd]));
+    }
+    for (BatchGroup &g : groups) {
+        if (g.par.size() > kMaxBatchSegs) return fail(ctx, HCA_E_INVAL, "more than 8192 data sets of one dimension");
+        batch_stencil(g);
+    }
+
+    // 2. placement of the staged rows, tables and offsets
+    size_t dev = 0, pin = 0;
+    for (BatchGroup &g : groups) {
+        const size_t ns = g.par.size(), n_off = g.off.size() / g.d;
+        g.d_seg = dev; dev = align256(dev + ns * sizeof(SegParam));
+        g.d_pts = dev; dev = align256(dev + (size_t)g.n * g.d * sizeof(int32_t));
+        g.d_segof = dev; dev = align256(dev + (size_t)g.n * sizeof(uint32_t));
+        g.d_lab = dev; dev = align256(dev + (size_t)g.n * sizeof(int32_t));
+        g.d_box = dev; dev = align256(dev + ns * 2 * g.d * sizeof(uint32_t));
+        g.d_off = dev; dev = align256(dev + g.off.size());
+        g.d_dirf = dev; dev = align256(dev + n_off * sizeof(uint16_t));
+        g.d_dirb = dev; dev = align256(dev + n_off * sizeof(uint16_t));
+        g.h_seg = pin; pin = align256(pin + ns * sizeof(SegParam));
+        g.h_off = pin; pin = align256(pin + g.off.size() + 2 * n_off * sizeof(uint16_t));
+        g.h_box = pin; pin = align256(pin + ns * 2 * g.d * sizeof(uint32_t));
+    }
+    hca_status st = ensure(ctx, &ctx->bws, &ctx->bws_size, dev, "batch staging");
+    if (st) return st;
+    st = ensure_pinned(ctx, pin);
+    if (st) return st;
+    char *db = (char *)ctx->bws, *hb = (char *)ctx->pinned;
+
+    // 3. stage every group's rows and take the data sets' bounding boxes
+    for (BatchGroup &g : groups) {
+        const size_t ns = g.par.size(), n_off = g.off.size() / g.d;
+        std::memcpy(hb + g.h_off, g.off.data(), g.off.size());
+        std::memcpy(hb + g.h_off + g.off.size(), g.dir_fwd.data(), n_off * 2);
+        std::memcpy(hb + g.h_off + g.off.size() + n_off * 2, g.dir_bwd.data(), n_off * 2);
+        HCA_HIP(hipMemcpyAsync(db + g.d_off, hb + g.h_off, g.off.size(), hipMemcpyHostToDevice, s), "offsets");
+        HCA_HIP(hipMemcpyAsync(db + g.d_dirf, hb + g.h_off + g.off.size(), n_off * 2, hipMemcpyHostToDevice, s),
+                "directions");
+        HCA_HIP(hipMemcpyAsync(db + g.d_dirb, hb + g.h_off + g.off.size() + n_off * 2, n_off * 2,
+                               hipMemcpyHostToDevice, s), "directions");
+        std::memcpy(hb + g.h_seg, g.par.data(), ns * sizeof(SegParam));
+        HCA_HIP(hipMemcpyAsync(db + g.d_seg, hb + g.h_seg, ns * sizeof(SegParam), hipMemcpyHostToDevice, s),
+                "data-set table");
+        launch_init((uint32_t *)(db + g.d_box), ns * 2 * g.d, nullptr, 0, s);
+        launch_seg_stage(g.d, (const SegParam *)(db + g.d_seg), (uint32_t)ns, points, (int32_t *)(db + g.d_pts),
+                         (uint32_t *)(db + g.d_segof), g.n, (uint32_t *)(db + g.d_box), s);
+        HCA_HIP(hipMemcpyAsync(hb + g.h_box, db + g.d_box, ns * 2 * g.d * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                               s), "box copy");
+    }
+    HCA_HIP(hipGetLastError(), "staging launch");
+    HCA_HIP(hipStreamSynchronize(s), "box sync");
+
+    // 4. per group: origins, one key layout for all its data sets, the plan
+    size_t ws_need = 0;
+    for (BatchGroup &g : groups) {
+        const int d = g.d;
+        const size_t ns = g.par.size();
+        const uint32_t *box = (const uint32_t *)(hb + g.h_box);
+        uint64_t cmax[kMaxDim] = {};
+        bool wide = false;
+        for (size_t i = 0; i < ns; i++) {
+            SegParam &sp = g.par[i];
+            if (rows[g.segs[i]] == 0) continue;
+            int64_t span_max = 0;
+            for (int k = 0; k < d; k++) {
+                const int32_t lo = (int32_t)(~box[i * 2 * d + k] ^ 0x80000000u);
+                const int32_t hi = (int32_t)(box[i * 2 * d + d + k] ^ 0x80000000u);
+                const int64_t span = (int64_t)hi - lo;
+                if (span >= (1ll << 30)) return fail(ctx, HCA_E_RANGE, "coordinate span >= 2^30 along an axis");
+                sp.origin[k] = lo;
+                span_max = std::max(span_max, span);
+                cmax[k] = std::max<uint64_t>(cmax[k], (uint64_t)span / (uint64_t)sp.side);
+            }
+            const unsigned __int128 reach = (unsigned __int128)(g.radius[i] + 1) * (uint64_t)sp.side - 1;
+            const uint64_t dmax = (uint64_t)std::min<unsigned __int128>(reach, (unsigned __int128)span_max);
+            wide |= (unsigned __int128)d * dmax * dmax >= ((unsigned __int128)1 << 31);
+        }
+        Plan &P = g.P;
+        std::memset(&P, 0, sizeof P);
+        P.n = g.n;
+        P.d = d;
+        P.m = 1;
+        P.side = 1;
+        P.gside = 1;
+        P.min_pts = 1;
+        P.eps2 = 0;
+        uint32_t bits = 0;
+        for (int k = d - 1; k >= 0; k--) {
+            P.gw[k] = bit_length(cmax[k]);
+            P.gmax[k] = P.gw[k] ? (uint32_t)((1ull << P.gw[k]) - 1) : 0u;
+            P.goff[k] = bits;
+            bits += P.gw[k];
+        }
+        P.nseg = (uint32_t)ns;
+        P.seg_shift = bits;
+        P.key_bits = bits + bit_length(ns - 1);
+        if (P.key_bits > 63) return fail(ctx, HCA_E_RANGE, "packed batch key needs more than 63 bits");
+        P.passes = std::max<uint32_t>(1, (P.key_bits + kRadixBits - 1) / kRadixBits);
+        P.wide = wide ? 1 : 0;
+        P.n_off = (uint32_t)(g.off.size() / d);
+        P.n_dir = g.n_dir;
+        P.off = (const int8_t *)(db + g.d_off);
+        P.dir_fwd = (const uint16_t *)(db + g.d_dirf);
+        P.dir_bwd = (const uint16_t *)(db + g.d_dirb);
+        P.seg = (SegParam *)(db + g.d_seg);
+        P.seg_of = (const uint32_t *)(db + g.d_segof);
+        P.pts = (const int32_t *)(db + g.d_pts);
+        P.labels = (int32_t *)(db + g.d_lab);
+        P.core_out = nullptr;
+        plan_sizes(P, P.key_bits, false, false, &g.Z);
+        ws_need = std::max(ws_need, ws_bytes(P, g.Z));
+        // origins into the device table (stream-ordered before the launches)
+        std::memcpy(hb + g.h_seg, g.par.data(), ns * sizeof(SegParam));
+        HCA_HIP(hipMemcpyAsync(db + g.d_seg, hb + g.h_seg, ns * sizeof(SegParam), hipMemcpyHostToDevice, s),
+                "data-set table");
+    }
+    st = ensure(ctx, &ctx->ws, &ctx->ws_size, ws_need, "workspace");
+    if (st) return st;
+
+    // 5. one launch sequence per dimension, labels back to the caller
+    const int32_t prof = ctx->prof;
+    ctx->prof = -1;
+    for (BatchGroup &g : groups) {
+        launch_sequence(ctx, g.P, g.Z);
+        launch_seg_scatter(g.P.seg, g.P.seg_of, g.P.labels, labels, g.n, s);
+    }
+    ctx->prof = prof;
+    HCA_HIP(hipGetLastError(), "kernel launch");
+    HCA_HIP(hipStreamSynchronize(s), "batch sync");
     return HCA_OK;
 }
 
@@ -680,6 +975,7 @@ void hca_destroy(hca_ctx *ctx)
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->io) (void)hipFree(ctx->io);
     if (ctx->geo_dev) (void)hipFree(ctx->geo_dev);
+    if (ctx->bws) (void)hipFree(ctx->bws);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     if (ctx->ev_made)
         for (auto &e : ctx->ev) (void)hipEventDestroy(e);
@@ -722,6 +1018,12 @@ hca_status hca_cluster_ex(hca_ctx *ctx, const int32_t *points, int64_t n, int32_
                           int32_t min_pts, int32_t *labels, uint8_t *core, hca_stats *stats)
 {
     return run(ctx, points, n, d, eps, min_pts, labels, core, stats);
+}
+
+hca_status hca_cluster_batch(hca_ctx *ctx, const int32_t *points, int32_t nseg, const int64_t *rows,
+                             const int32_t *dims, const double *eps, const int32_t *min_pts, int32_t *labels)
+{
+    return run_batch(ctx, points, nseg, rows, dims, eps, min_pts, labels);
 }
 
 hca_status hca_cluster_host(hca_ctx *ctx, const int32_t *points, int64_t n, int32_t d, double eps,

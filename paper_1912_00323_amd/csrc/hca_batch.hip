@@ -1,0 +1,124 @@
+// Batches: many independent data sets clustered by one launch sequence.
+//
+// The data sets of one dimension are staged one after the other; each keeps
+// its own eps, minPts, cube side and origin (SegParam), and its index sits
+// above the cube coordinates in the packed key, so the sort, the cube tables,
+// the lookup and the union-find see one key space in which cubes of
+// different data sets are never neighbours.  These kernels stage the rows,
+// take every data set's bounding box and write the labels back.
+#include <algorithm>
+
+#include "hca_device.h"
+#include "hca_kernels.h"
+
+namespace hca {
+
+// Data set of staged row r: last s with vstart[s] <= r (empty data sets share
+// their successor's start and are skipped).
+__device__ __forceinline__ uint32_t seg_of_row(const uint32_t *s_vs, uint32_t nseg, uint32_t r)
+{
+    uint32_t lo = 0, hi = nseg;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (s_vs[mid] <= r) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Copy the rows of every data set (at its own offset in the caller's array)
+// into one contiguous array, and record each row's data set.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_seg_gather(const SegParam *seg, uint32_t nseg, const int32_t *src,
+                                                       int32_t *dst, uint32_t *seg_of, uint32_t n)
+{
+    extern __shared__ uint32_t s_vs[];
+    for (uint32_t i = threadIdx.x; i < nseg; i += kBlock) s_vs[i] = seg[i].vstart;
+    __syncthreads();
+    for (uint32_t r = blockIdx.x * kBlock + threadIdx.x; r < n; r += gridDim.x * kBlock) {
+        const uint32_t s = seg_of_row(s_vs, nseg, r);
+        const int32_t *p = src + seg[s].src_elem + (uint64_t)(r - s_vs[s]) * D;
+#pragma unroll
+        for (int k = 0; k < D; k++) dst[(uint64_t)r * D + k] = p[k];
+        seg_of[r] = s;
+    }
+}
+
+// Bounding box of every data set: order-preserving unsigned images of the
+// coordinates, the maximum of ~image for the minimum and of the image for the
+// maximum, so that a zeroed array is the neutral start.  One atomic per wave
+// and axis when the wave's rows share a data set.
+__device__ __forceinline__ uint32_t ord32(int32_t v) { return (uint32_t)v ^ 0x80000000u; }
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_seg_bbox(const int32_t *pts, const uint32_t *seg_of, uint32_t n,
+                                                     uint32_t *box)
+{
+    for (uint32_t base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
+        const uint32_t r = base + threadIdx.x;
+        const bool in = r < n;
+        const uint32_t s = in ? seg_of[r] : kNone;
+        const uint32_t s0 = __shfl(s, 0);
+        const bool same = __ballot(in && s != s0) == 0;
+        const Pt<D> p = load_pt<D>(pts, in ? r : 0);
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+            const uint32_t lo = in ? ~ord32(p.x[k]) : 0u, hi = in ? ord32(p.x[k]) : 0u;
+            if (same) {
+                const uint32_t wlo = wave_max(lo), whi = wave_max(hi);
+                if (lane_id() == 0 && s0 != kNone) {
+                    atomicMax(box + (uint64_t)s0 * 2 * D + k, wlo);
+                    atomicMax(box + (uint64_t)s0 * 2 * D + D + k, whi);
+                }
+            } else if (in) {
+                atomicMax(box + (uint64_t)s * 2 * D + k, lo);
+                atomicMax(box + (uint64_t)s * 2 * D + D + k, hi);
+            }
+        }
+    }
+}
+
+// Labels back to the caller's layout.
+__global__ __launch_bounds__(kBlock) void k_seg_scatter(const SegParam *seg, const uint32_t *seg_of,
+                                                        const int32_t *staged, int32_t *out, uint32_t n)
+{
+    for (uint32_t r = blockIdx.x * kBlock + threadIdx.x; r < n; r += gridDim.x * kBlock) {
+        const SegParam &sp = seg[seg_of[r]];
+        out[(uint64_t)sp.dst_row + (r - sp.vstart)] = staged[r];
+    }
+}
+
+template <int D>
+static void gather_d(const SegParam *seg, uint32_t nseg, const int32_t *src, int32_t *dst, uint32_t *seg_of,
+                     uint32_t n, hipStream_t s)
+{
+    const int blocks = (int)std::min<uint64_t>((n + kBlock - 1) / kBlock, 2048);
+    hipLaunchKernelGGL(k_seg_gather<D>, dim3(blocks), dim3(kBlock), nseg * sizeof(uint32_t), s, seg, nseg, src,
+                       dst, seg_of, n);
+}
+
+template <int D>
+static void bbox_d(const int32_t *pts, const uint32_t *seg_of, uint32_t n, uint32_t *box, hipStream_t s)
+{
+    const int blocks = (int)std::min<uint64_t>((n + kBlock - 1) / kBlock, 2048);
+    hipLaunchKernelGGL(k_seg_bbox<D>, dim3(blocks), dim3(kBlock), 0, s, pts, seg_of, n, box);
+}
+
+void launch_seg_stage(int d, const SegParam *seg, uint32_t nseg, const int32_t *src, int32_t *dst,
+                      uint32_t *seg_of, uint32_t n, uint32_t *box, hipStream_t s)
+{
+    switch (d) {
+    case 1: gather_d<1>(seg, nseg, src, dst, seg_of, n, s); bbox_d<1>(dst, seg_of, n, box, s); break;
+    case 2: gather_d<2>(seg, nseg, src, dst, seg_of, n, s); bbox_d<2>(dst, seg_of, n, box, s); break;
+    case 3: gather_d<3>(seg, nseg, src, dst, seg_of, n, s); bbox_d<3>(dst, seg_of, n, box, s); break;
+    case 4: gather_d<4>(seg, nseg, src, dst, seg_of, n, s); bbox_d<4>(dst, seg_of, n, box, s); break;
+    }
+}
+
+void launch_seg_scatter(const SegParam *seg, const uint32_t *seg_of, const int32_t *staged, int32_t *out,
+                        uint32_t n, hipStream_t s)
+{
+    const int blocks = (int)std::min<uint64_t>((n + kBlock - 1) / kBlock, 2048);
+    hipLaunchKernelGGL(k_seg_scatter, dim3(blocks), dim3(kBlock), 0, s, seg, seg_of, staged, out, n);
+}
+
+}  // namespace hca

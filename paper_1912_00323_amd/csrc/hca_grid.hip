@@ -23,6 +23,42 @@ struct QBox {
     int32_t lo[D], hi[D];
 };
 
+// Search parameters of a cube: the call's, or in a batch those of the cube's
+// data set (the top bits of its key).
+template <int D>
+struct Geo {
+    int64_t eps2;
+    int64_t gside;
+    int32_t origin[D];
+    uint32_t min_pts;
+};
+
+template <int D>
+__device__ __forceinline__ Geo<D> call_geo(const Plan &P)
+{
+    Geo<D> g;
+    g.eps2 = P.eps2;
+    g.gside = P.gside;
+#pragma unroll
+    for (int e = 0; e < D; e++) g.origin[e] = P.origin[e];
+    g.min_pts = (uint32_t)P.min_pts;
+    return g;
+}
+
+template <int D>
+__device__ __forceinline__ Geo<D> cube_geo(const Plan &P, uint64_t key)
+{
+    if (!P.nseg) return call_geo<D>(P);
+    const SegParam &sp = P.seg[(uint32_t)(key >> P.seg_shift)];
+    Geo<D> g;
+    g.eps2 = sp.eps2;
+    g.gside = sp.side;
+#pragma unroll
+    for (int e = 0; e < D; e++) g.origin[e] = sp.origin[e];
+    g.min_pts = sp.min_pts;
+    return g;
+}
+
 template <int D>
 __device__ __forceinline__ QBox<D> chunk_box(const Pt<D> *pp, uint32_t mask)
 {
@@ -44,20 +80,26 @@ __device__ __forceinline__ QBox<D> chunk_box(const Pt<D> *pp, uint32_t mask)
 // Can the group with key nk hold a point within eps of the query box q?
 // (closest approach of the group's box to q, from the key alone)
 template <int D>
-__device__ __forceinline__ bool group_box_within(const Plan &P, uint64_t nk, const QBox<D> &q)
+__device__ __forceinline__ bool group_box_within(const Plan &P, uint64_t nk, const QBox<D> &q, const Geo<D> &geo)
 {
     int64_t acc = 0;
 #pragma unroll
     for (int e = 0; e < D; e++) {
         const int64_t gc = (int64_t)((nk >> P.goff[e]) & ((1ull << P.gw[e]) - 1ull));
-        const int64_t glo = (int64_t)P.origin[e] + gc * P.gside;
-        const int64_t ghi = glo + P.gside - 1;
+        const int64_t glo = (int64_t)geo.origin[e] + gc * geo.gside;
+        const int64_t ghi = glo + geo.gside - 1;
         int64_t gap = 0;
         if (glo > q.hi[e]) gap = glo - q.hi[e];
         else if ((int64_t)q.lo[e] > ghi) gap = (int64_t)q.lo[e] - ghi;
         acc += gap * gap;
     }
-    return acc <= P.eps2;
+    return acc <= geo.eps2;
+}
+
+template <int D>
+__device__ __forceinline__ bool group_box_within(const Plan &P, uint64_t nk, const QBox<D> &q)
+{
+    return group_box_within<D>(P, nk, q, call_geo<D>(P));
 }
 
 // ---------------------------------------------------------------------------
@@ -107,7 +149,7 @@ __device__ __forceinline__ uint32_t load_neighbours(const Plan &P, uint32_t g, u
                                                     const NbrSrc &src, uint32_t first,
                                                     uint32_t lowest, bool need_core,
                                                     const QBox<D> &q, uint32_t *s_beg,
-                                                    uint32_t *s_pre)
+                                                    uint32_t *s_pre, const Geo<D> &geo)
 {
     const uint32_t l = lane_id();
     const uint32_t j = first + l;
@@ -117,10 +159,10 @@ __device__ __forceinline__ uint32_t load_neighbours(const Plan &P, uint32_t g, u
         if (src.lists) {
             uint64_t nk;
             G = slot_group<D>(P, g, gkey, src, j, &nk);
-            if (!group_box_within<D>(P, nk, q)) G = kNone;
+            if (!group_box_within<D>(P, nk, q, geo)) G = kNone;
         } else {
             const uint64_t nk = group_neighbour<D>(P, gkey, P.off + (uint64_t)j * D);
-            if (nk != ~0ull && group_box_within<D>(P, nk, q)) G = group_lookup(P, nk);
+            if (nk != ~0ull && group_box_within<D>(P, nk, q, geo)) G = group_lookup(P, nk);
         }
         if (G != kNone && G >= lowest &&
             !(need_core && (P.m == 1 ? P.ncore[G] == 0 : P.gcube[G] == kNone))) {
@@ -416,15 +458,15 @@ __global__ __launch_bounds__(kBlock) void k_nbr_lists(Plan P)
 template <int D, bool WIDE>
 __device__ __forceinline__ uint32_t count_walk(const Plan &P, uint32_t g, uint64_t gkey, const Pt<D> *pp,
                                                uint32_t done, uint32_t *cnt, uint32_t *s_beg,
-                                               uint32_t *s_pre, uint32_t &lt)
+                                               uint32_t *s_pre, uint32_t &lt, const Geo<D> &geo)
 {
     const uint32_t l = lane_id();
-    const uint32_t minpts = (uint32_t)P.min_pts;
+    const uint32_t minpts = geo.min_pts;
     const uint32_t all = (1u << kPch) - 1u;
     const QBox<D> qb = chunk_box<D>(pp, ~done);
     const NbrSrc src = nbr_source(P, g);
     for (uint32_t oc = 0; oc < src.slots && done != all; oc += kWave) {
-        const uint32_t total = load_neighbours<D>(P, g, gkey, src, oc, 0, false, qb, s_beg, s_pre);
+        const uint32_t total = load_neighbours<D>(P, g, gkey, src, oc, 0, false, qb, s_beg, s_pre, geo);
         for (uint32_t ci = 0; ci < total && done != all; ci += kWave) {
             const uint32_t c = ci + l;
             const bool ok = c < total;
@@ -438,7 +480,7 @@ __device__ __forceinline__ uint32_t count_walk(const Plan &P, uint32_t g, uint64
             for (int k = 0; k < kPch; k++) {
                 if (done & (1u << k)) continue;
                 lt += ok;
-                const bool hit = ok && within<D, WIDE>(pp[k], q, P.eps2);
+                const bool hit = ok && within<D, WIDE>(pp[k], q, geo.eps2);
                 cnt[k] += __popcll(__ballot(hit));
                 if (cnt[k] >= minpts) done |= 1u << k;
             }
@@ -463,13 +505,14 @@ __global__ __launch_bounds__(kBlock) void k_core(Plan P)
     __shared__ uint32_t s_beg[kWavesPerBlock][kWave], s_pre[kWavesPerBlock][kWave];
     const uint32_t w = wave_in_block(), l = lane_id();
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
-    const uint32_t minpts = (uint32_t)P.min_pts;
     uint32_t lt = 0;
     const WaveRange hca_wr_ = wave_range();
     HCA_FOR_UNITS(g, ng) {
         const uint32_t p0 = P.group_start[g], p1 = P.group_start[g + 1];
         const uint32_t c0 = P.group_cell[g], c1 = P.group_cell[g + 1];
         const uint64_t gkey = P.group_key[g];
+        const Geo<D> geo = cube_geo<D>(P, gkey);
+        const uint32_t minpts = geo.min_pts;
         bool any_sparse = false;
         for (uint32_t c = c0; c < c1; c++) {
             const uint32_t a = P.cell_start[c], b = P.cell_start[c + 1];
@@ -501,7 +544,7 @@ __global__ __launch_bounds__(kBlock) void k_core(Plan P)
             }
             done = uniform(done);
             const uint32_t all = (1u << kPch) - 1u;
-            if (done != all) done = count_walk<D, WIDE>(P, g, gkey, pp, done, cnt, s_beg[w], s_pre[w], lt);
+            if (done != all) done = count_walk<D, WIDE>(P, g, gkey, pp, done, cnt, s_beg[w], s_pre[w], lt, geo);
             // lane k < np writes the result of point pc + k
             uint32_t mine = 0;
 #pragma unroll
@@ -554,6 +597,7 @@ __global__ __launch_bounds__(kBlock) void k_core_chunks(Plan P)
     __shared__ uint32_t s_beg[kWavesPerBlock][kWave], s_pre[kWavesPerBlock][kWave];
     const uint32_t w = wave_in_block(), l = lane_id();
     const uint32_t n = P.n, minpts = (uint32_t)P.min_pts;
+    const Geo<D> geo = call_geo<D>(P);
     const uint32_t all = (1u << kPch) - 1u;
     uint32_t lt = 0;
     const WaveRange hca_wr_ = wave_range();
@@ -580,7 +624,7 @@ __global__ __launch_bounds__(kBlock) void k_core_chunks(Plan P)
                 const uint32_t run = (uint32_t)__ballot(grp == g) & left;
                 left &= ~run;
                 const uint32_t got = count_walk<D, WIDE>(P, g, P.group_key[g], pp, ~run & all, cnt, s_beg[w],
-                                                         s_pre[w], lt);
+                                                         s_pre[w], lt, geo);
                 done |= got & run;
             }
         }
@@ -627,7 +671,6 @@ template <int D>
 __global__ __launch_bounds__(kBlock) void k_reps(Plan P)
 {
     const uint32_t l = lane_id();
-    const int64_t s = P.side;
     uint32_t zero = 0, mul = 1;
 #pragma unroll
     for (int k = 0; k < D; k++) { zero += mul; mul *= 3; }
@@ -645,10 +688,12 @@ __global__ __launch_bounds__(kBlock) void k_reps(Plan P)
         {
             const Pt<D> p = load_pt<D>(P.spts, in ? q : 0);
             const uint64_t gkey = in ? P.group_key[c] : 0;
+            const SegParam *sp = P.nseg ? P.seg + (uint32_t)(gkey >> P.seg_shift) : nullptr;
+            const int64_t s = sp ? sp->side : (int64_t)P.side;
 #pragma unroll
             for (int k = 0; k < D; k++) {
                 const int64_t gc = (int64_t)((gkey >> P.goff[k]) & ((1ull << P.gw[k]) - 1ull));
-                const int64_t u = (int64_t)p.x[k] - ((int64_t)P.origin[k] + gc * s);
+                const int64_t u = (int64_t)p.x[k] - ((int64_t)(sp ? sp->origin[k] : P.origin[k]) + gc * s);
                 up[k] = (uint64_t)((s - u) * (s - u));
                 dn[k] = (uint64_t)(u * u);
             }
@@ -698,6 +743,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_rep(Plan P)
     HCA_FOR_UNITS(A, nc) {
         if (P.ncore[A] == 0) continue;
         const uint64_t gkey = P.group_key[A];
+        const int64_t eps2 = cube_geo<D>(P, gkey).eps2;
         for (uint32_t oc = 1; oc < P.n_off; oc += kWave) {
             const uint32_t j = oc + l;
             uint32_t B = kNone;
@@ -712,7 +758,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_rep(Plan P)
                 const uint32_t qa = (uint32_t)ld_agent(P.rep + (uint64_t)A * P.n_dir + P.dir_fwd[j]);
                 const uint32_t qb = (uint32_t)ld_agent(P.rep + (uint64_t)B * P.n_dir + P.dir_bwd[j]);
                 lt++;
-                joined = within<D, WIDE>(load_pt<D>(P.spts, qa), load_pt<D>(P.spts, qb), P.eps2);
+                joined = within<D, WIDE>(load_pt<D>(P.spts, qa), load_pt<D>(P.spts, qb), eps2);
                 if (joined) uf_union(P.parent, A, B);
             }
             const bool exact = todo && !joined;
@@ -753,6 +799,7 @@ __device__ void exact_pair(const Plan &P, uint32_t A, uint32_t B, uint32_t &lt)
 {
     const uint32_t l = lane_id();
     if (uf_find(P.parent, A) == uf_find(P.parent, B)) return;
+    const int64_t eps2 = cube_geo<D>(P, P.group_key[A]).eps2;
     const uint32_t a0 = P.cell_start[A], na = P.cell_start[A + 1] - a0;
     const uint32_t b0 = P.cell_start[B], nb = P.cell_start[B + 1] - b0;
     const uint64_t total = (uint64_t)na * nb;
@@ -766,7 +813,7 @@ __device__ void exact_pair(const Plan &P, uint32_t A, uint32_t B, uint32_t &lt)
             const uint32_t pa = a0 + i, pb = b0 + j;
             if (P.core[pa] && P.core[pb]) {
                 lt++;
-                hit = within<D, WIDE>(load_pt<D>(P.spts, pa), load_pt<D>(P.spts, pb), P.eps2);
+                hit = within<D, WIDE>(load_pt<D>(P.spts, pa), load_pt<D>(P.spts, pb), eps2);
             }
         }
         if (__ballot(hit)) { found = true; break; }
@@ -1299,13 +1346,14 @@ __global__ __launch_bounds__(kBlock) void k_compress(Plan P)
 template <int D, bool WIDE>
 __device__ __forceinline__ void border_walk(const Plan &P, uint32_t g, uint64_t gkey, const Pt<D> *pp,
                                             uint32_t todo, int64_t *bd, uint32_t *bi, uint32_t *bp,
-                                            uint32_t *s_beg, uint32_t *s_pre, uint32_t &lt)
+                                            uint32_t *s_beg, uint32_t *s_pre, uint32_t &lt, const Geo<D> &geo)
 {
+    const int64_t eps2 = geo.eps2;
     const uint32_t l = lane_id();
     const QBox<D> qb = chunk_box<D>(pp, todo);
     const NbrSrc src = nbr_source(P, g);
     for (uint32_t oc = 0; oc < src.slots; oc += kWave) {
-        const uint32_t total = load_neighbours<D>(P, g, gkey, src, oc, 0, true, qb, s_beg, s_pre);
+        const uint32_t total = load_neighbours<D>(P, g, gkey, src, oc, 0, true, qb, s_beg, s_pre, geo);
         for (uint32_t ci = 0; ci < total; ci += kWave) {
             const uint32_t c = ci + l;
             bool ok = c < total;
@@ -1323,14 +1371,14 @@ __device__ __forceinline__ void border_walk(const Plan &P, uint32_t g, uint64_t 
             for (int k = 0; k < kPch; k++) {
                 if (todo & (1u << k)) lt += ok;
                 dd[k] = dist2<D, WIDE>(pp[k], q);
-                near |= (todo & (1u << k)) && ok && dd[k] <= P.eps2 && dd[k] <= bd[k];
+                near |= (todo & (1u << k)) && ok && dd[k] <= eps2 && dd[k] <= bd[k];
             }
             if (!near) continue;
             const uint32_t qi = P.sidx[pos];
 #pragma unroll
             for (int k = 0; k < kPch; k++) {
                 if (!(todo & (1u << k))) continue;
-                if (ok && dd[k] <= P.eps2 && (dd[k] < bd[k] || (dd[k] == bd[k] && qi < bi[k]))) {
+                if (ok && dd[k] <= eps2 && (dd[k] < bd[k] || (dd[k] == bd[k] && qi < bi[k]))) {
                     bd[k] = dd[k]; bi[k] = qi; bp[k] = pos;
                 }
             }
@@ -1383,6 +1431,7 @@ __global__ __launch_bounds__(kBlock) void k_border(Plan P)
         const uint32_t p0 = P.group_start[g], p1 = P.group_start[g + 1];
         const uint64_t gkey = P.group_key[g];
         if (P.m == 1 && P.ncore[g] == p1 - p0) continue;     // a cube of core points only
+        const Geo<D> geo = cube_geo<D>(P, gkey);
         for (uint32_t pc = p0; pc < p1; pc += kPch) {
             Pt<D> pp[kPch];
             uint32_t todo = 0;
@@ -1397,7 +1446,7 @@ __global__ __launch_bounds__(kBlock) void k_border(Plan P)
             uint32_t bi[kPch], bp[kPch];
 #pragma unroll
             for (int k = 0; k < kPch; k++) { bd[k] = INT64_MAX; bi[k] = kNone; bp[k] = kNone; }
-            border_walk<D, WIDE>(P, g, gkey, pp, todo, bd, bi, bp, s_beg[w], s_pre[w], lt);
+            border_walk<D, WIDE>(P, g, gkey, pp, todo, bd, bi, bp, s_beg[w], s_pre[w], lt, geo);
             border_finish(P, pc, todo, bd, bi, bp);
         }
     }
@@ -1412,6 +1461,7 @@ __global__ __launch_bounds__(kBlock) void k_border_chunks(Plan P)
     __shared__ uint32_t s_beg[kWavesPerBlock][kWave], s_pre[kWavesPerBlock][kWave];
     const uint32_t w = wave_in_block(), l = lane_id();
     const uint32_t n = P.n;
+    const Geo<D> geo = call_geo<D>(P);
     uint32_t lt = 0;
     const WaveRange hca_wr_ = wave_range();
     HCA_FOR_UNITS(u, (n + kPch - 1) / kPch) {
@@ -1431,7 +1481,7 @@ __global__ __launch_bounds__(kBlock) void k_border_chunks(Plan P)
             const uint32_t g = __shfl(grp, __ffs(left) - 1);
             const uint32_t run = (uint32_t)__ballot(grp == g) & left;
             left &= ~run;
-            border_walk<D, WIDE>(P, g, P.group_key[g], pp, run, bd, bi, bp, s_beg[w], s_pre[w], lt);
+            border_walk<D, WIDE>(P, g, P.group_key[g], pp, run, bd, bi, bp, s_beg[w], s_pre[w], lt, geo);
         }
         border_finish(P, pc, todo, bd, bi, bp);
     }
@@ -1490,6 +1540,21 @@ __global__ __launch_bounds__(kBlock) void k_label_scan(Plan P, uint64_t *status,
     if (t == 0 && base + kScanTile >= nw) P.ctr->n_clusters = run;
 }
 
+// Batch: clusters of the data sets before each one = marks before its first
+// staged row.
+__global__ __launch_bounds__(kBlock) void k_seg_label_base(Plan P)
+{
+    for (uint32_t sg = blockIdx.x * kBlock + threadIdx.x; sg < P.nseg; sg += gridDim.x * kBlock) {
+        const uint32_t r = P.seg[sg].vstart;
+        uint32_t base = 0;
+        if (r < P.n) {
+            const uint32_t wd = r >> 5;
+            base = P.wrank[wd] + __popc(ld_agent32(P.first + wd) & ((1u << (r & 31u)) - 1u));
+        }
+        P.seg[sg].label_base = base;
+    }
+}
+
 // Label of every cube's cluster (-1 for a cube without core points).
 __global__ __launch_bounds__(kBlock) void k_label_cubes(Plan P)
 {
@@ -1502,6 +1567,8 @@ __global__ __launch_bounds__(kBlock) void k_label_cubes(Plan P)
             const uint32_t wd = m >> 5;
             label = (int32_t)(P.wrank[wd] +
                               __popc(ld_agent32(P.first + wd) & ((1u << (m & 31u)) - 1u)));
+            // batch: clusters are numbered from 0 within each data set
+            if (P.nseg) label -= (int32_t)P.seg[(uint32_t)(P.group_key[c] >> P.seg_shift)].label_base;
         }
         P.label_of[c] = label;
     }
@@ -1651,6 +1718,8 @@ void launch_labels(const Plan &P, uint64_t *status, uint32_t *ticket, hipStream_
     const uint32_t nw = (P.n + 31u) >> 5;
     const uint32_t tiles = (nw + kScanTile - 1) / kScanTile;
     hipLaunchKernelGGL(k_label_scan, dim3(tiles), dim3(kBlock), 0, s, P, status, ticket);
+    if (P.nseg)
+        hipLaunchKernelGGL(k_seg_label_base, dim3((P.nseg + kBlock - 1) / kBlock), dim3(kBlock), 0, s, P);
     hipLaunchKernelGGL(k_label_cubes, dim3(cb), dim3(kBlock), 0, s, P);
     const int blocks = (int)std::min<uint64_t>((P.n + kBlock - 1) / kBlock, 4096);
     hipLaunchKernelGGL(k_label_write, dim3(blocks), dim3(kBlock), 0, s, P);

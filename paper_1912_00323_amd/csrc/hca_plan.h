@@ -57,6 +57,20 @@ struct Counters {
 
 enum { kTestsCore = 0, kTestsMerge = 1, kTestsBorder = 2, kTestsIntra = 3 };
 
+// One data set of a batch: its exact eps^2, minPts, cube side and origin,
+// where its rows sit, and (filled on the device) the clusters of the data
+// sets before it.
+struct SegParam {
+    int64_t eps2;
+    int64_t side;
+    uint64_t src_elem;          // first coordinate in the caller's point array
+    int32_t origin[kMaxDim];
+    uint32_t min_pts;
+    uint32_t vstart;            // first row in the staged (contiguous) order
+    uint32_t dst_row;           // first row in the caller's label array
+    uint32_t label_base;        // clusters of the earlier data sets of the batch
+};
+
 struct Plan {
     // problem
     uint32_t n;
@@ -119,6 +133,13 @@ struct Plan {
     uint32_t *nbr_start;        // [n]
     uint32_t *nbr;              // [nbr_cap]
     uint32_t *group_of;         // [n] cube -> its group
+    // batches (nseg > 0): the data set of a cube is key >> seg_shift; its
+    // parameters replace eps2, min_pts, side and origin (search groups of one
+    // cube only)
+    uint32_t nseg;
+    uint32_t seg_shift;
+    SegParam *seg;              // [nseg]
+    const uint32_t *seg_of;     // [n] staged row -> data set
     uint64_t *tile_status;      // look-back words of the tile scan
     uint32_t *work;             // [2 * work_cap] cube pairs for exact tests
     uint32_t work_cap;          // multiple of kWorkRegions

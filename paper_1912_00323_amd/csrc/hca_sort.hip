@@ -57,9 +57,21 @@ __global__ __launch_bounds__(kBlock) void k_bbox(const int32_t *__restrict__ pts
 // Cube keys and the digit histograms of every radix pass, in one read.
 // ---------------------------------------------------------------------------
 template <int D, typename K>
-__device__ __forceinline__ K cube_key(const Plan &P, const Pt<D> &p)
+__device__ __forceinline__ K cube_key(const Plan &P, const Pt<D> &p, uint32_t i)
 {
     uint64_t key = 0;
+    if (P.nseg) {
+        // batch: the data set's own origin and side, its index above the cube
+        const uint32_t sg = P.seg_of[i];
+        const SegParam &sp = P.seg[sg];
+        const uint32_t side = (uint32_t)sp.side;
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+            const uint32_t u = (uint32_t)(p.x[k] - sp.origin[k]);    // < 2^30 (host checked)
+            key |= (uint64_t)(u / side) << P.goff[k];
+        }
+        return (K)(key | (uint64_t)sg << P.seg_shift);
+    }
 #pragma unroll
     for (int k = 0; k < D; k++) {
         const uint32_t u = (uint32_t)(p.x[k] - P.origin[k]);     // < 2^30 (host checked)
@@ -82,7 +94,7 @@ __global__ __launch_bounds__(kBlock) void k_keys_hist(Plan P, K *__restrict__ ke
     for (uint32_t e = threadIdx.x; e < passes * kRadix; e += kBlock) s_hist[e] = 0;
     __syncthreads();
     for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < P.n; i += gridDim.x * kBlock) {
-        const K key = cube_key<D, K>(P, load_pt<D>(P.pts, i));
+        const K key = cube_key<D, K>(P, load_pt<D>(P.pts, i), i);
         keys[i] = key;
         vals[i] = i;
         for (uint32_t q = 0; q < passes; q++)

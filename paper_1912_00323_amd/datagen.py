@@ -115,6 +115,30 @@ def make_mixed(seed: int, n: int, d: int, q: int = 14) -> Workload:
                     {"eps_real": eps, "seed": seed, "blobs": n_blobs, "noise": noise})
 
 
+def make_batch(seed: int = 4, count: int = 256, n_range=(1_000, 200_000), dims=(2, 3, 4),
+               q: int = 14) -> list:
+    """The batched workload: ``count`` independent jobs, job k drawn from the
+    k-th child of ``SeedSequence(seed)``.  Each job has n log-uniform in
+    ``n_range``, d uniform in ``dims``, 3-30 blobs with per-blob std uniform in
+    [0.005, 0.03] (multinomial sizes, equal shares), 5-15 % noise, eps uniform
+    in [0.005, 0.03] and minPts uniform in 4..12; coordinates are 2^-q fixed
+    point."""
+    jobs = []
+    for k, child in enumerate(np.random.SeedSequence(seed).spawn(count)):
+        rng = np.random.Generator(np.random.PCG64(child))
+        n = int(round(float(np.exp(rng.uniform(np.log(n_range[0]), np.log(n_range[1]))))))
+        d = int(rng.choice(np.asarray(dims)))
+        n_blobs = int(rng.integers(3, 31))
+        stds = rng.uniform(0.005, 0.03, size=n_blobs)
+        noise = float(rng.uniform(0.05, 0.15))
+        eps = float(rng.uniform(0.005, 0.03))
+        min_pts = int(rng.integers(4, 13))
+        x = make_blobs(rng, n, d, n_blobs, stds, noise, "equal")
+        jobs.append(Workload(f"batch{seed}_{k}_{d}d_{n}", quantise(x, q), eps * 2 ** q, min_pts, q,
+                             {"eps_real": eps, "seed": seed, "job": k, "blobs": n_blobs, "noise": noise}))
+    return jobs
+
+
 CONFIG_NAMES = {1: "blobs2d_10k", 2: "blobs2d_1m", 3: "blobs8d_500k"}
 
 

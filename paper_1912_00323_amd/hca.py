@@ -81,6 +81,8 @@ def load_library(path: str | Path | None = None) -> ctypes.CDLL:
     lib.hca_cluster_ex.restype = ctypes.c_int
     lib.hca_cluster_host.argtypes = [vp, vp, i64, i32, dbl, i32, vp]
     lib.hca_cluster_host.restype = ctypes.c_int
+    lib.hca_cluster_batch.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp]
+    lib.hca_cluster_batch.restype = ctypes.c_int
     lib.hca_set_profiling.argtypes = [vp, i32]
     lib.hca_set_profiling.restype = ctypes.c_int
     lib.hca_phase_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32]
@@ -175,6 +177,32 @@ class Context:
         if stats:
             res.append(st_obj.as_dict())
         return res[0] if len(res) == 1 else tuple(res)
+
+    def cluster_batch(self, points, rows, dims, eps, min_pts, out=None):
+        """Cluster the data sets packed one after the other in the CUDA int32
+        tensor ``points`` (flat, data set i being rows[i] x dims[i]).  Returns
+        an int32 tensor with every data set's own labels at its rows."""
+        import torch
+        if not (isinstance(points, torch.Tensor) and points.is_cuda and points.dtype == torch.int32):
+            raise TypeError("points must be a CUDA (HIP) int32 torch tensor")
+        pts = points.contiguous()
+        nseg = len(rows)
+        r = np.ascontiguousarray(rows, dtype=np.int64)
+        dm = np.ascontiguousarray(dims, dtype=np.int32)
+        ep = np.ascontiguousarray(eps, dtype=np.float64)
+        mp = np.ascontiguousarray(min_pts, dtype=np.int32)
+        if not (len(dm) == len(ep) == len(mp) == nseg):
+            raise ValueError("rows, dims, eps and min_pts must have one entry per data set")
+        if int((r * dm).sum()) != pts.numel():
+            raise ValueError("points does not hold sum(rows * dims) coordinates")
+        total = int(r.sum())
+        labels = out if out is not None else torch.empty(total, dtype=torch.int32, device=pts.device)
+        self.set_stream(torch.cuda.current_stream(pts.device).cuda_stream)
+        self._check(self._lib.hca_cluster_batch(
+            self._ctx, ctypes.c_void_p(pts.data_ptr()), nseg, r.ctypes.data_as(ctypes.c_void_p),
+            dm.ctypes.data_as(ctypes.c_void_p), ep.ctypes.data_as(ctypes.c_void_p),
+            mp.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(labels.data_ptr())))
+        return labels
 
     def cluster_ptr(self, points_ptr: int, n: int, d: int, eps: float, min_pts: int,
                     labels_ptr: int):

@@ -1,9 +1,10 @@
-"""Write tests/golden/full_size_expected.json: the oracle's labels for the fixed
-workloads, stored as SHA-256 digests of the little-endian int32 label arrays
-plus summary counts.  Calls only the CPU oracle (definition part) and the
-seeded input generator.
+"""Write tests/golden/full_size_expected.json (the fixed workloads) and
+tests/golden/batch_expected.json (the 256 jobs of the batched workload): the
+oracle's labels, stored as SHA-256 digests of the little-endian int32 label
+arrays plus summary counts.  Calls only the CPU oracle (definition part) and
+the seeded input generator.
 
-    python tests/golden/make_expected.py [--threads N]
+    python tests/golden/make_expected.py [--threads N] [--only fixed|batch]
 """
 from __future__ import annotations
 
@@ -20,9 +21,10 @@ ROOT = Path(__file__).resolve().parents[2]
 sys.path.insert(0, str(ROOT))
 
 import oracle  # noqa: E402
-from paper_1912_00323_amd.datagen import make_config  # noqa: E402
+from paper_1912_00323_amd.datagen import make_batch, make_config  # noqa: E402
 
 OUT = Path(__file__).resolve().parent / "full_size_expected.json"
+OUT_BATCH = Path(__file__).resolve().parent / "batch_expected.json"
 
 
 def digest(a: np.ndarray) -> str:
@@ -32,7 +34,12 @@ def digest(a: np.ndarray) -> str:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--only", choices=["fixed", "batch"], default=None)
     args = ap.parse_args()
+    if args.only != "fixed":
+        batch(args.threads)
+    if args.only == "batch":
+        return
     out = {"note": "labels of the CPU oracle (DBSCAN definition) on the seeded workloads; "
                    "points_sha256 guards against generator drift",
            "workloads": {}}
@@ -56,6 +63,24 @@ def main():
         }
         print(w.name, out["workloads"][w.name], flush=True)
     OUT.write_text(json.dumps(out, indent=1) + "\n")
+
+
+def batch(threads: int):
+    jobs = make_batch(seed=4, count=256)
+    out = {"note": "labels of the CPU oracle (DBSCAN definition) on each job of the batched workload "
+                   "(make_batch(seed=4, count=256)); points_sha256 guards against generator drift",
+           "seed": 4, "count": len(jobs), "jobs": []}
+    t_all = time.time()
+    for w in jobs:
+        labels = oracle.dbscan(w.points, w.eps, w.min_pts, threads=threads)
+        out["jobs"].append({"name": w.name, "n": w.n, "d": w.d, "eps": w.eps, "min_pts": w.min_pts,
+                            "points_sha256": digest(w.points.reshape(-1)),
+                            "labels_sha256": digest(labels),
+                            "n_clusters": int(labels.max() + 1) if len(labels) else 0,
+                            "n_noise": int((labels < 0).sum())})
+    print(f"batch: {len(jobs)} jobs, {sum(j['n'] for j in out['jobs'])} points, "
+          f"{time.time() - t_all:.1f} s", flush=True)
+    OUT_BATCH.write_text(json.dumps(out, indent=1) + "\n")
 
 
 if __name__ == "__main__":
