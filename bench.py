@@ -26,7 +26,7 @@ METRIC = "points clustered/s (2-D 1M, 8-D 500k) vs HBM roofline; served p50/p99 
 HBM_PEAK_GBS = 8000.0
 # int32 VALU lane-ops: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 /s
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-WORKLOADS = {"2d": 2, "8d": 3, "small": 1}
+WORKLOADS = {"2d": 2, "8d": 3, "small": 1, "batch": 4}
 HBM_PHASES = ("bbox", "sort", "cells", "labels")
 ALU_PHASES = {"core": "tests_core", "intra": "tests_intra", "merge": "tests_merge",
               "border": "tests_border"}
@@ -126,6 +126,9 @@ def main() -> int:
               f"this path is a design, not a measured mode", file=sys.stderr)
         return 2
 
+    if args.workload == "batch":
+        return bench_batch(args)
+
     import torch
     from paper_1912_00323_amd import hca
     from paper_1912_00323_amd.datagen import make_config
@@ -221,6 +224,96 @@ def main() -> int:
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(line), flush=True)
+    ctx.close()
+    return 0
+
+
+def bench_batch(args) -> int:
+    """The batched workload: 256 independent data sets (n log-uniform in
+    [1e3, 2e5], d in {2, 3, 4}, per-set eps and minPts) clustered by one
+    hca_cluster_batch call per step; the plain path (one hca_cluster call per
+    data set) is timed on the same data beside it."""
+    import torch
+    import numpy as np
+    from paper_1912_00323_amd import hca
+    from paper_1912_00323_amd.datagen import make_batch
+
+    jobs = make_batch(seed=4, count=256)
+    total = sum(j.n for j in jobs)
+    dev = torch.device("cuda:0")
+    flat = torch.from_numpy(np.concatenate([j.points.reshape(-1) for j in jobs])).to(dev)
+    rows = [j.n for j in jobs]
+    dims = [j.d for j in jobs]
+    eps = [j.eps for j in jobs]
+    mps = [j.min_pts for j in jobs]
+    labels = torch.empty(total, dtype=torch.int32, device=dev)
+    ctx = hca.Context(0)
+    ctx.set_stream(torch.cuda.current_stream(dev).cuda_stream)
+    for _ in range(args.warmup):
+        ctx.cluster_batch(flat, rows, dims, eps, mps, out=labels)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.cluster_batch(flat, rows, dims, eps, mps, out=labels)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+
+    # the plain path on the same data: one call per data set, inputs resident
+    singles = [torch.from_numpy(j.points).to(dev) for j in jobs]
+    outs = [torch.empty(j.n, dtype=torch.int32, device=dev) for j in jobs]
+    for x, o, j in zip(singles, outs, jobs):
+        ctx.cluster(x, j.eps, j.min_pts, out=o)
+    reps = max(1, min(3, args.steps))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        for x, o, j in zip(singles, outs, jobs):
+            ctx.cluster(x, j.eps, j.min_pts, out=o)
+    torch.cuda.synchronize()
+    dt_plain = (time.perf_counter() - t1) / reps
+    same = bool(torch.equal(torch.cat(outs), labels))
+
+    # binning and sort bytes of every data set against the whole call
+    ab = sum(algorithmic_bytes("sort", j.n, j.d, 8, 5, 0) + algorithmic_bytes("bbox", j.n, j.d, 8, 5, 0)
+             for j in jobs)
+    ms = dt * 1e3 / args.steps
+    achieved = ab / (ms * 1e-3) / 1e9
+    line = {
+        "metric": METRIC,
+        "value": total * args.steps / dt,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i32",
+        "data": "synthetic",
+        "config": {"workload": "batch256_mixed", "jobs": len(jobs), "points": total,
+                   "d": sorted(set(dims)), "parallelism": "single-gpu"},
+        "plain_path": {"value": total / dt_plain, "unit": "points/s", "ms_per_batch": round(dt_plain * 1e3, 3),
+                       "calls": len(jobs), "labels_identical": same},
+        "speedup_vs_plain": round((total * args.steps / dt) / (total / dt_plain), 3),
+        "roofline": {"bound": "hbm", "phase": "whole batch call (binning and sort bytes only)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "algorithmic_bytes": ab},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+        done, pts_done, t_start = 0, 0, time.perf_counter()
+        while done < len(jobs) and time.perf_counter() - t_start < 20.0:
+            j = jobs[done]
+            oracle.hca_grid(j.points, j.eps, j.min_pts, threads=threads)
+            done += 1
+            pts_done += j.n
+        tcpu = time.perf_counter() - t_start
+        line["cpu_baseline"] = {"value": pts_done / tcpu, "unit": "points/s", "cores": threads, "kind": "oracle",
+                                "sample": f"the first {done} of the {len(jobs)} data sets ({pts_done} points), "
+                                          f"one oracle.hca_grid call each"}
     print(json.dumps(line), flush=True)
     ctx.close()
     return 0

@@ -166,8 +166,10 @@ hca_status hca_cluster_host(hca_ctx *ctx, const int32_t *points, int64_t n, int3
  * Blocking like hca_cluster.  HCA_E_INVAL for bad arguments, d > 4, more than
  * 2^31-1 rows in all or more than 8192 data sets of one dimension;
  * HCA_E_RANGE when a data set spans 2^30 or more along an axis or the packed
- * keys of one dimension need more than 63 bits.  Phase profiling does not
- * apply to batches. */
+ * keys of one dimension need more than 63 bits.  With phase profiling on,
+ * the groups of one dimension are timed one after the other (a stream sync
+ * between them) and hca_phase_times gives each phase summed over the groups;
+ * the bounding-box phase is not timed. */
 hca_status hca_cluster_batch(hca_ctx *ctx, const int32_t *points, int32_t nseg, const int64_t *rows,
                              const int32_t *dims, const double *eps, const int32_t *min_pts,
                              int32_t *labels);

@@ -338,6 +338,17 @@ struct Carver {
     }
 };
 
+// Neighbour lists in cube mode pay when the stencil is large (d >= 3): they
+// are built once and walked by core marking, merging and border assignment.
+// Returns 2R + 1 when they are used, else 0.
+uint32_t cube_list_width(int d, int32_t radius, uint32_t n_off)
+{
+    const uint32_t w = 2u * (uint32_t)radius + 1u;
+    uint64_t half = 1;
+    for (int k = 0; k < (d + 1) / 2; k++) half *= w;
+    return d >= 3 && n_off > 64 && half <= 128 ? w : 0u;
+}
+
 // Sizes of one launch sequence, fixed before the workspace is carved.
 struct Sizes {
     bool wide_keys = false;
@@ -376,7 +387,8 @@ void plan_sizes(Plan &P, uint32_t gbits, bool count_work, bool want_stats, Sizes
     uint64_t list_cap = std::min<uint64_t>(std::max<uint64_t>(64ull * n, 4096ull * waves), 1ull << 29);
     if (const char *e = std::getenv("HCA_LIST_SLAB"))
         list_cap = std::min<uint64_t>((uint64_t)std::max(0, std::atoi(e)) * waves, 1ull << 29);
-    P.nbr_cap = P.m > 1 ? (uint32_t)list_cap : 0;
+    if (P.m > 1) P.list_w = 3;
+    P.nbr_cap = P.list_w ? (uint32_t)list_cap : 0;
 }
 
 // The device workspace of one launch sequence (the first bytes hold the
@@ -629,6 +641,7 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
         P.dir_fwd = (const uint16_t *)(gd + align256(G.off.size()));
         P.dir_bwd = (const uint16_t *)(gd + align256(G.off.size()) + align256((size_t)n_off * 2));
     }
+    P.list_w = P.m == 1 ? cube_list_width(d, G.radius, n_off) : 0;
     Sizes Z;
     plan_sizes(P, gbits, stats != nullptr && ctx->prof != -1, stats != nullptr, &Z);
     P.pts = points;
@@ -904,6 +917,9 @@ hca_status run_batch(hca_ctx *ctx, const int32_t *points, int32_t nseg, const in
         P.pts = (const int32_t *)(db + g.d_pts);
         P.labels = (int32_t *)(db + g.d_lab);
         P.core_out = nullptr;
+        int32_t rmax = 0;
+        for (int32_t v : g.radius) rmax = std::max(rmax, v);
+        P.list_w = cube_list_width(d, rmax, P.n_off);
         plan_sizes(P, P.key_bits, false, false, &g.Z);
         ws_need = std::max(ws_need, ws_bytes(P, g.Z));
         // origins into the device table (stream-ordered before the launches)
@@ -914,16 +930,26 @@ hca_status run_batch(hca_ctx *ctx, const int32_t *points, int32_t nseg, const in
     st = ensure(ctx, &ctx->ws, &ctx->ws_size, ws_need, "workspace");
     if (st) return st;
 
-    // 5. one launch sequence per dimension, labels back to the caller
-    const int32_t prof = ctx->prof;
-    ctx->prof = -1;
+    // 5. one launch sequence per dimension, labels back to the caller; with
+    //    phase profiling on, each group is timed on its own and the phase
+    //    times are summed over the groups
+    float acc[HCA_PHASES] = {};
     for (BatchGroup &g : groups) {
+        for (bool &u : ctx->ev_used) u = false;
         launch_sequence(ctx, g.P, g.Z);
         launch_seg_scatter(g.P.seg, g.P.seg_of, g.P.labels, labels, g.n, s);
+        if (ctx->prof != -1) {
+            HCA_HIP(hipStreamSynchronize(s), "batch sync");
+            for (int ph = 0; ph < HCA_PHASES; ph++) {
+                float ms = 0.f;
+                if (ctx->ev_used[ph]) (void)hipEventElapsedTime(&ms, ctx->ev[2 * ph], ctx->ev[2 * ph + 1]);
+                acc[ph] += ms;
+            }
+        }
     }
-    ctx->prof = prof;
     HCA_HIP(hipGetLastError(), "kernel launch");
     HCA_HIP(hipStreamSynchronize(s), "batch sync");
+    for (int ph = 0; ph < HCA_PHASES; ph++) ctx->phase_ms[ph] = acc[ph];
     return HCA_OK;
 }
 

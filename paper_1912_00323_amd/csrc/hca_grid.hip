@@ -284,47 +284,50 @@ __device__ __forceinline__ QBox<D> group_points_box(const Plan &P, uint32_t p0, 
     return b;
 }
 
-constexpr int pow3(int k) { return k == 0 ? 1 : 3 * pow3(k - 1); }
-
 // Squared gap along axis e between the query box [lo, hi] and the group at
-// coordinate c + o (o in {-1, 0, 1}), or -1 when that group lies outside the
-// grid.
-__device__ __forceinline__ int64_t axis_gap2(const Plan &P, uint64_t gkey, int e, int o, int32_t lo, int32_t hi)
+// coordinate c + o, or -1 when that group lies outside the grid.
+template <int D>
+__device__ __forceinline__ int64_t axis_gap2(const Plan &P, uint64_t gkey, int e, int o, int32_t lo, int32_t hi,
+                                             const Geo<D> &geo)
 {
     const int64_t c = (int64_t)((gkey >> P.goff[e]) & ((1ull << P.gw[e]) - 1ull)) + o;
     if (c < 0 || c > (int64_t)P.gmax[e]) return -1;
-    const int64_t glo = (int64_t)P.origin[e] + c * P.gside, ghi = glo + P.gside - 1;
+    const int64_t glo = (int64_t)geo.origin[e] + c * geo.gside, ghi = glo + geo.gside - 1;
     const int64_t gap = glo > hi ? glo - hi : (lo > ghi ? lo - ghi : 0);
     return gap * gap;
 }
 
 // Half of the axes (first, first + K): the sum of squared gaps of the offset
-// combination `idx` (base-3 digits, axis `first` lowest), or INT64_MAX when
-// it leaves the grid or already exceeds eps.
+// combination `idx` (base-W digits for offsets -R..R, W = 2R + 1, axis
+// `first` lowest), or INT64_MAX when it leaves the grid or exceeds eps.
 template <int D, int K>
 __device__ __forceinline__ int64_t half_gap2(const Plan &P, uint64_t gkey, int first, uint32_t idx,
-                                             const QBox<D> &q)
+                                             const QBox<D> &q, const Geo<D> &geo)
 {
+    const uint32_t W = P.list_w;
+    const int R = (int)(W >> 1);
     int64_t acc = 0;
 #pragma unroll
     for (int e = 0; e < K; e++) {
-        const int o = (int)(idx % 3u) - 1;
-        idx /= 3u;
-        const int64_t g2 = axis_gap2(P, gkey, first + e, o, q.lo[first + e], q.hi[first + e]);
+        const int o = (int)(idx % W) - R;
+        idx /= W;
+        const int64_t g2 = axis_gap2<D>(P, gkey, first + e, o, q.lo[first + e], q.hi[first + e], geo);
         if (g2 < 0) return INT64_MAX;
         acc += g2;
     }
-    return acc <= P.eps2 ? acc : INT64_MAX;
+    return acc <= geo.eps2 ? acc : INT64_MAX;
 }
 
 template <int K>
 __device__ __forceinline__ int64_t half_key_delta(const Plan &P, int first, uint32_t idx)
 {
+    const uint32_t W = P.list_w;
+    const int R = (int)(W >> 1);
     int64_t kd = 0;
 #pragma unroll
     for (int e = 0; e < K; e++) {
-        const int o = (int)(idx % 3u) - 1;
-        idx /= 3u;
+        const int o = (int)(idx % W) - R;
+        idx /= W;
         kd += (int64_t)o * (int64_t)(1ull << P.goff[first + e]);
     }
     return kd;
@@ -347,8 +350,9 @@ __device__ __forceinline__ void rank_sort(const int64_t *s_in, int n, int64_t *s
     }
 }
 
-// Neighbour-group lists (group mode), one wave per group.  The offsets in
-// {-1, 0, 1}^d split into two halves of the axes; the squared gaps between
+// Neighbour lists, one wave per group (a cube when m = 1).  The offsets in
+// [-R, R]^d (R = 1 for groups of m > 1 cubes, the stencil radius for cubes)
+// split into two halves of the axes; the squared gaps between
 // the group's point box and the neighbour boxes add over axes, so the
 // offsets that can hold a point within eps are the pairs (i, j) of the two
 // halves with sum_a[i] + sum_b[j] <= eps^2.  Both halves are sorted, so for
@@ -357,15 +361,20 @@ __device__ __forceinline__ void rank_sort(const int64_t *s_in, int n, int64_t *s
 // searched over the stencil instead.
 constexpr int kListBatch = 4;        // lookups in flight per lane
 
+constexpr int kListHalf = 128;       // offset combinations per half of the axes, at most
+
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_nbr_lists(Plan P)
 {
-    constexpr int DA = D / 2, DB = D - DA, NA = pow3(DA), NB = pow3(DB);
-    __shared__ int64_t s_in[kWavesPerBlock][NA > NB ? NA : NB];
-    __shared__ int64_t s_sa[kWavesPerBlock][NA], s_sb[kWavesPerBlock][NB];
-    __shared__ uint8_t s_ia[kWavesPerBlock][NA], s_ib[kWavesPerBlock][NB];
-    __shared__ int64_t s_ka[kWavesPerBlock][NA], s_kb[kWavesPerBlock][NB];
-    __shared__ uint32_t s_pre[kWavesPerBlock][NA + 1];
+    constexpr int DA = D / 2, DB = D - DA;
+    __shared__ int64_t s_sa[kWavesPerBlock][kListHalf], s_sb[kWavesPerBlock][kListHalf];
+    __shared__ uint8_t s_ia[kWavesPerBlock][kListHalf], s_ib[kWavesPerBlock][kListHalf];
+    __shared__ int64_t s_ka[kWavesPerBlock][kListHalf], s_kb[kWavesPerBlock][kListHalf];
+    __shared__ uint32_t s_pre[kWavesPerBlock][kListHalf + 1];
+    int64_t(*s_in)[kListHalf] = s_ka;     // unsorted sums, before the key offsets
+    int NA = 1, NB = 1;
+    for (int e = 0; e < DA; e++) NA *= (int)P.list_w;
+    for (int e = 0; e < DB; e++) NB *= (int)P.list_w;
     const uint32_t w = wave_in_block(), l = lane_id();
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
     const uint32_t waves = gridDim.x * kWavesPerBlock;
@@ -376,13 +385,14 @@ __global__ __launch_bounds__(kBlock) void k_nbr_lists(Plan P)
     const WaveRange hca_wr_ = wave_range();
     HCA_FOR_UNITS(g, ng) {
         const uint64_t gkey = P.group_key[g];
+        const Geo<D> geo = cube_geo<D>(P, gkey);
         const QBox<D> qb = group_points_box<D>(P, P.group_start[g], P.group_start[g + 1]);
         // both halves' gap sums, sorted ascending
-        for (int i = l; i < NA; i += kWave) s_in[w][i] = half_gap2<D, DA>(P, gkey, 0, i, qb);
+        for (int i = l; i < NA; i += kWave) s_in[w][i] = half_gap2<D, DA>(P, gkey, 0, i, qb, geo);
         __builtin_amdgcn_wave_barrier();
         rank_sort(s_in[w], NA, s_sa[w], s_ia[w]);
         __builtin_amdgcn_wave_barrier();
-        for (int j = l; j < NB; j += kWave) s_in[w][j] = half_gap2<D, DB>(P, gkey, DA, j, qb);
+        for (int j = l; j < NB; j += kWave) s_in[w][j] = half_gap2<D, DB>(P, gkey, DA, j, qb, geo);
         __builtin_amdgcn_wave_barrier();
         rank_sort(s_in[w], NB, s_sb[w], s_ib[w]);
         __builtin_amdgcn_wave_barrier();
@@ -392,7 +402,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr_lists(Plan P)
             const int i = i0 + (int)l;
             uint32_t c = 0;
             if (i < NA && s_sa[w][i] != INT64_MAX) {
-                const int64_t lim = P.eps2 - s_sa[w][i];
+                const int64_t lim = geo.eps2 - s_sa[w][i];
                 int lo = 0, hi = NB;                      // first j with s_sb > lim
                 while (lo < hi) {
                     const int mid = (lo + hi) >> 1;
@@ -667,6 +677,14 @@ __global__ __launch_bounds__(kBlock) void k_core_chunks(Plan P)
 // folds it into the cube's representative with a 64-bit atomic minimum of
 // (score, position).
 // ---------------------------------------------------------------------------
+// Every representative slot to "none" (all ones) before the atomic minima.
+__global__ __launch_bounds__(kBlock) void k_reps_init(Plan P)
+{
+    const uint64_t total = (uint64_t)ld_agent32(&P.ctr->n_cells) * P.n_dir;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (uint64_t)gridDim.x * kBlock)
+        st_agent(P.rep + i, ~0ull);
+}
+
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_reps(Plan P)
 {
@@ -733,6 +751,27 @@ __global__ __launch_bounds__(kBlock) void k_reps(Plan P)
 template <int D, bool WIDE>
 __device__ void exact_pair(const Plan &P, uint32_t A, uint32_t B, uint32_t &lt);
 
+// Representative directions of the pair (A, B) from their keys: the signs of
+// B's coordinates minus A's (A's side) and their opposites (B's side), as
+// base-3 digits, axis 0 lowest, without the all-zero direction.
+template <int D>
+__device__ __forceinline__ void rep_directions(const Plan &P, uint64_t ka, uint64_t kb, uint32_t *fw, uint32_t *bw)
+{
+    uint32_t vf = 0, vb = 0, zero = 0, mul = 1;
+#pragma unroll
+    for (int k = 0; k < D; k++) {
+        const uint64_t mask = (1ull << P.gw[k]) - 1ull;
+        const int64_t ca = (int64_t)((ka >> P.goff[k]) & mask), cb = (int64_t)((kb >> P.goff[k]) & mask);
+        const int sg = cb > ca ? 1 : (cb < ca ? -1 : 0);
+        vf += (uint32_t)(sg + 1) * mul;
+        vb += (uint32_t)(1 - sg) * mul;
+        zero += mul;
+        mul *= 3;
+    }
+    *fw = vf > zero ? vf - 1 : vf;
+    *bw = vb > zero ? vb - 1 : vb;
+}
+
 template <int D, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_merge_rep(Plan P)
 {
@@ -744,19 +783,26 @@ __global__ __launch_bounds__(kBlock) void k_merge_rep(Plan P)
         if (P.ncore[A] == 0) continue;
         const uint64_t gkey = P.group_key[A];
         const int64_t eps2 = cube_geo<D>(P, gkey).eps2;
-        for (uint32_t oc = 1; oc < P.n_off; oc += kWave) {
+        const NbrSrc src = nbr_source(P, A);
+        for (uint32_t oc = 1; oc < src.slots; oc += kWave) {
             const uint32_t j = oc + l;
-            uint32_t B = kNone;
-            if (j < P.n_off) {
-                const uint64_t nk = group_neighbour<D>(P, gkey, P.off + (uint64_t)j * D);
-                if (nk != ~0ull) B = group_lookup(P, nk);
+            uint32_t B = kNone, dfw = 0, dbw = 0;
+            if (j < src.slots) {
+                if (src.lists) {
+                    B = P.nbr[src.start + j - 1];
+                    if (B > A && P.n_dir) rep_directions<D>(P, gkey, P.group_key[B], &dfw, &dbw);
+                } else {
+                    const uint64_t nk = group_neighbour<D>(P, gkey, P.off + (uint64_t)j * D);
+                    if (nk != ~0ull) B = group_lookup(P, nk);
+                    if (P.n_dir) { dfw = P.dir_fwd[j]; dbw = P.dir_bwd[j]; }
+                }
             }
             bool todo = B != kNone && B > A && P.ncore[B] > 0;
             if (todo) todo = uf_find(P.parent, A) != uf_find(P.parent, B);
             bool joined = false;
             if (todo && P.n_dir) {
-                const uint32_t qa = (uint32_t)ld_agent(P.rep + (uint64_t)A * P.n_dir + P.dir_fwd[j]);
-                const uint32_t qb = (uint32_t)ld_agent(P.rep + (uint64_t)B * P.n_dir + P.dir_bwd[j]);
+                const uint32_t qa = (uint32_t)ld_agent(P.rep + (uint64_t)A * P.n_dir + dfw);
+                const uint32_t qb = (uint32_t)ld_agent(P.rep + (uint64_t)B * P.n_dir + dbw);
                 lt++;
                 joined = within<D, WIDE>(load_pt<D>(P.spts, qa), load_pt<D>(P.spts, qb), eps2);
                 if (joined) uf_union(P.parent, A, B);
@@ -1670,6 +1716,8 @@ void launch_core(const Plan &P, int blocks, hipStream_t s)
 
 void launch_reps(const Plan &P, int blocks, hipStream_t s)
 {
+    const int ib = (int)std::min<uint64_t>(((uint64_t)P.n * P.n_dir + kBlock - 1) / kBlock, 2048);
+    hipLaunchKernelGGL(k_reps_init, dim3(std::max(1, ib)), dim3(kBlock), 0, s, P);
     switch (P.d) {
     case 1: hipLaunchKernelGGL(k_reps<1>, dim3(blocks), dim3(kBlock), 0, s, P); break;
     case 2: hipLaunchKernelGGL(k_reps<2>, dim3(blocks), dim3(kBlock), 0, s, P); break;

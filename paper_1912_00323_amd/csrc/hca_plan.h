@@ -129,6 +129,7 @@ struct Plan {
     // wave fills its own slab of nbr_cap / waves entries; a group whose list
     // does not fit gets nbr_count = kNone and is searched over the stencil.
     uint32_t nbr_cap;
+    uint32_t list_w;            // offsets per axis walked by the list build: 2R + 1
     uint32_t *nbr_count;        // [n]
     uint32_t *nbr_start;        // [n]
     uint32_t *nbr;              // [nbr_cap]

@@ -290,7 +290,6 @@ __global__ __launch_bounds__(kBlock) void k_cells(Plan P, uint64_t *__restrict__
                 // per-cube core tallies, accumulated with atomics in group mode
                 st_agent32(P.ncore + cell, 0u);
                 st_agent32(P.cmin + cell, kNone);
-                for (uint32_t t = 0; t < P.n_dir; t++) st_agent(P.rep + (uint64_t)cell * P.n_dir + t, ~0ull);
             }
             if (v[j] >> 31) {
                 const uint32_t g = (uint32_t)(inc >> 31) - 1u;
