@@ -26,7 +26,7 @@ METRIC = "points clustered/s (2-D 1M, 8-D 500k) vs HBM roofline; served p50/p99 
 HBM_PEAK_GBS = 8000.0
 # int32 VALU lane-ops: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 /s
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-WORKLOADS = {"2d": 2, "8d": 3, "small": 1, "batch": 4}
+WORKLOADS = {"2d": 2, "8d": 3, "small": 1, "batch": 4, "served": 5}
 HBM_PHASES = ("bbox", "sort", "cells", "labels")
 ALU_PHASES = {"core": "tests_core", "intra": "tests_intra", "merge": "tests_merge",
               "border": "tests_border"}
@@ -128,6 +128,8 @@ def main() -> int:
 
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "served":
+        return bench_served(args)
 
     import torch
     from paper_1912_00323_amd import hca
@@ -316,6 +318,109 @@ def bench_batch(args) -> int:
                                           f"one oracle.hca_grid call each"}
     print(json.dumps(line), flush=True)
     ctx.close()
+    return 0
+
+
+def bench_served(args, pool_size: int = 48, requests: int = 400, loads=(0.8, 1.0, 1.25, 1.5),
+                 main_load: float = 1.25, workers: int = 2) -> int:
+    """The served workload: Poisson arrivals of clustering requests (n
+    log-uniform in [1e4, 2e6], d in {2, 3, 5}, per-request eps and minPts) at
+    several loads, given as multiples of the request rate the plain sequential
+    path sustains.  The request loop (hca_server: continuous batching over
+    `workers` workers) and the plain path (one hca_cluster call at a time, in
+    arrival order) replay the same arrival trace; latency = completion -
+    arrival.  Both also run saturated (every request at time 0)."""
+    import torch
+    import numpy as np
+    from paper_1912_00323_amd import hca
+    from paper_1912_00323_amd.datagen import make_served, poisson_arrivals
+
+    pool = make_served(seed=5, count=pool_size)
+    dev = torch.device("cuda:0")
+    xs = [torch.from_numpy(j.points).to(dev) for j in pool]
+    ctx = hca.Context(0)
+    ctx.set_stream(torch.cuda.current_stream(dev).cuda_stream)
+    ref = [ctx.cluster(x, j.eps, j.min_pts) for x, j in zip(xs, pool)]   # warm-up, reference labels
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for x, j in zip(xs, pool):
+        ctx.cluster(x, j.eps, j.min_pts)
+    torch.cuda.synchronize()
+    plain_rate = len(pool) / (time.perf_counter() - t0)  # requests/s the plain path sustains
+    which = [k % len(pool) for k in range(requests)]
+    points = sum(pool[w].n for w in which)
+    outs = [torch.empty(pool[w].n, dtype=torch.int32, device=dev) for w in which]
+    srv = hca.Server(0, workers=workers, budget_bytes=48 << 30, max_batch=64)
+    same = True
+
+    def plain(arr):
+        lat = []
+        start = hca.clock() + 0.02
+        for k, w in enumerate(which):
+            while hca.clock() < start + arr[k]:
+                pass
+            ctx.cluster(xs[w], pool[w].eps, pool[w].min_pts, out=outs[k])
+            lat.append(hca.clock() - (start + arr[k]))
+        return lat, hca.clock() - start
+
+    def served(arr):
+        nonlocal same
+        for o in outs:
+            o.fill_(-9)
+        done = {}
+        start = hca.clock() + 0.02
+        for k, w in enumerate(which):
+            while hca.clock() < start + arr[k]:
+                for t, st, td in srv.poll():
+                    done[t] = (st, td)
+            srv.submit(xs[w], pool[w].eps, pool[w].min_pts, outs[k], tag=k)
+        srv.drain()
+        for t, st, td in srv.poll(1 << 16):
+            done[t] = (st, td)
+        same = same and all(done[k][0] == 0 and torch.equal(outs[k], ref[w]) for k, w in enumerate(which))
+        lat = [done[k][1] - (start + arr[k]) for k in range(requests)]
+        return lat, max(done[k][1] for k in range(requests)) - start
+
+    def summary(lat, span):
+        v = np.asarray(lat) * 1e3
+        return {"p50_ms": round(float(np.percentile(v, 50)), 3), "p99_ms": round(float(np.percentile(v, 99)), 3),
+                "points_per_s": points / span}
+
+    sweep = {}
+    for load in loads:
+        arr = poisson_arrivals(5, requests, load * plain_rate)
+        sweep[str(load)] = {"served": summary(*served(arr)), "plain_sequential": summary(*plain(arr))}
+    zero = np.zeros(requests)
+    saturated = {"served": summary(*served(zero)), "plain_sequential": summary(*plain(zero))}
+    srv.close()
+    ctx.close()
+    main = sweep[str(main_load)]
+    line = {
+        "metric": METRIC,
+        "value": main["served"]["points_per_s"],
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": requests,
+        "warmup": len(pool),
+        "ms_per_step": round(points / main["served"]["points_per_s"] * 1e3 / requests, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i32",
+        "data": "synthetic",
+        "config": {"workload": "served_poisson", "requests": requests, "pool": len(pool), "load_vs_plain": main_load,
+                   "arrival_rate_per_s": round(main_load * plain_rate, 3), "points": points,
+                   "d": sorted(set(j.d for j in pool)), "workers": workers, "parallelism": "single-gpu"},
+        "served": main["served"],
+        "plain_sequential": main["plain_sequential"] | {"sustained_requests_per_s": round(plain_rate, 3)},
+        "load_sweep": sweep,
+        "saturated": saturated,
+        "labels_identical": bool(same),
+        "roofline": {"bound": "alu", "phase": "served requests (mixed phases)", "achieved": None,
+                     "peak": round(ALU_PEAK_TOPS, 2), "unit": "Tops/s (int32 lane-ops)", "frac": None,
+                     "traffic": None},
+    }
+    print(json.dumps(line), flush=True)
     return 0
 
 

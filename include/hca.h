@@ -174,6 +174,47 @@ hca_status hca_cluster_batch(hca_ctx *ctx, const int32_t *points, int32_t nseg, 
                              const int32_t *dims, const double *eps, const int32_t *min_pts,
                              int32_t *labels);
 
+/* Batched form over data sets that each keep their own arrays: the same as
+ * hca_cluster_batch, with data set i's rows at points[i] (DEVICE, row-major
+ * int32[rows[i]][dims[i]]) and its labels written to labels[i] (DEVICE
+ * int32[rows[i]]).  points, labels, rows, dims, eps, min_pts are HOST arrays
+ * of nseg entries.  Same errors as hca_cluster_batch. */
+hca_status hca_cluster_sets(hca_ctx *ctx, const int32_t *const *points, int32_t *const *labels, int32_t nseg,
+                            const int64_t *rows, const int32_t *dims, const double *eps,
+                            const int32_t *min_pts);
+
+/* Served form: a request loop (continuous batching).  Requests wait in one
+ * FIFO queue; `workers` threads, each with its own context and HIP stream,
+ * take the next requests whenever they are free: consecutive requests of
+ * d <= 4 are clustered together by one hca_cluster_sets call, a request of
+ * larger d alone by hca_cluster.  A batch is admitted only while the
+ * estimated device footprint of the running batches stays within
+ * budget_bytes (an idle server always admits one request); the work of
+ * different workers overlaps on the device.  Every result equals what
+ * hca_cluster returns for the request alone.
+ *   hca_server_create: workers in [1, 16], budget_bytes > 0, max_batch >= 1
+ *     (requests per batch); HCA_E_INVAL otherwise, HCA_E_DEVICE / NOMEM.
+ *   hca_server_submit: queue a request; points (DEVICE int32[n][d]) must stay
+ *     valid and labels (DEVICE int32[n]) unread until the request completes;
+ *     tag is the caller's.  HCA_E_INVAL for bad arguments or after destroy
+ *     began.
+ *   hca_server_poll: move up to max completed requests into tags, status
+ *     (the clustering call's status) and t_done (hca_clock seconds);
+ *     returns how many.  HOST arrays owned by the caller.
+ *   hca_server_drain: block until the queue is empty and no batch runs.
+ *   hca_server_destroy: finish the queued requests, stop the workers, free
+ *     everything.  NULL-safe.
+ * hca_clock: seconds of the steady clock the completion times use. */
+typedef struct hca_server hca_server;
+hca_status hca_server_create(hca_server **out, int32_t device, int32_t workers, int64_t budget_bytes,
+                             int32_t max_batch);
+hca_status hca_server_submit(hca_server *srv, const int32_t *points, int64_t n, int32_t d, double eps,
+                             int32_t min_pts, int32_t *labels, uint64_t tag);
+int32_t hca_server_poll(hca_server *srv, uint64_t *tags, int32_t *status, double *t_done, int32_t max);
+hca_status hca_server_drain(hca_server *srv);
+void hca_server_destroy(hca_server *srv);
+double hca_clock(void);
+
 /* Phases of one call, in launch order, for hca_set_profiling / hca_phase_times:
  * origin shift (bounding box); cube keys and their radix sort with the gather
  * of points into cube order (methodology, pre-processing sort); cube and group

@@ -759,27 +759,36 @@ void batch_stencil(BatchGroup &g)
         }
 }
 
-hca_status run_batch(hca_ctx *ctx, const int32_t *points, int32_t nseg, const int64_t *rows, const int32_t *dims,
-                     const double *eps, const int32_t *min_pts, int32_t *labels)
+// One data set of a batch: its own device rows and label array.
+struct BatchSet {
+    const int32_t *pts;
+    int32_t *labels;
+    int64_t n;
+    int32_t d;
+    double eps;
+    int32_t min_pts;
+};
+
+hca_status run_sets(hca_ctx *ctx, const BatchSet *sets, int32_t nseg)
 {
     if (!ctx) return HCA_E_INVAL;
     ctx->err.clear();
     if (nseg < 0) return fail(ctx, HCA_E_INVAL, "nseg must be >= 0");
     if (nseg == 0) return HCA_OK;
-    if (!rows || !dims || !eps || !min_pts) return fail(ctx, HCA_E_INVAL, "per-data-set arrays must not be NULL");
-    uint64_t total_rows = 0, total_elems = 0;
+    if (!sets) return fail(ctx, HCA_E_INVAL, "data sets must not be NULL");
+    uint64_t total_rows = 0;
     for (int32_t i = 0; i < nseg; i++) {
-        if (rows[i] < 0) return fail(ctx, HCA_E_INVAL, "rows must be >= 0");
-        if (dims[i] < 1 || dims[i] > kMaxBatchDim) return fail(ctx, HCA_E_INVAL, "batch data sets need d in [1, 4]");
-        if (!(eps[i] > 0.0) || !std::isfinite(eps[i])) return fail(ctx, HCA_E_INVAL, "eps must be finite and > 0");
-        if (min_pts[i] < 1) return fail(ctx, HCA_E_INVAL, "min_pts must be >= 1");
-        total_rows += (uint64_t)rows[i];
-        total_elems += (uint64_t)rows[i] * (uint64_t)dims[i];
+        const BatchSet &b = sets[i];
+        if (b.n < 0) return fail(ctx, HCA_E_INVAL, "rows must be >= 0");
+        if (b.d < 1 || b.d > kMaxBatchDim) return fail(ctx, HCA_E_INVAL, "batch data sets need d in [1, 4]");
+        if (!(b.eps > 0.0) || !std::isfinite(b.eps)) return fail(ctx, HCA_E_INVAL, "eps must be finite and > 0");
+        if (b.min_pts < 1) return fail(ctx, HCA_E_INVAL, "min_pts must be >= 1");
+        if (b.n > 0 && (!b.pts || !b.labels)) return fail(ctx, HCA_E_INVAL, "points and labels must not be NULL");
+        if ((uintptr_t)b.pts % 4 || (uintptr_t)b.labels % 4) return fail(ctx, HCA_E_INVAL, "misaligned arrays");
+        total_rows += (uint64_t)b.n;
         if (total_rows > (uint64_t)INT32_MAX) return fail(ctx, HCA_E_INVAL, "more than 2^31 - 1 rows in all");
     }
     if (total_rows == 0) return HCA_OK;
-    if (!points || !labels) return fail(ctx, HCA_E_INVAL, "points and labels must not be NULL");
-    if ((uintptr_t)points % 4 || (uintptr_t)labels % 4) return fail(ctx, HCA_E_INVAL, "misaligned arrays");
     hipStream_t s = ctx->stream;
     HCA_HIP(hipSetDevice(ctx->device), "hipSetDevice");
 
@@ -787,25 +796,23 @@ hca_status run_batch(hca_ctx *ctx, const int32_t *points, int32_t nseg, const in
     std::vector<BatchGroup> groups;
     {
         BatchGroup by_d[kMaxBatchDim + 1];
-        uint64_t elem = 0, row = 0;
         for (int32_t i = 0; i < nseg; i++) {
-            BatchGroup &g = by_d[dims[i]];
-            g.d = dims[i];
+            const BatchSet &b = sets[i];
+            BatchGroup &g = by_d[b.d];
+            g.d = b.d;
             SegParam sp;
             std::memset(&sp, 0, sizeof sp);
-            exact_eps2(eps[i], &sp.eps2);
-            sp.side = std::max<int64_t>(1, (int64_t)isqrt_u64((uint64_t)sp.eps2 / (uint64_t)dims[i]));
+            exact_eps2(b.eps, &sp.eps2);
+            sp.side = std::max<int64_t>(1, (int64_t)isqrt_u64((uint64_t)sp.eps2 / (uint64_t)b.d));
             sp.side = std::min<int64_t>(sp.side, 1ll << 31);
-            sp.src_elem = elem;
-            sp.min_pts = (uint32_t)min_pts[i];
+            sp.src = b.pts;
+            sp.dst = b.labels;
+            sp.min_pts = (uint32_t)b.min_pts;
             sp.vstart = g.n;
-            sp.dst_row = (uint32_t)row;
             g.segs.push_back(i);
             g.par.push_back(sp);
             g.radius.push_back(offset_radius(sp.side, sp.eps2));
-            g.n += (uint32_t)rows[i];
-            elem += (uint64_t)rows[i] * (uint64_t)dims[i];
-            row += (uint64_t)rows[i];
+            g.n += (uint32_t)b.n;
         }
         for (int dd = 1; dd <= kMaxBatchDim; dd++)
             if (by_d[dd].n > 0) groups.push_back(std::move(by_d[dd]));
@@ -852,7 +859,7 @@ hca_status run_batch(hca_ctx *ctx, const int32_t *points, int32_t nseg, const in
         HCA_HIP(hipMemcpyAsync(db + g.d_seg, hb + g.h_seg, ns * sizeof(SegParam), hipMemcpyHostToDevice, s),
                 "data-set table");
         launch_init((uint32_t *)(db + g.d_box), ns * 2 * g.d, nullptr, 0, s);
-        launch_seg_stage(g.d, (const SegParam *)(db + g.d_seg), (uint32_t)ns, points, (int32_t *)(db + g.d_pts),
+        launch_seg_stage(g.d, (const SegParam *)(db + g.d_seg), (uint32_t)ns, (int32_t *)(db + g.d_pts),
                          (uint32_t *)(db + g.d_segof), g.n, (uint32_t *)(db + g.d_box), s);
         HCA_HIP(hipMemcpyAsync(hb + g.h_box, db + g.d_box, ns * 2 * g.d * sizeof(uint32_t), hipMemcpyDeviceToHost,
                                s), "box copy");
@@ -870,7 +877,7 @@ hca_status run_batch(hca_ctx *ctx, const int32_t *points, int32_t nseg, const in
         bool wide = false;
         for (size_t i = 0; i < ns; i++) {
             SegParam &sp = g.par[i];
-            if (rows[g.segs[i]] == 0) continue;
+            if (sets[g.segs[i]].n == 0) continue;
             int64_t span_max = 0;
             for (int k = 0; k < d; k++) {
                 const int32_t lo = (int32_t)(~box[i * 2 * d + k] ^ 0x80000000u);
@@ -937,7 +944,7 @@ hca_status run_batch(hca_ctx *ctx, const int32_t *points, int32_t nseg, const in
     for (BatchGroup &g : groups) {
         for (bool &u : ctx->ev_used) u = false;
         launch_sequence(ctx, g.P, g.Z);
-        launch_seg_scatter(g.P.seg, g.P.seg_of, g.P.labels, labels, g.n, s);
+        launch_seg_scatter(g.P.seg, g.P.seg_of, g.P.labels, g.n, s);
         if (ctx->prof != -1) {
             HCA_HIP(hipStreamSynchronize(s), "batch sync");
             for (int ph = 0; ph < HCA_PHASES; ph++) {
@@ -951,6 +958,26 @@ hca_status run_batch(hca_ctx *ctx, const int32_t *points, int32_t nseg, const in
     HCA_HIP(hipStreamSynchronize(s), "batch sync");
     for (int ph = 0; ph < HCA_PHASES; ph++) ctx->phase_ms[ph] = acc[ph];
     return HCA_OK;
+}
+
+hca_status run_batch(hca_ctx *ctx, const int32_t *points, int32_t nseg, const int64_t *rows, const int32_t *dims,
+                     const double *eps, const int32_t *min_pts, int32_t *labels)
+{
+    if (!ctx) return HCA_E_INVAL;
+    if (nseg < 0) return fail(ctx, HCA_E_INVAL, "nseg must be >= 0");
+    if (nseg == 0) return HCA_OK;
+    if (!rows || !dims || !eps || !min_pts) return fail(ctx, HCA_E_INVAL, "per-data-set arrays must not be NULL");
+    std::vector<BatchSet> sets((size_t)nseg);
+    uint64_t elem = 0, row = 0;
+    for (int32_t i = 0; i < nseg; i++) {
+        if (rows[i] < 0 || dims[i] < 1 || dims[i] > kMaxBatchDim)
+            return fail(ctx, HCA_E_INVAL, "rows must be >= 0 and d in [1, 4]");
+        sets[i] = {points ? points + elem : nullptr, labels ? labels + row : nullptr, rows[i], dims[i], eps[i],
+                   min_pts[i]};
+        elem += (uint64_t)rows[i] * (uint64_t)dims[i];
+        row += (uint64_t)rows[i];
+    }
+    return run_sets(ctx, sets.data(), nseg);
 }
 
 }  // namespace
@@ -1050,6 +1077,19 @@ hca_status hca_cluster_batch(hca_ctx *ctx, const int32_t *points, int32_t nseg, 
                              const int32_t *dims, const double *eps, const int32_t *min_pts, int32_t *labels)
 {
     return run_batch(ctx, points, nseg, rows, dims, eps, min_pts, labels);
+}
+
+hca_status hca_cluster_sets(hca_ctx *ctx, const int32_t *const *points, int32_t *const *labels, int32_t nseg,
+                            const int64_t *rows, const int32_t *dims, const double *eps, const int32_t *min_pts)
+{
+    if (!ctx) return HCA_E_INVAL;
+    if (nseg < 0) return fail(ctx, HCA_E_INVAL, "nseg must be >= 0");
+    if (nseg == 0) return HCA_OK;
+    if (!points || !labels || !rows || !dims || !eps || !min_pts)
+        return fail(ctx, HCA_E_INVAL, "per-data-set arrays must not be NULL");
+    std::vector<BatchSet> sets((size_t)nseg);
+    for (int32_t i = 0; i < nseg; i++) sets[i] = {points[i], labels[i], rows[i], dims[i], eps[i], min_pts[i]};
+    return run_sets(ctx, sets.data(), nseg);
 }
 
 hca_status hca_cluster_host(hca_ctx *ctx, const int32_t *points, int64_t n, int32_t d, double eps,

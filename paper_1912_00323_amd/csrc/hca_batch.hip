@@ -25,18 +25,18 @@ __device__ __forceinline__ uint32_t seg_of_row(const uint32_t *s_vs, uint32_t ns
     return lo;
 }
 
-// Copy the rows of every data set (at its own offset in the caller's array)
-// into one contiguous array, and record each row's data set.
+// Copy the rows of every data set (from its own array) into one contiguous
+// array, and record each row's data set.
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_seg_gather(const SegParam *seg, uint32_t nseg, const int32_t *src,
-                                                       int32_t *dst, uint32_t *seg_of, uint32_t n)
+__global__ __launch_bounds__(kBlock) void k_seg_gather(const SegParam *seg, uint32_t nseg, int32_t *dst,
+                                                       uint32_t *seg_of, uint32_t n)
 {
     extern __shared__ uint32_t s_vs[];
     for (uint32_t i = threadIdx.x; i < nseg; i += kBlock) s_vs[i] = seg[i].vstart;
     __syncthreads();
     for (uint32_t r = blockIdx.x * kBlock + threadIdx.x; r < n; r += gridDim.x * kBlock) {
         const uint32_t s = seg_of_row(s_vs, nseg, r);
-        const int32_t *p = src + seg[s].src_elem + (uint64_t)(r - s_vs[s]) * D;
+        const int32_t *p = seg[s].src + (uint64_t)(r - s_vs[s]) * D;
 #pragma unroll
         for (int k = 0; k < D; k++) dst[(uint64_t)r * D + k] = p[k];
         seg_of[r] = s;
@@ -77,23 +77,23 @@ __global__ __launch_bounds__(kBlock) void k_seg_bbox(const int32_t *pts, const u
     }
 }
 
-// Labels back to the caller's layout.
+// Labels back to each data set's own array.
 __global__ __launch_bounds__(kBlock) void k_seg_scatter(const SegParam *seg, const uint32_t *seg_of,
-                                                        const int32_t *staged, int32_t *out, uint32_t n)
+                                                        const int32_t *staged, uint32_t n)
 {
     for (uint32_t r = blockIdx.x * kBlock + threadIdx.x; r < n; r += gridDim.x * kBlock) {
         const SegParam &sp = seg[seg_of[r]];
-        out[(uint64_t)sp.dst_row + (r - sp.vstart)] = staged[r];
+        sp.dst[r - sp.vstart] = staged[r];
     }
 }
 
 template <int D>
-static void gather_d(const SegParam *seg, uint32_t nseg, const int32_t *src, int32_t *dst, uint32_t *seg_of,
-                     uint32_t n, hipStream_t s)
+static void gather_d(const SegParam *seg, uint32_t nseg, int32_t *dst, uint32_t *seg_of, uint32_t n,
+                     hipStream_t s)
 {
     const int blocks = (int)std::min<uint64_t>((n + kBlock - 1) / kBlock, 2048);
-    hipLaunchKernelGGL(k_seg_gather<D>, dim3(blocks), dim3(kBlock), nseg * sizeof(uint32_t), s, seg, nseg, src,
-                       dst, seg_of, n);
+    hipLaunchKernelGGL(k_seg_gather<D>, dim3(blocks), dim3(kBlock), nseg * sizeof(uint32_t), s, seg, nseg, dst,
+                       seg_of, n);
 }
 
 template <int D>
@@ -103,22 +103,22 @@ static void bbox_d(const int32_t *pts, const uint32_t *seg_of, uint32_t n, uint3
     hipLaunchKernelGGL(k_seg_bbox<D>, dim3(blocks), dim3(kBlock), 0, s, pts, seg_of, n, box);
 }
 
-void launch_seg_stage(int d, const SegParam *seg, uint32_t nseg, const int32_t *src, int32_t *dst,
-                      uint32_t *seg_of, uint32_t n, uint32_t *box, hipStream_t s)
+void launch_seg_stage(int d, const SegParam *seg, uint32_t nseg, int32_t *dst, uint32_t *seg_of, uint32_t n,
+                      uint32_t *box, hipStream_t s)
 {
     switch (d) {
-    case 1: gather_d<1>(seg, nseg, src, dst, seg_of, n, s); bbox_d<1>(dst, seg_of, n, box, s); break;
-    case 2: gather_d<2>(seg, nseg, src, dst, seg_of, n, s); bbox_d<2>(dst, seg_of, n, box, s); break;
-    case 3: gather_d<3>(seg, nseg, src, dst, seg_of, n, s); bbox_d<3>(dst, seg_of, n, box, s); break;
-    case 4: gather_d<4>(seg, nseg, src, dst, seg_of, n, s); bbox_d<4>(dst, seg_of, n, box, s); break;
+    case 1: gather_d<1>(seg, nseg, dst, seg_of, n, s); bbox_d<1>(dst, seg_of, n, box, s); break;
+    case 2: gather_d<2>(seg, nseg, dst, seg_of, n, s); bbox_d<2>(dst, seg_of, n, box, s); break;
+    case 3: gather_d<3>(seg, nseg, dst, seg_of, n, s); bbox_d<3>(dst, seg_of, n, box, s); break;
+    case 4: gather_d<4>(seg, nseg, dst, seg_of, n, s); bbox_d<4>(dst, seg_of, n, box, s); break;
     }
 }
 
-void launch_seg_scatter(const SegParam *seg, const uint32_t *seg_of, const int32_t *staged, int32_t *out,
-                        uint32_t n, hipStream_t s)
+void launch_seg_scatter(const SegParam *seg, const uint32_t *seg_of, const int32_t *staged, uint32_t n,
+                        hipStream_t s)
 {
     const int blocks = (int)std::min<uint64_t>((n + kBlock - 1) / kBlock, 2048);
-    hipLaunchKernelGGL(k_seg_scatter, dim3(blocks), dim3(kBlock), 0, s, seg, seg_of, staged, out, n);
+    hipLaunchKernelGGL(k_seg_scatter, dim3(blocks), dim3(kBlock), 0, s, seg, seg_of, staged, n);
 }
 
 }  // namespace hca

@@ -33,10 +33,11 @@ void launch_border(const Plan &P, int blocks, hipStream_t s);
 void launch_labels(const Plan &P, uint64_t *status, uint32_t *ticket, hipStream_t s);
 
 // batches: stage the data sets of one dimension d <= 4 contiguously (rows and
-// their data set) and take their bounding boxes; labels back to the caller
-void launch_seg_stage(int d, const SegParam *seg, uint32_t nseg, const int32_t *src, int32_t *dst,
-                      uint32_t *seg_of, uint32_t n, uint32_t *box, hipStream_t s);
-void launch_seg_scatter(const SegParam *seg, const uint32_t *seg_of, const int32_t *staged, int32_t *out,
-                        uint32_t n, hipStream_t s);
+// their data set, read from each data set's own rows) and take their bounding
+// boxes; labels back to each data set's own array
+void launch_seg_stage(int d, const SegParam *seg, uint32_t nseg, int32_t *dst, uint32_t *seg_of, uint32_t n,
+                      uint32_t *box, hipStream_t s);
+void launch_seg_scatter(const SegParam *seg, const uint32_t *seg_of, const int32_t *staged, uint32_t n,
+                        hipStream_t s);
 
 }  // namespace hca

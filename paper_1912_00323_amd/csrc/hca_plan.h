@@ -63,12 +63,13 @@ enum { kTestsCore = 0, kTestsMerge = 1, kTestsBorder = 2, kTestsIntra = 3 };
 struct SegParam {
     int64_t eps2;
     int64_t side;
-    uint64_t src_elem;          // first coordinate in the caller's point array
+    const int32_t *src;         // the data set's rows (device), row-major
+    int32_t *dst;               // its labels (device)
     int32_t origin[kMaxDim];
     uint32_t min_pts;
     uint32_t vstart;            // first row in the staged (contiguous) order
-    uint32_t dst_row;           // first row in the caller's label array
     uint32_t label_base;        // clusters of the earlier data sets of the batch
+    uint32_t pad;
 };
 
 struct Plan {

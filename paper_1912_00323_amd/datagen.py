@@ -139,6 +139,20 @@ def make_batch(seed: int = 4, count: int = 256, n_range=(1_000, 200_000), dims=(
     return jobs
 
 
+def make_served(seed: int = 5, count: int = 64, n_range=(10_000, 2_000_000), dims=(2, 3, 5),
+                q: int = 14) -> list:
+    """Request data sets of the served workload: job k drawn from the k-th
+    child of ``SeedSequence(seed)``, with the batched workload's recipe but n
+    log-uniform in ``n_range`` and d uniform in ``dims``."""
+    return make_batch(seed=seed, count=count, n_range=n_range, dims=dims, q=q)
+
+
+def poisson_arrivals(seed: int, count: int, rate: float) -> np.ndarray:
+    """Arrival times (seconds from 0) of a Poisson process of the given rate."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 1])))
+    return np.cumsum(rng.exponential(1.0 / rate, size=count))
+
+
 CONFIG_NAMES = {1: "blobs2d_10k", 2: "blobs2d_1m", 3: "blobs8d_500k"}
 
 

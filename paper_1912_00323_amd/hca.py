@@ -83,6 +83,20 @@ def load_library(path: str | Path | None = None) -> ctypes.CDLL:
     lib.hca_cluster_host.restype = ctypes.c_int
     lib.hca_cluster_batch.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp]
     lib.hca_cluster_batch.restype = ctypes.c_int
+    lib.hca_cluster_sets.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
+    lib.hca_cluster_sets.restype = ctypes.c_int
+    lib.hca_server_create.argtypes = [ctypes.POINTER(vp), i32, i32, i64, i32]
+    lib.hca_server_create.restype = ctypes.c_int
+    lib.hca_server_submit.argtypes = [vp, vp, i64, i32, dbl, i32, vp, ctypes.c_uint64]
+    lib.hca_server_submit.restype = ctypes.c_int
+    lib.hca_server_poll.argtypes = [vp, vp, vp, vp, i32]
+    lib.hca_server_poll.restype = i32
+    lib.hca_server_drain.argtypes = [vp]
+    lib.hca_server_drain.restype = ctypes.c_int
+    lib.hca_server_destroy.argtypes = [vp]
+    lib.hca_server_destroy.restype = None
+    lib.hca_clock.argtypes = []
+    lib.hca_clock.restype = dbl
     lib.hca_set_profiling.argtypes = [vp, i32]
     lib.hca_set_profiling.restype = ctypes.c_int
     lib.hca_phase_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32]
@@ -90,6 +104,66 @@ def load_library(path: str | Path | None = None) -> ctypes.CDLL:
     if path is None:
         _lib = lib
     return lib
+
+
+def clock() -> float:
+    """Seconds of the steady clock the server stamps completions with."""
+    return float(load_library().hca_clock())
+
+
+class Server:
+    """The served form (hca_server_*): submit requests on device tensors,
+    poll completions.  Keep every submitted tensor alive until its request
+    completes."""
+
+    def __init__(self, device: int = 0, workers: int = 2, budget_bytes: int = 32 << 30,
+                 max_batch: int = 64):
+        self._lib = load_library()
+        self._srv = ctypes.c_void_p()
+        st = self._lib.hca_server_create(ctypes.byref(self._srv), int(device), int(workers),
+                                         int(budget_bytes), int(max_batch))
+        if st != HCA_OK:
+            raise HcaError(st, "hca_server_create failed")
+        self._keep = {}
+
+    def submit(self, points, eps: float, min_pts: int, labels, tag: int):
+        import torch
+        if not (isinstance(points, torch.Tensor) and points.is_cuda and points.dtype == torch.int32
+                and points.dim() == 2 and points.is_contiguous()):
+            raise TypeError("points must be a contiguous CUDA int32 tensor [n, d]")
+        n, d = points.shape
+        self._keep[int(tag)] = (points, labels)
+        st = self._lib.hca_server_submit(self._srv, ctypes.c_void_p(points.data_ptr()), n, d, float(eps),
+                                         int(min_pts), ctypes.c_void_p(labels.data_ptr()), int(tag))
+        if st != HCA_OK:
+            self._keep.pop(int(tag), None)
+            raise HcaError(st, "hca_server_submit failed")
+
+    def poll(self, max_items: int = 4096):
+        """Completed requests: list of (tag, status, t_done)."""
+        tags = (ctypes.c_uint64 * max_items)()
+        status = (ctypes.c_int32 * max_items)()
+        tdone = (ctypes.c_double * max_items)()
+        k = self._lib.hca_server_poll(self._srv, tags, status, tdone, max_items)
+        out = [(int(tags[i]), int(status[i]), float(tdone[i])) for i in range(k)]
+        for t, _, _ in out:
+            self._keep.pop(t, None)
+        return out
+
+    def drain(self):
+        self._lib.hca_server_drain(self._srv)
+
+    def close(self):
+        if self._srv:
+            self._lib.hca_server_destroy(self._srv)
+            self._srv = ctypes.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def exact_eps2(eps: float) -> int:

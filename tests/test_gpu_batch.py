@@ -122,3 +122,53 @@ def test_batch_full_workload(ctx):
         assert digest(g) == e["labels_sha256"], j.name
     again = run_batch(ctx, jobs)
     assert all(np.array_equal(a, b) for a, b in zip(got, again))
+
+
+def test_cluster_sets_own_arrays(ctx):
+    import torch
+    import ctypes
+    jobs = make_batch(seed=13, count=10, n_range=(100, 8000), dims=(2, 3, 4))
+    pts = [torch.from_numpy(j.points).cuda() for j in jobs]
+    outs = [torch.full((j.n,), -7, dtype=torch.int32, device="cuda") for j in jobs]
+    lib = ctx._lib
+    P = (ctypes.c_void_p * len(jobs))(*[p.data_ptr() for p in pts])
+    L = (ctypes.c_void_p * len(jobs))(*[o.data_ptr() for o in outs])
+    rows = np.array([j.n for j in jobs], np.int64)
+    dims = np.array([j.d for j in jobs], np.int32)
+    eps = np.array([j.eps for j in jobs], np.float64)
+    mps = np.array([j.min_pts for j in jobs], np.int32)
+    st = lib.hca_cluster_sets(ctx._ctx, P, L, len(jobs), rows.ctypes.data_as(ctypes.c_void_p),
+                              dims.ctypes.data_as(ctypes.c_void_p), eps.ctypes.data_as(ctypes.c_void_p),
+                              mps.ctypes.data_as(ctypes.c_void_p))
+    assert st == 0
+    for j, o in zip(jobs, outs):
+        assert np.array_equal(o.cpu().numpy(), oracle.dbscan(j.points, j.eps, j.min_pts)), j.name
+
+
+def test_server_results_alone_and_in_the_mix():
+    """Requests submitted together (batched, overlapping on two workers, a
+    5-D request among them) get exactly what each gets alone."""
+    import torch
+    from paper_1912_00323_amd import hca
+    jobs = make_batch(seed=14, count=30, n_range=(500, 40000), dims=(2, 3, 5))
+    srv = hca.Server(0, workers=2, budget_bytes=1 << 30, max_batch=8)
+    pts = [torch.from_numpy(j.points).cuda() for j in jobs]
+    outs = [torch.full((j.n,), -7, dtype=torch.int32, device="cuda") for j in jobs]
+    print(f"[case] server mix of {len(jobs)} requests", flush=True)
+    for k, (j, p, o) in enumerate(zip(jobs, pts, outs)):
+        srv.submit(p, j.eps, j.min_pts, o, tag=k)
+    srv.drain()
+    done = {}
+    while len(done) < len(jobs):
+        got = srv.poll()
+        assert got, "server drained without reporting every request"
+        for t, st, _ in got:
+            done[t] = st
+    srv.close()
+    assert all(st == 0 for st in done.values())
+    c = hca.Context(0)
+    for j, p, o in zip(jobs, pts, outs):
+        alone = c.cluster(p, j.eps, j.min_pts).cpu().numpy()
+        assert np.array_equal(o.cpu().numpy(), alone), j.name
+        assert np.array_equal(alone, oracle.dbscan(j.points, j.eps, j.min_pts)), j.name
+    c.close()
