@@ -420,6 +420,11 @@ void carve_ws(Carver &cv, Plan &P, SortBuffers &B, const Sizes &Z, uint32_t **ze
         P.nbr_count = cv.take<uint32_t>(n);
         P.nbr_start = cv.take<uint32_t>(n);
         P.nbr = cv.take<uint32_t>(P.nbr_cap);
+        P.nbr_bcount = cv.take<uint32_t>(n);
+        P.nbr_bstart = cv.take<uint32_t>(n);
+        P.nbr_bcursor = cv.take<uint32_t>(n);
+        P.nbr_back = cv.take<uint32_t>(P.nbr_cap);
+        P.gbox = cv.take<int32_t>((size_t)n * 2 * P.d);
     }
     P.work = cv.take<uint32_t>((size_t)2 * P.work_cap);
     P.owner = cv.take<uint32_t>(n);
@@ -435,6 +440,7 @@ void carve_ws(Carver &cv, Plan &P, SortBuffers &B, const Sizes &Z, uint32_t **ze
     P.scan_status = cv.take<uint64_t>((size_t)2 * Z.scan_tiles + 64);
     P.first = cv.take<uint32_t>(((size_t)n + 31) / 32);
     P.tile_status = cv.take<uint64_t>((size_t)Z.scan_tiles + 64);
+    P.nbr_status = P.nbr_cap ? cv.take<uint64_t>((size_t)Z.scan_tiles + 64) : nullptr;
     *zero_bytes = cv.off - zstart;
     *zero_begin = (uint32_t *)(cv.base ? cv.base + zstart : nullptr);
     // lookup table, filled with all-ones

@@ -134,6 +134,40 @@ __device__ __forceinline__ WaveRange wave_range()
     for (uint32_t k_ = hca_wr_.first, u = hca_wr_.unit(k_); u < (units);                \
          k_ += hca_wr_.step, u = hca_wr_.unit(k_))
 
+// Dynamic form, for units of very uneven cost: the units an XCD owns (as
+// above) are dealt round-robin to its queues; each wave takes its next unit
+// from its queue's counter, so waves that finish early take more.  Within a
+// queue the units grow with every take, so the first one past the end closes
+// the loop.
+struct DynRange {
+    uint32_t *cnt;
+    uint32_t xcd, q, nq;
+};
+
+// The grid is a multiple of 8 blocks, so every XCD holds gridDim.x / 8 blocks
+// of 4 waves; an XCD has min(8, its waves) queues, each with a wave.
+__device__ __forceinline__ DynRange dyn_range(uint32_t *queues)
+{
+    const uint32_t b = blockIdx.x;
+    DynRange d;
+    d.xcd = b & 7u;
+    d.nq = min(8u, (gridDim.x >> 3) * (kBlock / kWave));
+    d.q = ((b >> 3) * (kBlock / kWave) + wave_in_block()) % d.nq;
+    d.cnt = queues + (d.xcd * 8u + d.q) * kCounterStride;
+    return d;
+}
+
+__device__ __forceinline__ uint32_t dyn_next(const DynRange &d)
+{
+    uint32_t i = 0;
+    if (lane_id() == 0) i = atomicAdd(d.cnt, 1u);
+    i = __builtin_amdgcn_readfirstlane(i);
+    const uint32_t k = i * d.nq + d.q;
+    return ((k / kXcdRun) * 8u + d.xcd) * kXcdRun + (k % kXcdRun);
+}
+
+#define HCA_FOR_UNITS_DYN(u, units, dr) for (uint32_t u = dyn_next(dr); u < (units); u = dyn_next(dr))
+
 // ---- work counters ----------------------------------------------------------
 // Pair tests a lane executed; one atomic per wave, spread over many lines.
 __device__ __forceinline__ void flush_tests(const Plan &P, int which, uint32_t lane_tests)

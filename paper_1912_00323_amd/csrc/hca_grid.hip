@@ -108,17 +108,32 @@ __device__ __forceinline__ bool group_box_within(const Plan &P, uint64_t nk, con
 // itself.
 // ---------------------------------------------------------------------------
 struct NbrSrc {
-    uint32_t lists, start, slots;
+    uint32_t lists, start, fcount, bstart, slots;
 };
 
+// The lists are used when they were built and every group's forward list fit
+// (a group that did not fit would be missing from its neighbours' backward
+// lists); otherwise every group is searched over the stencil.
 __device__ __forceinline__ NbrSrc nbr_source(const Plan &P, uint32_t g)
 {
     NbrSrc src;
-    const uint32_t c = P.nbr_cap ? P.nbr_count[g] : kNone;
-    src.lists = c != kNone;
-    src.start = src.lists ? P.nbr_start[g] : 0;
-    src.slots = src.lists ? c + 1 : P.n_off;
+    src.lists = P.nbr_cap && P.ctr->nbr_overflow == 0;
+    if (src.lists) {
+        src.start = P.nbr_start[g];
+        src.fcount = P.nbr_count[g];
+        src.bstart = P.nbr_bstart[g];
+        src.slots = 1 + src.fcount + P.nbr_bcount[g];
+    } else {
+        src.start = src.fcount = src.bstart = 0;
+        src.slots = P.n_off;
+    }
     return src;
+}
+
+// Group at list slot j >= 1: forward entries, then backward ones.
+__device__ __forceinline__ uint32_t list_slot(const Plan &P, const NbrSrc &src, uint32_t j)
+{
+    return j <= src.fcount ? P.nbr[src.start + j - 1] : P.nbr_back[src.bstart + j - 1 - src.fcount];
 }
 
 // Group at slot j (or kNone), with its key in *nk.
@@ -127,7 +142,7 @@ __device__ __forceinline__ uint32_t slot_group(const Plan &P, uint32_t g, uint64
                                                uint32_t j, uint64_t *nk)
 {
     if (src.lists) {
-        const uint32_t G = j == 0 ? g : P.nbr[src.start + j - 1];
+        const uint32_t G = j == 0 ? g : list_slot(P, src, j);
         *nk = P.group_key[G];
         return G;
     }
@@ -334,19 +349,52 @@ __device__ __forceinline__ int64_t half_key_delta(const Plan &P, int first, uint
 }
 
 // Sort the n <= 128 gap sums of one half ascending (ties by index) into
-// s_sum / s_idx, by counting ranks; input in s_in.
-__device__ __forceinline__ void rank_sort(const int64_t *s_in, int n, int64_t *s_sum, uint8_t *s_idx)
+// s_sum / s_idx: a bitonic network over the next power of two of n, two
+// elements per lane (element i in lane i % 64, slot i / 64), partners one
+// lane-xor apart; padding elements sort last.
+__device__ __forceinline__ bool sum_less(int64_t a, uint32_t ia, int64_t b, uint32_t ib)
+{
+    return a < b || (a == b && ia < ib);
+}
+
+__device__ __forceinline__ void bitonic_sort(const int64_t *s_in, int n, int64_t *s_sum, uint8_t *s_idx)
 {
     const uint32_t l = lane_id();
-    for (int i = l; i < n; i += kWave) {
-        const int64_t v = s_in[i];
-        int r = 0;
-        for (int j = 0; j < n; j++) {
-            const int64_t u = s_in[j];
-            r += u < v || (u == v && j < i);
+    int n2 = 1;
+    while (n2 < n) n2 <<= 1;
+    int64_t v[2];
+    uint32_t ix[2];
+#pragma unroll
+    for (int sl = 0; sl < 2; sl++) {
+        const uint32_t i = sl * kWave + l;
+        v[sl] = (int)i < n ? s_in[i] : INT64_MAX;
+        ix[sl] = i;
+    }
+    for (int k = 2; k <= n2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j == kWave) {                         // k = 128: the two slots of a lane, ascending
+                if (sum_less(v[1], ix[1], v[0], ix[0])) {
+                    const int64_t tv = v[0]; v[0] = v[1]; v[1] = tv;
+                    const uint32_t ti = ix[0]; ix[0] = ix[1]; ix[1] = ti;
+                }
+                continue;
+            }
+#pragma unroll
+            for (int sl = 0; sl < 2; sl++) {
+                if (sl * kWave >= n2) continue;
+                const int64_t y = __shfl_xor(v[sl], j);
+                const uint32_t iy = __shfl_xor(ix[sl], j);
+                const uint32_t i = sl * kWave + l;
+                const bool asc = (i & (uint32_t)k) == 0, lower = (l & (uint32_t)j) == 0;
+                const bool mine_less = sum_less(v[sl], ix[sl], y, iy);
+                if ((lower == asc) != mine_less) { v[sl] = y; ix[sl] = iy; }
+            }
         }
-        s_sum[r] = v;
-        s_idx[r] = (uint8_t)i;
+    }
+#pragma unroll
+    for (int sl = 0; sl < 2; sl++) {
+        const uint32_t r = sl * kWave + l;
+        if ((int)r < n) { s_sum[r] = v[sl]; s_idx[r] = (uint8_t)ix[sl]; }
     }
 }
 
@@ -357,18 +405,77 @@ __device__ __forceinline__ void rank_sort(const int64_t *s_in, int n, int64_t *s
 // offsets that can hold a point within eps are the pairs (i, j) of the two
 // halves with sum_a[i] + sum_b[j] <= eps^2.  Both halves are sorted, so for
 // each i the valid j form a prefix; only those offsets are looked up.  Each
-// wave appends to its own slab; a group that does not fit is flagged and
+// wave appends to its own slab; when a group does not fit, every group is
 // searched over the stencil instead.
+
+// Point box of every group, and the backward counters cleared.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_group_box(Plan P)
+{
+    const uint32_t l = lane_id();
+    const uint32_t ng = ld_agent32(&P.ctr->n_groups);
+    const WaveRange hca_wr_ = wave_range();
+    HCA_FOR_UNITS(g, ng) {
+        const QBox<D> b = group_points_box<D>(P, P.group_start[g], P.group_start[g + 1]);
+        if (l < (uint32_t)D) {
+            int32_t lo = 0, hi = 0;
+#pragma unroll
+            for (int e = 0; e < D; e++)
+                if ((uint32_t)e == l) { lo = b.lo[e]; hi = b.hi[e]; }
+            P.gbox[(uint64_t)g * 2 * D + l] = lo;
+            P.gbox[(uint64_t)g * 2 * D + D + l] = hi;
+        }
+        if (l == 0) {
+            st_agent32(P.nbr_bcount + g, 0u);
+            st_agent32(P.nbr_bcursor + g, 0u);
+        }
+    }
+}
+
+template <int D>
+__device__ __forceinline__ QBox<D> load_gbox(const Plan &P, uint32_t g)
+{
+    QBox<D> b;
+#pragma unroll
+    for (int e = 0; e < D; e++) {
+        b.lo[e] = P.gbox[(uint64_t)g * 2 * D + e];
+        b.hi[e] = P.gbox[(uint64_t)g * 2 * D + D + e];
+    }
+    return b;
+}
+
+// Lexicographic sign (axis `first` most significant) of the offset
+// combination idx of K axes: the sign of its first non-zero component.
+template <int K>
+__device__ __forceinline__ int8_t half_sign(const Plan &P, uint32_t idx)
+{
+    const uint32_t W = P.list_w;
+    const int R = (int)(W >> 1);
+    int sg = 0;
+#pragma unroll
+    for (int e = 0; e < K; e++) {
+        const int o = (int)(idx % W) - R;
+        idx /= W;
+        if (sg == 0) sg = o;
+    }
+    return (int8_t)(sg > 0 ? 1 : (sg < 0 ? -1 : 0));
+}
+
 constexpr int kListBatch = 4;        // lookups in flight per lane
 
 constexpr int kListHalf = 128;       // offset combinations per half of the axes, at most
 
+// Forward lists, one wave per group: only offsets that lead to a larger key
+// (the first non-zero component, from axis 0, is positive) are looked up,
+// and a found group is kept when the two point boxes come within eps; its
+// backward counter is raised.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_nbr_lists(Plan P)
 {
     constexpr int DA = D / 2, DB = D - DA;
     __shared__ int64_t s_sa[kWavesPerBlock][kListHalf], s_sb[kWavesPerBlock][kListHalf];
     __shared__ uint8_t s_ia[kWavesPerBlock][kListHalf], s_ib[kWavesPerBlock][kListHalf];
+    __shared__ int8_t s_ga[kWavesPerBlock][kListHalf], s_gb[kWavesPerBlock][kListHalf];
     __shared__ int64_t s_ka[kWavesPerBlock][kListHalf], s_kb[kWavesPerBlock][kListHalf];
     __shared__ uint32_t s_pre[kWavesPerBlock][kListHalf + 1];
     int64_t(*s_in)[kListHalf] = s_ka;     // unsorted sums, before the key offsets
@@ -382,26 +489,29 @@ __global__ __launch_bounds__(kBlock) void k_nbr_lists(Plan P)
     uint32_t at = (blockIdx.x * kWavesPerBlock + w) * slab;
     const uint32_t end = at + slab;
     uint32_t overflow = 0;
-    const WaveRange hca_wr_ = wave_range();
-    HCA_FOR_UNITS(g, ng) {
+    const DynRange dr_ = dyn_range(P.ctr->dyn[kDynLists]);
+    HCA_FOR_UNITS_DYN(g, ng, dr_) {
         const uint64_t gkey = P.group_key[g];
         const Geo<D> geo = cube_geo<D>(P, gkey);
-        const QBox<D> qb = group_points_box<D>(P, P.group_start[g], P.group_start[g + 1]);
-        // both halves' gap sums, sorted ascending
+        const QBox<D> qb = load_gbox<D>(P, g);
+        // both halves' gap sums, sorted ascending, with their signs
         for (int i = l; i < NA; i += kWave) s_in[w][i] = half_gap2<D, DA>(P, gkey, 0, i, qb, geo);
         __builtin_amdgcn_wave_barrier();
-        rank_sort(s_in[w], NA, s_sa[w], s_ia[w]);
+        bitonic_sort(s_in[w], NA, s_sa[w], s_ia[w]);
         __builtin_amdgcn_wave_barrier();
         for (int j = l; j < NB; j += kWave) s_in[w][j] = half_gap2<D, DB>(P, gkey, DA, j, qb, geo);
         __builtin_amdgcn_wave_barrier();
-        rank_sort(s_in[w], NB, s_sb[w], s_ib[w]);
+        bitonic_sort(s_in[w], NB, s_sb[w], s_ib[w]);
         __builtin_amdgcn_wave_barrier();
-        // valid j per i (a prefix of the sorted second half), then their prefix
+        for (int i = l; i < NA; i += kWave) s_ga[w][i] = half_sign<DA>(P, s_ia[w][i]);
+        for (int j = l; j < NB; j += kWave) s_gb[w][j] = half_sign<DB>(P, s_ib[w][j]);
+        // valid j per i (a prefix of the sorted second half; none when the
+        // first half points backwards), then their prefix
         uint32_t tot = 0;
         for (int i0 = 0; i0 < NA; i0 += kWave) {
             const int i = i0 + (int)l;
             uint32_t c = 0;
-            if (i < NA && s_sa[w][i] != INT64_MAX) {
+            if (i < NA && s_sa[w][i] != INT64_MAX && s_ga[w][i] >= 0) {
                 const int64_t lim = geo.eps2 - s_sa[w][i];
                 int lo = 0, hi = NB;                      // first j with s_sb > lim
                 while (lo < hi) {
@@ -435,17 +545,31 @@ __global__ __launch_bounds__(kBlock) void k_nbr_lists(Plan P)
                         if (s_pre[w][mid] <= t) lo = mid; else hi = mid;
                     }
                     const uint32_t j = t - s_pre[w][lo];
-                    nk[b] = gkey + (uint64_t)(s_ka[w][lo] + s_kb[w][j]);
-                    if (nk[b] == gkey) nk[b] = ~0ull;     // the group itself
+                    // first half zero: the second half must point forwards
+                    if (s_ga[w][lo] > 0 || s_gb[w][j] > 0) nk[b] = gkey + (uint64_t)(s_ka[w][lo] + s_kb[w][j]);
                 }
             }
             group_lookup_n<kListBatch>(P, nk, G);
 #pragma unroll
             for (int b = 0; b < kListBatch; b++) {
+                // both groups' point boxes within eps
+                if (G[b] != kNone) {
+                    const QBox<D> ob = load_gbox<D>(P, G[b]);
+                    int64_t acc = 0;
+#pragma unroll
+                    for (int e = 0; e < D; e++) {
+                        const int64_t gap = max((int64_t)ob.lo[e] - qb.hi[e], (int64_t)qb.lo[e] - ob.hi[e]);
+                        acc += gap > 0 ? gap * gap : 0;
+                    }
+                    if (acc > geo.eps2) G[b] = kNone;
+                }
                 const uint64_t m = __ballot(G[b] != kNone);
                 const uint32_t k = (uint32_t)__popcll(m);
                 if (at + k > end) fits = false;
-                if (fits && G[b] != kNone) P.nbr[at + __popcll(m & __lanemask_lt())] = G[b];
+                if (fits && G[b] != kNone) {
+                    P.nbr[at + __popcll(m & __lanemask_lt())] = G[b];
+                    atomicAdd(P.nbr_bcount + G[b], 1u);
+                }
                 if (fits) at += k;
             }
         }
@@ -460,6 +584,59 @@ __global__ __launch_bounds__(kBlock) void k_nbr_lists(Plan P)
         }
     }
     if (l == 0 && overflow) atomicAdd(&P.ctr->nbr_overflow, overflow);
+}
+
+// Exclusive prefix of the backward counts over the groups.
+__global__ __launch_bounds__(kBlock) void k_nbr_bscan(Plan P)
+{
+    __shared__ uint32_t s_red[kBlock / kWave];
+    __shared__ uint32_t s_tile, s_excl;
+    const uint32_t t = threadIdx.x;
+    const uint32_t ng = ld_agent32(&P.ctr->n_groups);
+    if (t == 0) s_tile = atomicAdd(&P.ctr->nbr_ticket, 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile, base = tile * kScanTile;
+    uint32_t f[kScanItems];
+    uint32_t local = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; j++) {
+        const uint32_t g = base + j * kBlock + t;
+        f[j] = g < ng ? ld_agent32(P.nbr_bcount + g) : 0u;
+        local += f[j];
+    }
+    uint32_t agg;
+    block_exclusive_scan<uint32_t>(local, s_red, &agg);
+    if (t < kWave) {
+        const uint32_t e = (uint32_t)scan_lookback_wave(P.nbr_status, tile, agg);
+        if (t == 0) s_excl = e;
+    }
+    __syncthreads();
+    uint32_t run = s_excl;
+#pragma unroll
+    for (int j = 0; j < kScanItems; j++) {
+        uint32_t tot;
+        const uint32_t e = block_exclusive_scan<uint32_t>(f[j], s_red, &tot);
+        const uint32_t g = base + j * kBlock + t;
+        if (g < ng) P.nbr_bstart[g] = run + e;
+        run += tot;
+    }
+}
+
+// Backward entries: every forward pair (g, G) puts g into G's list.
+__global__ __launch_bounds__(kBlock) void k_nbr_back(Plan P)
+{
+    if (P.ctr->nbr_overflow) return;                     // lists unused
+    const uint32_t l = lane_id();
+    const uint32_t ng = ld_agent32(&P.ctr->n_groups);
+    const WaveRange hca_wr_ = wave_range();
+    HCA_FOR_UNITS(g, ng) {
+        const uint32_t s0 = P.nbr_start[g], c = P.nbr_count[g];
+        for (uint32_t k = l; k < c; k += kWave) {
+            const uint32_t G = P.nbr[s0 + k];
+            const uint32_t pos = atomicAdd(P.nbr_bcursor + G, 1u);
+            P.nbr_back[P.nbr_bstart[G] + pos] = g;
+        }
+    }
 }
 
 // Neighbour counts of the chunk points not yet flagged in `done`, over group
@@ -610,8 +787,8 @@ __global__ __launch_bounds__(kBlock) void k_core_chunks(Plan P)
     const Geo<D> geo = call_geo<D>(P);
     const uint32_t all = (1u << kPch) - 1u;
     uint32_t lt = 0;
-    const WaveRange hca_wr_ = wave_range();
-    HCA_FOR_UNITS(u, (n + kPch - 1) / kPch) {
+    const DynRange dr_ = dyn_range(P.ctr->dyn[kDynCore]);
+    HCA_FOR_UNITS_DYN(u, (n + kPch - 1) / kPch, dr_) {
         const uint32_t pc = u * kPch, np = min((uint32_t)kPch, n - pc);
         // lane k < np: cube, group and density of point pc + k
         uint32_t cell = kNone, grp = kNone;
@@ -784,10 +961,12 @@ __global__ __launch_bounds__(kBlock) void k_merge_rep(Plan P)
         const uint64_t gkey = P.group_key[A];
         const int64_t eps2 = cube_geo<D>(P, gkey).eps2;
         const NbrSrc src = nbr_source(P, A);
-        for (uint32_t oc = 1; oc < src.slots; oc += kWave) {
+        // cubes B > A: the forward list, or the whole stencil
+        const uint32_t slots = src.lists ? 1 + src.fcount : src.slots;
+        for (uint32_t oc = 1; oc < slots; oc += kWave) {
             const uint32_t j = oc + l;
             uint32_t B = kNone, dfw = 0, dbw = 0;
-            if (j < src.slots) {
+            if (j < slots) {
                 if (src.lists) {
                     B = P.nbr[src.start + j - 1];
                     if (B > A && P.n_dir) rep_directions<D>(P, gkey, P.group_key[B], &dfw, &dbw);
@@ -1208,8 +1387,8 @@ __global__ __launch_bounds__(kBlock) void k_merge_inter(Plan P)
     const uint32_t cap = pair_tile_cap(P);
     uint32_t lt = 0;
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
-    const WaveRange hca_wr_ = wave_range();
-    HCA_FOR_UNITS(GA, ng) {
+    const DynRange dr_ = dyn_range(P.ctr->dyn[kDynMerge]);
+    HCA_FOR_UNITS_DYN(GA, ng, dr_) {
         const uint32_t ga = P.gcube[GA];
         if (ga == kNone) continue;                                 // no core point
         const bool ua = P.unified[GA];
@@ -1230,11 +1409,13 @@ __global__ __launch_bounds__(kBlock) void k_merge_inter(Plan P)
 #pragma unroll
         for (int e = 0; e < D; e++) { qb.lo[e] = wave_min(qb.lo[e]); qb.hi[e] = wave_max(qb.hi[e]); }
         const NbrSrc src = nbr_source(P, GA);
-        for (uint32_t oc = 1; oc < src.slots; oc += kWave) {
+        // groups GB > GA: the forward list, or the whole stencil
+        const uint32_t slots = src.lists ? 1 + src.fcount : src.slots;
+        for (uint32_t oc = 1; oc < slots; oc += kWave) {
             const uint32_t j = oc + l;
             uint32_t GB = kNone, tiles = 0, ntb = 1;
             bool both = false;
-            if (j < src.slots) {
+            if (j < slots) {
                 uint64_t nk = ~0ull;
                 if (src.lists) {
                     const uint32_t G = P.nbr[src.start + j - 1];
@@ -1472,8 +1653,8 @@ __global__ __launch_bounds__(kBlock) void k_border(Plan P)
     const uint32_t w = wave_in_block(), l = lane_id();
     uint32_t lt = 0;
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
-    const WaveRange hca_wr_ = wave_range();
-    HCA_FOR_UNITS(g, ng) {
+    const DynRange dr_ = dyn_range(P.ctr->dyn[kDynBorder]);
+    HCA_FOR_UNITS_DYN(g, ng, dr_) {
         const uint32_t p0 = P.group_start[g], p1 = P.group_start[g + 1];
         const uint64_t gkey = P.group_key[g];
         if (P.m == 1 && P.ncore[g] == p1 - p0) continue;     // a cube of core points only
@@ -1509,8 +1690,8 @@ __global__ __launch_bounds__(kBlock) void k_border_chunks(Plan P)
     const uint32_t n = P.n;
     const Geo<D> geo = call_geo<D>(P);
     uint32_t lt = 0;
-    const WaveRange hca_wr_ = wave_range();
-    HCA_FOR_UNITS(u, (n + kPch - 1) / kPch) {
+    const DynRange dr_ = dyn_range(P.ctr->dyn[kDynBorder]);
+    HCA_FOR_UNITS_DYN(u, (n + kPch - 1) / kPch, dr_) {
         const uint32_t pc = u * kPch, np = min((uint32_t)kPch, n - pc);
         const bool mine = l < np && !P.core[pc + l];
         const uint32_t todo = (uint32_t)__ballot(mine) & ((1u << kPch) - 1u);
@@ -1697,15 +1878,18 @@ void launch_lists(const Plan &P, int blocks, hipStream_t s)
 {
     if (!P.nbr_cap) return;
     switch (P.d) {
-    case 1: hipLaunchKernelGGL(k_nbr_lists<1>, dim3(blocks), dim3(kBlock), 0, s, P); break;
-    case 2: hipLaunchKernelGGL(k_nbr_lists<2>, dim3(blocks), dim3(kBlock), 0, s, P); break;
-    case 3: hipLaunchKernelGGL(k_nbr_lists<3>, dim3(blocks), dim3(kBlock), 0, s, P); break;
-    case 4: hipLaunchKernelGGL(k_nbr_lists<4>, dim3(blocks), dim3(kBlock), 0, s, P); break;
-    case 5: hipLaunchKernelGGL(k_nbr_lists<5>, dim3(blocks), dim3(kBlock), 0, s, P); break;
-    case 6: hipLaunchKernelGGL(k_nbr_lists<6>, dim3(blocks), dim3(kBlock), 0, s, P); break;
-    case 7: hipLaunchKernelGGL(k_nbr_lists<7>, dim3(blocks), dim3(kBlock), 0, s, P); break;
-    case 8: hipLaunchKernelGGL(k_nbr_lists<8>, dim3(blocks), dim3(kBlock), 0, s, P); break;
+#define HCA_LISTS_D(DD)                                                                        \
+    case DD:                                                                                   \
+        hipLaunchKernelGGL(k_group_box<DD>, dim3(blocks), dim3(kBlock), 0, s, P);             \
+        hipLaunchKernelGGL(k_nbr_lists<DD>, dim3(blocks), dim3(kBlock), 0, s, P);             \
+        break;
+        HCA_LISTS_D(1) HCA_LISTS_D(2) HCA_LISTS_D(3) HCA_LISTS_D(4)
+        HCA_LISTS_D(5) HCA_LISTS_D(6) HCA_LISTS_D(7) HCA_LISTS_D(8)
+#undef HCA_LISTS_D
     }
+    const uint32_t tiles = (P.n + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(k_nbr_bscan, dim3(tiles), dim3(kBlock), 0, s, P);
+    hipLaunchKernelGGL(k_nbr_back, dim3(blocks), dim3(kBlock), 0, s, P);
 }
 
 void launch_core(const Plan &P, int blocks, hipStream_t s)

@@ -48,14 +48,18 @@ struct Counters {
     uint32_t tile_ticket;
     uint32_t nbr_overflow;      // groups whose neighbour list did not fit
     uint32_t hmask;             // hash slots in use - 1 (a power of two - 1)
-    uint32_t pad[9];
+    uint32_t nbr_ticket;        // tiles of the backward-list scan
+    uint32_t pad[8];
     uint32_t work_count[kWorkRegions * kCounterStride];   // region r at [r * kCounterStride]
     // pair tests executed, per phase (core, merge, border), spread over
     // kWorkRegions lines of eight 64-bit words; counted only on request
     unsigned long long tests[4][kWorkRegions * 8];
+    // work queues of the dynamically balanced kernels: [kernel][64 queues]
+    uint32_t dyn[4][kWorkRegions * kCounterStride];
 };
 
 enum { kTestsCore = 0, kTestsMerge = 1, kTestsBorder = 2, kTestsIntra = 3 };
+enum { kDynLists = 0, kDynCore = 1, kDynBorder = 2, kDynMerge = 3 };
 
 // One data set of a batch: its exact eps^2, minPts, cube side and origin,
 // where its rows sit, and (filled on the device) the clusters of the data
@@ -129,11 +133,20 @@ struct Plan {
     // excluded) that can hold a point within eps of one of its points.  Each
     // wave fills its own slab of nbr_cap / waves entries; a group whose list
     // does not fit gets nbr_count = kNone and is searched over the stencil.
+    // The lookups find each pair once, from the smaller key ("forward"); the
+    // pair is kept when the two groups' point boxes come within eps, and the
+    // reverse entries ("backward") are filled in afterwards.
     uint32_t nbr_cap;
     uint32_t list_w;            // offsets per axis walked by the list build: 2R + 1
-    uint32_t *nbr_count;        // [n]
+    uint32_t *nbr_count;        // [n] forward entries
     uint32_t *nbr_start;        // [n]
-    uint32_t *nbr;              // [nbr_cap]
+    uint32_t *nbr;              // [nbr_cap] forward entries in per-wave slabs
+    uint32_t *nbr_bcount;       // [n] backward entries
+    uint32_t *nbr_bstart;       // [n]
+    uint32_t *nbr_bcursor;      // [n]
+    uint32_t *nbr_back;         // [nbr_cap]
+    uint64_t *nbr_status;       // look-back words of the backward-list scan
+    int32_t *gbox;              // [n][2][d] point box of every group
     uint32_t *group_of;         // [n] cube -> its group
     // batches (nseg > 0): the data set of a cube is key >> seg_shift; its
     // parameters replace eps2, min_pts, side and origin (search groups of one
