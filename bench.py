@@ -120,6 +120,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="2d")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--merge", choices=("exact", "representatives"), default="exact",
+                    help="representatives: the paper's merge test on cube representatives alone "
+                         "(approximate; cubes as search groups only)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU form of "
@@ -142,6 +145,11 @@ def main() -> int:
     ctx = hca.Context(0)
     stream = torch.cuda.current_stream(dev)
     ctx.set_stream(stream.cuda_stream)
+    approx = None
+    if args.merge == "representatives":
+        exact_labels = ctx.cluster(pts, w.eps, w.min_pts).cpu().numpy()
+        ctx.set_exact(False)
+        approx = disagreement(exact_labels, ctx.cluster(pts, w.eps, w.min_pts).cpu().numpy())
 
     for _ in range(args.warmup):
         ctx.cluster(pts, w.eps, w.min_pts, out=labels)
@@ -218,17 +226,39 @@ def main() -> int:
         "dtype": "i32",
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "d": w.d, "eps": w.eps, "min_pts": w.min_pts,
-                   "fixed_point_bits": w.q, "parallelism": "single-gpu"},
+                   "fixed_point_bits": w.q, "parallelism": "single-gpu", "merge": args.merge},
         "roofline": roofline,
         "roofline_binning_sort": hbm_roofline("sort", phase_ms["sort"]),
         "phase_ms": {p: round(v, 4) for p, v in phase_ms.items() if v > 0},
         "stats": stats,
     }
-    if not args.no_cpu_baseline:
+    if approx is not None:
+        line["approximate"] = approx
+    if not args.no_cpu_baseline and approx is None:
         line["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(line), flush=True)
     ctx.close()
     return 0
+
+
+def disagreement(exact, approx) -> dict:
+    """How far labels from the representative-only merge are from exact DBSCAN.
+    Core points and noise are the same in both, and a representative-only merge
+    implies an exact one, so each exact cluster falls apart into fragments; a
+    point disagrees when it lies outside the largest fragment of its cluster."""
+    import numpy as np
+    noise_diff = int(np.count_nonzero((exact < 0) != (approx < 0)))
+    m = (exact >= 0) & (approx >= 0)
+    e, a = exact[m].astype(np.int64), approx[m].astype(np.int64)
+    pair, cnt = np.unique(e * (int(a.max(initial=0)) + 1) + a, return_counts=True)
+    owner = pair // (int(a.max(initial=0)) + 1)
+    best = np.zeros(int(e.max(initial=-1)) + 1, np.int64)
+    np.maximum.at(best, owner, cnt)
+    frags = np.bincount(owner, minlength=best.size)
+    differ = int(m.sum() - best.sum()) + noise_diff
+    return {"points_differing": differ, "fraction": differ / max(1, exact.size),
+            "clusters_exact": int(best.size), "clusters_approx": int(np.unique(a).size),
+            "exact_clusters_split": int(np.count_nonzero(frags > 1)), "noise_differing": noise_diff}
 
 
 def bench_batch(args) -> int:

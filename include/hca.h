@@ -215,6 +215,19 @@ hca_status hca_server_drain(hca_server *srv);
 void hca_server_destroy(hca_server *srv);
 double hca_clock(void);
 
+/* Merge rule of later hca_cluster / hca_cluster_ex / hca_cluster_host calls
+ * on this context.  exact = 1 (default): exact DBSCAN; facing representatives
+ * are only a fast accept and a miss falls back to exact pair tests.
+ * exact = 0: the paper's merge as printed (Depth First Search paragraph,
+ * Algorithm 3): neighbouring core cubes merge only when their facing
+ * representatives (Algorithm 2) are within eps, which can split a DBSCAN
+ * cluster; the result is approximate.  It needs cubes as search groups and
+ * d <= 4 (else those calls return HCA_E_INVAL), and it matches the paper's
+ * method exactly while d * side^2 < 2^32 (representative scores are 32-bit).
+ * Batches and the server always merge exactly.  HCA_E_INVAL for other values
+ * or a NULL context. */
+hca_status hca_set_exact(hca_ctx *ctx, int32_t exact);
+
 /* Phases of one call, in launch order, for hca_set_profiling / hca_phase_times:
  * origin shift (bounding box); cube keys and their radix sort with the gather
  * of points into cube order (methodology, pre-processing sort); cube and group

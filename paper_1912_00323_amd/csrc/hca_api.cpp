@@ -252,6 +252,7 @@ struct hca_ctx {
     bool geo_reps = true;
     Geometry geo;
     std::string err;
+    bool exact = true;                // false: merge on representatives alone
     // phase timing with HIP events on the context's stream
     int32_t prof = -1;                // -1 off, -2 every phase, k >= 0 phase k only
     hipEvent_t ev[2 * HCA_PHASES] = {};
@@ -646,6 +647,12 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
         P.off = (const int8_t *)gd;
         P.dir_fwd = (const uint16_t *)(gd + align256(G.off.size()));
         P.dir_bwd = (const uint16_t *)(gd + align256(G.off.size()) + align256((size_t)n_off * 2));
+    }
+    if (!ctx->exact) {
+        if (P.m != 1 || !P.n_dir)
+            return fail(ctx, HCA_E_INVAL, "merging on representatives alone needs cubes as search groups, d <= 4 "
+                                          "and representatives enabled");
+        P.rep_only = 1;
     }
     P.list_w = P.m == 1 ? cube_list_width(d, G.radius, n_off) : 0;
     Sizes Z;
@@ -1050,6 +1057,13 @@ hca_status hca_set_stream(hca_ctx *ctx, void *stream)
 {
     if (!ctx) return HCA_E_INVAL;
     ctx->stream = (hipStream_t)stream;
+    return HCA_OK;
+}
+
+hca_status hca_set_exact(hca_ctx *ctx, int32_t exact)
+{
+    if (!ctx || (exact != 0 && exact != 1)) return HCA_E_INVAL;
+    ctx->exact = exact != 0;
     return HCA_OK;
 }
 

@@ -986,7 +986,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_rep(Plan P)
                 joined = within<D, WIDE>(load_pt<D>(P.spts, qa), load_pt<D>(P.spts, qb), eps2);
                 if (joined) uf_union(P.parent, A, B);
             }
-            const bool exact = todo && !joined;
+            const bool exact = todo && !joined && !P.rep_only;
             const uint64_t m = __ballot(exact);
             if (m) {
                 // region of this wave; slots of region r are [r * cap, (r + 1) * cap)
@@ -1924,7 +1924,7 @@ void launch_merge(const Plan &P, int blocks, hipStream_t s)
 {
     if (P.m == 1) {
         HCA_DISPATCH_DW(k_merge_rep, P, blocks, s);
-        HCA_DISPATCH_DW(k_merge_exact, P, blocks, s);
+        if (!P.rep_only) HCA_DISPATCH_DW(k_merge_exact, P, blocks, s);
     } else {
         HCA_DISPATCH_DW(k_merge_inter, P, blocks, s);
         hipLaunchKernelGGL(k_flatten, dim3(1024), dim3(kBlock), 0, s, P);

@@ -136,6 +136,7 @@ struct Plan {
     // The lookups find each pair once, from the smaller key ("forward"); the
     // pair is kept when the two groups' point boxes come within eps, and the
     // reverse entries ("backward") are filled in afterwards.
+    uint32_t rep_only;          // merge on representatives alone (approximate)
     uint32_t nbr_cap;
     uint32_t list_w;            // offsets per axis walked by the list build: 2R + 1
     uint32_t *nbr_count;        // [n] forward entries

@@ -97,6 +97,8 @@ def load_library(path: str | Path | None = None) -> ctypes.CDLL:
     lib.hca_server_destroy.restype = None
     lib.hca_clock.argtypes = []
     lib.hca_clock.restype = dbl
+    lib.hca_set_exact.argtypes = [vp, i32]
+    lib.hca_set_exact.restype = ctypes.c_int
     lib.hca_set_profiling.argtypes = [vp, i32]
     lib.hca_set_profiling.restype = ctypes.c_int
     lib.hca_phase_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32]
@@ -211,6 +213,11 @@ class Context:
 
     def set_stream(self, stream_handle: int | None):
         self._check(self._lib.hca_set_stream(self._ctx, ctypes.c_void_p(stream_handle or 0)))
+
+    def set_exact(self, exact: bool):
+        """True (default): exact DBSCAN.  False: the paper's merge on facing
+        representatives alone (approximate; cubes as search groups, d <= 4)."""
+        self._check(self._lib.hca_set_exact(self._ctx, 1 if exact else 0))
 
     def set_profiling(self, phase: int | str | None):
         """Time later calls with HIP events: None = off, "all", or one phase."""

@@ -259,3 +259,39 @@ def test_repeatable(ctx):
     for _ in range(5):
         assert np.array_equal(gpu_labels(ctx, w.points, w.eps, w.min_pts), first)
     assert np.array_equal(first, oracle.dbscan(w.points, w.eps, w.min_pts))
+
+
+def test_representative_only_mode(ctx):
+    """The paper's merge as printed (facing representatives alone) against the
+    oracle's representative-only mode, including the fixture where it splits a
+    DBSCAN cluster; then back to exact."""
+    from paper_1912_00323_amd import hca
+    import torch
+    g = json.loads((GOLDEN / "representative_split.json").read_text())
+    ctx.set_exact(False)
+    try:
+        for case in g["cases"]:
+            pts = np.array(g["points"], np.int32)
+            got = gpu_labels(ctx, pts, case["eps"], case["min_pts"])
+            assert got.tolist() == case["rep_only_labels"]
+        for d in (2, 3, 4):
+            for seed in range(3):
+                rng = np.random.default_rng(300 + 10 * d + seed)
+                x = make_blobs(rng, 6000, d, 6, 0.04, 0.15)
+                pts = quantise(x, 12)
+                eps, mp = (0.03 + 0.01 * d) * 2 ** 12, 5
+                print(f"[case] representatives only d={d} seed={seed}", flush=True)
+                want = oracle.hca_grid(pts, eps, mp, rep_mode=1)
+                got = gpu_labels(ctx, pts, eps, mp)
+                assert np.array_equal(got, want), (d, seed)
+        w = make_config(2, n=200_000)
+        assert np.array_equal(gpu_labels(ctx, w.points, w.eps, w.min_pts),
+                              oracle.hca_grid(w.points, w.eps, w.min_pts, rep_mode=1))
+        with pytest.raises(hca.HcaError) as e:                 # d = 8: search groups, no representatives
+            w8 = make_config(3, n=2000)
+            ctx.cluster(torch.from_numpy(w8.points).cuda(), w8.eps, w8.min_pts)
+        assert e.value.status == hca.HCA_E_INVAL
+    finally:
+        ctx.set_exact(True)
+    pts = np.array(g["points"], np.int32)
+    assert gpu_labels(ctx, pts, 14.15, 1).tolist() == [0, 0, 0]

@@ -101,3 +101,23 @@ def test_no_cpu_fallback_in_binding():
     for f in (ROOT / "paper_1912_00323_amd" / "csrc").glob("*.*"):
         if f.is_file():
             assert "oracle" not in f.read_text(errors="ignore"), f
+
+
+def test_bench_disagreement_measure():
+    """The label-disagreement figure the bench reports for the approximate
+    merge: points outside the largest fragment of their exact cluster."""
+    import sys
+    sys.path.insert(0, str(Path(__file__).resolve().parents[1]))
+    import bench
+    e = np.array([0, 0, 0, 1, 1, -1, 2, 2, 3])
+    a = np.array([0, 0, 1, 2, 2, -1, 3, 4, 5])
+    r = bench.disagreement(e, a)
+    assert r["points_differing"] == 2 and r["exact_clusters_split"] == 2
+    assert r["clusters_exact"] == 4 and r["clusters_approx"] == 6 and r["noise_differing"] == 0
+    assert bench.disagreement(e, e)["points_differing"] == 0
+    # the fixture on which representatives alone split a cluster
+    g = json.loads((Path(__file__).parent / "golden" / "representative_split.json").read_text())
+    pts = np.array(g["points"], np.int32)
+    exact = oracle.dbscan(pts, 14.15, 1)
+    approx = oracle.hca_grid(pts, 14.15, 1, rep_mode=1)
+    assert bench.disagreement(exact, approx)["points_differing"] == 1
