@@ -215,6 +215,11 @@ def pin_sklearn(lib):
         _sklearn_check(pts, eps, mp, lib)
     w = make_config(1)
     _sklearn_check(w.points, w.eps, w.min_pts, lib)
+    # the paper's data sets reach 16, 27 and 54 dimensions (Table 1)
+    for d, n, k, std, eps, mp in [(16, 500, 5, 0.03, 0.16, 4), (27, 400, 4, 0.03, 0.2, 4),
+                                  (54, 300, 3, 0.02, 0.17, 3)]:
+        pts = quantise(make_blobs(np.random.default_rng(23), n, d, k, std, 0.1), 8)
+        _sklearn_check(pts, eps * 2 ** 8, mp, lib)
 
 
 def pin_scipy_min_pts_1(lib):
@@ -246,6 +251,12 @@ def pin_expand_cluster(lib):
         want = dbscan_expand(pts, rational_eps2(eps), mp)
         got = oracle.dbscan(pts, eps, mp, lib=lib)
         assert np.array_equal(got, want), (trial, d, n, eps, mp)
+    for trial, d in enumerate((12, 27, 54)):
+        pts = rand_points(rng, 60, d, 2, 0.2)
+        eps = float(rng.uniform(3.0, 9.0))
+        want = dbscan_expand(pts, rational_eps2(eps), 3)
+        got = oracle.dbscan(pts, eps, 3, lib=lib)
+        assert np.array_equal(got, want), (trial, d, eps)
 
 
 def pin_special_cases(lib):
@@ -285,6 +296,14 @@ def pin_invariances(lib):
         shift = rng.integers(-10_000, 10_000, size=d).astype(np.int32)
         assert np.array_equal(oracle.dbscan(pts + shift, eps, mp, lib=lib), base)
         assert np.array_equal(oracle.dbscan(pts * 4, eps * 4, mp, lib=lib), base)
+    # axes permuted and constant axes added change no distance
+    x = make_blobs(rng, 500, 6, 4, 0.04, 0.1)
+    pts = quantise(x, 8)
+    eps, mp = 0.07 * 2 ** 8, 4
+    base = oracle.dbscan(pts, eps, mp, lib=lib)
+    pad = np.concatenate([pts, np.full((500, 48), 77, np.int32)], axis=1)
+    perm = rng.permutation(54)
+    assert np.array_equal(oracle.dbscan(np.ascontiguousarray(pad[:, perm]), eps, mp, lib=lib), base)
 
 
 PINS = [pin_eps2_rational, pin_golden, pin_closed_form_1d, pin_sklearn, pin_scipy_min_pts_1,
@@ -388,7 +407,15 @@ def test_domain_errors():
     with pytest.raises(ValueError):
         oracle.dbscan(pts, 1.0, 1)
     with pytest.raises(ValueError):
-        oracle.dbscan(np.zeros((3, 9), np.int32), 1.0, 1)
+        oracle.dbscan(np.zeros((3, 65), np.int32), 1.0, 1)
+    # d > 8: the sum of squared spans must stay below 2^63
+    wide = np.zeros((2, 9), np.int32)
+    wide[1] = (1 << 30) - 1
+    with pytest.raises(ValueError):
+        oracle.dbscan(wide, 1.0, 1)
+    wide[1, :8] = (1 << 30) - 1
+    wide[1, 8] = 0
+    assert oracle.dbscan(wide, 1.0, 1).tolist() == [0, 1]
     with pytest.raises(ValueError):
         oracle.dbscan(np.zeros((3, 2), np.int32), 0.0, 1)
     with pytest.raises(ValueError):
