@@ -42,10 +42,11 @@ typedef struct hca_ctx hca_ctx;
 
 typedef enum {
     HCA_OK = 0,
-    HCA_E_INVAL = 1,   /* bad argument: NULL pointer, n < 0, n > 2^31-1, d not in [1,8],
+    HCA_E_INVAL = 1,   /* bad argument: NULL pointer, n < 0, n > 2^31-1, d not in [1,64],
                           eps not finite or <= 0, min_pts < 1 */
-    HCA_E_RANGE = 2,   /* a per-dimension coordinate span (max - min) >= 2^30, or the
-                          packed cube key needs more than 63 bits */
+    HCA_E_RANGE = 2,   /* a per-dimension coordinate span (max - min) >= 2^30, the
+                          packed cube key needs more than 63 bits (d <= 8), or the
+                          squared spans of all axes add up to 2^63 or more (d > 8) */
     HCA_E_NOMEM = 3,   /* device or pinned host allocation failed */
     HCA_E_DEVICE = 4   /* HIP runtime error (no device, launch or sync failure) */
 } hca_status;
@@ -64,6 +65,8 @@ typedef enum {
  *         over the stencil; >1 = groups of side >= sqrt(eps2), searched over
  *         the 3^d surrounding groups).
  * group_stencil: number of group offsets searched, self included.
+ * For d > 8: stencil and group_stencil are -1 (the groups span key axes that
+ * depend on the data; up to 3^8 group offsets are searched), reps is 0.
  * reps:   representative points per cube, 3^d - 1 ("Choosing Representative
  *         Points"), or 0 when they are not used (group > 1 or d > 4). */
 typedef struct {
@@ -124,7 +127,12 @@ const char *hca_last_error(const hca_ctx *ctx);
  * default stream.  The caller keeps ownership of the stream. */
 hca_status hca_set_stream(hca_ctx *ctx, void *stream);
 
-/* Cluster n points of dimension d.
+/* Cluster n points of dimension d, 1 <= d <= 64 (the paper's data sets reach
+ * 54 dimensions, Table 1).  For d > 8 the cube stencil is far too large to
+ * walk, so the neighbour search runs over groups of side >= eps along at most
+ * 8 key axes (those the data spans with the most groups), unbounded along the
+ * others; cubes over all axes still make points within eps of each other and
+ * stay the union-find nodes.  The result is the same exact DBSCAN.
  * points: DEVICE pointer to n*d int32, row-major [n][d], fixed-point units;
  *         read only, owned by the caller.  Aligned to 8 bytes for d = 2 and
  *         to 16 bytes for d = 4 or 8 (HCA_E_INVAL otherwise); the start of

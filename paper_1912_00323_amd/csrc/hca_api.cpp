@@ -226,7 +226,7 @@ bool plan_geometry(double eps, int d, Geometry *g, bool with_offsets)
     return true;
 }
 
-size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+constexpr size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 }  // namespace
 
@@ -397,13 +397,15 @@ void plan_sizes(Plan &P, uint32_t gbits, bool count_work, bool want_stats, Sizes
 void carve_ws(Carver &cv, Plan &P, SortBuffers &B, const Sizes &Z, uint32_t **zero_begin, size_t *zero_bytes)
 {
     const uint32_t n = P.n;
-    cv.take<int32_t>((size_t)kBboxBlocks * 2 * kMaxDim);
+    cv.take<int32_t>((size_t)kBboxBlocks * 2 * kMaxDimHigh);
+    if (P.hd) P.hd_origin = cv.take<int32_t>(kMaxDimHigh);
     const size_t ksz = Z.wide_keys ? 8 : 4;
     B.keys_a = cv.take<char>((size_t)n * ksz);
     B.keys_b = cv.take<char>((size_t)n * ksz);
     B.vals_a = cv.take<uint32_t>(n);
     B.vals_b = cv.take<uint32_t>(n);
-    P.spts = cv.take<int32_t>((size_t)n * P.d);
+    const size_t sd = std::max<uint32_t>(P.sd, (uint32_t)P.d);   // row stride of points and group boxes
+    P.spts = cv.take<int32_t>((size_t)n * sd);
     P.cell_of = cv.take<uint32_t>(n);
     P.cell_start = cv.take<uint32_t>((size_t)n + 1);
     P.group_start = cv.take<uint32_t>((size_t)n + 1);
@@ -425,7 +427,7 @@ void carve_ws(Carver &cv, Plan &P, SortBuffers &B, const Sizes &Z, uint32_t **ze
         P.nbr_bstart = cv.take<uint32_t>(n);
         P.nbr_bcursor = cv.take<uint32_t>(n);
         P.nbr_back = cv.take<uint32_t>(P.nbr_cap);
-        P.gbox = cv.take<int32_t>((size_t)n * 2 * P.d);
+        P.gbox = cv.take<int32_t>((size_t)n * 2 * sd);
     }
     P.work = cv.take<uint32_t>((size_t)2 * P.work_cap);
     P.owner = cv.take<uint32_t>(n);
@@ -527,13 +529,231 @@ void launch_sequence(hca_ctx *ctx, Plan &P, const Sizes &Z)
     mark(ctx, HCA_PHASE_LABELS, true);
 }
 
+// Counters of the call just finished (copied to the pinned buffer) into *stats.
+void fill_stats(hca_ctx *ctx, const Plan &P, hca_stats *stats)
+{
+    const Counters *hc = (const Counters *)ctx->pinned;
+    stats->n_cells = hc->n_cells;
+    stats->n_groups = hc->n_groups;
+    int64_t pairs = 0;
+    for (int r = 0; r < kWorkRegions; r++) pairs += hc->work_count[r * kCounterStride];
+    stats->exact_pairs = pairs;
+    stats->n_core_points = hc->n_core;
+    stats->n_noise = hc->n_noise;
+    stats->n_clusters = hc->n_clusters;
+    int64_t *const dst[4] = {&stats->tests_core, &stats->tests_merge, &stats->tests_border,
+                             &stats->tests_intra};
+    for (int ph = 0; ph < 4; ph++) {
+        int64_t t = 0;
+        for (int r = 0; r < kWorkRegions; r++) t += (int64_t)hc->tests[ph][r * 8];
+        *dst[ph] = t;
+    }
+        stats->key_bits = (int32_t)P.key_bits;
+        stats->sort_passes = (int32_t)P.passes;
+        stats->group = (int32_t)P.m;
+        stats->wide = P.wide;
+        stats->dense_table = (int32_t)P.dense;
+        stats->list_overflow = (int32_t)hc->nbr_overflow;
+}
+
+// ---- more than kMaxDim axes ----------------------------------------------------
+// Pinned staging: bounding-box partials and the counters of a call at 0, the
+// origin of every axis (uploaded for the kernels) after them.
+constexpr size_t kPinnedOrigin = align256(std::max(sizeof(int32_t) * kBboxBlocks * 2 * kMaxDimHigh,
+                                                   sizeof(Counters)));
+constexpr size_t kPinnedBytes = kPinnedOrigin + sizeof(int32_t) * kMaxDimHigh;
+constexpr uint64_t kHdListMax = 1ull << 30;   // neighbour-list entries, at most
+
+// Init, sort, cube and group tables, lookup and neighbour lists; the host
+// then checks that every list fit before the rest runs.
+void launch_hd_first(hca_ctx *ctx, Plan &P, const Sizes &Z)
+{
+    hipStream_t s = ctx->stream;
+    SortBuffers B;
+    std::memset(&B, 0, sizeof B);
+    uint32_t *zbeg;
+    size_t zbytes;
+    Carver cv{(char *)ctx->ws};
+    carve_ws(cv, P, B, Z, &zbeg, &zbytes);
+    B.tickets = P.ctr->sort_tickets;
+    launch_init(zbeg, zbytes / sizeof(uint32_t), P.dense ? P.table : nullptr, P.dense ? (1ull << Z.gbits) : 0, s);
+    (void)hipMemcpyAsync((void *)P.hd_origin, (char *)ctx->pinned + kPinnedOrigin, sizeof(int32_t) * P.d,
+                         hipMemcpyHostToDevice, s);
+    mark(ctx, HCA_PHASE_SORT, false);
+    launch_sort_hd(P, B, s);
+    mark(ctx, HCA_PHASE_SORT, true);
+    P.skeys = B.result_keys;
+    mark(ctx, HCA_PHASE_CELLS, false);
+    launch_cells(P, true, P.scan_status, P.ctr->scan_tickets + 0, s);
+    launch_table(P, Z.tb, s);
+    mark(ctx, HCA_PHASE_CELLS, true);
+    mark(ctx, HCA_PHASE_LISTS, false);
+    launch_hd_lists(P, Z.wb, s);
+    mark(ctx, HCA_PHASE_LISTS, true);
+}
+
+// Core points, merging, border points, labels.
+void launch_hd_rest(hca_ctx *ctx, Plan &P, const Sizes &Z)
+{
+    hipStream_t s = ctx->stream;
+    mark(ctx, HCA_PHASE_CORE, false);
+    launch_hd_core(P, Z.wb, s);
+    mark(ctx, HCA_PHASE_CORE, true);
+    mark(ctx, HCA_PHASE_MERGE, false);
+    launch_hd_merge(P, Z.wb, s);
+    launch_compress(P, Z.tb, s);
+    mark(ctx, HCA_PHASE_MERGE, true);
+    mark(ctx, HCA_PHASE_BORDER, false);
+    launch_hd_border(P, Z.wb, s);
+    mark(ctx, HCA_PHASE_BORDER, true);
+    mark(ctx, HCA_PHASE_LABELS, false);
+    launch_labels(P, P.scan_status + Z.scan_tiles + 32, P.ctr->scan_tickets + 1, s);
+    mark(ctx, HCA_PHASE_LABELS, true);
+}
+
+// A call with d in (kMaxDim, kMaxDimHigh]: search groups of side >= eps over
+// at most kMaxDim key axes (the axes with the most groups), cubes told apart
+// by a hash of their bands over all axes.
+hca_status run_hd(hca_ctx *ctx, const int32_t *points, uint32_t n, int32_t d, double eps, int32_t min_pts,
+                  int32_t *labels, uint8_t *core_out, hca_stats *stats)
+{
+    if (!ctx->exact)
+        return fail(ctx, HCA_E_INVAL, "merging on representatives alone needs cubes as search groups, d <= 4 "
+                                      "and representatives enabled");
+    hipStream_t s = ctx->stream;
+    HCA_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    int64_t eps2;
+    exact_eps2(eps, &eps2);
+
+    // 1. bounding box
+    const uint32_t rpb = (uint32_t)(kBlock / d);
+    const int bb = (int)std::min<uint64_t>(kBboxBlocks, (n + rpb - 1) / rpb);
+    Carver c0{nullptr};
+    c0.take<int32_t>((size_t)kBboxBlocks * 2 * kMaxDimHigh);
+    hca_status st = ensure(ctx, &ctx->ws, &ctx->ws_size, c0.off, "workspace");
+    if (st) return st;
+    st = ensure_pinned(ctx, kPinnedBytes);
+    if (st) return st;
+    int32_t *partial = (int32_t *)ctx->ws;
+    for (bool &u : ctx->ev_used) u = false;
+    mark(ctx, HCA_PHASE_BBOX, false);
+    launch_bbox_hd(d, points, n, partial, bb, s);
+    mark(ctx, HCA_PHASE_BBOX, true);
+    HCA_HIP(hipGetLastError(), "bbox launch");
+    HCA_HIP(hipMemcpyAsync(ctx->pinned, partial, (size_t)bb * 2 * d * sizeof(int32_t), hipMemcpyDeviceToHost, s),
+            "bbox copy");
+    HCA_HIP(hipStreamSynchronize(s), "bbox sync");
+    const int32_t *hp = (const int32_t *)ctx->pinned;
+    int64_t mn[kMaxDimHigh], mx[kMaxDimHigh];
+    unsigned __int128 reach = 0;
+    for (int k = 0; k < d; k++) {
+        mn[k] = INT64_MAX;
+        mx[k] = INT64_MIN;
+        for (int b = 0; b < bb; b++) {
+            mn[k] = std::min<int64_t>(mn[k], hp[b * 2 * d + k]);
+            mx[k] = std::max<int64_t>(mx[k], hp[b * 2 * d + d + k]);
+        }
+        if (mx[k] - mn[k] >= (1ll << 30)) return fail(ctx, HCA_E_RANGE, "coordinate span >= 2^30 along an axis");
+        reach += (unsigned __int128)(mx[k] - mn[k]) * (uint64_t)(mx[k] - mn[k]);
+    }
+    if (reach > (unsigned __int128)INT64_MAX)
+        return fail(ctx, HCA_E_RANGE, "the squared spans of the axes add up to 2^63 or more");
+    int32_t *org = (int32_t *)((char *)ctx->pinned + kPinnedOrigin);
+    for (int k = 0; k < d; k++) org[k] = (int32_t)mn[k];
+
+    // 2. cube side, group side and key axes
+    Plan P;
+    std::memset(&P, 0, sizeof P);
+    P.n = n;
+    P.d = d;
+    P.min_pts = min_pts;
+    P.eps2 = eps2;
+    P.hd = 1;
+    P.sd = ((uint32_t)d + 3u) & ~3u;
+    const uint64_t side = std::max<uint64_t>(1, isqrt_u64((uint64_t)eps2 / (uint64_t)d));
+    const uint64_t E = isqrt_u64((uint64_t)eps2);
+    const uint64_t m = std::max<uint64_t>(1, (E + side - 1) / side);
+    P.side = (uint32_t)side;                         // <= sqrt(2^63 / 9) < 2^31
+    P.m = (uint32_t)m;
+    P.gside = (int64_t)(m * side);
+    std::vector<int> axes(d);
+    std::vector<uint64_t> gmax(d);
+    for (int k = 0; k < d; k++) {
+        axes[k] = k;
+        gmax[k] = (uint64_t)(mx[k] - mn[k]) / (uint64_t)P.gside;
+    }
+    std::stable_sort(axes.begin(), axes.end(), [&](int a, int b) { return gmax[a] > gmax[b]; });
+    uint32_t gbits = 0, kd = 0;
+    for (int a : axes) {
+        const uint32_t w = bit_length(gmax[a]);
+        if (kd == (uint32_t)kMaxDim || w == 0 || gbits + w > 47) break;
+        P.kdim[kd++] = (uint8_t)a;
+        gbits += w;
+    }
+    if (kd == 0) P.kdim[kd++] = (uint8_t)axes[0];    // every point in one group
+    P.kd = kd;
+    gbits = 0;
+    for (int e = (int)kd - 1; e >= 0; e--) {          // key position 0 most significant
+        const int a = P.kdim[e];
+        P.origin[e] = (int32_t)mn[a];
+        P.gmax[e] = (uint32_t)gmax[a];
+        P.gw[e] = bit_length(gmax[a]);
+        P.goff[e] = gbits;
+        gbits += P.gw[e];
+    }
+    P.key_bits = std::min<uint32_t>(63, (gbits + 16 + 7) / 8 * 8);
+    // HCA_HASH_BITS: fewer cube-hash bits, so that cubes share keys (a test
+    // of the split after the sort); the result does not change
+    if (const char *e = std::getenv("HCA_HASH_BITS"))
+        P.key_bits = gbits + (uint32_t)std::min<int>(std::max(1, std::atoi(e)), 63 - (int)gbits);
+    P.fine_bits = P.key_bits - gbits;                 // hash bits
+    P.passes = (P.key_bits + kRadixBits - 1) / kRadixBits;
+    P.wide = reach >= ((unsigned __int128)1 << 31) ? 1 : 0;
+    P.list_w = 3;
+    Sizes Z;
+    plan_sizes(P, gbits, stats != nullptr && ctx->prof != -1, stats != nullptr, &Z);
+    Z.wide_keys = true;
+    const uint64_t waves = (uint64_t)Z.wb * (kBlock / kWave);
+    P.nbr_cap = (uint32_t)std::max<uint64_t>(P.nbr_cap, waves);
+    P.pts = points;
+    P.labels = labels;
+    P.core_out = core_out;
+
+    // 3. the launch sequence; lists that did not fit: again with 4x the room
+    while (true) {
+        st = ensure(ctx, &ctx->ws, &ctx->ws_size, ws_bytes(P, Z), "workspace");
+        if (st) return st;
+        launch_hd_first(ctx, P, Z);
+        HCA_HIP(hipGetLastError(), "kernel launch");
+        HCA_HIP(hipMemcpyAsync(ctx->pinned, &P.ctr->nbr_overflow, sizeof(uint32_t), hipMemcpyDeviceToHost, s),
+                "list check");
+        HCA_HIP(hipStreamSynchronize(s), "list sync");
+        if (*(const uint32_t *)ctx->pinned == 0) break;
+        if (P.nbr_cap >= kHdListMax)
+            return fail(ctx, HCA_E_NOMEM, "neighbour lists need more than 2^30 entries");
+        P.nbr_cap = (uint32_t)std::min<uint64_t>(4ull * P.nbr_cap, kHdListMax);
+    }
+    launch_hd_rest(ctx, P, Z);
+    HCA_HIP(hipGetLastError(), "kernel launch");
+    if (stats)
+        HCA_HIP(hipMemcpyAsync((char *)ctx->pinned, P.ctr, sizeof(Counters), hipMemcpyDeviceToHost, s),
+                "stats copy");
+    HCA_HIP(hipStreamSynchronize(s), "clustering sync");
+    for (int ph = 0; ph < HCA_PHASES; ph++) {
+        ctx->phase_ms[ph] = 0.f;
+        if (ctx->ev_used[ph]) (void)hipEventElapsedTime(&ctx->phase_ms[ph], ctx->ev[2 * ph], ctx->ev[2 * ph + 1]);
+    }
+    if (stats) fill_stats(ctx, P, stats);
+    return HCA_OK;
+}
+
 hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, double eps,
                int32_t min_pts, int32_t *labels, uint8_t *core_out, hca_stats *stats)
 {
     if (!ctx) return HCA_E_INVAL;
     ctx->err.clear();
     if (n64 < 0 || n64 > INT32_MAX) return fail(ctx, HCA_E_INVAL, "n must be in [0, 2^31 - 1]");
-    if (d < 1 || d > kMaxDim) return fail(ctx, HCA_E_INVAL, "d must be in [1, 8]");
+    if (d < 1 || d > kMaxDimHigh) return fail(ctx, HCA_E_INVAL, "d must be in [1, 64]");
     if (!(eps > 0.0) || !std::isfinite(eps)) return fail(ctx, HCA_E_INVAL, "eps must be finite and > 0");
     if (min_pts < 1) return fail(ctx, HCA_E_INVAL, "min_pts must be >= 1");
     if (n64 > 0 && (!points || !labels)) return fail(ctx, HCA_E_INVAL, "points and labels must not be NULL");
@@ -545,6 +765,7 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
     }
     if (stats) std::memset(stats, 0, sizeof *stats);
     if (n64 == 0) return HCA_OK;
+    if (d > kMaxDim) return run_hd(ctx, points, (uint32_t)n64, d, eps, min_pts, labels, core_out, stats);
     const uint32_t n = (uint32_t)n64;
     hipStream_t s = ctx->stream;
     HCA_HIP(hipSetDevice(ctx->device), "hipSetDevice");
@@ -581,10 +802,10 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
     // 1. bounding box (origin shift); the host reduces the per-block partials
     const int bb = (int)std::min<uint64_t>(kBboxBlocks, (n + kBlock - 1) / kBlock);
     Carver c0{nullptr};
-    c0.take<int32_t>((size_t)kBboxBlocks * 2 * kMaxDim);
+    c0.take<int32_t>((size_t)kBboxBlocks * 2 * kMaxDimHigh);
     hca_status st = ensure(ctx, &ctx->ws, &ctx->ws_size, c0.off, "workspace");
     if (st) return st;
-    st = ensure_pinned(ctx, (size_t)kBboxBlocks * 2 * kMaxDim * sizeof(int32_t) + sizeof(Counters));
+    st = ensure_pinned(ctx, kPinnedBytes);
     if (st) return st;
     int32_t *partial = (int32_t *)ctx->ws;
     for (bool &u : ctx->ev_used) u = false;
@@ -621,6 +842,7 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
     P.gside = G.gside;
     P.bm = bit_length(G.m - 1);
     P.fine_bits = P.bm * d;
+    P.sd = (uint32_t)d;
     uint32_t gbits = 0;
     int64_t span_max = 0;
     for (int k = d - 1; k >= 0; k--) {
@@ -673,30 +895,7 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
         ctx->phase_ms[ph] = 0.f;
         if (ctx->ev_used[ph]) (void)hipEventElapsedTime(&ctx->phase_ms[ph], ctx->ev[2 * ph], ctx->ev[2 * ph + 1]);
     }
-    if (stats) {
-        const Counters *hc = (const Counters *)ctx->pinned;
-        stats->n_cells = hc->n_cells;
-        stats->n_groups = hc->n_groups;
-        int64_t pairs = 0;
-        for (int r = 0; r < kWorkRegions; r++) pairs += hc->work_count[r * kCounterStride];
-        stats->exact_pairs = pairs;
-        stats->n_core_points = hc->n_core;
-        stats->n_noise = hc->n_noise;
-        stats->n_clusters = hc->n_clusters;
-        int64_t *const dst[4] = {&stats->tests_core, &stats->tests_merge, &stats->tests_border,
-                                 &stats->tests_intra};
-        for (int ph = 0; ph < 4; ph++) {
-            int64_t t = 0;
-            for (int r = 0; r < kWorkRegions; r++) t += (int64_t)hc->tests[ph][r * 8];
-            *dst[ph] = t;
-        }
-        stats->key_bits = (int32_t)P.key_bits;
-        stats->sort_passes = (int32_t)P.passes;
-        stats->group = (int32_t)P.m;
-        stats->wide = P.wide;
-        stats->dense_table = (int32_t)P.dense;
-        stats->list_overflow = (int32_t)hc->nbr_overflow;
-    }
+    if (stats) fill_stats(ctx, P, stats);
     return HCA_OK;
 }
 
@@ -909,6 +1108,7 @@ hca_status run_sets(hca_ctx *ctx, const BatchSet *sets, int32_t nseg)
         std::memset(&P, 0, sizeof P);
         P.n = g.n;
         P.d = d;
+        P.sd = (uint32_t)d;
         P.m = 1;
         P.side = 1;
         P.gside = 1;
@@ -1006,7 +1206,22 @@ hca_status hca_exact_eps2(double eps, int64_t *eps2)
 
 hca_status hca_get_geometry(double eps, int32_t d, hca_geometry *out)
 {
-    if (!out || d < 1 || d > kMaxDim) return HCA_E_INVAL;
+    if (!out || d < 1 || d > kMaxDimHigh) return HCA_E_INVAL;
+    if (d > kMaxDim) {
+        // groups of side >= sqrt(eps2) over key axes that depend on the data
+        int64_t eps2;
+        if (!exact_eps2(eps, &eps2)) return HCA_E_INVAL;
+        std::memset(out, 0, sizeof *out);
+        const uint64_t side = std::max<uint64_t>(1, isqrt_u64((uint64_t)eps2 / (uint64_t)d));
+        const uint64_t E = isqrt_u64((uint64_t)eps2);
+        out->eps2 = eps2;
+        out->side = (int64_t)side;
+        out->radius = offset_radius((int64_t)side, eps2);
+        out->group = (int32_t)std::max<uint64_t>(1, (E + side - 1) / side);
+        out->stencil = -1;
+        out->group_stencil = -1;
+        return HCA_OK;
+    }
     Geometry g;
     if (!plan_geometry(eps, d, &g, true)) return HCA_E_INVAL;
     std::memset(out, 0, sizeof *out);
@@ -1116,8 +1331,8 @@ hca_status hca_cluster_host(hca_ctx *ctx, const int32_t *points, int64_t n, int3
                             int32_t min_pts, int32_t *labels)
 {
     if (!ctx) return HCA_E_INVAL;
-    if (n < 0 || n > INT32_MAX || d < 1 || d > kMaxDim)
-        return fail(ctx, HCA_E_INVAL, "n must be in [0, 2^31 - 1] and d in [1, 8]");
+    if (n < 0 || n > INT32_MAX || d < 1 || d > kMaxDimHigh)
+        return fail(ctx, HCA_E_INVAL, "n must be in [0, 2^31 - 1] and d in [1, 64]");
     if (n > 0 && (!points || !labels)) return fail(ctx, HCA_E_INVAL, "points and labels must not be NULL");
     if (n == 0) return run(ctx, nullptr, 0, d, eps, min_pts, nullptr, nullptr, nullptr);
     const size_t pbytes = align256((size_t)n * d * sizeof(int32_t));

@@ -458,4 +458,103 @@ __device__ __forceinline__ uint64_t scan_lookback(uint64_t *status, uint32_t til
     return excl;
 }
 
+
+// ---- shared by the neighbour phases ------------------------------------------
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kPch = 8;           // points of the own group handled per sweep
+
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int32_t uniform_i(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Sort the n <= 128 gap sums of one half ascending (ties by index) into
+// s_sum / s_idx: a bitonic network over the next power of two of n, two
+// elements per lane (element i in lane i % 64, slot i / 64), partners one
+// lane-xor apart; padding elements sort last.
+__device__ __forceinline__ bool sum_less(int64_t a, uint32_t ia, int64_t b, uint32_t ib)
+{
+    return a < b || (a == b && ia < ib);
+}
+
+__device__ __forceinline__ void bitonic_sort(const int64_t *s_in, int n, int64_t *s_sum, uint8_t *s_idx)
+{
+    const uint32_t l = lane_id();
+    int n2 = 1;
+    while (n2 < n) n2 <<= 1;
+    int64_t v[2];
+    uint32_t ix[2];
+#pragma unroll
+    for (int sl = 0; sl < 2; sl++) {
+        const uint32_t i = sl * kWave + l;
+        v[sl] = (int)i < n ? s_in[i] : INT64_MAX;
+        ix[sl] = i;
+    }
+    for (int k = 2; k <= n2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j == kWave) {                         // k = 128: the two slots of a lane, ascending
+                if (sum_less(v[1], ix[1], v[0], ix[0])) {
+                    const int64_t tv = v[0]; v[0] = v[1]; v[1] = tv;
+                    const uint32_t ti = ix[0]; ix[0] = ix[1]; ix[1] = ti;
+                }
+                continue;
+            }
+#pragma unroll
+            for (int sl = 0; sl < 2; sl++) {
+                if (sl * kWave >= n2) continue;
+                const int64_t y = __shfl_xor(v[sl], j);
+                const uint32_t iy = __shfl_xor(ix[sl], j);
+                const uint32_t i = sl * kWave + l;
+                const bool asc = (i & (uint32_t)k) == 0, lower = (l & (uint32_t)j) == 0;
+                const bool mine_less = sum_less(v[sl], ix[sl], y, iy);
+                if ((lower == asc) != mine_less) { v[sl] = y; ix[sl] = iy; }
+            }
+        }
+    }
+#pragma unroll
+    for (int sl = 0; sl < 2; sl++) {
+        const uint32_t r = sl * kWave + l;
+        if ((int)r < n) { s_sum[r] = v[sl]; s_idx[r] = (uint8_t)ix[sl]; }
+    }
+}
+
+// Reduce the per-lane bests over the wave; each point flagged in `todo`
+// takes the root of its nearest core point (kNone: noise) and, when it has
+// one, offers its input index to that cluster's smallest member.
+__device__ __forceinline__ void border_finish(const Plan &P, uint32_t pc, uint32_t todo, const int64_t *bd,
+                                              const uint32_t *bi, const uint32_t *bp)
+{
+    const uint32_t l = lane_id();
+#pragma unroll
+    for (int k = 0; k < kPch; k++) {
+        if (!(todo & (1u << k))) continue;
+        int64_t d0 = bd[k];
+        uint32_t i0 = bi[k], q0 = bp[k];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const int64_t d1 = __shfl_xor(d0, o);
+            const uint32_t i1 = __shfl_xor(i0, o), q1 = __shfl_xor(q0, o);
+            if (d1 < d0 || (d1 == d0 && i1 < i0)) { d0 = d1; i0 = i1; q0 = q1; }
+        }
+        if (l == 0) {
+            const uint32_t root = q0 == kNone ? kNone : ld_parent(P.parent + P.cell_of[q0]);
+            P.owner[pc + k] = root;
+            if (root != kNone) {
+                const uint32_t me = P.sidx[pc + k];
+                if (me < ld_agent32(P.minmem + root)) atomicMin(P.minmem + root, me);
+            }
+        }
+    }
+}
+
+// Lane of the chunk that holds candidate ci (ci < total): last l with s_pre[l] <= ci.
+__device__ __forceinline__ uint32_t candidate_lane(uint32_t ci, const uint32_t *s_pre)
+{
+    uint32_t lo = 0, hi = kWave;
+#pragma unroll
+    for (int it = 0; it < 6; it++) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (s_pre[mid] <= ci) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
 }  // namespace hca

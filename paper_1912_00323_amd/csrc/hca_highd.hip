@@ -1,0 +1,675 @@
+// Data with more than eight axes (the paper's data sets reach 54; Table 1).
+//
+// The cube of side eps/sqrt(d) stays the unit that holds points within eps of
+// each other (a cube with minPts points makes them all core, and a cube is
+// the union-find node), but its stencil grows like (2 ceil(sqrt(d)) + 1)^d, so
+// the neighbour search runs over search groups: boxes of side >= eps along at
+// most eight key axes (those with the most groups), unbounded along the
+// others.  Every point within eps of a point of group G lies in G or in a
+// group at an offset in {-1, 0, 1} along each key axis; the neighbour lists
+// keep the groups whose point boxes come within eps over all axes.
+//
+// Points are rows of sd int32 words (d padded with zeros to a multiple of 4),
+// in sorted order.  A wave takes chunks of 8 consecutive points, stages them
+// in LDS, and streams candidate rows through its lanes with 16-byte loads,
+// each lane testing its candidate against all 8 staged points at once.
+#include <algorithm>
+
+#include "hca_device.h"
+#include "hca_kernels.h"
+
+namespace hca {
+
+// ---------------------------------------------------------------------------
+// Point box of every group over all axes (lane e owns axis e), the backward
+// list counters cleared, and "no core cube yet" for every group.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_hd_group_box(Plan P)
+{
+    const uint32_t l = lane_id(), sd = P.sd;
+    const uint32_t ng = ld_agent32(&P.ctr->n_groups);
+    const WaveRange hca_wr_ = wave_range();
+    HCA_FOR_UNITS(g, ng) {
+        const uint32_t p0 = P.group_start[g], p1 = P.group_start[g + 1];
+        if (l < sd) {
+            int32_t lo = INT32_MAX, hi = INT32_MIN;
+            const int32_t *col = P.spts + l;
+            uint32_t q = p0;
+            for (; q + 4 <= p1; q += 4) {
+                const int32_t a = col[(uint64_t)q * sd], b = col[(uint64_t)(q + 1) * sd];
+                const int32_t c = col[(uint64_t)(q + 2) * sd], e = col[(uint64_t)(q + 3) * sd];
+                lo = min(lo, min(min(a, b), min(c, e)));
+                hi = max(hi, max(max(a, b), max(c, e)));
+            }
+            for (; q < p1; q++) {
+                const int32_t a = col[(uint64_t)q * sd];
+                lo = min(lo, a);
+                hi = max(hi, a);
+            }
+            P.gbox[(uint64_t)g * 2 * sd + l] = lo;
+            P.gbox[(uint64_t)g * 2 * sd + sd + l] = hi;
+        }
+        if (l == 0) {
+            st_agent32(P.nbr_bcount + g, 0u);
+            st_agent32(P.nbr_bcursor + g, 0u);
+            st_agent32(P.gcube + g, kNone);
+        }
+    }
+}
+
+// Squared gap between two point boxes (rows [lo: sd][hi: sd]); stops once it
+// exceeds eps2, so any value above eps2 only means "farther than eps".
+__device__ __forceinline__ int64_t hd_box_gap2(const int32_t *a, const int32_t *b, uint32_t sd, int64_t eps2)
+{
+    int64_t acc = 0;
+    for (uint32_t e = 0; e < sd && acc <= eps2; e++) {
+        const int64_t gap = max((int64_t)b[e] - a[sd + e], (int64_t)a[e] - b[sd + e]);
+        if (gap > 0) acc += gap * gap;
+    }
+    return acc;
+}
+
+// ---------------------------------------------------------------------------
+// Neighbour lists over the key axes.  As for search groups in up to eight
+// axes: the 3^kd offsets split into two halves of the key axes; the squared
+// gaps between the group's point box and the neighbour group's slab add over
+// axes, both halves are sorted, and for each first-half offset the valid
+// second-half ones form a prefix.  Only offsets to a larger key are looked up
+// (forward entries); a found group is kept when the two point boxes come
+// within eps over all axes, and its backward counter is raised.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t hd_axis_gap2(const Plan &P, uint64_t gkey, int e, int o, int32_t lo, int32_t hi)
+{
+    const int64_t c = (int64_t)((gkey >> P.goff[e]) & ((1ull << P.gw[e]) - 1ull)) + o;
+    if (c < 0 || c > (int64_t)P.gmax[e]) return -1;
+    const int64_t glo = (int64_t)P.origin[e] + c * P.gside, ghi = glo + P.gside - 1;
+    const int64_t gap = glo > hi ? glo - hi : (lo > ghi ? lo - ghi : 0);
+    return gap * gap;
+}
+
+template <int FIRST, int K, int KD>
+__device__ __forceinline__ int64_t hd_half_gap2(const Plan &P, uint64_t gkey, uint32_t idx, const int32_t *qlo,
+                                                const int32_t *qhi)
+{
+    int64_t acc = 0;
+#pragma unroll
+    for (int e = 0; e < K; e++) {
+        const int o = (int)(idx % 3u) - 1;
+        idx /= 3u;
+        const int64_t g2 = hd_axis_gap2(P, gkey, FIRST + e, o, qlo[FIRST + e], qhi[FIRST + e]);
+        if (g2 < 0) return INT64_MAX;
+        acc += g2;
+    }
+    return acc <= P.eps2 ? acc : INT64_MAX;
+}
+
+template <int FIRST, int K>
+__device__ __forceinline__ int64_t hd_half_key_delta(const Plan &P, uint32_t idx)
+{
+    int64_t kd = 0;
+#pragma unroll
+    for (int e = 0; e < K; e++) {
+        const int o = (int)(idx % 3u) - 1;
+        idx /= 3u;
+        kd += (int64_t)o * (int64_t)(1ull << P.goff[FIRST + e]);
+    }
+    return kd;
+}
+
+// Sign of the first non-zero component (the half's first axis most significant).
+template <int K>
+__device__ __forceinline__ int8_t hd_half_sign(uint32_t idx)
+{
+    int sg = 0;
+#pragma unroll
+    for (int e = 0; e < K; e++) {
+        const int o = (int)(idx % 3u) - 1;
+        idx /= 3u;
+        if (sg == 0) sg = o;
+    }
+    return (int8_t)(sg > 0 ? 1 : (sg < 0 ? -1 : 0));
+}
+
+constexpr int kHdListBatch = 4;     // lookups in flight per lane
+constexpr int kHdHalf = 81;         // 3^4 offset combinations per half, at most
+
+template <int KD>
+__global__ __launch_bounds__(kBlock) void k_hd_lists(Plan P)
+{
+    constexpr int DA = KD / 2, DB = KD - DA;
+    constexpr int NA = DA == 0 ? 1 : DA == 1 ? 3 : DA == 2 ? 9 : DA == 3 ? 27 : 81;
+    constexpr int NB = DB == 1 ? 3 : DB == 2 ? 9 : DB == 3 ? 27 : 81;
+    __shared__ int64_t s_sa[kWavesPerBlock][kHdHalf], s_sb[kWavesPerBlock][kHdHalf];
+    __shared__ int64_t s_ka[kWavesPerBlock][kHdHalf], s_kb[kWavesPerBlock][kHdHalf];
+    __shared__ int64_t s_in[kWavesPerBlock][kHdHalf];
+    __shared__ uint8_t s_ia[kWavesPerBlock][kHdHalf], s_ib[kWavesPerBlock][kHdHalf];
+    __shared__ int8_t s_ga[kWavesPerBlock][kHdHalf], s_gb[kWavesPerBlock][kHdHalf];
+    __shared__ uint32_t s_pre[kWavesPerBlock][kHdHalf + 1];
+    const uint32_t w = wave_in_block(), l = lane_id(), sd = P.sd;
+    const int64_t eps2 = P.eps2;
+    const uint32_t ng = ld_agent32(&P.ctr->n_groups);
+    const uint32_t waves = gridDim.x * kWavesPerBlock;
+    const uint32_t slab = P.nbr_cap / waves;
+    uint32_t at = (blockIdx.x * kWavesPerBlock + w) * slab;
+    const uint32_t end = at + slab;
+    uint32_t overflow = 0;
+    const DynRange dr_ = dyn_range(P.ctr->dyn[kDynLists]);
+    HCA_FOR_UNITS_DYN(g, ng, dr_) {
+        const uint64_t gkey = P.group_key[g];
+        const int32_t *gb = P.gbox + (uint64_t)g * 2 * sd;
+        int32_t qlo[KD], qhi[KD];
+#pragma unroll
+        for (int e = 0; e < KD; e++) {
+            qlo[e] = gb[P.kdim[e]];
+            qhi[e] = gb[sd + P.kdim[e]];
+        }
+        for (int i = l; i < NA; i += kWave) s_in[w][i] = hd_half_gap2<0, DA, KD>(P, gkey, i, qlo, qhi);
+        __builtin_amdgcn_wave_barrier();
+        bitonic_sort(s_in[w], NA, s_sa[w], s_ia[w]);
+        __builtin_amdgcn_wave_barrier();
+        for (int j = l; j < NB; j += kWave) s_in[w][j] = hd_half_gap2<DA, DB, KD>(P, gkey, j, qlo, qhi);
+        __builtin_amdgcn_wave_barrier();
+        bitonic_sort(s_in[w], NB, s_sb[w], s_ib[w]);
+        __builtin_amdgcn_wave_barrier();
+        for (int i = l; i < NA; i += kWave) s_ga[w][i] = hd_half_sign<DA>(s_ia[w][i]);
+        for (int j = l; j < NB; j += kWave) s_gb[w][j] = hd_half_sign<DB>(s_ib[w][j]);
+        // valid second-half offsets per first-half one (none when the first
+        // half points backwards), then their prefix
+        uint32_t tot = 0;
+        for (int i0 = 0; i0 < NA; i0 += kWave) {
+            const int i = i0 + (int)l;
+            uint32_t c = 0;
+            if (i < NA && s_sa[w][i] != INT64_MAX && s_ga[w][i] >= 0) {
+                const int64_t lim = eps2 - s_sa[w][i];
+                int lo = 0, hi = NB;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_sb[w][mid] <= lim) lo = mid + 1; else hi = mid;
+                }
+                c = (uint32_t)lo;
+            }
+            const uint32_t inc = wave_inclusive_scan(c);
+            if (i < NA) s_pre[w][i] = tot + inc - c;
+            tot += __shfl(inc, kWave - 1);
+        }
+        if (l == 0) s_pre[w][NA] = tot;
+        for (int i = l; i < NA; i += kWave) s_ka[w][i] = hd_half_key_delta<0, DA>(P, s_ia[w][i]);
+        for (int j = l; j < NB; j += kWave) s_kb[w][j] = hd_half_key_delta<DA, DB>(P, s_ib[w][j]);
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t start = at;
+        bool fits = true;
+        for (uint32_t t0 = 0; t0 < tot; t0 += kWave * kHdListBatch) {
+            uint64_t nk[kHdListBatch];
+            uint32_t G[kHdListBatch];
+#pragma unroll
+            for (int b = 0; b < kHdListBatch; b++) {
+                const uint32_t t = t0 + b * kWave + l;
+                nk[b] = ~0ull;
+                if (t < tot) {
+                    int lo = 0, hi = NA;                  // last i with s_pre[i] <= t
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (s_pre[w][mid] <= t) lo = mid; else hi = mid;
+                    }
+                    const uint32_t j = t - s_pre[w][lo];
+                    if (s_ga[w][lo] > 0 || s_gb[w][j] > 0) nk[b] = gkey + (uint64_t)(s_ka[w][lo] + s_kb[w][j]);
+                }
+            }
+            group_lookup_n<kHdListBatch>(P, nk, G);
+#pragma unroll
+            for (int b = 0; b < kHdListBatch; b++) {
+                if (G[b] != kNone && hd_box_gap2(gb, P.gbox + (uint64_t)G[b] * 2 * sd, sd, eps2) > eps2)
+                    G[b] = kNone;
+                const uint64_t m = __ballot(G[b] != kNone);
+                const uint32_t k = (uint32_t)__popcll(m);
+                if (at + k > end) fits = false;
+                if (fits && G[b] != kNone) {
+                    P.nbr[at + __popcll(m & __lanemask_lt())] = G[b];
+                    atomicAdd(P.nbr_bcount + G[b], 1u);
+                }
+                if (fits) at += k;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (l == 0) {
+            P.nbr_start[g] = start;
+            P.nbr_count[g] = fits ? at - start : kNone;
+        }
+        if (!fits) {
+            at = start;
+            overflow++;
+        }
+    }
+    if (l == 0 && overflow) atomicAdd(&P.ctr->nbr_overflow, overflow);
+}
+
+// ---------------------------------------------------------------------------
+// Walks over a group and its listed neighbours.
+// ---------------------------------------------------------------------------
+// Slot 0 is the group itself, then its forward entries, then (unless
+// forward_only) its backward ones.
+struct HdSrc {
+    uint32_t start, fcount, bstart, slots;
+};
+
+__device__ __forceinline__ HdSrc hd_source(const Plan &P, uint32_t g, bool forward_only)
+{
+    HdSrc s;
+    s.start = P.nbr_start[g];
+    s.fcount = P.nbr_count[g];
+    s.bstart = P.nbr_bstart[g];
+    s.slots = 1 + s.fcount + (forward_only ? 0u : P.nbr_bcount[g]);
+    return s;
+}
+
+__device__ __forceinline__ uint32_t hd_slot(const Plan &P, uint32_t g, const HdSrc &s, uint32_t j)
+{
+    if (j == 0) return g;
+    return j <= s.fcount ? P.nbr[s.start + j - 1] : P.nbr_back[s.bstart + j - 1 - s.fcount];
+}
+
+// The 8 rows from sorted position pc (the last one repeated past np) into LDS.
+__device__ __forceinline__ void hd_stage(const Plan &P, uint32_t pc, uint32_t np, int32_t (*own)[kMaxDimHigh])
+{
+    const uint32_t sd = P.sd;
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t i = lane_id(); i < kPch * sd; i += kWave) {
+        const uint32_t k = i / sd, e = i - k * sd;
+        own[k][e] = P.spts[(uint64_t)(pc + min(k, np - 1)) * sd + e];
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Box of the staged points flagged in mask, into qb[0, sd) and qb[sd, 2 sd).
+__device__ __forceinline__ void hd_chunk_box(const Plan &P, const int32_t (*own)[kMaxDimHigh], uint32_t mask,
+                                             int32_t *qb)
+{
+    const uint32_t l = lane_id(), sd = P.sd;
+    __builtin_amdgcn_wave_barrier();
+    if (l < sd) {
+        int32_t lo = INT32_MAX, hi = INT32_MIN;
+#pragma unroll
+        for (int k = 0; k < kPch; k++)
+            if (mask & (1u << k)) {
+                lo = min(lo, own[k][l]);
+                hi = max(hi, own[k][l]);
+            }
+        qb[l] = lo;
+        qb[sd + l] = hi;
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Candidates of slots [first, first + 64): lane l resolves slot first + l; a
+// group is dropped when it has no core point (need_core) or its box is
+// farther than eps from the query box qb.  Returns the candidate count.
+__device__ __forceinline__ uint32_t hd_load_neighbours(const Plan &P, uint32_t g, const HdSrc &src, uint32_t first,
+                                                       bool need_core, const int32_t *qb, uint32_t *s_beg,
+                                                       uint32_t *s_pre)
+{
+    const uint32_t l = lane_id(), j = first + l;
+    uint32_t a = 0, size = 0;
+    if (j < src.slots) {
+        const uint32_t G = hd_slot(P, g, src, j);
+        if (!(need_core && P.gcube[G] == kNone) &&
+            hd_box_gap2(qb, P.gbox + (uint64_t)G * 2 * P.sd, P.sd, P.eps2) <= P.eps2) {
+            a = P.group_start[G];
+            size = P.group_start[G + 1] - a;
+        }
+    }
+    const uint32_t inc = wave_inclusive_scan(size);
+    __builtin_amdgcn_wave_barrier();
+    s_beg[l] = a;
+    s_pre[l] = inc - size;
+    __builtin_amdgcn_wave_barrier();
+    return __shfl(inc, kWave - 1);
+}
+
+// Squared distances from the candidate row at sorted position pos to the 8
+// staged points (exact: 64-bit, or 32-bit when the host has shown that every
+// tested pair's sum fits).
+template <bool WIDE>
+__device__ __forceinline__ void hd_dist(const Plan &P, const int32_t (*own)[kMaxDimHigh], uint32_t pos, int64_t *dd)
+{
+    const int4 *row = reinterpret_cast<const int4 *>(P.spts + (uint64_t)pos * P.sd);
+    const uint32_t n4 = P.sd >> 2;
+    if constexpr (WIDE) {
+        int64_t acc[kPch];
+#pragma unroll
+        for (int k = 0; k < kPch; k++) acc[k] = 0;
+        for (uint32_t e = 0; e < n4; e++) {
+            const int4 v = row[e];
+#pragma unroll
+            for (int k = 0; k < kPch; k++) {
+                const int4 o = reinterpret_cast<const int4 *>(own[k])[e];
+                const int64_t a = (int64_t)v.x - o.x, b = (int64_t)v.y - o.y;
+                const int64_t c = (int64_t)v.z - o.z, f = (int64_t)v.w - o.w;
+                acc[k] += a * a + b * b + c * c + f * f;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kPch; k++) dd[k] = acc[k];
+    } else {
+        int32_t acc[kPch];
+#pragma unroll
+        for (int k = 0; k < kPch; k++) acc[k] = 0;
+        for (uint32_t e = 0; e < n4; e++) {
+            const int4 v = row[e];
+#pragma unroll
+            for (int k = 0; k < kPch; k++) {
+                const int4 o = reinterpret_cast<const int4 *>(own[k])[e];
+                const int32_t a = v.x - o.x, b = v.y - o.y, c = v.z - o.z, f = v.w - o.w;
+                acc[k] += __mul24(a, a) + __mul24(b, b) + __mul24(c, c) + __mul24(f, f);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kPch; k++) dd[k] = acc[k];
+    }
+}
+
+__device__ __forceinline__ uint32_t hd_candidate(uint32_t c, const uint32_t *s_beg, const uint32_t *s_pre)
+{
+    const uint32_t ln = candidate_lane(c, s_pre);
+    return s_beg[ln] + (c - s_pre[ln]);
+}
+
+// ---------------------------------------------------------------------------
+// Core marking (appendix, Definition 2), chunks of 8 sorted points: a point
+// of a cube with at least minPts points is core; any other point counts the
+// points within eps in its group and the listed neighbours, stopping at
+// minPts.  Per cube: core points and the smallest core input index.
+// ---------------------------------------------------------------------------
+template <bool WIDE>
+__device__ __forceinline__ uint32_t hd_count_walk(const Plan &P, uint32_t g, const int32_t (*own)[kMaxDimHigh],
+                                                  uint32_t done, uint32_t *cnt, int32_t *qb, uint32_t *s_beg,
+                                                  uint32_t *s_pre, uint32_t &lt)
+{
+    const uint32_t l = lane_id(), minpts = (uint32_t)P.min_pts, all = (1u << kPch) - 1u;
+    hd_chunk_box(P, own, ~done & all, qb);
+    const HdSrc src = hd_source(P, g, false);
+    for (uint32_t oc = 0; oc < src.slots && done != all; oc += kWave) {
+        const uint32_t total = hd_load_neighbours(P, g, src, oc, false, qb, s_beg, s_pre);
+        for (uint32_t ci = 0; ci < total && done != all; ci += kWave) {
+            const uint32_t c = ci + l;
+            const bool ok = c < total;
+            const uint32_t pos = ok ? hd_candidate(c, s_beg, s_pre) : 0u;
+            int64_t dd[kPch];
+            hd_dist<WIDE>(P, own, pos, dd);
+#pragma unroll
+            for (int k = 0; k < kPch; k++) {
+                if (done & (1u << k)) continue;
+                lt += ok;
+                cnt[k] += __popcll(__ballot(ok && dd[k] <= P.eps2));
+                if (cnt[k] >= minpts) done |= 1u << k;
+            }
+            done = uniform(done);
+        }
+    }
+    return done;
+}
+
+template <bool WIDE>
+__global__ __launch_bounds__(kBlock) void k_hd_core(Plan P)
+{
+    __shared__ __align__(16) int32_t s_own[kWavesPerBlock][kPch][kMaxDimHigh];
+    __shared__ int32_t s_qb[kWavesPerBlock][2 * kMaxDimHigh];
+    __shared__ uint32_t s_beg[kWavesPerBlock][kWave], s_pre[kWavesPerBlock][kWave];
+    const uint32_t w = wave_in_block(), l = lane_id();
+    const uint32_t n = P.n, minpts = (uint32_t)P.min_pts, all = (1u << kPch) - 1u;
+    uint32_t lt = 0;
+    const DynRange dr_ = dyn_range(P.ctr->dyn[kDynCore]);
+    HCA_FOR_UNITS_DYN(u, (n + kPch - 1) / kPch, dr_) {
+        const uint32_t pc = u * kPch, np = min((uint32_t)kPch, n - pc);
+        uint32_t cell = kNone, grp = kNone;
+        bool dense = true;
+        if (l < np) {
+            cell = P.cell_of[pc + l];
+            grp = P.group_of[cell];
+            dense = P.cell_start[cell + 1] - P.cell_start[cell] >= minpts;
+        }
+        uint32_t done = (uint32_t)__ballot(dense) & all;
+        uint32_t cnt[kPch];
+#pragma unroll
+        for (int k = 0; k < kPch; k++) cnt[k] = 0;
+        if (done != all) {
+            hd_stage(P, pc, np, s_own[w]);
+            uint32_t left = ~done & all;
+            while (left) {
+                const uint32_t g = __shfl(grp, __ffs(left) - 1);
+                const uint32_t run = (uint32_t)__ballot(grp == g) & left;
+                left &= ~run;
+                done |= hd_count_walk<WIDE>(P, g, s_own[w], ~run & all, cnt, s_qb[w], s_beg[w], s_pre[w], lt) & run;
+            }
+        }
+        uint32_t mine = 0;
+#pragma unroll
+        for (int k = 0; k < kPch; k++)
+            if ((uint32_t)k == l) mine = cnt[k];
+        const bool core = l < np && (dense || mine >= minpts);
+        if (l < np) P.core[pc + l] = core;
+        const uint32_t me = core ? P.sidx[pc + l] : kNone;
+        uint64_t pend = __ballot(l < np);
+        while (pend) {
+            const uint32_t k0 = __ffsll((unsigned long long)pend) - 1;
+            const uint32_t c = __shfl(cell, k0);
+            const uint64_t same = __ballot(l < np && cell == c);
+            const uint32_t cores = (uint32_t)__popcll(__ballot(l < np && cell == c && core));
+            const uint32_t mn = wave_min(cell == c ? me : kNone);
+            if (l == k0 && cores) {
+                atomicAdd(P.ncore + c, cores);
+                atomicMin(P.cmin + c, mn);
+            }
+            pend &= ~same;
+        }
+    }
+    flush_tests(P, kTestsCore, lt);
+}
+
+// First cube with a core point of every group (kNone: none).
+__global__ __launch_bounds__(kBlock) void k_hd_gcore(Plan P)
+{
+    const uint32_t nc = ld_agent32(&P.ctr->n_cells);
+    for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < nc; c += gridDim.x * kBlock)
+        if (P.ncore[c]) atomicMin(P.gcube + P.group_of[c], c);
+}
+
+// ---------------------------------------------------------------------------
+// Merging (Definitions 3-5): every pair of core points within eps joins its
+// two cubes.  Each core point of a chunk walks its own group and the groups
+// after it (the forward entries), so every pair of cubes is seen from the
+// smaller one; roots are cached and a batch of candidates is skipped when no
+// pair in it could join two different sets.
+// ---------------------------------------------------------------------------
+template <bool WIDE>
+__device__ __forceinline__ void hd_link_walk(const Plan &P, uint32_t g, const int32_t (*own)[kMaxDimHigh],
+                                             uint32_t run, const uint32_t *ck, int32_t *qb, uint32_t *s_beg,
+                                             uint32_t *s_pre, uint32_t &lt)
+{
+    const uint32_t l = lane_id();
+    hd_chunk_box(P, own, run, qb);
+    const HdSrc src = hd_source(P, g, true);
+    uint32_t rk[kPch];
+#pragma unroll
+    for (int k = 0; k < kPch; k++) rk[k] = (run & (1u << k)) ? uf_find(P.parent, ck[k]) : kNone;
+    for (uint32_t oc = 0; oc < src.slots; oc += kWave) {
+        const uint32_t total = hd_load_neighbours(P, g, src, oc, true, qb, s_beg, s_pre);
+        for (uint32_t ci = 0; ci < total; ci += kWave) {
+            const uint32_t c = ci + l;
+            bool ok = c < total;
+            const uint32_t pos = ok ? hd_candidate(c, s_beg, s_pre) : 0u;
+            ok = ok && P.core[pos];
+            const uint32_t cq = ok ? P.cell_of[pos] : 0u;
+            uint32_t rq = ok ? uf_find(P.parent, cq) : kNone;
+            bool any = false;
+#pragma unroll
+            for (int k = 0; k < kPch; k++)
+                if (run & (1u << k)) any |= ok && cq > ck[k] && rq != rk[k];
+            if (!__ballot(any)) continue;
+            int64_t dd[kPch];
+            hd_dist<WIDE>(P, own, pos, dd);
+#pragma unroll
+            for (int k = 0; k < kPch; k++) {
+                if (!(run & (1u << k))) continue;
+                lt += ok;
+                const bool need = ok && cq > ck[k] && rq != rk[k] && dd[k] <= P.eps2;
+                if (__ballot(need)) {
+                    if (need) uf_union(P.parent, ck[k], cq);
+                    rq = ok ? uf_find(P.parent, cq) : kNone;
+#pragma unroll
+                    for (int k2 = 0; k2 < kPch; k2++)
+                        if (run & (1u << k2)) rk[k2] = uf_find(P.parent, ck[k2]);
+                }
+            }
+        }
+    }
+}
+
+template <bool WIDE>
+__global__ __launch_bounds__(kBlock) void k_hd_merge(Plan P)
+{
+    __shared__ __align__(16) int32_t s_own[kWavesPerBlock][kPch][kMaxDimHigh];
+    __shared__ int32_t s_qb[kWavesPerBlock][2 * kMaxDimHigh];
+    __shared__ uint32_t s_beg[kWavesPerBlock][kWave], s_pre[kWavesPerBlock][kWave];
+    const uint32_t w = wave_in_block(), l = lane_id();
+    const uint32_t n = P.n, all = (1u << kPch) - 1u;
+    uint32_t lt = 0;
+    const DynRange dr_ = dyn_range(P.ctr->dyn[kDynMerge]);
+    HCA_FOR_UNITS_DYN(u, (n + kPch - 1) / kPch, dr_) {
+        const uint32_t pc = u * kPch, np = min((uint32_t)kPch, n - pc);
+        const bool core = l < np && P.core[pc + l];
+        const uint32_t live = (uint32_t)__ballot(core) & all;
+        if (!live) continue;
+        const uint32_t cell = core ? P.cell_of[pc + l] : kNone;
+        const uint32_t grp = core ? P.group_of[cell] : kNone;
+        uint32_t ck[kPch];
+#pragma unroll
+        for (int k = 0; k < kPch; k++) ck[k] = uniform(__shfl(cell, k));
+        hd_stage(P, pc, np, s_own[w]);
+        uint32_t left = live;
+        while (left) {
+            const uint32_t g = __shfl(grp, __ffs(left) - 1);
+            const uint32_t run = (uint32_t)__ballot(grp == g) & left;
+            left &= ~run;
+            hd_link_walk<WIDE>(P, g, s_own[w], run, ck, s_qb[w], s_beg[w], s_pre[w], lt);
+        }
+    }
+    flush_tests(P, kTestsMerge, lt);
+}
+
+// ---------------------------------------------------------------------------
+// Border points: each non-core point of a chunk takes the root of its nearest
+// core point within eps (ties to the smaller input index); none -> noise.
+// ---------------------------------------------------------------------------
+template <bool WIDE>
+__device__ __forceinline__ void hd_border_walk(const Plan &P, uint32_t g, const int32_t (*own)[kMaxDimHigh],
+                                               uint32_t todo, int64_t *bd, uint32_t *bi, uint32_t *bp, int32_t *qb,
+                                               uint32_t *s_beg, uint32_t *s_pre, uint32_t &lt)
+{
+    const uint32_t l = lane_id();
+    const int64_t eps2 = P.eps2;
+    hd_chunk_box(P, own, todo, qb);
+    const HdSrc src = hd_source(P, g, false);
+    for (uint32_t oc = 0; oc < src.slots; oc += kWave) {
+        const uint32_t total = hd_load_neighbours(P, g, src, oc, true, qb, s_beg, s_pre);
+        for (uint32_t ci = 0; ci < total; ci += kWave) {
+            const uint32_t c = ci + l;
+            bool ok = c < total;
+            const uint32_t pos = ok ? hd_candidate(c, s_beg, s_pre) : 0u;
+            ok = ok && P.core[pos];
+            if (!__ballot(ok)) continue;
+            int64_t dd[kPch];
+            hd_dist<WIDE>(P, own, pos, dd);
+            bool near = false;
+#pragma unroll
+            for (int k = 0; k < kPch; k++) {
+                if (todo & (1u << k)) lt += ok;
+                near |= (todo & (1u << k)) && ok && dd[k] <= eps2 && dd[k] <= bd[k];
+            }
+            if (!near) continue;
+            const uint32_t qi = P.sidx[pos];
+#pragma unroll
+            for (int k = 0; k < kPch; k++) {
+                if (!(todo & (1u << k))) continue;
+                if (ok && dd[k] <= eps2 && (dd[k] < bd[k] || (dd[k] == bd[k] && qi < bi[k]))) {
+                    bd[k] = dd[k];
+                    bi[k] = qi;
+                    bp[k] = pos;
+                }
+            }
+        }
+    }
+}
+
+template <bool WIDE>
+__global__ __launch_bounds__(kBlock) void k_hd_border(Plan P)
+{
+    __shared__ __align__(16) int32_t s_own[kWavesPerBlock][kPch][kMaxDimHigh];
+    __shared__ int32_t s_qb[kWavesPerBlock][2 * kMaxDimHigh];
+    __shared__ uint32_t s_beg[kWavesPerBlock][kWave], s_pre[kWavesPerBlock][kWave];
+    const uint32_t w = wave_in_block(), l = lane_id();
+    const uint32_t n = P.n;
+    uint32_t lt = 0;
+    const DynRange dr_ = dyn_range(P.ctr->dyn[kDynBorder]);
+    HCA_FOR_UNITS_DYN(u, (n + kPch - 1) / kPch, dr_) {
+        const uint32_t pc = u * kPch, np = min((uint32_t)kPch, n - pc);
+        const bool mine = l < np && !P.core[pc + l];
+        const uint32_t todo = (uint32_t)__ballot(mine) & ((1u << kPch) - 1u);
+        if (!todo) continue;
+        const uint32_t grp = mine ? P.group_of[P.cell_of[pc + l]] : kNone;
+        hd_stage(P, pc, np, s_own[w]);
+        int64_t bd[kPch];
+        uint32_t bi[kPch], bp[kPch];
+#pragma unroll
+        for (int k = 0; k < kPch; k++) { bd[k] = INT64_MAX; bi[k] = kNone; bp[k] = kNone; }
+        uint32_t left = todo;
+        while (left) {
+            const uint32_t g = __shfl(grp, __ffs(left) - 1);
+            const uint32_t run = (uint32_t)__ballot(grp == g) & left;
+            left &= ~run;
+            hd_border_walk<WIDE>(P, g, s_own[w], run, bd, bi, bp, s_qb[w], s_beg[w], s_pre[w], lt);
+        }
+        border_finish(P, pc, todo, bd, bi, bp);
+    }
+    flush_tests(P, kTestsBorder, lt);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+void launch_hd_lists(const Plan &P, int blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_hd_group_box, dim3(blocks), dim3(kBlock), 0, s, P);
+    switch (P.kd) {
+    case 1: hipLaunchKernelGGL(k_hd_lists<1>, dim3(blocks), dim3(kBlock), 0, s, P); break;
+    case 2: hipLaunchKernelGGL(k_hd_lists<2>, dim3(blocks), dim3(kBlock), 0, s, P); break;
+    case 3: hipLaunchKernelGGL(k_hd_lists<3>, dim3(blocks), dim3(kBlock), 0, s, P); break;
+    case 4: hipLaunchKernelGGL(k_hd_lists<4>, dim3(blocks), dim3(kBlock), 0, s, P); break;
+    case 5: hipLaunchKernelGGL(k_hd_lists<5>, dim3(blocks), dim3(kBlock), 0, s, P); break;
+    case 6: hipLaunchKernelGGL(k_hd_lists<6>, dim3(blocks), dim3(kBlock), 0, s, P); break;
+    case 7: hipLaunchKernelGGL(k_hd_lists<7>, dim3(blocks), dim3(kBlock), 0, s, P); break;
+    case 8: hipLaunchKernelGGL(k_hd_lists<8>, dim3(blocks), dim3(kBlock), 0, s, P); break;
+    }
+    launch_lists_back(P, blocks, s);
+}
+
+void launch_hd_core(const Plan &P, int blocks, hipStream_t s)
+{
+    if (P.wide) hipLaunchKernelGGL(k_hd_core<true>, dim3(blocks), dim3(kBlock), 0, s, P);
+    else hipLaunchKernelGGL(k_hd_core<false>, dim3(blocks), dim3(kBlock), 0, s, P);
+    const int cb = (int)std::min<uint64_t>((P.n + kBlock - 1) / kBlock, 1024);
+    hipLaunchKernelGGL(k_hd_gcore, dim3(cb), dim3(kBlock), 0, s, P);
+}
+
+void launch_hd_merge(const Plan &P, int blocks, hipStream_t s)
+{
+    if (P.wide) hipLaunchKernelGGL(k_hd_merge<true>, dim3(blocks), dim3(kBlock), 0, s, P);
+    else hipLaunchKernelGGL(k_hd_merge<false>, dim3(blocks), dim3(kBlock), 0, s, P);
+}
+
+void launch_hd_border(const Plan &P, int blocks, hipStream_t s)
+{
+    if (P.wide) hipLaunchKernelGGL(k_hd_border<true>, dim3(blocks), dim3(kBlock), 0, s, P);
+    else hipLaunchKernelGGL(k_hd_border<false>, dim3(blocks), dim3(kBlock), 0, s, P);
+}
+
+}  // namespace hca

@@ -24,6 +24,7 @@ void launch_cells(const Plan &P, bool wide_keys, uint64_t *status, uint32_t *tic
 void launch_init(uint32_t *zero, uint64_t zero_words, uint32_t *table, uint64_t tsize, hipStream_t s);
 void launch_table(const Plan &P, int blocks, hipStream_t s);
 void launch_lists(const Plan &P, int blocks, hipStream_t s);
+void launch_lists_back(const Plan &P, int blocks, hipStream_t s);   // backward entries of built lists
 void launch_core(const Plan &P, int blocks, hipStream_t s);
 void launch_reps(const Plan &P, int blocks, hipStream_t s);
 void launch_merge_intra(const Plan &P, int blocks, hipStream_t s);
@@ -31,6 +32,16 @@ void launch_merge(const Plan &P, int blocks, hipStream_t s);
 void launch_compress(const Plan &P, int blocks, hipStream_t s);
 void launch_border(const Plan &P, int blocks, hipStream_t s);
 void launch_labels(const Plan &P, uint64_t *status, uint32_t *ticket, hipStream_t s);
+
+// more than kMaxDim axes (P.hd): bounding box partials [blocks][2][d], sort of
+// the keys with the rows gathered afterwards, neighbour lists, core points,
+// merging and border points
+void launch_bbox_hd(int d, const int32_t *pts, uint32_t n, int32_t *partial, int blocks, hipStream_t s);
+void launch_sort_hd(Plan &P, SortBuffers &B, hipStream_t s);
+void launch_hd_lists(const Plan &P, int blocks, hipStream_t s);
+void launch_hd_core(const Plan &P, int blocks, hipStream_t s);
+void launch_hd_merge(const Plan &P, int blocks, hipStream_t s);
+void launch_hd_border(const Plan &P, int blocks, hipStream_t s);
 
 // batches: stage the data sets of one dimension d <= 4 contiguously (rows and
 // their data set, read from each data set's own rows) and take their bounding

@@ -7,7 +7,8 @@
 
 namespace hca {
 
-constexpr int kMaxDim = 8;
+constexpr int kMaxDim = 8;                     // axes of the packed cube key
+constexpr int kMaxDimHigh = 64;                // axes of a point (more than 8: hashed cubes)
 constexpr int kWave = 64;
 constexpr int kBlock = 256;                    // 4 waves per workgroup
 constexpr uint32_t kNone = 0xFFFFFFFFu;
@@ -97,6 +98,16 @@ struct Plan {
     uint32_t gmax[kMaxDim];     // largest group coordinate per axis
     uint32_t key_bits;
     uint32_t passes;
+    // more than kMaxDim axes (hd = 1): search groups over the kd key axes
+    // kdim[0..kd) (position e of the group key holds axis kdim[e], with
+    // origin[e], goff[e], gw[e], gmax[e]); below them the key holds
+    // fine_bits bits of a hash of the point's cube over all d axes.  Points
+    // and group boxes are stored with rows of sd >= d int32 (zero padded).
+    uint32_t hd;
+    uint32_t sd;
+    uint32_t kd;
+    uint8_t kdim[kMaxDim];
+    const int32_t *hd_origin;   // [d] origin of every axis (hd)
     // neighbour search over groups: offsets in [-R, R]^d, self first
     uint32_t n_off;
     const int8_t *off;          // [n_off][d]

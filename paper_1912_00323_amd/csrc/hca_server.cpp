@@ -54,7 +54,8 @@ size_t footprint(int64_t n, int32_t d)
 {
     uint64_t dirs = 1;
     for (int k = 0; k < std::min(d, 4); k++) dirs *= 3;
-    const uint64_t per_point = 256 + 8ull * (dirs - 1) + 16ull * (uint64_t)d + (d >= 3 ? 264 : 0);
+    uint64_t per_point = 256 + 8ull * (dirs - 1) + 16ull * (uint64_t)d + (d >= 3 ? 264 : 0);
+    if (d > 8) per_point += 12ull * (((uint64_t)d + 3) & ~3ull);      // padded rows and group boxes
     return (size_t)((uint64_t)n * per_point + (1ull << 20));
 }
 
@@ -201,7 +202,7 @@ hca_status hca_server_create(hca_server **out, int32_t device, int32_t workers, 
 hca_status hca_server_submit(hca_server *srv, const int32_t *points, int64_t n, int32_t d, double eps,
                              int32_t min_pts, int32_t *labels, uint64_t tag)
 {
-    if (!srv || n < 0 || d < 1 || d > 8 || min_pts < 1 || !(eps > 0.0)) return HCA_E_INVAL;
+    if (!srv || n < 0 || d < 1 || d > 64 || min_pts < 1 || !(eps > 0.0)) return HCA_E_INVAL;
     if (n > 0 && (!points || !labels)) return HCA_E_INVAL;
     {
         std::lock_guard<std::mutex> lk(srv->mu);

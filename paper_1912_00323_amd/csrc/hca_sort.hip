@@ -53,6 +53,33 @@ __global__ __launch_bounds__(kBlock) void k_bbox(const int32_t *__restrict__ pts
     }
 }
 
+// More than kMaxDim axes: thread t owns axis t % d of the rows t / d,
+// t / d + rpb, ... (rpb = 256 / d rows per sweep), so a sweep reads
+// consecutive words; the threads sharing an axis are folded in LDS.
+__global__ __launch_bounds__(kBlock) void k_hd_bbox(const int32_t *__restrict__ pts, uint32_t n, uint32_t d,
+                                                    int32_t *__restrict__ partial)
+{
+    __shared__ int32_t s_mn[kBlock], s_mx[kBlock];
+    const uint32_t t = threadIdx.x, rpb = kBlock / d;
+    const uint32_t e = t % d, r0 = t / d;
+    int32_t mn = INT32_MAX, mx = INT32_MIN;
+    if (r0 < rpb)
+        for (uint64_t r = (uint64_t)blockIdx.x * rpb + r0; r < n; r += (uint64_t)gridDim.x * rpb) {
+            const int32_t v = pts[r * d + e];
+            mn = min(mn, v);
+            mx = max(mx, v);
+        }
+    s_mn[t] = mn;
+    s_mx[t] = mx;
+    __syncthreads();
+    if (t < d) {
+        int32_t a = s_mn[t], b = s_mx[t];
+        for (uint32_t j = t + d; j < rpb * d; j += d) { a = min(a, s_mn[j]); b = max(b, s_mx[j]); }
+        partial[blockIdx.x * 2 * d + t] = a;
+        partial[blockIdx.x * 2 * d + d + t] = b;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Cube keys and the digit histograms of every radix pass, in one read.
 // ---------------------------------------------------------------------------
@@ -103,6 +130,67 @@ __global__ __launch_bounds__(kBlock) void k_keys_hist(Plan P, K *__restrict__ ke
     __syncthreads();
     for (uint32_t e = threadIdx.x; e < passes * kRadix; e += kBlock)
         if (s_hist[e]) atomicAdd(&hist[e], s_hist[e]);
+}
+
+// More than kMaxDim axes: the group coordinates over the key axes, and below
+// them the top fine_bits bits of a hash of the cube (its band along every
+// axis).  Points of one cube share a key; two cubes that share one are told
+// apart after the sort (k_cells compares their bands).
+__global__ __launch_bounds__(kBlock) void k_hd_keys_hist(Plan P, uint64_t *__restrict__ keys,
+                                                         uint32_t *__restrict__ vals, uint32_t *__restrict__ hist)
+{
+    __shared__ uint32_t s_hist[8 * kRadix];
+    __shared__ int32_t s_org[kMaxDimHigh];
+    const uint32_t passes = P.passes, d = (uint32_t)P.d, hb = P.fine_bits;
+    for (uint32_t e = threadIdx.x; e < passes * kRadix; e += kBlock) s_hist[e] = 0;
+    for (uint32_t e = threadIdx.x; e < d; e += kBlock) s_org[e] = P.hd_origin[e];
+    __syncthreads();
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < P.n; i += gridDim.x * kBlock) {
+        const int32_t *row = P.pts + (uint64_t)i * d;
+        uint64_t gk = 0;
+#pragma unroll
+        for (int e = 0; e < kMaxDim; e++) {
+            if ((uint32_t)e >= P.kd) break;
+            const uint32_t a = P.kdim[e];
+            const uint32_t u = (uint32_t)(row[a] - s_org[a]);     // < 2^30 (host checked)
+            gk |= (uint64_t)(u / P.side / P.m) << P.goff[e];
+        }
+        uint64_t h = 0x243F6A8885A308D3ull;
+        for (uint32_t a = 0; a < d; a++) {
+            const uint32_t c = (uint32_t)(row[a] - s_org[a]) / P.side;
+            h = mix64(h ^ ((uint64_t)a << 32 | c));
+        }
+        const uint64_t key = (gk << hb) | (h >> (64u - hb));
+        keys[i] = key;
+        vals[i] = i;
+        for (uint32_t q = 0; q < passes; q++)
+            atomicAdd(&s_hist[q * kRadix + (uint32_t)((key >> (q * kRadixBits)) & (kRadix - 1))], 1u);
+    }
+    __syncthreads();
+    for (uint32_t e = threadIdx.x; e < passes * kRadix; e += kBlock)
+        if (s_hist[e]) atomicAdd(&hist[e], s_hist[e]);
+}
+
+// Rows gathered into sorted order, padded with zeros to sd words: thread t
+// owns word t % sd of the rows t / sd, t / sd + rpb, ... (rpb = 256 / sd).
+__global__ __launch_bounds__(kBlock) void k_hd_gather(Plan P)
+{
+    const uint32_t d = (uint32_t)P.d, sd = P.sd, rpb = kBlock / sd;
+    const uint32_t e = threadIdx.x % sd, r0 = threadIdx.x / sd;
+    if (r0 >= rpb) return;
+    for (uint64_t r = (uint64_t)blockIdx.x * rpb + r0; r < P.n; r += (uint64_t)gridDim.x * rpb)
+        P.spts[r * sd + e] = e < d ? P.pts[(uint64_t)P.sidx[r] * d + e] : 0;
+}
+
+// Does sorted point idx lie in another cube than point idx - 1 (hd)?
+__device__ __forceinline__ bool hd_new_cube(const Plan &P, uint32_t idx)
+{
+    const int32_t *x = P.spts + (uint64_t)idx * P.sd, *y = x - P.sd;
+    for (uint32_t a = 0; a < (uint32_t)P.d; a++) {
+        const int32_t o = P.hd_origin[a];
+        if ((uint32_t)(x[a] - o) / P.side != (uint32_t)(y[a] - o) / P.side) return true;
+    }
+    return false;
 }
 
 // ---------------------------------------------------------------------------
@@ -257,7 +345,7 @@ __global__ __launch_bounds__(kBlock) void k_cells(Plan P, uint64_t *__restrict__
                 fc = fg = 1;
             } else {
                 const uint64_t a = (uint64_t)skeys[idx], b = (uint64_t)skeys[idx - 1];
-                fc = a != b;
+                fc = a != b || (P.hd && hd_new_cube(P, idx));
                 fg = (a >> fb) != (b >> fb);
             }
         }
@@ -374,6 +462,35 @@ void launch_sort(const Plan &P, SortBuffers &B, bool wide_keys, hipStream_t s)
     const bool odd = P.passes & 1u;
     B.result_keys = odd ? B.keys_b : B.keys_a;
     B.result_vals = odd ? B.vals_b : B.vals_a;
+}
+
+void launch_bbox_hd(int d, const int32_t *pts, uint32_t n, int32_t *partial, int blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_hd_bbox, dim3(blocks), dim3(kBlock), 0, s, pts, n, (uint32_t)d, partial);
+}
+
+// More than kMaxDim axes: 64-bit keys, the sort carries input indices only,
+// and the rows are gathered afterwards.
+void launch_sort_hd(Plan &P, SortBuffers &B, hipStream_t s)
+{
+    const int hb = (int)std::min<uint64_t>((P.n + kBlock * 16 - 1) / (kBlock * 16), 256);
+    uint64_t *ka = (uint64_t *)B.keys_a, *kb = (uint64_t *)B.keys_b;
+    uint32_t *va = B.vals_a, *vb = B.vals_b;
+    hipLaunchKernelGGL(k_hd_keys_hist, dim3(hb), dim3(kBlock), 0, s, P, ka, va, B.hist);
+    const uint32_t tiles = (P.n + kSortTile - 1) / kSortTile;
+    for (uint32_t q = 0; q < P.passes; q++) {
+        uint64_t *st = B.status + (uint64_t)q * tiles * kRadix;
+        hipLaunchKernelGGL((k_onesweep<uint64_t, 1, false>), dim3(tiles), dim3(kBlock), 0, s, P, ka, va, kb, vb,
+                           q * kRadixBits, B.hist + q * kRadix, st, B.tickets + q);
+        uint64_t *tk = ka; ka = kb; kb = tk;
+        uint32_t *tv = va; va = vb; vb = tv;
+    }
+    B.result_keys = ka;
+    B.result_vals = va;
+    P.sidx = va;
+    const uint64_t rpb = kBlock / P.sd;
+    const int gb = (int)std::min<uint64_t>((P.n + rpb - 1) / rpb, 4096);
+    hipLaunchKernelGGL(k_hd_gather, dim3(gb), dim3(kBlock), 0, s, P);
 }
 
 void launch_cells(const Plan &P, bool wide_keys, uint64_t *status, uint32_t *ticket, hipStream_t s)

@@ -90,8 +90,25 @@ def test_argument_checks_without_device(lib):
     assert lib.hca_create(None, 0) == hca.HCA_E_INVAL
     geo = hca.Geometry()
     assert lib.hca_get_geometry(1.0, 0, ctypes.byref(geo)) == hca.HCA_E_INVAL
-    assert lib.hca_get_geometry(1.0, 9, ctypes.byref(geo)) == hca.HCA_E_INVAL
+    assert lib.hca_get_geometry(1.0, 65, ctypes.byref(geo)) == hca.HCA_E_INVAL
     assert lib.hca_get_geometry(-1.0, 2, ctypes.byref(geo)) == hca.HCA_E_INVAL
+
+
+def test_geometry_many_axes(lib):
+    """d > 8: cube side floor(sqrt(floor(eps^2 / d))) (space diagonal at most
+    eps, Overlaying Hypercubes), groups of ceil(sqrt(eps2) / side) cubes so
+    their side reaches eps, no enumerable stencil."""
+    geo = hca.Geometry()
+    for d in (9, 16, 27, 54, 64):
+        for eps in (0.5, 1.0, 7.3, 61.44, 245.76, 4096.0, 123456.7):
+            assert lib.hca_get_geometry(eps, d, ctypes.byref(geo)) == hca.HCA_OK
+            e2 = math.floor(Fraction(eps) ** 2)
+            side = max(1, math.isqrt(e2 // d))
+            assert geo.eps2 == e2 and geo.side == side
+            assert d * side * side <= max(e2, d)
+            assert geo.group == max(1, -(-math.isqrt(e2) // side))
+            assert geo.group * side >= math.isqrt(e2)
+            assert geo.stencil == -1 and geo.group_stencil == -1 and geo.reps == 0
 
 
 def test_no_cpu_fallback_in_binding():
