@@ -398,7 +398,12 @@ void carve_ws(Carver &cv, Plan &P, SortBuffers &B, const Sizes &Z, uint32_t **ze
 {
     const uint32_t n = P.n;
     cv.take<int32_t>((size_t)kBboxBlocks * 2 * kMaxDimHigh);
-    if (P.hd) P.hd_origin = cv.take<int32_t>(kMaxDimHigh);
+    if (P.hd) {
+        P.hd_origin = cv.take<int32_t>(kMaxDimHigh);
+        P.hd_list = cv.take<uint32_t>((size_t)2 * n);
+        P.hd_rec = cv.take<uint32_t>((size_t)kHdRec * n);
+        P.hd_nrec = cv.take<uint8_t>(n);
+    }
     const size_t ksz = Z.wide_keys ? 8 : 4;
     B.keys_a = cv.take<char>((size_t)n * ksz);
     B.keys_b = cv.take<char>((size_t)n * ksz);

@@ -280,6 +280,17 @@ __device__ __forceinline__ void hd_stage(const Plan &P, uint32_t pc, uint32_t np
     __builtin_amdgcn_wave_barrier();
 }
 
+// The 8 rows at sorted positions pos[0..8) (wave-uniform) into LDS.
+__device__ __forceinline__ void hd_stage_at(const Plan &P, const uint32_t *pos, int32_t (*own)[kMaxDimHigh])
+{
+    const uint32_t sd = P.sd, l = lane_id();
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int k = 0; k < kPch; k++)
+        if (l < sd) own[k][l] = P.spts[(uint64_t)pos[k] * sd + l];
+    __builtin_amdgcn_wave_barrier();
+}
+
 // Box of the staged points flagged in mask, into qb[0, sd) and qb[sd, 2 sd).
 __device__ __forceinline__ void hd_chunk_box(const Plan &P, const int32_t (*own)[kMaxDimHigh], uint32_t mask,
                                              int32_t *qb)
@@ -300,19 +311,43 @@ __device__ __forceinline__ void hd_chunk_box(const Plan &P, const int32_t (*own)
     __builtin_amdgcn_wave_barrier();
 }
 
-// Candidates of slots [first, first + 64): lane l resolves slot first + l; a
-// group is dropped when it has no core point (need_core) or its box is
-// farther than eps from the query box qb.  Returns the candidate count.
-__device__ __forceinline__ uint32_t hd_load_neighbours(const Plan &P, uint32_t g, const HdSrc &src, uint32_t first,
-                                                       bool need_core, const int32_t *qb, uint32_t *s_beg,
-                                                       uint32_t *s_pre)
+// Squared gap between a staged point and a group box; stops once above eps2.
+__device__ __forceinline__ int64_t hd_point_box_gap2(const int32_t *p, const int32_t *b, uint32_t sd, int64_t eps2)
 {
-    const uint32_t l = lane_id(), j = first + l;
+    int64_t acc = 0;
+    for (uint32_t e = 0; e < sd && acc <= eps2; e++) {
+        const int64_t gap = max((int64_t)b[e] - p[e], (int64_t)p[e] - b[sd + e]);
+        if (gap > 0) acc += gap * gap;
+    }
+    return acc;
+}
+
+// Candidates of slots [first, first + 64): lane l resolves slot first + l.  A
+// group is dropped when it has no core point (need_core), when its box is
+// farther than eps from the query box qb or from every staged point in
+// `mask`, or (skip_root != kNone) when all its core cubes already share the
+// root skip_root.  Returns the candidate count.
+__device__ __forceinline__ uint32_t hd_load_neighbours(const Plan &P, uint32_t g, const HdSrc &src, uint32_t first,
+                                                       bool need_core, const int32_t *qb,
+                                                       const int32_t (*own)[kMaxDimHigh], uint32_t mask,
+                                                       uint32_t skip_root, uint32_t *s_beg, uint32_t *s_pre)
+{
+    const uint32_t l = lane_id(), j = first + l, sd = P.sd;
+    const int64_t eps2 = P.eps2;
     uint32_t a = 0, size = 0;
     if (j < src.slots) {
         const uint32_t G = hd_slot(P, g, src, j);
-        if (!(need_core && P.gcube[G] == kNone) &&
-            hd_box_gap2(qb, P.gbox + (uint64_t)G * 2 * P.sd, P.sd, P.eps2) <= P.eps2) {
+        const int32_t *gb = P.gbox + (uint64_t)G * 2 * sd;
+        bool keep = !(need_core && P.gcube[G] == kNone) && hd_box_gap2(qb, gb, sd, eps2) <= eps2;
+        if (keep && __popc(mask) > 1) {
+            bool nearby = false;
+#pragma unroll
+            for (int k = 0; k < kPch; k++)
+                if (!nearby && (mask & (1u << k))) nearby = hd_point_box_gap2(own[k], gb, sd, eps2) <= eps2;
+            keep = nearby;
+        }
+        if (keep && skip_root != kNone && P.unified[G] && uf_find(P.parent, P.gcube[G]) == skip_root) keep = false;
+        if (keep) {
             a = P.group_start[G];
             size = P.group_start[G + 1] - a;
         }
@@ -327,7 +362,8 @@ __device__ __forceinline__ uint32_t hd_load_neighbours(const Plan &P, uint32_t g
 
 // Squared distances from the candidate row at sorted position pos to the 8
 // staged points (exact: 64-bit, or 32-bit when the host has shown that every
-// tested pair's sum fits).
+// tested pair's sum fits).  The 32-bit form loads the whole row before any
+// arithmetic; the 64-bit form, short of registers, goes 16 bytes at a time.
 template <bool WIDE>
 __device__ __forceinline__ void hd_dist(const Plan &P, const int32_t (*own)[kMaxDimHigh], uint32_t pos, int64_t *dd)
 {
@@ -350,15 +386,23 @@ __device__ __forceinline__ void hd_dist(const Plan &P, const int32_t (*own)[kMax
 #pragma unroll
         for (int k = 0; k < kPch; k++) dd[k] = acc[k];
     } else {
+        // the whole row in flight at once (one memory latency per candidate)
+        int4 v[kMaxDimHigh / 4];
+#pragma unroll
+        for (int e = 0; e < kMaxDimHigh / 4; e++) {
+            v[e] = make_int4(0, 0, 0, 0);
+            if ((uint32_t)e < n4) v[e] = row[e];
+        }
         int32_t acc[kPch];
 #pragma unroll
         for (int k = 0; k < kPch; k++) acc[k] = 0;
-        for (uint32_t e = 0; e < n4; e++) {
-            const int4 v = row[e];
+#pragma unroll
+        for (int e = 0; e < kMaxDimHigh / 4; e++) {
+            if ((uint32_t)e >= n4) continue;
 #pragma unroll
             for (int k = 0; k < kPch; k++) {
                 const int4 o = reinterpret_cast<const int4 *>(own[k])[e];
-                const int32_t a = v.x - o.x, b = v.y - o.y, c = v.z - o.z, f = v.w - o.w;
+                const int32_t a = v[e].x - o.x, b = v[e].y - o.y, c = v[e].z - o.z, f = v[e].w - o.w;
                 acc[k] += __mul24(a, a) + __mul24(b, b) + __mul24(c, c) + __mul24(f, f);
             }
         }
@@ -379,17 +423,23 @@ __device__ __forceinline__ uint32_t hd_candidate(uint32_t c, const uint32_t *s_b
 // points within eps in its group and the listed neighbours, stopping at
 // minPts.  Per cube: core points and the smallest core input index.
 // ---------------------------------------------------------------------------
+// Stops after `budget` candidates; *cut tells whether it stopped there with
+// points left undecided.
+// The first kHdRec neighbours found of staged point k (sorted position
+// qpos[k]) are recorded for merging.
 template <bool WIDE>
 __device__ __forceinline__ uint32_t hd_count_walk(const Plan &P, uint32_t g, const int32_t (*own)[kMaxDimHigh],
-                                                  uint32_t done, uint32_t *cnt, int32_t *qb, uint32_t *s_beg,
-                                                  uint32_t *s_pre, uint32_t &lt)
+                                                  const uint32_t *qpos, uint32_t done, uint32_t *cnt, int32_t *qb,
+                                                  uint32_t *s_beg, uint32_t *s_pre, uint32_t &lt, uint32_t budget,
+                                                  bool *cut)
 {
     const uint32_t l = lane_id(), minpts = (uint32_t)P.min_pts, all = (1u << kPch) - 1u;
     hd_chunk_box(P, own, ~done & all, qb);
     const HdSrc src = hd_source(P, g, false);
-    for (uint32_t oc = 0; oc < src.slots && done != all; oc += kWave) {
-        const uint32_t total = hd_load_neighbours(P, g, src, oc, false, qb, s_beg, s_pre);
-        for (uint32_t ci = 0; ci < total && done != all; ci += kWave) {
+    uint32_t seen = 0;
+    for (uint32_t oc = 0; oc < src.slots && done != all && seen < budget; oc += kWave) {
+        const uint32_t total = hd_load_neighbours(P, g, src, oc, false, qb, own, ~done & all, kNone, s_beg, s_pre);
+        for (uint32_t ci = 0; ci < total && done != all && seen < budget; ci += kWave, seen += kWave) {
             const uint32_t c = ci + l;
             const bool ok = c < total;
             const uint32_t pos = ok ? hd_candidate(c, s_beg, s_pre) : 0u;
@@ -399,15 +449,48 @@ __device__ __forceinline__ uint32_t hd_count_walk(const Plan &P, uint32_t g, con
             for (int k = 0; k < kPch; k++) {
                 if (done & (1u << k)) continue;
                 lt += ok;
-                cnt[k] += __popcll(__ballot(ok && dd[k] <= P.eps2));
+                const bool hit = ok && dd[k] <= P.eps2;
+                const uint64_t hm = __ballot(hit);
+                if (hm && cnt[k] < (uint32_t)kHdRec) {
+                    const uint32_t r = cnt[k] + __popcll(hm & __lanemask_lt());
+                    if (hit && r < (uint32_t)kHdRec) P.hd_rec[(uint64_t)qpos[k] * kHdRec + r] = pos;
+                }
+                cnt[k] += __popcll(hm);
                 if (cnt[k] >= minpts) done |= 1u << k;
             }
             done = uniform(done);
         }
     }
+    *cut = done != all && seen >= budget;
     return done;
 }
 
+// Candidates a point of the first core pass looks at before it is left to
+// the second pass (which walks chunks of such points only).
+constexpr uint32_t kHdCoreBudget = 16384;
+
+// Per-cube tallies of a chunk's decided core points: one atomic per cube.
+__device__ __forceinline__ void hd_tally(const Plan &P, bool in, uint32_t cell, bool core, uint32_t me)
+{
+    const uint32_t l = lane_id();
+    uint64_t pend = __ballot(in && core);
+    while (pend) {
+        const uint32_t k0 = __ffsll((unsigned long long)pend) - 1;
+        const uint32_t c = __shfl(cell, k0);
+        const bool mine = in && core && cell == c;
+        const uint64_t same = __ballot(mine);
+        const uint32_t mn = wave_min(mine ? me : kNone);
+        if (l == k0) {
+            atomicAdd(P.ncore + c, (uint32_t)__popcll(same));
+            atomicMin(P.cmin + c, mn);
+        }
+        pend &= ~same;
+    }
+}
+
+// First pass: chunks of 8 consecutive sorted points, each point looking at
+// up to kHdCoreBudget candidates; points still undecided are appended to
+// the list of the second pass.
 template <bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_hd_core(Plan P)
 {
@@ -427,10 +510,13 @@ __global__ __launch_bounds__(kBlock) void k_hd_core(Plan P)
             grp = P.group_of[cell];
             dense = P.cell_start[cell + 1] - P.cell_start[cell] >= minpts;
         }
-        uint32_t done = (uint32_t)__ballot(dense) & all;
+        uint32_t done = (uint32_t)__ballot(dense) & all, undec = 0;
         uint32_t cnt[kPch];
 #pragma unroll
         for (int k = 0; k < kPch; k++) cnt[k] = 0;
+        uint32_t qpos[kPch];
+#pragma unroll
+        for (int k = 0; k < kPch; k++) qpos[k] = pc + min((uint32_t)k, np - 1);
         if (done != all) {
             hd_stage(P, pc, np, s_own[w]);
             uint32_t left = ~done & all;
@@ -438,29 +524,82 @@ __global__ __launch_bounds__(kBlock) void k_hd_core(Plan P)
                 const uint32_t g = __shfl(grp, __ffs(left) - 1);
                 const uint32_t run = (uint32_t)__ballot(grp == g) & left;
                 left &= ~run;
-                done |= hd_count_walk<WIDE>(P, g, s_own[w], ~run & all, cnt, s_qb[w], s_beg[w], s_pre[w], lt) & run;
+                bool cut;
+                const uint32_t got = hd_count_walk<WIDE>(P, g, s_own[w], qpos, ~run & all, cnt, s_qb[w], s_beg[w],
+                                                         s_pre[w], lt, kHdCoreBudget, &cut);
+                done |= got & run;
+                if (cut) undec |= run & ~got;
             }
         }
         uint32_t mine = 0;
 #pragma unroll
         for (int k = 0; k < kPch; k++)
             if ((uint32_t)k == l) mine = cnt[k];
-        const bool core = l < np && (dense || mine >= minpts);
-        if (l < np) P.core[pc + l] = core;
-        const uint32_t me = core ? P.sidx[pc + l] : kNone;
-        uint64_t pend = __ballot(l < np);
-        while (pend) {
-            const uint32_t k0 = __ffsll((unsigned long long)pend) - 1;
-            const uint32_t c = __shfl(cell, k0);
-            const uint64_t same = __ballot(l < np && cell == c);
-            const uint32_t cores = (uint32_t)__popcll(__ballot(l < np && cell == c && core));
-            const uint32_t mn = wave_min(cell == c ? me : kNone);
-            if (l == k0 && cores) {
-                atomicAdd(P.ncore + c, cores);
-                atomicMin(P.cmin + c, mn);
-            }
-            pend &= ~same;
+        const bool in = l < np, later = in && ((undec >> l) & 1u);
+        const bool core = in && !later && (dense || mine >= minpts);
+        if (in && !later) {
+            P.core[pc + l] = core;
+            P.hd_nrec[pc + l] = (uint8_t)min(dense ? 0u : mine, (uint32_t)kHdRec);
         }
+        const uint64_t um = __ballot(later);
+        if (um) {
+            uint32_t base = 0;
+            if (l == 0) base = atomicAdd(&P.ctr->hd_left, (uint32_t)__popcll(um));
+            base = __shfl(base, 0);
+            if (later) P.hd_list[base + __popcll(um & __lanemask_lt())] = pc + l;
+        }
+        hd_tally(P, in, cell, core, core ? P.sidx[pc + l] : kNone);
+    }
+    flush_tests(P, kTestsCore, lt);
+}
+
+// Second pass: chunks of 8 points of the list, walked to the end.
+template <bool WIDE>
+__global__ __launch_bounds__(kBlock) void k_hd_core_rest(Plan P)
+{
+    __shared__ __align__(16) int32_t s_own[kWavesPerBlock][kPch][kMaxDimHigh];
+    __shared__ int32_t s_qb[kWavesPerBlock][2 * kMaxDimHigh];
+    __shared__ uint32_t s_beg[kWavesPerBlock][kWave], s_pre[kWavesPerBlock][kWave];
+    const uint32_t w = wave_in_block(), l = lane_id();
+    const uint32_t nl = ld_agent32(&P.ctr->hd_left), minpts = (uint32_t)P.min_pts;
+    const uint32_t all = (1u << kPch) - 1u;
+    uint32_t lt = 0;
+    const DynRange dr_ = dyn_range(P.ctr->dyn[kDynCoreRest]);
+    HCA_FOR_UNITS_DYN(u, (nl + kPch - 1) / kPch, dr_) {
+        const uint32_t b0 = u * kPch, np = min((uint32_t)kPch, nl - b0);
+        uint32_t pos[kPch];
+#pragma unroll
+        for (int k = 0; k < kPch; k++) pos[k] = P.hd_list[b0 + min((uint32_t)k, np - 1)];
+        uint32_t q = pos[0];
+#pragma unroll
+        for (int k = 1; k < kPch; k++)
+            if ((uint32_t)k == l) q = pos[k];
+        const bool in = l < np;
+        const uint32_t cell = in ? P.cell_of[q] : kNone;
+        const uint32_t grp = in ? P.group_of[cell] : kNone;
+        hd_stage_at(P, pos, s_own[w]);
+        uint32_t cnt[kPch];
+#pragma unroll
+        for (int k = 0; k < kPch; k++) cnt[k] = 0;
+        uint32_t left = (uint32_t)__ballot(in) & all;
+        while (left) {
+            const uint32_t g = __shfl(grp, __ffs(left) - 1);
+            const uint32_t run = (uint32_t)__ballot(grp == g) & left;
+            left &= ~run;
+            bool cut;
+            (void)hd_count_walk<WIDE>(P, g, s_own[w], pos, ~run & all, cnt, s_qb[w], s_beg[w], s_pre[w], lt, ~0u,
+                                      &cut);
+        }
+        uint32_t mine = 0;
+#pragma unroll
+        for (int k = 0; k < kPch; k++)
+            if ((uint32_t)k == l) mine = cnt[k];
+        const bool core = in && mine >= minpts;
+        if (in) {
+            P.core[q] = core;
+            P.hd_nrec[q] = (uint8_t)min(mine, (uint32_t)kHdRec);
+        }
+        hd_tally(P, in, cell, core, core ? P.sidx[q] : kNone);
     }
     flush_tests(P, kTestsCore, lt);
 }
@@ -492,7 +631,17 @@ __device__ __forceinline__ void hd_link_walk(const Plan &P, uint32_t g, const in
 #pragma unroll
     for (int k = 0; k < kPch; k++) rk[k] = (run & (1u << k)) ? uf_find(P.parent, ck[k]) : kNone;
     for (uint32_t oc = 0; oc < src.slots; oc += kWave) {
-        const uint32_t total = hd_load_neighbours(P, g, src, oc, true, qb, s_beg, s_pre);
+        // the root all the walking points share, if they do
+        uint32_t common = kNone;
+        bool one = true;
+#pragma unroll
+        for (int k = 0; k < kPch; k++) {
+            if (!(run & (1u << k))) continue;
+            if (common == kNone) common = rk[k];
+            else one = one && rk[k] == common;
+        }
+        if (!one) common = kNone;
+        const uint32_t total = hd_load_neighbours(P, g, src, oc, true, qb, own, run, common, s_beg, s_pre);
         for (uint32_t ci = 0; ci < total; ci += kWave) {
             const uint32_t c = ci + l;
             bool ok = c < total;
@@ -524,6 +673,9 @@ __device__ __forceinline__ void hd_link_walk(const Plan &P, uint32_t g, const in
     }
 }
 
+// After the recorded pairs are joined: the whole walk, where a group whose
+// core cubes all share the walking points' root is skipped without looking
+// at its points.
 template <bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_hd_merge(Plan P)
 {
@@ -556,6 +708,44 @@ __global__ __launch_bounds__(kBlock) void k_hd_merge(Plan P)
     flush_tests(P, kTestsMerge, lt);
 }
 
+// The pairs recorded by core marking: each core point joins its cube with
+// those of its recorded core neighbours (all within eps), no test needed.
+__global__ __launch_bounds__(kBlock) void k_hd_link_recorded(Plan P)
+{
+    for (uint32_t q = blockIdx.x * kBlock + threadIdx.x; q < P.n; q += gridDim.x * kBlock) {
+        if (!P.core[q]) continue;
+        const uint32_t c = P.cell_of[q], nr = P.hd_nrec[q];
+        for (uint32_t r = 0; r < nr; r++) {
+            const uint32_t q2 = P.hd_rec[(uint64_t)q * kHdRec + r];
+            if (!P.core[q2]) continue;
+            const uint32_t c2 = P.cell_of[q2];
+            if (c2 != c) uf_union(P.parent, c, c2);
+        }
+    }
+}
+
+// Before the walk: whether all core cubes of each group share one root
+// (one wave per group; the group's cubes are consecutive).
+__global__ __launch_bounds__(kBlock) void k_hd_unify(Plan P)
+{
+    const uint32_t l = lane_id();
+    const uint32_t ng = ld_agent32(&P.ctr->n_groups);
+    const WaveRange hca_wr_ = wave_range();
+    HCA_FOR_UNITS(g, ng) {
+        const uint32_t first = P.gcube[g];
+        bool unified = first != kNone;
+        if (unified) {
+            const uint32_t r0 = uf_find(P.parent, first), c1 = P.group_cell[g + 1];
+            for (uint32_t cb = first; cb < c1 && unified; cb += kWave) {
+                const uint32_t c = cb + l;
+                const bool other = c < c1 && P.ncore[c] > 0 && uf_find(P.parent, c) != r0;
+                unified = __ballot(other) == 0;
+            }
+        }
+        if (l == 0) P.unified[g] = unified;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Border points: each non-core point of a chunk takes the root of its nearest
 // core point within eps (ties to the smaller input index); none -> noise.
@@ -570,7 +760,7 @@ __device__ __forceinline__ void hd_border_walk(const Plan &P, uint32_t g, const 
     hd_chunk_box(P, own, todo, qb);
     const HdSrc src = hd_source(P, g, false);
     for (uint32_t oc = 0; oc < src.slots; oc += kWave) {
-        const uint32_t total = hd_load_neighbours(P, g, src, oc, true, qb, s_beg, s_pre);
+        const uint32_t total = hd_load_neighbours(P, g, src, oc, true, qb, own, todo, kNone, s_beg, s_pre);
         for (uint32_t ci = 0; ci < total; ci += kWave) {
             const uint32_t c = ci + l;
             bool ok = c < total;
@@ -600,6 +790,27 @@ __device__ __forceinline__ void hd_border_walk(const Plan &P, uint32_t g, const 
     }
 }
 
+// Non-core points (sorted positions, in runs of a wave) into the second half
+// of the list.
+__global__ __launch_bounds__(kBlock) void k_hd_noncore_list(Plan P)
+{
+    const uint32_t l = lane_id();
+    for (uint32_t base = (blockIdx.x * kBlock + threadIdx.x) & ~(kWave - 1u); base < P.n;
+         base += gridDim.x * kBlock) {
+        const uint32_t q = base + l;
+        const bool nc = q < P.n && !P.core[q];
+        const uint64_t m = __ballot(nc);
+        if (!m) continue;
+        uint32_t at = 0;
+        if (l == 0) at = atomicAdd(&P.ctr->hd_noncore, (uint32_t)__popcll(m));
+        at = __shfl(at, 0);
+        if (nc) P.hd_list[P.n + at + __popcll(m & __lanemask_lt())] = q;
+    }
+}
+
+// Chunks of 8 non-core points of the list.  Each takes the root of its
+// nearest core point within eps (ties to the smaller input index) and offers
+// its input index to that cluster's smallest member; none -> noise.
 template <bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_hd_border(Plan P)
 {
@@ -607,16 +818,23 @@ __global__ __launch_bounds__(kBlock) void k_hd_border(Plan P)
     __shared__ int32_t s_qb[kWavesPerBlock][2 * kMaxDimHigh];
     __shared__ uint32_t s_beg[kWavesPerBlock][kWave], s_pre[kWavesPerBlock][kWave];
     const uint32_t w = wave_in_block(), l = lane_id();
-    const uint32_t n = P.n;
+    const uint32_t nl = ld_agent32(&P.ctr->hd_noncore);
+    const uint32_t *list = P.hd_list + P.n;
     uint32_t lt = 0;
     const DynRange dr_ = dyn_range(P.ctr->dyn[kDynBorder]);
-    HCA_FOR_UNITS_DYN(u, (n + kPch - 1) / kPch, dr_) {
-        const uint32_t pc = u * kPch, np = min((uint32_t)kPch, n - pc);
-        const bool mine = l < np && !P.core[pc + l];
-        const uint32_t todo = (uint32_t)__ballot(mine) & ((1u << kPch) - 1u);
-        if (!todo) continue;
-        const uint32_t grp = mine ? P.group_of[P.cell_of[pc + l]] : kNone;
-        hd_stage(P, pc, np, s_own[w]);
+    HCA_FOR_UNITS_DYN(u, (nl + kPch - 1) / kPch, dr_) {
+        const uint32_t b0 = u * kPch, np = min((uint32_t)kPch, nl - b0);
+        uint32_t pos[kPch];
+#pragma unroll
+        for (int k = 0; k < kPch; k++) pos[k] = list[b0 + min((uint32_t)k, np - 1)];
+        uint32_t q = pos[0];
+#pragma unroll
+        for (int k = 1; k < kPch; k++)
+            if ((uint32_t)k == l) q = pos[k];
+        const bool in = l < np;
+        const uint32_t todo = (uint32_t)__ballot(in) & ((1u << kPch) - 1u);
+        const uint32_t grp = in ? P.group_of[P.cell_of[q]] : kNone;
+        hd_stage_at(P, pos, s_own[w]);
         int64_t bd[kPch];
         uint32_t bi[kPch], bp[kPch];
 #pragma unroll
@@ -628,7 +846,26 @@ __global__ __launch_bounds__(kBlock) void k_hd_border(Plan P)
             left &= ~run;
             hd_border_walk<WIDE>(P, g, s_own[w], run, bd, bi, bp, s_qb[w], s_beg[w], s_pre[w], lt);
         }
-        border_finish(P, pc, todo, bd, bi, bp);
+#pragma unroll
+        for (int k = 0; k < kPch; k++) {
+            if (!(todo & (1u << k))) continue;
+            int64_t d0 = bd[k];
+            uint32_t i0 = bi[k], q0 = bp[k];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const int64_t d1 = __shfl_xor(d0, o);
+                const uint32_t i1 = __shfl_xor(i0, o), q1 = __shfl_xor(q0, o);
+                if (d1 < d0 || (d1 == d0 && i1 < i0)) { d0 = d1; i0 = i1; q0 = q1; }
+            }
+            if (l == 0) {
+                const uint32_t root = q0 == kNone ? kNone : ld_parent(P.parent + P.cell_of[q0]);
+                P.owner[pos[k]] = root;
+                if (root != kNone) {
+                    const uint32_t me = P.sidx[pos[k]];
+                    if (me < ld_agent32(P.minmem + root)) atomicMin(P.minmem + root, me);
+                }
+            }
+        }
     }
     flush_tests(P, kTestsBorder, lt);
 }
@@ -654,20 +891,30 @@ void launch_hd_lists(const Plan &P, int blocks, hipStream_t s)
 
 void launch_hd_core(const Plan &P, int blocks, hipStream_t s)
 {
-    if (P.wide) hipLaunchKernelGGL(k_hd_core<true>, dim3(blocks), dim3(kBlock), 0, s, P);
-    else hipLaunchKernelGGL(k_hd_core<false>, dim3(blocks), dim3(kBlock), 0, s, P);
+    if (P.wide) {
+        hipLaunchKernelGGL(k_hd_core<true>, dim3(blocks), dim3(kBlock), 0, s, P);
+        hipLaunchKernelGGL(k_hd_core_rest<true>, dim3(blocks), dim3(kBlock), 0, s, P);
+    } else {
+        hipLaunchKernelGGL(k_hd_core<false>, dim3(blocks), dim3(kBlock), 0, s, P);
+        hipLaunchKernelGGL(k_hd_core_rest<false>, dim3(blocks), dim3(kBlock), 0, s, P);
+    }
     const int cb = (int)std::min<uint64_t>((P.n + kBlock - 1) / kBlock, 1024);
     hipLaunchKernelGGL(k_hd_gcore, dim3(cb), dim3(kBlock), 0, s, P);
 }
 
 void launch_hd_merge(const Plan &P, int blocks, hipStream_t s)
 {
+    const int cb = (int)std::min<uint64_t>((P.n + kBlock - 1) / kBlock, 2048);
+    hipLaunchKernelGGL(k_hd_link_recorded, dim3(cb), dim3(kBlock), 0, s, P);
+    hipLaunchKernelGGL(k_hd_unify, dim3(blocks), dim3(kBlock), 0, s, P);
     if (P.wide) hipLaunchKernelGGL(k_hd_merge<true>, dim3(blocks), dim3(kBlock), 0, s, P);
     else hipLaunchKernelGGL(k_hd_merge<false>, dim3(blocks), dim3(kBlock), 0, s, P);
 }
 
 void launch_hd_border(const Plan &P, int blocks, hipStream_t s)
 {
+    const int cb = (int)std::min<uint64_t>((P.n + kBlock - 1) / kBlock, 2048);
+    hipLaunchKernelGGL(k_hd_noncore_list, dim3(cb), dim3(kBlock), 0, s, P);
     if (P.wide) hipLaunchKernelGGL(k_hd_border<true>, dim3(blocks), dim3(kBlock), 0, s, P);
     else hipLaunchKernelGGL(k_hd_border<false>, dim3(blocks), dim3(kBlock), 0, s, P);
 }

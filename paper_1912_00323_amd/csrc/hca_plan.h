@@ -9,6 +9,7 @@ namespace hca {
 
 constexpr int kMaxDim = 8;                     // axes of the packed cube key
 constexpr int kMaxDimHigh = 64;                // axes of a point (more than 8: hashed cubes)
+constexpr int kHdRec = 8;                      // neighbours recorded per point (more than 8 axes)
 constexpr int kWave = 64;
 constexpr int kBlock = 256;                    // 4 waves per workgroup
 constexpr uint32_t kNone = 0xFFFFFFFFu;
@@ -50,17 +51,19 @@ struct Counters {
     uint32_t nbr_overflow;      // groups whose neighbour list did not fit
     uint32_t hmask;             // hash slots in use - 1 (a power of two - 1)
     uint32_t nbr_ticket;        // tiles of the backward-list scan
-    uint32_t pad[8];
+    uint32_t hd_left;           // more than kMaxDim axes: points left undecided by the first core pass
+    uint32_t hd_noncore;        // more than kMaxDim axes: non-core points
+    uint32_t pad[6];
     uint32_t work_count[kWorkRegions * kCounterStride];   // region r at [r * kCounterStride]
     // pair tests executed, per phase (core, merge, border), spread over
     // kWorkRegions lines of eight 64-bit words; counted only on request
     unsigned long long tests[4][kWorkRegions * 8];
     // work queues of the dynamically balanced kernels: [kernel][64 queues]
-    uint32_t dyn[4][kWorkRegions * kCounterStride];
+    uint32_t dyn[6][kWorkRegions * kCounterStride];
 };
 
 enum { kTestsCore = 0, kTestsMerge = 1, kTestsBorder = 2, kTestsIntra = 3 };
-enum { kDynLists = 0, kDynCore = 1, kDynBorder = 2, kDynMerge = 3 };
+enum { kDynLists = 0, kDynCore = 1, kDynBorder = 2, kDynMerge = 3, kDynCoreRest = 4, kDynMergeRest = 5 };
 
 // One data set of a batch: its exact eps^2, minPts, cube side and origin,
 // where its rows sit, and (filled on the device) the clusters of the data
@@ -108,6 +111,9 @@ struct Plan {
     uint32_t kd;
     uint8_t kdim[kMaxDim];
     const int32_t *hd_origin;   // [d] origin of every axis (hd)
+    uint32_t *hd_list;          // [2n] sorted positions: undecided points, then non-core points (hd)
+    uint32_t *hd_rec;           // [n][kHdRec] first neighbours found by core marking (sorted positions, hd)
+    uint8_t *hd_nrec;           // [n] how many of them were recorded (hd)
     // neighbour search over groups: offsets in [-R, R]^d, self first
     uint32_t n_off;
     const int8_t *off;          // [n_off][d]

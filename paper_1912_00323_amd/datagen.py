@@ -101,6 +101,20 @@ def _cfg_8d_500k(seed: int, n: int = 500_000) -> Workload:
                     0.06 * 2 ** q, 10, q, {"eps_real": 0.06, "seed": seed})
 
 
+def make_high(d: int, n: int, seed: int = 6) -> Workload:
+    """Data with many axes, built like the 8-D workload: 20 blobs (std 0.02),
+    5 % noise, 2^-12 units, minPts 10, and eps = 0.015 * sqrt(2 d) (0.06 at
+    d = 8: three quarters of the typical distance between two points of a
+    blob).  At d = 54 and n = 3,850,505 it has the shape of the paper's
+    largest data set (PAMAP2, Table 1)."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, d, n])))
+    q = 12
+    eps = 0.015 * float(np.sqrt(2.0 * d))
+    x = make_blobs(rng, n, d, 20, 0.02, 0.05, "equal")
+    return Workload(f"blobs{d}d_{n}", quantise(x, q), eps * 2 ** q, 10, q,
+                    {"eps_real": eps, "seed": seed})
+
+
 def make_mixed(seed: int, n: int, d: int, q: int = 14) -> Workload:
     """One job of the mixed-size family: 3-30 blobs with per-blob std uniform in
     [0.005, 0.03], 5-15 % noise, eps uniform in [0.005, 0.03], minPts in 4..12."""
