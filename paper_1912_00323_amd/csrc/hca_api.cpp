@@ -403,6 +403,7 @@ void carve_ws(Carver &cv, Plan &P, SortBuffers &B, const Sizes &Z, uint32_t **ze
         P.hd_list = cv.take<uint32_t>((size_t)2 * n);
         P.hd_rec = cv.take<uint32_t>((size_t)kHdRec * n);
         P.hd_nrec = cv.take<uint8_t>(n);
+        P.spts16 = P.hd16 ? cv.take<uint32_t>((size_t)n * (P.sd / 2)) : nullptr;
     }
     const size_t ksz = Z.wide_keys ? 8 : 4;
     B.keys_a = cv.take<char>((size_t)n * ksz);
@@ -674,7 +675,7 @@ hca_status run_hd(hca_ctx *ctx, const int32_t *points, uint32_t n, int32_t d, do
     P.min_pts = min_pts;
     P.eps2 = eps2;
     P.hd = 1;
-    P.sd = ((uint32_t)d + 3u) & ~3u;
+    P.sd = ((uint32_t)d + 7u) & ~7u;
     const uint64_t side = std::max<uint64_t>(1, isqrt_u64((uint64_t)eps2 / (uint64_t)d));
     const uint64_t E = isqrt_u64((uint64_t)eps2);
     const uint64_t m = std::max<uint64_t>(1, (E + side - 1) / side);
@@ -714,6 +715,12 @@ hca_status run_hd(hca_ctx *ctx, const int32_t *points, uint32_t n, int32_t d, do
     P.fine_bits = P.key_bits - gbits;                 // hash bits
     P.passes = (P.key_bits + kRadixBits - 1) / kRadixBits;
     P.wide = reach >= ((unsigned __int128)1 << 31) ? 1 : 0;
+    // packed int16 rows when every span is below 2^15 and sums fit 32 bits
+    // (HCA_PACKED=0 turns them off)
+    bool narrow16 = !P.wide;
+    for (int k = 0; k < d; k++) narrow16 = narrow16 && mx[k] - mn[k] < (1ll << 15);
+    if (const char *e = std::getenv("HCA_PACKED")) narrow16 = narrow16 && std::strcmp(e, "0") != 0;
+    P.hd16 = narrow16 ? 1u : 0u;
     P.list_w = 3;
     Sizes Z;
     plan_sizes(P, gbits, stats != nullptr && ctx->prof != -1, stats != nullptr, &Z);

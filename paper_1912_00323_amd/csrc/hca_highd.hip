@@ -20,6 +20,20 @@
 
 namespace hca {
 
+// A staged point in LDS: its int32 coordinates, then (packed form) its
+// coordinates less the origin as int16 pairs.
+constexpr int kOwnStride = kMaxDimHigh + kMaxDimHigh / 2;
+
+typedef short short2_t __attribute__((ext_vector_type(2)));
+
+// acc + (a.lo - b.lo)^2 + (a.hi - b.hi)^2 for two packed int16 pairs (their
+// differences fit int16: every span is below 2^15).
+__device__ __forceinline__ int32_t sq_dot16(uint32_t a, uint32_t b, int32_t acc)
+{
+    const short2_t d = __builtin_bit_cast(short2_t, a) - __builtin_bit_cast(short2_t, b);
+    return __builtin_amdgcn_sdot2(d, d, acc, false);
+}
+
 // ---------------------------------------------------------------------------
 // Point box of every group over all axes (lane e owns axis e), the backward
 // list counters cleared, and "no core cube yet" for every group.
@@ -269,7 +283,7 @@ __device__ __forceinline__ uint32_t hd_slot(const Plan &P, uint32_t g, const HdS
 }
 
 // The 8 rows from sorted position pc (the last one repeated past np) into LDS.
-__device__ __forceinline__ void hd_stage(const Plan &P, uint32_t pc, uint32_t np, int32_t (*own)[kMaxDimHigh])
+__device__ __forceinline__ void hd_stage(const Plan &P, uint32_t pc, uint32_t np, int32_t (*own)[kOwnStride])
 {
     const uint32_t sd = P.sd;
     __builtin_amdgcn_wave_barrier();
@@ -277,22 +291,31 @@ __device__ __forceinline__ void hd_stage(const Plan &P, uint32_t pc, uint32_t np
         const uint32_t k = i / sd, e = i - k * sd;
         own[k][e] = P.spts[(uint64_t)(pc + min(k, np - 1)) * sd + e];
     }
+    if (P.spts16) {
+        const uint32_t hw = sd >> 1;
+        for (uint32_t i = lane_id(); i < kPch * hw; i += kWave) {
+            const uint32_t k = i / hw, e = i - k * hw;
+            own[k][kMaxDimHigh + e] = (int32_t)P.spts16[(uint64_t)(pc + min(k, np - 1)) * hw + e];
+        }
+    }
     __builtin_amdgcn_wave_barrier();
 }
 
 // The 8 rows at sorted positions pos[0..8) (wave-uniform) into LDS.
-__device__ __forceinline__ void hd_stage_at(const Plan &P, const uint32_t *pos, int32_t (*own)[kMaxDimHigh])
+__device__ __forceinline__ void hd_stage_at(const Plan &P, const uint32_t *pos, int32_t (*own)[kOwnStride])
 {
     const uint32_t sd = P.sd, l = lane_id();
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int k = 0; k < kPch; k++)
+    for (int k = 0; k < kPch; k++) {
         if (l < sd) own[k][l] = P.spts[(uint64_t)pos[k] * sd + l];
+        if (P.spts16 && l < (sd >> 1)) own[k][kMaxDimHigh + l] = (int32_t)P.spts16[(uint64_t)pos[k] * (sd >> 1) + l];
+    }
     __builtin_amdgcn_wave_barrier();
 }
 
 // Box of the staged points flagged in mask, into qb[0, sd) and qb[sd, 2 sd).
-__device__ __forceinline__ void hd_chunk_box(const Plan &P, const int32_t (*own)[kMaxDimHigh], uint32_t mask,
+__device__ __forceinline__ void hd_chunk_box(const Plan &P, const int32_t (*own)[kOwnStride], uint32_t mask,
                                              int32_t *qb)
 {
     const uint32_t l = lane_id(), sd = P.sd;
@@ -329,7 +352,7 @@ __device__ __forceinline__ int64_t hd_point_box_gap2(const int32_t *p, const int
 // root skip_root.  Returns the candidate count.
 __device__ __forceinline__ uint32_t hd_load_neighbours(const Plan &P, uint32_t g, const HdSrc &src, uint32_t first,
                                                        bool need_core, const int32_t *qb,
-                                                       const int32_t (*own)[kMaxDimHigh], uint32_t mask,
+                                                       const int32_t (*own)[kOwnStride], uint32_t mask,
                                                        uint32_t skip_root, uint32_t *s_beg, uint32_t *s_pre)
 {
     const uint32_t l = lane_id(), j = first + l, sd = P.sd;
@@ -365,7 +388,7 @@ __device__ __forceinline__ uint32_t hd_load_neighbours(const Plan &P, uint32_t g
 // tested pair's sum fits).  The 32-bit form loads the whole row before any
 // arithmetic; the 64-bit form, short of registers, goes 16 bytes at a time.
 template <bool WIDE>
-__device__ __forceinline__ void hd_dist(const Plan &P, const int32_t (*own)[kMaxDimHigh], uint32_t pos, int64_t *dd)
+__device__ __forceinline__ void hd_dist(const Plan &P, const int32_t (*own)[kOwnStride], uint32_t pos, int64_t *dd)
 {
     const int4 *row = reinterpret_cast<const int4 *>(P.spts + (uint64_t)pos * P.sd);
     const uint32_t n4 = P.sd >> 2;
@@ -381,6 +404,33 @@ __device__ __forceinline__ void hd_dist(const Plan &P, const int32_t (*own)[kMax
                 const int64_t a = (int64_t)v.x - o.x, b = (int64_t)v.y - o.y;
                 const int64_t c = (int64_t)v.z - o.z, f = (int64_t)v.w - o.w;
                 acc[k] += a * a + b * b + c * c + f * f;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kPch; k++) dd[k] = acc[k];
+    } else if (P.spts16) {
+        // packed int16 coordinates: two axes per subtract and dot step
+        const uint4 *prow = reinterpret_cast<const uint4 *>(P.spts16 + (uint64_t)pos * (P.sd >> 1));
+        const uint32_t n8 = P.sd >> 3;
+        uint4 v[kMaxDimHigh / 8];
+#pragma unroll
+        for (int e = 0; e < kMaxDimHigh / 8; e++) {
+            v[e] = make_uint4(0, 0, 0, 0);
+            if ((uint32_t)e < n8) v[e] = prow[e];
+        }
+        int32_t acc[kPch];
+#pragma unroll
+        for (int k = 0; k < kPch; k++) acc[k] = 0;
+#pragma unroll
+        for (int e = 0; e < kMaxDimHigh / 8; e++) {
+            if ((uint32_t)e >= n8) continue;
+#pragma unroll
+            for (int k = 0; k < kPch; k++) {
+                const uint4 o = reinterpret_cast<const uint4 *>(own[k] + kMaxDimHigh)[e];
+                acc[k] = sq_dot16(v[e].x, o.x, acc[k]);
+                acc[k] = sq_dot16(v[e].y, o.y, acc[k]);
+                acc[k] = sq_dot16(v[e].z, o.z, acc[k]);
+                acc[k] = sq_dot16(v[e].w, o.w, acc[k]);
             }
         }
 #pragma unroll
@@ -428,7 +478,7 @@ __device__ __forceinline__ uint32_t hd_candidate(uint32_t c, const uint32_t *s_b
 // The first kHdRec neighbours found of staged point k (sorted position
 // qpos[k]) are recorded for merging.
 template <bool WIDE>
-__device__ __forceinline__ uint32_t hd_count_walk(const Plan &P, uint32_t g, const int32_t (*own)[kMaxDimHigh],
+__device__ __forceinline__ uint32_t hd_count_walk(const Plan &P, uint32_t g, const int32_t (*own)[kOwnStride],
                                                   const uint32_t *qpos, uint32_t done, uint32_t *cnt, int32_t *qb,
                                                   uint32_t *s_beg, uint32_t *s_pre, uint32_t &lt, uint32_t budget,
                                                   bool *cut)
@@ -494,7 +544,7 @@ __device__ __forceinline__ void hd_tally(const Plan &P, bool in, uint32_t cell, 
 template <bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_hd_core(Plan P)
 {
-    __shared__ __align__(16) int32_t s_own[kWavesPerBlock][kPch][kMaxDimHigh];
+    __shared__ __align__(16) int32_t s_own[kWavesPerBlock][kPch][kOwnStride];
     __shared__ int32_t s_qb[kWavesPerBlock][2 * kMaxDimHigh];
     __shared__ uint32_t s_beg[kWavesPerBlock][kWave], s_pre[kWavesPerBlock][kWave];
     const uint32_t w = wave_in_block(), l = lane_id();
@@ -557,7 +607,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_core(Plan P)
 template <bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_hd_core_rest(Plan P)
 {
-    __shared__ __align__(16) int32_t s_own[kWavesPerBlock][kPch][kMaxDimHigh];
+    __shared__ __align__(16) int32_t s_own[kWavesPerBlock][kPch][kOwnStride];
     __shared__ int32_t s_qb[kWavesPerBlock][2 * kMaxDimHigh];
     __shared__ uint32_t s_beg[kWavesPerBlock][kWave], s_pre[kWavesPerBlock][kWave];
     const uint32_t w = wave_in_block(), l = lane_id();
@@ -620,7 +670,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_gcore(Plan P)
 // pair in it could join two different sets.
 // ---------------------------------------------------------------------------
 template <bool WIDE>
-__device__ __forceinline__ void hd_link_walk(const Plan &P, uint32_t g, const int32_t (*own)[kMaxDimHigh],
+__device__ __forceinline__ void hd_link_walk(const Plan &P, uint32_t g, const int32_t (*own)[kOwnStride],
                                              uint32_t run, const uint32_t *ck, int32_t *qb, uint32_t *s_beg,
                                              uint32_t *s_pre, uint32_t &lt)
 {
@@ -679,7 +729,7 @@ __device__ __forceinline__ void hd_link_walk(const Plan &P, uint32_t g, const in
 template <bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_hd_merge(Plan P)
 {
-    __shared__ __align__(16) int32_t s_own[kWavesPerBlock][kPch][kMaxDimHigh];
+    __shared__ __align__(16) int32_t s_own[kWavesPerBlock][kPch][kOwnStride];
     __shared__ int32_t s_qb[kWavesPerBlock][2 * kMaxDimHigh];
     __shared__ uint32_t s_beg[kWavesPerBlock][kWave], s_pre[kWavesPerBlock][kWave];
     const uint32_t w = wave_in_block(), l = lane_id();
@@ -751,7 +801,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_unify(Plan P)
 // core point within eps (ties to the smaller input index); none -> noise.
 // ---------------------------------------------------------------------------
 template <bool WIDE>
-__device__ __forceinline__ void hd_border_walk(const Plan &P, uint32_t g, const int32_t (*own)[kMaxDimHigh],
+__device__ __forceinline__ void hd_border_walk(const Plan &P, uint32_t g, const int32_t (*own)[kOwnStride],
                                                uint32_t todo, int64_t *bd, uint32_t *bi, uint32_t *bp, int32_t *qb,
                                                uint32_t *s_beg, uint32_t *s_pre, uint32_t &lt)
 {
@@ -814,7 +864,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_noncore_list(Plan P)
 template <bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_hd_border(Plan P)
 {
-    __shared__ __align__(16) int32_t s_own[kWavesPerBlock][kPch][kMaxDimHigh];
+    __shared__ __align__(16) int32_t s_own[kWavesPerBlock][kPch][kOwnStride];
     __shared__ int32_t s_qb[kWavesPerBlock][2 * kMaxDimHigh];
     __shared__ uint32_t s_beg[kWavesPerBlock][kWave], s_pre[kWavesPerBlock][kWave];
     const uint32_t w = wave_in_block(), l = lane_id();

@@ -114,6 +114,8 @@ struct Plan {
     uint32_t *hd_list;          // [2n] sorted positions: undecided points, then non-core points (hd)
     uint32_t *hd_rec;           // [n][kHdRec] first neighbours found by core marking (sorted positions, hd)
     uint8_t *hd_nrec;           // [n] how many of them were recorded (hd)
+    uint32_t hd16;              // packed rows wanted (hd, every span below 2^15 and 32-bit sums)
+    uint32_t *spts16;           // [n][sd / 2] sorted points less the origin as packed int16 pairs, or null
     // neighbour search over groups: offsets in [-R, R]^d, self first
     uint32_t n_off;
     const int8_t *off;          // [n_off][d]

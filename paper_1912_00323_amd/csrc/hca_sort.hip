@@ -171,15 +171,21 @@ __global__ __launch_bounds__(kBlock) void k_hd_keys_hist(Plan P, uint64_t *__res
         if (s_hist[e]) atomicAdd(&hist[e], s_hist[e]);
 }
 
-// Rows gathered into sorted order, padded with zeros to sd words: thread t
-// owns word t % sd of the rows t / sd, t / sd + rpb, ... (rpb = 256 / sd).
+// Rows gathered into sorted order, padded with zeros to sd words (and, when
+// packed rows are used, less the origin as int16): thread t owns word t % sd
+// of the rows t / sd, t / sd + rpb, ... (rpb = 256 / sd).
 __global__ __launch_bounds__(kBlock) void k_hd_gather(Plan P)
 {
     const uint32_t d = (uint32_t)P.d, sd = P.sd, rpb = kBlock / sd;
     const uint32_t e = threadIdx.x % sd, r0 = threadIdx.x / sd;
     if (r0 >= rpb) return;
-    for (uint64_t r = (uint64_t)blockIdx.x * rpb + r0; r < P.n; r += (uint64_t)gridDim.x * rpb)
-        P.spts[r * sd + e] = e < d ? P.pts[(uint64_t)P.sidx[r] * d + e] : 0;
+    const int32_t o = e < d ? P.hd_origin[e] : 0;
+    uint16_t *packed = reinterpret_cast<uint16_t *>(P.spts16);
+    for (uint64_t r = (uint64_t)blockIdx.x * rpb + r0; r < P.n; r += (uint64_t)gridDim.x * rpb) {
+        const int32_t v = e < d ? P.pts[(uint64_t)P.sidx[r] * d + e] : 0;
+        P.spts[r * sd + e] = v;
+        if (packed) packed[r * sd + e] = e < d ? (uint16_t)(v - o) : (uint16_t)0;   // < 2^15
+    }
 }
 
 // Does sorted point idx lie in another cube than point idx - 1 (hd)?

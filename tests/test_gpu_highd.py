@@ -148,3 +148,18 @@ def test_errors_many_axes(ctx):
         ctx.set_exact(True)
     check(ctx, blobs(1, 100, 12), 50.0, 2, "after errors")
     del torch
+
+
+@pytest.mark.parametrize("packed", ["0", "1"])
+def test_row_forms(ctx, packed, monkeypatch):
+    # spans below 2^15: packed int16 rows (default) or plain 32-bit rows; a
+    # span of 2^15 or more always takes the plain form
+    monkeypatch.setenv("HCA_PACKED", packed)
+    for d in (16, 54):
+        pts = blobs(60 + d, 4000, d)
+        for f, mp in ((0.75, 4), (0.9, 9)):
+            check(ctx, pts, 0.03 * math.sqrt(2 * d) * f * 2 ** 10, mp, f"rows packed={packed}")
+    big = blobs(61, 3000, 20, q=15)
+    big[0, 0] = 0
+    big[1, 0] = (1 << 15) + 7
+    check(ctx, big, 0.03 * math.sqrt(40) * 0.8 * 2 ** 15, 5, "span past 2^15")
