@@ -26,7 +26,9 @@ METRIC = "points clustered/s (2-D 1M, 8-D 500k) vs HBM roofline; served p50/p99 
 HBM_PEAK_GBS = 8000.0
 # int32 VALU lane-ops: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 /s
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-WORKLOADS = {"2d": 2, "8d": 3, "small": 1, "batch": 4, "served": 5}
+WORKLOADS = {"2d": 2, "8d": 3, "small": 1, "batch": 4, "served": 5, "54d": 54}
+# 54d: the shape of the paper's largest data set (PAMAP2, Table 1), 54 axes
+HIGH_N = 3_850_505
 HBM_PHASES = ("bbox", "sort", "cells", "labels")
 ALU_PHASES = {"core": "tests_core", "intra": "tests_intra", "merge": "tests_merge",
               "border": "tests_border"}
@@ -37,6 +39,15 @@ PHASE_KERNELS = {
     "merge": ["k_merge_rep", "k_merge_exact", "k_merge_inter", "k_merge_pairs", "k_compress"],
     "border": ["k_border", "k_border_chunks"],
     "labels": ["k_label_marks", "k_label_scan", "k_label_cubes", "k_label_write"],
+}
+# more than 8 axes: the kernels of each phase
+PHASE_KERNELS_HIGH = {
+    "bbox": ["k_hd_bbox"], "sort": ["k_hd_keys_hist", "k_onesweep", "k_hd_gather"],
+    "cells": ["k_cells", "k_table"], "lists": ["k_hd_group_box", "k_hd_lists", "k_nbr_bscan", "k_nbr_back"],
+    "core": ["k_hd_core", "k_hd_core_rest", "k_hd_gcore"],
+    "merge": ["k_hd_link_recorded", "k_hd_unify", "k_hd_merge", "k_compress"],
+    "border": ["k_hd_noncore_list", "k_hd_border"],
+    "labels": PHASE_KERNELS["labels"],
 }
 
 
@@ -83,16 +94,27 @@ def measured_traffic(phase: str, workload: str):
 
 
 def cpu_baseline(w, budget_s: float = 25.0) -> dict:
-    """The oracle's grid method on the host cores, on the whole workload when
-    it finishes within the budget, else on the first m points of the input
-    (which is in random order), m doubling from 20k while runs stay short."""
+    """The oracle on the host cores (its grid method up to 8 axes, the
+    definition above that), on the whole workload when it finishes within
+    the budget, else on the first m points of the input (which is in random
+    order), m doubling from 20k while runs stay short."""
     import oracle
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    if w.d > 8:
+        def run(p):
+            oracle.dbscan(p, w.eps, w.min_pts, threads=threads)
+        method = ("DBSCAN from its definition in plain C (oracle/dbscan_def.c: points visited in order "
+                  "of axis 0, OpenMP over points; the grid method's stencil is out of reach past 8 axes)")
+    else:
+        def run(p):
+            oracle.hca_grid(p, w.eps, w.min_pts, threads=threads)
+        method = ("the paper's hypercube method in plain C (oracle/hca_grid.c: OpenMP over points for "
+                  "core marking and borders, sequential depth-first merge)")
     t_all = time.perf_counter()
     m = min(w.n, 20_000)
     while True:
         t0 = time.perf_counter()
-        oracle.hca_grid(w.points[:m], w.eps, w.min_pts, threads=threads)
+        run(w.points[:m])
         t = time.perf_counter() - t0
         # the cost grows at least linearly in m: stop before overrunning
         if m == w.n or t * 4 > budget_s - (time.perf_counter() - t_all):
@@ -101,16 +123,14 @@ def cpu_baseline(w, budget_s: float = 25.0) -> dict:
     times = [t]
     while len(times) < 3 and time.perf_counter() - t_all + t < budget_s:
         t0 = time.perf_counter()
-        oracle.hca_grid(w.points[:m], w.eps, w.min_pts, threads=threads)
+        run(w.points[:m])
         times.append(time.perf_counter() - t0)
     t = statistics.median(times)
     what = (f"the whole {w.name} workload (n={w.n})" if m == w.n else
             f"the first {m} of the {w.n} points of {w.name} (same eps and minPts; lower density "
             f"than the whole set, so the per-point rate flatters the CPU)")
     return {"value": m / t, "unit": "points/s", "cores": threads, "kind": "oracle",
-            "sample": f"{what}; the paper's hypercube method in plain C (oracle/hca_grid.c: OpenMP "
-                      f"over points for core marking and borders, sequential depth-first merge), "
-                      f"median of {len(times)} run(s)"}
+            "sample": f"{what}; {method}, median of {len(times)} run(s)"}
 
 
 def main() -> int:
@@ -136,9 +156,9 @@ def main() -> int:
 
     import torch
     from paper_1912_00323_amd import hca
-    from paper_1912_00323_amd.datagen import make_config
+    from paper_1912_00323_amd.datagen import make_config, make_high
 
-    w = make_config(WORKLOADS[args.workload])
+    w = make_high(54, HIGH_N) if args.workload == "54d" else make_config(WORKLOADS[args.workload])
     dev = torch.device("cuda:0")
     pts = torch.from_numpy(w.points).to(dev)
     labels = torch.empty(w.n, dtype=torch.int32, device=dev)
@@ -183,12 +203,13 @@ def main() -> int:
     ctx.set_profiling(None)
     ms_per_step = dt * 1e3 / args.steps
     dom = statistics.mean(dom_ms)
-    key_bytes = 8 if stats["key_bits"] > 32 else 4
+    key_bytes = 8 if stats["key_bits"] > 32 or w.d > 8 else 4
+    kernels = PHASE_KERNELS_HIGH if w.d > 8 else PHASE_KERNELS
 
     def hbm_roofline(phase, ms):
         ab = algorithmic_bytes(phase, w.n, w.d, key_bytes, stats["sort_passes"], stats["n_cells"])
         achieved = ab / (ms * 1e-3) / 1e9
-        return {"bound": "hbm", "phase": phase, "kernels": PHASE_KERNELS[phase],
+        return {"bound": "hbm", "phase": phase, "kernels": kernels[phase],
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(phase, w.name),
                 "algorithmic_bytes": ab, "phase_ms": round(ms, 4)}
@@ -197,7 +218,7 @@ def main() -> int:
         n_tests = statistics.mean(tests[ALU_PHASES[phase]])
         ops = 3.0 * w.d * n_tests                        # d sub + d mul + (d-1) add + compare
         achieved = ops / (ms * 1e-3) / 1e12
-        return {"bound": "alu", "phase": phase, "kernels": PHASE_KERNELS[phase],
+        return {"bound": "alu", "phase": phase, "kernels": kernels[phase],
                 "achieved": round(achieved, 4), "peak": round(ALU_PEAK_TOPS, 2),
                 "unit": "Tops/s (int32 lane-ops)", "frac": round(achieved / ALU_PEAK_TOPS, 5),
                 "traffic": measured_traffic(phase, w.name), "pair_tests": n_tests,
@@ -208,7 +229,7 @@ def main() -> int:
     elif dominant in HBM_PHASES:
         roofline = hbm_roofline(dominant, dom)
     else:
-        roofline = {"bound": "alu", "phase": dominant, "kernels": PHASE_KERNELS[dominant],
+        roofline = {"bound": "alu", "phase": dominant, "kernels": kernels[dominant],
                     "achieved": None, "peak": round(ALU_PEAK_TOPS, 2), "unit": "Tops/s (int32 lane-ops)",
                     "frac": None, "traffic": measured_traffic(dominant, w.name), "phase_ms": round(dom, 4)}
 

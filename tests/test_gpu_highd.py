@@ -163,3 +163,51 @@ def test_row_forms(ctx, packed, monkeypatch):
     big[0, 0] = 0
     big[1, 0] = (1 << 15) + 7
     check(ctx, big, 0.03 * math.sqrt(40) * 0.8 * 2 ** 15, 5, "span past 2^15")
+
+
+def test_full_size_54_axes_sampled():
+    """The 54-axis workload at full size (the shape of the paper's PAMAP2
+    set, 3,850,505 points): the core flag of sampled points against their
+    brute-force neighbour counts, every core neighbour of a sampled core point
+    in its cluster, a sampled non-core point in the cluster of its nearest
+    core point (ties to the smaller index) or noise, and canonical numbering
+    over all labels.  Squared distances come from float64 products, exact
+    here (every product below 2^24, every sum below 2^31)."""
+    import torch
+    from paper_1912_00323_amd import hca
+    from paper_1912_00323_amd.datagen import make_high
+    w = make_high(54, 3_850_505)
+    print(f"[case] {w.name} eps={w.eps:.3f} minPts={w.min_pts}", flush=True)
+    c = hca.Context(0)
+    try:
+        t = torch.from_numpy(w.points).cuda()
+        lab, core = c.cluster(t, w.eps, w.min_pts, core=True)
+        lab, core = lab.cpu().numpy(), core.cpu().numpy().astype(bool)
+        del t
+    finally:
+        c.close()
+    eps2 = oracle.exact_eps2(w.eps)
+    # canonical: the first occurrences of the labels come in the order 0, 1, 2, ...
+    seen = lab[lab >= 0]
+    _, first = np.unique(seen, return_index=True)
+    assert np.array_equal(np.argsort(first), np.arange(len(first)))
+    rng = np.random.default_rng(99)
+    pick = np.concatenate([rng.choice(np.flatnonzero(core), 16, replace=False),
+                           rng.choice(np.flatnonzero(~core), 16, replace=False)])
+    S = w.points[pick].astype(np.float64)
+    s2 = (S * S).sum(1)
+    d2 = np.empty((len(pick), w.n), np.float64)
+    for a in range(0, w.n, 500_000):
+        X = w.points[a:a + 500_000].astype(np.float64)
+        d2[:, a:a + len(X)] = (X * X).sum(1)[None, :] + s2[:, None] - 2.0 * (S @ X.T)
+    for r, i in enumerate(pick):
+        nb = np.flatnonzero(d2[r] <= eps2)
+        assert core[i] == (len(nb) >= w.min_pts), ("core flag", i, len(nb))
+        cn = nb[core[nb]]
+        if core[i]:
+            assert (lab[cn] == lab[i]).all(), ("core neighbour in another cluster", i)
+        elif len(cn):
+            j = cn[np.lexsort((cn, d2[r][cn]))[0]]
+            assert lab[i] == lab[j], ("border owner", i, j)
+        else:
+            assert lab[i] == -1, ("noise", i)
