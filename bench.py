@@ -45,7 +45,7 @@ PHASE_KERNELS_HIGH = {
     "bbox": ["k_hd_bbox"], "sort": ["k_hd_keys_hist", "k_onesweep", "k_hd_gather"],
     "cells": ["k_cells", "k_table"], "lists": ["k_hd_group_box", "k_hd_lists", "k_nbr_bscan", "k_nbr_back"],
     "core": ["k_hd_core", "k_hd_core_rest", "k_hd_gcore"],
-    "merge": ["k_hd_link_recorded", "k_hd_unify", "k_hd_merge", "k_compress"],
+    "merge": ["k_link_recorded", "k_hd_unify", "k_hd_merge", "k_compress"],
     "border": ["k_hd_noncore_list", "k_hd_border"],
     "labels": PHASE_KERNELS["labels"],
 }

@@ -159,6 +159,14 @@ int env_mode()
     return 0;
 }
 
+// HCA_RECORD=0: search groups of several cubes merge without the pairs
+// recorded by core marking (the result is the same)
+bool env_record()
+{
+    const char *e = std::getenv("HCA_RECORD");
+    return !(e && !std::strcmp(e, "0"));
+}
+
 bool env_reps()
 {
     const char *e = std::getenv("HCA_REPS");
@@ -401,8 +409,11 @@ void carve_ws(Carver &cv, Plan &P, SortBuffers &B, const Sizes &Z, uint32_t **ze
     if (P.hd) {
         P.hd_origin = cv.take<int32_t>(kMaxDimHigh);
         P.hd_list = cv.take<uint32_t>((size_t)2 * n);
-        P.hd_rec = cv.take<uint32_t>((size_t)kHdRec * n);
-        P.hd_nrec = cv.take<uint8_t>(n);
+        P.rec = cv.take<uint32_t>((size_t)kRec * n);
+        P.nrec = cv.take<uint8_t>(n);
+    } else if (P.m > 1 && !P.nseg && env_record()) {
+        P.rec = cv.take<uint32_t>((size_t)kRec * n);
+        P.nrec = cv.take<uint8_t>(n);
         P.spts16 = P.hd16 ? cv.take<uint32_t>((size_t)n * (P.sd / 2)) : nullptr;
     }
     const size_t ksz = Z.wide_keys ? 8 : 4;

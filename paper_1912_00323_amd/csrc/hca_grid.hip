@@ -576,12 +576,16 @@ __global__ __launch_bounds__(kBlock) void k_nbr_back(Plan P)
 
 // Neighbour counts of the chunk points not yet flagged in `done`, over group
 // g and its neighbour groups, until each reaches minPts (then its bit is
-// set).  Returns the updated mask.
+// set).  Returns the updated mask.  With P.rec and a chunk position pc
+// (not kNone), the first kRec neighbours found of point pc + k are recorded
+// for merging.
 template <int D, bool WIDE>
 __device__ __forceinline__ uint32_t count_walk(const Plan &P, uint32_t g, uint64_t gkey, const Pt<D> *pp,
                                                uint32_t done, uint32_t *cnt, uint32_t *s_beg,
-                                               uint32_t *s_pre, uint32_t &lt, const Geo<D> &geo)
+                                               uint32_t *s_pre, uint32_t &lt, const Geo<D> &geo,
+                                               uint32_t pc = kNone)
 {
+    const bool record = P.rec != nullptr && pc != kNone;
     const uint32_t l = lane_id();
     const uint32_t minpts = geo.min_pts;
     const uint32_t all = (1u << kPch) - 1u;
@@ -603,7 +607,12 @@ __device__ __forceinline__ uint32_t count_walk(const Plan &P, uint32_t g, uint64
                 if (done & (1u << k)) continue;
                 lt += ok;
                 const bool hit = ok && within<D, WIDE>(pp[k], q, geo.eps2);
-                cnt[k] += __popcll(__ballot(hit));
+                const uint64_t hm = __ballot(hit);
+                if (record && hm && cnt[k] < (uint32_t)kRec) {
+                    const uint32_t r = cnt[k] + __popcll(hm & __lanemask_lt());
+                    if (hit && r < (uint32_t)kRec) P.rec[(uint64_t)(pc + k) * kRec + r] = pos;
+                }
+                cnt[k] += __popcll(hm);
                 if (cnt[k] >= minpts) done |= 1u << k;
             }
             done = uniform(done);
@@ -746,7 +755,7 @@ __global__ __launch_bounds__(kBlock) void k_core_chunks(Plan P)
                 const uint32_t run = (uint32_t)__ballot(grp == g) & left;
                 left &= ~run;
                 const uint32_t got = count_walk<D, WIDE>(P, g, P.group_key[g], pp, ~run & all, cnt, s_beg[w],
-                                                         s_pre[w], lt, geo);
+                                                         s_pre[w], lt, geo, pc);
                 done |= got & run;
             }
         }
@@ -755,7 +764,10 @@ __global__ __launch_bounds__(kBlock) void k_core_chunks(Plan P)
         for (int k = 0; k < kPch; k++)
             if ((uint32_t)k == l) mine = cnt[k];
         const bool core = l < np && (dense || mine >= minpts);
-        if (l < np) P.core[pc + l] = core;
+        if (l < np) {
+            P.core[pc + l] = core;
+            if (P.rec) P.nrec[pc + l] = (uint8_t)min(dense ? 0u : mine, (uint32_t)kRec);
+        }
         const uint32_t me = core ? P.sidx[pc + l] : kNone;
         // one atomic per cube of the chunk (cubes are runs of lanes)
         uint64_t pend = __ballot(l < np);
@@ -1825,6 +1837,7 @@ void launch_reps(const Plan &P, int blocks, hipStream_t s)
 void launch_merge_intra(const Plan &P, int blocks, hipStream_t s)
 {
     if (P.m == 1) return;
+    if (P.rec) launch_link_recorded(P, s);
     const uint32_t tiles = (P.n + kScanTile - 1) / kScanTile;
     hipLaunchKernelGGL(k_tile_scan, dim3(tiles), dim3(kBlock), 0, s, P, P.tile_status, &P.ctr->tile_ticket);
     HCA_DISPATCH_DW(k_merge_tiles, P, blocks, s);

@@ -475,7 +475,7 @@ __device__ __forceinline__ uint32_t hd_candidate(uint32_t c, const uint32_t *s_b
 // ---------------------------------------------------------------------------
 // Stops after `budget` candidates; *cut tells whether it stopped there with
 // points left undecided.
-// The first kHdRec neighbours found of staged point k (sorted position
+// The first kRec neighbours found of staged point k (sorted position
 // qpos[k]) are recorded for merging.
 template <bool WIDE>
 __device__ __forceinline__ uint32_t hd_count_walk(const Plan &P, uint32_t g, const int32_t (*own)[kOwnStride],
@@ -501,9 +501,9 @@ __device__ __forceinline__ uint32_t hd_count_walk(const Plan &P, uint32_t g, con
                 lt += ok;
                 const bool hit = ok && dd[k] <= P.eps2;
                 const uint64_t hm = __ballot(hit);
-                if (hm && cnt[k] < (uint32_t)kHdRec) {
+                if (hm && cnt[k] < (uint32_t)kRec) {
                     const uint32_t r = cnt[k] + __popcll(hm & __lanemask_lt());
-                    if (hit && r < (uint32_t)kHdRec) P.hd_rec[(uint64_t)qpos[k] * kHdRec + r] = pos;
+                    if (hit && r < (uint32_t)kRec) P.rec[(uint64_t)qpos[k] * kRec + r] = pos;
                 }
                 cnt[k] += __popcll(hm);
                 if (cnt[k] >= minpts) done |= 1u << k;
@@ -589,7 +589,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_core(Plan P)
         const bool core = in && !later && (dense || mine >= minpts);
         if (in && !later) {
             P.core[pc + l] = core;
-            P.hd_nrec[pc + l] = (uint8_t)min(dense ? 0u : mine, (uint32_t)kHdRec);
+            P.nrec[pc + l] = (uint8_t)min(dense ? 0u : mine, (uint32_t)kRec);
         }
         const uint64_t um = __ballot(later);
         if (um) {
@@ -647,7 +647,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_core_rest(Plan P)
         const bool core = in && mine >= minpts;
         if (in) {
             P.core[q] = core;
-            P.hd_nrec[q] = (uint8_t)min(mine, (uint32_t)kHdRec);
+            P.nrec[q] = (uint8_t)min(mine, (uint32_t)kRec);
         }
         hd_tally(P, in, cell, core, core ? P.sidx[q] : kNone);
     }
@@ -758,15 +758,16 @@ __global__ __launch_bounds__(kBlock) void k_hd_merge(Plan P)
     flush_tests(P, kTestsMerge, lt);
 }
 
-// The pairs recorded by core marking: each core point joins its cube with
-// those of its recorded core neighbours (all within eps), no test needed.
-__global__ __launch_bounds__(kBlock) void k_hd_link_recorded(Plan P)
+// The pairs recorded by core marking (more than 8 axes, or search groups of
+// more than one cube): each core point joins its cube with those of its
+// recorded core neighbours (all within eps), no test needed.
+__global__ __launch_bounds__(kBlock) void k_link_recorded(Plan P)
 {
     for (uint32_t q = blockIdx.x * kBlock + threadIdx.x; q < P.n; q += gridDim.x * kBlock) {
         if (!P.core[q]) continue;
-        const uint32_t c = P.cell_of[q], nr = P.hd_nrec[q];
+        const uint32_t c = P.cell_of[q], nr = P.nrec[q];
         for (uint32_t r = 0; r < nr; r++) {
-            const uint32_t q2 = P.hd_rec[(uint64_t)q * kHdRec + r];
+            const uint32_t q2 = P.rec[(uint64_t)q * kRec + r];
             if (!P.core[q2]) continue;
             const uint32_t c2 = P.cell_of[q2];
             if (c2 != c) uf_union(P.parent, c, c2);
@@ -923,6 +924,12 @@ __global__ __launch_bounds__(kBlock) void k_hd_border(Plan P)
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+void launch_link_recorded(const Plan &P, hipStream_t s)
+{
+    const int cb = (int)std::min<uint64_t>((P.n + kBlock - 1) / kBlock, 2048);
+    hipLaunchKernelGGL(k_link_recorded, dim3(cb), dim3(kBlock), 0, s, P);
+}
+
 void launch_hd_lists(const Plan &P, int blocks, hipStream_t s)
 {
     hipLaunchKernelGGL(k_hd_group_box, dim3(blocks), dim3(kBlock), 0, s, P);
@@ -954,8 +961,7 @@ void launch_hd_core(const Plan &P, int blocks, hipStream_t s)
 
 void launch_hd_merge(const Plan &P, int blocks, hipStream_t s)
 {
-    const int cb = (int)std::min<uint64_t>((P.n + kBlock - 1) / kBlock, 2048);
-    hipLaunchKernelGGL(k_hd_link_recorded, dim3(cb), dim3(kBlock), 0, s, P);
+    launch_link_recorded(P, s);
     hipLaunchKernelGGL(k_hd_unify, dim3(blocks), dim3(kBlock), 0, s, P);
     if (P.wide) hipLaunchKernelGGL(k_hd_merge<true>, dim3(blocks), dim3(kBlock), 0, s, P);
     else hipLaunchKernelGGL(k_hd_merge<false>, dim3(blocks), dim3(kBlock), 0, s, P);

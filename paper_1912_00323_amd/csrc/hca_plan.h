@@ -9,7 +9,7 @@ namespace hca {
 
 constexpr int kMaxDim = 8;                     // axes of the packed cube key
 constexpr int kMaxDimHigh = 64;                // axes of a point (more than 8: hashed cubes)
-constexpr int kHdRec = 8;                      // neighbours recorded per point (more than 8 axes)
+constexpr int kRec = 8;                        // neighbours recorded per point by core marking
 constexpr int kWave = 64;
 constexpr int kBlock = 256;                    // 4 waves per workgroup
 constexpr uint32_t kNone = 0xFFFFFFFFu;
@@ -112,8 +112,9 @@ struct Plan {
     uint8_t kdim[kMaxDim];
     const int32_t *hd_origin;   // [d] origin of every axis (hd)
     uint32_t *hd_list;          // [2n] sorted positions: undecided points, then non-core points (hd)
-    uint32_t *hd_rec;           // [n][kHdRec] first neighbours found by core marking (sorted positions, hd)
-    uint8_t *hd_nrec;           // [n] how many of them were recorded (hd)
+    uint32_t *rec;              // [n][kRec] first neighbours found by core marking (sorted positions),
+                                // or null (kept for more than 8 axes and for groups of several cubes)
+    uint8_t *nrec;              // [n] how many of them were recorded
     uint32_t hd16;              // packed rows wanted (hd, every span below 2^15 and 32-bit sums)
     uint32_t *spts16;           // [n][sd / 2] sorted points less the origin as packed int16 pairs, or null
     // neighbour search over groups: offsets in [-R, R]^d, self first

@@ -109,6 +109,22 @@ def test_group_lists_fallback(ctx, slab, monkeypatch):
             assert stats["list_overflow"] == 0
 
 
+@pytest.mark.parametrize("record", ["0", "1"])
+def test_group_recorded_pairs(ctx, record, monkeypatch):
+    """Search groups of several cubes with and without joining the neighbour
+    pairs recorded by core marking before the merge tiles: the same labels."""
+    monkeypatch.setenv("HCA_SEARCH", "group")
+    monkeypatch.setenv("HCA_RECORD", record)
+    for d in (3, 5, 8):
+        rng = np.random.default_rng(80 + d)
+        x = make_blobs(rng, 8000, d, 6, 0.03, 0.1)
+        pts = quantise(x, 12)
+        for f, mp in ((0.06, 5), (0.09, 12), (0.12, 1)):
+            print(f"[case] recorded pairs={record} d={d} eps={f} minPts={mp}", flush=True)
+            want = oracle.dbscan(pts, f * 2 ** 12, mp)
+            assert np.array_equal(gpu_labels(ctx, pts, f * 2 ** 12, mp), want), (record, d, f, mp)
+
+
 def test_mixed_family(ctx):
     for seed in range(6):
         d = (2, 3, 4)[seed % 3]
