@@ -103,6 +103,8 @@ typedef struct {
     int64_t tests_merge;      /* between neighbouring cubes or groups */
     int64_t tests_border;
     int64_t tests_intra;      /* inside search groups (m > 1) */
+    int32_t packed_rows;      /* d > 8: 1 if candidate rows were packed as int16 pairs */
+    int32_t key_axes;         /* d > 8: axes spanned by the search-group key (0 for d <= 8) */
 } hca_stats;
 
 /* Exact floor(eps^2) of a double (no device needed).  HCA_E_INVAL if eps is

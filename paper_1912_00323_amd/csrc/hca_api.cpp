@@ -411,10 +411,10 @@ void carve_ws(Carver &cv, Plan &P, SortBuffers &B, const Sizes &Z, uint32_t **ze
         P.hd_list = cv.take<uint32_t>((size_t)2 * n);
         P.rec = cv.take<uint32_t>((size_t)kRec * n);
         P.nrec = cv.take<uint8_t>(n);
+        P.spts16 = P.hd16 ? cv.take<uint32_t>((size_t)n * (P.sd / 2)) : nullptr;
     } else if (P.m > 1 && !P.nseg && env_record()) {
         P.rec = cv.take<uint32_t>((size_t)kRec * n);
         P.nrec = cv.take<uint8_t>(n);
-        P.spts16 = P.hd16 ? cv.take<uint32_t>((size_t)n * (P.sd / 2)) : nullptr;
     }
     const size_t ksz = Z.wide_keys ? 8 : 4;
     B.keys_a = cv.take<char>((size_t)n * ksz);
@@ -571,6 +571,8 @@ void fill_stats(hca_ctx *ctx, const Plan &P, hca_stats *stats)
         stats->wide = P.wide;
         stats->dense_table = (int32_t)P.dense;
         stats->list_overflow = (int32_t)hc->nbr_overflow;
+    stats->packed_rows = P.spts16 != nullptr ? 1 : 0;
+    stats->key_axes = P.hd ? (int32_t)P.kd : 0;
 }
 
 // ---- more than kMaxDim axes ----------------------------------------------------

@@ -44,7 +44,8 @@ class Stats(ctypes.Structure):
                 ("group", ctypes.c_int32), ("wide", ctypes.c_int32),
                 ("dense_table", ctypes.c_int32), ("list_overflow", ctypes.c_int32),
                 ("tests_core", ctypes.c_int64), ("tests_merge", ctypes.c_int64),
-                ("tests_border", ctypes.c_int64), ("tests_intra", ctypes.c_int64)]
+                ("tests_border", ctypes.c_int64), ("tests_intra", ctypes.c_int64),
+                ("packed_rows", ctypes.c_int32), ("key_axes", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

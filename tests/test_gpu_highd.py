@@ -159,10 +159,13 @@ def test_row_forms(ctx, packed, monkeypatch):
         pts = blobs(60 + d, 4000, d)
         for f, mp in ((0.75, 4), (0.9, 9)):
             check(ctx, pts, 0.03 * math.sqrt(2 * d) * f * 2 ** 10, mp, f"rows packed={packed}")
+        _, st = gpu_run(ctx, pts, 0.03 * math.sqrt(2 * d) * 2 ** 10, 4, stats=True)
+        assert st["packed_rows"] == int(packed) and 1 <= st["key_axes"] <= 8
     big = blobs(61, 3000, 20, q=15)
     big[0, 0] = 0
     big[1, 0] = (1 << 15) + 7
     check(ctx, big, 0.03 * math.sqrt(40) * 0.8 * 2 ** 15, 5, "span past 2^15")
+    assert gpu_run(ctx, big, 100.0, 5, stats=True)[1]["packed_rows"] == 0
 
 
 def test_full_size_54_axes_sampled():
