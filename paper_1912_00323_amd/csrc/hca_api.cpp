@@ -18,7 +18,7 @@ using namespace hca;
 
 namespace {
 
-constexpr int kBboxBlocks = 256;
+constexpr int kBboxBlocks = 1024;
 constexpr int kPersistBlocks = 2048;       // multiple of the 8 XCDs
 constexpr int kMaxBatchDim = 4;            // batches: search groups of one cube, d <= 4
 constexpr size_t kMaxBatchSegs = 8192;     // data sets of one dimension per batch
@@ -727,6 +727,7 @@ hca_status run_hd(hca_ctx *ctx, const int32_t *points, uint32_t n, int32_t d, do
         P.key_bits = gbits + (uint32_t)std::min<int>(std::max(1, std::atoi(e)), 63 - (int)gbits);
     P.fine_bits = P.key_bits - gbits;                 // hash bits
     P.passes = (P.key_bits + kRadixBits - 1) / kRadixBits;
+    P.digit_bits = (P.key_bits + P.passes - 1) / P.passes;
     P.wide = reach >= ((unsigned __int128)1 << 31) ? 1 : 0;
     // packed int16 rows when every span is below 2^15 and sums fit 32 bits
     // (HCA_PACKED=0 turns them off)
@@ -883,6 +884,7 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
     P.key_bits = gbits + P.fine_bits;
     if (P.key_bits > 63) return fail(ctx, HCA_E_RANGE, "packed cube key needs more than 63 bits");
     P.passes = std::max<uint32_t>(1, (P.key_bits + kRadixBits - 1) / kRadixBits);
+    P.digit_bits = std::max<uint32_t>(1, (P.key_bits + P.passes - 1) / P.passes);
     // largest coordinate difference of any pair the kernels test
     const unsigned __int128 reach = (unsigned __int128)(G.gradius + 1) * (uint64_t)G.gside - 1;
     const uint64_t dmax = (uint64_t)std::min<unsigned __int128>(reach, (unsigned __int128)span_max);
@@ -1151,6 +1153,7 @@ hca_status run_sets(hca_ctx *ctx, const BatchSet *sets, int32_t nseg)
         P.key_bits = bits + bit_length(ns - 1);
         if (P.key_bits > 63) return fail(ctx, HCA_E_RANGE, "packed batch key needs more than 63 bits");
         P.passes = std::max<uint32_t>(1, (P.key_bits + kRadixBits - 1) / kRadixBits);
+        P.digit_bits = std::max<uint32_t>(1, (P.key_bits + P.passes - 1) / P.passes);
         P.wide = wide ? 1 : 0;
         P.n_off = (uint32_t)(g.off.size() / d);
         P.n_dir = g.n_dir;

@@ -101,6 +101,7 @@ struct Plan {
     uint32_t gmax[kMaxDim];     // largest group coordinate per axis
     uint32_t key_bits;
     uint32_t passes;
+    uint32_t digit_bits;        // bits per radix pass: ceil(key_bits / passes) <= kRadixBits
     // more than kMaxDim axes (hd = 1): search groups over the kd key axes
     // kdim[0..kd) (position e of the group key holds axis kdim[e], with
     // origin[e], goff[e], gw[e], gmax[e]); below them the key holds

@@ -117,7 +117,7 @@ __global__ __launch_bounds__(kBlock) void k_keys_hist(Plan P, K *__restrict__ ke
                                                       uint32_t *__restrict__ hist)
 {
     __shared__ uint32_t s_hist[8 * kRadix];
-    const uint32_t passes = P.passes;
+    const uint32_t passes = P.passes, dmask = (1u << P.digit_bits) - 1u;
     for (uint32_t e = threadIdx.x; e < passes * kRadix; e += kBlock) s_hist[e] = 0;
     __syncthreads();
     for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < P.n; i += gridDim.x * kBlock) {
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(kBlock) void k_keys_hist(Plan P, K *__restrict__ ke
         keys[i] = key;
         vals[i] = i;
         for (uint32_t q = 0; q < passes; q++)
-            atomicAdd(&s_hist[q * kRadix + (uint32_t)((key >> (q * kRadixBits)) & (kRadix - 1))], 1u);
+            atomicAdd(&s_hist[q * kRadix + (uint32_t)((key >> (q * P.digit_bits)) & dmask)], 1u);
     }
     __syncthreads();
     for (uint32_t e = threadIdx.x; e < passes * kRadix; e += kBlock)
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_keys_hist(Plan P, uint64_t *__res
 {
     __shared__ uint32_t s_hist[8 * kRadix];
     __shared__ int32_t s_org[kMaxDimHigh];
-    const uint32_t passes = P.passes, d = (uint32_t)P.d, hb = P.fine_bits;
+    const uint32_t passes = P.passes, d = (uint32_t)P.d, hb = P.fine_bits, dmask = (1u << P.digit_bits) - 1u;
     for (uint32_t e = threadIdx.x; e < passes * kRadix; e += kBlock) s_hist[e] = 0;
     for (uint32_t e = threadIdx.x; e < d; e += kBlock) s_org[e] = P.hd_origin[e];
     __syncthreads();
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_keys_hist(Plan P, uint64_t *__res
         keys[i] = key;
         vals[i] = i;
         for (uint32_t q = 0; q < passes; q++)
-            atomicAdd(&s_hist[q * kRadix + (uint32_t)((key >> (q * kRadixBits)) & (kRadix - 1))], 1u);
+            atomicAdd(&s_hist[q * kRadix + (uint32_t)((key >> (q * P.digit_bits)) & dmask)], 1u);
     }
     __syncthreads();
     for (uint32_t e = threadIdx.x; e < passes * kRadix; e += kBlock)
@@ -200,7 +200,10 @@ __device__ __forceinline__ bool hd_new_cube(const Plan &P, uint32_t idx)
 }
 
 // ---------------------------------------------------------------------------
-// One stable LSD pass with decoupled look-back (one launch per digit).
+// One stable LSD pass with decoupled look-back (one launch per digit).  A
+// digit has P.digit_bits <= 8 bits: the key bits spread evenly over the
+// passes, so that the runs a tile writes per digit are as long as they can
+// be for that number of passes.
 //
 // A workgroup takes the next 2048-key tile by ticket.  Each wave owns 512
 // consecutive keys and ranks them in eight rounds of 64: lanes with equal
@@ -234,6 +237,7 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(Plan P, const K *__restrict
     const uint32_t n = P.n;
     const uint32_t base = tile * kSortTile + w * PER_WAVE;
     const uint64_t lt_mask = __lanemask_lt();
+    const uint32_t nbits = P.digit_bits, dmask = (1u << nbits) - 1u;
 
     K key[kSortItems];
     uint32_t val[kSortItems], rank[kSortItems], dig[kSortItems];
@@ -248,10 +252,11 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(Plan P, const K *__restrict
     for (int j = 0; j < kSortItems; j++) {
         const uint32_t idx = base + j * kWave + l;
         const bool ok = idx < n;
-        const uint32_t dg = (uint32_t)(key[j] >> shift) & (kRadix - 1);
+        const uint32_t dg = (uint32_t)(key[j] >> shift) & dmask;
         uint64_t peers = __ballot(ok);
 #pragma unroll
         for (int b = 0; b < kRadixBits; b++) {
+            if (b >= (int)nbits) break;                  // higher digit bits are zero
             const bool bit = (dg >> b) & 1u;
             const uint64_t m = __ballot(bit);
             peers &= bit ? m : ~m;
@@ -313,7 +318,7 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(Plan P, const K *__restrict
     for (uint32_t i = t; i < tile_n; i += kBlock) {
         const K kk = s_keys[i];
         const uint32_t vv = s_vals[i];
-        const uint32_t pos = s_gbase[(uint32_t)(kk >> shift) & (kRadix - 1)] + i;
+        const uint32_t pos = s_gbase[(uint32_t)(kk >> shift) & dmask] + i;
         kout[pos] = kk;
         vout[pos] = vv;
         if constexpr (GATHER) store_pt<D>(P.spts, pos, load_pt<D>(P.pts, vv));
@@ -443,10 +448,10 @@ static void sort_d(const Plan &P, const SortBuffers &B, hipStream_t s)
         const bool last = q + 1 == P.passes;
         if (last)
             hipLaunchKernelGGL((k_onesweep<K, D, true>), dim3(tiles), dim3(kBlock), 0, s, P, ka, va,
-                               kb, vb, q * kRadixBits, B.hist + q * kRadix, st, B.tickets + q);
+                               kb, vb, q * P.digit_bits, B.hist + q * kRadix, st, B.tickets + q);
         else
             hipLaunchKernelGGL((k_onesweep<K, D, false>), dim3(tiles), dim3(kBlock), 0, s, P, ka,
-                               va, kb, vb, q * kRadixBits, B.hist + q * kRadix, st, B.tickets + q);
+                               va, kb, vb, q * P.digit_bits, B.hist + q * kRadix, st, B.tickets + q);
         K *tk = ka; ka = kb; kb = tk;
         uint32_t *tv = va; va = vb; vb = tv;
     }
@@ -487,7 +492,7 @@ void launch_sort_hd(Plan &P, SortBuffers &B, hipStream_t s)
     for (uint32_t q = 0; q < P.passes; q++) {
         uint64_t *st = B.status + (uint64_t)q * tiles * kRadix;
         hipLaunchKernelGGL((k_onesweep<uint64_t, 1, false>), dim3(tiles), dim3(kBlock), 0, s, P, ka, va, kb, vb,
-                           q * kRadixBits, B.hist + q * kRadix, st, B.tickets + q);
+                           q * P.digit_bits, B.hist + q * kRadix, st, B.tickets + q);
         uint64_t *tk = ka; ka = kb; kb = tk;
         uint32_t *tv = va; va = vb; vb = tv;
     }
