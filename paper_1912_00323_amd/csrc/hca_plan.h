@@ -14,11 +14,16 @@ constexpr int kWave = 64;
 constexpr int kBlock = 256;                    // 4 waves per workgroup
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
-// Radix sort of cube keys: 8-bit digits, 2048-key tiles (256 threads x 8 keys).
+// Radix sort of cube keys: digits of at most 8 bits, tiles of 256 threads x
+// 16 (32-bit keys) or 8 (64-bit keys) keys.
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
-constexpr int kSortItems = 8;
-constexpr int kSortTile = kBlock * kSortItems;
+// 32-bit keys take 16 per thread (4096-key tiles), 64-bit keys 8 (2048-key
+// tiles: their LDS staging would otherwise halve the resident tiles);
+// kSortTile, the smaller, sizes the look-back words.
+template <typename K>
+constexpr int sort_items() { return sizeof(K) == 4 ? 16 : 8; }
+constexpr int kSortTile = kBlock * 8;
 
 // Device-wide scans: 256 threads x 16 items.
 constexpr int kScanItems = 16;

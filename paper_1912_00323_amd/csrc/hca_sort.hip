@@ -220,9 +220,11 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(Plan P, const K *__restrict
                                                      uint64_t *__restrict__ status, uint32_t *ticket)
 {
     constexpr int W = kBlock / kWave;
-    constexpr int PER_WAVE = kWave * kSortItems;
-    __shared__ K s_keys[kSortTile];
-    __shared__ uint32_t s_vals[kSortTile];
+    constexpr int kItems = sort_items<K>();
+    constexpr int kTile = kBlock * kItems;
+    constexpr int PER_WAVE = kWave * kItems;
+    __shared__ K s_keys[kTile];
+    __shared__ uint32_t s_vals[kTile];
     __shared__ uint32_t s_wcnt[W][kRadix];      // per-wave digit counts, then offsets
     __shared__ uint32_t s_tstart[kRadix];       // tile-local start of each digit
     __shared__ uint32_t s_gbase[kRadix];        // global position of tile-local 0 per digit
@@ -235,21 +237,21 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(Plan P, const K *__restrict
     __syncthreads();
     const uint32_t tile = s_tile;
     const uint32_t n = P.n;
-    const uint32_t base = tile * kSortTile + w * PER_WAVE;
+    const uint32_t base = tile * kTile + w * PER_WAVE;
     const uint64_t lt_mask = __lanemask_lt();
     const uint32_t nbits = P.digit_bits, dmask = (1u << nbits) - 1u;
 
-    K key[kSortItems];
-    uint32_t val[kSortItems], rank[kSortItems], dig[kSortItems];
+    K key[kItems];
+    uint32_t val[kItems], rank[kItems], dig[kItems];
 #pragma unroll
-    for (int j = 0; j < kSortItems; j++) {
+    for (int j = 0; j < kItems; j++) {
         const uint32_t idx = base + j * kWave + l;
         const bool ok = idx < n;
         key[j] = ok ? kin[idx] : (K)0;
         val[j] = ok ? vin[idx] : 0u;
     }
 #pragma unroll
-    for (int j = 0; j < kSortItems; j++) {
+    for (int j = 0; j < kItems; j++) {
         const uint32_t idx = base + j * kWave + l;
         const bool ok = idx < n;
         const uint32_t dg = (uint32_t)(key[j] >> shift) & dmask;
@@ -305,7 +307,7 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(Plan P, const K *__restrict
     __syncthreads();
 
 #pragma unroll
-    for (int j = 0; j < kSortItems; j++) {
+    for (int j = 0; j < kItems; j++) {
         if (dig[j] < kRadix) {
             const uint32_t lp = s_tstart[dig[j]] + s_wcnt[w][dig[j]] + rank[j];
             s_keys[lp] = key[j];
@@ -313,8 +315,8 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(Plan P, const K *__restrict
         }
     }
     __syncthreads();
-    const uint32_t tile_base = tile * kSortTile;
-    const uint32_t tile_n = min((uint32_t)kSortTile, n - tile_base);
+    const uint32_t tile_base = tile * kTile;
+    const uint32_t tile_n = min((uint32_t)kTile, n - tile_base);
     for (uint32_t i = t; i < tile_n; i += kBlock) {
         const K kk = s_keys[i];
         const uint32_t vv = s_vals[i];
@@ -442,7 +444,7 @@ static void sort_d(const Plan &P, const SortBuffers &B, hipStream_t s)
     K *ka = (K *)B.keys_a, *kb = (K *)B.keys_b;
     uint32_t *va = B.vals_a, *vb = B.vals_b;
     hipLaunchKernelGGL((k_keys_hist<D, K>), dim3(hb), dim3(kBlock), 0, s, P, ka, va, B.hist);
-    const uint32_t tiles = (P.n + kSortTile - 1) / kSortTile;
+    const uint32_t tiles = (P.n + kBlock * sort_items<K>() - 1) / (kBlock * sort_items<K>());
     for (uint32_t q = 0; q < P.passes; q++) {
         uint64_t *st = B.status + (uint64_t)q * tiles * kRadix;
         const bool last = q + 1 == P.passes;
@@ -488,7 +490,7 @@ void launch_sort_hd(Plan &P, SortBuffers &B, hipStream_t s)
     uint64_t *ka = (uint64_t *)B.keys_a, *kb = (uint64_t *)B.keys_b;
     uint32_t *va = B.vals_a, *vb = B.vals_b;
     hipLaunchKernelGGL(k_hd_keys_hist, dim3(hb), dim3(kBlock), 0, s, P, ka, va, B.hist);
-    const uint32_t tiles = (P.n + kSortTile - 1) / kSortTile;
+    const uint32_t tiles = (P.n + kBlock * sort_items<uint64_t>() - 1) / (kBlock * sort_items<uint64_t>());
     for (uint32_t q = 0; q < P.passes; q++) {
         uint64_t *st = B.status + (uint64_t)q * tiles * kRadix;
         hipLaunchKernelGGL((k_onesweep<uint64_t, 1, false>), dim3(tiles), dim3(kBlock), 0, s, P, ka, va, kb, vb,
