@@ -159,8 +159,9 @@ int env_mode()
     return 0;
 }
 
-// HCA_RECORD=0: search groups of several cubes merge without the pairs
-// recorded by core marking (the result is the same)
+// HCA_RECORD=0: core marking records no neighbours, so search groups of
+// several cubes merge without the recorded pairs and every border point is
+// found by a walk (the result is the same)
 bool env_record()
 {
     const char *e = std::getenv("HCA_RECORD");
@@ -412,7 +413,7 @@ void carve_ws(Carver &cv, Plan &P, SortBuffers &B, const Sizes &Z, uint32_t **ze
         P.rec = cv.take<uint32_t>((size_t)kRec * n);
         P.nrec = cv.take<uint8_t>(n);
         P.spts16 = P.hd16 ? cv.take<uint32_t>((size_t)n * (P.sd / 2)) : nullptr;
-    } else if (P.m > 1 && !P.nseg && env_record()) {
+    } else if (env_record()) {
         P.rec = cv.take<uint32_t>((size_t)kRec * n);
         P.nrec = cv.take<uint8_t>(n);
     }

@@ -245,7 +245,7 @@ __device__ __forceinline__ bool within(const Pt<D> &a, const Pt<D> &b, int64_t e
             int32_t t = a.x[k] - b.x[k];
             s += __mul24(t, t);
         }
-        return s <= (int32_t)eps2;
+        return s <= (int32_t)min(eps2, (int64_t)INT32_MAX);   // a narrow sum is below 2^31
     }
 }
 
@@ -513,6 +513,24 @@ __device__ __forceinline__ void bitonic_sort(const int64_t *s_in, int n, int64_t
     for (int sl = 0; sl < 2; sl++) {
         const uint32_t r = sl * kWave + l;
         if ((int)r < n) { s_sum[r] = v[sl]; s_idx[r] = (uint8_t)ix[sl]; }
+    }
+}
+
+// Were all neighbours of sorted point p recorded by core marking?
+__device__ __forceinline__ bool rec_complete(const Plan &P, uint32_t p)
+{
+    return P.rec != nullptr && P.nrec[p] <= (uint32_t)kRec;
+}
+
+// Border point p (sorted position) takes the root of core point q (kNone:
+// noise) and offers its input index to that cluster's smallest member.
+__device__ __forceinline__ void finish_owner(const Plan &P, uint32_t p, uint32_t q)
+{
+    const uint32_t root = q == kNone ? kNone : ld_parent(P.parent + P.cell_of[q]);
+    P.owner[p] = root;
+    if (root != kNone) {
+        const uint32_t me = P.sidx[p];
+        if (me < ld_agent32(P.minmem + root)) atomicMin(P.minmem + root, me);
     }
 }
 

@@ -487,16 +487,29 @@ __global__ __launch_bounds__(kBlock) void k_nbr_lists(Plan P)
             group_lookup_n<kListBatch>(P, nk, G);
 #pragma unroll
             for (int b = 0; b < kListBatch; b++) {
-                // both groups' point boxes within eps
+                // both groups' point boxes within eps (32-bit when the host has
+                // shown that every tested pair's squared distance fits)
                 if (G[b] != kNone) {
                     const QBox<D> ob = load_gbox<D>(P, G[b]);
-                    int64_t acc = 0;
+                    bool far;
+                    if (P.wide) {
+                        int64_t acc = 0;
 #pragma unroll
-                    for (int e = 0; e < D; e++) {
-                        const int64_t gap = max((int64_t)ob.lo[e] - qb.hi[e], (int64_t)qb.lo[e] - ob.hi[e]);
-                        acc += gap > 0 ? gap * gap : 0;
+                        for (int e = 0; e < D; e++) {
+                            const int64_t gap = max((int64_t)ob.lo[e] - qb.hi[e], (int64_t)qb.lo[e] - ob.hi[e]);
+                            acc += gap > 0 ? gap * gap : 0;
+                        }
+                        far = acc > geo.eps2;
+                    } else {
+                        int32_t acc = 0;
+#pragma unroll
+                        for (int e = 0; e < D; e++) {
+                            const int32_t gap = max(max(ob.lo[e] - qb.hi[e], qb.lo[e] - ob.hi[e]), 0);
+                            acc += __mul24(gap, gap);
+                        }
+                        far = acc > (int32_t)min(geo.eps2, (int64_t)INT32_MAX);
                     }
-                    if (acc > geo.eps2) G[b] = kNone;
+                    if (far) G[b] = kNone;
                 }
                 const uint64_t m = __ballot(G[b] != kNone);
                 const uint32_t k = (uint32_t)__popcll(m);
@@ -675,7 +688,7 @@ __global__ __launch_bounds__(kBlock) void k_core(Plan P)
             }
             done = uniform(done);
             const uint32_t all = (1u << kPch) - 1u;
-            if (done != all) done = count_walk<D, WIDE>(P, g, gkey, pp, done, cnt, s_beg[w], s_pre[w], lt, geo);
+            if (done != all) done = count_walk<D, WIDE>(P, g, gkey, pp, done, cnt, s_beg[w], s_pre[w], lt, geo, pc);
             // lane k < np writes the result of point pc + k
             uint32_t mine = 0;
 #pragma unroll
@@ -685,7 +698,10 @@ __global__ __launch_bounds__(kBlock) void k_core(Plan P)
                 const uint32_t q = pc + l;
                 const uint32_t c = P.cell_of[q];
                 const bool dense = P.cell_start[c + 1] - P.cell_start[c] >= minpts;
-                if (!dense) P.core[q] = mine >= minpts;
+                if (!dense) {
+                    P.core[q] = mine >= minpts;
+                    if (P.rec) P.nrec[q] = (uint8_t)rec_count(mine);
+                }
             }
             // per-cube tallies in point order
 #pragma unroll
@@ -766,7 +782,7 @@ __global__ __launch_bounds__(kBlock) void k_core_chunks(Plan P)
         const bool core = l < np && (dense || mine >= minpts);
         if (l < np) {
             P.core[pc + l] = core;
-            if (P.rec) P.nrec[pc + l] = (uint8_t)min(dense ? 0u : mine, (uint32_t)kRec);
+            if (P.rec) P.nrec[pc + l] = (uint8_t)(dense ? 0u : rec_count(mine));
         }
         const uint32_t me = core ? P.sidx[pc + l] : kNone;
         // one atomic per cube of the chunk (cubes are runs of lanes)
@@ -1562,6 +1578,31 @@ __device__ __forceinline__ void border_walk(const Plan &P, uint32_t g, uint64_t 
 
 
 // ---------------------------------------------------------------------------
+// Border points whose neighbours core marking saw in full (all within eps,
+// all recorded: fewer than minPts of them, at most kRec): the nearest core
+// point among them, ties to the smaller input index, one thread per point.
+// The walks below take the other non-core points.
+// ---------------------------------------------------------------------------
+template <int D, bool WIDE>
+__global__ __launch_bounds__(kBlock) void k_border_rec(Plan P)
+{
+    for (uint32_t p = blockIdx.x * kBlock + threadIdx.x; p < P.n; p += gridDim.x * kBlock) {
+        if (P.core[p] || !rec_complete(P, p)) continue;
+        const Pt<D> a = load_pt<D>(P.spts, p);
+        int64_t bd = INT64_MAX;
+        uint32_t bi = kNone, bq = kNone;
+        for (uint32_t r = 0, nr = P.nrec[p]; r < nr; r++) {
+            const uint32_t q = P.rec[(uint64_t)p * kRec + r];
+            if (!P.core[q]) continue;
+            const int64_t dd = dist2<D, WIDE>(a, load_pt<D>(P.spts, q));
+            const uint32_t qi = P.sidx[q];
+            if (dd < bd || (dd == bd && qi < bi)) { bd = dd; bi = qi; bq = q; }
+        }
+        finish_owner(P, p, bq);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Border points: each non-core point takes the root of its nearest core
 // point within eps, ties to the smaller input index; none -> noise.
 // ---------------------------------------------------------------------------
@@ -1585,7 +1626,7 @@ __global__ __launch_bounds__(kBlock) void k_border(Plan P)
             load_chunk<D>(P, pc, np, pp);
 #pragma unroll
             for (int k = 0; k < kPch; k++)
-                if (k < (int)np && !P.core[pc + k]) todo |= 1u << k;
+                if (k < (int)np && !P.core[pc + k] && !rec_complete(P, pc + k)) todo |= 1u << k;
             todo = uniform(todo);
             if (!todo) continue;
             int64_t bd[kPch];
@@ -1612,7 +1653,7 @@ __global__ __launch_bounds__(kBlock) void k_border_chunks(Plan P)
     const DynRange dr_ = dyn_range(P.ctr->dyn[kDynBorder]);
     HCA_FOR_UNITS_DYN(u, (n + kPch - 1) / kPch, dr_) {
         const uint32_t pc = u * kPch, np = min((uint32_t)kPch, n - pc);
-        const bool mine = l < np && !P.core[pc + l];
+        const bool mine = l < np && !P.core[pc + l] && !rec_complete(P, pc + l);
         const uint32_t todo = (uint32_t)__ballot(mine) & ((1u << kPch) - 1u);
         if (!todo) continue;
         const uint32_t grp = mine ? P.group_of[P.cell_of[pc + l]] : kNone;
@@ -1864,6 +1905,10 @@ void launch_compress(const Plan &P, int blocks, hipStream_t s)
 
 void launch_border(const Plan &P, int blocks, hipStream_t s)
 {
+    if (P.rec) {
+        const int cb = (int)std::min<uint64_t>((P.n + kBlock - 1) / kBlock, 2048);
+        HCA_DISPATCH_DW(k_border_rec, P, cb, s);
+    }
     if (P.m > 1) HCA_DISPATCH_DW(k_border_chunks, P, blocks, s);
     else HCA_DISPATCH_DW(k_border, P, blocks, s);
 }

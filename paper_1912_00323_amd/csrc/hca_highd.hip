@@ -589,7 +589,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_core(Plan P)
         const bool core = in && !later && (dense || mine >= minpts);
         if (in && !later) {
             P.core[pc + l] = core;
-            P.nrec[pc + l] = (uint8_t)min(dense ? 0u : mine, (uint32_t)kRec);
+            P.nrec[pc + l] = (uint8_t)(dense ? 0u : rec_count(mine));
         }
         const uint64_t um = __ballot(later);
         if (um) {
@@ -647,7 +647,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_core_rest(Plan P)
         const bool core = in && mine >= minpts;
         if (in) {
             P.core[q] = core;
-            P.nrec[q] = (uint8_t)min(mine, (uint32_t)kRec);
+            P.nrec[q] = (uint8_t)rec_count(mine);
         }
         hd_tally(P, in, cell, core, core ? P.sidx[q] : kNone);
     }
@@ -765,7 +765,7 @@ __global__ __launch_bounds__(kBlock) void k_link_recorded(Plan P)
 {
     for (uint32_t q = blockIdx.x * kBlock + threadIdx.x; q < P.n; q += gridDim.x * kBlock) {
         if (!P.core[q]) continue;
-        const uint32_t c = P.cell_of[q], nr = P.nrec[q];
+        const uint32_t c = P.cell_of[q], nr = min((uint32_t)P.nrec[q], (uint32_t)kRec);
         for (uint32_t r = 0; r < nr; r++) {
             const uint32_t q2 = P.rec[(uint64_t)q * kRec + r];
             if (!P.core[q2]) continue;
@@ -841,21 +841,47 @@ __device__ __forceinline__ void hd_border_walk(const Plan &P, uint32_t g, const 
     }
 }
 
-// Non-core points (sorted positions, in runs of a wave) into the second half
-// of the list.
+// Non-core points whose neighbours were not all recorded (sorted positions,
+// in runs of a wave) into the second half of the list.
 __global__ __launch_bounds__(kBlock) void k_hd_noncore_list(Plan P)
 {
     const uint32_t l = lane_id();
     for (uint32_t base = (blockIdx.x * kBlock + threadIdx.x) & ~(kWave - 1u); base < P.n;
          base += gridDim.x * kBlock) {
         const uint32_t q = base + l;
-        const bool nc = q < P.n && !P.core[q];
+        const bool nc = q < P.n && !P.core[q] && !rec_complete(P, q);
         const uint64_t m = __ballot(nc);
         if (!m) continue;
         uint32_t at = 0;
         if (l == 0) at = atomicAdd(&P.ctr->hd_noncore, (uint32_t)__popcll(m));
         at = __shfl(at, 0);
         if (nc) P.hd_list[P.n + at + __popcll(m & __lanemask_lt())] = q;
+    }
+}
+
+// Non-core points whose neighbours were all recorded: the nearest core point
+// among them (exact 64-bit distances over the int32 rows), one thread per point.
+__global__ __launch_bounds__(kBlock) void k_hd_border_rec(Plan P)
+{
+    const uint32_t sd = P.sd;
+    for (uint32_t p = blockIdx.x * kBlock + threadIdx.x; p < P.n; p += gridDim.x * kBlock) {
+        if (P.core[p] || !rec_complete(P, p)) continue;
+        const int32_t *a = P.spts + (uint64_t)p * sd;
+        int64_t bd = INT64_MAX;
+        uint32_t bi = kNone, bq = kNone;
+        for (uint32_t r = 0, nr = P.nrec[p]; r < nr; r++) {
+            const uint32_t q = P.rec[(uint64_t)p * kRec + r];
+            if (!P.core[q]) continue;
+            const int32_t *b = P.spts + (uint64_t)q * sd;
+            int64_t dd = 0;
+            for (uint32_t e = 0; e < sd; e++) {
+                const int64_t t = (int64_t)a[e] - b[e];
+                dd += t * t;
+            }
+            const uint32_t qi = P.sidx[q];
+            if (dd < bd || (dd == bd && qi < bi)) { bd = dd; bi = qi; bq = q; }
+        }
+        finish_owner(P, p, bq);
     }
 }
 
@@ -970,6 +996,7 @@ void launch_hd_merge(const Plan &P, int blocks, hipStream_t s)
 void launch_hd_border(const Plan &P, int blocks, hipStream_t s)
 {
     const int cb = (int)std::min<uint64_t>((P.n + kBlock - 1) / kBlock, 2048);
+    hipLaunchKernelGGL(k_hd_border_rec, dim3(cb), dim3(kBlock), 0, s, P);
     hipLaunchKernelGGL(k_hd_noncore_list, dim3(cb), dim3(kBlock), 0, s, P);
     if (P.wide) hipLaunchKernelGGL(k_hd_border<true>, dim3(blocks), dim3(kBlock), 0, s, P);
     else hipLaunchKernelGGL(k_hd_border<false>, dim3(blocks), dim3(kBlock), 0, s, P);

@@ -10,6 +10,9 @@ namespace hca {
 constexpr int kMaxDim = 8;                     // axes of the packed cube key
 constexpr int kMaxDimHigh = 64;                // axes of a point (more than 8: hashed cubes)
 constexpr int kRec = 8;                        // neighbours recorded per point by core marking
+
+// nrec value of a point that found c neighbours: c when all were recorded
+__host__ __device__ constexpr uint32_t rec_count(uint32_t c) { return c <= (uint32_t)kRec ? c : kRec + 1; }
 constexpr int kWave = 64;
 constexpr int kBlock = 256;                    // 4 waves per workgroup
 constexpr uint32_t kNone = 0xFFFFFFFFu;
@@ -118,9 +121,9 @@ struct Plan {
     uint8_t kdim[kMaxDim];
     const int32_t *hd_origin;   // [d] origin of every axis (hd)
     uint32_t *hd_list;          // [2n] sorted positions: undecided points, then non-core points (hd)
-    uint32_t *rec;              // [n][kRec] first neighbours found by core marking (sorted positions),
-                                // or null (kept for more than 8 axes and for groups of several cubes)
-    uint8_t *nrec;              // [n] how many of them were recorded
+    uint32_t *rec;              // [n][kRec] first neighbours found by core marking (sorted positions), or null
+    uint8_t *nrec;              // [n] neighbours found when at most kRec (then all are recorded), else
+                                // kRec + 1; 0 for points of cubes with minPts points
     uint32_t hd16;              // packed rows wanted (hd, every span below 2^15 and 32-bit sums)
     uint32_t *spts16;           // [n][sd / 2] sorted points less the origin as packed int16 pairs, or null
     // neighbour search over groups: offsets in [-R, R]^d, self first

@@ -111,8 +111,9 @@ def test_group_lists_fallback(ctx, slab, monkeypatch):
 
 @pytest.mark.parametrize("record", ["0", "1"])
 def test_group_recorded_pairs(ctx, record, monkeypatch):
-    """Search groups of several cubes with and without joining the neighbour
-    pairs recorded by core marking before the merge tiles: the same labels."""
+    """With and without the neighbours recorded by core marking (joined
+    before the merge tiles of search groups, and deciding the border points
+    whose neighbours were all recorded): the same labels."""
     monkeypatch.setenv("HCA_SEARCH", "group")
     monkeypatch.setenv("HCA_RECORD", record)
     for d in (3, 5, 8):
@@ -123,6 +124,44 @@ def test_group_recorded_pairs(ctx, record, monkeypatch):
             print(f"[case] recorded pairs={record} d={d} eps={f} minPts={mp}", flush=True)
             want = oracle.dbscan(pts, f * 2 ** 12, mp)
             assert np.array_equal(gpu_labels(ctx, pts, f * 2 ** 12, mp), want), (record, d, f, mp)
+    # cubes as search groups: the records decide most border points
+    monkeypatch.delenv("HCA_SEARCH")
+    for d in (2, 4):
+        rng = np.random.default_rng(90 + d)
+        pts = quantise(make_blobs(rng, 20000, d, 8, 0.02, 0.15), 12)
+        for f, mp in ((0.01, 4), (0.02, 9), (0.03, 12)):
+            print(f"[case] recorded neighbours={record} d={d} eps={f} minPts={mp}", flush=True)
+            want = oracle.dbscan(pts, f * 2 ** 12, mp)
+            assert np.array_equal(gpu_labels(ctx, pts, f * 2 ** 12, mp), want), (record, d, f, mp)
+
+
+def test_eps_past_int32(ctx):
+    """eps^2 between 2^31 and 2^32 over small spans: 32-bit squared distances
+    with a threshold past int32 (the data then sits in one cube per axis),
+    here and through the batch path (one cluster per data set)."""
+    rng = np.random.default_rng(91)
+    for d, mode in ((2, None), (3, "group"), (8, None)):
+        pts = rng.integers(0, 1000, size=(3000, d)).astype(np.int32)
+        pts[:50] += 20000                               # a second, distant clump
+        for eps in (50_000.0, 60_000.0, 65_000.0):      # eps^2 = 2.5e9, 3.6e9, 4.2e9
+            os.environ.pop("HCA_SEARCH", None)
+            if mode:
+                os.environ["HCA_SEARCH"] = mode
+            try:
+                print(f"[case] eps past int32 d={d} eps={eps}", flush=True)
+                want = oracle.dbscan(pts, eps, 5)
+                assert np.array_equal(gpu_labels(ctx, pts, eps, 5), want), (d, eps)
+            finally:
+                os.environ.pop("HCA_SEARCH", None)
+    # the batch path with the same data sets
+    from paper_1912_00323_amd.datagen import Workload
+    jobs = [Workload(f"big{d}", rng.integers(0, 1000, size=(2000, d)).astype(np.int32), 60_000.0, 4, 0)
+            for d in (1, 2, 3, 4)]
+    import torch
+    flat = torch.from_numpy(np.concatenate([j.points.ravel() for j in jobs]).astype(np.int32)).cuda()
+    got = ctx.cluster_batch(flat, [j.n for j in jobs], [j.d for j in jobs], [j.eps for j in jobs],
+                            [j.min_pts for j in jobs]).cpu().numpy()
+    assert (got == 0).all()
 
 
 def test_mixed_family(ctx):
