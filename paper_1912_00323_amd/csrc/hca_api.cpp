@@ -412,10 +412,12 @@ void carve_ws(Carver &cv, Plan &P, SortBuffers &B, const Sizes &Z, uint32_t **ze
         P.hd_list = cv.take<uint32_t>((size_t)2 * n);
         P.rec = cv.take<uint32_t>((size_t)kRec * n);
         P.nrec = cv.take<uint8_t>(n);
+        P.blist = P.hd_list + n;
         P.spts16 = P.hd16 ? cv.take<uint32_t>((size_t)n * (P.sd / 2)) : nullptr;
     } else if (env_record()) {
         P.rec = cv.take<uint32_t>((size_t)kRec * n);
         P.nrec = cv.take<uint8_t>(n);
+        P.blist = cv.take<uint32_t>(n);
     }
     const size_t ksz = Z.wide_keys ? 8 : 4;
     B.keys_a = cv.take<char>((size_t)n * ksz);

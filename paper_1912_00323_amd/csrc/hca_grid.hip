@@ -1602,6 +1602,84 @@ __global__ __launch_bounds__(kBlock) void k_border_rec(Plan P)
     }
 }
 
+// The non-core points whose neighbours were not all recorded (sorted
+// positions, in runs of a wave) into P.blist.
+__global__ __launch_bounds__(kBlock) void k_border_list(Plan P)
+{
+    const uint32_t l = lane_id();
+    for (uint32_t base = (blockIdx.x * kBlock + threadIdx.x) & ~(kWave - 1u); base < P.n;
+         base += gridDim.x * kBlock) {
+        const uint32_t q = base + l;
+        const bool left = q < P.n && !P.core[q] && !rec_complete(P, q);
+        const uint64_t m = __ballot(left);
+        if (!m) continue;
+        uint32_t at = 0;
+        if (l == 0) at = atomicAdd(&P.ctr->n_blist, (uint32_t)__popcll(m));
+        at = __shfl(at, 0);
+        if (left) P.blist[at + __popcll(m & __lanemask_lt())] = q;
+    }
+}
+
+// Chunks of 8 points of P.blist (1 when the list is short), walked group by
+// group (group mode or cubes as groups, batches included): the nearest core
+// point within eps.
+template <int D, bool WIDE>
+__global__ __launch_bounds__(kBlock) void k_border_walk_list(Plan P)
+{
+    __shared__ uint32_t s_beg[kWavesPerBlock][kWave], s_pre[kWavesPerBlock][kWave];
+    const uint32_t w = wave_in_block(), l = lane_id();
+    const uint32_t nl = ld_agent32(&P.ctr->n_blist);
+    // a short list: one point per wave, so that the walks run side by side
+    const uint32_t per = nl >= (uint32_t)kPch * gridDim.x * kWavesPerBlock ? (uint32_t)kPch : 1u;
+    uint32_t lt = 0;
+    const DynRange dr_ = dyn_range(P.ctr->dyn[kDynBorder]);
+    HCA_FOR_UNITS_DYN(u, (nl + per - 1) / per, dr_) {
+        const uint32_t b0 = u * per, np = min(per, nl - b0);
+        uint32_t pos[kPch];
+        Pt<D> pp[kPch];
+#pragma unroll
+        for (int k = 0; k < kPch; k++) {
+            pos[k] = uniform(P.blist[b0 + min((uint32_t)k, np - 1)]);
+            pp[k] = load_pt<D>(P.spts, pos[k]);
+#pragma unroll
+            for (int e = 0; e < D; e++) pp[k].x[e] = uniform_i(pp[k].x[e]);
+        }
+        uint32_t q = pos[0];
+#pragma unroll
+        for (int k = 1; k < kPch; k++)
+            if ((uint32_t)k == l) q = pos[k];
+        const bool in = l < np;
+        const uint32_t todo = (uint32_t)__ballot(in) & ((1u << kPch) - 1u);
+        const uint32_t grp = in ? P.group_of[P.cell_of[q]] : kNone;
+        int64_t bd[kPch];
+        uint32_t bi[kPch], bp[kPch];
+#pragma unroll
+        for (int k = 0; k < kPch; k++) { bd[k] = INT64_MAX; bi[k] = kNone; bp[k] = kNone; }
+        uint32_t left = todo;
+        while (left) {
+            const uint32_t g = __shfl(grp, __ffs(left) - 1);
+            const uint32_t run = (uint32_t)__ballot(grp == g) & left;
+            left &= ~run;
+            const uint64_t gkey = P.group_key[g];
+            border_walk<D, WIDE>(P, g, gkey, pp, run, bd, bi, bp, s_beg[w], s_pre[w], lt, cube_geo<D>(P, gkey));
+        }
+#pragma unroll
+        for (int k = 0; k < kPch; k++) {
+            if (!(todo & (1u << k))) continue;
+            int64_t d0 = bd[k];
+            uint32_t i0 = bi[k], q0 = bp[k];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const int64_t d1 = __shfl_xor(d0, o);
+                const uint32_t i1 = __shfl_xor(i0, o), q1 = __shfl_xor(q0, o);
+                if (d1 < d0 || (d1 == d0 && i1 < i0)) { d0 = d1; i0 = i1; q0 = q1; }
+            }
+            if (l == 0) finish_owner(P, pos[k], q0);
+        }
+    }
+    flush_tests(P, kTestsBorder, lt);
+}
+
 // ---------------------------------------------------------------------------
 // Border points: each non-core point takes the root of its nearest core
 // point within eps, ties to the smaller input index; none -> noise.
@@ -1903,11 +1981,22 @@ void launch_compress(const Plan &P, int blocks, hipStream_t s)
     hipLaunchKernelGGL(k_compress, dim3(blocks), dim3(kBlock), 0, s, P);
 }
 
+void launch_border_list(const Plan &P, hipStream_t s)
+{
+    const int cb = (int)std::min<uint64_t>((P.n + kBlock - 1) / kBlock, 2048);
+    hipLaunchKernelGGL(k_border_list, dim3(cb), dim3(kBlock), 0, s, P);
+}
+
+// With recorded neighbours: the points they decide, then a walk over the
+// list of the others; without: a walk over all points.
 void launch_border(const Plan &P, int blocks, hipStream_t s)
 {
     if (P.rec) {
         const int cb = (int)std::min<uint64_t>((P.n + kBlock - 1) / kBlock, 2048);
         HCA_DISPATCH_DW(k_border_rec, P, cb, s);
+        launch_border_list(P, s);
+        HCA_DISPATCH_DW(k_border_walk_list, P, blocks, s);
+        return;
     }
     if (P.m > 1) HCA_DISPATCH_DW(k_border_chunks, P, blocks, s);
     else HCA_DISPATCH_DW(k_border, P, blocks, s);

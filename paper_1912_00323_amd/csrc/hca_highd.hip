@@ -841,24 +841,6 @@ __device__ __forceinline__ void hd_border_walk(const Plan &P, uint32_t g, const 
     }
 }
 
-// Non-core points whose neighbours were not all recorded (sorted positions,
-// in runs of a wave) into the second half of the list.
-__global__ __launch_bounds__(kBlock) void k_hd_noncore_list(Plan P)
-{
-    const uint32_t l = lane_id();
-    for (uint32_t base = (blockIdx.x * kBlock + threadIdx.x) & ~(kWave - 1u); base < P.n;
-         base += gridDim.x * kBlock) {
-        const uint32_t q = base + l;
-        const bool nc = q < P.n && !P.core[q] && !rec_complete(P, q);
-        const uint64_t m = __ballot(nc);
-        if (!m) continue;
-        uint32_t at = 0;
-        if (l == 0) at = atomicAdd(&P.ctr->hd_noncore, (uint32_t)__popcll(m));
-        at = __shfl(at, 0);
-        if (nc) P.hd_list[P.n + at + __popcll(m & __lanemask_lt())] = q;
-    }
-}
-
 // Non-core points whose neighbours were all recorded: the nearest core point
 // among them (exact 64-bit distances over the int32 rows), one thread per point.
 __global__ __launch_bounds__(kBlock) void k_hd_border_rec(Plan P)
@@ -895,12 +877,14 @@ __global__ __launch_bounds__(kBlock) void k_hd_border(Plan P)
     __shared__ int32_t s_qb[kWavesPerBlock][2 * kMaxDimHigh];
     __shared__ uint32_t s_beg[kWavesPerBlock][kWave], s_pre[kWavesPerBlock][kWave];
     const uint32_t w = wave_in_block(), l = lane_id();
-    const uint32_t nl = ld_agent32(&P.ctr->hd_noncore);
-    const uint32_t *list = P.hd_list + P.n;
+    const uint32_t nl = ld_agent32(&P.ctr->n_blist);
+    const uint32_t *list = P.blist;
+    // a short list: one point per wave, so that the walks run side by side
+    const uint32_t per = nl >= (uint32_t)kPch * gridDim.x * kWavesPerBlock ? (uint32_t)kPch : 1u;
     uint32_t lt = 0;
     const DynRange dr_ = dyn_range(P.ctr->dyn[kDynBorder]);
-    HCA_FOR_UNITS_DYN(u, (nl + kPch - 1) / kPch, dr_) {
-        const uint32_t b0 = u * kPch, np = min((uint32_t)kPch, nl - b0);
+    HCA_FOR_UNITS_DYN(u, (nl + per - 1) / per, dr_) {
+        const uint32_t b0 = u * per, np = min(per, nl - b0);
         uint32_t pos[kPch];
 #pragma unroll
         for (int k = 0; k < kPch; k++) pos[k] = list[b0 + min((uint32_t)k, np - 1)];
@@ -997,7 +981,7 @@ void launch_hd_border(const Plan &P, int blocks, hipStream_t s)
 {
     const int cb = (int)std::min<uint64_t>((P.n + kBlock - 1) / kBlock, 2048);
     hipLaunchKernelGGL(k_hd_border_rec, dim3(cb), dim3(kBlock), 0, s, P);
-    hipLaunchKernelGGL(k_hd_noncore_list, dim3(cb), dim3(kBlock), 0, s, P);
+    launch_border_list(P, s);
     if (P.wide) hipLaunchKernelGGL(k_hd_border<true>, dim3(blocks), dim3(kBlock), 0, s, P);
     else hipLaunchKernelGGL(k_hd_border<false>, dim3(blocks), dim3(kBlock), 0, s, P);
 }

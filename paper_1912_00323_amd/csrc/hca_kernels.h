@@ -44,6 +44,8 @@ void launch_hd_merge(const Plan &P, int blocks, hipStream_t s);
 void launch_hd_border(const Plan &P, int blocks, hipStream_t s);
 // join the cubes of the neighbour pairs recorded by core marking (P.rec)
 void launch_link_recorded(const Plan &P, hipStream_t s);
+// the non-core points whose neighbours were not all recorded into P.blist
+void launch_border_list(const Plan &P, hipStream_t s);
 
 // batches: stage the data sets of one dimension d <= 4 contiguously (rows and
 // their data set, read from each data set's own rows) and take their bounding

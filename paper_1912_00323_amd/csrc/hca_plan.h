@@ -9,7 +9,7 @@ namespace hca {
 
 constexpr int kMaxDim = 8;                     // axes of the packed cube key
 constexpr int kMaxDimHigh = 64;                // axes of a point (more than 8: hashed cubes)
-constexpr int kRec = 8;                        // neighbours recorded per point by core marking
+constexpr int kRec = 16;                       // neighbours recorded per point by core marking
 
 // nrec value of a point that found c neighbours: c when all were recorded
 __host__ __device__ constexpr uint32_t rec_count(uint32_t c) { return c <= (uint32_t)kRec ? c : kRec + 1; }
@@ -60,7 +60,7 @@ struct Counters {
     uint32_t hmask;             // hash slots in use - 1 (a power of two - 1)
     uint32_t nbr_ticket;        // tiles of the backward-list scan
     uint32_t hd_left;           // more than kMaxDim axes: points left undecided by the first core pass
-    uint32_t hd_noncore;        // more than kMaxDim axes: non-core points
+    uint32_t n_blist;           // non-core points left for the border walk (blist)
     uint32_t pad[6];
     uint32_t work_count[kWorkRegions * kCounterStride];   // region r at [r * kCounterStride]
     // pair tests executed, per phase (core, merge, border), spread over
@@ -124,6 +124,7 @@ struct Plan {
     uint32_t *rec;              // [n][kRec] first neighbours found by core marking (sorted positions), or null
     uint8_t *nrec;              // [n] neighbours found when at most kRec (then all are recorded), else
                                 // kRec + 1; 0 for points of cubes with minPts points
+    uint32_t *blist;            // [n] non-core points whose neighbours were not all recorded (with rec)
     uint32_t hd16;              // packed rows wanted (hd, every span below 2^15 and 32-bit sums)
     uint32_t *spts16;           // [n][sd / 2] sorted points less the origin as packed int16 pairs, or null
     // neighbour search over groups: offsets in [-R, R]^d, self first
