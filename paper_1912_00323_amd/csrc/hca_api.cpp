@@ -168,6 +168,13 @@ bool env_record()
     return !(e && !std::strcmp(e, "0"));
 }
 
+// HCA_PREFIX=0: group-mode lists look every offset up (no prefix ranges)
+bool env_prefix()
+{
+    const char *e = std::getenv("HCA_PREFIX");
+    return !(e && !std::strcmp(e, "0"));
+}
+
 bool env_reps()
 {
     const char *e = std::getenv("HCA_REPS");
@@ -362,6 +369,7 @@ uint32_t cube_list_width(int d, int32_t radius, uint32_t n_off)
 // Sizes of one launch sequence, fixed before the workspace is carved.
 struct Sizes {
     bool wide_keys = false;
+    uint32_t pbits = 0;              // bits of the group-key prefix of the first d/2 axes (0: no prefix ranges)
     uint32_t gbits = 0;              // bits of the group key (direct table: 2^gbits slots)
     uint64_t hcap = 0;               // hash slots allocated
     uint32_t sort_tiles = 0, scan_tiles = 0;
@@ -448,6 +456,10 @@ void carve_ws(Carver &cv, Plan &P, SortBuffers &B, const Sizes &Z, uint32_t **ze
         P.nbr_bcursor = cv.take<uint32_t>(n);
         P.nbr_back = cv.take<uint32_t>(P.nbr_cap);
         P.gbox = cv.take<int32_t>((size_t)n * 2 * sd);
+    }
+    if (Z.pbits) {
+        P.pstart = cv.take<uint32_t>((size_t)1 << Z.pbits);
+        P.pend = cv.take<uint32_t>((size_t)1 << Z.pbits);
     }
     P.work = cv.take<uint32_t>((size_t)2 * P.work_cap);
     P.owner = cv.take<uint32_t>(n);
@@ -909,6 +921,14 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
     P.list_w = P.m == 1 ? cube_list_width(d, G.radius, n_off) : 0;
     Sizes Z;
     plan_sizes(P, gbits, stats != nullptr && ctx->prof != -1, stats != nullptr, &Z);
+    // group-mode lists: ranges of groups per prefix of the first d/2 axes,
+    // when that prefix takes at most 22 bits (HCA_PREFIX=0 turns it off)
+    if (P.m > 1 && P.nbr_cap && d >= 2 && env_prefix()) {
+        const int da = d / 2;
+        P.pshift = P.goff[da - 1];
+        const uint32_t pbits = gbits - P.pshift;
+        if (pbits <= 22) Z.pbits = std::max<uint32_t>(1, pbits);
+    }
     P.pts = points;
     P.labels = labels;
     P.core_out = core_out;

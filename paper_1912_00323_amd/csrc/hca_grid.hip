@@ -367,6 +367,20 @@ __global__ __launch_bounds__(kBlock) void k_group_box(Plan P)
     }
 }
 
+// Group mode: the range of groups of every prefix of the first d/2 axes
+// (groups are numbered in key order, so each prefix's groups are
+// consecutive).  Entries of prefixes absent from this call keep stale
+// values, which the readers reject (the group at pstart has another prefix).
+__global__ __launch_bounds__(kBlock) void k_prefix_ranges(Plan P)
+{
+    const uint32_t ng = ld_agent32(&P.ctr->n_groups);
+    for (uint32_t g = blockIdx.x * kBlock + threadIdx.x; g < ng; g += gridDim.x * kBlock) {
+        const uint64_t p = P.group_key[g] >> P.pshift;
+        if (g == 0 || (P.group_key[g - 1] >> P.pshift) != p) P.pstart[p] = g;
+        if (g + 1 == ng || (P.group_key[g + 1] >> P.pshift) != p) P.pend[p] = g + 1;
+    }
+}
+
 template <int D>
 __device__ __forceinline__ QBox<D> load_gbox(const Plan &P, uint32_t g)
 {
@@ -400,6 +414,132 @@ constexpr int kListBatch = 4;        // lookups in flight per lane
 
 constexpr int kListHalf = 128;       // offset combinations per half of the axes, at most
 
+// Append the forward entries (G > g, point boxes within eps) in the wave's
+// slab; a group that does not fit is marked and counted by the caller.
+template <int D>
+__device__ __forceinline__ void list_append(const Plan &P, uint32_t G, const QBox<D> &qb, int64_t eps2,
+                                            uint32_t &at, uint32_t end, bool &fits)
+{
+    if (G != kNone) {
+        const QBox<D> ob = load_gbox<D>(P, G);
+        bool far;
+        if (P.wide) {
+            int64_t acc = 0;
+#pragma unroll
+            for (int e = 0; e < D; e++) {
+                const int64_t gap = max((int64_t)ob.lo[e] - qb.hi[e], (int64_t)qb.lo[e] - ob.hi[e]);
+                acc += gap > 0 ? gap * gap : 0;
+            }
+            far = acc > eps2;
+        } else {
+            int32_t acc = 0;
+#pragma unroll
+            for (int e = 0; e < D; e++) {
+                const int32_t gap = max(max(ob.lo[e] - qb.hi[e], qb.lo[e] - ob.hi[e]), 0);
+                acc += __mul24(gap, gap);
+            }
+            far = acc > (int32_t)min(eps2, (int64_t)INT32_MAX);
+        }
+        if (far) G = kNone;
+    }
+    const uint64_t m = __ballot(G != kNone);
+    const uint32_t k = (uint32_t)__popcll(m);
+    if (at + k > end) fits = false;
+    if (fits && G != kNone) {
+        P.nbr[at + __popcll(m & __lanemask_lt())] = G;
+        atomicAdd(P.nbr_bcount + G, 1u);
+    }
+    if (fits) at += k;
+}
+
+// Group mode with prefix ranges: for every first-half offset that can hold a
+// point within eps and points forwards (or is zero), the groups of its
+// prefix are scanned instead of looking up each second-half offset; a group
+// is kept when its point box comes within eps (which also bounds its
+// second-half offsets to one step) and, for a zero first half, when its
+// second half points forwards.  Returns false, with nothing written, when a
+// range is longer than kPrefixScanMax (then the offsets are looked up).
+constexpr uint32_t kPrefixScanMax = 128;
+
+template <int D>
+__device__ __forceinline__ bool list_by_prefix(const Plan &P, uint32_t g, uint64_t gkey, const QBox<D> &qb,
+                                               const Geo<D> &geo, uint32_t ng, int NA, uint32_t *s_pre,
+                                               uint32_t *s_rs, int8_t *s_ga, uint32_t &at, uint32_t end,
+                                               uint32_t &overflow)
+{
+    constexpr int DA = D / 2;
+    const uint32_t l = lane_id();
+    const uint64_t gpre = gkey >> P.pshift;
+    uint32_t tot = 0;
+    bool big = false;
+    for (int i0 = 0; i0 < NA; i0 += kWave) {
+        const int i = i0 + (int)l;
+        uint32_t size = 0, rs = 0;
+        int8_t sg = 0;
+        if (i < NA) {
+            sg = half_sign<DA>(P, (uint32_t)i);
+            if (sg >= 0 && half_gap2<D, DA>(P, gkey, 0, (uint32_t)i, qb, geo) != INT64_MAX) {
+                const uint64_t pr = gpre + (uint64_t)(half_key_delta<DA>(P, 0, (uint32_t)i) >> P.pshift);
+                const uint32_t a = P.pstart[pr];
+                if (a < ng && (P.group_key[a] >> P.pshift) == pr) {
+                    rs = a;
+                    size = P.pend[pr] - a;
+                }
+            }
+        }
+        big |= size > kPrefixScanMax;
+        const uint32_t inc = wave_inclusive_scan(size);
+        __builtin_amdgcn_wave_barrier();
+        if (i < NA) {
+            s_pre[i] = tot + inc - size;
+            s_rs[i] = rs;
+            s_ga[i] = sg;
+        }
+        tot += __shfl(inc, kWave - 1);
+    }
+    if (__ballot(big)) return false;
+    if (l == 0) s_pre[NA] = tot;
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t start = at;
+    bool fits = true;
+    for (uint32_t t0 = 0; t0 < tot; t0 += kWave) {
+        const uint32_t t = t0 + l;
+        uint32_t G = kNone;
+        if (t < tot) {
+            int lo = 0, hi = NA;                          // last i with s_pre[i] <= t
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (s_pre[mid] <= t) lo = mid; else hi = mid;
+            }
+            const uint32_t c = s_rs[lo] + (t - s_pre[lo]);
+            bool ok = true;
+            if (s_ga[lo] == 0) {                          // zero first half: the second must point forwards
+                const uint64_t ck = P.group_key[c];
+                int lead = 0;
+#pragma unroll
+                for (int e = DA; e < D; e++) {
+                    const uint64_t mask = (1ull << P.gw[e]) - 1ull;
+                    const int64_t dlt = (int64_t)((ck >> P.goff[e]) & mask) - (int64_t)((gkey >> P.goff[e]) & mask);
+                    if (lead == 0) lead = dlt > 0 ? 1 : (dlt < 0 ? -1 : 0);
+                }
+                ok = lead > 0;
+            }
+            if (ok) G = c;
+        }
+        list_append<D>(P, G, qb, geo.eps2, at, end, fits);
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (l == 0) {
+        P.nbr_start[g] = start;
+        P.nbr_count[g] = fits ? at - start : kNone;
+    }
+    if (!fits) {
+        at = start;
+        overflow++;
+    }
+    return true;
+}
+
 // Forward lists, one wave per group: only offsets that lead to a larger key
 // (the first non-zero component, from axis 0, is positive) are looked up,
 // and a found group is kept when the two point boxes come within eps; its
@@ -413,6 +553,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr_lists(Plan P)
     __shared__ int8_t s_ga[kWavesPerBlock][kListHalf], s_gb[kWavesPerBlock][kListHalf];
     __shared__ int64_t s_ka[kWavesPerBlock][kListHalf], s_kb[kWavesPerBlock][kListHalf];
     __shared__ uint32_t s_pre[kWavesPerBlock][kListHalf + 1];
+    __shared__ uint32_t s_rs[kWavesPerBlock][kListHalf];
     int64_t(*s_in)[kListHalf] = s_ka;     // unsorted sums, before the key offsets
     int NA = 1, NB = 1;
     for (int e = 0; e < DA; e++) NA *= (int)P.list_w;
@@ -429,6 +570,11 @@ __global__ __launch_bounds__(kBlock) void k_nbr_lists(Plan P)
         const uint64_t gkey = P.group_key[g];
         const Geo<D> geo = cube_geo<D>(P, gkey);
         const QBox<D> qb = load_gbox<D>(P, g);
+        if constexpr (DA >= 1) {
+            if (P.pstart && list_by_prefix<D>(P, g, gkey, qb, geo, ng, NA, s_pre[w], s_rs[w], s_ga[w], at, end,
+                                              overflow))
+                continue;
+        }
         // both halves' gap sums, sorted ascending, with their signs
         for (int i = l; i < NA; i += kWave) s_in[w][i] = half_gap2<D, DA>(P, gkey, 0, i, qb, geo);
         __builtin_amdgcn_wave_barrier();
@@ -1919,6 +2065,7 @@ void launch_lists(const Plan &P, int blocks, hipStream_t s)
 #define HCA_LISTS_D(DD)                                                                        \
     case DD:                                                                                   \
         hipLaunchKernelGGL(k_group_box<DD>, dim3(blocks), dim3(kBlock), 0, s, P);             \
+        if (P.pstart) hipLaunchKernelGGL(k_prefix_ranges, dim3(1024), dim3(kBlock), 0, s, P); \
         hipLaunchKernelGGL(k_nbr_lists<DD>, dim3(blocks), dim3(kBlock), 0, s, P);             \
         break;
         HCA_LISTS_D(1) HCA_LISTS_D(2) HCA_LISTS_D(3) HCA_LISTS_D(4)

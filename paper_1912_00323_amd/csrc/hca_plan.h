@@ -169,6 +169,12 @@ struct Plan {
     uint32_t rep_only;          // merge on representatives alone (approximate)
     uint32_t nbr_cap;
     uint32_t list_w;            // offsets per axis walked by the list build: 2R + 1
+    // group mode: the groups sharing a prefix of the first d/2 axes (the key
+    // above bit pshift) are consecutive; pstart / pend give the range of
+    // each prefix (valid when group_key[pstart[p]] >> pshift == p), or null
+    uint32_t pshift;
+    uint32_t *pstart;           // [2^pbits]
+    uint32_t *pend;             // [2^pbits]
     uint32_t *nbr_count;        // [n] forward entries
     uint32_t *nbr_start;        // [n]
     uint32_t *nbr;              // [nbr_cap] forward entries in per-wave slabs

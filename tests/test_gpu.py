@@ -164,6 +164,28 @@ def test_eps_past_int32(ctx):
     assert (got == 0).all()
 
 
+@pytest.mark.parametrize("prefix", ["0", "1"])
+def test_group_prefix_ranges(ctx, prefix, monkeypatch):
+    """Group-mode lists built by scanning the groups of each first-half
+    prefix, or by looking every offset up: the same labels, also when the
+    data varies along one half of the axes only (long prefix ranges fall back
+    to lookups) or along the other."""
+    monkeypatch.setenv("HCA_SEARCH", "group")
+    monkeypatch.setenv("HCA_PREFIX", prefix)
+    for d in (4, 6, 8):
+        rng = np.random.default_rng(120 + d)
+        pts = quantise(make_blobs(rng, 8000, d, 6, 0.03, 0.1), 12)
+        flat_first = pts.copy()
+        flat_first[:, : d // 2] = 7                     # one prefix: every range is the whole set
+        flat_second = pts.copy()
+        flat_second[:, d // 2:] = 7
+        for name, p in (("blobs", pts), ("first half constant", flat_first), ("second half constant", flat_second)):
+            for f, mp in ((0.07, 5), (0.1, 1)):
+                print(f"[case] prefix={prefix} d={d} {name} eps={f} minPts={mp}", flush=True)
+                want = oracle.dbscan(p, f * 2 ** 12, mp)
+                assert np.array_equal(gpu_labels(ctx, p, f * 2 ** 12, mp), want), (prefix, d, name, f, mp)
+
+
 def test_mixed_family(ctx):
     for seed in range(6):
         d = (2, 3, 4)[seed % 3]
