@@ -409,6 +409,18 @@ void plan_sizes(Plan &P, uint32_t gbits, bool count_work, bool want_stats, Sizes
     P.nbr_cap = P.list_w ? (uint32_t)list_cap : 0;
 }
 
+// Neighbour lists from prefix ranges: the groups sharing the group-key
+// prefix of the first d/2 axes are consecutive, so the lists can scan them
+// (when that prefix takes at most 24 bits; HCA_PREFIX=0 turns it off).
+void plan_prefix(Plan &P, uint32_t gbits, Sizes *Z)
+{
+    Z->pbits = 0;
+    if (!P.nbr_cap || P.d < 2 || P.hd || !env_prefix()) return;
+    P.pshift = P.goff[P.d / 2 - 1];
+    const uint32_t pbits = gbits - P.pshift;
+    if (pbits <= 24) Z->pbits = std::max<uint32_t>(1, pbits);
+}
+
 // The device workspace of one launch sequence (the first bytes hold the
 // bounding-box partials).
 void carve_ws(Carver &cv, Plan &P, SortBuffers &B, const Sizes &Z, uint32_t **zero_begin, size_t *zero_bytes)
@@ -921,14 +933,7 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
     P.list_w = P.m == 1 ? cube_list_width(d, G.radius, n_off) : 0;
     Sizes Z;
     plan_sizes(P, gbits, stats != nullptr && ctx->prof != -1, stats != nullptr, &Z);
-    // group-mode lists: ranges of groups per prefix of the first d/2 axes,
-    // when that prefix takes at most 22 bits (HCA_PREFIX=0 turns it off)
-    if (P.m > 1 && P.nbr_cap && d >= 2 && env_prefix()) {
-        const int da = d / 2;
-        P.pshift = P.goff[da - 1];
-        const uint32_t pbits = gbits - P.pshift;
-        if (pbits <= 22) Z.pbits = std::max<uint32_t>(1, pbits);
-    }
+    plan_prefix(P, gbits, &Z);
     P.pts = points;
     P.labels = labels;
     P.core_out = core_out;
@@ -1192,6 +1197,7 @@ hca_status run_sets(hca_ctx *ctx, const BatchSet *sets, int32_t nseg)
         for (int32_t v : g.radius) rmax = std::max(rmax, v);
         P.list_w = cube_list_width(d, rmax, P.n_off);
         plan_sizes(P, P.key_bits, false, false, &g.Z);
+        plan_prefix(P, P.key_bits, &g.Z);
         ws_need = std::max(ws_need, ws_bytes(P, g.Z));
         // origins into the device table (stream-ordered before the launches)
         std::memcpy(hb + g.h_seg, g.par.data(), ns * sizeof(SegParam));

@@ -452,24 +452,25 @@ __device__ __forceinline__ void list_append(const Plan &P, uint32_t G, const QBo
     if (fits) at += k;
 }
 
-// Group mode with prefix ranges: for every first-half offset that can hold a
-// point within eps and points forwards (or is zero), the groups of its
-// prefix are scanned instead of looking up each second-half offset; a group
-// is kept when its point box comes within eps (which also bounds its
-// second-half offsets to one step) and, for a zero first half, when its
-// second half points forwards.  Returns false, with nothing written, when a
-// range is longer than kPrefixScanMax (then the offsets are looked up).
-constexpr uint32_t kPrefixScanMax = 128;
+// With prefix ranges: for every first-half offset that can hold a point
+// within eps and points forwards (or is zero), the groups of its prefix are
+// scanned instead of looking up each second-half offset; a group is kept
+// when its point box comes within eps (which also bounds each of its
+// second-half offsets to R) and, for a zero first half, when its second half
+// points forwards.  Returns false, with nothing written, when a range is
+// longer than twice the second-half offsets, at least 64 (then the offsets
+// are looked up).
 
 template <int D>
 __device__ __forceinline__ bool list_by_prefix(const Plan &P, uint32_t g, uint64_t gkey, const QBox<D> &qb,
                                                const Geo<D> &geo, uint32_t ng, int NA, uint32_t *s_pre,
                                                uint32_t *s_rs, int8_t *s_ga, uint32_t &at, uint32_t end,
-                                               uint32_t &overflow)
+                                               uint32_t &overflow, int NB)
 {
     constexpr int DA = D / 2;
     const uint32_t l = lane_id();
     const uint64_t gpre = gkey >> P.pshift;
+    const uint32_t scan_max = max(64u, 2u * (uint32_t)NB);
     uint32_t tot = 0;
     bool big = false;
     for (int i0 = 0; i0 < NA; i0 += kWave) {
@@ -487,7 +488,7 @@ __device__ __forceinline__ bool list_by_prefix(const Plan &P, uint32_t g, uint64
                 }
             }
         }
-        big |= size > kPrefixScanMax;
+        big |= size > scan_max;
         const uint32_t inc = wave_inclusive_scan(size);
         __builtin_amdgcn_wave_barrier();
         if (i < NA) {
@@ -572,7 +573,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr_lists(Plan P)
         const QBox<D> qb = load_gbox<D>(P, g);
         if constexpr (DA >= 1) {
             if (P.pstart && list_by_prefix<D>(P, g, gkey, qb, geo, ng, NA, s_pre[w], s_rs[w], s_ga[w], at, end,
-                                              overflow))
+                                              overflow, NB))
                 continue;
         }
         // both halves' gap sums, sorted ascending, with their signs

@@ -184,6 +184,15 @@ def test_group_prefix_ranges(ctx, prefix, monkeypatch):
                 print(f"[case] prefix={prefix} d={d} {name} eps={f} minPts={mp}", flush=True)
                 want = oracle.dbscan(p, f * 2 ** 12, mp)
                 assert np.array_equal(gpu_labels(ctx, p, f * 2 ** 12, mp), want), (prefix, d, name, f, mp)
+    # cubes as search groups with lists over offsets -R..R (3-D and 4-D)
+    monkeypatch.delenv("HCA_SEARCH")
+    for d in (3, 4):
+        rng = np.random.default_rng(130 + d)
+        pts = quantise(make_blobs(rng, 20000, d, 8, 0.02, 0.1), 12)
+        for f, mp in ((0.012, 4), (0.02, 9)):
+            print(f"[case] prefix={prefix} cubes d={d} eps={f} minPts={mp}", flush=True)
+            want = oracle.dbscan(pts, f * 2 ** 12, mp)
+            assert np.array_equal(gpu_labels(ctx, pts, f * 2 ** 12, mp), want), (prefix, "cubes", d, f, mp)
 
 
 def test_mixed_family(ctx):
