@@ -145,6 +145,31 @@ __device__ __forceinline__ uint32_t slot_group(const Plan &P, uint32_t g, uint64
     return *nk == ~0ull ? kNone : group_lookup(P, *nk);
 }
 
+// Can group G (its stored point box, kept whenever lists are built) hold a
+// point within eps of the query box q?  32-bit when the host has shown that
+// every tested pair's squared distance fits.
+template <int D>
+__device__ __forceinline__ bool gbox_within(const Plan &P, uint32_t G, const QBox<D> &q, int64_t eps2)
+{
+    const int32_t *b = P.gbox + (uint64_t)G * 2 * D;
+    if (P.wide) {
+        int64_t acc = 0;
+#pragma unroll
+        for (int e = 0; e < D; e++) {
+            const int64_t gap = max((int64_t)b[e] - q.hi[e], (int64_t)q.lo[e] - b[D + e]);
+            acc += gap > 0 ? gap * gap : 0;
+        }
+        return acc <= eps2;
+    }
+    int32_t acc = 0;
+#pragma unroll
+    for (int e = 0; e < D; e++) {
+        const int32_t gap = max(max(b[e] - q.hi[e], q.lo[e] - b[D + e]), 0);
+        acc += __mul24(gap, gap);
+    }
+    return acc <= (int32_t)min(eps2, (int64_t)INT32_MAX);
+}
+
 // ---------------------------------------------------------------------------
 // Candidate lists: the points of the neighbour groups in slots
 // [first, first + 64), laid out one after the other.  Lane l resolves slot
@@ -167,9 +192,8 @@ __device__ __forceinline__ uint32_t load_neighbours(const Plan &P, uint32_t g, u
     if (j < src.slots) {
         uint32_t G = kNone;
         if (src.lists) {
-            uint64_t nk;
-            G = slot_group<D>(P, g, gkey, src, j, &nk);
-            if (!group_box_within<D>(P, nk, q, geo)) G = kNone;
+            G = j == 0 ? g : list_slot(P, src, j);
+            if (!gbox_within<D>(P, G, q, geo.eps2)) G = kNone;
         } else {
             const uint64_t nk = group_neighbour<D>(P, gkey, P.off + (uint64_t)j * D);
             if (nk != ~0ull && group_box_within<D>(P, nk, q, geo)) G = group_lookup(P, nk);

@@ -67,11 +67,11 @@ struct Counters {
     // kWorkRegions lines of eight 64-bit words; counted only on request
     unsigned long long tests[4][kWorkRegions * 8];
     // work queues of the dynamically balanced kernels: [kernel][64 queues]
-    uint32_t dyn[6][kWorkRegions * kCounterStride];
+    uint32_t dyn[5][kWorkRegions * kCounterStride];
 };
 
 enum { kTestsCore = 0, kTestsMerge = 1, kTestsBorder = 2, kTestsIntra = 3 };
-enum { kDynLists = 0, kDynCore = 1, kDynBorder = 2, kDynMerge = 3, kDynCoreRest = 4, kDynMergeRest = 5 };
+enum { kDynLists = 0, kDynCore = 1, kDynBorder = 2, kDynMerge = 3, kDynCoreRest = 4 };
 
 // One data set of a batch: its exact eps^2, minPts, cube side and origin,
 // where its rows sit, and (filled on the device) the clusters of the data
