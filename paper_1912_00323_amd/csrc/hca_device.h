@@ -465,6 +465,9 @@ constexpr int kPch = 8;           // points of the own group handled per sweep
 
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ int32_t uniform_i(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+// Lane `src` of v, wave-uniform (src must be the same in every lane): one
+// readlane into a scalar register, so loops bounded by it stay scalar.
+__device__ __forceinline__ uint32_t lane_value(uint32_t v, uint32_t src) { return __builtin_amdgcn_readlane(v, src); }
 
 // Sort the n <= 128 gap sums of one half ascending (ties by index) into
 // s_sum / s_idx: a bitonic network over the next power of two of n, two

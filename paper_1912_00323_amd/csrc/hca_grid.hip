@@ -208,7 +208,7 @@ __device__ __forceinline__ uint32_t load_neighbours(const Plan &P, uint32_t g, u
     s_beg[l] = a;
     s_pre[l] = inc - size;
     __builtin_amdgcn_wave_barrier();
-    return __shfl(inc, kWave - 1);
+    return lane_value(inc, kWave - 1);
 }
 
 
@@ -520,7 +520,7 @@ __device__ __forceinline__ bool list_by_prefix(const Plan &P, uint32_t g, uint64
             s_rs[i] = rs;
             s_ga[i] = sg;
         }
-        tot += __shfl(inc, kWave - 1);
+        tot += lane_value(inc, kWave - 1);
     }
     if (__ballot(big)) return false;
     if (l == 0) s_pre[NA] = tot;
@@ -628,7 +628,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr_lists(Plan P)
             }
             const uint32_t inc = wave_inclusive_scan(c);
             if (i < NA) s_pre[w][i] = tot + inc - c;
-            tot += __shfl(inc, kWave - 1);
+            tot += lane_value(inc, kWave - 1);
         }
         if (l == 0) s_pre[w][NA] = tot;
         // key offsets of both halves in sorted order
@@ -758,6 +758,16 @@ __global__ __launch_bounds__(kBlock) void k_nbr_back(Plan P)
     }
 }
 
+// Sorted position of candidate c of a batch laid out by load_neighbours (0,
+// a valid row, past the batch's end).
+__device__ __forceinline__ uint32_t candidate_pos(uint32_t c, uint32_t total, const uint32_t *s_beg,
+                                                  const uint32_t *s_pre)
+{
+    if (c >= total) return 0;
+    const uint32_t ln = candidate_lane(c, s_pre);
+    return s_beg[ln] + (c - s_pre[ln]);
+}
+
 // Neighbour counts of the chunk points not yet flagged in `done`, over group
 // g and its neighbour groups, until each reaches minPts (then its bit is
 // set).  Returns the updated mask.  With P.rec and a chunk position pc
@@ -777,20 +787,23 @@ __device__ __forceinline__ uint32_t count_walk(const Plan &P, uint32_t g, uint64
     const NbrSrc src = nbr_source(P, g);
     for (uint32_t oc = 0; oc < src.slots && done != all; oc += kWave) {
         const uint32_t total = load_neighbours<D>(P, g, gkey, src, oc, 0, false, qb, s_beg, s_pre, geo);
+        // candidate ci + l of the batch; the next batch's point is loaded
+        // before this one is tested, so its latency overlaps the tests
+        uint32_t nxt = candidate_pos(l, total, s_beg, s_pre);
+        Pt<D> qn = load_pt<D>(P.spts, nxt);
         for (uint32_t ci = 0; ci < total && done != all; ci += kWave) {
-            const uint32_t c = ci + l;
-            const bool ok = c < total;
-            uint32_t pos = 0;
-            if (ok) {
-                const uint32_t ln = candidate_lane(c, s_pre);
-                pos = s_beg[ln] + (c - s_pre[ln]);
+            const bool ok = ci + l < total;
+            const uint32_t pos = nxt;
+            const Pt<D> q = qn;
+            if (ci + kWave < total) {
+                nxt = candidate_pos(ci + kWave + l, total, s_beg, s_pre);
+                qn = load_pt<D>(P.spts, nxt);
             }
-            const Pt<D> q = load_pt<D>(P.spts, pos);
 #pragma unroll
             for (int k = 0; k < kPch; k++) {
                 if (done & (1u << k)) continue;
                 lt += ok;
-                const bool hit = ok && within<D, WIDE>(pp[k], q, geo.eps2);
+                const bool hit = within<D, WIDE>(pp[k], q, geo.eps2) & ok;
                 const uint64_t hm = __ballot(hit);
                 if (record && hm && cnt[k] < (uint32_t)kRec) {
                     const uint32_t r = cnt[k] + __popcll(hm & __lanemask_lt());
@@ -938,7 +951,7 @@ __global__ __launch_bounds__(kBlock) void k_core_chunks(Plan P)
             load_chunk<D>(P, pc, np, pp);
             uint32_t left = ~done & all;
             while (left) {
-                const uint32_t g = __shfl(grp, __ffs(left) - 1);
+                const uint32_t g = lane_value(grp, __ffs(left) - 1);
                 const uint32_t run = (uint32_t)__ballot(grp == g) & left;
                 left &= ~run;
                 const uint32_t got = count_walk<D, WIDE>(P, g, P.group_key[g], pp, ~run & all, cnt, s_beg[w],
@@ -1192,7 +1205,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_exact(Plan P)
     const uint32_t inc = wave_inclusive_scan(cnt);
     s_pre[w][l] = inc - cnt;
     __builtin_amdgcn_wave_barrier();
-    const uint32_t items = __shfl(inc, kWave - 1);
+    const uint32_t items = lane_value(inc, kWave - 1);
     uint32_t lt = 0;
     const WaveRange hca_wr_ = wave_range();
     HCA_FOR_UNITS(it, items) {
@@ -1593,7 +1606,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_inter(Plan P)
             // pair of unified groups (its search ends at the first hit)
             const uint32_t want = GB == kNone ? 0u : both ? 1u : tiles;
             const uint32_t inc = wave_inclusive_scan(want);
-            const uint32_t total = __shfl(inc, kWave - 1);
+            const uint32_t total = lane_value(inc, kWave - 1);
             if (!total) continue;
             uint32_t base = 0;
             if (l == 0) base = atomicAdd(P.ctr->work_count + region * kCounterStride, total);
@@ -1644,7 +1657,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_pairs(Plan P)
     const uint32_t inc = wave_inclusive_scan(cnt);
     s_pre[w][l] = inc - cnt;
     __builtin_amdgcn_wave_barrier();
-    const uint32_t items = __shfl(inc, kWave - 1);
+    const uint32_t items = lane_value(inc, kWave - 1);
     uint32_t lt = 0;
     const WaveRange hca_wr_ = wave_range();
     HCA_FOR_UNITS(it, items) {
@@ -1828,7 +1841,7 @@ __global__ __launch_bounds__(kBlock) void k_border_walk_list(Plan P)
         for (int k = 0; k < kPch; k++) { bd[k] = INT64_MAX; bi[k] = kNone; bp[k] = kNone; }
         uint32_t left = todo;
         while (left) {
-            const uint32_t g = __shfl(grp, __ffs(left) - 1);
+            const uint32_t g = lane_value(grp, __ffs(left) - 1);
             const uint32_t run = (uint32_t)__ballot(grp == g) & left;
             left &= ~run;
             const uint64_t gkey = P.group_key[g];
@@ -1914,7 +1927,7 @@ __global__ __launch_bounds__(kBlock) void k_border_chunks(Plan P)
         for (int k = 0; k < kPch; k++) { bd[k] = INT64_MAX; bi[k] = kNone; bp[k] = kNone; }
         uint32_t left = todo;
         while (left) {
-            const uint32_t g = __shfl(grp, __ffs(left) - 1);
+            const uint32_t g = lane_value(grp, __ffs(left) - 1);
             const uint32_t run = (uint32_t)__ballot(grp == g) & left;
             left &= ~run;
             border_walk<D, WIDE>(P, g, P.group_key[g], pp, run, bd, bi, bp, s_beg[w], s_pre[w], lt, geo);

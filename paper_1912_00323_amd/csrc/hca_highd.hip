@@ -204,7 +204,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_lists(Plan P)
             }
             const uint32_t inc = wave_inclusive_scan(c);
             if (i < NA) s_pre[w][i] = tot + inc - c;
-            tot += __shfl(inc, kWave - 1);
+            tot += lane_value(inc, kWave - 1);
         }
         if (l == 0) s_pre[w][NA] = tot;
         for (int i = l; i < NA; i += kWave) s_ka[w][i] = hd_half_key_delta<0, DA>(P, s_ia[w][i]);
@@ -380,7 +380,7 @@ __device__ __forceinline__ uint32_t hd_load_neighbours(const Plan &P, uint32_t g
     s_beg[l] = a;
     s_pre[l] = inc - size;
     __builtin_amdgcn_wave_barrier();
-    return __shfl(inc, kWave - 1);
+    return lane_value(inc, kWave - 1);
 }
 
 // Squared distances from the candidate row at sorted position pos to the 8
@@ -571,7 +571,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_core(Plan P)
             hd_stage(P, pc, np, s_own[w]);
             uint32_t left = ~done & all;
             while (left) {
-                const uint32_t g = __shfl(grp, __ffs(left) - 1);
+                const uint32_t g = lane_value(grp, __ffs(left) - 1);
                 const uint32_t run = (uint32_t)__ballot(grp == g) & left;
                 left &= ~run;
                 bool cut;
@@ -633,7 +633,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_core_rest(Plan P)
         for (int k = 0; k < kPch; k++) cnt[k] = 0;
         uint32_t left = (uint32_t)__ballot(in) & all;
         while (left) {
-            const uint32_t g = __shfl(grp, __ffs(left) - 1);
+            const uint32_t g = lane_value(grp, __ffs(left) - 1);
             const uint32_t run = (uint32_t)__ballot(grp == g) & left;
             left &= ~run;
             bool cut;
@@ -745,11 +745,11 @@ __global__ __launch_bounds__(kBlock) void k_hd_merge(Plan P)
         const uint32_t grp = core ? P.group_of[cell] : kNone;
         uint32_t ck[kPch];
 #pragma unroll
-        for (int k = 0; k < kPch; k++) ck[k] = uniform(__shfl(cell, k));
+        for (int k = 0; k < kPch; k++) ck[k] = lane_value(cell, k);
         hd_stage(P, pc, np, s_own[w]);
         uint32_t left = live;
         while (left) {
-            const uint32_t g = __shfl(grp, __ffs(left) - 1);
+            const uint32_t g = lane_value(grp, __ffs(left) - 1);
             const uint32_t run = (uint32_t)__ballot(grp == g) & left;
             left &= ~run;
             hd_link_walk<WIDE>(P, g, s_own[w], run, ck, s_qb[w], s_beg[w], s_pre[w], lt);
@@ -902,7 +902,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_border(Plan P)
         for (int k = 0; k < kPch; k++) { bd[k] = INT64_MAX; bi[k] = kNone; bp[k] = kNone; }
         uint32_t left = todo;
         while (left) {
-            const uint32_t g = __shfl(grp, __ffs(left) - 1);
+            const uint32_t g = lane_value(grp, __ffs(left) - 1);
             const uint32_t run = (uint32_t)__ballot(grp == g) & left;
             left &= ~run;
             hd_border_walk<WIDE>(P, g, s_own[w], run, bd, bi, bp, s_qb[w], s_beg[w], s_pre[w], lt);
