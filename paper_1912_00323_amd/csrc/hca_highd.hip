@@ -760,17 +760,49 @@ __global__ __launch_bounds__(kBlock) void k_hd_merge(Plan P)
 
 // The pairs recorded by core marking (more than 8 axes, or search groups of
 // more than one cube): each core point joins its cube with those of its
-// recorded core neighbours (all within eps), no test needed.
+// recorded core neighbours (all within eps), no test needed.  The records,
+// then the flags and cubes of all of them, are loaded before the first
+// union, so their latencies overlap; the point's own root is carried from
+// one union to the next.
 __global__ __launch_bounds__(kBlock) void k_link_recorded(Plan P)
 {
     for (uint32_t q = blockIdx.x * kBlock + threadIdx.x; q < P.n; q += gridDim.x * kBlock) {
         if (!P.core[q]) continue;
         const uint32_t c = P.cell_of[q], nr = min((uint32_t)P.nrec[q], (uint32_t)kRec);
-        for (uint32_t r = 0; r < nr; r++) {
-            const uint32_t q2 = P.rec[(uint64_t)q * kRec + r];
-            if (!P.core[q2]) continue;
-            const uint32_t c2 = P.cell_of[q2];
-            if (c2 != c) uf_union(P.parent, c, c2);
+        if (!nr) continue;
+        uint32_t q2[kRec];
+        const uint4 *rp = reinterpret_cast<const uint4 *>(P.rec + (uint64_t)q * kRec);
+#pragma unroll
+        for (int i = 0; i < kRec / 4; i++) {
+            const uint4 v = rp[i];
+            q2[4 * i] = v.x;
+            q2[4 * i + 1] = v.y;
+            q2[4 * i + 2] = v.z;
+            q2[4 * i + 3] = v.w;
+        }
+        // cube of each recorded core neighbour (kNone: not core, or past nr,
+        // where the record holds no position)
+        uint32_t c2[kRec];
+#pragma unroll
+        for (int r = 0; r < kRec; r++) {
+            c2[r] = kNone;
+            if ((uint32_t)r < nr) {
+                const bool cp = P.core[q2[r]];
+                const uint32_t cc = P.cell_of[q2[r]];
+                c2[r] = cp ? cc : kNone;
+            }
+        }
+        uint32_t rc = kNone;
+#pragma unroll
+        for (int r = 0; r < kRec; r++) {
+            if (c2[r] == kNone || c2[r] == c) continue;
+            if (rc == kNone) rc = uf_find(P.parent, c);
+            // rc was c's root when found and stays an ancestor of c, so a
+            // neighbour under rc is already in c's cluster
+            const uint32_t r2 = uf_find(P.parent, c2[r]);
+            if (r2 == rc) continue;
+            uf_union(P.parent, rc, r2);
+            rc = uf_find(P.parent, rc);
         }
     }
 }
