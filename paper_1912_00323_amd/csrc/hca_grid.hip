@@ -921,9 +921,10 @@ __global__ __launch_bounds__(kBlock) void k_core(Plan P)
 // thousands of points of a dense group are spread over many waves.  A chunk
 // may straddle groups; its points are walked group by group.  The per-cube
 // tallies (core points, smallest core input index) are accumulated with one
-// atomic per cube run of the chunk.
+// atomic per cube run of the chunk.  Held to 80 registers (six waves per
+// SIMD): the walks wait on memory, and more waves hide more of it.
 template <int D, bool WIDE>
-__global__ __launch_bounds__(kBlock) void k_core_chunks(Plan P)
+__global__ __launch_bounds__(kBlock, 6) void k_core_chunks(Plan P)
 {
     __shared__ uint32_t s_beg[kWavesPerBlock][kWave], s_pre[kWavesPerBlock][kWave];
     const uint32_t w = wave_in_block(), l = lane_id();

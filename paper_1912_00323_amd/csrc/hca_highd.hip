@@ -383,16 +383,25 @@ __device__ __forceinline__ uint32_t hd_load_neighbours(const Plan &P, uint32_t g
     return lane_value(inc, kWave - 1);
 }
 
+// Row forms, fixed per call by the host, one kernel instance each: 32-bit
+// sums of int32 rows, 64-bit sums, or packed int16 rows.
+constexpr int kRowNarrow = 0, kRowWide = 1, kRowPacked = 2;
+
+__host__ __device__ inline int row_form(const Plan &P)
+{
+    return P.wide ? kRowWide : P.spts16 ? kRowPacked : kRowNarrow;
+}
+
 // Squared distances from the candidate row at sorted position pos to the 8
 // staged points (exact: 64-bit, or 32-bit when the host has shown that every
 // tested pair's sum fits).  The 32-bit form loads the whole row before any
 // arithmetic; the 64-bit form, short of registers, goes 16 bytes at a time.
-template <bool WIDE>
+template <int ROW>
 __device__ __forceinline__ void hd_dist(const Plan &P, const int32_t (*own)[kOwnStride], uint32_t pos, int64_t *dd)
 {
     const int4 *row = reinterpret_cast<const int4 *>(P.spts + (uint64_t)pos * P.sd);
     const uint32_t n4 = P.sd >> 2;
-    if constexpr (WIDE) {
+    if constexpr (ROW == kRowWide) {
         int64_t acc[kPch];
 #pragma unroll
         for (int k = 0; k < kPch; k++) acc[k] = 0;
@@ -408,7 +417,7 @@ __device__ __forceinline__ void hd_dist(const Plan &P, const int32_t (*own)[kOwn
         }
 #pragma unroll
         for (int k = 0; k < kPch; k++) dd[k] = acc[k];
-    } else if (P.spts16) {
+    } else if constexpr (ROW == kRowPacked) {
         // packed int16 coordinates: two axes per subtract and dot step
         const uint4 *prow = reinterpret_cast<const uint4 *>(P.spts16 + (uint64_t)pos * (P.sd >> 1));
         const uint32_t n8 = P.sd >> 3;
@@ -477,7 +486,7 @@ __device__ __forceinline__ uint32_t hd_candidate(uint32_t c, const uint32_t *s_b
 // points left undecided.
 // The first kRec neighbours found of staged point k (sorted position
 // qpos[k]) are recorded for merging.
-template <bool WIDE>
+template <int ROW>
 __device__ __forceinline__ uint32_t hd_count_walk(const Plan &P, uint32_t g, const int32_t (*own)[kOwnStride],
                                                   const uint32_t *qpos, uint32_t done, uint32_t *cnt, int32_t *qb,
                                                   uint32_t *s_beg, uint32_t *s_pre, uint32_t &lt, uint32_t budget,
@@ -494,7 +503,7 @@ __device__ __forceinline__ uint32_t hd_count_walk(const Plan &P, uint32_t g, con
             const bool ok = c < total;
             const uint32_t pos = ok ? hd_candidate(c, s_beg, s_pre) : 0u;
             int64_t dd[kPch];
-            hd_dist<WIDE>(P, own, pos, dd);
+            hd_dist<ROW>(P, own, pos, dd);
 #pragma unroll
             for (int k = 0; k < kPch; k++) {
                 if (done & (1u << k)) continue;
@@ -541,8 +550,9 @@ __device__ __forceinline__ void hd_tally(const Plan &P, bool in, uint32_t cell, 
 // First pass: chunks of 8 consecutive sorted points, each point looking at
 // up to kHdCoreBudget candidates; points still undecided are appended to
 // the list of the second pass.
-template <bool WIDE>
-__global__ __launch_bounds__(kBlock) void k_hd_core(Plan P)
+// The packed form is held to 128 registers (four waves per SIMD).
+template <int ROW>
+__global__ __launch_bounds__(kBlock, ROW == kRowPacked ? 4 : 1) void k_hd_core(Plan P)
 {
     __shared__ __align__(16) int32_t s_own[kWavesPerBlock][kPch][kOwnStride];
     __shared__ int32_t s_qb[kWavesPerBlock][2 * kMaxDimHigh];
@@ -575,7 +585,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_core(Plan P)
                 const uint32_t run = (uint32_t)__ballot(grp == g) & left;
                 left &= ~run;
                 bool cut;
-                const uint32_t got = hd_count_walk<WIDE>(P, g, s_own[w], qpos, ~run & all, cnt, s_qb[w], s_beg[w],
+                const uint32_t got = hd_count_walk<ROW>(P, g, s_own[w], qpos, ~run & all, cnt, s_qb[w], s_beg[w],
                                                          s_pre[w], lt, kHdCoreBudget, &cut);
                 done |= got & run;
                 if (cut) undec |= run & ~got;
@@ -604,8 +614,8 @@ __global__ __launch_bounds__(kBlock) void k_hd_core(Plan P)
 }
 
 // Second pass: chunks of 8 points of the list, walked to the end.
-template <bool WIDE>
-__global__ __launch_bounds__(kBlock) void k_hd_core_rest(Plan P)
+template <int ROW>
+__global__ __launch_bounds__(kBlock, ROW == kRowPacked ? 4 : 1) void k_hd_core_rest(Plan P)
 {
     __shared__ __align__(16) int32_t s_own[kWavesPerBlock][kPch][kOwnStride];
     __shared__ int32_t s_qb[kWavesPerBlock][2 * kMaxDimHigh];
@@ -637,7 +647,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_core_rest(Plan P)
             const uint32_t run = (uint32_t)__ballot(grp == g) & left;
             left &= ~run;
             bool cut;
-            (void)hd_count_walk<WIDE>(P, g, s_own[w], pos, ~run & all, cnt, s_qb[w], s_beg[w], s_pre[w], lt, ~0u,
+            (void)hd_count_walk<ROW>(P, g, s_own[w], pos, ~run & all, cnt, s_qb[w], s_beg[w], s_pre[w], lt, ~0u,
                                       &cut);
         }
         uint32_t mine = 0;
@@ -669,7 +679,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_gcore(Plan P)
 // smaller one; roots are cached and a batch of candidates is skipped when no
 // pair in it could join two different sets.
 // ---------------------------------------------------------------------------
-template <bool WIDE>
+template <int ROW>
 __device__ __forceinline__ void hd_link_walk(const Plan &P, uint32_t g, const int32_t (*own)[kOwnStride],
                                              uint32_t run, const uint32_t *ck, int32_t *qb, uint32_t *s_beg,
                                              uint32_t *s_pre, uint32_t &lt)
@@ -705,7 +715,7 @@ __device__ __forceinline__ void hd_link_walk(const Plan &P, uint32_t g, const in
                 if (run & (1u << k)) any |= ok && cq > ck[k] && rq != rk[k];
             if (!__ballot(any)) continue;
             int64_t dd[kPch];
-            hd_dist<WIDE>(P, own, pos, dd);
+            hd_dist<ROW>(P, own, pos, dd);
 #pragma unroll
             for (int k = 0; k < kPch; k++) {
                 if (!(run & (1u << k))) continue;
@@ -726,7 +736,7 @@ __device__ __forceinline__ void hd_link_walk(const Plan &P, uint32_t g, const in
 // After the recorded pairs are joined: the whole walk, where a group whose
 // core cubes all share the walking points' root is skipped without looking
 // at its points.
-template <bool WIDE>
+template <int ROW>
 __global__ __launch_bounds__(kBlock) void k_hd_merge(Plan P)
 {
     __shared__ __align__(16) int32_t s_own[kWavesPerBlock][kPch][kOwnStride];
@@ -752,7 +762,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_merge(Plan P)
             const uint32_t g = lane_value(grp, __ffs(left) - 1);
             const uint32_t run = (uint32_t)__ballot(grp == g) & left;
             left &= ~run;
-            hd_link_walk<WIDE>(P, g, s_own[w], run, ck, s_qb[w], s_beg[w], s_pre[w], lt);
+            hd_link_walk<ROW>(P, g, s_own[w], run, ck, s_qb[w], s_beg[w], s_pre[w], lt);
         }
     }
     flush_tests(P, kTestsMerge, lt);
@@ -833,7 +843,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_unify(Plan P)
 // Border points: each non-core point of a chunk takes the root of its nearest
 // core point within eps (ties to the smaller input index); none -> noise.
 // ---------------------------------------------------------------------------
-template <bool WIDE>
+template <int ROW>
 __device__ __forceinline__ void hd_border_walk(const Plan &P, uint32_t g, const int32_t (*own)[kOwnStride],
                                                uint32_t todo, int64_t *bd, uint32_t *bi, uint32_t *bp, int32_t *qb,
                                                uint32_t *s_beg, uint32_t *s_pre, uint32_t &lt)
@@ -851,7 +861,7 @@ __device__ __forceinline__ void hd_border_walk(const Plan &P, uint32_t g, const 
             ok = ok && P.core[pos];
             if (!__ballot(ok)) continue;
             int64_t dd[kPch];
-            hd_dist<WIDE>(P, own, pos, dd);
+            hd_dist<ROW>(P, own, pos, dd);
             bool near = false;
 #pragma unroll
             for (int k = 0; k < kPch; k++) {
@@ -902,7 +912,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_border_rec(Plan P)
 // Chunks of 8 non-core points of the list.  Each takes the root of its
 // nearest core point within eps (ties to the smaller input index) and offers
 // its input index to that cluster's smallest member; none -> noise.
-template <bool WIDE>
+template <int ROW>
 __global__ __launch_bounds__(kBlock) void k_hd_border(Plan P)
 {
     __shared__ __align__(16) int32_t s_own[kWavesPerBlock][kPch][kOwnStride];
@@ -937,7 +947,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_border(Plan P)
             const uint32_t g = lane_value(grp, __ffs(left) - 1);
             const uint32_t run = (uint32_t)__ballot(grp == g) & left;
             left &= ~run;
-            hd_border_walk<WIDE>(P, g, s_own[w], run, bd, bi, bp, s_qb[w], s_beg[w], s_pre[w], lt);
+            hd_border_walk<ROW>(P, g, s_own[w], run, bd, bi, bp, s_qb[w], s_beg[w], s_pre[w], lt);
         }
 #pragma unroll
         for (int k = 0; k < kPch; k++) {
@@ -990,12 +1000,18 @@ void launch_hd_lists(const Plan &P, int blocks, hipStream_t s)
 
 void launch_hd_core(const Plan &P, int blocks, hipStream_t s)
 {
-    if (P.wide) {
-        hipLaunchKernelGGL(k_hd_core<true>, dim3(blocks), dim3(kBlock), 0, s, P);
-        hipLaunchKernelGGL(k_hd_core_rest<true>, dim3(blocks), dim3(kBlock), 0, s, P);
-    } else {
-        hipLaunchKernelGGL(k_hd_core<false>, dim3(blocks), dim3(kBlock), 0, s, P);
-        hipLaunchKernelGGL(k_hd_core_rest<false>, dim3(blocks), dim3(kBlock), 0, s, P);
+    switch (row_form(P)) {
+    case kRowWide:
+        hipLaunchKernelGGL(k_hd_core<kRowWide>, dim3(blocks), dim3(kBlock), 0, s, P);
+        hipLaunchKernelGGL(k_hd_core_rest<kRowWide>, dim3(blocks), dim3(kBlock), 0, s, P);
+        break;
+    case kRowPacked:
+        hipLaunchKernelGGL(k_hd_core<kRowPacked>, dim3(blocks), dim3(kBlock), 0, s, P);
+        hipLaunchKernelGGL(k_hd_core_rest<kRowPacked>, dim3(blocks), dim3(kBlock), 0, s, P);
+        break;
+    default:
+        hipLaunchKernelGGL(k_hd_core<kRowNarrow>, dim3(blocks), dim3(kBlock), 0, s, P);
+        hipLaunchKernelGGL(k_hd_core_rest<kRowNarrow>, dim3(blocks), dim3(kBlock), 0, s, P);
     }
     const int cb = (int)std::min<uint64_t>((P.n + kBlock - 1) / kBlock, 1024);
     hipLaunchKernelGGL(k_hd_gcore, dim3(cb), dim3(kBlock), 0, s, P);
@@ -1005,8 +1021,11 @@ void launch_hd_merge(const Plan &P, int blocks, hipStream_t s)
 {
     launch_link_recorded(P, s);
     hipLaunchKernelGGL(k_hd_unify, dim3(blocks), dim3(kBlock), 0, s, P);
-    if (P.wide) hipLaunchKernelGGL(k_hd_merge<true>, dim3(blocks), dim3(kBlock), 0, s, P);
-    else hipLaunchKernelGGL(k_hd_merge<false>, dim3(blocks), dim3(kBlock), 0, s, P);
+    switch (row_form(P)) {
+    case kRowWide: hipLaunchKernelGGL(k_hd_merge<kRowWide>, dim3(blocks), dim3(kBlock), 0, s, P); break;
+    case kRowPacked: hipLaunchKernelGGL(k_hd_merge<kRowPacked>, dim3(blocks), dim3(kBlock), 0, s, P); break;
+    default: hipLaunchKernelGGL(k_hd_merge<kRowNarrow>, dim3(blocks), dim3(kBlock), 0, s, P);
+    }
 }
 
 void launch_hd_border(const Plan &P, int blocks, hipStream_t s)
@@ -1014,8 +1033,11 @@ void launch_hd_border(const Plan &P, int blocks, hipStream_t s)
     const int cb = (int)std::min<uint64_t>((P.n + kBlock - 1) / kBlock, 2048);
     hipLaunchKernelGGL(k_hd_border_rec, dim3(cb), dim3(kBlock), 0, s, P);
     launch_border_list(P, s);
-    if (P.wide) hipLaunchKernelGGL(k_hd_border<true>, dim3(blocks), dim3(kBlock), 0, s, P);
-    else hipLaunchKernelGGL(k_hd_border<false>, dim3(blocks), dim3(kBlock), 0, s, P);
+    switch (row_form(P)) {
+    case kRowWide: hipLaunchKernelGGL(k_hd_border<kRowWide>, dim3(blocks), dim3(kBlock), 0, s, P); break;
+    case kRowPacked: hipLaunchKernelGGL(k_hd_border<kRowPacked>, dim3(blocks), dim3(kBlock), 0, s, P); break;
+    default: hipLaunchKernelGGL(k_hd_border<kRowNarrow>, dim3(blocks), dim3(kBlock), 0, s, P);
+    }
 }
 
 }  // namespace hca
