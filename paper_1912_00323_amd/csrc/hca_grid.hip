@@ -295,12 +295,20 @@ __device__ __forceinline__ QBox<D> group_points_box(const Plan &P, uint32_t p0, 
     QBox<D> b;
 #pragma unroll
     for (int e = 0; e < D; e++) { b.lo[e] = INT32_MAX; b.hi[e] = INT32_MIN; }
-    for (uint32_t q = p0 + l; q < p1 + l; q += kWave) {
-        if (q < p1) {
-            const Pt<D> p = load_pt<D>(P.spts, q);
+    // four rows per lane in flight at once; a lane past the end re-reads
+    // row p0, which leaves the box unchanged
+    constexpr int kU = 4;
+    for (uint32_t q0 = p0 + l; q0 < p1 + l; q0 += kU * kWave) {
+        Pt<D> v[kU];
 #pragma unroll
-            for (int e = 0; e < D; e++) { b.lo[e] = min(b.lo[e], p.x[e]); b.hi[e] = max(b.hi[e], p.x[e]); }
+        for (int u = 0; u < kU; u++) {
+            const uint32_t q = q0 + u * kWave;
+            v[u] = load_pt<D>(P.spts, q < p1 ? q : p0);
         }
+#pragma unroll
+        for (int u = 0; u < kU; u++)
+#pragma unroll
+            for (int e = 0; e < D; e++) { b.lo[e] = min(b.lo[e], v[u].x[e]); b.hi[e] = max(b.hi[e], v[u].x[e]); }
     }
 #pragma unroll
     for (int e = 0; e < D; e++) { b.lo[e] = wave_min(b.lo[e]); b.hi[e] = wave_max(b.hi[e]); }
@@ -1526,8 +1534,10 @@ __device__ __forceinline__ void link_tile(const Plan &P, uint32_t GA, uint32_t G
 // spot).
 constexpr uint32_t kInlineTiles = 4;
 
+// Held to 128 registers (four waves per SIMD): a few spill, and the walk
+// still gains from the extra wave.
 template <int D, bool WIDE>
-__global__ __launch_bounds__(kBlock) void k_merge_inter(Plan P)
+__global__ __launch_bounds__(kBlock, 4) void k_merge_inter(Plan P)
 {
     __shared__ int32_t s_pt[kWavesPerBlock][kWave][D];
     const uint32_t w = wave_in_block(), l = lane_id();

@@ -49,6 +49,17 @@ __global__ __launch_bounds__(kBlock) void k_hd_group_box(Plan P)
             int32_t lo = INT32_MAX, hi = INT32_MIN;
             const int32_t *col = P.spts + l;
             uint32_t q = p0;
+            // sixteen rows in flight at once
+            for (; q + 16 <= p1; q += 16) {
+                int32_t v[16];
+#pragma unroll
+                for (int u = 0; u < 16; u++) v[u] = col[(uint64_t)(q + u) * sd];
+#pragma unroll
+                for (int u = 0; u < 16; u++) {
+                    lo = min(lo, v[u]);
+                    hi = max(hi, v[u]);
+                }
+            }
             for (; q + 4 <= p1; q += 4) {
                 const int32_t a = col[(uint64_t)q * sd], b = col[(uint64_t)(q + 1) * sd];
                 const int32_t c = col[(uint64_t)(q + 2) * sd], e = col[(uint64_t)(q + 3) * sd];
