@@ -561,9 +561,10 @@ __device__ __forceinline__ void hd_tally(const Plan &P, bool in, uint32_t cell, 
 // First pass: chunks of 8 consecutive sorted points, each point looking at
 // up to kHdCoreBudget candidates; points still undecided are appended to
 // the list of the second pass.
-// The packed form is held to 128 registers (four waves per SIMD).
+// The packed form is held to 96 registers (five waves per SIMD): some
+// spill, and the walk still gains from the extra wave.
 template <int ROW>
-__global__ __launch_bounds__(kBlock, ROW == kRowPacked ? 4 : 1) void k_hd_core(Plan P)
+__global__ __launch_bounds__(kBlock, ROW == kRowPacked ? 5 : 1) void k_hd_core(Plan P)
 {
     __shared__ __align__(16) int32_t s_own[kWavesPerBlock][kPch][kOwnStride];
     __shared__ int32_t s_qb[kWavesPerBlock][2 * kMaxDimHigh];
@@ -626,7 +627,7 @@ __global__ __launch_bounds__(kBlock, ROW == kRowPacked ? 4 : 1) void k_hd_core(P
 
 // Second pass: chunks of 8 points of the list, walked to the end.
 template <int ROW>
-__global__ __launch_bounds__(kBlock, ROW == kRowPacked ? 4 : 1) void k_hd_core_rest(Plan P)
+__global__ __launch_bounds__(kBlock, ROW == kRowPacked ? 5 : 1) void k_hd_core_rest(Plan P)
 {
     __shared__ __align__(16) int32_t s_own[kWavesPerBlock][kPch][kOwnStride];
     __shared__ int32_t s_qb[kWavesPerBlock][2 * kMaxDimHigh];
