@@ -1105,6 +1105,55 @@ __device__ __forceinline__ void rep_directions(const Plan &P, uint64_t ka, uint6
     *bw = vb > zero ? vb - 1 : vb;
 }
 
+// Pair (A, B) of one lane, B > A: unless the two cubes already share a root,
+// their facing representatives are tested and joined on a hit.  Returns
+// whether the pair still needs the exact test.
+template <int D, bool WIDE>
+__device__ __forceinline__ bool rep_pair(const Plan &P, uint32_t A, uint32_t B, uint32_t dfw, uint32_t dbw,
+                                         int64_t eps2, uint32_t &lt)
+{
+    bool todo = B != kNone && B > A && P.ncore[B] > 0;
+    if (todo) todo = uf_find(P.parent, A) != uf_find(P.parent, B);
+    bool joined = false;
+    if (todo && P.n_dir) {
+        const uint32_t qa = (uint32_t)ld_agent(P.rep + (uint64_t)A * P.n_dir + dfw);
+        const uint32_t qb = (uint32_t)ld_agent(P.rep + (uint64_t)B * P.n_dir + dbw);
+        lt++;
+        joined = within<D, WIDE>(load_pt<D>(P.spts, qa), load_pt<D>(P.spts, qb), eps2);
+        if (joined) uf_union(P.parent, A, B);
+    }
+    return todo && !joined && !P.rep_only;
+}
+
+// The lanes' pairs that need the exact test go to this wave's region of the
+// worklist; when the region is full they are tested here, one at a time.
+template <int D, bool WIDE>
+__device__ __forceinline__ void queue_exact(const Plan &P, bool exact, uint32_t A, uint32_t B, uint32_t &lt)
+{
+    const uint32_t l = lane_id();
+    const uint64_t m = __ballot(exact);
+    if (!m) return;
+    // region of this wave; slots of region r are [r * cap, (r + 1) * cap)
+    const uint32_t region = (blockIdx.x * kWavesPerBlock + wave_in_block()) % kWorkRegions;
+    const uint32_t cap = P.work_cap / kWorkRegions;
+    uint32_t base = 0;
+    if (l == 0) base = atomicAdd(P.ctr->work_count + region * kCounterStride, (uint32_t)__popcll(m));
+    base = lane_value(base, 0);
+    const uint32_t slot = base + __popcll(m & __lanemask_lt());
+    const bool spill = exact && slot >= cap;
+    if (exact && !spill) {
+        const uint64_t at = (uint64_t)region * cap + slot;
+        P.work[2ull * at] = A;
+        P.work[2ull * at + 1] = B;
+    }
+    uint64_t sm = __ballot(spill);
+    while (sm) {
+        const uint32_t src = __ffsll((unsigned long long)sm) - 1;
+        exact_pair<D, WIDE>(P, lane_value(A, src), lane_value(B, src), lt);
+        sm &= sm - 1;
+    }
+}
+
 template <int D, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_merge_rep(Plan P)
 {
@@ -1112,60 +1161,59 @@ __global__ __launch_bounds__(kBlock) void k_merge_rep(Plan P)
     uint32_t lt = 0;
     const uint32_t nc = ld_agent32(&P.ctr->n_cells);
     const WaveRange hca_wr_ = wave_range();
-    HCA_FOR_UNITS(A, nc) {
-        if (P.ncore[A] == 0) continue;
-        const uint64_t gkey = P.group_key[A];
-        const int64_t eps2 = cube_geo<D>(P, gkey).eps2;
-        const NbrSrc src = nbr_source(P, A);
-        // cubes B > A: the forward list, or the whole stencil
-        const uint32_t slots = src.lists ? 1 + src.fcount : src.slots;
-        for (uint32_t oc = 1; oc < slots; oc += kWave) {
-            const uint32_t j = oc + l;
-            uint32_t B = kNone, dfw = 0, dbw = 0;
-            if (j < slots) {
-                if (src.lists) {
-                    B = P.nbr[src.start + j - 1];
-                    if (B > A && P.n_dir) rep_directions<D>(P, gkey, P.group_key[B], &dfw, &dbw);
-                } else {
-                    const uint64_t nk = group_neighbour<D>(P, gkey, P.off + (uint64_t)j * D);
+    const bool lists = P.nbr_cap && P.ctr->nbr_overflow == 0;
+    const uint64_t flat_units = ((uint64_t)nc * P.n_off + kWave - 1) / kWave;
+    if (!lists && flat_units <= 0xffffffffull) {
+        // stencil: one (cube, offset) pair per lane, so the few forward
+        // offsets of small d fill the wave
+        HCA_FOR_UNITS(wu, (uint32_t)flat_units) {
+            const uint64_t u = (uint64_t)wu * kWave + l;
+            uint32_t A = kNone, B = kNone, dfw = 0, dbw = 0;
+            int64_t eps2 = 0;
+            if (u < (uint64_t)nc * P.n_off) {
+                A = (uint32_t)(u / P.n_off);
+                const uint32_t j = (uint32_t)(u - (uint64_t)A * P.n_off);
+                // cubes are numbered in key order: B > A exactly when the
+                // first non-zero component of the offset is positive
+                const int8_t *o = P.off + (uint64_t)j * D;
+                int lead = 0;
+#pragma unroll
+                for (int e = 0; e < D; e++)
+                    if (lead == 0) lead = o[e];
+                if (lead > 0 && P.ncore[A] != 0) {
+                    const uint64_t gkey = P.group_key[A];
+                    eps2 = cube_geo<D>(P, gkey).eps2;
+                    const uint64_t nk = group_neighbour<D>(P, gkey, o);
                     if (nk != ~0ull) B = group_lookup(P, nk);
                     if (P.n_dir) { dfw = P.dir_fwd[j]; dbw = P.dir_bwd[j]; }
                 }
             }
-            bool todo = B != kNone && B > A && P.ncore[B] > 0;
-            if (todo) todo = uf_find(P.parent, A) != uf_find(P.parent, B);
-            bool joined = false;
-            if (todo && P.n_dir) {
-                const uint32_t qa = (uint32_t)ld_agent(P.rep + (uint64_t)A * P.n_dir + dfw);
-                const uint32_t qb = (uint32_t)ld_agent(P.rep + (uint64_t)B * P.n_dir + dbw);
-                lt++;
-                joined = within<D, WIDE>(load_pt<D>(P.spts, qa), load_pt<D>(P.spts, qb), eps2);
-                if (joined) uf_union(P.parent, A, B);
-            }
-            const bool exact = todo && !joined && !P.rep_only;
-            const uint64_t m = __ballot(exact);
-            if (m) {
-                // region of this wave; slots of region r are [r * cap, (r + 1) * cap)
-                const uint32_t region = (blockIdx.x * kWavesPerBlock + wave_in_block()) % kWorkRegions;
-                const uint32_t cap = P.work_cap / kWorkRegions;
-                uint32_t base = 0;
-                if (l == 0)
-                    base = atomicAdd(P.ctr->work_count + region * kCounterStride, (uint32_t)__popcll(m));
-                base = __shfl(base, 0);
-                const uint32_t slot = base + __popcll(m & __lanemask_lt());
-                const bool spill = exact && slot >= cap;
-                if (exact && !spill) {
-                    const uint64_t at = (uint64_t)region * cap + slot;
-                    P.work[2ull * at] = A;
-                    P.work[2ull * at + 1] = B;
+            const bool exact = rep_pair<D, WIDE>(P, A, B, dfw, dbw, eps2, lt);
+            queue_exact<D, WIDE>(P, exact, A, B, lt);
+        }
+    } else {
+        HCA_FOR_UNITS(A, nc) {
+            if (P.ncore[A] == 0) continue;
+            const uint64_t gkey = P.group_key[A];
+            const int64_t eps2 = cube_geo<D>(P, gkey).eps2;
+            const NbrSrc src = nbr_source(P, A);
+            // cubes B > A: the forward list, or the whole stencil
+            const uint32_t slots = src.lists ? 1 + src.fcount : src.slots;
+            for (uint32_t oc = 1; oc < slots; oc += kWave) {
+                const uint32_t j = oc + l;
+                uint32_t B = kNone, dfw = 0, dbw = 0;
+                if (j < slots) {
+                    if (src.lists) {
+                        B = P.nbr[src.start + j - 1];
+                        if (B > A && P.n_dir) rep_directions<D>(P, gkey, P.group_key[B], &dfw, &dbw);
+                    } else {
+                        const uint64_t nk = group_neighbour<D>(P, gkey, P.off + (uint64_t)j * D);
+                        if (nk != ~0ull) B = group_lookup(P, nk);
+                        if (P.n_dir) { dfw = P.dir_fwd[j]; dbw = P.dir_bwd[j]; }
+                    }
                 }
-                // worklist full: test here, one spilled pair at a time
-                uint64_t sm = __ballot(spill);
-                while (sm) {
-                    const uint32_t src = __ffsll((unsigned long long)sm) - 1;
-                    exact_pair<D, WIDE>(P, A, __shfl(B, src), lt);
-                    sm &= sm - 1;
-                }
+                const bool exact = rep_pair<D, WIDE>(P, A, B, dfw, dbw, eps2, lt);
+                queue_exact<D, WIDE>(P, exact, A, B, lt);
             }
         }
     }
