@@ -755,7 +755,7 @@ hca_status run_hd(hca_ctx *ctx, const int32_t *points, uint32_t n, int32_t d, do
     if (const char *e = std::getenv("HCA_HASH_BITS"))
         P.key_bits = gbits + (uint32_t)std::min<int>(std::max(1, std::atoi(e)), 63 - (int)gbits);
     P.fine_bits = P.key_bits - gbits;                 // hash bits
-    P.passes = (P.key_bits + kRadixBits - 1) / kRadixBits;
+    P.passes = sort_passes(P.key_bits, true);
     P.digit_bits = (P.key_bits + P.passes - 1) / P.passes;
     P.wide = reach >= ((unsigned __int128)1 << 31) ? 1 : 0;
     // packed int16 rows when every span is below 2^15 and sums fit 32 bits
@@ -912,7 +912,7 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
     }
     P.key_bits = gbits + P.fine_bits;
     if (P.key_bits > 63) return fail(ctx, HCA_E_RANGE, "packed cube key needs more than 63 bits");
-    P.passes = std::max<uint32_t>(1, (P.key_bits + kRadixBits - 1) / kRadixBits);
+    P.passes = sort_passes(P.key_bits, P.key_bits > 32);
     P.digit_bits = std::max<uint32_t>(1, (P.key_bits + P.passes - 1) / P.passes);
     // largest coordinate difference of any pair the kernels test
     const unsigned __int128 reach = (unsigned __int128)(G.gradius + 1) * (uint64_t)G.gside - 1;
@@ -1182,7 +1182,7 @@ hca_status run_sets(hca_ctx *ctx, const BatchSet *sets, int32_t nseg)
         P.seg_shift = bits;
         P.key_bits = bits + bit_length(ns - 1);
         if (P.key_bits > 63) return fail(ctx, HCA_E_RANGE, "packed batch key needs more than 63 bits");
-        P.passes = std::max<uint32_t>(1, (P.key_bits + kRadixBits - 1) / kRadixBits);
+        P.passes = sort_passes(P.key_bits, P.key_bits > 32);
         P.digit_bits = std::max<uint32_t>(1, (P.key_bits + P.passes - 1) / P.passes);
         P.wide = wide ? 1 : 0;
         P.n_off = (uint32_t)(g.off.size() / d);

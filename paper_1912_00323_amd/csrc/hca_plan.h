@@ -17,10 +17,21 @@ constexpr int kWave = 64;
 constexpr int kBlock = 256;                    // 4 waves per workgroup
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
-// Radix sort of cube keys: digits of at most 8 bits, tiles of 256 threads x
-// 16 (32-bit keys) or 8 (64-bit keys) keys.
-constexpr int kRadixBits = 8;
+// Radix sort of cube keys: digits of at most 9 bits for 32-bit keys (an
+// 18-bit key in two passes, not three) and 8 bits for 64-bit keys (where the
+// wider digit measured slower), tiles of 256 threads x 16 (32-bit keys) or 8
+// (64-bit keys) keys.  Each thread of a pass owns 2^digit / 256 digits;
+// histograms and look-back words keep a stride of kRadix per pass and tile.
+constexpr int kRadixBits = 9;
 constexpr int kRadix = 1 << kRadixBits;
+template <typename K>
+constexpr int radix_bits() { return sizeof(K) == 4 ? 9 : 8; }
+// Passes for a key of key_bits bits held in 64-bit words (wide) or not.
+inline uint32_t sort_passes(uint32_t key_bits, bool wide)
+{
+    const uint32_t rb = wide ? 8u : 9u;
+    return key_bits ? (key_bits + rb - 1) / rb : 1u;
+}
 // 32-bit keys take 16 per thread (4096-key tiles), 64-bit keys 8 (2048-key
 // tiles: their LDS staging would otherwise halve the resident tiles);
 // kSortTile, the smaller, sizes the look-back words.

@@ -201,14 +201,14 @@ __device__ __forceinline__ bool hd_new_cube(const Plan &P, uint32_t idx)
 
 // ---------------------------------------------------------------------------
 // One stable LSD pass with decoupled look-back (one launch per digit).  A
-// digit has P.digit_bits <= 8 bits: the key bits spread evenly over the
+// digit has P.digit_bits <= 9 bits: the key bits spread evenly over the
 // passes, so that the runs a tile writes per digit are as long as they can
 // be for that number of passes.
 //
-// A workgroup takes the next 2048-key tile by ticket.  Each wave owns 512
-// consecutive keys and ranks them in eight rounds of 64: lanes with equal
-// digits find each other with eight ballots, and a per-wave digit counter in
-// LDS gives each key its rank.  The tile's digit counts are published at once
+// A workgroup takes the next tile (sort_items keys per thread) by ticket.
+// Each wave owns a quarter of it, consecutive keys, and ranks them in rounds
+// of 64: lanes with equal digits find each other with one ballot per digit
+// bit, and a per-wave digit counter in LDS gives each key its rank.  The tile's digit counts are published at once
 // and turned into global offsets by looking back over earlier tiles; keys
 // are then staged in LDS in digit order and written out in runs.
 // ---------------------------------------------------------------------------
@@ -223,17 +223,18 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(Plan P, const K *__restrict
     constexpr int kItems = sort_items<K>();
     constexpr int kTile = kBlock * kItems;
     constexpr int PER_WAVE = kWave * kItems;
+    constexpr int RADIX = 1 << radix_bits<K>();
     __shared__ K s_keys[kTile];
     __shared__ uint32_t s_vals[kTile];
-    __shared__ uint32_t s_wcnt[W][kRadix];      // per-wave digit counts, then offsets
-    __shared__ uint32_t s_tstart[kRadix];       // tile-local start of each digit
-    __shared__ uint32_t s_gbase[kRadix];        // global position of tile-local 0 per digit
+    __shared__ uint32_t s_wcnt[W][RADIX];       // per-wave digit counts, then offsets
+    __shared__ uint32_t s_tstart[RADIX];        // tile-local start of each digit
+    __shared__ uint32_t s_gbase[RADIX];         // global position of tile-local 0 per digit
     __shared__ uint32_t s_red[W];
     __shared__ uint32_t s_tile;
 
     const uint32_t t = threadIdx.x, w = wave_in_block(), l = lane_id();
     if (t == 0) s_tile = atomicAdd(ticket, 1u);
-    for (uint32_t e = t; e < W * kRadix; e += kBlock) (&s_wcnt[0][0])[e] = 0;
+    for (uint32_t e = t; e < W * RADIX; e += kBlock) (&s_wcnt[0][0])[e] = 0;
     __syncthreads();
     const uint32_t tile = s_tile;
     const uint32_t n = P.n;
@@ -257,7 +258,7 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(Plan P, const K *__restrict
         const uint32_t dg = (uint32_t)(key[j] >> shift) & dmask;
         uint64_t peers = __ballot(ok);
 #pragma unroll
-        for (int b = 0; b < kRadixBits; b++) {
+        for (int b = 0; b < radix_bits<K>(); b++) {
             if (b >= (int)nbits) break;                  // higher digit bits are zero
             const bool bit = (dg >> b) & 1u;
             const uint64_t m = __ballot(bit);
@@ -269,46 +270,64 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(Plan P, const K *__restrict
         if (ok && below == 0) s_wcnt[w][dg] = before + __popcll(peers);
         __builtin_amdgcn_wave_barrier();
         rank[j] = before + below;
-        dig[j] = ok ? dg : kRadix;
+        dig[j] = ok ? dg : RADIX;
     }
     __syncthreads();
 
-    // thread t owns digit t: tile count, per-wave offsets, look-back
-    uint32_t cnt = 0;
-    {
+    // thread t owns digits t, t + 256, ...: tile counts and per-wave offsets;
+    // the counts of the pass's digits (those below 2^digit_bits; the others
+    // are empty in every tile) are published before any look-back starts
+    constexpr int R = RADIX / kBlock;
+    const uint32_t ndig = 1u << nbits;
+    uint32_t cnt[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const uint32_t dd = t + r * kBlock;
         uint32_t c[W];
 #pragma unroll
-        for (int i = 0; i < W; i++) c[i] = s_wcnt[i][t];
+        for (int i = 0; i < W; i++) c[i] = s_wcnt[i][dd];
         uint32_t run = 0;
 #pragma unroll
-        for (int i = 0; i < W; i++) { s_wcnt[i][t] = run; run += c[i]; }
-        cnt = run;
+        for (int i = 0; i < W; i++) { s_wcnt[i][dd] = run; run += c[i]; }
+        cnt[r] = run;
+        if (dd < ndig) st_agent(status + (uint64_t)tile * kRadix + dd, (tile == 0 ? kFlagInc : kFlagAgg) | run);
     }
-    uint64_t *my = status + (uint64_t)tile * kRadix + t;
-    st_agent(my, (tile == 0 ? kFlagInc : kFlagAgg) | cnt);
-    uint32_t total;
-    const uint32_t tstart = block_exclusive_scan<uint32_t>(cnt, s_red, &total);
-    const uint32_t gstart = block_exclusive_scan<uint32_t>(ld_agent32(hist + t), s_red, &total);
-    uint64_t excl = 0;
-    if (tile > 0) {
-        int64_t k = (int64_t)tile - 1;
-        while (true) {
-            const uint64_t v = ld_agent(status + (uint64_t)k * kRadix + t);
-            const uint64_t f = v & ~kValMask;
-            if (f == 0) { __builtin_amdgcn_s_sleep(1); continue; }
-            excl += v & kValMask;
-            if (f == kFlagInc) break;
-            k--;
+    // tile-local and global starts: exclusive scans over the digits in order
+    uint32_t tstart[R], gstart[R];
+    {
+        uint32_t tacc = 0, gacc = 0, total;
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            tstart[r] = tacc + block_exclusive_scan<uint32_t>(cnt[r], s_red, &total);
+            tacc += total;
+            gstart[r] = gacc + block_exclusive_scan<uint32_t>(ld_agent32(hist + t + r * kBlock), s_red, &total);
+            gacc += total;
         }
-        st_agent(my, kFlagInc | (excl + cnt));
     }
-    s_tstart[t] = tstart;
-    s_gbase[t] = gstart + (uint32_t)excl - tstart;
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const uint32_t dd = t + r * kBlock;
+        uint64_t excl = 0;
+        if (tile > 0 && dd < ndig) {
+            int64_t k = (int64_t)tile - 1;
+            while (true) {
+                const uint64_t v = ld_agent(status + (uint64_t)k * kRadix + dd);
+                const uint64_t f = v & ~kValMask;
+                if (f == 0) { __builtin_amdgcn_s_sleep(1); continue; }
+                excl += v & kValMask;
+                if (f == kFlagInc) break;
+                k--;
+            }
+            st_agent(status + (uint64_t)tile * kRadix + dd, kFlagInc | (excl + cnt[r]));
+        }
+        s_tstart[dd] = tstart[r];
+        s_gbase[dd] = gstart[r] + (uint32_t)excl - tstart[r];
+    }
     __syncthreads();
 
 #pragma unroll
     for (int j = 0; j < kItems; j++) {
-        if (dig[j] < kRadix) {
+        if (dig[j] < RADIX) {
             const uint32_t lp = s_tstart[dig[j]] + s_wcnt[w][dig[j]] + rank[j];
             s_keys[lp] = key[j];
             s_vals[lp] = val[j];
