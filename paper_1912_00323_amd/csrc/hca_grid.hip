@@ -1116,11 +1116,15 @@ __device__ __forceinline__ bool rep_pair(const Plan &P, uint32_t A, uint32_t B, 
     if (todo) todo = uf_find(P.parent, A) != uf_find(P.parent, B);
     bool joined = false;
     if (todo && P.n_dir) {
-        const uint32_t qa = (uint32_t)ld_agent(P.rep + (uint64_t)A * P.n_dir + dfw);
-        const uint32_t qb = (uint32_t)ld_agent(P.rep + (uint64_t)B * P.n_dir + dbw);
-        lt++;
-        joined = within<D, WIDE>(load_pt<D>(P.spts, qa), load_pt<D>(P.spts, qb), eps2);
-        if (joined) uf_union(P.parent, A, B);
+        const uint64_t ra = ld_agent(P.rep + (uint64_t)A * P.n_dir + dfw);
+        const uint64_t rb = ld_agent(P.rep + (uint64_t)B * P.n_dir + dbw);
+        // a core cube always has a representative in every direction; a slot
+        // still "none" (all ones) is left to the exact test rather than read
+        if (ra != ~0ull && rb != ~0ull) {
+            lt++;
+            joined = within<D, WIDE>(load_pt<D>(P.spts, (uint32_t)ra), load_pt<D>(P.spts, (uint32_t)rb), eps2);
+            if (joined) uf_union(P.parent, A, B);
+        }
     }
     return todo && !joined && !P.rep_only;
 }

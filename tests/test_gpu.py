@@ -109,11 +109,7 @@ def test_group_lists_fallback(ctx, slab, monkeypatch):
             assert stats["list_overflow"] == 0
 
 
-@pytest.mark.parametrize("record", [
-    pytest.param("0", marks=pytest.mark.skip(
-        reason="this case ended in a GPU memory fault with a variant of the representative kernel (since taken "
-               "out) and no cause was found; it stays off the GPU until one is")),
-    "1"])
+@pytest.mark.parametrize("record", ["0", "1"])
 def test_group_recorded_pairs(ctx, record, monkeypatch):
     """With and without the neighbours recorded by core marking (joined
     before the merge tiles of search groups, and deciding the border points
