@@ -261,6 +261,21 @@ def test_wide_distances(ctx):
     assert np.array_equal(got, oracle.dbscan(pts, eps, 5))
 
 
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
+def test_sort_digit_widths(ctx, d):
+    """Cube keys from a few bits to past 32 (9-bit digits for 32-bit keys, 8-bit
+    ones for 64-bit keys, the pass count evened out over the key): the same
+    labels as the oracle at every width."""
+    rng = np.random.default_rng(300 + d)
+    pts = quantise(make_blobs(rng, 1500, d, 4, 0.01, 0.3), 14)
+    for eps in (3.0, 10.0, 40.0, 160.0, 640.0):
+        check(ctx, pts, eps, 3, f"digit widths d={d}")
+        _, st = gpu_labels(ctx, pts, eps, 3, stats=True)
+        kb = st["key_bits"]
+        rb = 9 if kb <= 32 else 8
+        assert st["sort_passes"] == max(1, -(-kb // rb)), (kb, st["sort_passes"])
+
+
 def test_errors(ctx):
     from paper_1912_00323_amd import hca
     import torch
