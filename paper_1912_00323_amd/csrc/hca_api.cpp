@@ -411,15 +411,17 @@ void plan_sizes(Plan &P, uint32_t gbits, bool count_work, bool want_stats, Sizes
 
 // Neighbour lists from prefix ranges: the groups sharing the group-key
 // prefix of the first d/2 axes are consecutive, so the lists can scan them
-// (when that prefix takes at most 24 bits and its table at most 16 entries
-// per point, or 2^20; HCA_PREFIX=0 turns it off).
+// (when that prefix takes at most 26 bits and its table at most 32 entries
+// per point, or 2^20: a batch's data-set bits sit above the prefix; the table
+// is written only where groups exist, so its size costs memory, not
+// traffic; HCA_PREFIX=0 turns it off).
 void plan_prefix(Plan &P, uint32_t gbits, Sizes *Z)
 {
     Z->pbits = 0;
     if (!P.nbr_cap || P.d < 2 || P.hd || !env_prefix()) return;
     P.pshift = P.goff[P.d / 2 - 1];
     const uint32_t pbits = gbits - P.pshift;
-    if (pbits <= 24 && (1ull << pbits) <= std::max<uint64_t>(16ull * P.n, 1ull << 20))
+    if (pbits <= 26 && (1ull << pbits) <= std::max<uint64_t>(32ull * P.n, 1ull << 20))
         Z->pbits = std::max<uint32_t>(1, pbits);
 }
 

@@ -55,8 +55,8 @@ size_t footprint(int64_t n, int32_t d)
     uint64_t dirs = 1;
     for (int k = 0; k < std::min(d, 4); k++) dirs *= 3;
     // + 72 B for the neighbours recorded by core marking, and for lists (d >= 3)
-    // up to 128 B of prefix-range table
-    uint64_t per_point = 256 + 72 + 8ull * (dirs - 1) + 16ull * (uint64_t)d + (d >= 3 ? 264 + 128 : 0);
+    // up to 256 B of prefix-range table
+    uint64_t per_point = 256 + 72 + 8ull * (dirs - 1) + 16ull * (uint64_t)d + (d >= 3 ? 264 + 256 : 0);
     if (d > 8) per_point += 12ull * (((uint64_t)d + 3) & ~3ull);      // padded rows and group boxes
     return (size_t)((uint64_t)n * per_point + (1ull << 20));
 }
