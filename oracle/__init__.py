@@ -125,7 +125,7 @@ def dbscan(points, eps: float, min_pts: int, threads: int = 0, details: bool = F
 
 
 def hca_grid(points, eps: float, min_pts: int, rep_mode: int = 0, threads: int = 1,
-             details: bool = False):
+             details: bool = False, lib=None):
     """The paper's hypercube method on the CPU (exact unless ``rep_mode == 1``).
     Returns int32 canonical labels; with ``details`` also (core flags, stats dict)."""
     p = _points(points)
@@ -133,7 +133,7 @@ def hca_grid(points, eps: float, min_pts: int, rep_mode: int = 0, threads: int =
     labels = np.empty(n, np.int32)
     core = np.empty(n, np.int32)
     stats = np.zeros(8, np.int64)
-    _check(_load().oracle_hca_grid(_ptr(p, ctypes.c_int32), n, d, float(eps), int(min_pts),
+    _check((lib or _load()).oracle_hca_grid(_ptr(p, ctypes.c_int32), n, d, float(eps), int(min_pts),
                                    int(rep_mode), _ptr(labels, ctypes.c_int32),
                                    _ptr(core, ctypes.c_int32), _ptr(stats, ctypes.c_int64),
                                    int(threads)))

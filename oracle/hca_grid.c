@@ -51,6 +51,14 @@
 #include <omp.h>
 #endif
 
+/* Planted mistakes, compiled in only with -DORACLE_MUTANT=k by the test that
+ * checks that the pins catch each of them (k = 11..14 live in this file).
+ * The default build has k = 0. */
+#ifndef ORACLE_MUTANT
+#define ORACLE_MUTANT 0
+#endif
+#define MUT(k) (ORACLE_MUTANT == (k))
+
 #define ORC_OK 0
 #define ORC_EINVAL 1
 #define ORC_ERANGE 2
@@ -292,12 +300,14 @@ int oracle_hca_grid(const int32_t *pts, int64_t n, int32_t d, double eps, int32_
                         if (!delta[k]) continue;
                         int64_t c = g.ccoord[A * d + k];
                         int64_t ideal = (delta[k] > 0 ? c + 1 : c) * g.s;
+                        if (MUT(13) && delta[k] > 0) ideal = c * g.s;        /* +1 on the lower face */
+                        if (MUT(14) && delta[k] < 0) ideal = (c + 1) * g.s;  /* -1 on the upper face */
                         int64_t ya = (int64_t)p[k] - origin[k] - ideal;
                         int64_t yb = (int64_t)r[k] - origin[k] - ideal;
                         sa += ya * ya;
                         sb += yb * yb;
                     }
-                    if (sa < sb) rA[t] = a;  /* replace only when strictly closer */
+                    if (sa < sb || (MUT(12) && sa == sb)) rA[t] = a;  /* replace only when strictly closer */
                 }
             }
         }
@@ -324,7 +334,7 @@ int oracle_hca_grid(const int32_t *pts, int64_t n, int32_t d, double eps, int32_
                     for (int k = 0; k < d; k++) {
                         int64_t dd = g.ccoord[Y * d + k] - g.ccoord[X * d + k];
                         dx[k] = (dd > 0) - (dd < 0);
-                        dy[k] = -dx[k];
+                        dy[k] = MUT(11) ? dx[k] : -dx[k];   /* Y faces back towards X */
                     }
                     int64_t rx = rep[X * ndir + dir_index(dx, d)];
                     int64_t ry = rep[Y * ndir + dir_index(dy, d)];

@@ -375,6 +375,12 @@ def test_representative_only_mode(ctx):
             pts = np.array(g["points"], np.int32)
             got = gpu_labels(ctx, pts, case["eps"], case["min_pts"])
             assert got.tolist() == case["rep_only_labels"]
+        faces = json.loads((GOLDEN / "representative_faces.json").read_text())
+        for case in faces["cases"]:
+            pts = np.array(case["points"], np.int32)
+            print(f"[case] representatives only, fixture {case['name']}", flush=True)
+            got = gpu_labels(ctx, pts, case["eps"], case["min_pts"])
+            assert got.tolist() == case["rep_only_labels"], case["name"]
         for d in (2, 3, 4):
             for seed in range(3):
                 rng = np.random.default_rng(300 + 10 * d + seed)

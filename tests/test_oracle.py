@@ -306,8 +306,28 @@ def pin_invariances(lib):
     assert np.array_equal(oracle.dbscan(np.ascontiguousarray(pad[:, perm]), eps, mp, lib=lib), base)
 
 
+def pin_representative_faces(lib):
+    """The grid part's representative-only merge (the paper's merge as printed)
+    on hand-derived cases: the facing rule (sign of the offset against its
+    opposite) along an axis, on a diagonal and on a knight offset, the ideal
+    position on the upper face for +1 and the lower face for -1, and ties
+    kept by the first point (Algorithm 2; Depth First Search paragraph)."""
+    g = json.loads((GOLDEN / "representative_faces.json").read_text())
+    for case in g["cases"]:
+        pts = np.array(case["points"], np.int32)
+        got = oracle.hca_grid(pts, case["eps"], case["min_pts"], rep_mode=1, lib=lib)
+        assert got.tolist() == case["rep_only_labels"], case["name"]
+        for mode in (0, 2):
+            got = oracle.hca_grid(pts, case["eps"], case["min_pts"], rep_mode=mode, lib=lib)
+            assert got.tolist() == case["labels"], (case["name"], mode)
+    split = json.loads((GOLDEN / "representative_split.json").read_text())
+    c = split["cases"][0]
+    pts = np.array(split["points"], np.int32)
+    assert oracle.hca_grid(pts, c["eps"], c["min_pts"], rep_mode=1, lib=lib).tolist() == c["rep_only_labels"]
+
+
 PINS = [pin_eps2_rational, pin_golden, pin_closed_form_1d, pin_sklearn, pin_scipy_min_pts_1,
-        pin_expand_cluster, pin_special_cases, pin_invariances]
+        pin_expand_cluster, pin_special_cases, pin_invariances, pin_representative_faces]
 
 
 @pytest.mark.parametrize("pin", PINS, ids=[p.__name__ for p in PINS])
@@ -315,7 +335,7 @@ def test_oracle_pin(pin):
     pin(None)
 
 
-N_MUTANTS = 10
+N_MUTANTS = 14
 
 
 def test_planted_mistakes_are_caught(tmp_path):
@@ -351,6 +371,39 @@ def test_grid_part_matches_definition_random():
         for mode in (0, 2):
             got = oracle.hca_grid(pts, eps, mp, rep_mode=mode)
             assert np.array_equal(got, want), (trial, d, n, eps, mp, mode)
+
+
+def test_representative_only_refines_exact():
+    """Representative-only merging joins two cubes only when two of their core
+    points are within eps, so it can split exact clusters but never join two:
+    core and noise points are the same, every representative-only cluster of
+    core points lies inside one exact cluster, and on 1-D data (one facing
+    pair per cube pair: the last point of the left cube, the first of the
+    right) it equals the exact result whenever the cubes hold one point."""
+    rng = np.random.default_rng(31)
+    for trial in range(80):
+        d = int(rng.integers(1, 5))
+        n = int(rng.integers(1, 300))
+        pts = rand_points(rng, n, d, int(rng.integers(2, 60)), 0.1)
+        eps = float(rng.uniform(0.5, 25.0))
+        mp = int(rng.integers(1, 6))
+        exact, core_e, _ = oracle.hca_grid(pts, eps, mp, details=True)
+        approx, core_a, _ = oracle.hca_grid(pts, eps, mp, rep_mode=1, details=True)
+        assert np.array_equal(core_e, core_a)
+        assert np.array_equal(exact < 0, approx < 0), trial
+        where = {}
+        for i in np.flatnonzero(core_a):
+            assert where.setdefault(int(approx[i]), int(exact[i])) == int(exact[i]), trial
+    # 1-D, minPts = 1, cube side s = floor(sqrt(eps2)): every point is core and
+    # sits alone in its cube when points are spaced at least s apart; then the
+    # facing representatives are the points themselves
+    for trial in range(20):
+        eps = float(rng.uniform(3.0, 20.0))
+        s = oracle.grid_geometry(eps, 1)[0]
+        x = np.cumsum(rng.integers(s, 2 * s + 10, size=60)).reshape(-1, 1).astype(np.int32)
+        x = x[rng.permutation(60)]
+        want = oracle.dbscan(x, eps, 1)
+        assert np.array_equal(oracle.hca_grid(x, eps, 1, rep_mode=1), want), trial
 
 
 def test_grid_part_matches_definition_small_workload():
