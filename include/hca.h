@@ -105,6 +105,8 @@ typedef struct {
     int64_t tests_intra;      /* inside search groups (m > 1) */
     int32_t packed_rows;      /* d > 8: 1 if candidate rows were packed as int16 pairs */
     int32_t key_axes;         /* d > 8: axes spanned by the search-group key (0 for d <= 8) */
+    int64_t core_rest;        /* d > 8: points left undecided by the first core-marking pass
+                               * (candidate budget spent) and walked by the second */
 } hca_stats;
 
 /* Exact floor(eps^2) of a double (no device needed).  HCA_E_INVAL if eps is
@@ -136,9 +138,10 @@ hca_status hca_set_stream(hca_ctx *ctx, void *stream);
  * others; cubes over all axes still make points within eps of each other and
  * stay the union-find nodes.  The result is the same exact DBSCAN.
  * points: DEVICE pointer to n*d int32, row-major [n][d], fixed-point units;
- *         read only, owned by the caller.  Aligned to 8 bytes for d = 2 and
- *         to 16 bytes for d = 4 or 8 (HCA_E_INVAL otherwise); the start of
- *         any device allocation qualifies.
+ *         read only, owned by the caller; 4-byte aligned (HCA_E_INVAL
+ *         otherwise).  For d = 2, 4 or 8 rows not on an 8- (d = 2) or
+ *         16-byte (d = 4, 8) boundary are first copied to an aligned buffer
+ *         of the context (one extra pass over the rows).
  * eps:    radius in the same units (e.g. 0.02 * 2^12).
  * min_pts: >= 1; |N(p)| counts p itself (Definition 2).
  * labels: DEVICE pointer to n int32, owned by the caller: -1 for noise, else
@@ -206,8 +209,14 @@ hca_status hca_cluster_sets(hca_ctx *ctx, const int32_t *const *points, int32_t 
  *     (requests per batch); HCA_E_INVAL otherwise, HCA_E_DEVICE / NOMEM.
  *   hca_server_submit: queue a request; points (DEVICE int32[n][d]) must stay
  *     valid and labels (DEVICE int32[n]) unread until the request completes;
- *     tag is the caller's.  HCA_E_INVAL for bad arguments or after destroy
- *     began.
+ *     tag is the caller's.  after_stream (a hipStream_t; NULL is the
+ *     device's default stream): the request's kernels start only after all
+ *     work queued on that stream before this call (an event recorded there is
+ *     waited on by the worker's stream), so points written and labels filled
+ *     on the caller's stream are ordered before it.  Once hca_server_poll
+ *     returns the tag, the labels are final and visible to every stream.
+ *     HCA_E_INVAL for bad arguments or after destroy began; HCA_E_DEVICE if
+ *     the event cannot be recorded.
  *   hca_server_poll: move up to max completed requests into tags, status
  *     (the clustering call's status) and t_done (hca_clock seconds);
  *     returns how many.  HOST arrays owned by the caller.
@@ -219,7 +228,7 @@ typedef struct hca_server hca_server;
 hca_status hca_server_create(hca_server **out, int32_t device, int32_t workers, int64_t budget_bytes,
                              int32_t max_batch);
 hca_status hca_server_submit(hca_server *srv, const int32_t *points, int64_t n, int32_t d, double eps,
-                             int32_t min_pts, int32_t *labels, uint64_t tag);
+                             int32_t min_pts, int32_t *labels, uint64_t tag, void *after_stream);
 int32_t hca_server_poll(hca_server *srv, uint64_t *tags, int32_t *status, double *t_done, int32_t max);
 hca_status hca_server_drain(hca_server *srv);
 void hca_server_destroy(hca_server *srv);

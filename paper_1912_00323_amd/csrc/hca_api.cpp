@@ -175,6 +175,16 @@ bool env_prefix()
     return !(e && !std::strcmp(e, "0"));
 }
 
+// HCA_HD_BUDGET=k: candidates per point in the first core pass of the
+// many-axis path (at least 64; default kHdCoreBudget), so that tests can make
+// the second pass do real work on small inputs
+uint32_t env_hd_budget()
+{
+    const char *e = std::getenv("HCA_HD_BUDGET");
+    if (!e) return kHdCoreBudget;
+    return (uint32_t)std::min<long>(std::max<long>(64, std::atol(e)), 1l << 30);
+}
+
 bool env_reps()
 {
     const char *e = std::getenv("HCA_REPS");
@@ -256,6 +266,8 @@ struct hca_ctx {
     size_t pinned_size = 0;
     void *io = nullptr;               // staging for hca_cluster_host
     size_t io_size = 0;
+    void *aligned = nullptr;          // rows of a call whose points are off their vector alignment
+    size_t aligned_size = 0;
     void *geo_dev = nullptr;          // offsets and direction tables
     size_t geo_dev_size = 0;
     void *bws = nullptr;              // batches: staged rows, data-set tables, offsets
@@ -604,6 +616,7 @@ void fill_stats(hca_ctx *ctx, const Plan &P, hca_stats *stats)
         stats->list_overflow = (int32_t)hc->nbr_overflow;
     stats->packed_rows = P.spts16 != nullptr ? 1 : 0;
     stats->key_axes = P.hd ? (int32_t)P.kd : 0;
+    stats->core_rest = P.hd ? (int64_t)hc->hd_left : 0;
 }
 
 // ---- more than kMaxDim axes ----------------------------------------------------
@@ -719,6 +732,7 @@ hca_status run_hd(hca_ctx *ctx, const int32_t *points, uint32_t n, int32_t d, do
     P.min_pts = min_pts;
     P.eps2 = eps2;
     P.hd = 1;
+    P.hd_budget = env_hd_budget();
     P.sd = ((uint32_t)d + 7u) & ~7u;
     const uint64_t side = std::max<uint64_t>(1, isqrt_u64((uint64_t)eps2 / (uint64_t)d));
     const uint64_t E = isqrt_u64((uint64_t)eps2);
@@ -814,18 +828,27 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
     if (!(eps > 0.0) || !std::isfinite(eps)) return fail(ctx, HCA_E_INVAL, "eps must be finite and > 0");
     if (min_pts < 1) return fail(ctx, HCA_E_INVAL, "min_pts must be >= 1");
     if (n64 > 0 && (!points || !labels)) return fail(ctx, HCA_E_INVAL, "points and labels must not be NULL");
-    {
-        // rows are read with 8- or 16-byte vector loads when d is 2, 4 or 8
-        const uintptr_t need = d == 2 ? 8 : (d == 4 || d == 8) ? 16 : 4;
-        if (((uintptr_t)points % need) || ((uintptr_t)labels % 4))
-            return fail(ctx, HCA_E_INVAL, "points must be aligned to 8 bytes (d=2) or 16 bytes (d=4, 8)");
-    }
+    if (((uintptr_t)points % 4) || ((uintptr_t)labels % 4))
+        return fail(ctx, HCA_E_INVAL, "points and labels must be aligned to 4 bytes (int32)");
     if (stats) std::memset(stats, 0, sizeof *stats);
     if (n64 == 0) return HCA_OK;
     if (d > kMaxDim) return run_hd(ctx, points, (uint32_t)n64, d, eps, min_pts, labels, core_out, stats);
     const uint32_t n = (uint32_t)n64;
     hipStream_t s = ctx->stream;
     HCA_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    {
+        // rows are read with 8- or 16-byte vector loads when d is 2, 4 or 8:
+        // rows that start off that alignment are first copied to an aligned
+        // staging buffer on the stream
+        const uintptr_t need = d == 2 ? 8 : (d == 4 || d == 8) ? 16 : 4;
+        if ((uintptr_t)points % need) {
+            const size_t bytes = (size_t)n * d * sizeof(int32_t);
+            hca_status st = ensure(ctx, &ctx->aligned, &ctx->aligned_size, bytes, "aligned rows");
+            if (st) return st;
+            HCA_HIP(hipMemcpyAsync(ctx->aligned, points, bytes, hipMemcpyDeviceToDevice, s), "aligned rows");
+            points = (const int32_t *)ctx->aligned;
+        }
+    }
 
     // geometry (cached between calls with the same eps2, d and settings)
     int64_t eps2;
@@ -1316,6 +1339,7 @@ void hca_destroy(hca_ctx *ctx)
     (void)hipSetDevice(ctx->device);
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->io) (void)hipFree(ctx->io);
+    if (ctx->aligned) (void)hipFree(ctx->aligned);
     if (ctx->geo_dev) (void)hipFree(ctx->geo_dev);
     if (ctx->bws) (void)hipFree(ctx->bws);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);

@@ -464,13 +464,19 @@ __device__ __forceinline__ void list_append(const Plan &P, uint32_t G, const QBo
             }
             far = acc > eps2;
         } else {
-            int32_t acc = 0;
+            // The host's narrow-distance bound covers pairs within the
+            // stencil's reach, but a prefix-range scan also meets groups far
+            // beyond it: each gap is clamped to 46341 (whose square already
+            // exceeds any int32 eps^2) and the sum saturates at 2^31, so the
+            // test stays exact without overflowing.
+            uint32_t acc = 0;
 #pragma unroll
             for (int e = 0; e < D; e++) {
                 const int32_t gap = max(max(ob.lo[e] - qb.hi[e], qb.lo[e] - ob.hi[e]), 0);
-                acc += __mul24(gap, gap);
+                const uint32_t gc = min((uint32_t)gap, 46341u);
+                acc = min(acc + __umul24(gc, gc), 0x80000000u);
             }
-            far = acc > (int32_t)min(eps2, (int64_t)INT32_MAX);
+            far = acc > (uint32_t)min(eps2, (int64_t)INT32_MAX);
         }
         if (far) G = kNone;
     }

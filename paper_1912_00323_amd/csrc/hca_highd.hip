@@ -535,10 +535,6 @@ __device__ __forceinline__ uint32_t hd_count_walk(const Plan &P, uint32_t g, con
     return done;
 }
 
-// Candidates a point of the first core pass looks at before it is left to
-// the second pass (which walks chunks of such points only).
-constexpr uint32_t kHdCoreBudget = 16384;
-
 // Per-cube tallies of a chunk's decided core points: one atomic per cube.
 __device__ __forceinline__ void hd_tally(const Plan &P, bool in, uint32_t cell, bool core, uint32_t me)
 {
@@ -559,7 +555,7 @@ __device__ __forceinline__ void hd_tally(const Plan &P, bool in, uint32_t cell, 
 }
 
 // First pass: chunks of 8 consecutive sorted points, each point looking at
-// up to kHdCoreBudget candidates; points still undecided are appended to
+// up to P.hd_budget candidates; points still undecided are appended to
 // the list of the second pass.
 // The packed form is held to 96 registers (five waves per SIMD): some
 // spill, and the walk still gains from the extra wave.
@@ -598,7 +594,7 @@ __global__ __launch_bounds__(kBlock, ROW == kRowPacked ? 5 : 1) void k_hd_core(P
                 left &= ~run;
                 bool cut;
                 const uint32_t got = hd_count_walk<ROW>(P, g, s_own[w], qpos, ~run & all, cnt, s_qb[w], s_beg[w],
-                                                         s_pre[w], lt, kHdCoreBudget, &cut);
+                                                         s_pre[w], lt, P.hd_budget, &cut);
                 done |= got & run;
                 if (cut) undec |= run & ~got;
             }

@@ -10,6 +10,10 @@ namespace hca {
 constexpr int kMaxDim = 8;                     // axes of the packed cube key
 constexpr int kMaxDimHigh = 64;                // axes of a point (more than 8: hashed cubes)
 constexpr int kRec = 16;                       // neighbours recorded per point by core marking
+// More than kMaxDim axes: candidates a point of the first core pass looks at
+// before it is left to the second pass (which walks chunks of such points
+// only); the host may lower it per call.
+constexpr uint32_t kHdCoreBudget = 16384;
 
 // nrec value of a point that found c neighbours: c when all were recorded
 __host__ __device__ constexpr uint32_t rec_count(uint32_t c) { return c <= (uint32_t)kRec ? c : kRec + 1; }
@@ -127,6 +131,7 @@ struct Plan {
     // fine_bits bits of a hash of the point's cube over all d axes.  Points
     // and group boxes are stored with rows of sd >= d int32 (zero padded).
     uint32_t hd;
+    uint32_t hd_budget;         // candidates per point in the first core pass (hd)
     uint32_t sd;
     uint32_t kd;
     uint8_t kdim[kMaxDim];

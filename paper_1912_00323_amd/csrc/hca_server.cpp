@@ -39,6 +39,7 @@ struct Request {
     int32_t *labels;
     uint64_t tag;
     size_t bytes;
+    hipEvent_t ready;           // recorded on the caller's stream at submission, or null
 };
 
 struct Done {
@@ -74,6 +75,7 @@ struct hca_server {
     std::condition_variable cv_work, cv_idle;
     std::deque<Request> queue;
     std::vector<Done> done;
+    std::vector<hipEvent_t> spare_events;   // recorded-and-waited events for reuse
     size_t in_flight = 0;
     int active = 0;
     bool stop = false;
@@ -114,7 +116,10 @@ void hca_server::run_worker(int w)
             in_flight += bytes;
             active++;
         }
-        // run the batch on this worker's stream
+        // run the batch on this worker's stream, after the work its requests'
+        // callers queued before submitting them
+        for (const Request &r : batch)
+            if (r.ready) (void)hipStreamWaitEvent(streams[w], r.ready, 0);
         std::vector<int32_t> status(batch.size(), HCA_OK);
         if (batch.size() == 1 && batch[0].d > kBatchDimMax) {
             const Request &r = batch[0];
@@ -151,6 +156,8 @@ void hca_server::run_worker(int w)
             for (size_t i = 0; i < batch.size(); i++) {
                 bytes += batch[i].bytes;
                 done.push_back({batch[i].tag, status[i], t});
+                // the clustering call synchronised the stream that waited on it
+                if (batch[i].ready) spare_events.push_back(batch[i].ready);
             }
             in_flight -= bytes;
             active--;
@@ -202,14 +209,32 @@ hca_status hca_server_create(hca_server **out, int32_t device, int32_t workers, 
 }
 
 hca_status hca_server_submit(hca_server *srv, const int32_t *points, int64_t n, int32_t d, double eps,
-                             int32_t min_pts, int32_t *labels, uint64_t tag)
+                             int32_t min_pts, int32_t *labels, uint64_t tag, void *after_stream)
 {
     if (!srv || n < 0 || d < 1 || d > 64 || min_pts < 1 || !(eps > 0.0)) return HCA_E_INVAL;
     if (n > 0 && (!points || !labels)) return HCA_E_INVAL;
+    hipEvent_t ev = nullptr;
+    {
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            if (!srv->spare_events.empty()) {
+                ev = srv->spare_events.back();
+                srv->spare_events.pop_back();
+            }
+        }
+        if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return HCA_E_DEVICE;
+        if (hipEventRecord(ev, (hipStream_t)after_stream) != hipSuccess) {
+            (void)hipEventDestroy(ev);
+            return HCA_E_DEVICE;
+        }
+    }
     {
         std::lock_guard<std::mutex> lk(srv->mu);
-        if (srv->stop) return HCA_E_INVAL;
-        srv->queue.push_back({points, n, d, eps, min_pts, labels, tag, footprint(n, d)});
+        if (srv->stop) {
+            if (ev) srv->spare_events.push_back(ev);
+            return HCA_E_INVAL;
+        }
+        srv->queue.push_back({points, n, d, eps, min_pts, labels, tag, footprint(n, d), ev});
     }
     srv->cv_work.notify_one();
     return HCA_OK;
@@ -251,6 +276,7 @@ void hca_server_destroy(hca_server *srv)
         hca_destroy(srv->ctx[i]);
         (void)hipStreamDestroy(srv->streams[i]);
     }
+    for (hipEvent_t e : srv->spare_events) (void)hipEventDestroy(e);
     delete srv;
 }
 

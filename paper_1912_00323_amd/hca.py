@@ -45,7 +45,8 @@ class Stats(ctypes.Structure):
                 ("dense_table", ctypes.c_int32), ("list_overflow", ctypes.c_int32),
                 ("tests_core", ctypes.c_int64), ("tests_merge", ctypes.c_int64),
                 ("tests_border", ctypes.c_int64), ("tests_intra", ctypes.c_int64),
-                ("packed_rows", ctypes.c_int32), ("key_axes", ctypes.c_int32)]
+                ("packed_rows", ctypes.c_int32), ("key_axes", ctypes.c_int32),
+                ("core_rest", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -88,7 +89,7 @@ def load_library(path: str | Path | None = None) -> ctypes.CDLL:
     lib.hca_cluster_sets.restype = ctypes.c_int
     lib.hca_server_create.argtypes = [ctypes.POINTER(vp), i32, i32, i64, i32]
     lib.hca_server_create.restype = ctypes.c_int
-    lib.hca_server_submit.argtypes = [vp, vp, i64, i32, dbl, i32, vp, ctypes.c_uint64]
+    lib.hca_server_submit.argtypes = [vp, vp, i64, i32, dbl, i32, vp, ctypes.c_uint64, vp]
     lib.hca_server_submit.restype = ctypes.c_int
     lib.hca_server_poll.argtypes = [vp, vp, vp, vp, i32]
     lib.hca_server_poll.restype = i32
@@ -107,6 +108,20 @@ def load_library(path: str | Path | None = None) -> ctypes.CDLL:
     if path is None:
         _lib = lib
     return lib
+
+
+def check_labels(t, n: int, device, what: str = "out"):
+    """A label array the library will write: a contiguous int32 CUDA tensor of
+    exactly n elements on the points' device (raises TypeError / ValueError)."""
+    import torch
+    if not getattr(t, "is_cuda", False) or getattr(t, "dtype", None) != torch.int32:
+        raise TypeError(f"{what} must be a CUDA int32 tensor")
+    if t.device != device:
+        raise ValueError(f"{what} is on {t.device}, the points on {device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if t.numel() != n:
+        raise ValueError(f"{what} has {t.numel()} elements, {n} are needed")
 
 
 def clock() -> float:
@@ -130,14 +145,21 @@ class Server:
         self._keep = {}
 
     def submit(self, points, eps: float, min_pts: int, labels, tag: int):
+        """Queue one request.  It runs after the work already queued on the
+        current torch stream of the points' device (so tensors written or
+        filled there are ready); its labels are final once poll() returns its
+        tag."""
         import torch
         if not (isinstance(points, torch.Tensor) and points.is_cuda and points.dtype == torch.int32
                 and points.dim() == 2 and points.is_contiguous()):
             raise TypeError("points must be a contiguous CUDA int32 tensor [n, d]")
         n, d = points.shape
+        check_labels(labels, n, points.device, "labels")
+        stream = torch.cuda.current_stream(points.device).cuda_stream
         self._keep[int(tag)] = (points, labels)
         st = self._lib.hca_server_submit(self._srv, ctypes.c_void_p(points.data_ptr()), n, d, float(eps),
-                                         int(min_pts), ctypes.c_void_p(labels.data_ptr()), int(tag))
+                                         int(min_pts), ctypes.c_void_p(labels.data_ptr()), int(tag),
+                                         ctypes.c_void_p(stream))
         if st != HCA_OK:
             self._keep.pop(int(tag), None)
             raise HcaError(st, "hca_server_submit failed")
@@ -244,6 +266,8 @@ class Context:
             raise TypeError("points must be int32 with shape [n, d]")
         pts = points.contiguous()
         n, d = pts.shape
+        if out is not None:
+            check_labels(out, n, pts.device)
         labels = out if out is not None else torch.empty(n, dtype=torch.int32, device=pts.device)
         core_t = torch.empty(n, dtype=torch.uint8, device=pts.device) if core else None
         st_obj = Stats() if stats else None
@@ -278,6 +302,8 @@ class Context:
         if int((r * dm).sum()) != pts.numel():
             raise ValueError("points does not hold sum(rows * dims) coordinates")
         total = int(r.sum())
+        if out is not None:
+            check_labels(out, total, pts.device)
         labels = out if out is not None else torch.empty(total, dtype=torch.int32, device=pts.device)
         self.set_stream(torch.cuda.current_stream(pts.device).cuda_stream)
         self._check(self._lib.hca_cluster_batch(

@@ -195,6 +195,55 @@ def test_group_prefix_ranges(ctx, prefix, monkeypatch):
             assert np.array_equal(gpu_labels(ctx, pts, f * 2 ** 12, mp), want), (prefix, "cubes", d, f, mp)
 
 
+def test_prefix_scan_far_groups(ctx, monkeypatch):
+    """4-D search groups whose prefix ranges hold groups far beyond the
+    stencil (gaps of about 50,000 units along the second half of the axes,
+    whose squares pass 2^31) while every tested pair is narrow: the list
+    build must drop them (no slab overflow from a wrapped box test) and the
+    labels equal the oracle's."""
+    monkeypatch.setenv("HCA_SEARCH", "group")
+    rng = np.random.default_rng(141)
+    parts = []
+    for k in range(10):
+        # wide along the prefix axes (0, 1), one or two groups along 2 and 3:
+        # each prefix range holds a few groups of every clump, under the
+        # 64-group limit above which the offsets are looked up instead
+        c = rng.integers(0, 300, size=(300, 4))
+        c[:, 2:] = rng.integers(0, 30, size=(300, 2))
+        c[:, 3] += 50_000 * k
+        parts.append(c)
+    pts = np.ascontiguousarray(np.concatenate(parts)[rng.permutation(3000)], np.int32)
+    for eps, mp in ((30.0, 4), (45.0, 8)):
+        print(f"[case] far prefix groups eps={eps} minPts={mp}", flush=True)
+        want = oracle.dbscan(pts, eps, mp)
+        got, st = gpu_labels(ctx, pts, eps, mp, stats=True)
+        assert np.array_equal(got, want), eps
+        assert st["wide"] == 0 and st["list_overflow"] == 0, st
+
+
+def test_unaligned_rows(ctx):
+    """Rows that start off their vector alignment (views one to three
+    elements into a tensor) are clustered like aligned ones, in 2-, 4- and
+    8-D."""
+    import torch
+    for d, cfg in ((2, 1), (4, None), (8, 3)):
+        if cfg is None:
+            rng = np.random.default_rng(151)
+            pts, eps, mp = quantise(make_blobs(rng, 5000, 4, 5, 0.03, 0.1), 12), 0.05 * 2 ** 12, 5
+        else:
+            w = make_config(cfg, n=5000)
+            pts, eps, mp = w.points, w.eps, w.min_pts
+        n = len(pts)
+        flat = torch.zeros(n * d + 3, dtype=torch.int32, device="cuda")
+        for off in (1, 2, 3):
+            view = flat[off:off + n * d].view(n, d)
+            view.copy_(torch.from_numpy(pts).cuda())
+            assert view.data_ptr() % 16 != 0 or d == 2
+            print(f"[case] unaligned rows d={d} offset={off}", flush=True)
+            got = ctx.cluster(view, eps, mp).cpu().numpy()
+            assert np.array_equal(got, oracle.dbscan(pts, eps, mp)), (d, off)
+
+
 def test_mixed_family(ctx):
     for seed in range(6):
         d = (2, 3, 4)[seed % 3]

@@ -67,6 +67,30 @@ def test_paper_shapes(ctx, n, d):
         check(ctx, pts, 0.025 * math.sqrt(2 * d) * f * 2 ** 10, mp, f"paper shape {n}x{d}")
 
 
+@pytest.mark.parametrize("budget", ["64", "256"])
+def test_second_core_pass(ctx, budget, monkeypatch):
+    """A candidate budget so small that the first core-marking pass leaves
+    many points undecided: the second pass walks them to the end, and labels
+    and core flags still equal the oracle's, on the paper's shapes and on
+    blobs at 9 to 64 axes."""
+    monkeypatch.setenv("HCA_HD_BUDGET", budget)
+    cases = [(blobs(40 + d, n, d, k=8, std=0.025), 0.025 * math.sqrt(2 * d) * f * 2 ** 10, mp, f"{n}x{d}")
+             for n, d in ((5045, 27), (3853, 54), (340, 16)) for f, mp in ((0.75, 5), (0.9, 10))]
+    cases += [(blobs(600 + d, 3000, d), 0.03 * math.sqrt(2 * d) * 0.8 * 2 ** 10, 9, f"blobs 3000x{d}")
+              for d in (9, 12, 64)]
+    rest = 0
+    for pts, eps, mp, tag in cases:
+        print(f"[case] second core pass budget={budget} {tag} eps={eps:.3f} minPts={mp}", flush=True)
+        want, counts, _ = oracle.dbscan(pts, eps, mp, details=True)
+        got, core, st = gpu_run(ctx, pts, eps, mp, core=True, stats=True)
+        assert np.array_equal(core.astype(bool), counts >= mp), tag
+        assert np.array_equal(got, want), tag
+        rest += st["core_rest"]
+        if len(pts) > 1000:
+            assert st["core_rest"] > 0, tag
+    assert rest > 0
+
+
 def test_stats_many_axes(ctx):
     pts = blobs(7, 4000, 20)
     eps, mp = 0.03 * math.sqrt(40) * 0.8 * 2 ** 10, 6

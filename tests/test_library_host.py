@@ -138,3 +138,36 @@ def test_bench_disagreement_measure():
     exact = oracle.dbscan(pts, 14.15, 1)
     approx = oracle.hca_grid(pts, 14.15, 1, rep_mode=1)
     assert bench.disagreement(exact, approx)["points_differing"] == 1
+
+
+def test_label_tensor_checks():
+    """Label arrays the library writes are checked before any C call: CUDA,
+    int32, on the points' device, contiguous and exactly n elements."""
+    import torch
+
+    class FakeCuda:                     # stands in for a CUDA tensor on a GPU-less host
+        is_cuda = True
+
+        def __init__(self, n, dtype=torch.int32, device="cuda:0", contiguous=True):
+            self.dtype, self.device, self._n, self._c = dtype, torch.device(device), n, contiguous
+
+        def is_contiguous(self):
+            return self._c
+
+        def numel(self):
+            return self._n
+
+    dev = torch.device("cuda:0")
+    hca.check_labels(FakeCuda(10), 10, dev)
+    with pytest.raises(TypeError):
+        hca.check_labels(torch.zeros(10, dtype=torch.int32), 10, dev)       # host tensor
+    with pytest.raises(TypeError):
+        hca.check_labels(FakeCuda(10, dtype=torch.int64), 10, dev)
+    with pytest.raises(ValueError):
+        hca.check_labels(FakeCuda(9), 10, dev)
+    with pytest.raises(ValueError):
+        hca.check_labels(FakeCuda(11), 10, dev)
+    with pytest.raises(ValueError):
+        hca.check_labels(FakeCuda(10, contiguous=False), 10, dev)
+    with pytest.raises(ValueError):
+        hca.check_labels(FakeCuda(10, device="cuda:1"), 10, dev)
