@@ -93,13 +93,40 @@ def measured_traffic(phase: str, workload: str):
     return e.get("bytes_per_call")
 
 
-def cpu_baseline(w, budget_s: float = 25.0) -> dict:
-    """The oracle on the host cores (its grid method up to 8 axes, the
+def cpu_model() -> str:
+    """The host CPU's model string (as lscpu prints it), from /proc/cpuinfo."""
+    try:
+        for line in Path("/proc/cpuinfo").read_text().splitlines():
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads() -> int:
+    return len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+
+
+def cpu_baseline(w, budget_s: float = 12.0) -> dict:
+    """The oracle on the host cores with OpenMP over all of them, and on one
+    thread; each leg takes about budget_s seconds."""
+    threads = host_threads()
+    multi = cpu_oracle_rate(w, threads, budget_s)
+    single = cpu_oracle_rate(w, 1, budget_s)
+    return {"value": multi["value"], "unit": "points/s", "cores": threads, "kind": "oracle",
+            "sample": multi["sample"],
+            "single_thread": {"value": single["value"], "unit": "points/s", "cores": 1,
+                              "sample": single["sample"]},
+            "cpu_model": cpu_model(), "host_threads": threads}
+
+
+def cpu_oracle_rate(w, threads: int, budget_s: float) -> dict:
+    """The oracle on `threads` host threads (its grid method up to 8 axes, the
     definition above that), on the whole workload when it finishes within
     the budget, else on the first m points of the input (which is in random
     order), m doubling from 20k while runs stay short."""
     import oracle
-    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     if w.d > 8:
         def run(p):
             oracle.dbscan(p, w.eps, w.min_pts, threads=threads)
@@ -130,7 +157,7 @@ def cpu_baseline(w, budget_s: float = 25.0) -> dict:
             f"the first {m} of the {w.n} points of {w.name} (same eps and minPts; lower density "
             f"than the whole set, so the per-point rate flatters the CPU)")
     return {"value": m / t, "unit": "points/s", "cores": threads, "kind": "oracle",
-            "sample": f"{what}; {method}, median of {len(times)} run(s)"}
+            "sample": f"{what}; {method}, {threads} thread(s), median of {len(times)} run(s)"}
 
 
 def main() -> int:
@@ -140,6 +167,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="2d")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-second", action="store_true",
+                    help="2d workload: skip the 8-D 500k workload that is measured beside it")
     ap.add_argument("--merge", choices=("exact", "representatives"), default="exact",
                     help="representatives: the paper's merge test on cube representatives alone "
                          "(approximate; cubes as search groups only)")
@@ -154,11 +183,44 @@ def main() -> int:
     if args.workload == "served":
         return bench_served(args)
 
-    import torch
-    from paper_1912_00323_amd import hca
     from paper_1912_00323_amd.datagen import make_config, make_high
 
     w = make_high(54, HIGH_N) if args.workload == "54d" else make_config(WORKLOADS[args.workload])
+    res = measure(w, args.steps, args.warmup, args.merge, not args.no_cpu_baseline)
+    line = {
+        "metric": METRIC,
+        "value": res["value"],
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "d": w.d, "eps": w.eps, "min_pts": w.min_pts,
+                   "fixed_point_bits": w.q, "parallelism": "single-gpu", "merge": args.merge},
+    }
+    line.update({k: v for k, v in res.items() if k not in ("value", "ms_per_step")})
+    if args.workload == "2d" and args.merge == "exact" and not args.no_second:
+        # the metric's second workload (8-D, 500k points), measured the same way
+        w8 = make_config(WORKLOADS["8d"])
+        r8 = measure(w8, args.steps, args.warmup, "exact", not args.no_cpu_baseline)
+        line["blobs8d_500k"] = {"config": {"workload": w8.name, "n": w8.n, "d": w8.d, "eps": w8.eps,
+                                           "min_pts": w8.min_pts, "fixed_point_bits": w8.q}, **r8}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def measure(w, steps: int, warmup: int, merge: str, with_cpu: bool) -> dict:
+    """Time `steps` whole clustering calls on workload w (points resident in
+    HBM) and derive the dominant phase's roofline; optionally time the CPU
+    oracle beside it."""
+    import torch
+    from paper_1912_00323_amd import hca
+
     dev = torch.device("cuda:0")
     pts = torch.from_numpy(w.points).to(dev)
     labels = torch.empty(w.n, dtype=torch.int32, device=dev)
@@ -166,12 +228,12 @@ def main() -> int:
     stream = torch.cuda.current_stream(dev)
     ctx.set_stream(stream.cuda_stream)
     approx = None
-    if args.merge == "representatives":
+    if merge == "representatives":
         exact_labels = ctx.cluster(pts, w.eps, w.min_pts).cpu().numpy()
         ctx.set_exact(False)
         approx = disagreement(exact_labels, ctx.cluster(pts, w.eps, w.min_pts).cpu().numpy())
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         ctx.cluster(pts, w.eps, w.min_pts, out=labels)
 
     # per-phase breakdown and pair-test counts (HIP events on the library's
@@ -180,7 +242,7 @@ def main() -> int:
     acc = {p: [] for p in hca.PHASES}
     tests = {k: [] for k in ALU_PHASES.values()}
     stats = None
-    for _ in range(max(3, min(args.steps, 10))):
+    for _ in range(max(3, min(steps, 10))):
         _, stats = ctx.cluster(pts, w.eps, w.min_pts, out=labels, stats=True)
         for p, v in ctx.phase_times().items():
             acc[p].append(v)
@@ -195,33 +257,40 @@ def main() -> int:
     dom_ms = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         ctx.cluster(pts, w.eps, w.min_pts, out=labels)
         dom_ms.append(ctx.phase_times()[dominant])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ctx.set_profiling(None)
-    ms_per_step = dt * 1e3 / args.steps
+    ms_per_step = dt * 1e3 / steps
     dom = statistics.mean(dom_ms)
     key_bytes = 8 if stats["key_bits"] > 32 or w.d > 8 else 4
     kernels = PHASE_KERNELS_HIGH if w.d > 8 else PHASE_KERNELS
 
+    def traffic(phase):
+        t = measured_traffic(phase, w.name)
+        return t, ("profiles/pmc_traffic.json, taken on the current kernel sources" if t is not None else
+                   "no PMC run of the current kernel sources for this phase and workload")
+
     def hbm_roofline(phase, ms):
         ab = algorithmic_bytes(phase, w.n, w.d, key_bytes, stats["sort_passes"], stats["n_cells"])
         achieved = ab / (ms * 1e-3) / 1e9
+        t, src = traffic(phase)
         return {"bound": "hbm", "phase": phase, "kernels": kernels[phase],
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(phase, w.name),
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": t, "traffic_source": src,
                 "algorithmic_bytes": ab, "phase_ms": round(ms, 4)}
 
     def alu_roofline(phase, ms):
         n_tests = statistics.mean(tests[ALU_PHASES[phase]])
         ops = 3.0 * w.d * n_tests                        # d sub + d mul + (d-1) add + compare
         achieved = ops / (ms * 1e-3) / 1e12
+        t, src = traffic(phase)
         return {"bound": "alu", "phase": phase, "kernels": kernels[phase],
                 "achieved": round(achieved, 4), "peak": round(ALU_PEAK_TOPS, 2),
                 "unit": "Tops/s (int32 lane-ops)", "frac": round(achieved / ALU_PEAK_TOPS, 5),
-                "traffic": measured_traffic(phase, w.name), "pair_tests": n_tests,
+                "traffic": t, "traffic_source": src, "pair_tests": n_tests,
                 "ops_per_test": 3 * w.d, "phase_ms": round(ms, 4)}
 
     if dominant in ALU_PHASES:
@@ -229,37 +298,24 @@ def main() -> int:
     elif dominant in HBM_PHASES:
         roofline = hbm_roofline(dominant, dom)
     else:
+        t, src = traffic(dominant)
         roofline = {"bound": "alu", "phase": dominant, "kernels": kernels[dominant],
                     "achieved": None, "peak": round(ALU_PEAK_TOPS, 2), "unit": "Tops/s (int32 lane-ops)",
-                    "frac": None, "traffic": measured_traffic(dominant, w.name), "phase_ms": round(dom, 4)}
-
-    line = {
-        "metric": METRIC,
-        "value": w.n * args.steps / dt,
-        "unit": "points/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+                    "frac": None, "traffic": t, "traffic_source": src, "phase_ms": round(dom, 4)}
+    out = {
+        "value": w.n * steps / dt,
         "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "i32",
-        "data": "synthetic",
-        "config": {"workload": w.name, "n": w.n, "d": w.d, "eps": w.eps, "min_pts": w.min_pts,
-                   "fixed_point_bits": w.q, "parallelism": "single-gpu", "merge": args.merge},
         "roofline": roofline,
         "roofline_binning_sort": hbm_roofline("sort", phase_ms["sort"]),
         "phase_ms": {p: round(v, 4) for p, v in phase_ms.items() if v > 0},
         "stats": stats,
     }
     if approx is not None:
-        line["approximate"] = approx
-    if not args.no_cpu_baseline and approx is None:
-        line["cpu_baseline"] = cpu_baseline(w)
-    print(json.dumps(line), flush=True)
+        out["approximate"] = approx
     ctx.close()
-    return 0
+    if with_cpu and approx is None:
+        out["cpu_baseline"] = cpu_baseline(w)
+    return out
 
 
 def disagreement(exact, approx) -> dict:
