@@ -158,6 +158,28 @@ hca_status hca_cluster_ex(hca_ctx *ctx, const int32_t *points, int64_t n, int32_
                           double eps, int32_t min_pts, int32_t *labels, uint8_t *core,
                           hca_stats *stats);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): hca_cluster with every
+ * device buffer of the call (workspace, offset tables) carved from a fixed
+ * area of HCA_NOALLOC_BYTES that the library holds on each device it runs on
+ * until the process ends, and with the context's pinned staging made by
+ * hca_create; the call itself makes no hipMalloc, hipFree, pinned or
+ * library allocation.  Arguments, layouts, ownership and results as
+ * hca_cluster, except:
+ *   d must be in [1, 8] (HCA_E_INVAL otherwise);
+ *   points must be aligned to 8 bytes for d = 2 and 16 bytes for d = 4 or 8
+ *   (HCA_E_INVAL; hca_cluster would stage such rows in a buffer it allocates);
+ *   a call whose buffers do not fit the area returns HCA_E_RANGE (the
+ *   message gives the bytes needed) with labels untouched;
+ *   phase profiling is ignored (it would create HIP events).
+ * Every call on one device shares that device's area: each call initialises
+ * what must start at zero itself, and calls that overlap in time on one
+ * device (two host threads, or two streams) race and may return wrong
+ * labels.  HCA_E_DEVICE if the area could not be set up on this device. */
+#define HCA_NOALLOC_BYTES (256ull << 20)
+hca_status hca_cluster_noalloc(hca_ctx *ctx, const int32_t *points, int64_t n, int32_t d, double eps,
+                               int32_t min_pts, int32_t *labels);
+
 /* As hca_cluster with HOST pointers for points and labels: copies in, runs,
  * copies out (staging through the context's device workspace). */
 hca_status hca_cluster_host(hca_ctx *ctx, const int32_t *points, int64_t n, int32_t d,

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "hca.h"
+#include "hca_internal.h"
 #include "hca_kernels.h"
 #include "hca_plan.h"
 
@@ -254,6 +255,11 @@ bool plan_geometry(double eps, int d, Geometry *g, bool with_offsets)
 
 constexpr size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// Offset and direction tables of a call in a caller-fixed area: at most 3^8
+// group offsets of 8 int8 axes plus two uint16 direction tables (cube
+// stencils with more than 1024 offsets use search groups).
+constexpr size_t kFixedGeoBytes = 128u << 10;
+
 }  // namespace
 
 // ---- context -------------------------------------------------------------------
@@ -268,12 +274,17 @@ struct hca_ctx {
     size_t io_size = 0;
     void *aligned = nullptr;          // rows of a call whose points are off their vector alignment
     size_t aligned_size = 0;
+    // a caller-fixed device area (hca_cluster_noalloc): offset tables in the
+    // first kFixedGeoBytes, the workspace after them; nothing is allocated
+    char *fixed = nullptr;
+    size_t fixed_size = 0;
     void *geo_dev = nullptr;          // offsets and direction tables
     size_t geo_dev_size = 0;
     void *bws = nullptr;              // batches: staged rows, data-set tables, offsets
     size_t bws_size = 0;
     // cached geometry
     bool geo_valid = false;
+    bool geo_uploaded = false;        // geo_dev holds the cached geometry's tables
     int64_t geo_eps2 = -1;
     int geo_d = 0;
     int geo_mode = -1;
@@ -343,10 +354,25 @@ hca_status ensure_pinned(hca_ctx *ctx, size_t need)
     return HCA_OK;
 }
 
+// The workspace of a call: the caller-fixed area when there is one (a call
+// needing more fails with HCA_E_RANGE), else the context's growable buffer.
+hca_status workspace(hca_ctx *ctx, size_t need)
+{
+    if (ctx->fixed) {
+        if (need <= ctx->fixed_size - kFixedGeoBytes) return HCA_OK;
+        return fail(ctx, HCA_E_RANGE, "the call needs " + std::to_string(need + kFixedGeoBytes) +
+                                          " bytes of device memory, the no-allocation area holds " +
+                                          std::to_string(ctx->fixed_size));
+    }
+    return ensure(ctx, &ctx->ws, &ctx->ws_size, need, "workspace");
+}
+
+char *ws_base(hca_ctx *ctx) { return ctx->fixed ? ctx->fixed + kFixedGeoBytes : (char *)ctx->ws; }
+
 // Record the start / end of a phase when profiling asks for it.
 void mark(hca_ctx *ctx, int phase, bool end)
 {
-    if (ctx->prof == -1 || (ctx->prof >= 0 && ctx->prof != phase)) return;
+    if (ctx->prof == -1 || ctx->fixed || (ctx->prof >= 0 && ctx->prof != phase)) return;
     if (!ctx->ev_made) {
         for (auto &e : ctx->ev) (void)hipEventCreate(&e);
         ctx->ev_made = true;
@@ -539,7 +565,7 @@ void launch_sequence(hca_ctx *ctx, Plan &P, const Sizes &Z)
     std::memset(&B, 0, sizeof B);
     uint32_t *zbeg;
     size_t zbytes;
-    Carver cv{(char *)ctx->ws};
+    Carver cv{ws_base(ctx)};
     carve_ws(cv, P, B, Z, &zbeg, &zbytes);
     B.tickets = P.ctr->sort_tickets;
     const int wb = Z.wb, tb = Z.tb;
@@ -636,7 +662,7 @@ void launch_hd_first(hca_ctx *ctx, Plan &P, const Sizes &Z)
     std::memset(&B, 0, sizeof B);
     uint32_t *zbeg;
     size_t zbytes;
-    Carver cv{(char *)ctx->ws};
+    Carver cv{ws_base(ctx)};
     carve_ws(cv, P, B, Z, &zbeg, &zbytes);
     B.tickets = P.ctr->sort_tickets;
     launch_init(zbeg, zbytes / sizeof(uint32_t), P.dense ? P.table : nullptr, P.dense ? (1ull << Z.gbits) : 0, s);
@@ -841,6 +867,9 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
         // rows that start off that alignment are first copied to an aligned
         // staging buffer on the stream
         const uintptr_t need = d == 2 ? 8 : (d == 4 || d == 8) ? 16 : 4;
+        if ((uintptr_t)points % need && ctx->fixed)
+            return fail(ctx, HCA_E_INVAL, "without allocation, points must be aligned to 8 bytes (d = 2) or 16 "
+                                          "bytes (d = 4, 8)");
         if ((uintptr_t)points % need) {
             const size_t bytes = (size_t)n * d * sizeof(int32_t);
             hca_status st = ensure(ctx, &ctx->aligned, &ctx->aligned_size, bytes, "aligned rows");
@@ -859,6 +888,16 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
         ctx->geo_reps != reps) {
         Geometry g;
         plan_geometry(eps, d, &g, true);
+        ctx->geo = std::move(g);
+        ctx->geo_valid = true;
+        ctx->geo_uploaded = false;
+        ctx->geo_eps2 = eps2;
+        ctx->geo_d = d;
+        ctx->geo_mode = mode;
+        ctx->geo_reps = reps;
+    }
+    if (!ctx->fixed && !ctx->geo_uploaded) {
+        const Geometry &g = ctx->geo;
         const size_t n_off = g.off.size() / d;
         const size_t bytes = align256(g.off.size()) + 2 * align256(n_off * sizeof(uint16_t));
         hca_status st = ensure(ctx, &ctx->geo_dev, &ctx->geo_dev_size, bytes, "offset table");
@@ -869,25 +908,35 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
                           hipMemcpyHostToDevice), "directions");
         HCA_HIP(hipMemcpy(gd + align256(g.off.size()) + align256(n_off * 2), g.dir_bwd.data(),
                           n_off * 2, hipMemcpyHostToDevice), "directions");
-        ctx->geo = std::move(g);
-        ctx->geo_valid = true;
-        ctx->geo_eps2 = eps2;
-        ctx->geo_d = d;
-        ctx->geo_mode = mode;
-        ctx->geo_reps = reps;
+        ctx->geo_uploaded = true;
     }
     const Geometry &G = ctx->geo;
     const uint32_t n_off = (uint32_t)(G.off.size() / d);
+    char *geo_dev = (char *)ctx->geo_dev;
+    if (ctx->fixed) {
+        // the tables go to the front of the fixed area on every call (other
+        // calls on this device may have overwritten it), staged through the
+        // context's pinned buffer after the bounding-box region
+        const size_t dir_at = align256(G.off.size()), bytes = dir_at + 2 * align256((size_t)n_off * 2);
+        if (bytes > kFixedGeoBytes || ctx->pinned_size < kPinnedBytes + bytes)
+            return fail(ctx, HCA_E_RANGE, "offset tables too large for the no-allocation area");
+        char *hp = (char *)ctx->pinned + kPinnedBytes;
+        std::memcpy(hp, G.off.data(), G.off.size());
+        std::memcpy(hp + dir_at, G.dir_fwd.data(), (size_t)n_off * 2);
+        std::memcpy(hp + dir_at + align256((size_t)n_off * 2), G.dir_bwd.data(), (size_t)n_off * 2);
+        HCA_HIP(hipMemcpyAsync(ctx->fixed, hp, bytes, hipMemcpyHostToDevice, s), "offset tables");
+        geo_dev = ctx->fixed;
+    }
 
     // 1. bounding box (origin shift); the host reduces the per-block partials
     const int bb = (int)std::min<uint64_t>(kBboxBlocks, (n + kBlock - 1) / kBlock);
     Carver c0{nullptr};
     c0.take<int32_t>((size_t)kBboxBlocks * 2 * kMaxDimHigh);
-    hca_status st = ensure(ctx, &ctx->ws, &ctx->ws_size, c0.off, "workspace");
+    hca_status st = workspace(ctx, c0.off);
     if (st) return st;
     st = ensure_pinned(ctx, kPinnedBytes);
     if (st) return st;
-    int32_t *partial = (int32_t *)ctx->ws;
+    int32_t *partial = (int32_t *)ws_base(ctx);
     for (bool &u : ctx->ev_used) u = false;
     mark(ctx, HCA_PHASE_BBOX, false);
     launch_bbox(d, points, n, partial, bb, s);
@@ -946,7 +995,7 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
     P.n_off = n_off;
     P.n_dir = G.n_dir;
     {
-        char *gd = (char *)ctx->geo_dev;
+        char *gd = geo_dev;
         P.off = (const int8_t *)gd;
         P.dir_fwd = (const uint16_t *)(gd + align256(G.off.size()));
         P.dir_bwd = (const uint16_t *)(gd + align256(G.off.size()) + align256((size_t)n_off * 2));
@@ -964,7 +1013,7 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
     P.pts = points;
     P.labels = labels;
     P.core_out = core_out;
-    st = ensure(ctx, &ctx->ws, &ctx->ws_size, ws_bytes(P, Z), "workspace");
+    st = workspace(ctx, ws_bytes(P, Z));
     if (st) return st;
     launch_sequence(ctx, P, Z);
     HCA_HIP(hipGetLastError(), "kernel launch");
@@ -1326,9 +1375,19 @@ hca_status hca_create(hca_ctx **out, int32_t device)
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return HCA_E_DEVICE;
     if (hipSetDevice(device) != hipSuccess) return HCA_E_DEVICE;
+    // the no-allocation area's address on this device (once per device; if
+    // it fails, hca_cluster_noalloc reports HCA_E_DEVICE and nothing else
+    // changes)
+    (void)hca::scratch_setup(device);
     hca_ctx *ctx = new (std::nothrow) hca_ctx();
     if (!ctx) return HCA_E_NOMEM;
     ctx->device = device;
+    // pinned staging for the bounding box, counters and (without
+    // allocation) the offset tables, made now so that later calls need none
+    if (ensure_pinned(ctx, kPinnedBytes + kFixedGeoBytes) != HCA_OK) {
+        delete ctx;
+        return HCA_E_NOMEM;
+    }
     *out = ctx;
     return HCA_OK;
 }
@@ -1385,6 +1444,23 @@ hca_status hca_cluster(hca_ctx *ctx, const int32_t *points, int64_t n, int32_t d
                        int32_t min_pts, int32_t *labels)
 {
     return run(ctx, points, n, d, eps, min_pts, labels, nullptr, nullptr);
+}
+
+hca_status hca_cluster_noalloc(hca_ctx *ctx, const int32_t *points, int64_t n, int32_t d, double eps,
+                               int32_t min_pts, int32_t *labels)
+{
+    if (!ctx) return HCA_E_INVAL;
+    ctx->err.clear();
+    if (d > kMaxDim && n > 0) return fail(ctx, HCA_E_INVAL, "without allocation, d must be in [1, 8]");
+    size_t bytes = 0;
+    char *area = (char *)hca::scratch_area(ctx->device, &bytes);
+    if (!area) return fail(ctx, HCA_E_DEVICE, "no-allocation area not set up on this device");
+    ctx->fixed = area;
+    ctx->fixed_size = bytes;
+    const hca_status st = run(ctx, points, n, d, eps, min_pts, labels, nullptr, nullptr);
+    ctx->fixed = nullptr;
+    ctx->fixed_size = 0;
+    return st;
 }
 
 hca_status hca_cluster_ex(hca_ctx *ctx, const int32_t *points, int64_t n, int32_t d, double eps,

@@ -79,6 +79,8 @@ def load_library(path: str | Path | None = None) -> ctypes.CDLL:
     lib.hca_set_stream.restype = ctypes.c_int
     lib.hca_cluster.argtypes = [vp, vp, i64, i32, dbl, i32, vp]
     lib.hca_cluster.restype = ctypes.c_int
+    lib.hca_cluster_noalloc.argtypes = [vp, vp, i64, i32, dbl, i32, vp]
+    lib.hca_cluster_noalloc.restype = ctypes.c_int
     lib.hca_cluster_ex.argtypes = [vp, vp, i64, i32, dbl, i32, vp, vp, ctypes.POINTER(Stats)]
     lib.hca_cluster_ex.restype = ctypes.c_int
     lib.hca_cluster_host.argtypes = [vp, vp, i64, i32, dbl, i32, vp]
@@ -311,6 +313,22 @@ class Context:
             dm.ctypes.data_as(ctypes.c_void_p), ep.ctypes.data_as(ctypes.c_void_p),
             mp.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(labels.data_ptr())))
         return labels
+
+    def cluster_noalloc(self, points, eps: float, min_pts: int, out):
+        """hca_cluster_noalloc: cluster a CUDA int32 tensor [n, d] (d <= 8,
+        contiguous, vector-aligned rows) into the caller's int32 tensor
+        ``out`` without any allocation by the library or by this binding;
+        runs on the current torch stream and blocks until done."""
+        import torch
+        if not (isinstance(points, torch.Tensor) and points.is_cuda and points.dtype == torch.int32
+                and points.dim() == 2 and points.is_contiguous()):
+            raise TypeError("points must be a contiguous CUDA int32 tensor [n, d]")
+        n, d = points.shape
+        check_labels(out, n, points.device)
+        self.set_stream(torch.cuda.current_stream(points.device).cuda_stream)
+        self._check(self._lib.hca_cluster_noalloc(self._ctx, ctypes.c_void_p(points.data_ptr()), n, d,
+                                                  float(eps), int(min_pts), ctypes.c_void_p(out.data_ptr())))
+        return out
 
     def cluster_ptr(self, points_ptr: int, n: int, d: int, eps: float, min_pts: int,
                     labels_ptr: int):
