@@ -170,7 +170,9 @@ hca_status hca_cluster_ex(hca_ctx *ctx, const int32_t *points, int64_t n, int32_
  *   points must be aligned to 8 bytes for d = 2 and 16 bytes for d = 4 or 8
  *   (HCA_E_INVAL; hca_cluster would stage such rows in a buffer it allocates);
  *   a call whose buffers do not fit the area returns HCA_E_RANGE (the
- *   message gives the bytes needed) with labels untouched;
+ *   message gives the bytes needed) with labels untouched; a call takes
+ *   about 256 bytes per point in 2-D and 900 in 8-D, so the area holds about
+ *   1.0M points in 2-D and 0.29M in 8-D;
  *   phase profiling is ignored (it would create HIP events).
  * Every call on one device shares that device's area: each call initialises
  * what must start at zero itself, and calls that overlap in time on one

@@ -41,11 +41,11 @@ def test_noalloc_matches_hca_cluster(hca_mod):
             assert np.array_equal(got, want), tag
         assert np.array_equal(got, oracle.dbscan(cases[1][1].points, cases[1][1].eps, cases[1][1].min_pts))
         # 8-D (search groups, neighbour lists), then 3-D cubes with lists, then 1-D
-        w8 = make_config(3, n=200_000)
+        w8 = make_config(3, n=100_000)
         rng = np.random.default_rng(161)
         p3 = quantise(make_blobs(rng, 20000, 3, 6, 0.02, 0.1), 12)
         p1 = quantise(make_blobs(rng, 5000, 1, 4, 0.02, 0.1), 12)
-        for tag, pts, eps, mp in (("8-D 200k", w8.points, w8.eps, w8.min_pts),
+        for tag, pts, eps, mp in (("8-D 100k", w8.points, w8.eps, w8.min_pts),
                                   ("3-D 20k", p3, 0.015 * 2 ** 12, 6), ("1-D 5k", p1, 0.004 * 2 ** 12, 4)):
             print(f"[case] noalloc {tag}", flush=True)
             got, want = run_both(hca, ctx, pts, eps, mp)
