@@ -105,8 +105,9 @@ typedef struct {
     int64_t tests_intra;      /* inside search groups (m > 1) */
     int32_t packed_rows;      /* d > 8: 1 if candidate rows were packed as int16 pairs */
     int32_t key_axes;         /* d > 8: axes spanned by the search-group key (0 for d <= 8) */
-    int64_t core_rest;        /* d > 8: points left undecided by the first core-marking pass
-                               * (candidate budget spent) and walked by the second */
+    int64_t core_rest;        /* points left undecided by the first core-marking pass (its
+                               * candidate budget spent) and walked by a second: d > 8, and
+                               * d <= 2 with one lane per point of a sparse cube */
 } hca_stats;
 
 /* Exact floor(eps^2) of a double (no device needed).  HCA_E_INVAL if eps is

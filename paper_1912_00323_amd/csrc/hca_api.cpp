@@ -186,6 +186,30 @@ uint32_t env_hd_budget()
     return (uint32_t)std::min<long>(std::max<long>(64, std::atol(e)), 1l << 30);
 }
 
+// HCA_CORE_LANES=0: cube-mode core marking with a wave per cube even for
+// d <= 2; HCA_CORE_BUDGET=k: candidates per lane before a point is deferred
+bool env_core_lanes()
+{
+    const char *e = std::getenv("HCA_CORE_LANES");
+    return !(e && !std::strcmp(e, "0"));
+}
+
+uint32_t env_core_budget()
+{
+    const char *e = std::getenv("HCA_CORE_BUDGET");
+    if (!e) return kCoreLaneBudget;
+    return (uint32_t)std::min<long>(std::max<long>(1, std::atol(e)), 1l << 30);
+}
+
+// Lane walk for core marking: cubes as search groups, no neighbour lists,
+// one or two axes, offsets within kColR.
+void plan_core_lanes(Plan &P, int32_t radius)
+{
+    P.radius = (uint32_t)std::max(0, radius);
+    P.core_budget = env_core_budget();
+    P.core_lanes = P.m == 1 && P.list_w == 0 && !P.hd && P.d <= 2 && radius <= kColR && env_core_lanes() ? 1u : 0u;
+}
+
 bool env_reps()
 {
     const char *e = std::getenv("HCA_REPS");
@@ -516,6 +540,10 @@ void carve_ws(Carver &cv, Plan &P, SortBuffers &B, const Sizes &Z, uint32_t **ze
         P.pend = cv.take<uint32_t>((size_t)1 << Z.pbits);
     }
     P.work = cv.take<uint32_t>((size_t)2 * P.work_cap);
+    // the lane walk's point lists live in the worklist, unused until merging
+    const bool lanes = P.core_lanes && (uint64_t)n <= P.work_cap;
+    P.core_list = lanes ? P.work : nullptr;
+    P.core_defer = lanes ? P.work + n : nullptr;
     P.owner = cv.take<uint32_t>(n);
     P.cmin = cv.take<uint32_t>(n);
     P.minmem = cv.take<uint32_t>(n);
@@ -642,7 +670,7 @@ void fill_stats(hca_ctx *ctx, const Plan &P, hca_stats *stats)
         stats->list_overflow = (int32_t)hc->nbr_overflow;
     stats->packed_rows = P.spts16 != nullptr ? 1 : 0;
     stats->key_axes = P.hd ? (int32_t)P.kd : 0;
-    stats->core_rest = P.hd ? (int64_t)hc->hd_left : 0;
+    stats->core_rest = P.hd ? (int64_t)hc->hd_left : P.core_list ? (int64_t)hc->n_defer : 0;
 }
 
 // ---- more than kMaxDim axes ----------------------------------------------------
@@ -1007,6 +1035,7 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
         P.rep_only = 1;
     }
     P.list_w = P.m == 1 ? cube_list_width(d, G.radius, n_off) : 0;
+    plan_core_lanes(P, G.radius);
     Sizes Z;
     plan_sizes(P, gbits, stats != nullptr && ctx->prof != -1, stats != nullptr, &Z);
     plan_prefix(P, gbits, &Z);
@@ -1272,6 +1301,7 @@ hca_status run_sets(hca_ctx *ctx, const BatchSet *sets, int32_t nseg)
         int32_t rmax = 0;
         for (int32_t v : g.radius) rmax = std::max(rmax, v);
         P.list_w = cube_list_width(d, rmax, P.n_off);
+        plan_core_lanes(P, rmax);
         plan_sizes(P, P.key_bits, false, false, &g.Z);
         plan_prefix(P, P.key_bits, &g.Z);
         ws_need = std::max(ws_need, ws_bytes(P, g.Z));

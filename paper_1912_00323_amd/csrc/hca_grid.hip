@@ -786,14 +786,14 @@ __device__ __forceinline__ uint32_t candidate_pos(uint32_t c, uint32_t total, co
 // g and its neighbour groups, until each reaches minPts (then its bit is
 // set).  Returns the updated mask.  With P.rec and a chunk position pc
 // (not kNone), the first kRec neighbours found of point pc + k are recorded
-// for merging.
+// for merging; with qpos, those of point qpos[k] (wave-uniform).
 template <int D, bool WIDE>
 __device__ __forceinline__ uint32_t count_walk(const Plan &P, uint32_t g, uint64_t gkey, const Pt<D> *pp,
                                                uint32_t done, uint32_t *cnt, uint32_t *s_beg,
                                                uint32_t *s_pre, uint32_t &lt, const Geo<D> &geo,
-                                               uint32_t pc = kNone)
+                                               uint32_t pc = kNone, const uint32_t *qpos = nullptr)
 {
-    const bool record = P.rec != nullptr && pc != kNone;
+    const bool record = P.rec != nullptr && (pc != kNone || qpos != nullptr);
     const uint32_t l = lane_id();
     const uint32_t minpts = geo.min_pts;
     const uint32_t all = (1u << kPch) - 1u;
@@ -821,7 +821,7 @@ __device__ __forceinline__ uint32_t count_walk(const Plan &P, uint32_t g, uint64
                 const uint64_t hm = __ballot(hit);
                 if (record && hm && cnt[k] < (uint32_t)kRec) {
                     const uint32_t r = cnt[k] + __popcll(hm & __lanemask_lt());
-                    if (hit && r < (uint32_t)kRec) P.rec[(uint64_t)(pc + k) * kRec + r] = pos;
+                    if (hit && r < (uint32_t)kRec) P.rec[(uint64_t)(qpos ? qpos[k] : pc + k) * kRec + r] = pos;
                 }
                 cnt[k] += __popcll(hm);
                 if (cnt[k] >= minpts) done |= 1u << k;
@@ -998,6 +998,292 @@ __global__ __launch_bounds__(kBlock, 6) void k_core_chunks(Plan P)
             }
             pend &= ~same;
         }
+    }
+    flush_tests(P, kTestsCore, lt);
+}
+
+
+// ---------------------------------------------------------------------------
+// Core marking in cube mode for d <= 2 (no neighbour lists), one lane per
+// point.  Most points of such data sit in cubes holding at least minPts
+// points, which are core outright (Definition 2 with the same-cube
+// guarantee); the others are spread thinly over many small cubes, where a
+// wave per cube would leave most lanes idle.
+//   1. k_core_flat, one thread per sorted point: points of dense cubes are
+//      core (a cube's first point writes its tallies); the others are
+//      appended to core_list (runs of sorted positions).
+//   2. k_core_lanes, one lane per listed point: it looks up every cube that
+//      can hold a point within eps of it at once.  Its own cube counts whole
+//      without tests.  Per offset along axis 0 the others are one run of
+//      consecutive keys along the last axis, i.e. one contiguous range of
+//      sorted points; the lane tests those ranges (nearest column first)
+//      until it has minPts neighbours, recording the first kRec.  A lane that
+//      tests core_budget candidates without deciding leaves its point to 3.
+//   3. k_core_deferred: the points left, one per block of 256 lanes.
+// ---------------------------------------------------------------------------
+constexpr int kLaneBatch = 8;     // candidates a lane loads before testing them
+
+// Blocks of 1024 threads: the list grows by one atomic per block (a counter
+// that every block hits costs more than the rest of the pass when it is
+// taken per wave).
+constexpr int kFlatBlock = 1024;
+
+template <int D>
+__global__ __launch_bounds__(kFlatBlock) void k_core_flat(Plan P)
+{
+    __shared__ uint32_t s_cnt[kFlatBlock / kWave];
+    __shared__ uint32_t s_base;
+    const uint32_t n = P.n, l = lane_id(), w = threadIdx.x / kWave;
+    const uint32_t q = blockIdx.x * kFlatBlock + threadIdx.x;
+    bool sparse = false;
+    if (q < n) {
+        const uint32_t c = P.cell_of[q];
+        const uint32_t a = P.cell_start[c], b = P.cell_start[c + 1];
+        const uint32_t minpts = P.nseg ? P.seg[(uint32_t)(P.group_key[c] >> P.seg_shift)].min_pts
+                                       : (uint32_t)P.min_pts;
+        if (b - a >= minpts) {
+            P.core[q] = 1;
+            if (P.rec) P.nrec[q] = 0;
+            if (q == a) {
+                st_agent32(P.ncore + c, b - a);
+                st_agent32(P.cmin + c, P.sidx[a]);
+            }
+        } else {
+            sparse = true;
+        }
+    }
+    const uint64_t m = __ballot(sparse);
+    if (l == 0) s_cnt[w] = (uint32_t)__popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tot = 0;
+        for (int i = 0; i < kFlatBlock / kWave; i++) {
+            const uint32_t c = s_cnt[i];
+            s_cnt[i] = tot;
+            tot += c;
+        }
+        s_base = tot ? atomicAdd(&P.ctr->n_sparse, tot) : 0u;
+    }
+    __syncthreads();
+    if (sparse) P.core_list[s_base + s_cnt[w] + __popcll(m & __lanemask_lt())] = q;
+}
+
+// Gap between a point at offset u in [0, s) of its cube and the cube at
+// offset dlt along the same axis.
+__device__ __forceinline__ int64_t cube_gap(int dlt, int64_t u, int64_t s)
+{
+    return dlt > 0 ? (int64_t)dlt * s - u : (dlt < 0 ? u + (int64_t)(-dlt - 1) * s + 1 : 0);
+}
+
+// The neighbourhood of sorted point q as ranges of sorted points: its own
+// cube [a0, b0) (every point within eps), then per offset along axis 0
+// (nearest first: 0, -1, 1, -2, 2; one in 1-D) the run of cubes along the
+// last axis that can hold a point within eps of q (column 0 split around the
+// own cube).  Cubes of a column are consecutive in key order, so the ones
+// found form one run of cube ids.  All lookups are issued at once.
+template <int D>
+struct Nbhd {
+    static constexpr int W = 2 * kColR + 1;
+    static constexpr int NC = D == 2 ? W : 1;     // columns
+    static constexpr int NR = NC + 1;             // ranges
+    Pt<D> p;
+    Geo<D> geo;
+    uint32_t c, a0, b0;
+    uint32_t pre[NR + 1];                         // candidates before range r
+    uint32_t rb[NR];                              // first sorted position of range r
+};
+
+template <int D>
+__device__ __forceinline__ void neighbourhood(const Plan &P, uint32_t q, Nbhd<D> &nb)
+{
+    constexpr int W = Nbhd<D>::W, NC = Nbhd<D>::NC, LA = D - 1;
+    const int R = (int)P.radius;
+    nb.c = P.cell_of[q];
+    const uint64_t gkey = P.group_key[nb.c];
+    nb.geo = cube_geo<D>(P, gkey);
+    nb.p = load_pt<D>(P.spts, q);
+    int64_t gc[D], u[D];
+#pragma unroll
+    for (int k = 0; k < D; k++) {
+        gc[k] = (int64_t)((gkey >> P.goff[k]) & ((1ull << P.gw[k]) - 1ull));
+        u[k] = (int64_t)nb.p.x[k] - ((int64_t)nb.geo.origin[k] + gc[k] * nb.geo.gside);
+    }
+    uint64_t keys[NC * W];
+#pragma unroll
+    for (int ci = 0; ci < NC; ci++) {
+        const int dx = ((ci + 1) / 2) * ((ci & 1) ? -1 : 1);
+        bool col = dx >= -R && dx <= R;
+        int64_t g0 = 0;
+        if constexpr (D == 2) {
+            const int64_t cx = gc[0] + dx;
+            col = col && cx >= 0 && cx <= (int64_t)P.gmax[0];
+            g0 = cube_gap(dx, u[0], nb.geo.gside);
+            col = col && g0 * g0 <= nb.geo.eps2;
+        }
+#pragma unroll
+        for (int j = 0; j < W; j++) {
+            const int dy = j - kColR;
+            const int64_t cy = gc[LA] + dy;
+            const int64_t g1 = cube_gap(dy, u[LA], nb.geo.gside);
+            const bool ok = col && dy >= -R && dy <= R && !(dx == 0 && dy == 0) && cy >= 0 &&
+                            cy <= (int64_t)P.gmax[LA] && g0 * g0 + g1 * g1 <= nb.geo.eps2;
+            uint64_t k2 = gkey + ((uint64_t)(int64_t)dy << P.goff[LA]);
+            if (D == 2) k2 += (uint64_t)(int64_t)dx << P.goff[0];
+            keys[ci * W + j] = ok ? k2 : ~0ull;
+        }
+    }
+    uint32_t ids[NC * W];
+    group_lookup_n<NC * W>(P, keys, ids);
+    uint32_t re[NC + 1];
+#pragma unroll
+    for (int ci = 0; ci < NC; ci++) {
+        uint32_t lo = kNone, hi = 0, lo2 = kNone, hi2 = 0;
+#pragma unroll
+        for (int j = 0; j < W; j++) {
+            const uint32_t id = ids[ci * W + j];
+            if (id == kNone) continue;
+            if (ci == 0 && j > kColR) {
+                lo2 = min(lo2, id);
+                hi2 = max(hi2, id);
+            } else {
+                lo = min(lo, id);
+                hi = max(hi, id);
+            }
+        }
+        const int r = ci == 0 ? 0 : ci + 1;
+        nb.rb[r] = lo != kNone ? P.group_start[lo] : 0u;
+        re[r] = lo != kNone ? P.group_start[hi + 1] : 0u;
+        if (ci == 0) {
+            nb.rb[1] = lo2 != kNone ? P.group_start[lo2] : 0u;
+            re[1] = lo2 != kNone ? P.group_start[hi2 + 1] : 0u;
+        }
+    }
+    nb.a0 = P.group_start[nb.c];
+    nb.b0 = P.group_start[nb.c + 1];
+    nb.pre[0] = 0;
+#pragma unroll
+    for (int r = 0; r < NC + 1; r++) nb.pre[r + 1] = nb.pre[r] + (re[r] - nb.rb[r]);
+}
+
+// Sorted position of candidate v (< the total) of a neighbourhood.
+template <int D>
+__device__ __forceinline__ uint32_t nbhd_pos(const Nbhd<D> &nb, uint32_t v)
+{
+    uint32_t ps = 0;
+#pragma unroll
+    for (int r = 0; r < Nbhd<D>::NR; r++)
+        if (v >= nb.pre[r]) ps = nb.rb[r] + (v - nb.pre[r]);
+    return ps;
+}
+
+// The outcome of core marking for sorted point q of cube c with cnt
+// neighbours (all of them recorded when cnt <= kRec).
+__device__ __forceinline__ void core_result(const Plan &P, uint32_t q, uint32_t c, uint32_t cnt, uint32_t minpts)
+{
+    const bool core = cnt >= minpts;
+    P.core[q] = core;
+    if (P.rec) P.nrec[q] = (uint8_t)rec_count(cnt);
+    if (core) {
+        atomicAdd(P.ncore + c, 1u);
+        atomicMin(P.cmin + c, P.sidx[q]);
+    }
+}
+
+template <int D, bool WIDE>
+__global__ __launch_bounds__(kBlock) void k_core_lanes(Plan P)
+{
+    static_assert(D <= 2, "lane walk for one or two axes");
+    const uint32_t ns = ld_agent32(&P.ctr->n_sparse);
+    const uint32_t stride = gridDim.x * kBlock;
+    const uint32_t l = lane_id();
+    uint32_t lt = 0;
+    // wave-uniform loop, so that the points a wave defers keep their order
+    for (uint32_t base = (blockIdx.x * kBlock + threadIdx.x) & ~(uint32_t)(kWave - 1); base < ns;
+         base += stride) {
+        const uint32_t i = base + l;
+        bool defer = false;
+        uint32_t q = kNone;
+        if (i < ns) {
+            q = P.core_list[i];
+            Nbhd<D> nb;
+            neighbourhood<D>(P, q, nb);
+            // the own cube counts whole (recorded first), then the ranges are
+            // tested in batches
+            uint32_t cnt = nb.b0 - nb.a0;
+            if (P.rec)
+                for (uint32_t t = 0; t < cnt && t < (uint32_t)kRec; t++) P.rec[(uint64_t)q * kRec + t] = nb.a0 + t;
+            const uint32_t total = nb.pre[Nbhd<D>::NR], minpts = nb.geo.min_pts, budget = P.core_budget;
+            uint32_t v = 0;
+            for (; v < total && cnt < minpts && v < budget; v += kLaneBatch) {
+                uint32_t pos[kLaneBatch];
+                Pt<D> o[kLaneBatch];
+#pragma unroll
+                for (int b = 0; b < kLaneBatch; b++) {
+                    pos[b] = nbhd_pos<D>(nb, min(v + (uint32_t)b, total - 1u));
+                    o[b] = load_pt<D>(P.spts, pos[b]);
+                }
+#pragma unroll
+                for (int b = 0; b < kLaneBatch; b++) {
+                    if (v + (uint32_t)b >= total) break;
+                    lt++;
+                    if (within<D, WIDE>(nb.p, o[b], nb.geo.eps2)) {
+                        if (P.rec && cnt < (uint32_t)kRec) P.rec[(uint64_t)q * kRec + cnt] = pos[b];
+                        cnt++;
+                    }
+                }
+            }
+            // budget spent: a whole block decides this point
+            defer = cnt < minpts && v < total;
+            if (!defer) core_result(P, q, nb.c, cnt, minpts);
+        }
+        const uint64_t m = __ballot(defer);
+        if (m) {
+            const uint32_t lead = (uint32_t)__ffsll((unsigned long long)m) - 1u;
+            uint32_t at = 0;
+            if (l == lead) at = atomicAdd(&P.ctr->n_defer, (uint32_t)__popcll(m));
+            at = __shfl(at, lead);
+            if (defer) P.core_defer[at + __popcll(m & __lanemask_lt())] = q;
+        }
+    }
+    flush_tests(P, kTestsCore, lt);
+}
+
+// The deferred points, one per block: the block's 256 lanes test the
+// neighbourhood's candidates side by side, counting (and numbering the
+// recorded neighbours) with an LDS atomic, until minPts or the end.
+template <int D, bool WIDE>
+__global__ __launch_bounds__(kBlock) void k_core_deferred(Plan P)
+{
+    __shared__ Nbhd<D> s_nb;
+    __shared__ uint32_t s_cnt;
+    const uint32_t nd = ld_agent32(&P.ctr->n_defer);
+    uint32_t lt = 0;
+    for (uint32_t i = blockIdx.x; i < nd; i += gridDim.x) {
+        const uint32_t q = P.core_defer[i];
+        if (threadIdx.x == 0) {
+            Nbhd<D> nb;
+            neighbourhood<D>(P, q, nb);
+            s_nb = nb;
+            const uint32_t own = nb.b0 - nb.a0;
+            if (P.rec)
+                for (uint32_t t = 0; t < own && t < (uint32_t)kRec; t++) P.rec[(uint64_t)q * kRec + t] = nb.a0 + t;
+            s_cnt = own;
+        }
+        __syncthreads();
+        const uint32_t total = s_nb.pre[Nbhd<D>::NR], minpts = s_nb.geo.min_pts;
+        const Pt<D> p = s_nb.p;
+        for (uint32_t v = threadIdx.x; v < total; v += kBlock) {
+            if (__hip_atomic_load(&s_cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= minpts) break;
+            const uint32_t pos = nbhd_pos<D>(s_nb, v);
+            lt++;
+            if (within<D, WIDE>(p, load_pt<D>(P.spts, pos), s_nb.geo.eps2)) {
+                const uint32_t slot = atomicAdd(&s_cnt, 1u);
+                if (P.rec && slot < (uint32_t)kRec) P.rec[(uint64_t)q * kRec + slot] = pos;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) core_result(P, q, s_nb.c, s_cnt, minpts);
+        __syncthreads();
     }
     flush_tests(P, kTestsCore, lt);
 }
@@ -2189,8 +2475,25 @@ void launch_lists_back(const Plan &P, int blocks, hipStream_t s)
     hipLaunchKernelGGL(k_nbr_back, dim3(blocks), dim3(kBlock), 0, s, P);
 }
 
+// Cube mode for d <= 2 without lists: the lane walk (when the host enabled it
+// through core_list); otherwise one wave per cube or per chunk of points.
 void launch_core(const Plan &P, int blocks, hipStream_t s)
 {
+    if (P.m == 1 && P.core_list) {
+        const int fb = (int)std::max<uint64_t>(1, (P.n + kFlatBlock - 1) / kFlatBlock);
+        switch (P.d * 2 + (P.wide ? 1 : 0)) {
+#define HCA_CORE_LANES(DD, WW)                                                                \
+    hipLaunchKernelGGL(k_core_flat<DD>, dim3(fb), dim3(kFlatBlock), 0, s, P);                 \
+    hipLaunchKernelGGL((k_core_lanes<DD, WW>), dim3(blocks), dim3(kBlock), 0, s, P);           \
+    hipLaunchKernelGGL((k_core_deferred<DD, WW>), dim3(blocks), dim3(kBlock), 0, s, P);
+        case 2: HCA_CORE_LANES(1, false) break;
+        case 3: HCA_CORE_LANES(1, true) break;
+        case 4: HCA_CORE_LANES(2, false) break;
+        case 5: HCA_CORE_LANES(2, true) break;
+#undef HCA_CORE_LANES
+        }
+        return;
+    }
     if (P.m > 1) HCA_DISPATCH_DW(k_core_chunks, P, blocks, s);
     else HCA_DISPATCH_DW(k_core, P, blocks, s);
 }

@@ -14,6 +14,11 @@ constexpr int kRec = 16;                       // neighbours recorded per point 
 // before it is left to the second pass (which walks chunks of such points
 // only); the host may lower it per call.
 constexpr uint32_t kHdCoreBudget = 16384;
+// Cube mode for d <= 2: core marking with one lane per point of a sparse cube
+// when the cube-offset radius is at most kColR, each lane testing at most
+// kCoreLaneBudget candidates before a wave-wide walk takes its point over.
+constexpr int kColR = 2;
+constexpr uint32_t kCoreLaneBudget = 64;
 
 // nrec value of a point that found c neighbours: c when all were recorded
 __host__ __device__ constexpr uint32_t rec_count(uint32_t c) { return c <= (uint32_t)kRec ? c : kRec + 1; }
@@ -76,7 +81,9 @@ struct Counters {
     uint32_t nbr_ticket;        // tiles of the backward-list scan
     uint32_t hd_left;           // more than kMaxDim axes: points left undecided by the first core pass
     uint32_t n_blist;           // non-core points left for the border walk (blist)
-    uint32_t pad[6];
+    uint32_t n_sparse;          // cube-mode points of cubes with fewer than minPts points (core_list)
+    uint32_t n_defer;           // of those, points whose candidate budget ran out (core_defer)
+    uint32_t pad[4];
     uint32_t work_count[kWorkRegions * kCounterStride];   // region r at [r * kCounterStride]
     // pair tests executed, per phase (core, merge, border), spread over
     // kWorkRegions lines of eight 64-bit words; counted only on request
@@ -143,6 +150,15 @@ struct Plan {
     uint32_t *blist;            // [n] non-core points whose neighbours were not all recorded (with rec)
     uint32_t hd16;              // packed rows wanted (hd, every span below 2^15 and 32-bit sums)
     uint32_t *spts16;           // [n][sd / 2] sorted points less the origin as packed int16 pairs, or null
+    // cube mode, one lane per point: the largest cube-offset radius R of the
+    // call (of any data set in a batch), the candidates a lane tests before
+    // it leaves the point to a wave-wide walk, and the two point lists
+    // (carved from the worklist, which is free until merging)
+    uint32_t radius;
+    uint32_t core_lanes;        // use the lane walk (carves core_list and core_defer)
+    uint32_t core_budget;
+    uint32_t *core_list;        // [n] sorted positions of points of sparse cubes
+    uint32_t *core_defer;       // [n] the points left to the wave-wide walk
     // neighbour search over groups: offsets in [-R, R]^d, self first
     uint32_t n_off;
     const int8_t *off;          // [n_off][d]

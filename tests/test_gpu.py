@@ -244,6 +244,41 @@ def test_unaligned_rows(ctx):
             assert np.array_equal(got, oracle.dbscan(pts, eps, mp)), (d, off)
 
 
+@pytest.mark.parametrize("lanes,budget", [("1", "1"), ("1", "24"), ("1", "512"), ("0", "512")])
+def test_core_lane_walk(ctx, lanes, budget, monkeypatch):
+    """Cube-mode core marking for one and two axes: one lane per point of a
+    sparse cube (budgets so small that most points go on to the wave-wide
+    walk, and the default), or a wave per cube; the same labels and core
+    flags as the oracle, also through the batch path."""
+    monkeypatch.setenv("HCA_CORE_LANES", lanes)
+    monkeypatch.setenv("HCA_CORE_BUDGET", budget)
+    for d in (1, 2):
+        rng = np.random.default_rng(170 + d)
+        pts = quantise(make_blobs(rng, 30000, d, 8, 0.01, 0.2), 14)
+        for f, mp in ((0.002, 4), (0.004, 8), (0.01, 20)):
+            eps = f * 2 ** 14
+            print(f"[case] core lanes={lanes} budget={budget} d={d} eps={eps} minPts={mp}", flush=True)
+            want, counts, _ = oracle.dbscan(pts, eps, mp, details=True)
+            got, core, st = gpu_labels(ctx, pts, eps, mp, core=True, stats=True)
+            assert np.array_equal(core.astype(bool), counts >= mp), (d, f, mp)
+            assert np.array_equal(got, want), (d, f, mp)
+            if lanes == "1" and budget == "1" and d == 2 and f == 0.004:
+                assert st["core_rest"] > 0, st
+    w = make_config(2, n=300_000)
+    print(f"[case] core lanes={lanes} budget={budget} 2-D 300k", flush=True)
+    assert np.array_equal(gpu_labels(ctx, w.points, w.eps, w.min_pts),
+                          oracle.hca_grid(w.points, w.eps, w.min_pts, threads=0))
+    import torch
+    jobs = [make_mixed(1200 + k, 4000 + 3000 * k, 2) for k in range(4)]
+    flat = torch.from_numpy(np.concatenate([j.points.ravel() for j in jobs]).astype(np.int32)).cuda()
+    got = ctx.cluster_batch(flat, [j.n for j in jobs], [j.d for j in jobs], [j.eps for j in jobs],
+                            [j.min_pts for j in jobs]).cpu().numpy()
+    at = 0
+    for j in jobs:
+        assert np.array_equal(got[at:at + j.n], oracle.dbscan(j.points, j.eps, j.min_pts)), j.name
+        at += j.n
+
+
 def test_mixed_family(ctx):
     for seed in range(6):
         d = (2, 3, 4)[seed % 3]
