@@ -541,14 +541,19 @@ void carve_ws(Carver &cv, Plan &P, SortBuffers &B, const Sizes &Z, uint32_t **ze
     }
     P.work = cv.take<uint32_t>((size_t)2 * P.work_cap);
     // the lane walk's point lists live in the worklist, unused until merging
-    const bool lanes = P.core_lanes && (uint64_t)n <= P.work_cap;
+    const bool lanes = P.core_lanes && 2ull * n <= P.work_cap;
     P.core_list = lanes ? P.work : nullptr;
     P.core_defer = lanes ? P.work + n : nullptr;
+    P.rep_chunks = lanes ? P.work + 2 * (size_t)n : nullptr;
+
     P.owner = cv.take<uint32_t>(n);
     P.cmin = cv.take<uint32_t>(n);
     P.minmem = cv.take<uint32_t>(n);
     P.wrank = cv.take<uint32_t>(((size_t)n + 31) / 32);
     P.label_of = cv.take<int32_t>(n);
+    // the lane path's core-cube lists, in arrays free until borders and labels
+    P.core_cubes = P.core_list ? P.owner : nullptr;
+    P.big_cubes = P.core_list ? (uint32_t *)P.label_of : nullptr;
     // zeroed before every call: counters, histograms, look-back words
     const size_t zstart = cv.off;
     P.ctr = cv.take<Counters>(1);

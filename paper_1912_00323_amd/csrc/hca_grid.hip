@@ -1288,6 +1288,58 @@ __global__ __launch_bounds__(kBlock) void k_core_deferred(Plan P)
     flush_tests(P, kTestsCore, lt);
 }
 
+// The core cubes of the lane path, for representatives and merging: cubes of
+// at most kRepLanePts points (a lane each) and the larger ones (a block each),
+// one atomic per list and block.
+// A big cube also gets one (cube, chunk) record per kRepChunk of its points
+// and its representative slots set to "none" for the chunks' atomic minima.
+__global__ __launch_bounds__(kFlatBlock) void k_core_cubes(Plan P)
+{
+    __shared__ uint32_t s_cnt[3][kFlatBlock / kWave];
+    __shared__ uint32_t s_base[3];
+    const uint32_t nc = ld_agent32(&P.ctr->n_cells), l = lane_id(), w = threadIdx.x / kWave;
+    const uint32_t c = blockIdx.x * kFlatBlock + threadIdx.x;
+    bool small = false, big = false;
+    uint32_t size = 0;
+    if (c < nc && ld_agent32(P.ncore + c) > 0) {
+        size = P.cell_start[c + 1] - P.cell_start[c];
+        big = size > kRepLanePts;
+        small = !big;
+    }
+    const uint32_t nch = big ? (size + kRepChunk - 1) / kRepChunk : 0u;
+    const uint64_t ms = __ballot(small), mb = __ballot(big);
+    const uint32_t chi = wave_inclusive_scan(nch);
+    if (l == 0) {
+        s_cnt[0][w] = (uint32_t)__popcll(ms);
+        s_cnt[1][w] = (uint32_t)__popcll(mb);
+    }
+    if (l == kWave - 1) s_cnt[2][w] = chi;
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const uint32_t k = threadIdx.x;
+        uint32_t tot = 0;
+        for (int i = 0; i < kFlatBlock / kWave; i++) {
+            const uint32_t v = s_cnt[k][i];
+            s_cnt[k][i] = tot;
+            tot += v;
+        }
+        uint32_t *ctr = k == 0 ? &P.ctr->n_small : k == 1 ? &P.ctr->n_big : &P.ctr->n_chunks;
+        s_base[k] = tot ? atomicAdd(ctr, tot) : 0u;
+    }
+    __syncthreads();
+    if (small) P.core_cubes[s_base[0] + s_cnt[0][w] + __popcll(ms & __lanemask_lt())] = c;
+    if (big) {
+        P.big_cubes[s_base[1] + s_cnt[1][w] + __popcll(mb & __lanemask_lt())] = c;
+        const uint32_t at = s_base[2] + s_cnt[2][w] + chi - nch;
+        for (uint32_t k = 0; k < nch; k++) {
+            P.rep_chunks[2ull * (at + k)] = c;
+            P.rep_chunks[2ull * (at + k) + 1] = k;
+        }
+        if (P.n_dir)
+            for (uint32_t t = 0; t < P.n_dir; t++) st_agent(P.rep + (uint64_t)c * P.n_dir + t, ~0ull);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Representative points (Choosing Representative Points; Algorithm 2), for
 // m == 1 and d <= 4: for each of the 3^d - 1 directions, the core point of the
@@ -1366,6 +1418,146 @@ __global__ __launch_bounds__(kBlock) void k_reps(Plan P)
     }
 }
 
+// Squared gaps of point x of the cube with key gkey to the cube's upper and
+// lower faces, per axis.
+template <int D>
+__device__ __forceinline__ void face_gaps(const Plan &P, uint64_t gkey, const Pt<D> &x, uint64_t *up, uint64_t *dn)
+{
+    const SegParam *sp = P.nseg ? P.seg + (uint32_t)(gkey >> P.seg_shift) : nullptr;
+    const int64_t s = sp ? sp->side : (int64_t)P.side;
+#pragma unroll
+    for (int k = 0; k < D; k++) {
+        const int64_t gc = (int64_t)((gkey >> P.goff[k]) & ((1ull << P.gw[k]) - 1ull));
+        const int64_t u = (int64_t)x.x[k] - ((int64_t)(sp ? sp->origin[k] : P.origin[k]) + gc * s);
+        up[k] = (uint64_t)((s - u) * (s - u));
+        dn[k] = (uint64_t)(u * u);
+    }
+}
+
+// (score << 32 | sorted position q) of direction t (base-3 digits, axis 0
+// lowest, the all-zero direction skipped): the squared distance to the
+// ideal position over the axes where the direction is not 0.  Scores past
+// 32 bits only blur the choice between representatives (speed, not labels).
+template <int D>
+__device__ __forceinline__ uint64_t rep_key(uint32_t t, const uint64_t *up, const uint64_t *dn, uint32_t q)
+{
+    uint32_t zero = 0, mul = 1;
+#pragma unroll
+    for (int k = 0; k < D; k++) { zero += mul; mul *= 3; }
+    uint32_t v = t >= zero ? t + 1 : t;
+    uint64_t sc = 0;
+#pragma unroll
+    for (int k = 0; k < D; k++) {
+        const uint32_t digit = v % 3;
+        v /= 3;
+        sc += digit == 2 ? up[k] : (digit == 0 ? dn[k] : 0);
+    }
+    return (min(sc, (uint64_t)0xFFFFFFFFull) << 32) | q;
+}
+
+template <int D>
+constexpr int rep_dirs() { return D == 1 ? 2 : D == 2 ? 8 : D == 3 ? 26 : 80; }
+
+// Lane path: the representatives of a small core cube (at most kRepLanePts
+// points) by a group of kRepGroup lanes, each scoring up to kRepPer points,
+// reduced over the group; every slot is written once, with no atomics.  Ties
+// go to the first point in sorted order, as the packed minimum of (score,
+// position) gives.
+constexpr int kRepGroup = 8;
+constexpr int kRepPer = (int)kRepLanePts / kRepGroup;
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_reps_small(Plan P)
+{
+    constexpr int ND = rep_dirs<D>();
+    const uint32_t ns = ld_agent32(&P.ctr->n_small);
+    const uint32_t gl = threadIdx.x % kRepGroup;
+    const uint32_t stride = gridDim.x * (kBlock / kRepGroup);
+    // group-uniform loop: the reduction below needs every lane of the wave
+    for (uint32_t base = (blockIdx.x * kBlock + threadIdx.x) / kWave * (kWave / kRepGroup);
+         base < ns; base += stride) {
+        const uint32_t i = base + (threadIdx.x % kWave) / kRepGroup;
+        uint64_t best[ND];
+#pragma unroll
+        for (int t = 0; t < ND; t++) best[t] = ~0ull;
+        uint32_t c = kNone;
+        if (i < ns) {
+            c = P.core_cubes[i];
+            const uint64_t gkey = P.group_key[c];
+            const uint32_t a = P.cell_start[c], b = P.cell_start[c + 1];
+            Pt<D> x[kRepPer];
+            bool on[kRepPer];
+#pragma unroll
+            for (int k = 0; k < kRepPer; k++) {
+                const uint32_t q = a + gl + (uint32_t)k * kRepGroup;
+                on[k] = q < b && P.core[min(q, b - 1u)];
+                x[k] = load_pt<D>(P.spts, min(q, b - 1u));
+            }
+#pragma unroll
+            for (int k = 0; k < kRepPer; k++) {
+                if (!on[k]) continue;
+                const uint32_t q = a + gl + (uint32_t)k * kRepGroup;
+                uint64_t up[D], dn[D];
+                face_gaps<D>(P, gkey, x[k], up, dn);
+#pragma unroll
+                for (int t = 0; t < ND; t++) best[t] = min(best[t], rep_key<D>((uint32_t)t, up, dn, q));
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < ND; t++) {
+#pragma unroll
+            for (int o = 1; o < kRepGroup; o <<= 1) best[t] = min(best[t], (uint64_t)__shfl_xor(best[t], o));
+        }
+        if (c != kNone && gl == 0)
+#pragma unroll
+            for (int t = 0; t < ND; t++) st_agent(P.rep + (uint64_t)c * ND + t, best[t]);
+    }
+}
+
+// Lane path: the representatives of a larger core cube, from chunks of
+// kRepChunk of its points, one wave each (eight points per lane), folded in
+// with one 64-bit atomic minimum per chunk and direction.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_reps_big(Plan P)
+{
+    constexpr int ND = rep_dirs<D>();
+    const uint32_t nch = ld_agent32(&P.ctr->n_chunks), l = lane_id();
+    const WaveRange hca_wr_ = wave_range();
+    HCA_FOR_UNITS(u, nch) {
+        const uint32_t c = P.rep_chunks[2ull * u], k = P.rep_chunks[2ull * u + 1];
+        const uint64_t gkey = P.group_key[c];
+        const uint32_t a = P.cell_start[c] + k * kRepChunk;
+        const uint32_t b = min(P.cell_start[c + 1], a + kRepChunk);
+        uint64_t best[ND];
+#pragma unroll
+        for (int t = 0; t < ND; t++) best[t] = ~0ull;
+        constexpr int PER = (int)kRepChunk / kWave;
+        Pt<D> x[PER];
+        bool on[PER];
+#pragma unroll
+        for (int j = 0; j < PER; j++) {
+            const uint32_t q = a + l + (uint32_t)j * kWave;
+            on[j] = q < b && P.core[min(q, b - 1u)];
+            x[j] = load_pt<D>(P.spts, min(q, b - 1u));
+        }
+#pragma unroll
+        for (int j = 0; j < PER; j++) {
+            if (!on[j]) continue;
+            uint64_t up[D], dn[D];
+            face_gaps<D>(P, gkey, x[j], up, dn);
+#pragma unroll
+            for (int t = 0; t < ND; t++)
+                best[t] = min(best[t], rep_key<D>((uint32_t)t, up, dn, a + l + (uint32_t)j * kWave));
+        }
+#pragma unroll
+        for (int t = 0; t < ND; t++) {
+            const uint64_t m = wave_min(best[t]);
+            if (l == (uint32_t)t && m != ~0ull)
+                atomicMin((unsigned long long *)(P.rep + (uint64_t)c * ND + t), (unsigned long long)m);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Merging, m == 1 (Depth First Search and Layering paragraphs; Algorithm 3):
 // for each core cube A and neighbour core cube B > A not yet in A's set, the
@@ -1405,8 +1597,10 @@ __device__ __forceinline__ bool rep_pair(const Plan &P, uint32_t A, uint32_t B, 
                                          int64_t eps2, uint32_t &lt)
 {
     bool todo = B != kNone && B > A && P.ncore[B] > 0;
-    if (todo) todo = uf_find(P.parent, A) != uf_find(P.parent, B);
     bool joined = false;
+    // the facing representatives first (their loads need no root); the
+    // roots are looked at on a hit (by the union) or on a miss (before the
+    // pair is queued for the exact test)
     if (todo && P.n_dir) {
         const uint64_t ra = ld_agent(P.rep + (uint64_t)A * P.n_dir + dfw);
         const uint64_t rb = ld_agent(P.rep + (uint64_t)B * P.n_dir + dbw);
@@ -1418,6 +1612,7 @@ __device__ __forceinline__ bool rep_pair(const Plan &P, uint32_t A, uint32_t B, 
             if (joined) uf_union(P.parent, A, B);
         }
     }
+    if (todo && !joined && !P.rep_only) todo = uf_find(P.parent, A) != uf_find(P.parent, B);
     return todo && !joined && !P.rep_only;
 }
 
@@ -1512,6 +1707,56 @@ __global__ __launch_bounds__(kBlock) void k_merge_rep(Plan P)
                 queue_exact<D, WIDE>(P, exact, A, B, lt);
             }
         }
+    }
+    flush_tests(P, kTestsMerge, lt);
+}
+
+// Lane path (cubes as groups, stencil of at most 64 offsets): one lane per
+// (core cube A, forward offset), over the lists of core cubes, so that no
+// lane is spent on a cube without core points or on a backward offset.
+template <int D, bool WIDE>
+__global__ __launch_bounds__(kBlock) void k_merge_cubes(Plan P)
+{
+    __shared__ uint32_t s_fwd[kWavesPerBlock][kWave];
+    const uint32_t w = wave_in_block(), l = lane_id();
+    // forward offsets: cubes are numbered in key order, so B > A exactly when
+    // the first non-zero component of the offset is positive
+    bool fw = false;
+    if (l < P.n_off) {
+        const int8_t *o = P.off + (uint64_t)l * D;
+        int lead = 0;
+#pragma unroll
+        for (int e = 0; e < D; e++)
+            if (lead == 0) lead = o[e];
+        fw = lead > 0;
+    }
+    const uint64_t fm = __ballot(fw);
+    if (fw) s_fwd[w][__popcll(fm & __lanemask_lt())] = l;
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t nf = (uint32_t)__popcll(fm);
+    const uint32_t ns = ld_agent32(&P.ctr->n_small), ncc = ns + ld_agent32(&P.ctr->n_big);
+    const uint64_t pairs = (uint64_t)ncc * nf;
+    uint32_t lt = 0;
+    const WaveRange hca_wr_ = wave_range();
+    HCA_FOR_UNITS(wu, (uint32_t)((pairs + kWave - 1) / kWave)) {
+        const uint64_t u = (uint64_t)wu * kWave + l;
+        uint32_t A = kNone, B = kNone, dfw = 0, dbw = 0;
+        int64_t eps2 = 0;
+        if (u < pairs) {
+            const uint32_t ci = (uint32_t)(u / nf), f = (uint32_t)(u - (uint64_t)ci * nf);
+            A = ci < ns ? P.core_cubes[ci] : P.big_cubes[ci - ns];
+            const uint32_t j = s_fwd[w][f];
+            const uint64_t gkey = P.group_key[A];
+            eps2 = cube_geo<D>(P, gkey).eps2;
+            const uint64_t nk = group_neighbour<D>(P, gkey, P.off + (uint64_t)j * D);
+            if (nk != ~0ull) B = group_lookup(P, nk);
+            if (P.n_dir) {
+                dfw = P.dir_fwd[j];
+                dbw = P.dir_bwd[j];
+            }
+        }
+        const bool exact = rep_pair<D, WIDE>(P, A, B, dfw, dbw, eps2, lt);
+        queue_exact<D, WIDE>(P, exact, A, B, lt);
     }
     flush_tests(P, kTestsMerge, lt);
 }
@@ -2492,6 +2737,7 @@ void launch_core(const Plan &P, int blocks, hipStream_t s)
         case 5: HCA_CORE_LANES(2, true) break;
 #undef HCA_CORE_LANES
         }
+        hipLaunchKernelGGL(k_core_cubes, dim3(fb), dim3(kFlatBlock), 0, s, P);
         return;
     }
     if (P.m > 1) HCA_DISPATCH_DW(k_core_chunks, P, blocks, s);
@@ -2500,6 +2746,17 @@ void launch_core(const Plan &P, int blocks, hipStream_t s)
 
 void launch_reps(const Plan &P, int blocks, hipStream_t s)
 {
+    if (P.core_list) {
+        // per core cube (lane path): every slot of a core cube written once
+        if (P.d == 1) {
+            hipLaunchKernelGGL(k_reps_small<1>, dim3(blocks), dim3(kBlock), 0, s, P);
+            hipLaunchKernelGGL(k_reps_big<1>, dim3(blocks), dim3(kBlock), 0, s, P);
+        } else {
+            hipLaunchKernelGGL(k_reps_small<2>, dim3(blocks), dim3(kBlock), 0, s, P);
+            hipLaunchKernelGGL(k_reps_big<2>, dim3(blocks), dim3(kBlock), 0, s, P);
+        }
+        return;
+    }
     const int ib = (int)std::min<uint64_t>(((uint64_t)P.n * P.n_dir + kBlock - 1) / kBlock, 2048);
     hipLaunchKernelGGL(k_reps_init, dim3(std::max(1, ib)), dim3(kBlock), 0, s, P);
     switch (P.d) {
@@ -2524,7 +2781,16 @@ void launch_merge_intra(const Plan &P, int blocks, hipStream_t s)
 void launch_merge(const Plan &P, int blocks, hipStream_t s)
 {
     if (P.m == 1) {
-        HCA_DISPATCH_DW(k_merge_rep, P, blocks, s);
+        if (P.core_list) {
+            switch (P.d * 2 + (P.wide ? 1 : 0)) {
+            case 2: hipLaunchKernelGGL((k_merge_cubes<1, false>), dim3(blocks), dim3(kBlock), 0, s, P); break;
+            case 3: hipLaunchKernelGGL((k_merge_cubes<1, true>), dim3(blocks), dim3(kBlock), 0, s, P); break;
+            case 4: hipLaunchKernelGGL((k_merge_cubes<2, false>), dim3(blocks), dim3(kBlock), 0, s, P); break;
+            case 5: hipLaunchKernelGGL((k_merge_cubes<2, true>), dim3(blocks), dim3(kBlock), 0, s, P); break;
+            }
+        } else {
+            HCA_DISPATCH_DW(k_merge_rep, P, blocks, s);
+        }
         if (!P.rep_only) HCA_DISPATCH_DW(k_merge_exact, P, blocks, s);
     } else {
         HCA_DISPATCH_DW(k_merge_inter, P, blocks, s);

@@ -19,6 +19,10 @@ constexpr uint32_t kHdCoreBudget = 16384;
 // kCoreLaneBudget candidates before a wave-wide walk takes its point over.
 constexpr int kColR = 2;
 constexpr uint32_t kCoreLaneBudget = 64;
+// On that path representatives are taken per core cube: a lane for a cube of
+// at most kRepLanePts points, a block for a larger one.
+constexpr uint32_t kRepLanePts = 32;
+constexpr uint32_t kRepChunk = 512;           // points of a big cube per wave
 
 // nrec value of a point that found c neighbours: c when all were recorded
 __host__ __device__ constexpr uint32_t rec_count(uint32_t c) { return c <= (uint32_t)kRec ? c : kRec + 1; }
@@ -83,7 +87,10 @@ struct Counters {
     uint32_t n_blist;           // non-core points left for the border walk (blist)
     uint32_t n_sparse;          // cube-mode points of cubes with fewer than minPts points (core_list)
     uint32_t n_defer;           // of those, points whose candidate budget ran out (core_defer)
-    uint32_t pad[4];
+    uint32_t n_small;           // core cubes of at most kRepLanePts points (core_cubes)
+    uint32_t n_big;             // the other core cubes (big_cubes)
+    uint32_t n_chunks;          // chunks of kRepChunk points of those (rep_chunks)
+    uint32_t pad[1];
     uint32_t work_count[kWorkRegions * kCounterStride];   // region r at [r * kCounterStride]
     // pair tests executed, per phase (core, merge, border), spread over
     // kWorkRegions lines of eight 64-bit words; counted only on request
@@ -159,6 +166,9 @@ struct Plan {
     uint32_t core_budget;
     uint32_t *core_list;        // [n] sorted positions of points of sparse cubes
     uint32_t *core_defer;       // [n] the points left to the wave-wide walk
+    uint32_t *core_cubes;       // [n] core cubes of at most kRepLanePts points (in owner, free until borders)
+    uint32_t *big_cubes;        // [n] the other core cubes (in label_of, free until labels)
+    uint32_t *rep_chunks;       // [2n] (cube, chunk) pairs of the big cubes (in the worklist)
     // neighbour search over groups: offsets in [-R, R]^d, self first
     uint32_t n_off;
     const int8_t *off;          // [n_off][d]
