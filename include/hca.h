@@ -221,6 +221,68 @@ hca_status hca_cluster_sets(hca_ctx *ctx, const int32_t *const *points, int32_t 
                             const int64_t *rows, const int32_t *dims, const double *eps,
                             const int32_t *min_pts);
 
+/* Batch handles: the batched form for batches of one fixed shape (the rows,
+ * d, eps and minPts of every data set), as a serving loop or a pipeline
+ * repeats them.  hca_batch_create checks the shape (as hca_cluster_batch;
+ * nseg >= 1), uploads the offset tables and makes one stream per dimension.
+ * tune: 0 keeps the default knobs; 1 takes each group's knobs (of the data
+ * sets of one dimension) from the autotuner's cache when it knows the group
+ * and tunes it on the first run otherwise; 2 always tunes on the first run.
+ * The knobs are the representative mode (on/off), the core-marking mode (a
+ * lane per point or a wave per cube), the enumeration mode (prefix-range
+ * list scans or lookups), the persistent blocks of the neighbour phases, the
+ * hash load factor, the radix digit width and the radix tile size; every
+ * choice gives the same labels.  The cache is a JSON file (HCA_TUNE_CACHE,
+ * else $HOME/.cache/hca_tune.json) keyed by dimension, rows, cubes per axis
+ * and data sets, in powers of two.
+ * hca_batch_run clusters one batch of that shape: points[i] (DEVICE,
+ * row-major int32[rows[i]][dims[i]], 4-byte aligned, never written) into
+ * labels[i] (DEVICE int32[rows[i]]), HOST arrays of nseg pointers, on the
+ * context's stream, blocking.  The first run plans on the host from the data
+ * sets' bounding boxes, tunes, runs and captures the whole batch in one HIP
+ * graph (every dimension on its own stream, in parallel); every later run is
+ * one graph launch with no host round trip before the final sync: the device
+ * takes the boxes, writes the origins and checks that the data still fit the
+ * captured key layout, and when they do not the run is planned and captured
+ * again.  Labels equal hca_cluster on each data set alone.  Errors as
+ * hca_cluster_batch.  The handle belongs to its context (same thread rules)
+ * and must be destroyed before it.
+ * hca_batch_stats: counters (runs, graph replays, plans) and, for up to
+ * max_groups groups, the plan and knobs in use with the tuned and default
+ * times of the group's launch sequence (ms; 0 when not timed). */
+typedef struct hca_batch hca_batch;
+typedef struct {
+    int64_t runs;
+    int64_t graph_replays;
+    int64_t plans;
+    int32_t groups;
+    int32_t reserved;
+} hca_batch_info;
+typedef struct {
+    int32_t d;
+    int32_t sets;
+    int64_t rows;
+    int32_t key_bits;
+    int32_t sort_passes;
+    int32_t wide;
+    int32_t reps;
+    int32_t lanes;
+    int32_t prefix;
+    int32_t wave_blocks;
+    int32_t hash_load;
+    int32_t digit_cap;
+    int32_t sort_items;
+    int32_t tuned;            /* 1 tuned on this handle's first run, 2 from the cache, 0 default */
+    int32_t reserved;
+    double tuned_ms;
+    double default_ms;
+} hca_batch_group;
+hca_status hca_batch_create(hca_ctx *ctx, int32_t nseg, const int64_t *rows, const int32_t *dims, const double *eps,
+                            const int32_t *min_pts, int32_t tune, hca_batch **out);
+hca_status hca_batch_run(hca_batch *b, const int32_t *const *points, int32_t *const *labels);
+hca_status hca_batch_stats(const hca_batch *b, hca_batch_info *info, hca_batch_group *groups, int32_t max_groups);
+void hca_batch_destroy(hca_batch *b);
+
 /* Served form: a request loop (continuous batching).  Requests wait in one
  * FIFO queue; `workers` threads, each with its own context and HIP stream,
  * take the next requests whenever they are free: consecutive requests of

@@ -12,7 +12,7 @@ ROOT = HERE.parent
 CSRC = HERE / "csrc"
 OUT = HERE / "libhca.so"
 SOURCES = ["hca_sort.hip", "hca_grid.hip", "hca_highd.hip", "hca_batch.hip", "hca_static.hip", "hca_api.cpp",
-           "hca_server.cpp"]
+           "hca_server.cpp", "hca_tune.cpp"]
 ARCH = os.environ.get("HCA_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -203,11 +203,21 @@ uint32_t env_core_budget()
 
 // Lane walk for core marking: cubes as search groups, no neighbour lists,
 // one or two axes, offsets within kColR.
-void plan_core_lanes(Plan &P, int32_t radius)
+void plan_core_lanes(Plan &P, int32_t radius, const Tune *t = nullptr)
 {
     P.radius = (uint32_t)std::max(0, radius);
     P.core_budget = env_core_budget();
-    P.core_lanes = P.m == 1 && P.list_w == 0 && !P.hd && P.d <= 2 && radius <= kColR && env_core_lanes() ? 1u : 0u;
+    const bool want = t && t->lanes >= 0 ? t->lanes != 0 : env_core_lanes();
+    P.core_lanes = P.m == 1 && P.list_w == 0 && !P.hd && P.d <= 2 && radius <= kColR && want ? 1u : 0u;
+}
+
+// Radix passes for a key of key_bits bits, digits no wider than the key
+// type's (9 bits for 32-bit keys, 8 for 64-bit ones) or the tuned cap.
+uint32_t key_passes(uint32_t key_bits, bool wide, const Tune *t = nullptr)
+{
+    uint32_t rb = wide ? 8u : 9u;
+    if (t && t->digit_cap > 0) rb = std::min<uint32_t>(rb, (uint32_t)t->digit_cap);
+    return key_bits ? (key_bits + rb - 1) / rb : 1u;
 }
 
 bool env_reps()
@@ -440,14 +450,16 @@ struct Sizes {
 };
 
 // Lookup form, worklist and list capacities, grid sizes.
-void plan_sizes(Plan &P, uint32_t gbits, bool count_work, bool want_stats, Sizes *Z)
+void plan_sizes(Plan &P, uint32_t gbits, bool count_work, bool want_stats, Sizes *Z, const Tune *t = nullptr)
 {
     const uint32_t n = P.n;
     Z->gbits = gbits;
     Z->wide_keys = P.key_bits > 32;
     P.dense = gbits <= 24 && (1ull << gbits) <= std::max<uint64_t>(16ull * n, 1ull << 20);
+    P.hash_load = t ? (uint32_t)std::min(std::max(t->hash_load, 1), 3) : 1u;
+    P.sort_items = t && t->sort_items == 16 ? 16u : 0u;
     Z->hcap = 1024;
-    while (Z->hcap < 2ull * n) Z->hcap <<= 1;
+    while (Z->hcap < ((uint64_t)n << P.hash_load)) Z->hcap <<= 1;
     P.hash_mask = Z->hcap - 1;
     Z->sort_tiles = (n + kSortTile - 1) / kSortTile;
     Z->scan_tiles = (n + kScanTile - 1) / kScanTile;
@@ -457,6 +469,7 @@ void plan_sizes(Plan &P, uint32_t gbits, bool count_work, bool want_stats, Sizes
     // persistent grids of the neighbour phases: enough waves to fill the chip
     int persist = kPersistBlocks;
     if (const char *e = std::getenv("HCA_WAVE_BLOCKS")) persist = std::max(8, std::atoi(e));
+    if (t && t->wave_blocks > 0) persist = std::max(8, t->wave_blocks);
     const int pb = (int)std::min<uint64_t>(persist, ((uint64_t)n + kBlock - 1) / kBlock * 4 + 8) & ~7;
     Z->wb = std::max(8, pb);
     Z->tb = (int)std::min<uint64_t>((n + kBlock - 1) / kBlock, 1024);
@@ -477,10 +490,11 @@ void plan_sizes(Plan &P, uint32_t gbits, bool count_work, bool want_stats, Sizes
 // per point, or 2^20: a batch's data-set bits sit above the prefix; the table
 // is written only where groups exist, so its size costs memory, not
 // traffic; HCA_PREFIX=0 turns it off).
-void plan_prefix(Plan &P, uint32_t gbits, Sizes *Z)
+void plan_prefix(Plan &P, uint32_t gbits, Sizes *Z, const Tune *t = nullptr)
 {
     Z->pbits = 0;
-    if (!P.nbr_cap || P.d < 2 || P.hd || !env_prefix()) return;
+    const bool want = t && t->prefix >= 0 ? t->prefix != 0 : env_prefix();
+    if (!P.nbr_cap || P.d < 2 || P.hd || !want) return;
     P.pshift = P.goff[P.d / 2 - 1];
     const uint32_t pbits = gbits - P.pshift;
     if (pbits <= 26 && (1ull << pbits) <= std::max<uint64_t>(32ull * P.n, 1ull << 20))
@@ -591,14 +605,14 @@ size_t ws_bytes(Plan P, const Sizes &Z)
 // Steps 3-12 of a call on the context's stream (the workspace is large
 // enough): initialisation, sort, cube tables and lookup, lists, core points,
 // representatives, merging, border points, labels.  No synchronisation.
-void launch_sequence(hca_ctx *ctx, Plan &P, const Sizes &Z)
+void launch_sequence(hca_ctx *ctx, Plan &P, const Sizes &Z, char *base = nullptr, hipStream_t stream = nullptr)
 {
-    hipStream_t s = ctx->stream;
+    hipStream_t s = stream ? stream : ctx->stream;
     SortBuffers B;
     std::memset(&B, 0, sizeof B);
     uint32_t *zbeg;
     size_t zbytes;
-    Carver cv{ws_base(ctx)};
+    Carver cv{base ? base : ws_base(ctx)};
     carve_ws(cv, P, B, Z, &zbeg, &zbytes);
     B.tickets = P.ctr->sort_tickets;
     const int wb = Z.wb, tb = Z.tb;
@@ -1081,6 +1095,15 @@ struct BatchGroup {
     size_t h_seg = 0, h_off = 0, h_box = 0;
     Plan P;
     Sizes Z;
+    // layout of the packed key shared by the data sets (from their boxes)
+    uint32_t gw[kMaxDim] = {};
+    bool wide = false;
+    uint32_t cubes_axis = 1;            // largest cube count along an axis of any data set
+    Tune tune;                          // knobs of its launch sequence
+    std::string tune_key;               // what the autotuner's cache knows it by
+    double tuned_ms = 0, default_ms = 0;
+    bool tuned = false, from_cache = false;
+    size_t ws_off = 0;                  // workspace region (batch handles: groups side by side)
 };
 
 // Offsets that some data set of the group can need: for a data set with side
@@ -1121,8 +1144,9 @@ void batch_stencil(BatchGroup &g)
     g.off.assign(d, 0);
     for (const auto &e : keep) g.off.insert(g.off.end(), e.second.begin(), e.second.end());
     const uint32_t n_off = (uint32_t)(g.off.size() / d);
+    // directions of representatives (used unless turned off per launch)
     g.n_dir = 0;
-    if (d <= 4 && env_reps()) {
+    if (d <= 4) {
         uint32_t v = 1;
         for (int k = 0; k < d; k++) v *= 3;
         g.n_dir = v - 1;
@@ -1146,13 +1170,12 @@ struct BatchSet {
     int32_t min_pts;
 };
 
-hca_status run_sets(hca_ctx *ctx, const BatchSet *sets, int32_t nseg)
+// Step 1: check the data sets and sort them into groups of one dimension,
+// each with its exact eps^2, cube side and offset radius, and the union of
+// their stencils.
+hca_status batch_groups(hca_ctx *ctx, const BatchSet *sets, int32_t nseg, std::vector<BatchGroup> &groups,
+                        uint64_t *total)
 {
-    if (!ctx) return HCA_E_INVAL;
-    ctx->err.clear();
-    if (nseg < 0) return fail(ctx, HCA_E_INVAL, "nseg must be >= 0");
-    if (nseg == 0) return HCA_OK;
-    if (!sets) return fail(ctx, HCA_E_INVAL, "data sets must not be NULL");
     uint64_t total_rows = 0;
     for (int32_t i = 0; i < nseg; i++) {
         const BatchSet &b = sets[i];
@@ -1160,70 +1183,74 @@ hca_status run_sets(hca_ctx *ctx, const BatchSet *sets, int32_t nseg)
         if (b.d < 1 || b.d > kMaxBatchDim) return fail(ctx, HCA_E_INVAL, "batch data sets need d in [1, 4]");
         if (!(b.eps > 0.0) || !std::isfinite(b.eps)) return fail(ctx, HCA_E_INVAL, "eps must be finite and > 0");
         if (b.min_pts < 1) return fail(ctx, HCA_E_INVAL, "min_pts must be >= 1");
-        if (b.n > 0 && (!b.pts || !b.labels)) return fail(ctx, HCA_E_INVAL, "points and labels must not be NULL");
-        if ((uintptr_t)b.pts % 4 || (uintptr_t)b.labels % 4) return fail(ctx, HCA_E_INVAL, "misaligned arrays");
         total_rows += (uint64_t)b.n;
         if (total_rows > (uint64_t)INT32_MAX) return fail(ctx, HCA_E_INVAL, "more than 2^31 - 1 rows in all");
     }
-    if (total_rows == 0) return HCA_OK;
-    hipStream_t s = ctx->stream;
-    HCA_HIP(hipSetDevice(ctx->device), "hipSetDevice");
-
-    // 1. data sets by dimension, with their exact eps^2, cube side, places
-    std::vector<BatchGroup> groups;
-    {
-        BatchGroup by_d[kMaxBatchDim + 1];
-        for (int32_t i = 0; i < nseg; i++) {
-            const BatchSet &b = sets[i];
-            BatchGroup &g = by_d[b.d];
-            g.d = b.d;
-            SegParam sp;
-            std::memset(&sp, 0, sizeof sp);
-            exact_eps2(b.eps, &sp.eps2);
-            sp.side = std::max<int64_t>(1, (int64_t)isqrt_u64((uint64_t)sp.eps2 / (uint64_t)b.d));
-            sp.side = std::min<int64_t>(sp.side, 1ll << 31);
-            sp.src = b.pts;
-            sp.dst = b.labels;
-            sp.min_pts = (uint32_t)b.min_pts;
-            sp.vstart = g.n;
-            g.segs.push_back(i);
-            g.par.push_back(sp);
-            g.radius.push_back(offset_radius(sp.side, sp.eps2));
-            g.n += (uint32_t)b.n;
-        }
-        for (int dd = 1; dd <= kMaxBatchDim; dd++)
-            if (by_d[dd].n > 0) groups.push_back(std::move(by_d[dd]));
+    *total = total_rows;
+    groups.clear();
+    BatchGroup by_d[kMaxBatchDim + 1];
+    for (int32_t i = 0; i < nseg; i++) {
+        const BatchSet &b = sets[i];
+        BatchGroup &g = by_d[b.d];
+        g.d = b.d;
+        SegParam sp;
+        std::memset(&sp, 0, sizeof sp);
+        exact_eps2(b.eps, &sp.eps2);
+        sp.side = std::max<int64_t>(1, (int64_t)isqrt_u64((uint64_t)sp.eps2 / (uint64_t)b.d));
+        sp.side = std::min<int64_t>(sp.side, 1ll << 31);
+        sp.src = b.pts;
+        sp.dst = b.labels;
+        sp.min_pts = (uint32_t)b.min_pts;
+        sp.vstart = g.n;
+        g.segs.push_back(i);
+        g.par.push_back(sp);
+        g.radius.push_back(offset_radius(sp.side, sp.eps2));
+        g.n += (uint32_t)b.n;
     }
+    for (int dd = 1; dd <= kMaxBatchDim; dd++)
+        if (by_d[dd].n > 0) groups.push_back(std::move(by_d[dd]));
     for (BatchGroup &g : groups) {
         if (g.par.size() > kMaxBatchSegs) return fail(ctx, HCA_E_INVAL, "more than 8192 data sets of one dimension");
         batch_stencil(g);
+        // squared distances in 64 bits when some data set's reach (the
+        // farthest coordinate difference its stencil can test) needs them:
+        // a bound that holds for any data, so a captured plan never depends
+        // on the spans
+        g.wide = false;
+        for (size_t i = 0; i < g.par.size(); i++) {
+            const unsigned __int128 reach = (unsigned __int128)(g.radius[i] + 1) * (uint64_t)g.par[i].side - 1;
+            g.wide |= (unsigned __int128)g.d * reach * reach >= ((unsigned __int128)1 << 31);
+        }
     }
+    return HCA_OK;
+}
 
-    // 2. placement of the staged rows, tables and offsets
-    size_t dev = 0, pin = 0;
+// Step 2: byte offsets of every group's device staging (rows, data set per
+// row, labels, boxes, tables) and pinned staging (tables, boxes) from *dev
+// and *pin on.
+void batch_place(std::vector<BatchGroup> &groups, size_t *dev, size_t *pin)
+{
     for (BatchGroup &g : groups) {
         const size_t ns = g.par.size(), n_off = g.off.size() / g.d;
-        g.d_seg = dev; dev = align256(dev + ns * sizeof(SegParam));
-        g.d_pts = dev; dev = align256(dev + (size_t)g.n * g.d * sizeof(int32_t));
-        g.d_segof = dev; dev = align256(dev + (size_t)g.n * sizeof(uint32_t));
-        g.d_lab = dev; dev = align256(dev + (size_t)g.n * sizeof(int32_t));
-        g.d_box = dev; dev = align256(dev + ns * 2 * g.d * sizeof(uint32_t));
-        g.d_off = dev; dev = align256(dev + g.off.size());
-        g.d_dirf = dev; dev = align256(dev + n_off * sizeof(uint16_t));
-        g.d_dirb = dev; dev = align256(dev + n_off * sizeof(uint16_t));
-        g.h_seg = pin; pin = align256(pin + ns * sizeof(SegParam));
-        g.h_off = pin; pin = align256(pin + g.off.size() + 2 * n_off * sizeof(uint16_t));
-        g.h_box = pin; pin = align256(pin + ns * 2 * g.d * sizeof(uint32_t));
+        g.d_seg = *dev; *dev = align256(*dev + ns * sizeof(SegParam));
+        g.d_pts = *dev; *dev = align256(*dev + (size_t)g.n * g.d * sizeof(int32_t));
+        g.d_segof = *dev; *dev = align256(*dev + (size_t)g.n * sizeof(uint32_t));
+        g.d_lab = *dev; *dev = align256(*dev + (size_t)g.n * sizeof(int32_t));
+        g.d_box = *dev; *dev = align256(*dev + ns * 2 * g.d * sizeof(uint32_t));
+        g.d_off = *dev; *dev = align256(*dev + g.off.size());
+        g.d_dirf = *dev; *dev = align256(*dev + n_off * sizeof(uint16_t));
+        g.d_dirb = *dev; *dev = align256(*dev + n_off * sizeof(uint16_t));
+        g.h_seg = *pin; *pin = align256(*pin + ns * sizeof(SegParam));
+        g.h_off = *pin; *pin = align256(*pin + g.off.size() + 2 * n_off * sizeof(uint16_t));
+        g.h_box = *pin; *pin = align256(*pin + ns * 2 * g.d * sizeof(uint32_t));
     }
-    hca_status st = ensure(ctx, &ctx->bws, &ctx->bws_size, dev, "batch staging");
-    if (st) return st;
-    st = ensure_pinned(ctx, pin);
-    if (st) return st;
-    char *db = (char *)ctx->bws, *hb = (char *)ctx->pinned;
+}
 
-    // 3. stage every group's rows and take the data sets' bounding boxes
+// Offset and direction tables of every group to the device (stream-ordered).
+hca_status batch_tables(hca_ctx *ctx, std::vector<BatchGroup> &groups, char *db, char *hb, hipStream_t s)
+{
     for (BatchGroup &g : groups) {
-        const size_t ns = g.par.size(), n_off = g.off.size() / g.d;
+        const size_t n_off = g.off.size() / g.d;
         std::memcpy(hb + g.h_off, g.off.data(), g.off.size());
         std::memcpy(hb + g.h_off + g.off.size(), g.dir_fwd.data(), n_off * 2);
         std::memcpy(hb + g.h_off + g.off.size() + n_off * 2, g.dir_bwd.data(), n_off * 2);
@@ -1232,6 +1259,16 @@ hca_status run_sets(hca_ctx *ctx, const BatchSet *sets, int32_t nseg)
                 "directions");
         HCA_HIP(hipMemcpyAsync(db + g.d_dirb, hb + g.h_off + g.off.size() + n_off * 2, n_off * 2,
                                hipMemcpyHostToDevice, s), "directions");
+    }
+    return HCA_OK;
+}
+
+// Step 3: the data-set tables to the device, every group's rows staged and
+// its data sets' boxes taken (and copied to the pinned staging); no sync.
+hca_status batch_stage(hca_ctx *ctx, std::vector<BatchGroup> &groups, char *db, char *hb, hipStream_t s)
+{
+    for (BatchGroup &g : groups) {
+        const size_t ns = g.par.size();
         std::memcpy(hb + g.h_seg, g.par.data(), ns * sizeof(SegParam));
         HCA_HIP(hipMemcpyAsync(db + g.d_seg, hb + g.h_seg, ns * sizeof(SegParam), hipMemcpyHostToDevice, s),
                 "data-set table");
@@ -1242,78 +1279,128 @@ hca_status run_sets(hca_ctx *ctx, const BatchSet *sets, int32_t nseg)
                                s), "box copy");
     }
     HCA_HIP(hipGetLastError(), "staging launch");
-    HCA_HIP(hipStreamSynchronize(s), "box sync");
+    return HCA_OK;
+}
 
-    // 4. per group: origins, one key layout for all its data sets, the plan
+// Step 4a: from the boxes (pinned, after a sync), every data set's origin
+// and the group's key layout: one field width per axis for all its data sets.
+hca_status batch_layout(hca_ctx *ctx, BatchGroup &g, const char *hb, const BatchSet *sets)
+{
+    const int d = g.d;
+    const uint32_t *box = (const uint32_t *)(hb + g.h_box);
+    uint64_t cmax[kMaxDim] = {};
+    for (size_t i = 0; i < g.par.size(); i++) {
+        SegParam &sp = g.par[i];
+        if (sets[g.segs[i]].n == 0) continue;
+        for (int k = 0; k < d; k++) {
+            const int32_t lo = (int32_t)(~box[i * 2 * d + k] ^ 0x80000000u);
+            const int32_t hi = (int32_t)(box[i * 2 * d + d + k] ^ 0x80000000u);
+            const int64_t span = (int64_t)hi - lo;
+            if (span >= (1ll << 30)) return fail(ctx, HCA_E_RANGE, "coordinate span >= 2^30 along an axis");
+            sp.origin[k] = lo;
+            cmax[k] = std::max<uint64_t>(cmax[k], (uint64_t)span / (uint64_t)sp.side);
+        }
+    }
+    uint32_t bits = 0;
+    g.cubes_axis = 1;
+    for (int k = d - 1; k >= 0; k--) {
+        g.gw[k] = bit_length(cmax[k]);
+        bits += g.gw[k];
+        g.cubes_axis = std::max<uint32_t>(g.cubes_axis, (uint32_t)std::min<uint64_t>(cmax[k] + 1, 1u << 30));
+    }
+    if (bits + bit_length(g.par.size() - 1) > 63)
+        return fail(ctx, HCA_E_RANGE, "packed batch key needs more than 63 bits");
+    return HCA_OK;
+}
+
+// Step 4b: the group's launch plan from its layout and knobs.
+void batch_plan(BatchGroup &g, char *db, const Tune *t)
+{
+    const int d = g.d;
+    const size_t ns = g.par.size();
+    Plan &P = g.P;
+    std::memset(&P, 0, sizeof P);
+    P.n = g.n;
+    P.d = d;
+    P.sd = (uint32_t)d;
+    P.m = 1;
+    P.side = 1;
+    P.gside = 1;
+    P.min_pts = 1;
+    P.eps2 = 0;
+    uint32_t bits = 0;
+    for (int k = d - 1; k >= 0; k--) {
+        P.gw[k] = g.gw[k];
+        P.gmax[k] = P.gw[k] ? (uint32_t)((1ull << P.gw[k]) - 1) : 0u;
+        P.goff[k] = bits;
+        bits += P.gw[k];
+    }
+    P.nseg = (uint32_t)ns;
+    P.seg_shift = bits;
+    P.key_bits = bits + bit_length(ns - 1);
+    P.passes = key_passes(P.key_bits, P.key_bits > 32, t);
+    P.digit_bits = std::max<uint32_t>(1, (P.key_bits + P.passes - 1) / P.passes);
+    P.wide = g.wide ? 1 : 0;
+    P.n_off = (uint32_t)(g.off.size() / d);
+    const bool reps = t && t->reps >= 0 ? t->reps != 0 : env_reps();
+    P.n_dir = reps ? g.n_dir : 0;
+    P.off = (const int8_t *)(db + g.d_off);
+    P.dir_fwd = (const uint16_t *)(db + g.d_dirf);
+    P.dir_bwd = (const uint16_t *)(db + g.d_dirb);
+    P.seg = (SegParam *)(db + g.d_seg);
+    P.seg_of = (const uint32_t *)(db + g.d_segof);
+    P.pts = (const int32_t *)(db + g.d_pts);
+    P.labels = (int32_t *)(db + g.d_lab);
+    P.core_out = nullptr;
+    int32_t rmax = 0;
+    for (int32_t v : g.radius) rmax = std::max(rmax, v);
+    P.list_w = cube_list_width(d, rmax, P.n_off);
+    plan_core_lanes(P, rmax, t);
+    plan_sizes(P, P.key_bits, false, false, &g.Z, t);
+    plan_prefix(P, P.key_bits, &g.Z, t);
+}
+
+hca_status run_sets(hca_ctx *ctx, const BatchSet *sets, int32_t nseg)
+{
+    if (!ctx) return HCA_E_INVAL;
+    ctx->err.clear();
+    if (nseg < 0) return fail(ctx, HCA_E_INVAL, "nseg must be >= 0");
+    if (nseg == 0) return HCA_OK;
+    if (!sets) return fail(ctx, HCA_E_INVAL, "data sets must not be NULL");
+    for (int32_t i = 0; i < nseg; i++) {
+        const BatchSet &b = sets[i];
+        if (b.n > 0 && (!b.pts || !b.labels)) return fail(ctx, HCA_E_INVAL, "points and labels must not be NULL");
+        if ((uintptr_t)b.pts % 4 || (uintptr_t)b.labels % 4) return fail(ctx, HCA_E_INVAL, "misaligned arrays");
+    }
+    std::vector<BatchGroup> groups;
+    uint64_t total_rows = 0;
+    hca_status st = batch_groups(ctx, sets, nseg, groups, &total_rows);
+    if (st) return st;
+    if (total_rows == 0) return HCA_OK;
+    hipStream_t s = ctx->stream;
+    HCA_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    size_t dev = 0, pin = 0;
+    batch_place(groups, &dev, &pin);
+    st = ensure(ctx, &ctx->bws, &ctx->bws_size, dev, "batch staging");
+    if (st) return st;
+    st = ensure_pinned(ctx, pin);
+    if (st) return st;
+    char *db = (char *)ctx->bws, *hb = (char *)ctx->pinned;
+    st = batch_tables(ctx, groups, db, hb, s);
+    if (st) return st;
+    st = batch_stage(ctx, groups, db, hb, s);
+    if (st) return st;
+    HCA_HIP(hipStreamSynchronize(s), "box sync");
     size_t ws_need = 0;
     for (BatchGroup &g : groups) {
-        const int d = g.d;
-        const size_t ns = g.par.size();
-        const uint32_t *box = (const uint32_t *)(hb + g.h_box);
-        uint64_t cmax[kMaxDim] = {};
-        bool wide = false;
-        for (size_t i = 0; i < ns; i++) {
-            SegParam &sp = g.par[i];
-            if (sets[g.segs[i]].n == 0) continue;
-            int64_t span_max = 0;
-            for (int k = 0; k < d; k++) {
-                const int32_t lo = (int32_t)(~box[i * 2 * d + k] ^ 0x80000000u);
-                const int32_t hi = (int32_t)(box[i * 2 * d + d + k] ^ 0x80000000u);
-                const int64_t span = (int64_t)hi - lo;
-                if (span >= (1ll << 30)) return fail(ctx, HCA_E_RANGE, "coordinate span >= 2^30 along an axis");
-                sp.origin[k] = lo;
-                span_max = std::max(span_max, span);
-                cmax[k] = std::max<uint64_t>(cmax[k], (uint64_t)span / (uint64_t)sp.side);
-            }
-            const unsigned __int128 reach = (unsigned __int128)(g.radius[i] + 1) * (uint64_t)sp.side - 1;
-            const uint64_t dmax = (uint64_t)std::min<unsigned __int128>(reach, (unsigned __int128)span_max);
-            wide |= (unsigned __int128)d * dmax * dmax >= ((unsigned __int128)1 << 31);
-        }
-        Plan &P = g.P;
-        std::memset(&P, 0, sizeof P);
-        P.n = g.n;
-        P.d = d;
-        P.sd = (uint32_t)d;
-        P.m = 1;
-        P.side = 1;
-        P.gside = 1;
-        P.min_pts = 1;
-        P.eps2 = 0;
-        uint32_t bits = 0;
-        for (int k = d - 1; k >= 0; k--) {
-            P.gw[k] = bit_length(cmax[k]);
-            P.gmax[k] = P.gw[k] ? (uint32_t)((1ull << P.gw[k]) - 1) : 0u;
-            P.goff[k] = bits;
-            bits += P.gw[k];
-        }
-        P.nseg = (uint32_t)ns;
-        P.seg_shift = bits;
-        P.key_bits = bits + bit_length(ns - 1);
-        if (P.key_bits > 63) return fail(ctx, HCA_E_RANGE, "packed batch key needs more than 63 bits");
-        P.passes = sort_passes(P.key_bits, P.key_bits > 32);
-        P.digit_bits = std::max<uint32_t>(1, (P.key_bits + P.passes - 1) / P.passes);
-        P.wide = wide ? 1 : 0;
-        P.n_off = (uint32_t)(g.off.size() / d);
-        P.n_dir = g.n_dir;
-        P.off = (const int8_t *)(db + g.d_off);
-        P.dir_fwd = (const uint16_t *)(db + g.d_dirf);
-        P.dir_bwd = (const uint16_t *)(db + g.d_dirb);
-        P.seg = (SegParam *)(db + g.d_seg);
-        P.seg_of = (const uint32_t *)(db + g.d_segof);
-        P.pts = (const int32_t *)(db + g.d_pts);
-        P.labels = (int32_t *)(db + g.d_lab);
-        P.core_out = nullptr;
-        int32_t rmax = 0;
-        for (int32_t v : g.radius) rmax = std::max(rmax, v);
-        P.list_w = cube_list_width(d, rmax, P.n_off);
-        plan_core_lanes(P, rmax);
-        plan_sizes(P, P.key_bits, false, false, &g.Z);
-        plan_prefix(P, P.key_bits, &g.Z);
-        ws_need = std::max(ws_need, ws_bytes(P, g.Z));
+        st = batch_layout(ctx, g, hb, sets);
+        if (st) return st;
+        batch_plan(g, db, nullptr);
+        ws_need = std::max(ws_need, ws_bytes(g.P, g.Z));
         // origins into the device table (stream-ordered before the launches)
-        std::memcpy(hb + g.h_seg, g.par.data(), ns * sizeof(SegParam));
-        HCA_HIP(hipMemcpyAsync(db + g.d_seg, hb + g.h_seg, ns * sizeof(SegParam), hipMemcpyHostToDevice, s),
-                "data-set table");
+        std::memcpy(hb + g.h_seg, g.par.data(), g.par.size() * sizeof(SegParam));
+        HCA_HIP(hipMemcpyAsync(db + g.d_seg, hb + g.h_seg, g.par.size() * sizeof(SegParam), hipMemcpyHostToDevice,
+                               s), "data-set table");
     }
     st = ensure(ctx, &ctx->ws, &ctx->ws_size, ws_need, "workspace");
     if (st) return st;
@@ -1324,7 +1411,7 @@ hca_status run_sets(hca_ctx *ctx, const BatchSet *sets, int32_t nseg)
     float acc[HCA_PHASES] = {};
     for (BatchGroup &g : groups) {
         for (bool &u : ctx->ev_used) u = false;
-        launch_sequence(ctx, g.P, g.Z);
+        launch_sequence(ctx, g.P, g.Z, (char *)ctx->ws, s);
         launch_seg_scatter(g.P.seg, g.P.seg_of, g.P.labels, g.n, s);
         if (ctx->prof != -1) {
             HCA_HIP(hipStreamSynchronize(s), "batch sync");
@@ -1359,6 +1446,268 @@ hca_status run_batch(hca_ctx *ctx, const int32_t *points, int32_t nseg, const in
         row += (uint64_t)rows[i];
     }
     return run_sets(ctx, sets.data(), nseg);
+}
+
+}  // namespace
+
+// ---- batch handles: a plan captured in a HIP graph, knobs tuned per group ----
+// A handle fixes the shape of a batch (rows, d, eps and minPts of every data
+// set).  Its first run plans on the host from the data sets' boxes (one sync),
+// tunes each group's knobs (or takes them from the cache) and captures the
+// whole batch, every group on its own stream, in one HIP graph.  Later runs
+// are one graph launch: the device stages the rows, takes the boxes, writes
+// every data set's origin and checks that the data still fit the captured
+// key layout; the host reads that flag after the final sync and, when the
+// data no longer fit, plans and captures again (the labels of that run come
+// from the new plan).
+struct hca_batch {
+    hca_ctx *ctx = nullptr;
+    std::vector<BatchSet> shape;
+    std::vector<BatchGroup> groups;
+    uint64_t total = 0;
+    void *dev = nullptr;                // staging: tables, rows, labels, boxes, the flag
+    size_t dev_size = 0;
+    void *ws = nullptr;                 // the groups' workspaces side by side
+    size_t ws_size = 0;
+    void *pin = nullptr;                // pinned tables, boxes, the flag
+    size_t pin_size = 0;
+    size_t d_flag = 0, h_flag = 0;
+    hipStream_t origin = nullptr;       // the handle's own stream (graphs cannot capture the null stream)
+    hipEvent_t ready = nullptr;         // the caller's stream up to the run
+    std::vector<hipStream_t> streams;
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> join;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int32_t tune_mode = 1;              // 0 default knobs, 1 cache then tune, 2 always tune
+    int64_t runs = 0, replays = 0, plans = 0;
+};
+
+namespace {
+
+constexpr int kTuneReps = 3;            // timed runs per candidate (the best counts)
+
+void batch_pointers(hca_batch *b, const int32_t *const *points, int32_t *const *labels)
+{
+    for (BatchGroup &g : b->groups)
+        for (size_t i = 0; i < g.par.size(); i++) {
+            g.par[i].src = points[g.segs[i]];
+            g.par[i].dst = labels[g.segs[i]];
+        }
+}
+
+// One group's launch sequence alone on the context's stream, timed with
+// events (milliseconds, the best of kTuneReps after one warm-up).
+hca_status time_group(hca_batch *b, BatchGroup &g, const Tune &t, double *ms)
+{
+    hca_ctx *ctx = b->ctx;
+    hipStream_t s = b->origin;
+    char *db = (char *)b->dev;
+    batch_plan(g, db, &t);
+    hca_status st = ensure(ctx, &b->ws, &b->ws_size, ws_bytes(g.P, g.Z), "batch workspace");
+    if (st) return st;
+    double best = 1e30;
+    for (int r = 0; r <= kTuneReps; r++) {
+        HCA_HIP(hipEventRecord(b->t0, s), "event");
+        launch_sequence(ctx, g.P, g.Z, (char *)b->ws, s);
+        HCA_HIP(hipEventRecord(b->t1, s), "event");
+        HCA_HIP(hipEventSynchronize(b->t1), "event sync");
+        float f = 0.f;
+        HCA_HIP(hipEventElapsedTime(&f, b->t0, b->t1), "event time");
+        if (r > 0) best = std::min(best, (double)f);
+    }
+    *ms = best;
+    return HCA_OK;
+}
+
+// What the tuner's cache knows a group by: its dimension, rows and cube
+// count along the widest axis (powers of two), and how many data sets.
+std::string group_key(const BatchGroup &g)
+{
+    auto lg = [](uint64_t v) {
+        int k = 0;
+        while ((2ull << k) <= v) k++;
+        return k;
+    };
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "d=%d rows=2^%d cubes=2^%d sets=2^%d", g.d, lg(g.n), lg(g.cubes_axis),
+                  lg(g.par.size()));
+    return buf;
+}
+
+// Knobs of a group: from the cache, else by trying each knob's values in
+// turn from the defaults and keeping what runs fastest (every candidate is
+// exact; only its time differs).
+hca_status tune_group(hca_batch *b, BatchGroup &g)
+{
+    g.tune = Tune();
+    g.tune.reps = env_reps() ? 1 : 0;
+    g.tune.lanes = env_core_lanes() ? 1 : 0;
+    g.tune.prefix = env_prefix() ? 1 : 0;
+    g.tune.wave_blocks = kPersistBlocks;
+    g.tuned = g.from_cache = false;
+    g.tuned_ms = g.default_ms = 0;
+    g.tune_key = group_key(g);
+    if (b->tune_mode == 0) return HCA_OK;
+    double cached = 0;
+    if (b->tune_mode == 1 && tune_cache_get(g.tune_key, &g.tune, &cached)) {
+        g.from_cache = true;
+        g.tuned_ms = cached;
+        return HCA_OK;
+    }
+    double best = 0;
+    hca_status st = time_group(b, g, g.tune, &best);
+    if (st) return st;
+    g.default_ms = best;
+    auto try_all = [&](const std::vector<Tune> &cands) -> hca_status {
+        for (const Tune &c : cands) {
+            double ms = 0;
+            hca_status e = time_group(b, g, c, &ms);
+            if (e) return e;
+            if (ms < best * 0.97) {            // keep a change only when it clearly pays
+                best = ms;
+                g.tune = c;
+            }
+        }
+        return HCA_OK;
+    };
+    // representative mode, core-walk mode, enumeration mode (prefix ranges),
+    // persistent tiles of the neighbour phases, hash load, digit width, radix
+    // tile size
+    {
+        Tune c = g.tune;
+        c.reps = 1 - c.reps;
+        st = try_all({c});
+        if (st) return st;
+    }
+    if (g.d <= 2) {
+        Tune c = g.tune;
+        c.lanes = 1 - c.lanes;
+        st = try_all({c});
+        if (st) return st;
+    }
+    if (g.d >= 3) {
+        Tune c = g.tune;
+        c.prefix = 1 - c.prefix;
+        st = try_all({c});
+        if (st) return st;
+    }
+    {
+        Tune a = g.tune, c = g.tune;
+        a.wave_blocks = 1024;
+        c.wave_blocks = 4096;
+        st = try_all({a, c});
+        if (st) return st;
+    }
+    {
+        Tune c = g.tune;
+        c.hash_load = 2;
+        st = try_all({c});
+        if (st) return st;
+    }
+    {
+        Tune c = g.tune;
+        c.digit_cap = 6;
+        st = try_all({c});
+        if (st) return st;
+    }
+    {
+        Tune c = g.tune;
+        c.sort_items = 16;
+        st = try_all({c});
+        if (st) return st;
+    }
+    g.tuned = true;
+    g.tuned_ms = best;
+    tune_cache_put(g.tune_key, g.tune, best);
+    return HCA_OK;
+}
+
+// The graph of one run: the data-set tables from the pinned staging (the
+// callers' pointers of that run), then per group on its own stream: boxes,
+// origins and the layout check, the launch sequence, the labels scattered
+// back; the flag comes back to the pinned staging last.
+hca_status batch_capture(hca_batch *b)
+{
+    hca_ctx *ctx = b->ctx;
+    hipStream_t s = b->origin;
+    char *db = (char *)b->dev, *hb = (char *)b->pin;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    const int32_t prof = ctx->prof;
+    ctx->prof = -1;
+    HCA_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+    launch_init((uint32_t *)(db + b->d_flag), 1, nullptr, 0, s);
+    (void)hipEventRecord(b->fork, s);
+    for (size_t gi = 0; gi < b->groups.size(); gi++) {
+        BatchGroup &g = b->groups[gi];
+        hipStream_t gs = b->streams[gi];
+        const size_t ns = g.par.size();
+        (void)hipStreamWaitEvent(gs, b->fork, 0);
+        (void)hipMemcpyAsync(db + g.d_seg, hb + g.h_seg, ns * sizeof(SegParam), hipMemcpyHostToDevice, gs);
+        launch_init((uint32_t *)(db + g.d_box), ns * 2 * g.d, nullptr, 0, gs);
+        launch_seg_stage(g.d, (const SegParam *)(db + g.d_seg), (uint32_t)ns, (int32_t *)(db + g.d_pts),
+                         (uint32_t *)(db + g.d_segof), g.n, (uint32_t *)(db + g.d_box), gs);
+        SegLayout lay;
+        for (int k = 0; k < kMaxDim; k++) lay.gmax[k] = k < g.d ? g.P.gmax[k] : 0u;
+        launch_seg_origin(g.d, (SegParam *)(db + g.d_seg), (uint32_t)ns, (const uint32_t *)(db + g.d_box), lay,
+                          (uint32_t *)(db + b->d_flag), gs);
+        launch_sequence(ctx, g.P, g.Z, (char *)b->ws + g.ws_off, gs);
+        launch_seg_scatter(g.P.seg, g.P.seg_of, g.P.labels, g.n, gs);
+        (void)hipEventRecord(b->join[gi], gs);
+        (void)hipStreamWaitEvent(s, b->join[gi], 0);
+    }
+    (void)hipMemcpyAsync(hb + b->h_flag, db + b->d_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &graph);
+    ctx->prof = prof;
+    HCA_HIP(e, "end capture");
+    b->graph = graph;
+    HCA_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "graph instantiate");
+    return HCA_OK;
+}
+
+// A run planned on the host from the data sets' boxes (one sync), tuned or
+// not, then captured for the runs after it.
+hca_status batch_plan_run(hca_batch *b)
+{
+    hca_ctx *ctx = b->ctx;
+    hipStream_t s = b->origin;
+    char *db = (char *)b->dev, *hb = (char *)b->pin;
+    hca_status st = batch_stage(ctx, b->groups, db, hb, s);
+    if (st) return st;
+    HCA_HIP(hipStreamSynchronize(s), "box sync");
+    for (BatchGroup &g : b->groups) {
+        st = batch_layout(ctx, g, hb, b->shape.data());
+        if (st) return st;
+        // origins into the device table before any launch sequence
+        std::memcpy(hb + g.h_seg, g.par.data(), g.par.size() * sizeof(SegParam));
+        HCA_HIP(hipMemcpyAsync(db + g.d_seg, hb + g.h_seg, g.par.size() * sizeof(SegParam), hipMemcpyHostToDevice,
+                               s), "data-set table");
+    }
+    for (BatchGroup &g : b->groups) {
+        st = tune_group(b, g);
+        if (st) return st;
+    }
+    size_t off = 0;
+    for (BatchGroup &g : b->groups) {
+        batch_plan(g, db, &g.tune);
+        g.ws_off = off;
+        off = align256(off + ws_bytes(g.P, g.Z));
+    }
+    st = ensure(ctx, &b->ws, &b->ws_size, off, "batch workspace");
+    if (st) return st;
+    for (BatchGroup &g : b->groups) {
+        launch_sequence(ctx, g.P, g.Z, (char *)b->ws + g.ws_off, s);
+        launch_seg_scatter(g.P.seg, g.P.seg_of, g.P.labels, g.n, s);
+    }
+    HCA_HIP(hipGetLastError(), "kernel launch");
+    HCA_HIP(hipStreamSynchronize(s), "batch sync");
+    b->plans++;
+    return batch_capture(b);
 }
 
 }  // namespace
@@ -1508,6 +1857,157 @@ hca_status hca_cluster_batch(hca_ctx *ctx, const int32_t *points, int32_t nseg, 
                              const int32_t *dims, const double *eps, const int32_t *min_pts, int32_t *labels)
 {
     return run_batch(ctx, points, nseg, rows, dims, eps, min_pts, labels);
+}
+
+hca_status hca_batch_create(hca_ctx *ctx, int32_t nseg, const int64_t *rows, const int32_t *dims, const double *eps,
+                            const int32_t *min_pts, int32_t tune, hca_batch **out)
+{
+    if (!out) return HCA_E_INVAL;
+    *out = nullptr;
+    if (!ctx) return HCA_E_INVAL;
+    ctx->err.clear();
+    if (nseg < 1) return fail(ctx, HCA_E_INVAL, "nseg must be >= 1");
+    if (!rows || !dims || !eps || !min_pts) return fail(ctx, HCA_E_INVAL, "per-data-set arrays must not be NULL");
+    if (tune < 0 || tune > 2) return fail(ctx, HCA_E_INVAL, "tune must be 0, 1 or 2");
+    hca_batch *b = new (std::nothrow) hca_batch();
+    if (!b) return HCA_E_NOMEM;
+    b->ctx = ctx;
+    b->tune_mode = tune;
+    b->shape.resize((size_t)nseg);
+    for (int32_t i = 0; i < nseg; i++) b->shape[i] = {nullptr, nullptr, rows[i], dims[i], eps[i], min_pts[i]};
+    auto bail = [&](hca_status st) {
+        hca_batch_destroy(b);
+        return st;
+    };
+    hca_status st = batch_groups(ctx, b->shape.data(), nseg, b->groups, &b->total);
+    if (st) return bail(st);
+    if (hipSetDevice(ctx->device) != hipSuccess) return bail(fail(ctx, HCA_E_DEVICE, "hipSetDevice"));
+    size_t dev = 0, pin = 0;
+    batch_place(b->groups, &dev, &pin);
+    b->d_flag = dev;
+    dev = align256(dev + sizeof(uint32_t));
+    b->h_flag = pin;
+    pin = align256(pin + sizeof(uint32_t));
+    st = ensure(ctx, &b->dev, &b->dev_size, dev, "batch staging");
+    if (st) return bail(st);
+    if (hipHostMalloc(&b->pin, pin, hipHostMallocDefault) != hipSuccess)
+        return bail(fail(ctx, HCA_E_NOMEM, "pinned batch staging"));
+    b->pin_size = pin;
+    if (hipStreamCreateWithFlags(&b->origin, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ready, hipEventDisableTiming) != hipSuccess)
+        return bail(fail(ctx, HCA_E_DEVICE, "stream"));
+    st = batch_tables(ctx, b->groups, (char *)b->dev, (char *)b->pin, b->origin);
+    if (st) return bail(st);
+    if (hipStreamSynchronize(b->origin) != hipSuccess) return bail(fail(ctx, HCA_E_DEVICE, "table upload"));
+    for (size_t gi = 0; gi < b->groups.size(); gi++) {
+        hipStream_t gs = nullptr;
+        hipEvent_t e = nullptr;
+        if (hipStreamCreateWithFlags(&gs, hipStreamNonBlocking) != hipSuccess)
+            return bail(fail(ctx, HCA_E_DEVICE, "stream"));
+        b->streams.push_back(gs);
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+            return bail(fail(ctx, HCA_E_DEVICE, "event"));
+        b->join.push_back(e);
+    }
+    if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess || hipEventCreate(&b->t0) != hipSuccess ||
+        hipEventCreate(&b->t1) != hipSuccess)
+        return bail(fail(ctx, HCA_E_DEVICE, "event"));
+    *out = b;
+    return HCA_OK;
+}
+
+hca_status hca_batch_run(hca_batch *b, const int32_t *const *points, int32_t *const *labels)
+{
+    if (!b) return HCA_E_INVAL;
+    hca_ctx *ctx = b->ctx;
+    ctx->err.clear();
+    if (!points || !labels) return fail(ctx, HCA_E_INVAL, "points and labels must not be NULL");
+    for (size_t i = 0; i < b->shape.size(); i++) {
+        if (b->shape[i].n > 0 && (!points[i] || !labels[i]))
+            return fail(ctx, HCA_E_INVAL, "points and labels must not be NULL");
+        if ((uintptr_t)points[i] % 4 || (uintptr_t)labels[i] % 4) return fail(ctx, HCA_E_INVAL, "misaligned arrays");
+    }
+    if (b->total == 0) return HCA_OK;
+    HCA_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    b->runs++;
+    batch_pointers(b, points, labels);
+    for (size_t i = 0; i < b->shape.size(); i++) {
+        b->shape[i].pts = points[i];
+        b->shape[i].labels = labels[i];
+    }
+    // the run starts after the work queued so far on the caller's stream
+    HCA_HIP(hipEventRecord(b->ready, ctx->stream), "event");
+    HCA_HIP(hipStreamWaitEvent(b->origin, b->ready, 0), "stream wait");
+    if (b->exec) {
+        char *hb = (char *)b->pin;
+        for (BatchGroup &g : b->groups) std::memcpy(hb + g.h_seg, g.par.data(), g.par.size() * sizeof(SegParam));
+        HCA_HIP(hipGraphLaunch(b->exec, b->origin), "graph launch");
+        HCA_HIP(hipStreamSynchronize(b->origin), "graph sync");
+        const uint32_t flag = *(volatile uint32_t *)(hb + b->h_flag);
+        if (!flag) {
+            b->replays++;
+            return HCA_OK;
+        }
+        // the data no longer fit the captured layout (or break the span
+        // rule): plan again from their boxes
+    }
+    // (phase events belong to the context's stream: off for the handle's)
+    const int32_t prof = ctx->prof;
+    ctx->prof = -1;
+    const hca_status st = batch_plan_run(b);
+    ctx->prof = prof;
+    return st;
+}
+
+hca_status hca_batch_stats(const hca_batch *b, hca_batch_info *info, hca_batch_group *groups, int32_t max_groups)
+{
+    if (!b || !info) return HCA_E_INVAL;
+    std::memset(info, 0, sizeof *info);
+    info->runs = b->runs;
+    info->graph_replays = b->replays;
+    info->plans = b->plans;
+    info->groups = (int32_t)b->groups.size();
+    for (int32_t i = 0; groups && i < max_groups && i < info->groups; i++) {
+        const BatchGroup &g = b->groups[i];
+        hca_batch_group &o = groups[i];
+        std::memset(&o, 0, sizeof o);
+        o.d = g.d;
+        o.sets = (int32_t)g.par.size();
+        o.rows = g.n;
+        o.key_bits = (int32_t)g.P.key_bits;
+        o.sort_passes = (int32_t)g.P.passes;
+        o.wide = g.P.wide;
+        o.reps = g.tune.reps;
+        o.lanes = g.tune.lanes;
+        o.prefix = g.tune.prefix;
+        o.wave_blocks = g.tune.wave_blocks;
+        o.hash_load = g.tune.hash_load;
+        o.digit_cap = g.tune.digit_cap;
+        o.sort_items = g.tune.sort_items;
+        o.tuned = g.tuned ? 1 : g.from_cache ? 2 : 0;
+        o.tuned_ms = g.tuned_ms;
+        o.default_ms = g.default_ms;
+    }
+    return HCA_OK;
+}
+
+void hca_batch_destroy(hca_batch *b)
+{
+    if (!b) return;
+    (void)hipSetDevice(b->ctx->device);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
+    if (b->origin) (void)hipStreamDestroy(b->origin);
+    if (b->ready) (void)hipEventDestroy(b->ready);
+    for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->t0) (void)hipEventDestroy(b->t0);
+    if (b->t1) (void)hipEventDestroy(b->t1);
+    if (b->dev) (void)hipFree(b->dev);
+    if (b->ws) (void)hipFree(b->ws);
+    if (b->pin) (void)hipHostFree(b->pin);
+    delete b;
 }
 
 hca_status hca_cluster_sets(hca_ctx *ctx, const int32_t *const *points, int32_t *const *labels, int32_t nseg,

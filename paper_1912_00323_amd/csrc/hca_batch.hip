@@ -77,6 +77,44 @@ __global__ __launch_bounds__(kBlock) void k_seg_bbox(const int32_t *pts, const u
     }
 }
 
+// A batch plan replayed on new data (a captured graph): every data set's
+// origin (the minimum of its box) into its parameters on the device, and
+// flags when the data do not fit the plan: bit 0, a span of 2^30 or more;
+// bit 1, a cube coordinate past its field of the key layout.  An empty data
+// set (box still neutral) is left alone.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_seg_origin(SegParam *seg, uint32_t nseg, const uint32_t *box,
+                                                       SegLayout lay, uint32_t *flag)
+{
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < nseg; i += gridDim.x * kBlock) {
+        uint32_t f = 0;
+        const int64_t side = seg[i].side;
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+            const int32_t lo = (int32_t)(~box[(uint64_t)i * 2 * D + k] ^ 0x80000000u);
+            const int32_t hi = (int32_t)(box[(uint64_t)i * 2 * D + D + k] ^ 0x80000000u);
+            if (hi < lo) continue;
+            const int64_t span = (int64_t)hi - lo;
+            if (span >= (1ll << 30)) f |= 1u;
+            else if (span / side > (int64_t)lay.gmax[k]) f |= 2u;
+            seg[i].origin[k] = lo;
+        }
+        if (f) atomicOr(flag, f);
+    }
+}
+
+void launch_seg_origin(int d, SegParam *seg, uint32_t nseg, const uint32_t *box, const SegLayout &lay,
+                       uint32_t *flag, hipStream_t s)
+{
+    const int blocks = (int)std::max<uint32_t>(1, std::min<uint32_t>((nseg + kBlock - 1) / kBlock, 64));
+    switch (d) {
+    case 1: hipLaunchKernelGGL(k_seg_origin<1>, dim3(blocks), dim3(kBlock), 0, s, seg, nseg, box, lay, flag); break;
+    case 2: hipLaunchKernelGGL(k_seg_origin<2>, dim3(blocks), dim3(kBlock), 0, s, seg, nseg, box, lay, flag); break;
+    case 3: hipLaunchKernelGGL(k_seg_origin<3>, dim3(blocks), dim3(kBlock), 0, s, seg, nseg, box, lay, flag); break;
+    case 4: hipLaunchKernelGGL(k_seg_origin<4>, dim3(blocks), dim3(kBlock), 0, s, seg, nseg, box, lay, flag); break;
+    }
+}
+
 // Labels back to each data set's own array.
 __global__ __launch_bounds__(kBlock) void k_seg_scatter(const SegParam *seg, const uint32_t *seg_of,
                                                         const int32_t *staged, uint32_t n)

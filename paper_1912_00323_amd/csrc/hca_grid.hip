@@ -243,14 +243,15 @@ __global__ __launch_bounds__(kBlock) void k_init(uint32_t *zero, uint64_t zero_w
 // ---------------------------------------------------------------------------
 // Group lookup table: direct index over the packed group key, or open
 // addressing with linear probing (64-bit keys, all-ones = empty).  The hash
-// uses a power of two >= 2x the groups of this call (at least 1024 slots), so
+// uses a power of two >= 2^hash_load x the groups of this call (at least 1024
+// slots; hash_load is 1 unless tuned), so
 // that the slots probed stay few and cache-resident; only those start empty.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_table_clear(Plan P)
 {
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
     uint64_t cap = 1024;
-    while (cap < 2ull * ng) cap <<= 1;
+    while (cap < ((uint64_t)ng << P.hash_load)) cap <<= 1;
     cap = min(cap, P.hash_mask + 1);
     if (blockIdx.x == 0 && threadIdx.x == 0) st_agent32(&P.ctr->hmask, (uint32_t)(cap - 1));
     for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < cap; i += (uint64_t)gridDim.x * kBlock) {

@@ -52,6 +52,8 @@ void launch_border_list(const Plan &P, hipStream_t s);
 // boxes; labels back to each data set's own array
 void launch_seg_stage(int d, const SegParam *seg, uint32_t nseg, int32_t *dst, uint32_t *seg_of, uint32_t n,
                       uint32_t *box, hipStream_t s);
+void launch_seg_origin(int d, SegParam *seg, uint32_t nseg, const uint32_t *box, const SegLayout &lay,
+                       uint32_t *flag, hipStream_t s);
 void launch_seg_scatter(const SegParam *seg, const uint32_t *seg_of, const int32_t *staged, uint32_t n,
                         hipStream_t s);
 

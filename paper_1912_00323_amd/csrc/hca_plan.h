@@ -117,6 +117,11 @@ struct SegParam {
     uint32_t pad;
 };
 
+// The field maximum of every cube coordinate of a batch's key layout.
+struct SegLayout {
+    uint32_t gmax[kMaxDim];
+};
+
 struct Plan {
     // problem
     uint32_t n;
@@ -180,6 +185,8 @@ struct Plan {
     // group lookup: direct table over the packed group key, or hash
     uint32_t dense;
     uint64_t hash_mask;         // allocated capacity - 1; the call uses Counters::hmask
+    uint32_t hash_load;         // slots in use >= groups << hash_load (at least 1024)
+    uint32_t sort_items;        // keys per thread of a radix tile (0: the key type's default)
 
     // buffers
     const int32_t *pts;         // [n][d] input order

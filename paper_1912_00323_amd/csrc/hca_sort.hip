@@ -92,10 +92,13 @@ __device__ __forceinline__ K cube_key(const Plan &P, const Pt<D> &p, uint32_t i)
         const uint32_t sg = P.seg_of[i];
         const SegParam &sp = P.seg[sg];
         const uint32_t side = (uint32_t)sp.side;
+        // the cube coordinate is held to its field: a captured plan replayed
+        // on data that no longer fits it is flagged by k_seg_origin and
+        // planned again, and its keys must stay inside the tables meanwhile
 #pragma unroll
         for (int k = 0; k < D; k++) {
-            const uint32_t u = (uint32_t)(p.x[k] - sp.origin[k]);    // < 2^30 (host checked)
-            key |= (uint64_t)(u / side) << P.goff[k];
+            const uint32_t u = (uint32_t)(p.x[k] - sp.origin[k]);    // < 2^30 (checked)
+            key |= (uint64_t)min(u / side, P.gmax[k]) << P.goff[k];
         }
         return (K)(key | (uint64_t)sg << P.seg_shift);
     }
@@ -212,7 +215,7 @@ __device__ __forceinline__ bool hd_new_cube(const Plan &P, uint32_t idx)
 // and turned into global offsets by looking back over earlier tiles; keys
 // are then staged in LDS in digit order and written out in runs.
 // ---------------------------------------------------------------------------
-template <typename K, int D, bool GATHER>
+template <typename K, int D, bool GATHER, int ITEMS = sort_items<K>()>
 __global__ __launch_bounds__(kBlock) void k_onesweep(Plan P, const K *__restrict__ kin,
                                                      const uint32_t *__restrict__ vin,
                                                      K *__restrict__ kout, uint32_t *__restrict__ vout,
@@ -220,7 +223,7 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(Plan P, const K *__restrict
                                                      uint64_t *__restrict__ status, uint32_t *ticket)
 {
     constexpr int W = kBlock / kWave;
-    constexpr int kItems = sort_items<K>();
+    constexpr int kItems = ITEMS;
     constexpr int kTile = kBlock * kItems;
     constexpr int PER_WAVE = kWave * kItems;
     constexpr int RADIX = 1 << radix_bits<K>();
@@ -455,6 +458,25 @@ void launch_bbox(int d, const int32_t *pts, uint32_t n, int32_t *partial, int bl
     }
 }
 
+template <int D, typename K, int ITEMS>
+static void sort_passes_d(const Plan &P, K *ka, K *kb, uint32_t *va, uint32_t *vb, const SortBuffers &B,
+                          hipStream_t s)
+{
+    const uint32_t tiles = (P.n + kBlock * ITEMS - 1) / (kBlock * ITEMS);
+    for (uint32_t q = 0; q < P.passes; q++) {
+        uint64_t *st = B.status + (uint64_t)q * tiles * kRadix;
+        const bool last = q + 1 == P.passes;
+        if (last)
+            hipLaunchKernelGGL((k_onesweep<K, D, true, ITEMS>), dim3(tiles), dim3(kBlock), 0, s, P, ka, va,
+                               kb, vb, q * P.digit_bits, B.hist + q * kRadix, st, B.tickets + q);
+        else
+            hipLaunchKernelGGL((k_onesweep<K, D, false, ITEMS>), dim3(tiles), dim3(kBlock), 0, s, P, ka,
+                               va, kb, vb, q * P.digit_bits, B.hist + q * kRadix, st, B.tickets + q);
+        K *tk = ka; ka = kb; kb = tk;
+        uint32_t *tv = va; va = vb; vb = tv;
+    }
+}
+
 template <int D, typename K>
 static void sort_d(const Plan &P, const SortBuffers &B, hipStream_t s)
 {
@@ -463,19 +485,15 @@ static void sort_d(const Plan &P, const SortBuffers &B, hipStream_t s)
     K *ka = (K *)B.keys_a, *kb = (K *)B.keys_b;
     uint32_t *va = B.vals_a, *vb = B.vals_b;
     hipLaunchKernelGGL((k_keys_hist<D, K>), dim3(hb), dim3(kBlock), 0, s, P, ka, va, B.hist);
-    const uint32_t tiles = (P.n + kBlock * sort_items<K>() - 1) / (kBlock * sort_items<K>());
-    for (uint32_t q = 0; q < P.passes; q++) {
-        uint64_t *st = B.status + (uint64_t)q * tiles * kRadix;
-        const bool last = q + 1 == P.passes;
-        if (last)
-            hipLaunchKernelGGL((k_onesweep<K, D, true>), dim3(tiles), dim3(kBlock), 0, s, P, ka, va,
-                               kb, vb, q * P.digit_bits, B.hist + q * kRadix, st, B.tickets + q);
-        else
-            hipLaunchKernelGGL((k_onesweep<K, D, false>), dim3(tiles), dim3(kBlock), 0, s, P, ka,
-                               va, kb, vb, q * P.digit_bits, B.hist + q * kRadix, st, B.tickets + q);
-        K *tk = ka; ka = kb; kb = tk;
-        uint32_t *tv = va; va = vb; vb = tv;
+    // 64-bit keys of up to four axes (batches) may take tiles of 4096 keys
+    // instead of 2048 when tuned so
+    if constexpr (sizeof(K) == 8 && D <= 4) {
+        if (P.sort_items == 16) {
+            sort_passes_d<D, K, 16>(P, ka, kb, va, vb, B, s);
+            return;
+        }
     }
+    sort_passes_d<D, K, sort_items<K>()>(P, ka, kb, va, vb, B, s);
 }
 
 // Returns via B.result_keys / result_vals which buffers hold the sorted data.

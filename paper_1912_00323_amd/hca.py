@@ -81,6 +81,14 @@ def load_library(path: str | Path | None = None) -> ctypes.CDLL:
     lib.hca_cluster.restype = ctypes.c_int
     lib.hca_cluster_noalloc.argtypes = [vp, vp, i64, i32, dbl, i32, vp]
     lib.hca_cluster_noalloc.restype = ctypes.c_int
+    lib.hca_batch_create.argtypes = [vp, i32, vp, vp, vp, vp, i32, vp]
+    lib.hca_batch_create.restype = ctypes.c_int
+    lib.hca_batch_run.argtypes = [vp, vp, vp]
+    lib.hca_batch_run.restype = ctypes.c_int
+    lib.hca_batch_stats.argtypes = [vp, vp, vp, i32]
+    lib.hca_batch_stats.restype = ctypes.c_int
+    lib.hca_batch_destroy.argtypes = [vp]
+    lib.hca_batch_destroy.restype = None
     lib.hca_cluster_ex.argtypes = [vp, vp, i64, i32, dbl, i32, vp, vp, ctypes.POINTER(Stats)]
     lib.hca_cluster_ex.restype = ctypes.c_int
     lib.hca_cluster_host.argtypes = [vp, vp, i64, i32, dbl, i32, vp]
@@ -110,6 +118,82 @@ def load_library(path: str | Path | None = None) -> ctypes.CDLL:
     if path is None:
         _lib = lib
     return lib
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("runs", ctypes.c_int64), ("graph_replays", ctypes.c_int64), ("plans", ctypes.c_int64),
+                ("groups", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class BatchGroupInfo(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("sets", ctypes.c_int32), ("rows", ctypes.c_int64),
+                ("key_bits", ctypes.c_int32), ("sort_passes", ctypes.c_int32), ("wide", ctypes.c_int32),
+                ("reps", ctypes.c_int32), ("lanes", ctypes.c_int32), ("prefix", ctypes.c_int32),
+                ("wave_blocks", ctypes.c_int32), ("hash_load", ctypes.c_int32), ("digit_cap", ctypes.c_int32),
+                ("sort_items", ctypes.c_int32), ("tuned", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tuned_ms", ctypes.c_double), ("default_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class Batch:
+    """A batch handle (hca_batch_*): batches of one fixed shape, the first run
+    planned, tuned and captured in a HIP graph, every later run one graph
+    launch.  tune: 0 default knobs, 1 cache then tune, 2 always tune."""
+
+    def __init__(self, ctx: "Context", rows, dims, eps, min_pts, tune: int = 1):
+        self._lib = ctx._lib
+        self._ctx = ctx
+        self.rows = [int(r) for r in rows]
+        self.dims = [int(d) for d in dims]
+        r = np.ascontiguousarray(self.rows, dtype=np.int64)
+        dm = np.ascontiguousarray(self.dims, dtype=np.int32)
+        ep = np.ascontiguousarray(eps, dtype=np.float64)
+        mp = np.ascontiguousarray(min_pts, dtype=np.int32)
+        if not (len(r) == len(dm) == len(ep) == len(mp)):
+            raise ValueError("rows, dims, eps and min_pts must have one entry per data set")
+        self._h = ctypes.c_void_p()
+        ctx._check(self._lib.hca_batch_create(ctx._ctx, len(r), r.ctypes.data_as(ctypes.c_void_p),
+                                              dm.ctypes.data_as(ctypes.c_void_p),
+                                              ep.ctypes.data_as(ctypes.c_void_p),
+                                              mp.ctypes.data_as(ctypes.c_void_p), int(tune), ctypes.byref(self._h)))
+
+    def run(self, points, labels):
+        """Cluster one batch: points[i] a contiguous CUDA int32 tensor
+        [rows[i], dims[i]], labels[i] a CUDA int32 tensor of rows[i]."""
+        import torch
+        n = len(self.rows)
+        if len(points) != n or len(labels) != n:
+            raise ValueError(f"{n} data sets expected")
+        for i, (p, o) in enumerate(zip(points, labels)):
+            if not (isinstance(p, torch.Tensor) and p.is_cuda and p.dtype == torch.int32 and p.is_contiguous()
+                    and p.numel() == self.rows[i] * self.dims[i]):
+                raise TypeError(f"points[{i}] must be a contiguous CUDA int32 tensor of {self.rows[i]} x "
+                                f"{self.dims[i]}")
+            check_labels(o, self.rows[i], p.device, f"labels[{i}]")
+        pp = (ctypes.c_void_p * n)(*[p.data_ptr() for p in points])
+        ll = (ctypes.c_void_p * n)(*[o.data_ptr() for o in labels])
+        self._ctx.set_stream(torch.cuda.current_stream(points[0].device).cuda_stream)
+        self._ctx._check(self._lib.hca_batch_run(self._h, pp, ll))
+
+    def stats(self) -> dict:
+        info = BatchInfo()
+        groups = (BatchGroupInfo * 8)()
+        self._ctx._check(self._lib.hca_batch_stats(self._h, ctypes.byref(info), groups, 8))
+        return {"runs": info.runs, "graph_replays": info.graph_replays, "plans": info.plans,
+                "groups": [groups[i].as_dict() for i in range(info.groups)]}
+
+    def close(self):
+        if self._h:
+            self._lib.hca_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def check_labels(t, n: int, device, what: str = "out"):
