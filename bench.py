@@ -167,6 +167,10 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="2d")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--requests", type=int, default=10_000, help="served workload: distinct requests")
+    ap.add_argument("--slo-ms", type=float, default=250.0, help="served workload: p99 latency objective")
+    ap.add_argument("--batch-ms", type=float, default=4.0,
+                    help="served workload: estimated device time a batch may gather")
     ap.add_argument("--no-second", action="store_true",
                     help="2d workload: skip the 8-D 500k workload that is measured beside it")
     ap.add_argument("--merge", choices=("exact", "representatives"), default="exact",
@@ -340,9 +344,12 @@ def disagreement(exact, approx) -> dict:
 
 def bench_batch(args) -> int:
     """The batched workload: 256 independent data sets (n log-uniform in
-    [1e3, 2e5], d in {2, 3, 4}, per-set eps and minPts) clustered by one
-    hca_cluster_batch call per step; the plain path (one hca_cluster call per
-    data set) is timed on the same data beside it."""
+    [1e3, 2e5], d in {2, 3, 4}, per-set eps and minPts).  One step = one
+    batch through a batch handle: a graph launch of the plan captured (and
+    tuned) on the handle's first run.  Timed beside it on the same data: the
+    same handle with default knobs, the host-planned batch call
+    (hca_cluster_batch) and the plain path (one hca_cluster call per set)."""
+    import tempfile
     import torch
     import numpy as np
     from paper_1912_00323_amd import hca
@@ -351,46 +358,66 @@ def bench_batch(args) -> int:
     jobs = make_batch(seed=4, count=256)
     total = sum(j.n for j in jobs)
     dev = torch.device("cuda:0")
-    flat = torch.from_numpy(np.concatenate([j.points.reshape(-1) for j in jobs])).to(dev)
     rows = [j.n for j in jobs]
     dims = [j.d for j in jobs]
     eps = [j.eps for j in jobs]
     mps = [j.min_pts for j in jobs]
-    labels = torch.empty(total, dtype=torch.int32, device=dev)
+    sets = [torch.from_numpy(j.points).to(dev) for j in jobs]
+    outs = [torch.empty(j.n, dtype=torch.int32, device=dev) for j in jobs]
     ctx = hca.Context(0)
     ctx.set_stream(torch.cuda.current_stream(dev).cuda_stream)
+
+    def timed(fn, steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    # the tuned handle (a fresh cache, so the tuning is measured every run)
+    cache = tempfile.NamedTemporaryFile(prefix="hca_tune_", suffix=".json", delete=False).name
+    os.environ["HCA_TUNE_CACHE"] = cache
+    tuned = hca.Batch(ctx, rows, dims, eps, mps, tune=2)
+    t_first = timed(lambda: tuned.run(sets, outs), 1)        # plan + tune + capture
     for _ in range(args.warmup):
-        ctx.cluster_batch(flat, rows, dims, eps, mps, out=labels)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ctx.cluster_batch(flat, rows, dims, eps, mps, out=labels)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-
+        tuned.run(sets, outs)
+    dt = timed(lambda: tuned.run(sets, outs), args.steps)
+    graph_labels = [o.clone() for o in outs]
+    st = tuned.stats()
+    default = hca.Batch(ctx, rows, dims, eps, mps, tune=0)
+    default.run(sets, outs)
+    dt_default = timed(lambda: default.run(sets, outs), max(3, args.steps // 2))
+    same_default = all(torch.equal(a, b) for a, b in zip(graph_labels, outs))
+    # the host-planned batch call (phase times of its groups for the roofline)
+    flat = torch.from_numpy(np.concatenate([j.points.reshape(-1) for j in jobs])).to(dev)
+    labels = torch.empty(total, dtype=torch.int32, device=dev)
+    ctx.cluster_batch(flat, rows, dims, eps, mps, out=labels)
+    dt_planned = timed(lambda: ctx.cluster_batch(flat, rows, dims, eps, mps, out=labels), max(3, args.steps // 2))
+    same_planned = bool(torch.equal(torch.cat(graph_labels), labels))
+    ctx.set_profiling("all")
+    ctx.cluster_batch(flat, rows, dims, eps, mps, out=labels)
+    phase_ms = ctx.phase_times()
+    ctx.set_profiling(None)
     # the plain path on the same data: one call per data set, inputs resident
-    singles = [torch.from_numpy(j.points).to(dev) for j in jobs]
-    outs = [torch.empty(j.n, dtype=torch.int32, device=dev) for j in jobs]
-    for x, o, j in zip(singles, outs, jobs):
+    for x, o, j in zip(sets, outs, jobs):
         ctx.cluster(x, j.eps, j.min_pts, out=o)
-    reps = max(1, min(3, args.steps))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(reps):
-        for x, o, j in zip(singles, outs, jobs):
-            ctx.cluster(x, j.eps, j.min_pts, out=o)
-    torch.cuda.synchronize()
-    dt_plain = (time.perf_counter() - t1) / reps
-    same = bool(torch.equal(torch.cat(outs), labels))
+    dt_plain = timed(lambda: [ctx.cluster(x, j.eps, j.min_pts, out=o) for x, o, j in zip(sets, outs, jobs)],
+                     max(1, min(3, args.steps)))
+    same_plain = all(torch.equal(a, b) for a, b in zip(graph_labels, outs))
 
-    # binning and sort bytes of every data set against the whole call
-    ab = sum(algorithmic_bytes("sort", j.n, j.d, 8, 5, 0) + algorithmic_bytes("bbox", j.n, j.d, 8, 5, 0)
-             for j in jobs)
-    ms = dt * 1e3 / args.steps
-    achieved = ab / (ms * 1e-3) / 1e9
+    # binning and sort bytes of every group from its plan's key width and
+    # passes, against the sort phase of the host-planned call
+    ab = 0.0
+    for g in st["groups"]:
+        kb = 8 if g["key_bits"] > 32 else 4
+        ab += algorithmic_bytes("sort", g["rows"], g["d"], kb, g["sort_passes"], 0)
+    sort_ms = phase_ms["sort"]
+    achieved = ab / (sort_ms * 1e-3) / 1e9 if sort_ms > 0 else None
+    ms = dt * 1e3
     line = {
         "metric": METRIC,
-        "value": total * args.steps / dt,
+        "value": total / dt,
         "unit": "points/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -402,17 +429,28 @@ def bench_batch(args) -> int:
         "dtype": "i32",
         "data": "synthetic",
         "config": {"workload": "batch256_mixed", "jobs": len(jobs), "points": total,
-                   "d": sorted(set(dims)), "parallelism": "single-gpu"},
+                   "d": sorted(set(dims)), "parallelism": "single-gpu", "form": "batch handle, one graph launch"},
+        "graph": {"replays": st["graph_replays"], "plans": st["plans"], "first_run_ms": round(t_first * 1e3, 2),
+                  "groups": st["groups"]},
+        "default_knobs": {"ms_per_batch": round(dt_default * 1e3, 3), "labels_identical": same_default},
+        "tuned_vs_default": round(dt_default / dt, 3),
+        "host_planned_batch": {"ms_per_batch": round(dt_planned * 1e3, 3), "labels_identical": same_planned},
         "plain_path": {"value": total / dt_plain, "unit": "points/s", "ms_per_batch": round(dt_plain * 1e3, 3),
-                       "calls": len(jobs), "labels_identical": same},
-        "speedup_vs_plain": round((total * args.steps / dt) / (total / dt_plain), 3),
-        "roofline": {"bound": "hbm", "phase": "whole batch call (binning and sort bytes only)",
-                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "algorithmic_bytes": ab},
+                       "calls": len(jobs), "labels_identical": same_plain},
+        "speedup_vs_plain": round(dt_plain / dt, 3),
+        "phase_ms": {p: round(v, 4) for p, v in phase_ms.items() if v > 0},
+        "roofline": {"bound": "hbm", "phase": "sort (all groups, host-planned call)",
+                     "kernels": PHASE_KERNELS["sort"], "achieved": round(achieved, 1) if achieved else None,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None, "traffic": None,
+                     "traffic_source": "no PMC run of the batched sequence",
+                     "algorithmic_bytes": ab, "phase_ms": round(sort_ms, 4)},
     }
+    tuned.close()
+    default.close()
     if not args.no_cpu_baseline:
         import oracle
-        threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+        threads = host_threads()
         done, pts_done, t_start = 0, 0, time.perf_counter()
         while done < len(jobs) and time.perf_counter() - t_start < 20.0:
             j = jobs[done]
@@ -422,51 +460,57 @@ def bench_batch(args) -> int:
         tcpu = time.perf_counter() - t_start
         line["cpu_baseline"] = {"value": pts_done / tcpu, "unit": "points/s", "cores": threads, "kind": "oracle",
                                 "sample": f"the first {done} of the {len(jobs)} data sets ({pts_done} points), "
-                                          f"one oracle.hca_grid call each"}
+                                          f"one oracle.hca_grid call each", "cpu_model": cpu_model()}
     print(json.dumps(line), flush=True)
     ctx.close()
+    try:
+        os.unlink(cache)
+    except OSError:
+        pass
     return 0
 
 
-def bench_served(args, pool_size: int = 48, requests: int = 400, loads=(0.8, 1.0, 1.25, 1.5),
-                 main_load: float = 1.25, workers: int = 2) -> int:
-    """The served workload: Poisson arrivals of clustering requests (n
-    log-uniform in [1e4, 2e6], d in {2, 3, 5}, per-request eps and minPts) at
+def bench_served(args, loads=(0.6, 0.9, 1.2, 1.5), workers: int = 2) -> int:
+    """The served workload: Poisson arrivals of --requests distinct clustering
+    requests (n log-uniform in [1e4, 2e6], d in {2, 3, 5}, per-request eps and
+    minPts; points drawn on the device from a seeded torch generator) at
     several loads, given as multiples of the request rate the plain sequential
     path sustains.  The request loop (hca_server: continuous batching over
-    `workers` workers) and the plain path (one hca_cluster call at a time, in
-    arrival order) replay the same arrival trace; latency = completion -
-    arrival.  Both also run saturated (every request at time 0)."""
+    `workers` workers, batches bounded by estimated device time) and the
+    plain path (one hca_cluster call at a time, in arrival order) replay the
+    same arrival trace; latency = completion - arrival.  Each path's
+    throughput is compared at the highest load whose p99 stays within the
+    SLO (--slo-ms)."""
     import torch
     import numpy as np
     from paper_1912_00323_amd import hca
-    from paper_1912_00323_amd.datagen import make_served, poisson_arrivals
+    from paper_1912_00323_amd.datagen import device_request, poisson_arrivals, served_requests
 
-    pool = make_served(seed=5, count=pool_size)
+    reqs = served_requests(seed=5, count=args.requests)
     dev = torch.device("cuda:0")
-    xs = [torch.from_numpy(j.points).to(dev) for j in pool]
+    xs = [device_request(r, dev) for r in reqs]
+    outs = [torch.empty(r["n"], dtype=torch.int32, device=dev) for r in reqs]
+    points = sum(r["n"] for r in reqs)
     ctx = hca.Context(0)
     ctx.set_stream(torch.cuda.current_stream(dev).cuda_stream)
-    ref = [ctx.cluster(x, j.eps, j.min_pts) for x, j in zip(xs, pool)]   # warm-up, reference labels
+    # reference labels and the plain path's sustained rate (one pass, warm)
+    ref = [ctx.cluster(x, r["eps"], r["min_pts"]) for x, r in zip(xs[:64], reqs[:64])]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for x, j in zip(xs, pool):
-        ctx.cluster(x, j.eps, j.min_pts)
+    ref = [ctx.cluster(x, r["eps"], r["min_pts"]) for x, r in zip(xs, reqs)]
     torch.cuda.synchronize()
-    plain_rate = len(pool) / (time.perf_counter() - t0)  # requests/s the plain path sustains
-    which = [k % len(pool) for k in range(requests)]
-    points = sum(pool[w].n for w in which)
-    outs = [torch.empty(pool[w].n, dtype=torch.int32, device=dev) for w in which]
-    srv = hca.Server(0, workers=workers, budget_bytes=48 << 30, max_batch=64)
+    plain_rate = len(reqs) / (time.perf_counter() - t0)
+    srv = hca.Server(0, workers=workers, budget_bytes=48 << 30, max_batch=64, batch_ms=args.batch_ms)
     same = True
+    count = len(reqs)
 
     def plain(arr):
         lat = []
         start = hca.clock() + 0.02
-        for k, w in enumerate(which):
+        for k, r in enumerate(reqs):
             while hca.clock() < start + arr[k]:
                 pass
-            ctx.cluster(xs[w], pool[w].eps, pool[w].min_pts, out=outs[k])
+            ctx.cluster(xs[k], r["eps"], r["min_pts"], out=outs[k])
             lat.append(hca.clock() - (start + arr[k]))
         return lat, hca.clock() - start
 
@@ -476,17 +520,17 @@ def bench_served(args, pool_size: int = 48, requests: int = 400, loads=(0.8, 1.0
             o.fill_(-9)
         done = {}
         start = hca.clock() + 0.02
-        for k, w in enumerate(which):
+        for k, r in enumerate(reqs):
             while hca.clock() < start + arr[k]:
                 for t, st, td in srv.poll():
                     done[t] = (st, td)
-            srv.submit(xs[w], pool[w].eps, pool[w].min_pts, outs[k], tag=k)
+            srv.submit(xs[k], r["eps"], r["min_pts"], outs[k], tag=k)
         srv.drain()
-        for t, st, td in srv.poll(1 << 16):
+        for t, st, td in srv.poll(1 << 20):
             done[t] = (st, td)
-        same = same and all(done[k][0] == 0 and torch.equal(outs[k], ref[w]) for k, w in enumerate(which))
-        lat = [done[k][1] - (start + arr[k]) for k in range(requests)]
-        return lat, max(done[k][1] for k in range(requests)) - start
+        same = same and all(done[k][0] == 0 and torch.equal(outs[k], ref[k]) for k in range(count))
+        lat = [done[k][1] - (start + arr[k]) for k in range(count)]
+        return lat, max(done[k][1] for k in range(count)) - start
 
     def summary(lat, span):
         v = np.asarray(lat) * 1e3
@@ -495,37 +539,52 @@ def bench_served(args, pool_size: int = 48, requests: int = 400, loads=(0.8, 1.0
 
     sweep = {}
     for load in loads:
-        arr = poisson_arrivals(5, requests, load * plain_rate)
-        sweep[str(load)] = {"served": summary(*served(arr)), "plain_sequential": summary(*plain(arr))}
-    zero = np.zeros(requests)
+        arr = poisson_arrivals(5, count, load * plain_rate)
+        sweep[str(load)] = {"arrival_rate_per_s": round(load * plain_rate, 2),
+                            "served": summary(*served(arr)), "plain_sequential": summary(*plain(arr))}
+        print(f"[load {load}] {json.dumps(sweep[str(load)])}", file=sys.stderr, flush=True)
+    zero = np.zeros(count)
     saturated = {"served": summary(*served(zero)), "plain_sequential": summary(*plain(zero))}
     srv.close()
     ctx.close()
-    main = sweep[str(main_load)]
+
+    def at_slo(path):
+        ok = [float(l) for l in sweep if sweep[l][path]["p99_ms"] <= args.slo_ms]
+        if not ok:
+            return None
+        best = str(max(ok))
+        return {"load": float(best), "points_per_s": sweep[best][path]["points_per_s"],
+                "p99_ms": sweep[best][path]["p99_ms"]}
+
+    slo = {"slo_ms": args.slo_ms, "served": at_slo("served"), "plain_sequential": at_slo("plain_sequential")}
+    main = max(sweep, key=lambda l: (sweep[l]["served"]["p99_ms"] <= args.slo_ms, float(l)))
     line = {
         "metric": METRIC,
-        "value": main["served"]["points_per_s"],
+        "value": sweep[main]["served"]["points_per_s"],
         "unit": "points/s",
         "n_gpus": 1,
-        "steps": requests,
-        "warmup": len(pool),
-        "ms_per_step": round(points / main["served"]["points_per_s"] * 1e3 / requests, 4),
+        "steps": count,
+        "warmup": 64,
+        "ms_per_step": round(points / sweep[main]["served"]["points_per_s"] * 1e3 / count, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "i32",
-        "data": "synthetic",
-        "config": {"workload": "served_poisson", "requests": requests, "pool": len(pool), "load_vs_plain": main_load,
-                   "arrival_rate_per_s": round(main_load * plain_rate, 3), "points": points,
-                   "d": sorted(set(j.d for j in pool)), "workers": workers, "parallelism": "single-gpu"},
-        "served": main["served"],
-        "plain_sequential": main["plain_sequential"] | {"sustained_requests_per_s": round(plain_rate, 3)},
+        "data": "synthetic (drawn on the device from a seeded torch generator)",
+        "config": {"workload": "served_poisson", "requests": count, "load_vs_plain": float(main),
+                   "arrival_rate_per_s": round(float(main) * plain_rate, 3), "points": points,
+                   "d": sorted(set(r["d"] for r in reqs)), "workers": workers, "batch_ms": args.batch_ms,
+                   "parallelism": "single-gpu"},
+        "served": sweep[main]["served"],
+        "plain_sequential": sweep[main]["plain_sequential"] | {"sustained_requests_per_s": round(plain_rate, 3)},
+        "throughput_at_slo": slo,
         "load_sweep": sweep,
         "saturated": saturated,
         "labels_identical": bool(same),
-        "roofline": {"bound": "alu", "phase": "served requests (mixed phases)", "achieved": None,
-                     "peak": round(ALU_PEAK_TOPS, 2), "unit": "Tops/s (int32 lane-ops)", "frac": None,
-                     "traffic": None},
+        "roofline": {"bound": None, "phase": None, "achieved": None, "peak": None, "unit": None, "frac": None,
+                     "traffic": None,
+                     "reason": "requests of 2, 3 and 5 axes run different launch sequences side by side; the "
+                               "roofline of each is that of the plain path at its shape (the 2-D and 8-D lines)"},
     }
     print(json.dumps(line), flush=True)
     return 0

@@ -304,6 +304,10 @@ void hca_batch_destroy(hca_batch *b);
  *     returns the tag, the labels are final and visible to every stream.
  *     HCA_E_INVAL for bad arguments or after destroy began; HCA_E_DEVICE if
  *     the event cannot be recorded.
+ *   hca_server_set_batch_time: a batch takes the next requests only while
+ *     their estimated device time (from rows and d) stays within ms
+ *     (default 4), so that small requests are not held behind large ones;
+ *     HCA_E_INVAL unless ms > 0.
  *   hca_server_poll: move up to max completed requests into tags, status
  *     (the clustering call's status) and t_done (hca_clock seconds);
  *     returns how many.  HOST arrays owned by the caller.
@@ -316,6 +320,7 @@ hca_status hca_server_create(hca_server **out, int32_t device, int32_t workers, 
                              int32_t max_batch);
 hca_status hca_server_submit(hca_server *srv, const int32_t *points, int64_t n, int32_t d, double eps,
                              int32_t min_pts, int32_t *labels, uint64_t tag, void *after_stream);
+hca_status hca_server_set_batch_time(hca_server *srv, double ms);
 int32_t hca_server_poll(hca_server *srv, uint64_t *tags, int32_t *status, double *t_done, int32_t max);
 hca_status hca_server_drain(hca_server *srv);
 void hca_server_destroy(hca_server *srv);

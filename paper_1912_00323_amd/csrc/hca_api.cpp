@@ -220,6 +220,18 @@ uint32_t key_passes(uint32_t key_bits, bool wide, const Tune *t = nullptr)
     return key_bits ? (key_bits + rb - 1) / rb : 1u;
 }
 
+// HCA_ORDER=reverse|permute: the wave-dealt units of the neighbour phases
+// taken in reverse or permuted order (tests: the result must not depend on
+// the schedule)
+uint32_t env_order()
+{
+    const char *e = std::getenv("HCA_ORDER");
+    if (!e) return 0;
+    if (!std::strcmp(e, "reverse")) return 1;
+    if (!std::strcmp(e, "permute")) return 2;
+    return 0;
+}
+
 bool env_reps()
 {
     const char *e = std::getenv("HCA_REPS");
@@ -466,6 +478,7 @@ void plan_sizes(Plan &P, uint32_t gbits, bool count_work, bool want_stats, Sizes
     P.work_cap = (uint32_t)std::min<uint64_t>(4ull * n + 1024, 1ull << 30) / kWorkRegions * kWorkRegions;
     P.want_stats = want_stats;
     P.count_work = count_work;
+    P.order = env_order();
     // persistent grids of the neighbour phases: enough waves to fill the chip
     int persist = kPersistBlocks;
     if (const char *e = std::getenv("HCA_WAVE_BLOCKS")) persist = std::max(8, std::atoi(e));

@@ -108,15 +108,26 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T *smem, T *total)
 // XCDs; within an XCD the waves take its units in turn.
 constexpr uint32_t kXcdRun = 32;
 
+// Tests of the result's independence of scheduling take the units in
+// another order (order 1: reversed, 2: a fixed permutation, u -> u * a mod
+// units with a prime a that does not divide units); 0 keeps them as dealt.
+__device__ __forceinline__ uint32_t unit_remap(uint32_t u, uint32_t units, uint32_t order)
+{
+    if (order == 0 || u >= units) return u;
+    if (order == 1) return units - 1u - u;
+    constexpr uint32_t kPrime = 2654435761u;
+    return units == kPrime ? u : (uint32_t)(((uint64_t)u * kPrime) % units);
+}
+
 struct WaveRange {
-    uint32_t first, step, xcd;
+    uint32_t first, step, xcd, order;
     __device__ __forceinline__ uint32_t unit(uint32_t k) const
     {
         return ((k / kXcdRun) * 8u + xcd) * kXcdRun + (k % kXcdRun);
     }
 };
 
-__device__ __forceinline__ WaveRange wave_range()
+__device__ __forceinline__ WaveRange wave_range(uint32_t order = 0)
 {
     const uint32_t nb = gridDim.x, b = blockIdx.x;
     const uint32_t xcd = b & 7u, bx = b >> 3;
@@ -125,14 +136,16 @@ __device__ __forceinline__ WaveRange wave_range()
     r.first = bx * (kBlock / kWave) + wave_in_block();
     r.step = nbx * (kBlock / kWave);
     r.xcd = xcd;
+    r.order = order;
     return r;
 }
 
-// for (unit u of this wave) { ... }: units grow with k, so the first one past
-// the end closes the loop.
-#define HCA_FOR_UNITS(u, units)                                                         \
-    for (uint32_t k_ = hca_wr_.first, u = hca_wr_.unit(k_); u < (units);                \
-         k_ += hca_wr_.step, u = hca_wr_.unit(k_))
+// for (unit u of this wave) { ... }: the dealt units grow with k, so the
+// first one past the end closes the loop; u is that unit taken in the
+// range's order.
+#define HCA_FOR_UNITS(u, units)                                                                     \
+    for (uint32_t k_ = hca_wr_.first, r_ = hca_wr_.unit(k_), u = unit_remap(r_, (units), hca_wr_.order); \
+         r_ < (units); k_ += hca_wr_.step, r_ = hca_wr_.unit(k_), u = unit_remap(r_, (units), hca_wr_.order))
 
 // Dynamic form, for units of very uneven cost: the units an XCD owns (as
 // above) are dealt round-robin to its queues; each wave takes its next unit
@@ -141,12 +154,12 @@ __device__ __forceinline__ WaveRange wave_range()
 // the loop.
 struct DynRange {
     uint32_t *cnt;
-    uint32_t xcd, q, nq;
+    uint32_t xcd, q, nq, order;
 };
 
 // The grid is a multiple of 8 blocks, so every XCD holds gridDim.x / 8 blocks
 // of 4 waves; an XCD has min(8, its waves) queues, each with a wave.
-__device__ __forceinline__ DynRange dyn_range(uint32_t *queues)
+__device__ __forceinline__ DynRange dyn_range(uint32_t *queues, uint32_t order = 0)
 {
     const uint32_t b = blockIdx.x;
     DynRange d;
@@ -154,6 +167,7 @@ __device__ __forceinline__ DynRange dyn_range(uint32_t *queues)
     d.nq = min(8u, (gridDim.x >> 3) * (kBlock / kWave));
     d.q = ((b >> 3) * (kBlock / kWave) + wave_in_block()) % d.nq;
     d.cnt = queues + (d.xcd * 8u + d.q) * kCounterStride;
+    d.order = order;
     return d;
 }
 
@@ -166,7 +180,9 @@ __device__ __forceinline__ uint32_t dyn_next(const DynRange &d)
     return ((k / kXcdRun) * 8u + d.xcd) * kXcdRun + (k % kXcdRun);
 }
 
-#define HCA_FOR_UNITS_DYN(u, units, dr) for (uint32_t u = dyn_next(dr); u < (units); u = dyn_next(dr))
+#define HCA_FOR_UNITS_DYN(u, units, dr)                                                          \
+    for (uint32_t r_ = dyn_next(dr), u = unit_remap(r_, (units), (dr).order); r_ < (units);    \
+         r_ = dyn_next(dr), u = unit_remap(r_, (units), (dr).order))
 
 // ---- work counters ----------------------------------------------------------
 // Pair tests a lane executed; one atomic per wave, spread over many lines.

@@ -382,7 +382,7 @@ __global__ __launch_bounds__(kBlock) void k_group_box(Plan P)
 {
     const uint32_t l = lane_id();
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
-    const WaveRange hca_wr_ = wave_range();
+    const WaveRange hca_wr_ = wave_range(P.order);
     HCA_FOR_UNITS(g, ng) {
         const QBox<D> b = group_points_box<D>(P, P.group_start[g], P.group_start[g + 1]);
         if (l < (uint32_t)D) {
@@ -605,7 +605,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr_lists(Plan P)
     uint32_t at = (blockIdx.x * kWavesPerBlock + w) * slab;
     const uint32_t end = at + slab;
     uint32_t overflow = 0;
-    const DynRange dr_ = dyn_range(P.ctr->dyn[kDynLists]);
+    const DynRange dr_ = dyn_range(P.ctr->dyn[kDynLists], P.order);
     HCA_FOR_UNITS_DYN(g, ng, dr_) {
         const uint64_t gkey = P.group_key[g];
         const Geo<D> geo = cube_geo<D>(P, gkey);
@@ -762,7 +762,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr_back(Plan P)
     if (P.ctr->nbr_overflow) return;                     // lists unused
     const uint32_t l = lane_id();
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
-    const WaveRange hca_wr_ = wave_range();
+    const WaveRange hca_wr_ = wave_range(P.order);
     HCA_FOR_UNITS(g, ng) {
         const uint32_t s0 = P.nbr_start[g], c = P.nbr_count[g];
         for (uint32_t k = l; k < c; k += kWave) {
@@ -849,7 +849,7 @@ __global__ __launch_bounds__(kBlock) void k_core(Plan P)
     const uint32_t w = wave_in_block(), l = lane_id();
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
     uint32_t lt = 0;
-    const WaveRange hca_wr_ = wave_range();
+    const WaveRange hca_wr_ = wave_range(P.order);
     HCA_FOR_UNITS(g, ng) {
         const uint32_t p0 = P.group_start[g], p1 = P.group_start[g + 1];
         const uint32_t c0 = P.group_cell[g], c1 = P.group_cell[g + 1];
@@ -947,7 +947,7 @@ __global__ __launch_bounds__(kBlock, 6) void k_core_chunks(Plan P)
     const Geo<D> geo = call_geo<D>(P);
     const uint32_t all = (1u << kPch) - 1u;
     uint32_t lt = 0;
-    const DynRange dr_ = dyn_range(P.ctr->dyn[kDynCore]);
+    const DynRange dr_ = dyn_range(P.ctr->dyn[kDynCore], P.order);
     HCA_FOR_UNITS_DYN(u, (n + kPch - 1) / kPch, dr_) {
         const uint32_t pc = u * kPch, np = min((uint32_t)kPch, n - pc);
         // lane k < np: cube, group and density of point pc + k
@@ -1371,7 +1371,7 @@ __global__ __launch_bounds__(kBlock) void k_reps(Plan P)
 #pragma unroll
     for (int k = 0; k < D; k++) { zero += mul; mul *= 3; }
     const uint32_t chunks = (P.n + kWave - 1) / kWave;
-    const WaveRange hca_wr_ = wave_range();
+    const WaveRange hca_wr_ = wave_range(P.order);
     HCA_FOR_UNITS(ch, chunks) {
         const uint32_t q = ch * kWave + l;
         const bool in = q < P.n;
@@ -1523,7 +1523,7 @@ __global__ __launch_bounds__(kBlock) void k_reps_big(Plan P)
 {
     constexpr int ND = rep_dirs<D>();
     const uint32_t nch = ld_agent32(&P.ctr->n_chunks), l = lane_id();
-    const WaveRange hca_wr_ = wave_range();
+    const WaveRange hca_wr_ = wave_range(P.order);
     HCA_FOR_UNITS(u, nch) {
         const uint32_t c = P.rep_chunks[2ull * u], k = P.rep_chunks[2ull * u + 1];
         const uint64_t gkey = P.group_key[c];
@@ -1652,7 +1652,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_rep(Plan P)
     const uint32_t l = lane_id();
     uint32_t lt = 0;
     const uint32_t nc = ld_agent32(&P.ctr->n_cells);
-    const WaveRange hca_wr_ = wave_range();
+    const WaveRange hca_wr_ = wave_range(P.order);
     const bool lists = P.nbr_cap && P.ctr->nbr_overflow == 0;
     const uint64_t flat_units = ((uint64_t)nc * P.n_off + kWave - 1) / kWave;
     if (!lists && flat_units <= 0xffffffffull) {
@@ -1738,7 +1738,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_cubes(Plan P)
     const uint32_t ns = ld_agent32(&P.ctr->n_small), ncc = ns + ld_agent32(&P.ctr->n_big);
     const uint64_t pairs = (uint64_t)ncc * nf;
     uint32_t lt = 0;
-    const WaveRange hca_wr_ = wave_range();
+    const WaveRange hca_wr_ = wave_range(P.order);
     HCA_FOR_UNITS(wu, (uint32_t)((pairs + kWave - 1) / kWave)) {
         const uint64_t u = (uint64_t)wu * kWave + l;
         uint32_t A = kNone, B = kNone, dfw = 0, dbw = 0;
@@ -1806,7 +1806,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_exact(Plan P)
     __builtin_amdgcn_wave_barrier();
     const uint32_t items = lane_value(inc, kWave - 1);
     uint32_t lt = 0;
-    const WaveRange hca_wr_ = wave_range();
+    const WaveRange hca_wr_ = wave_range(P.order);
     HCA_FOR_UNITS(it, items) {
         const uint32_t r = candidate_lane(it, s_pre[w]);
         const uint64_t at = (uint64_t)r * cap + (it - s_pre[w][r]);
@@ -1893,7 +1893,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_tiles(Plan P)
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
     const uint32_t total = ld_agent32(&P.ctr->n_tiles);
     uint32_t lt = 0;
-    const WaveRange hca_wr_ = wave_range();
+    const WaveRange hca_wr_ = wave_range(P.order);
     HCA_FOR_UNITS(u, total) {
         // group: last g with tile_start[g] <= u
         uint32_t lo = 0, hi = ng;
@@ -1963,7 +1963,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_unify(Plan P)
 {
     const uint32_t l = lane_id();
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
-    const WaveRange hca_wr_ = wave_range();
+    const WaveRange hca_wr_ = wave_range(P.order);
     HCA_FOR_UNITS(g, ng) {
         const uint32_t p0 = P.group_start[g], p1 = P.group_start[g + 1];
         const uint32_t c0 = P.group_cell[g], c1 = P.group_cell[g + 1];
@@ -2135,7 +2135,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_merge_inter(Plan P)
     const uint32_t cap = pair_tile_cap(P);
     uint32_t lt = 0;
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
-    const DynRange dr_ = dyn_range(P.ctr->dyn[kDynMerge]);
+    const DynRange dr_ = dyn_range(P.ctr->dyn[kDynMerge], P.order);
     HCA_FOR_UNITS_DYN(GA, ng, dr_) {
         const uint32_t ga = P.gcube[GA];
         if (ga == kNone) continue;                                 // no core point
@@ -2260,7 +2260,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_pairs(Plan P)
     __builtin_amdgcn_wave_barrier();
     const uint32_t items = lane_value(inc, kWave - 1);
     uint32_t lt = 0;
-    const WaveRange hca_wr_ = wave_range();
+    const WaveRange hca_wr_ = wave_range(P.order);
     HCA_FOR_UNITS(it, items) {
         const uint32_t r = candidate_lane(it, s_pre[w]);
         const uint32_t *e = P.work + 4ull * ((uint64_t)r * cap + (it - s_pre[w][r]));
@@ -2417,7 +2417,7 @@ __global__ __launch_bounds__(kBlock) void k_border_walk_list(Plan P)
     // a short list: one point per wave, so that the walks run side by side
     const uint32_t per = nl >= (uint32_t)kPch * gridDim.x * kWavesPerBlock ? (uint32_t)kPch : 1u;
     uint32_t lt = 0;
-    const DynRange dr_ = dyn_range(P.ctr->dyn[kDynBorder]);
+    const DynRange dr_ = dyn_range(P.ctr->dyn[kDynBorder], P.order);
     HCA_FOR_UNITS_DYN(u, (nl + per - 1) / per, dr_) {
         const uint32_t b0 = u * per, np = min(per, nl - b0);
         uint32_t pos[kPch];
@@ -2476,7 +2476,7 @@ __global__ __launch_bounds__(kBlock) void k_border(Plan P)
     const uint32_t w = wave_in_block(), l = lane_id();
     uint32_t lt = 0;
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
-    const DynRange dr_ = dyn_range(P.ctr->dyn[kDynBorder]);
+    const DynRange dr_ = dyn_range(P.ctr->dyn[kDynBorder], P.order);
     HCA_FOR_UNITS_DYN(g, ng, dr_) {
         const uint32_t p0 = P.group_start[g], p1 = P.group_start[g + 1];
         const uint64_t gkey = P.group_key[g];
@@ -2513,7 +2513,7 @@ __global__ __launch_bounds__(kBlock) void k_border_chunks(Plan P)
     const uint32_t n = P.n;
     const Geo<D> geo = call_geo<D>(P);
     uint32_t lt = 0;
-    const DynRange dr_ = dyn_range(P.ctr->dyn[kDynBorder]);
+    const DynRange dr_ = dyn_range(P.ctr->dyn[kDynBorder], P.order);
     HCA_FOR_UNITS_DYN(u, (n + kPch - 1) / kPch, dr_) {
         const uint32_t pc = u * kPch, np = min((uint32_t)kPch, n - pc);
         const bool mine = l < np && !P.core[pc + l] && !rec_complete(P, pc + l);

@@ -42,7 +42,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_group_box(Plan P)
 {
     const uint32_t l = lane_id(), sd = P.sd;
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
-    const WaveRange hca_wr_ = wave_range();
+    const WaveRange hca_wr_ = wave_range(P.order);
     HCA_FOR_UNITS(g, ng) {
         const uint32_t p0 = P.group_start[g], p1 = P.group_start[g + 1];
         if (l < sd) {
@@ -178,7 +178,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_lists(Plan P)
     uint32_t at = (blockIdx.x * kWavesPerBlock + w) * slab;
     const uint32_t end = at + slab;
     uint32_t overflow = 0;
-    const DynRange dr_ = dyn_range(P.ctr->dyn[kDynLists]);
+    const DynRange dr_ = dyn_range(P.ctr->dyn[kDynLists], P.order);
     HCA_FOR_UNITS_DYN(g, ng, dr_) {
         const uint64_t gkey = P.group_key[g];
         const int32_t *gb = P.gbox + (uint64_t)g * 2 * sd;
@@ -568,7 +568,7 @@ __global__ __launch_bounds__(kBlock, ROW == kRowPacked ? 5 : 1) void k_hd_core(P
     const uint32_t w = wave_in_block(), l = lane_id();
     const uint32_t n = P.n, minpts = (uint32_t)P.min_pts, all = (1u << kPch) - 1u;
     uint32_t lt = 0;
-    const DynRange dr_ = dyn_range(P.ctr->dyn[kDynCore]);
+    const DynRange dr_ = dyn_range(P.ctr->dyn[kDynCore], P.order);
     HCA_FOR_UNITS_DYN(u, (n + kPch - 1) / kPch, dr_) {
         const uint32_t pc = u * kPch, np = min((uint32_t)kPch, n - pc);
         uint32_t cell = kNone, grp = kNone;
@@ -632,7 +632,7 @@ __global__ __launch_bounds__(kBlock, ROW == kRowPacked ? 5 : 1) void k_hd_core_r
     const uint32_t nl = ld_agent32(&P.ctr->hd_left), minpts = (uint32_t)P.min_pts;
     const uint32_t all = (1u << kPch) - 1u;
     uint32_t lt = 0;
-    const DynRange dr_ = dyn_range(P.ctr->dyn[kDynCoreRest]);
+    const DynRange dr_ = dyn_range(P.ctr->dyn[kDynCoreRest], P.order);
     HCA_FOR_UNITS_DYN(u, (nl + kPch - 1) / kPch, dr_) {
         const uint32_t b0 = u * kPch, np = min((uint32_t)kPch, nl - b0);
         uint32_t pos[kPch];
@@ -753,7 +753,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_merge(Plan P)
     const uint32_t w = wave_in_block(), l = lane_id();
     const uint32_t n = P.n, all = (1u << kPch) - 1u;
     uint32_t lt = 0;
-    const DynRange dr_ = dyn_range(P.ctr->dyn[kDynMerge]);
+    const DynRange dr_ = dyn_range(P.ctr->dyn[kDynMerge], P.order);
     HCA_FOR_UNITS_DYN(u, (n + kPch - 1) / kPch, dr_) {
         const uint32_t pc = u * kPch, np = min((uint32_t)kPch, n - pc);
         const bool core = l < np && P.core[pc + l];
@@ -831,7 +831,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_unify(Plan P)
 {
     const uint32_t l = lane_id();
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
-    const WaveRange hca_wr_ = wave_range();
+    const WaveRange hca_wr_ = wave_range(P.order);
     HCA_FOR_UNITS(g, ng) {
         const uint32_t first = P.gcube[g];
         bool unified = first != kNone;
@@ -932,7 +932,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_border(Plan P)
     // a short list: one point per wave, so that the walks run side by side
     const uint32_t per = nl >= (uint32_t)kPch * gridDim.x * kWavesPerBlock ? (uint32_t)kPch : 1u;
     uint32_t lt = 0;
-    const DynRange dr_ = dyn_range(P.ctr->dyn[kDynBorder]);
+    const DynRange dr_ = dyn_range(P.ctr->dyn[kDynBorder], P.order);
     HCA_FOR_UNITS_DYN(u, (nl + per - 1) / per, dr_) {
         const uint32_t b0 = u * per, np = min(per, nl - b0);
         uint32_t pos[kPch];

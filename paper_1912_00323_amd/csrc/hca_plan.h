@@ -245,6 +245,7 @@ struct Plan {
     uint32_t *work;             // [2 * work_cap] cube pairs for exact tests
     uint32_t work_cap;          // multiple of kWorkRegions
     uint32_t want_stats;        // count core and noise points
+    uint32_t order;             // order the wave-dealt units are taken in: 0 as dealt, 1 reversed, 2 permuted
     uint32_t count_work;        // count pair tests per phase
     uint32_t *owner;            // [n] sorted position -> root cube (border), kNone
     uint32_t *cmin;             // [n] cube -> smallest input index of its core points, kNone

@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstdint>
 #include <deque>
@@ -39,6 +40,7 @@ struct Request {
     int32_t *labels;
     uint64_t tag;
     size_t bytes;
+    double est_ms;              // estimated device time alone
     hipEvent_t ready;           // recorded on the caller's stream at submission, or null
 };
 
@@ -62,12 +64,23 @@ size_t footprint(int64_t n, int32_t d)
     return (size_t)((uint64_t)n * per_point + (1ull << 20));
 }
 
+// Estimated device time of a request alone (ms), from its rows and axes:
+// the per-point costs measured for the launch sequence on one MI355X (about
+// 0.4 ns per point for up to two axes, 2.7 for three, 5.6 for four, more
+// with search groups), used only to bound how much work one batch gathers.
+double estimate_ms(int64_t n, int32_t d)
+{
+    const double ns_per_pt = d <= 2 ? 0.4 : d == 3 ? 2.7 : d == 4 ? 5.6 : d <= 8 ? 12.0 : 200.0;
+    return 0.02 + (double)n * ns_per_pt * 1e-6;
+}
+
 }  // namespace
 
 struct hca_server {
     int device = 0;
     size_t budget = 0;
     int32_t max_batch = 64;
+    double batch_ms = 4.0;      // a batch stops growing past this much estimated device time
     std::vector<hca_ctx *> ctx;
     std::vector<hipStream_t> streams;
     std::vector<std::thread> workers;
@@ -104,11 +117,16 @@ void hca_server::run_worker(int w)
             // the front request, then (if it can be batched) the requests of
             // d <= 4 behind it while they fit
             size_t bytes = 0;
+            double est = 0;
             const bool batchable = queue.front().d <= kBatchDimMax;
             while (!queue.empty() && (int32_t)batch.size() < max_batch) {
                 const Request &r = queue.front();
                 if (!batch.empty() && (!batchable || r.d > kBatchDimMax)) break;
                 if (!batch.empty() && in_flight + bytes + r.bytes > budget) break;
+                // small requests are not held behind large ones: a batch
+                // takes requests only while its estimated time stays short
+                if (!batch.empty() && est + r.est_ms > batch_ms) break;
+                est += r.est_ms;
                 bytes += r.bytes;
                 batch.push_back(r);
                 queue.pop_front();
@@ -234,9 +252,17 @@ hca_status hca_server_submit(hca_server *srv, const int32_t *points, int64_t n, 
             if (ev) srv->spare_events.push_back(ev);
             return HCA_E_INVAL;
         }
-        srv->queue.push_back({points, n, d, eps, min_pts, labels, tag, footprint(n, d), ev});
+        srv->queue.push_back({points, n, d, eps, min_pts, labels, tag, footprint(n, d), estimate_ms(n, d), ev});
     }
     srv->cv_work.notify_one();
+    return HCA_OK;
+}
+
+hca_status hca_server_set_batch_time(hca_server *srv, double ms)
+{
+    if (!srv || !(ms > 0.0) || !std::isfinite(ms)) return HCA_E_INVAL;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->batch_ms = ms;
     return HCA_OK;
 }
 

@@ -161,6 +161,49 @@ def make_served(seed: int = 5, count: int = 64, n_range=(10_000, 2_000_000), dim
     return make_batch(seed=seed, count=count, n_range=n_range, dims=dims, q=q)
 
 
+def served_requests(seed: int = 5, count: int = 10_000, n_range=(10_000, 2_000_000), dims=(2, 3, 5),
+                    q: int = 14) -> list:
+    """Parameters of ``count`` distinct requests of the served workload (the
+    batched workload's recipe: 3-30 blobs with per-blob std uniform in
+    [0.005, 0.03], 5-15 % noise, eps uniform in [0.005, 0.03], minPts in
+    4..12; n log-uniform in ``n_range``, d uniform in ``dims``), drawn on the
+    host; the points themselves come from :func:`device_request`."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 2])))
+    out = []
+    for k in range(count):
+        n = int(round(float(np.exp(rng.uniform(np.log(n_range[0]), np.log(n_range[1]))))))
+        d = int(rng.choice(np.asarray(dims)))
+        n_blobs = int(rng.integers(3, 31))
+        out.append({"k": k, "seed": seed, "n": n, "d": d, "q": q,
+                    "centres": rng.uniform(0.0, 1.0, size=(n_blobs, d)),
+                    "stds": rng.uniform(0.005, 0.03, size=n_blobs),
+                    "noise": float(rng.uniform(0.05, 0.15)),
+                    "eps": float(rng.uniform(0.005, 0.03)) * 2 ** q,
+                    "min_pts": int(rng.integers(4, 13))})
+    return out
+
+
+def device_request(req: dict, device):
+    """The points of one served request, drawn on the device by a torch
+    generator seeded from (seed, k): each blob point takes a blob uniformly
+    (equal shares), a Gaussian offset of that blob's std around its centre,
+    then the noise points uniform in [0,1]^d, one random order, quantised to
+    int32 as floor(x * 2^q + 0.5)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(req["seed"]) * 1_000_003 + int(req["k"]))
+    n, d = int(req["n"]), int(req["d"])
+    n_noise = int(round(req["noise"] * n))
+    centres = torch.as_tensor(req["centres"], dtype=torch.float64, device=device)
+    stds = torch.as_tensor(req["stds"], dtype=torch.float64, device=device)
+    which = torch.randint(0, centres.shape[0], (n - n_noise,), generator=g, device=device)
+    blob = centres[which] + stds[which, None] * torch.randn(n - n_noise, d, generator=g, device=device,
+                                                               dtype=torch.float64)
+    noise = torch.rand(n_noise, d, generator=g, device=device, dtype=torch.float64)
+    x = torch.cat([blob, noise])[torch.randperm(n, generator=g, device=device)]
+    return torch.floor(x * float(2 ** req["q"]) + 0.5).to(torch.int32).contiguous()
+
+
 def poisson_arrivals(seed: int, count: int, rate: float) -> np.ndarray:
     """Arrival times (seconds from 0) of a Poisson process of the given rate."""
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 1])))

@@ -101,6 +101,8 @@ def load_library(path: str | Path | None = None) -> ctypes.CDLL:
     lib.hca_server_create.restype = ctypes.c_int
     lib.hca_server_submit.argtypes = [vp, vp, i64, i32, dbl, i32, vp, ctypes.c_uint64, vp]
     lib.hca_server_submit.restype = ctypes.c_int
+    lib.hca_server_set_batch_time.argtypes = [vp, dbl]
+    lib.hca_server_set_batch_time.restype = ctypes.c_int
     lib.hca_server_poll.argtypes = [vp, vp, vp, vp, i32]
     lib.hca_server_poll.restype = i32
     lib.hca_server_drain.argtypes = [vp]
@@ -221,7 +223,7 @@ class Server:
     completes."""
 
     def __init__(self, device: int = 0, workers: int = 2, budget_bytes: int = 32 << 30,
-                 max_batch: int = 64):
+                 max_batch: int = 64, batch_ms: float | None = None):
         self._lib = load_library()
         self._srv = ctypes.c_void_p()
         st = self._lib.hca_server_create(ctypes.byref(self._srv), int(device), int(workers),
@@ -229,6 +231,10 @@ class Server:
         if st != HCA_OK:
             raise HcaError(st, "hca_server_create failed")
         self._keep = {}
+        if batch_ms is not None:
+            st = self._lib.hca_server_set_batch_time(self._srv, float(batch_ms))
+            if st != HCA_OK:
+                raise HcaError(st, "batch_ms must be > 0")
 
     def submit(self, points, eps: float, min_pts: int, labels, tag: int):
         """Queue one request.  It runs after the work already queued on the

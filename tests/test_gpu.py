@@ -279,6 +279,37 @@ def test_core_lane_walk(ctx, lanes, budget, monkeypatch):
         at += j.n
 
 
+@pytest.mark.parametrize("order", ["reverse", "permute"])
+def test_schedule_orders(ctx, order, monkeypatch):
+    """The wave-dealt units of every neighbour phase taken in reverse or in a
+    permuted order (another schedule of the same atomics and unions): labels
+    and core flags still equal the oracle's, in 2-D and 8-D, and in a batch."""
+    monkeypatch.setenv("HCA_ORDER", order)
+    for cfg, n in ((2, 200_000), (3, 100_000)):
+        w = make_config(cfg, n=n)
+        print(f"[case] order={order} {w.name} n={n}", flush=True)
+        want = oracle.hca_grid(w.points, w.eps, w.min_pts, threads=0)
+        got, core = gpu_labels(ctx, w.points, w.eps, w.min_pts, core=True)
+        assert np.array_equal(got, want), (order, cfg)
+        _, wcore, _ = oracle.hca_grid(w.points, w.eps, w.min_pts, threads=0, details=True)
+        assert np.array_equal(core.astype(bool), wcore), (order, cfg)
+    for mode in ("group", "cube"):
+        monkeypatch.setenv("HCA_SEARCH", mode)
+        rng = np.random.default_rng(181)
+        pts = quantise(make_blobs(rng, 20000, 4, 6, 0.03, 0.1), 12)
+        check(ctx, pts, 0.05 * 2 ** 12, 6, f"order={order} {mode} 4-D")
+    monkeypatch.delenv("HCA_SEARCH")
+    import torch
+    jobs = [make_mixed(1300 + k, 3000 + 2000 * k, (2, 3, 4)[k % 3]) for k in range(6)]
+    flat = torch.from_numpy(np.concatenate([j.points.ravel() for j in jobs]).astype(np.int32)).cuda()
+    got = ctx.cluster_batch(flat, [j.n for j in jobs], [j.d for j in jobs], [j.eps for j in jobs],
+                            [j.min_pts for j in jobs]).cpu().numpy()
+    at = 0
+    for j in jobs:
+        assert np.array_equal(got[at:at + j.n], oracle.dbscan(j.points, j.eps, j.min_pts)), (order, j.name)
+        at += j.n
+
+
 def test_mixed_family(ctx):
     for seed in range(6):
         d = (2, 3, 4)[seed % 3]

@@ -172,3 +172,38 @@ def test_server_results_alone_and_in_the_mix():
         assert np.array_equal(o.cpu().numpy(), alone), j.name
         assert np.array_equal(alone, oracle.dbscan(j.points, j.eps, j.min_pts)), j.name
     c.close()
+
+
+def test_served_full_range(ctx):
+    """Requests of the served workload across its whole range (up to 2M points
+    and 5 axes), submitted together with smaller ones to the request loop:
+    each result matches the oracle's stored digest, in the mix and alone."""
+    import torch
+    from paper_1912_00323_amd import hca
+    from paper_1912_00323_amd.datagen import make_served
+    exp = json.loads((GOLDEN / "served_expected.json").read_text())
+    reqs = make_served(seed=exp["seed"], count=exp["count"])
+    picked = {e["index"]: e for e in exp["requests"]}
+    for k, e in picked.items():
+        assert digest(reqs[k].points.reshape(-1)) == e["points_sha256"], "input generator drifted"
+    mix = sorted(set(picked) | set(range(0, 64, 3)))
+    pts = {k: torch.from_numpy(reqs[k].points).cuda() for k in mix}
+    outs = {k: torch.full((reqs[k].n,), -7, dtype=torch.int32, device="cuda") for k in mix}
+    print(f"[case] served mix of {len(mix)} requests, {sum(reqs[k].n for k in mix)} points", flush=True)
+    srv = hca.Server(0, workers=2, budget_bytes=64 << 30, max_batch=16, batch_ms=4.0)
+    try:
+        for k in mix:
+            srv.submit(pts[k], reqs[k].eps, reqs[k].min_pts, outs[k], tag=k)
+        srv.drain()
+        done = {t: st for t, st, _ in srv.poll(1 << 12)}
+    finally:
+        srv.close()
+    assert sorted(done) == mix and all(st == 0 for st in done.values())
+    for k, e in picked.items():
+        assert digest(outs[k].cpu().numpy()) == e["labels_sha256"], ("mix", e["name"])
+        alone = ctx.cluster(pts[k], reqs[k].eps, reqs[k].min_pts).cpu().numpy()
+        assert digest(alone) == e["labels_sha256"], ("alone", e["name"])
+    for k in mix:
+        if k not in picked:
+            alone = ctx.cluster(pts[k], reqs[k].eps, reqs[k].min_pts)
+            assert torch.equal(outs[k], alone), reqs[k].name
