@@ -169,6 +169,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--requests", type=int, default=10_000, help="served workload: distinct requests")
     ap.add_argument("--slo-ms", type=float, default=250.0, help="served workload: p99 latency objective")
+    ap.add_argument("--loads", default="0.7,1.0,1.3",
+                    help="served workload: arrival rates as multiples of the plain path's sustained rate")
+    ap.add_argument("--saturated", action="store_true", help="served workload: also every request at once")
     ap.add_argument("--batch-ms", type=float, default=4.0,
                     help="served workload: estimated device time a batch may gather")
     ap.add_argument("--no-second", action="store_true",
@@ -470,7 +473,7 @@ def bench_batch(args) -> int:
     return 0
 
 
-def bench_served(args, loads=(0.6, 0.9, 1.2, 1.5), workers: int = 2) -> int:
+def bench_served(args, workers: int = 2) -> int:
     """The served workload: Poisson arrivals of --requests distinct clustering
     requests (n log-uniform in [1e4, 2e6], d in {2, 3, 5}, per-request eps and
     minPts; points drawn on the device from a seeded torch generator) at
@@ -486,9 +489,18 @@ def bench_served(args, loads=(0.6, 0.9, 1.2, 1.5), workers: int = 2) -> int:
     from paper_1912_00323_amd import hca
     from paper_1912_00323_amd.datagen import device_request, poisson_arrivals, served_requests
 
+    loads = tuple(float(v) for v in args.loads.split(","))
     reqs = served_requests(seed=5, count=args.requests)
     dev = torch.device("cuda:0")
-    xs = [device_request(r, dev) for r in reqs]
+
+    def note(msg):
+        print(f"[served] {msg}", file=sys.stderr, flush=True)
+
+    xs = []
+    for k, r in enumerate(reqs):
+        xs.append(device_request(r, dev))
+        if k % 1000 == 999:
+            note(f"drew {k + 1} requests")
     outs = [torch.empty(r["n"], dtype=torch.int32, device=dev) for r in reqs]
     points = sum(r["n"] for r in reqs)
     ctx = hca.Context(0)
@@ -497,9 +509,14 @@ def bench_served(args, loads=(0.6, 0.9, 1.2, 1.5), workers: int = 2) -> int:
     ref = [ctx.cluster(x, r["eps"], r["min_pts"]) for x, r in zip(xs[:64], reqs[:64])]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ref = [ctx.cluster(x, r["eps"], r["min_pts"]) for x, r in zip(xs, reqs)]
+    ref = []
+    for k, (x, r) in enumerate(zip(xs, reqs)):
+        ref.append(ctx.cluster(x, r["eps"], r["min_pts"]))
+        if k % 1000 == 999:
+            note(f"plain reference pass: {k + 1} requests")
     torch.cuda.synchronize()
     plain_rate = len(reqs) / (time.perf_counter() - t0)
+    note(f"plain path sustains {plain_rate:.1f} requests/s")
     srv = hca.Server(0, workers=workers, budget_bytes=48 << 30, max_batch=64, batch_ms=args.batch_ms)
     same = True
     count = len(reqs)
@@ -512,6 +529,8 @@ def bench_served(args, loads=(0.6, 0.9, 1.2, 1.5), workers: int = 2) -> int:
                 pass
             ctx.cluster(xs[k], r["eps"], r["min_pts"], out=outs[k])
             lat.append(hca.clock() - (start + arr[k]))
+            if k % 2000 == 1999:
+                note(f"plain: {k + 1} requests")
         return lat, hca.clock() - start
 
     def served(arr):
@@ -525,6 +544,8 @@ def bench_served(args, loads=(0.6, 0.9, 1.2, 1.5), workers: int = 2) -> int:
                 for t, st, td in srv.poll():
                     done[t] = (st, td)
             srv.submit(xs[k], r["eps"], r["min_pts"], outs[k], tag=k)
+            if k % 2000 == 1999:
+                note(f"served: {k + 1} requests submitted")
         srv.drain()
         for t, st, td in srv.poll(1 << 20):
             done[t] = (st, td)
@@ -543,8 +564,10 @@ def bench_served(args, loads=(0.6, 0.9, 1.2, 1.5), workers: int = 2) -> int:
         sweep[str(load)] = {"arrival_rate_per_s": round(load * plain_rate, 2),
                             "served": summary(*served(arr)), "plain_sequential": summary(*plain(arr))}
         print(f"[load {load}] {json.dumps(sweep[str(load)])}", file=sys.stderr, flush=True)
-    zero = np.zeros(count)
-    saturated = {"served": summary(*served(zero)), "plain_sequential": summary(*plain(zero))}
+    saturated = None
+    if args.saturated:
+        zero = np.zeros(count)
+        saturated = {"served": summary(*served(zero)), "plain_sequential": summary(*plain(zero))}
     srv.close()
     ctx.close()
 

@@ -1833,8 +1833,9 @@ __global__ __launch_bounds__(kBlock) void k_merge_exact(Plan P)
 // Intra-group pairs are cut into 64 x 64 tiles of points, dealt to all waves
 // so that a group of thousands of points does not rest on one wave.  Groups
 // of one cube need none (a cube is one union-find node); groups beyond
-// kTileMaxChunks chunks are linked point by point in k_merge_unify.
-constexpr uint32_t kTileMaxChunks = 1024;
+// kTileMaxChunks chunks (8192 points) are linked cube pair by cube pair in
+// k_merge_big, whose work grows with their cubes rather than their points.
+constexpr uint32_t kTileMaxChunks = 128;
 
 __device__ __forceinline__ uint32_t group_tiles(const Plan &P, uint32_t g)
 {
@@ -1956,8 +1957,61 @@ __global__ __launch_bounds__(kBlock) void k_merge_tiles(Plan P)
     flush_tests(P, kTestsIntra, lt);
 }
 
+// Groups too large for tiles (more than kTileMaxChunks chunks of points, as
+// dense clusters in few dimensions give): their core cubes are linked pair by
+// pair, one wave per cube A over the cubes B > A of its group whose boxes can
+// hold a pair within eps (the cube stencil's rule on the in-group offsets),
+// each such pair not yet joined by the exact test with ballot early exit.
+// The work is quadratic in the group's cubes, not in its points.
+__device__ __forceinline__ uint64_t sorted_key(const Plan &P, uint32_t i)
+{
+    return P.key_bits > 32 ? ((const uint64_t *)P.skeys)[i] : (uint64_t)((const uint32_t *)P.skeys)[i];
+}
+
+template <int D, bool WIDE>
+__global__ __launch_bounds__(kBlock) void k_merge_big(Plan P)
+{
+    const uint32_t l = lane_id();
+    const uint32_t nc = ld_agent32(&P.ctr->n_cells);
+    const uint64_t fmask = (1ull << P.bm) - 1ull;
+    uint32_t lt = 0;
+    const WaveRange hca_wr_ = wave_range(P.order);
+    HCA_FOR_UNITS(A, nc) {
+        if (P.ncore[A] == 0) continue;
+        const uint32_t g = P.group_of[A];
+        const uint32_t p0 = P.group_start[g], p1 = P.group_start[g + 1];
+        const uint32_t c1 = P.group_cell[g + 1];
+        if ((p1 - p0 + kWave - 1) / kWave <= kTileMaxChunks || c1 - A < 2) continue;
+        const uint64_t ka = sorted_key(P, P.cell_start[A]);
+        for (uint32_t b0 = A + 1; b0 < c1; b0 += kWave) {
+            const uint32_t B = b0 + l;
+            bool cand = B < c1 && P.ncore[B] > 0;
+            if (cand) {
+                const uint64_t kb = sorted_key(P, P.cell_start[B]);
+                int64_t acc = 0;
+#pragma unroll
+                for (int k = 0; k < D; k++) {
+                    const uint32_t sh = P.bm * (uint32_t)(D - 1 - k);
+                    const int64_t fa = (int64_t)((ka >> sh) & fmask), fb = (int64_t)((kb >> sh) & fmask);
+                    const int64_t df = fa > fb ? fa - fb : fb - fa;
+                    const int64_t gap = df ? (df - 1) * (int64_t)P.side + 1 : 0;
+                    acc += gap * gap;
+                }
+                cand = acc <= P.eps2;
+            }
+            uint64_t m = __ballot(cand);
+            while (m) {
+                const uint32_t Bb = b0 + (uint32_t)__ffsll((unsigned long long)m) - 1u;
+                m &= m - 1;
+                if (uf_find(P.parent, A) != uf_find(P.parent, Bb)) exact_pair<D, WIDE>(P, A, Bb, lt);
+            }
+        }
+    }
+    flush_tests(P, kTestsIntra, lt);
+}
+
 // First core cube of each group and whether all its core cubes share one
-// root.  Groups too large for tiles are linked point by point here first.
+// root (after the tiles and k_merge_big).
 template <int D, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_merge_unify(Plan P)
 {
@@ -1965,38 +2019,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_unify(Plan P)
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
     const WaveRange hca_wr_ = wave_range(P.order);
     HCA_FOR_UNITS(g, ng) {
-        const uint32_t p0 = P.group_start[g], p1 = P.group_start[g + 1];
         const uint32_t c0 = P.group_cell[g], c1 = P.group_cell[g + 1];
-        if (c1 - c0 > 1 && (p1 - p0 + kWave - 1) / kWave > kTileMaxChunks) {
-            for (uint32_t pc = p0; pc < p1; pc += kPch) {
-                Pt<D> pp[kPch];
-                uint32_t cell[kPch];
-                uint32_t live = 0;
-                const uint32_t np = min((uint32_t)kPch, p1 - pc);
-                load_chunk<D>(P, pc, np, pp);
-#pragma unroll
-                for (int k = 0; k < kPch; k++) {
-                    const uint32_t q = pc + (k < (int)np ? k : 0);
-                    cell[k] = uniform(P.cell_of[q]);
-                    if (k < (int)np && P.core[q]) live |= 1u << k;
-                }
-                live = uniform(live);
-                if (!live) continue;
-                for (uint32_t base = pc; base < p1; base += kWave) {
-                    const uint32_t q = base + l;
-                    const bool ok = q < p1 && P.core[q];
-                    const Pt<D> pq = load_pt<D>(P.spts, ok ? q : pc);
-                    const uint32_t cq = ok ? P.cell_of[q] : 0;
-#pragma unroll
-                    for (int k = 0; k < kPch; k++) {
-                        if (!(live & (1u << k))) continue;
-                        const bool hit = ok && cq > cell[k] && within<D, WIDE>(pp[k], pq, P.eps2);
-                        if (hit && uf_find(P.parent, cell[k]) != uf_find(P.parent, cq))
-                            uf_union(P.parent, cell[k], cq);
-                    }
-                }
-            }
-        }
         uint32_t first = kNone;
         for (uint32_t cb = c0; cb < c1 && first == kNone; cb += kWave) {
             const uint32_t c = cb + l;
@@ -2775,6 +2798,7 @@ void launch_merge_intra(const Plan &P, int blocks, hipStream_t s)
     const uint32_t tiles = (P.n + kScanTile - 1) / kScanTile;
     hipLaunchKernelGGL(k_tile_scan, dim3(tiles), dim3(kBlock), 0, s, P, P.tile_status, &P.ctr->tile_ticket);
     HCA_DISPATCH_DW(k_merge_tiles, P, blocks, s);
+    HCA_DISPATCH_DW(k_merge_big, P, blocks, s);
     HCA_DISPATCH_DW(k_merge_unify, P, blocks, s);
     hipLaunchKernelGGL(k_flatten, dim3(1024), dim3(kBlock), 0, s, P);
 }

@@ -310,6 +310,16 @@ def test_schedule_orders(ctx, order, monkeypatch):
         at += j.n
 
 
+def test_dense_groups(ctx):
+    """Search groups holding tens of thousands of points (dense blobs in 5
+    and 6 axes with eps near their spread): their cubes are linked pair by
+    pair instead of point by point; labels equal the oracle's."""
+    rng = np.random.default_rng(191)
+    for d, n, std, f, mp in ((5, 60000, 0.006, 0.028, 8), (6, 40000, 0.01, 0.05, 10), (5, 30000, 0.004, 0.03, 4)):
+        pts = quantise(make_blobs(rng, n, d, 3, std, 0.05), 14)
+        check(ctx, pts, f * 2 ** 14, mp, f"dense groups d={d}")
+
+
 def test_mixed_family(ctx):
     for seed in range(6):
         d = (2, 3, 4)[seed % 3]
