@@ -33,11 +33,14 @@ HBM_PHASES = ("bbox", "sort", "cells", "labels")
 ALU_PHASES = {"core": "tests_core", "intra": "tests_intra", "merge": "tests_merge",
               "border": "tests_border"}
 PHASE_KERNELS = {
-    "bbox": ["k_bbox"], "sort": ["k_keys_hist", "k_onesweep"], "cells": ["k_cells", "k_table"],
-    "lists": ["k_nbr_lists"], "core": ["k_core", "k_core_chunks"], "reps": ["k_reps"],
-    "intra": ["k_tile_scan", "k_merge_tiles", "k_merge_unify"],
-    "merge": ["k_merge_rep", "k_merge_exact", "k_merge_inter", "k_merge_pairs", "k_compress"],
-    "border": ["k_border", "k_border_chunks"],
+    "bbox": ["k_bbox"], "sort": ["k_keys_hist", "k_onesweep"], "cells": ["k_cells", "k_table_clear", "k_table"],
+    "lists": ["k_group_box", "k_prefix_ranges", "k_nbr_lists", "k_nbr_bscan", "k_nbr_back"],
+    "core": ["k_core", "k_core_chunks", "k_core_flat", "k_core_lanes", "k_core_deferred", "k_core_cubes"],
+    "reps": ["k_reps_init", "k_reps", "k_reps_small", "k_reps_big"],
+    "intra": ["k_link_recorded", "k_tile_scan", "k_merge_tiles", "k_merge_big", "k_merge_unify"],
+    "merge": ["k_merge_rep", "k_merge_cubes", "k_merge_exact", "k_merge_inter", "k_merge_pairs", "k_flatten",
+              "k_compress"],
+    "border": ["k_border", "k_border_chunks", "k_border_rec", "k_border_list", "k_border_walk_list"],
     "labels": ["k_label_marks", "k_label_scan", "k_label_cubes", "k_label_write"],
 }
 # more than 8 axes: the kernels of each phase
