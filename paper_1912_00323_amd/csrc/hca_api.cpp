@@ -220,6 +220,18 @@ uint32_t key_passes(uint32_t key_bits, bool wide, const Tune *t = nullptr)
     return key_bits ? (key_bits + rb - 1) / rb : 1u;
 }
 
+// Threads that rank one radix tile (the tile size stays the key type's):
+// 1024 for 32-bit keys and 512 for 64-bit ones, where a call's few hundred
+// tiles leave one tile per CU and more waves hide more latency;
+// HCA_SORT_THREADS=256|512|1024 overrides.
+uint32_t sort_threads(bool wide_keys)
+{
+    const char *e = std::getenv("HCA_SORT_THREADS");
+    const int v = e ? std::atoi(e) : 0;
+    if (v == 256 || v == 512 || v == 1024) return (uint32_t)v;
+    return wide_keys ? 512u : 1024u;
+}
+
 // HCA_ORDER=reverse|permute: the wave-dealt units of the neighbour phases
 // taken in reverse or permuted order (tests: the result must not depend on
 // the schedule)
@@ -470,6 +482,7 @@ void plan_sizes(Plan &P, uint32_t gbits, bool count_work, bool want_stats, Sizes
     P.dense = gbits <= 24 && (1ull << gbits) <= std::max<uint64_t>(16ull * n, 1ull << 20);
     P.hash_load = t ? (uint32_t)std::min(std::max(t->hash_load, 1), 3) : 1u;
     P.sort_items = t && t->sort_items == 16 ? 16u : 0u;
+    P.sort_threads = sort_threads(Z->wide_keys);
     Z->hcap = 1024;
     while (Z->hcap < ((uint64_t)n << P.hash_load)) Z->hcap <<= 1;
     P.hash_mask = Z->hcap - 1;

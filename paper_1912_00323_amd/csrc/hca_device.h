@@ -80,9 +80,10 @@ __device__ __forceinline__ T wave_inclusive_scan(T v)
     return v;
 }
 
-// Exclusive scan over the 256 threads of a block.  `smem` holds 4 values.
-// Returns the exclusive prefix; *total receives the block sum.
-template <typename T>
+// Exclusive scan over the threads of a block of NW waves (256 threads by
+// default).  `smem` holds NW values.  Returns the exclusive prefix; *total
+// receives the block sum.
+template <typename T, int NW = kBlock / kWave>
 __device__ __forceinline__ T block_exclusive_scan(T v, T *smem, T *total)
 {
     T inc = wave_inclusive_scan(v);
@@ -91,7 +92,7 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T *smem, T *total)
     __syncthreads();
     T base = 0, all = 0;
 #pragma unroll
-    for (int i = 0; i < kBlock / kWave; i++) {
+    for (int i = 0; i < NW; i++) {
         T s = smem[i];
         if ((uint32_t)i < w) base += s;
         all += s;

@@ -729,30 +729,27 @@ __global__ __launch_bounds__(kBlock) void k_nbr_bscan(Plan P)
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
     if (t == 0) s_tile = atomicAdd(&P.ctr->nbr_ticket, 1u);
     __syncthreads();
-    const uint32_t tile = s_tile, base = tile * kScanTile;
+    const uint32_t tile = s_tile, g0 = tile * kScanTile + t * kScanItems;
+    // kScanItems consecutive groups per thread: one block scan per tile
     uint32_t f[kScanItems];
     uint32_t local = 0;
 #pragma unroll
     for (int j = 0; j < kScanItems; j++) {
-        const uint32_t g = base + j * kBlock + t;
-        f[j] = g < ng ? ld_agent32(P.nbr_bcount + g) : 0u;
+        f[j] = g0 + j < ng ? ld_agent32(P.nbr_bcount + g0 + j) : 0u;
         local += f[j];
     }
     uint32_t agg;
-    block_exclusive_scan<uint32_t>(local, s_red, &agg);
+    const uint32_t before = block_exclusive_scan<uint32_t>(local, s_red, &agg);
     if (t < kWave) {
         const uint32_t e = (uint32_t)scan_lookback_wave(P.nbr_status, tile, agg);
         if (t == 0) s_excl = e;
     }
     __syncthreads();
-    uint32_t run = s_excl;
+    uint32_t run = s_excl + before;
 #pragma unroll
     for (int j = 0; j < kScanItems; j++) {
-        uint32_t tot;
-        const uint32_t e = block_exclusive_scan<uint32_t>(f[j], s_red, &tot);
-        const uint32_t g = base + j * kBlock + t;
-        if (g < ng) P.nbr_bstart[g] = run + e;
-        run += tot;
+        if (g0 + j < ng) P.nbr_bstart[g0 + j] = run;
+        run += f[j];
     }
 }
 
@@ -1854,32 +1851,29 @@ __global__ __launch_bounds__(kBlock) void k_tile_scan(Plan P, uint64_t *status, 
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
     if (t == 0) s_tile = atomicAdd(ticket, 1u);
     __syncthreads();
-    const uint32_t tile = s_tile, base = tile * kScanTile;
+    const uint32_t tile = s_tile, base = tile * kScanTile, g0 = base + t * kScanItems;
+    // kScanItems consecutive groups per thread: one block scan per tile
     uint32_t f[kScanItems];
     uint32_t local = 0;
 #pragma unroll
     for (int j = 0; j < kScanItems; j++) {
-        const uint32_t g = base + j * kBlock + t;
-        f[j] = g < ng ? group_tiles(P, g) : 0u;
+        f[j] = g0 + j < ng ? group_tiles(P, g0 + j) : 0u;
         local += f[j];
     }
     uint32_t agg;
-    block_exclusive_scan<uint32_t>(local, s_red, &agg);
+    const uint32_t before = block_exclusive_scan<uint32_t>(local, s_red, &agg);
     if (t < kWave) {
         const uint32_t e = (uint32_t)scan_lookback_wave(status, tile, agg);
         if (t == 0) s_excl = e;
     }
     __syncthreads();
-    uint32_t run = s_excl;
+    uint32_t run = s_excl + before;
 #pragma unroll
     for (int j = 0; j < kScanItems; j++) {
-        uint32_t tot;
-        const uint32_t e = block_exclusive_scan<uint32_t>(f[j], s_red, &tot);
-        const uint32_t g = base + j * kBlock + t;
-        if (g < ng) P.tile_start[g] = run + e;
-        run += tot;
+        if (g0 + j < ng) P.tile_start[g0 + j] = run;
+        run += f[j];
     }
-    if (t == 0 && base + kScanTile >= ng) st_agent32(&P.ctr->n_tiles, run);
+    if (t == 0 && base + kScanTile >= ng) st_agent32(&P.ctr->n_tiles, s_excl + agg);
 }
 
 // One 64 x 64 tile of a group's point pairs per wave.  Lane l holds point l of
@@ -2586,31 +2580,29 @@ __global__ __launch_bounds__(kBlock) void k_label_scan(Plan P, uint64_t *status,
     if (t == 0) s_tile = atomicAdd(ticket, 1u);
     __syncthreads();
     const uint32_t tile = s_tile, base = tile * kScanTile;
+    // each thread ranks kScanItems consecutive words: one block scan per tile
+    const uint32_t i0 = base + t * kScanItems;
     uint32_t f[kScanItems];
     uint32_t local = 0;
 #pragma unroll
     for (int j = 0; j < kScanItems; j++) {
-        const uint32_t i = base + j * kBlock + t;
-        f[j] = i < nw ? __popc(ld_agent32(P.first + i)) : 0u;
+        f[j] = i0 + j < nw ? __popc(ld_agent32(P.first + i0 + j)) : 0u;
         local += f[j];
     }
     uint32_t agg;
-    block_exclusive_scan<uint32_t>(local, s_red, &agg);
+    const uint32_t before = block_exclusive_scan<uint32_t>(local, s_red, &agg);
     if (t < kWave) {
         const uint32_t e = (uint32_t)scan_lookback_wave(status, tile, agg);
         if (t == 0) s_excl = e;
     }
     __syncthreads();
-    uint32_t run = s_excl;
+    uint32_t run = s_excl + before;
 #pragma unroll
     for (int j = 0; j < kScanItems; j++) {
-        uint32_t tot;
-        const uint32_t e = block_exclusive_scan<uint32_t>(f[j], s_red, &tot);
-        const uint32_t i = base + j * kBlock + t;
-        if (i < nw) P.wrank[i] = run + e;
-        run += tot;
+        if (i0 + j < nw) P.wrank[i0 + j] = run;
+        run += f[j];
     }
-    if (t == 0 && base + kScanTile >= nw) P.ctr->n_clusters = run;
+    if (t == 0 && base + kScanTile >= nw) P.ctr->n_clusters = s_excl + agg;
 }
 
 // Batch: clusters of the data sets before each one = marks before its first

@@ -114,24 +114,42 @@ __device__ __forceinline__ K cube_key(const Plan &P, const Pt<D> &p, uint32_t i)
     return (K)key;
 }
 
+// Blocks of kHistBlock threads (16 waves per CU at one block per CU: the
+// grid is kept small so that few LDS histograms are flushed to the global one)
+constexpr int kHistBlock = 1024;
+
 template <int D, typename K>
-__global__ __launch_bounds__(kBlock) void k_keys_hist(Plan P, K *__restrict__ keys,
-                                                      uint32_t *__restrict__ vals,
-                                                      uint32_t *__restrict__ hist)
+__global__ __launch_bounds__(kHistBlock) void k_keys_hist(Plan P, K *__restrict__ keys,
+                                                          uint32_t *__restrict__ vals,
+                                                          uint32_t *__restrict__ hist)
 {
     __shared__ uint32_t s_hist[8 * kRadix];
     const uint32_t passes = P.passes, dmask = (1u << P.digit_bits) - 1u;
-    for (uint32_t e = threadIdx.x; e < passes * kRadix; e += kBlock) s_hist[e] = 0;
+    for (uint32_t e = threadIdx.x; e < passes * kRadix; e += kHistBlock) s_hist[e] = 0;
     __syncthreads();
-    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < P.n; i += gridDim.x * kBlock) {
-        const K key = cube_key<D, K>(P, load_pt<D>(P.pts, i), i);
-        keys[i] = key;
-        vals[i] = i;
-        for (uint32_t q = 0; q < passes; q++)
-            atomicAdd(&s_hist[q * kRadix + (uint32_t)((key >> (q * P.digit_bits)) & dmask)], 1u);
+    // U points per thread and round, all loaded before any key is computed
+    constexpr int U = D <= 2 ? 4 : 2;
+    const uint32_t stride = gridDim.x * kHistBlock;
+    for (uint32_t i0 = blockIdx.x * kHistBlock + threadIdx.x; i0 < P.n; i0 += U * stride) {
+        Pt<D> p[U];
+#pragma unroll
+        for (int j = 0; j < U; j++) {
+            const uint32_t i = i0 + j * stride;
+            if (i < P.n) p[j] = load_pt<D>(P.pts, i);
+        }
+#pragma unroll
+        for (int j = 0; j < U; j++) {
+            const uint32_t i = i0 + j * stride;
+            if (i >= P.n) break;
+            const K key = cube_key<D, K>(P, p[j], i);
+            keys[i] = key;
+            vals[i] = i;
+            for (uint32_t q = 0; q < passes; q++)
+                atomicAdd(&s_hist[q * kRadix + (uint32_t)((key >> (q * P.digit_bits)) & dmask)], 1u);
+        }
     }
     __syncthreads();
-    for (uint32_t e = threadIdx.x; e < passes * kRadix; e += kBlock)
+    for (uint32_t e = threadIdx.x; e < passes * kRadix; e += kHistBlock)
         if (s_hist[e]) atomicAdd(&hist[e], s_hist[e]);
 }
 
@@ -215,16 +233,16 @@ __device__ __forceinline__ bool hd_new_cube(const Plan &P, uint32_t idx)
 // and turned into global offsets by looking back over earlier tiles; keys
 // are then staged in LDS in digit order and written out in runs.
 // ---------------------------------------------------------------------------
-template <typename K, int D, bool GATHER, int ITEMS = sort_items<K>()>
-__global__ __launch_bounds__(kBlock) void k_onesweep(Plan P, const K *__restrict__ kin,
+template <typename K, int D, bool GATHER, int ITEMS = sort_items<K>(), int THREADS = kBlock>
+__global__ __launch_bounds__(THREADS) void k_onesweep(Plan P, const K *__restrict__ kin,
                                                      const uint32_t *__restrict__ vin,
                                                      K *__restrict__ kout, uint32_t *__restrict__ vout,
                                                      uint32_t shift, const uint32_t *hist,
                                                      uint64_t *__restrict__ status, uint32_t *ticket)
 {
-    constexpr int W = kBlock / kWave;
+    constexpr int W = THREADS / kWave;
     constexpr int kItems = ITEMS;
-    constexpr int kTile = kBlock * kItems;
+    constexpr int kTile = THREADS * kItems;
     constexpr int PER_WAVE = kWave * kItems;
     constexpr int RADIX = 1 << radix_bits<K>();
     __shared__ K s_keys[kTile];
@@ -237,7 +255,7 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(Plan P, const K *__restrict
 
     const uint32_t t = threadIdx.x, w = wave_in_block(), l = lane_id();
     if (t == 0) s_tile = atomicAdd(ticket, 1u);
-    for (uint32_t e = t; e < W * RADIX; e += kBlock) (&s_wcnt[0][0])[e] = 0;
+    for (uint32_t e = t; e < W * RADIX; e += THREADS) (&s_wcnt[0][0])[e] = 0;
     __syncthreads();
     const uint32_t tile = s_tile;
     const uint32_t n = P.n;
@@ -277,15 +295,17 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(Plan P, const K *__restrict
     }
     __syncthreads();
 
-    // thread t owns digits t, t + 256, ...: tile counts and per-wave offsets;
-    // the counts of the pass's digits (those below 2^digit_bits; the others
-    // are empty in every tile) are published before any look-back starts
-    constexpr int R = RADIX / kBlock;
+    // thread t owns digits t, t + THREADS, ...: tile counts and per-wave
+    // offsets; the counts of the pass's digits (those below 2^digit_bits; the
+    // others are empty in every tile) are published before any look-back
+    constexpr int R = (RADIX + THREADS - 1) / THREADS;
     const uint32_t ndig = 1u << nbits;
     uint32_t cnt[R];
 #pragma unroll
     for (int r = 0; r < R; r++) {
-        const uint32_t dd = t + r * kBlock;
+        const uint32_t dd = t + r * THREADS;
+        cnt[r] = 0;
+        if (RADIX % THREADS != 0 && dd >= RADIX) continue;
         uint32_t c[W];
 #pragma unroll
         for (int i = 0; i < W; i++) c[i] = s_wcnt[i][dd];
@@ -301,15 +321,18 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(Plan P, const K *__restrict
         uint32_t tacc = 0, gacc = 0, total;
 #pragma unroll
         for (int r = 0; r < R; r++) {
-            tstart[r] = tacc + block_exclusive_scan<uint32_t>(cnt[r], s_red, &total);
+            const uint32_t dd = t + r * THREADS;
+            tstart[r] = tacc + block_exclusive_scan<uint32_t, W>(cnt[r], s_red, &total);
             tacc += total;
-            gstart[r] = gacc + block_exclusive_scan<uint32_t>(ld_agent32(hist + t + r * kBlock), s_red, &total);
+            const uint32_t h = dd < (uint32_t)RADIX ? ld_agent32(hist + dd) : 0u;
+            gstart[r] = gacc + block_exclusive_scan<uint32_t, W>(h, s_red, &total);
             gacc += total;
         }
     }
 #pragma unroll
     for (int r = 0; r < R; r++) {
-        const uint32_t dd = t + r * kBlock;
+        const uint32_t dd = t + r * THREADS;
+        if (RADIX % THREADS != 0 && dd >= RADIX) continue;
         uint64_t excl = 0;
         if (tile > 0 && dd < ndig) {
             int64_t k = (int64_t)tile - 1;
@@ -339,7 +362,7 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(Plan P, const K *__restrict
     __syncthreads();
     const uint32_t tile_base = tile * kTile;
     const uint32_t tile_n = min((uint32_t)kTile, n - tile_base);
-    for (uint32_t i = t; i < tile_n; i += kBlock) {
+    for (uint32_t i = t; i < tile_n; i += THREADS) {
         const K kk = s_keys[i];
         const uint32_t vv = s_vals[i];
         const uint32_t pos = s_gbase[(uint32_t)(kk >> shift) & dmask] + i;
@@ -352,13 +375,17 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(Plan P, const K *__restrict
 // ---------------------------------------------------------------------------
 // Cube and group tables from the sorted keys (Algorithm 1's dictionary, for
 // non-empty cubes only).  One scan counts cube starts (bits 0..30) and group
-// starts (bits 31..61) together.
+// starts (bits 31..61) together.  Each thread owns kCellsItems consecutive
+// keys: its flags are summed in registers, so a tile takes one block scan.
 // ---------------------------------------------------------------------------
+constexpr int kCellsBlock = 1024;                       // 16 waves per tile
+constexpr int kCellsItems = kScanTile / kCellsBlock;
+
 template <typename K>
-__global__ __launch_bounds__(kBlock) void k_cells(Plan P, uint64_t *__restrict__ status,
+__global__ __launch_bounds__(kCellsBlock) void k_cells(Plan P, uint64_t *__restrict__ status,
                                                   uint32_t *ticket)
 {
-    __shared__ uint64_t s_red[kBlock / kWave];
+    __shared__ uint64_t s_red[kCellsBlock / kWave];
     __shared__ uint32_t s_tile;
     __shared__ uint64_t s_excl;
     const K *skeys = (const K *)P.skeys;
@@ -366,70 +393,96 @@ __global__ __launch_bounds__(kBlock) void k_cells(Plan P, uint64_t *__restrict__
     if (t == 0) s_tile = atomicAdd(ticket, 1u);
     __syncthreads();
     const uint32_t tile = s_tile;
-    const uint32_t base = tile * kScanTile;
+    const uint32_t i0 = tile * kScanTile + t * kCellsItems;
     const uint32_t fb = P.fine_bits;
+    const bool full = i0 + kCellsItems <= n;
 
-    uint64_t v[kScanItems];
+    K kk[kCellsItems];
+    if (full) {
+        // 16- or 32-byte aligned: i0 is a multiple of kCellsItems
+        constexpr int kVec = kCellsItems * sizeof(K) / sizeof(uint4);
+        const uint4 *src = reinterpret_cast<const uint4 *>(skeys + i0);
+        uint4 buf[kVec];
+#pragma unroll
+        for (int q = 0; q < kVec; q++) buf[q] = src[q];
+        __builtin_memcpy(kk, buf, sizeof kk);
+    } else {
+#pragma unroll
+        for (int j = 0; j < kCellsItems; j++) kk[j] = i0 + j < n ? skeys[i0 + j] : (K)0;
+    }
+    K prev = i0 > 0 && i0 <= n ? skeys[i0 - 1] : (K)0;
+    uint64_t pre[kCellsItems];
     uint64_t local = 0;
 #pragma unroll
-    for (int j = 0; j < kScanItems; j++) {
-        const uint32_t idx = base + j * kBlock + t;
+    for (int j = 0; j < kCellsItems; j++) {
+        const uint32_t idx = i0 + j;
         uint64_t fc = 0, fg = 0;
         if (idx < n) {
             if (idx == 0) {
                 fc = fg = 1;
             } else {
-                const uint64_t a = (uint64_t)skeys[idx], b = (uint64_t)skeys[idx - 1];
+                const uint64_t a = (uint64_t)kk[j], b = (uint64_t)prev;
                 fc = a != b || (P.hd && hd_new_cube(P, idx));
                 fg = (a >> fb) != (b >> fb);
             }
         }
-        v[j] = fc | (fg << 31);
-        local += v[j];
+        prev = kk[j];
+        local += fc | (fg << 31);
+        pre[j] = local;                              // inclusive, within the thread
     }
     uint64_t agg;
-    block_exclusive_scan<uint64_t>(local, s_red, &agg);
+    const uint64_t before = block_exclusive_scan<uint64_t, kCellsBlock / kWave>(local, s_red, &agg);
     if (t < kWave) {
         const uint64_t e = scan_lookback_wave(status, tile, agg);
         if (t == 0) s_excl = e;
     }
     __syncthreads();
-    uint64_t run = s_excl;
+    const uint64_t run = s_excl + before;
     const uint64_t lo_mask = (1ull << 31) - 1;
+    uint32_t cells[kCellsItems];
+    uint64_t last = run;
 #pragma unroll
-    for (int j = 0; j < kScanItems; j++) {
-        uint64_t tot;
-        const uint64_t e = block_exclusive_scan<uint64_t>(v[j], s_red, &tot);
-        const uint32_t idx = base + j * kBlock + t;
-        if (idx < n) {
-            const uint64_t inc = run + e + v[j];
-            const uint32_t cell = (uint32_t)(inc & lo_mask) - 1u;
-            P.cell_of[idx] = cell;
-            if (v[j] & 1u) {
-                P.cell_start[cell] = idx;
-                P.group_of[cell] = (uint32_t)(inc >> 31) - 1u;
-                st_parent(P.parent + cell, cell);
-                st_agent32(P.minmem + cell, kNone);
-                // per-cube core tallies, accumulated with atomics in group mode
-                st_agent32(P.ncore + cell, 0u);
-                st_agent32(P.cmin + cell, kNone);
-            }
-            if (v[j] >> 31) {
-                const uint32_t g = (uint32_t)(inc >> 31) - 1u;
-                P.group_start[g] = idx;
-                P.group_key[g] = (uint64_t)skeys[idx] >> fb;
-                P.group_cell[g] = cell;
-            }
-            if (idx == n - 1) {
-                const uint32_t nc = (uint32_t)(inc & lo_mask), ng = (uint32_t)(inc >> 31);
-                P.cell_start[nc] = n;
-                P.group_start[ng] = n;
-                P.group_cell[ng] = nc;
-                st_agent32(&P.ctr->n_cells, nc);
-                st_agent32(&P.ctr->n_groups, ng);
-            }
+    for (int j = 0; j < kCellsItems; j++) {
+        const uint32_t idx = i0 + j;
+        const uint64_t inc = run + pre[j];
+        const uint64_t v = inc - last;               // this key's flags
+        last = inc;
+        const uint32_t cell = (uint32_t)(inc & lo_mask) - 1u;
+        cells[j] = cell;
+        if (idx >= n) continue;
+        if (v & 1u) {
+            P.cell_start[cell] = idx;
+            P.group_of[cell] = (uint32_t)(inc >> 31) - 1u;
+            st_parent(P.parent + cell, cell);
+            st_agent32(P.minmem + cell, kNone);
+            // per-cube core tallies, accumulated with atomics in group mode
+            st_agent32(P.ncore + cell, 0u);
+            st_agent32(P.cmin + cell, kNone);
         }
-        run += tot;
+        if (v >> 31) {
+            const uint32_t g = (uint32_t)(inc >> 31) - 1u;
+            P.group_start[g] = idx;
+            P.group_key[g] = (uint64_t)kk[j] >> fb;
+            P.group_cell[g] = cell;
+        }
+        if (idx == n - 1) {
+            const uint32_t nc = (uint32_t)(inc & lo_mask), ng = (uint32_t)(inc >> 31);
+            P.cell_start[nc] = n;
+            P.group_start[ng] = n;
+            P.group_cell[ng] = nc;
+            st_agent32(&P.ctr->n_cells, nc);
+            st_agent32(&P.ctr->n_groups, ng);
+        }
+    }
+    if (full) {
+        uint4 *dst = reinterpret_cast<uint4 *>(P.cell_of + i0);
+#pragma unroll
+        for (int q = 0; q < kCellsItems / 4; q++)
+            dst[q] = make_uint4(cells[4 * q], cells[4 * q + 1], cells[4 * q + 2], cells[4 * q + 3]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < kCellsItems; j++)
+            if (i0 + j < n) P.cell_of[i0 + j] = cells[j];
     }
 }
 
@@ -458,19 +511,19 @@ void launch_bbox(int d, const int32_t *pts, uint32_t n, int32_t *partial, int bl
     }
 }
 
-template <int D, typename K, int ITEMS>
+template <int D, typename K, int ITEMS, int THREADS = kBlock>
 static void sort_passes_d(const Plan &P, K *ka, K *kb, uint32_t *va, uint32_t *vb, const SortBuffers &B,
                           hipStream_t s)
 {
-    const uint32_t tiles = (P.n + kBlock * ITEMS - 1) / (kBlock * ITEMS);
+    const uint32_t tiles = (P.n + THREADS * ITEMS - 1) / (THREADS * ITEMS);
     for (uint32_t q = 0; q < P.passes; q++) {
         uint64_t *st = B.status + (uint64_t)q * tiles * kRadix;
         const bool last = q + 1 == P.passes;
         if (last)
-            hipLaunchKernelGGL((k_onesweep<K, D, true, ITEMS>), dim3(tiles), dim3(kBlock), 0, s, P, ka, va,
-                               kb, vb, q * P.digit_bits, B.hist + q * kRadix, st, B.tickets + q);
+            hipLaunchKernelGGL((k_onesweep<K, D, true, ITEMS, THREADS>), dim3(tiles), dim3(THREADS), 0, s, P, ka,
+                               va, kb, vb, q * P.digit_bits, B.hist + q * kRadix, st, B.tickets + q);
         else
-            hipLaunchKernelGGL((k_onesweep<K, D, false, ITEMS>), dim3(tiles), dim3(kBlock), 0, s, P, ka,
+            hipLaunchKernelGGL((k_onesweep<K, D, false, ITEMS, THREADS>), dim3(tiles), dim3(THREADS), 0, s, P, ka,
                                va, kb, vb, q * P.digit_bits, B.hist + q * kRadix, st, B.tickets + q);
         K *tk = ka; ka = kb; kb = tk;
         uint32_t *tv = va; va = vb; vb = tv;
@@ -481,10 +534,10 @@ template <int D, typename K>
 static void sort_d(const Plan &P, const SortBuffers &B, hipStream_t s)
 {
     // few blocks: each flushes its LDS histogram with one global atomic per bin
-    const int hb = (int)std::min<uint64_t>((P.n + kBlock * 16 - 1) / (kBlock * 16), 256);
+    const int hb = (int)std::min<uint64_t>((P.n + kHistBlock * 4 - 1) / (kHistBlock * 4), 256);
     K *ka = (K *)B.keys_a, *kb = (K *)B.keys_b;
     uint32_t *va = B.vals_a, *vb = B.vals_b;
-    hipLaunchKernelGGL((k_keys_hist<D, K>), dim3(hb), dim3(kBlock), 0, s, P, ka, va, B.hist);
+    hipLaunchKernelGGL((k_keys_hist<D, K>), dim3(hb), dim3(kHistBlock), 0, s, P, ka, va, B.hist);
     // 64-bit keys of up to four axes (batches) may take tiles of 4096 keys
     // instead of 2048 when tuned so
     if constexpr (sizeof(K) == 8 && D <= 4) {
@@ -492,6 +545,16 @@ static void sort_d(const Plan &P, const SortBuffers &B, hipStream_t s)
             sort_passes_d<D, K, 16>(P, ka, kb, va, vb, B, s);
             return;
         }
+    }
+    // tiles ranked by 512 or 1024 threads (the tile size unchanged)
+    constexpr int T = sort_items<K>() * kBlock;
+    if (P.sort_threads == 512) {
+        sort_passes_d<D, K, T / 512, 512>(P, ka, kb, va, vb, B, s);
+        return;
+    }
+    if (P.sort_threads == 1024) {
+        sort_passes_d<D, K, T / 1024, 1024>(P, ka, kb, va, vb, B, s);
+        return;
     }
     sort_passes_d<D, K, sort_items<K>()>(P, ka, kb, va, vb, B, s);
 }
@@ -547,9 +610,9 @@ void launch_cells(const Plan &P, bool wide_keys, uint64_t *status, uint32_t *tic
 {
     const uint32_t tiles = (P.n + kScanTile - 1) / kScanTile;
     if (wide_keys)
-        hipLaunchKernelGGL(k_cells<uint64_t>, dim3(tiles), dim3(kBlock), 0, s, P, status, ticket);
+        hipLaunchKernelGGL(k_cells<uint64_t>, dim3(tiles), dim3(kCellsBlock), 0, s, P, status, ticket);
     else
-        hipLaunchKernelGGL(k_cells<uint32_t>, dim3(tiles), dim3(kBlock), 0, s, P, status, ticket);
+        hipLaunchKernelGGL(k_cells<uint32_t>, dim3(tiles), dim3(kCellsBlock), 0, s, P, status, ticket);
 }
 
 }  // namespace hca
