@@ -564,6 +564,7 @@ void carve_ws(Carver &cv, Plan &P, SortBuffers &B, const Sizes &Z, uint32_t **ze
     P.gcube = cv.take<uint32_t>(n);
     P.unified = cv.take<uint8_t>(n);
     P.tile_start = cv.take<uint32_t>(n);
+    P.groot = P.tile_start;             // free once the intra-group tiles are linked
     P.group_of = cv.take<uint32_t>(n);
     if (P.nbr_cap) {
         P.nbr_count = cv.take<uint32_t>(n);

@@ -1827,18 +1827,26 @@ __global__ __launch_bounds__(kBlock) void k_merge_exact(Plan P)
 // two cubes.  Pairs of unified groups are handled as they are found; the
 // others are queued and spread over all waves.
 // ---------------------------------------------------------------------------
-// Intra-group pairs are cut into 64 x 64 tiles of points, dealt to all waves
-// so that a group of thousands of points does not rest on one wave.  Groups
-// of one cube need none (a cube is one union-find node); groups beyond
-// kTileMaxChunks chunks (8192 points) are linked cube pair by cube pair in
-// k_merge_big, whose work grows with their cubes rather than their points.
+// Intra-group pairs are cut into 64 x 64 tiles of points.  Groups of one cube
+// need none (a cube is one union-find node); a group of one chunk (at most 64
+// points) is one tile, taken by the wave that takes the group; the tiles of
+// larger groups are dealt to all waves so that a group of thousands of points
+// does not rest on one wave.  Groups beyond kTileMaxChunks chunks (8192
+// points) are linked cube pair by cube pair in k_merge_big, whose work grows
+// with their cubes rather than their points.
 constexpr uint32_t kTileMaxChunks = 128;
 
-__device__ __forceinline__ uint32_t group_tiles(const Plan &P, uint32_t g)
+// Chunks of group g's points when it has at least two cubes, else 0.
+__device__ __forceinline__ uint32_t group_chunks(const Plan &P, uint32_t g)
 {
     if (P.group_cell[g + 1] - P.group_cell[g] < 2) return 0;
-    const uint32_t nc = (P.group_start[g + 1] - P.group_start[g] + kWave - 1) / kWave;
-    return nc > kTileMaxChunks ? 0 : nc * (nc + 1) / 2;
+    return (P.group_start[g + 1] - P.group_start[g] + kWave - 1) / kWave;
+}
+
+// Tiles of group g dealt to all waves (groups of 2..kTileMaxChunks chunks).
+__device__ __forceinline__ uint32_t dealt_tiles(uint32_t nc)
+{
+    return nc < 2 || nc > kTileMaxChunks ? 0 : nc * (nc + 1) / 2;
 }
 
 // Exclusive prefix of the tile counts over groups; the total goes to the
@@ -1854,12 +1862,15 @@ __global__ __launch_bounds__(kBlock) void k_tile_scan(Plan P, uint64_t *status, 
     const uint32_t tile = s_tile, base = tile * kScanTile, g0 = base + t * kScanItems;
     // kScanItems consecutive groups per thread: one block scan per tile
     uint32_t f[kScanItems];
-    uint32_t local = 0;
+    uint32_t local = 0, big = 0;
 #pragma unroll
     for (int j = 0; j < kScanItems; j++) {
-        f[j] = g0 + j < ng ? group_tiles(P, g0 + j) : 0u;
+        const uint32_t nc = g0 + j < ng ? group_chunks(P, g0 + j) : 0u;
+        f[j] = dealt_tiles(nc);
+        big += nc > kTileMaxChunks;
         local += f[j];
     }
+    if (big) atomicAdd(&P.ctr->n_big_groups, big);
     uint32_t agg;
     const uint32_t before = block_exclusive_scan<uint32_t>(local, s_red, &agg);
     if (t < kWave) {
@@ -1876,19 +1887,76 @@ __global__ __launch_bounds__(kBlock) void k_tile_scan(Plan P, uint64_t *status, 
     if (t == 0 && base + kScanTile >= ng) st_agent32(&P.ctr->n_tiles, s_excl + agg);
 }
 
-// One 64 x 64 tile of a group's point pairs per wave.  Lane l holds point l of
-// the column chunk and its cube's root; the row chunk's points sit in LDS and
-// are visited one at a time.  A pair within eps links its two cubes only when
-// the cached roots differ; roots are refreshed after any link.
+// One 64 x 64 tile of a group's point pairs, rows [i0, i0 + 64) against
+// columns [j0, j0 + 64) of the group's points [a0, a1), by one wave.  Lane l
+// holds point l of the column chunk and its cube's root; the row chunk's
+// points sit in LDS and are visited one at a time.  A pair within eps links
+// its two cubes only when the cached roots differ; roots are refreshed after
+// any link.
+template <int D, bool WIDE>
+__device__ __forceinline__ void group_tile(const Plan &P, uint32_t a0, uint32_t a1, uint32_t i0, uint32_t j0,
+                                           int32_t (*s_pt)[D], uint32_t &lt)
+{
+    const uint32_t l = lane_id();
+    const uint32_t qi = i0 + l, qj = j0 + l;
+    const bool core_i = qi < a1 && P.core[qi];
+    const bool core_j = qj < a1 && P.core[qj];
+    const uint64_t mi = __ballot(core_i);
+    if (!mi || !__ballot(core_j)) return;
+    const uint32_t cube_i = core_i ? P.cell_of[qi] : kNone;
+    const uint32_t cube_j = core_j ? P.cell_of[qj] : kNone;
+    const Pt<D> pi = load_pt<D>(P.spts, core_i ? qi : a0);
+    const Pt<D> pj = load_pt<D>(P.spts, core_j ? qj : a0);
+#pragma unroll
+    for (int e = 0; e < D; e++) s_pt[l][e] = pi.x[e];
+    __builtin_amdgcn_wave_barrier();
+    uint32_t root_i = core_i ? uf_find(P.parent, cube_i) : kNone;
+    uint32_t root_j = core_j ? uf_find(P.parent, cube_j) : kNone;
+    {
+        // nothing to link when every cube of the tile already has one root
+        const uint32_t r0 = __shfl(root_i, __ffsll((unsigned long long)mi) - 1);
+        if (!__ballot((core_i && root_i != r0) || (core_j && root_j != r0))) {
+            __builtin_amdgcn_wave_barrier();
+            return;
+        }
+    }
+    uint64_t rows = mi;
+    while (rows) {
+        const uint32_t r = __ffsll((unsigned long long)rows) - 1;
+        rows &= rows - 1;
+        const uint32_t cr = __shfl(cube_i, r);
+        const uint32_t rr = __shfl(root_i, r);
+        Pt<D> pr;
+#pragma unroll
+        for (int e = 0; e < D; e++) pr.x[e] = s_pt[r][e];
+        lt += core_j;
+        const bool hit = core_j && cube_j > cr && within<D, WIDE>(pr, pj, P.eps2);
+        const bool need = hit && root_j != rr;
+        if (__ballot(need)) {
+            if (need) uf_union(P.parent, cr, cube_j);
+            root_j = core_j ? uf_find(P.parent, cube_j) : kNone;
+            root_i = core_i ? uf_find(P.parent, cube_i) : kNone;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Groups of one chunk: one wave per group, its single tile.  Larger groups:
+// their tiles (prefix in tile_start) dealt one per wave.
 template <int D, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_merge_tiles(Plan P)
 {
     __shared__ int32_t s_pt[kWavesPerBlock][kWave][D];
-    const uint32_t w = wave_in_block(), l = lane_id();
+    const uint32_t w = wave_in_block();
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
     const uint32_t total = ld_agent32(&P.ctr->n_tiles);
     uint32_t lt = 0;
     const WaveRange hca_wr_ = wave_range(P.order);
+    HCA_FOR_UNITS(g, ng) {
+        if (group_chunks(P, g) != 1) continue;
+        const uint32_t a0 = P.group_start[g], a1 = P.group_start[g + 1];
+        group_tile<D, WIDE>(P, a0, a1, a0, a0, s_pt[w], lt);
+    }
     HCA_FOR_UNITS(u, total) {
         // group: last g with tile_start[g] <= u
         uint32_t lo = 0, hi = ng;
@@ -1905,48 +1973,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_tiles(Plan P)
         while (ci > 0 && ci * nc - ci * (ci - 1) / 2 > t) ci--;
         while ((ci + 1) * nc - (ci + 1) * ci / 2 <= t) ci++;
         const uint32_t cj = ci + (t - (ci * nc - ci * (ci - 1) / 2));
-        const uint32_t i0 = a0 + ci * kWave, j0 = a0 + cj * kWave;
-        const uint32_t qi = i0 + l, qj = j0 + l;
-        const bool core_i = qi < a1 && P.core[qi];
-        const bool core_j = qj < a1 && P.core[qj];
-        const uint64_t mi = __ballot(core_i);
-        if (!mi || !__ballot(core_j)) continue;
-        const uint32_t cube_i = core_i ? P.cell_of[qi] : kNone;
-        const uint32_t cube_j = core_j ? P.cell_of[qj] : kNone;
-        const Pt<D> pi = load_pt<D>(P.spts, core_i ? qi : a0);
-        const Pt<D> pj = load_pt<D>(P.spts, core_j ? qj : a0);
-#pragma unroll
-        for (int e = 0; e < D; e++) s_pt[w][l][e] = pi.x[e];
-        __builtin_amdgcn_wave_barrier();
-        uint32_t root_i = core_i ? uf_find(P.parent, cube_i) : kNone;
-        uint32_t root_j = core_j ? uf_find(P.parent, cube_j) : kNone;
-        {
-            // nothing to link when every cube of the tile already has one root
-            const uint32_t r0 = __shfl(root_i, __ffsll((unsigned long long)mi) - 1);
-            if (!__ballot((core_i && root_i != r0) || (core_j && root_j != r0))) {
-                __builtin_amdgcn_wave_barrier();
-                continue;
-            }
-        }
-        uint64_t rows = mi;
-        while (rows) {
-            const uint32_t r = __ffsll((unsigned long long)rows) - 1;
-            rows &= rows - 1;
-            const uint32_t cr = __shfl(cube_i, r);
-            const uint32_t rr = __shfl(root_i, r);
-            Pt<D> pr;
-#pragma unroll
-            for (int e = 0; e < D; e++) pr.x[e] = s_pt[w][r][e];
-            lt += core_j;
-            const bool hit = core_j && cube_j > cr && within<D, WIDE>(pr, pj, P.eps2);
-            const bool need = hit && root_j != rr;
-            if (__ballot(need)) {
-                if (need) uf_union(P.parent, cr, cube_j);
-                root_j = core_j ? uf_find(P.parent, cube_j) : kNone;
-                root_i = core_i ? uf_find(P.parent, cube_i) : kNone;
-            }
-        }
-        __builtin_amdgcn_wave_barrier();
+        group_tile<D, WIDE>(P, a0, a1, a0 + ci * kWave, a0 + cj * kWave, s_pt[w], lt);
     }
     flush_tests(P, kTestsIntra, lt);
 }
@@ -1966,6 +1993,7 @@ template <int D, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_merge_big(Plan P)
 {
     const uint32_t l = lane_id();
+    if (ld_agent32(&P.ctr->n_big_groups) == 0) return;      // counted by k_tile_scan
     const uint32_t nc = ld_agent32(&P.ctr->n_cells);
     const uint64_t fmask = (1ull << P.bm) - 1ull;
     uint32_t lt = 0;
@@ -2021,8 +2049,9 @@ __global__ __launch_bounds__(kBlock) void k_merge_unify(Plan P)
             if (m) first = cb + __ffsll((unsigned long long)m) - 1;
         }
         bool unified = true;
+        uint32_t r0 = kNone;
         if (first != kNone) {
-            const uint32_t r0 = uf_find(P.parent, first);
+            r0 = uf_find(P.parent, first);
             for (uint32_t cb = first; cb < c1 && unified; cb += kWave) {
                 const uint32_t c = cb + l;
                 const bool other = c < c1 && P.ncore[c] > 0 && uf_find(P.parent, c) != r0;
@@ -2032,6 +2061,9 @@ __global__ __launch_bounds__(kBlock) void k_merge_unify(Plan P)
         if (l == 0) {
             P.gcube[g] = first;
             P.unified[g] = unified;
+            // roots only ever join: two groups with the same snapshot root are
+            // in one cluster for good
+            P.groot[g] = unified ? r0 : kNone;
         }
     }
 }
@@ -2157,6 +2189,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_merge_inter(Plan P)
         const uint32_t ga = P.gcube[GA];
         if (ga == kNone) continue;                                 // no core point
         const bool ua = P.unified[GA];
+        const uint32_t rA = P.groot[GA];
         const uint64_t gkey = P.group_key[GA];
         // bounding box of GA's core points
         const uint32_t a0 = P.group_start[GA], a1 = P.group_start[GA + 1];
@@ -2184,7 +2217,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_merge_inter(Plan P)
                 uint64_t nk = ~0ull;
                 if (src.lists) {
                     const uint32_t G = P.nbr[src.start + j - 1];
-                    if (G > GA) { GB = G; nk = P.group_key[G]; }
+                    // a pair already joined by the intra-group linking needs nothing
+                    if (G > GA && (rA == kNone || P.groot[G] != rA)) { GB = G; nk = P.group_key[G]; }
                 } else {
                     // groups are numbered in key order: GB > GA exactly when
                     // the first non-zero component of the offset is positive

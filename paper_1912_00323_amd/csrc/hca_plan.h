@@ -90,7 +90,7 @@ struct Counters {
     uint32_t n_small;           // core cubes of at most kRepLanePts points (core_cubes)
     uint32_t n_big;             // the other core cubes (big_cubes)
     uint32_t n_chunks;          // chunks of kRepChunk points of those (rep_chunks)
-    uint32_t pad[1];
+    uint32_t n_big_groups;      // groups beyond kTileMaxChunks chunks (linked cube pair by cube pair)
     uint32_t work_count[kWorkRegions * kCounterStride];   // region r at [r * kCounterStride]
     // pair tests executed, per phase (core, merge, border), spread over
     // kWorkRegions lines of eight 64-bit words; counted only on request
@@ -208,6 +208,7 @@ struct Plan {
     uint32_t *parent;           // [n] union-find over cubes
     uint32_t *gcube;            // [n] group -> first cube with a core point, kNone if none
     uint8_t *unified;           // [n] group -> its core cubes share one union-find root
+    uint32_t *groot;            // [n] group -> that root when unified (snapshot after intra linking), else kNone; in tile_start's array
     uint32_t *tile_start;       // [n] group -> first intra-group tile
     // group mode: the non-empty neighbour groups of each group (self
     // excluded) that can hold a point within eps of one of its points.  Each
