@@ -550,6 +550,9 @@ void carve_ws(Carver &cv, Plan &P, SortBuffers &B, const Sizes &Z, uint32_t **ze
     B.keys_b = cv.take<char>((size_t)n * ksz);
     B.vals_a = cv.take<uint32_t>(n);
     B.vals_b = cv.take<uint32_t>(n);
+    // rows of one or two axes travel with the keys through the radix passes
+    // (more passes than four would move more than the gather it replaces)
+    B.rows = P.d <= 2 && P.passes <= 4 ? cv.take<int32_t>((size_t)n * P.d) : nullptr;
     const size_t sd = std::max<uint32_t>(P.sd, (uint32_t)P.d);   // row stride of points and group boxes
     P.spts = cv.take<int32_t>((size_t)n * sd);
     P.cell_of = cv.take<uint32_t>(n);

@@ -11,6 +11,7 @@ struct SortBuffers {
     uint32_t *hist;          // [passes][256], zeroed
     uint64_t *status;        // [passes][tiles][256], zeroed
     uint32_t *tickets;       // [passes], zeroed
+    int32_t *rows;           // [n][d] rows between passes when they travel with the keys, else null
     void *result_keys;       // set by launch_sort
     uint32_t *result_vals;
 };

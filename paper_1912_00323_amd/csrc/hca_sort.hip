@@ -143,7 +143,7 @@ __global__ __launch_bounds__(kHistBlock) void k_keys_hist(Plan P, K *__restrict_
             if (i >= P.n) break;
             const K key = cube_key<D, K>(P, p[j], i);
             keys[i] = key;
-            vals[i] = i;
+            if (vals) vals[i] = i;
             for (uint32_t q = 0; q < passes; q++)
                 atomicAdd(&s_hist[q * kRadix + (uint32_t)((key >> (q * P.digit_bits)) & dmask)], 1u);
         }
@@ -226,19 +226,30 @@ __device__ __forceinline__ bool hd_new_cube(const Plan &P, uint32_t idx)
 // passes, so that the runs a tile writes per digit are as long as they can
 // be for that number of passes.
 //
-// A workgroup takes the next tile (sort_items keys per thread) by ticket.
-// Each wave owns a quarter of it, consecutive keys, and ranks them in rounds
-// of 64: lanes with equal digits find each other with one ballot per digit
-// bit, and a per-wave digit counter in LDS gives each key its rank.  The tile's digit counts are published at once
-// and turned into global offsets by looking back over earlier tiles; keys
-// are then staged in LDS in digit order and written out in runs.
+// A workgroup takes the next tile (ITEMS keys per thread) by ticket.  Each
+// wave owns consecutive keys of it and ranks them in rounds of 64: lanes with
+// equal digits find each other with one ballot per digit bit, and a per-wave
+// digit counter in LDS gives each key its rank.  The tile's digit counts are
+// published at once and turned into global offsets by looking back over
+// earlier tiles; keys are then staged in LDS in digit order and written out
+// in runs.
+//
+// The values are input indices; the first pass (vin null) takes them from the
+// key's position.  The points reach cube order in one of two ways (MODE):
+// kSortGather, the last pass gathers each row from its input position; or
+// kSortCarry, the rows travel with the keys through every pass (read in tile
+// order, staged in LDS, written in runs), which replaces the last pass's
+// random row reads with ordered ones when rows are small.
 // ---------------------------------------------------------------------------
-template <typename K, int D, bool GATHER, int ITEMS = sort_items<K>(), int THREADS = kBlock>
+enum { kSortPlain = 0, kSortGather = 1, kSortCarry = 2 };
+
+template <typename K, int D, int MODE, int ITEMS = sort_items<K>(), int THREADS = kBlock>
 __global__ __launch_bounds__(THREADS) void k_onesweep(Plan P, const K *__restrict__ kin,
                                                      const uint32_t *__restrict__ vin,
                                                      K *__restrict__ kout, uint32_t *__restrict__ vout,
                                                      uint32_t shift, const uint32_t *hist,
-                                                     uint64_t *__restrict__ status, uint32_t *ticket)
+                                                     uint64_t *__restrict__ status, uint32_t *ticket,
+                                                     const int32_t *__restrict__ rin, int32_t *__restrict__ rout)
 {
     constexpr int W = THREADS / kWave;
     constexpr int kItems = ITEMS;
@@ -247,6 +258,7 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(Plan P, const K *__restric
     constexpr int RADIX = 1 << radix_bits<K>();
     __shared__ K s_keys[kTile];
     __shared__ uint32_t s_vals[kTile];
+    __shared__ Pt<D> s_rows[MODE == kSortCarry ? kTile : 1];
     __shared__ uint32_t s_wcnt[W][RADIX];       // per-wave digit counts, then offsets
     __shared__ uint32_t s_tstart[RADIX];        // tile-local start of each digit
     __shared__ uint32_t s_gbase[RADIX];         // global position of tile-local 0 per digit
@@ -265,12 +277,16 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(Plan P, const K *__restric
 
     K key[kItems];
     uint32_t val[kItems], rank[kItems], dig[kItems];
+    Pt<D> row[MODE == kSortCarry ? kItems : 1];
 #pragma unroll
     for (int j = 0; j < kItems; j++) {
         const uint32_t idx = base + j * kWave + l;
         const bool ok = idx < n;
         key[j] = ok ? kin[idx] : (K)0;
-        val[j] = ok ? vin[idx] : 0u;
+        val[j] = ok ? (vin ? vin[idx] : idx) : 0u;
+        if constexpr (MODE == kSortCarry) {
+            if (ok) row[j] = load_pt<D>(rin, idx);
+        }
     }
 #pragma unroll
     for (int j = 0; j < kItems; j++) {
@@ -357,6 +373,7 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(Plan P, const K *__restric
             const uint32_t lp = s_tstart[dig[j]] + s_wcnt[w][dig[j]] + rank[j];
             s_keys[lp] = key[j];
             s_vals[lp] = val[j];
+            if constexpr (MODE == kSortCarry) s_rows[lp] = row[j];
         }
     }
     __syncthreads();
@@ -368,7 +385,8 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(Plan P, const K *__restric
         const uint32_t pos = s_gbase[(uint32_t)(kk >> shift) & dmask] + i;
         kout[pos] = kk;
         vout[pos] = vv;
-        if constexpr (GATHER) store_pt<D>(P.spts, pos, load_pt<D>(P.pts, vv));
+        if constexpr (MODE == kSortGather) store_pt<D>(P.spts, pos, load_pt<D>(P.pts, vv));
+        if constexpr (MODE == kSortCarry) store_pt<D>(rout, pos, s_rows[i]);
     }
 }
 
@@ -516,15 +534,30 @@ static void sort_passes_d(const Plan &P, K *ka, K *kb, uint32_t *va, uint32_t *v
                           hipStream_t s)
 {
     const uint32_t tiles = (P.n + THREADS * ITEMS - 1) / (THREADS * ITEMS);
+    const bool carry = D <= 2 && B.rows != nullptr;
     for (uint32_t q = 0; q < P.passes; q++) {
         uint64_t *st = B.status + (uint64_t)q * tiles * kRadix;
         const bool last = q + 1 == P.passes;
-        if (last)
-            hipLaunchKernelGGL((k_onesweep<K, D, true, ITEMS, THREADS>), dim3(tiles), dim3(THREADS), 0, s, P, ka,
-                               va, kb, vb, q * P.digit_bits, B.hist + q * kRadix, st, B.tickets + q);
-        else
-            hipLaunchKernelGGL((k_onesweep<K, D, false, ITEMS, THREADS>), dim3(tiles), dim3(THREADS), 0, s, P, ka,
-                               va, kb, vb, q * P.digit_bits, B.hist + q * kRadix, st, B.tickets + q);
+        const uint32_t *vin = q == 0 ? nullptr : va;         // the first pass numbers the keys itself
+        if (carry) {
+            if constexpr (D <= 2) {
+                // rows: input -> ... -> sorted points, alternating with B.rows
+                // so that the last pass writes P.spts
+                const int32_t *rin = q == 0 ? P.pts : ((P.passes - q) & 1u) ? B.rows : P.spts;
+                int32_t *rout = ((P.passes - 1 - q) & 1u) ? B.rows : P.spts;
+                hipLaunchKernelGGL((k_onesweep<K, D, kSortCarry, ITEMS, THREADS>), dim3(tiles), dim3(THREADS), 0,
+                                   s, P, ka, vin, kb, vb, q * P.digit_bits, B.hist + q * kRadix, st, B.tickets + q,
+                                   rin, rout);
+            }
+        } else if (last) {
+            hipLaunchKernelGGL((k_onesweep<K, D, kSortGather, ITEMS, THREADS>), dim3(tiles), dim3(THREADS), 0, s,
+                               P, ka, vin, kb, vb, q * P.digit_bits, B.hist + q * kRadix, st, B.tickets + q,
+                               nullptr, nullptr);
+        } else {
+            hipLaunchKernelGGL((k_onesweep<K, D, kSortPlain, ITEMS, THREADS>), dim3(tiles), dim3(THREADS), 0, s,
+                               P, ka, vin, kb, vb, q * P.digit_bits, B.hist + q * kRadix, st, B.tickets + q,
+                               nullptr, nullptr);
+        }
         K *tk = ka; ka = kb; kb = tk;
         uint32_t *tv = va; va = vb; vb = tv;
     }
@@ -537,7 +570,8 @@ static void sort_d(const Plan &P, const SortBuffers &B, hipStream_t s)
     const int hb = (int)std::min<uint64_t>((P.n + kHistBlock * 4 - 1) / (kHistBlock * 4), 256);
     K *ka = (K *)B.keys_a, *kb = (K *)B.keys_b;
     uint32_t *va = B.vals_a, *vb = B.vals_b;
-    hipLaunchKernelGGL((k_keys_hist<D, K>), dim3(hb), dim3(kHistBlock), 0, s, P, ka, va, B.hist);
+    // the first radix pass numbers the keys itself: no values written here
+    hipLaunchKernelGGL((k_keys_hist<D, K>), dim3(hb), dim3(kHistBlock), 0, s, P, ka, (uint32_t *)nullptr, B.hist);
     // 64-bit keys of up to four axes (batches) may take tiles of 4096 keys
     // instead of 2048 when tuned so
     if constexpr (sizeof(K) == 8 && D <= 4) {
@@ -593,8 +627,8 @@ void launch_sort_hd(Plan &P, SortBuffers &B, hipStream_t s)
     const uint32_t tiles = (P.n + kBlock * sort_items<uint64_t>() - 1) / (kBlock * sort_items<uint64_t>());
     for (uint32_t q = 0; q < P.passes; q++) {
         uint64_t *st = B.status + (uint64_t)q * tiles * kRadix;
-        hipLaunchKernelGGL((k_onesweep<uint64_t, 1, false>), dim3(tiles), dim3(kBlock), 0, s, P, ka, va, kb, vb,
-                           q * P.digit_bits, B.hist + q * kRadix, st, B.tickets + q);
+        hipLaunchKernelGGL((k_onesweep<uint64_t, 1, kSortPlain>), dim3(tiles), dim3(kBlock), 0, s, P, ka, va, kb,
+                           vb, q * P.digit_bits, B.hist + q * kRadix, st, B.tickets + q, nullptr, nullptr);
         uint64_t *tk = ka; ka = kb; kb = tk;
         uint32_t *tv = va; va = vb; vb = tv;
     }
