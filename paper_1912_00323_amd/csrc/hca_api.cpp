@@ -232,6 +232,19 @@ uint32_t sort_threads(bool wide_keys)
     return wide_keys ? 512u : 1024u;
 }
 
+// Keys per radix tile of 32-bit keys: 8192 from 8M keys on (each tile's
+// runs per digit twice as long, with tiles enough to fill the chip), else
+// the default 4096; HCA_SORT_TILE=4096|8192 overrides.
+uint32_t sort_tile(uint32_t n, bool wide_keys)
+{
+    if (wide_keys) return 0u;
+    const char *e = std::getenv("HCA_SORT_TILE");
+    const int v = e ? std::atoi(e) : 0;
+    if (v == 4096) return 0u;
+    if (v == 8192) return 8192u;
+    return n >= (8u << 20) ? 8192u : 0u;
+}
+
 // HCA_ORDER=reverse|permute: the wave-dealt units of the neighbour phases
 // taken in reverse or permuted order (tests: the result must not depend on
 // the schedule)
@@ -483,6 +496,7 @@ void plan_sizes(Plan &P, uint32_t gbits, bool count_work, bool want_stats, Sizes
     P.hash_load = t ? (uint32_t)std::min(std::max(t->hash_load, 1), 3) : 1u;
     P.sort_items = t && t->sort_items == 16 ? 16u : 0u;
     P.sort_threads = sort_threads(Z->wide_keys);
+    P.sort_tile = sort_tile(n, Z->wide_keys);
     Z->hcap = 1024;
     while (Z->hcap < ((uint64_t)n << P.hash_load)) Z->hcap <<= 1;
     P.hash_mask = Z->hcap - 1;

@@ -188,6 +188,7 @@ struct Plan {
     uint32_t hash_load;         // slots in use >= groups << hash_load (at least 1024)
     uint32_t sort_items;        // keys per thread of a radix tile (0: the key type's default)
     uint32_t sort_threads;      // threads that rank a radix tile (256, 512 or 1024; the tile size is the key type's)
+    uint32_t sort_tile;         // keys per radix tile of 32-bit keys: 0 (4096) or 8192
 
     // buffers
     const int32_t *pts;         // [n][d] input order

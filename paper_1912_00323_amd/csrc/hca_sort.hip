@@ -580,6 +580,13 @@ static void sort_d(const Plan &P, const SortBuffers &B, hipStream_t s)
             return;
         }
     }
+    // 32-bit keys in tiles of 8192 (512 threads of 16 keys)
+    if constexpr (sizeof(K) == 4) {
+        if (P.sort_tile == 8192) {
+            sort_passes_d<D, K, 16, 512>(P, ka, kb, va, vb, B, s);
+            return;
+        }
+    }
     // tiles ranked by 512 or 1024 threads (the tile size unchanged)
     constexpr int T = sort_items<K>() * kBlock;
     if (P.sort_threads == 512) {

@@ -401,6 +401,41 @@ def test_sort_digit_widths(ctx, d):
         assert st["sort_passes"] == max(1, -(-kb // rb)), (kb, st["sort_passes"])
 
 
+@pytest.mark.parametrize("tile,threads", [("4096", "256"), ("4096", "512"), ("4096", "1024"), ("8192", "")])
+def test_sort_tiles(ctx, tile, threads, monkeypatch):
+    """Radix tiles ranked by 256, 512 or 1024 threads, and tiles of 8192 keys
+    (chosen from 8M keys on), with rows of one and two axes carried through
+    the passes and wider rows gathered: the oracle's labels, on inputs whose
+    length leaves a ragged last tile."""
+    monkeypatch.setenv("HCA_SORT_TILE", tile)
+    if threads:
+        monkeypatch.setenv("HCA_SORT_THREADS", threads)
+    rng = np.random.default_rng(410)
+    for d, n, eps in ((1, 30_001, 2.0), (2, 50_003, 60.0), (3, 20_011, 300.0)):
+        pts = quantise(make_blobs(rng, n, d, 6, 0.01, 0.1), 16)
+        check(ctx, pts, eps, 5, f"sort tiles {tile}/{threads or 'default'} d={d}")
+
+
+def test_large_sort_tiles_agree(ctx, monkeypatch):
+    """At 9M points (tiles of 8192 keys by default) the labels equal those
+    of tiles of 4096 keys, and core points of a sample pass the brute-force
+    check of the definition."""
+    import torch
+    w = make_config(2, n=9_000_000)
+    pts = torch.from_numpy(w.points).cuda()
+    print("[case] 9M 2-D, tiles of 8192 vs 4096", flush=True)
+    big, core = ctx.cluster(pts, w.eps, w.min_pts, core=True)
+    monkeypatch.setenv("HCA_SORT_TILE", "4096")
+    small = ctx.cluster(pts, w.eps, w.min_pts)
+    assert torch.equal(big, small)
+    rng = np.random.default_rng(5)
+    core = core.cpu().numpy()
+    e2 = oracle.exact_eps2(w.eps)
+    for i in rng.choice(w.n, 40, replace=False):
+        d2 = ((w.points.astype(np.int64) - w.points[i].astype(np.int64)) ** 2).sum(1)
+        assert bool(core[i]) == (int((d2 <= e2).sum()) >= w.min_pts), i
+
+
 def test_errors(ctx):
     from paper_1912_00323_amd import hca
     import torch
