@@ -1738,23 +1738,38 @@ __global__ __launch_bounds__(kBlock) void k_merge_cubes(Plan P)
     const WaveRange hca_wr_ = wave_range(P.order);
     HCA_FOR_UNITS(wu, (uint32_t)((pairs + kWave - 1) / kWave)) {
         const uint64_t u = (uint64_t)wu * kWave + l;
-        uint32_t A = kNone, B = kNone, dfw = 0, dbw = 0;
+        uint32_t A = kNone, B = kNone;
+        uint64_t ra = ~0ull, rb = ~0ull;
+        uint32_t ncb = 0;
         int64_t eps2 = 0;
+        // the loads of each step are issued together: A's key and facing
+        // representative, then B's core count and facing representative (a
+        // non-core cube's slot may hold anything and is read only once B's
+        // count shows it core)
         if (u < pairs) {
             const uint32_t ci = (uint32_t)(u / nf), f = (uint32_t)(u - (uint64_t)ci * nf);
             A = ci < ns ? P.core_cubes[ci] : P.big_cubes[ci - ns];
             const uint32_t j = s_fwd[w][f];
             const uint64_t gkey = P.group_key[A];
+            if (P.n_dir) ra = ld_agent(P.rep + (uint64_t)A * P.n_dir + P.dir_fwd[j]);
             eps2 = cube_geo<D>(P, gkey).eps2;
             const uint64_t nk = group_neighbour<D>(P, gkey, P.off + (uint64_t)j * D);
             if (nk != ~0ull) B = group_lookup(P, nk);
-            if (P.n_dir) {
-                dfw = P.dir_fwd[j];
-                dbw = P.dir_bwd[j];
+            if (B != kNone && B > A) {
+                ncb = P.ncore[B];
+                if (P.n_dir) rb = ld_agent(P.rep + (uint64_t)B * P.n_dir + P.dir_bwd[j]);
             }
         }
-        const bool exact = rep_pair<D, WIDE>(P, A, B, dfw, dbw, eps2, lt);
-        queue_exact<D, WIDE>(P, exact, A, B, lt);
+        bool todo = ncb > 0, joined = false;
+        // a core cube always has a representative in every direction; a slot
+        // still "none" (all ones) is left to the exact test rather than read
+        if (todo && ra != ~0ull && rb != ~0ull) {
+            lt++;
+            joined = within<D, WIDE>(load_pt<D>(P.spts, (uint32_t)ra), load_pt<D>(P.spts, (uint32_t)rb), eps2);
+            if (joined) uf_union(P.parent, A, B);
+        }
+        if (todo && !joined && !P.rep_only) todo = uf_find(P.parent, A) != uf_find(P.parent, B);
+        queue_exact<D, WIDE>(P, todo && !joined && !P.rep_only, A, B, lt);
     }
     flush_tests(P, kTestsMerge, lt);
 }
@@ -2417,24 +2432,69 @@ __device__ __forceinline__ void border_walk(const Plan &P, uint32_t g, uint64_t 
 // Border points whose neighbours core marking saw in full (all within eps,
 // all recorded: fewer than minPts of them, at most kRec): the nearest core
 // point among them, ties to the smaller input index, one thread per point.
-// The walks below take the other non-core points.
+// The other non-core points are listed in P.blist for the walks below.
 // ---------------------------------------------------------------------------
 template <int D, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_border_rec(Plan P)
 {
-    for (uint32_t p = blockIdx.x * kBlock + threadIdx.x; p < P.n; p += gridDim.x * kBlock) {
-        if (P.core[p] || !rec_complete(P, p)) continue;
-        const Pt<D> a = load_pt<D>(P.spts, p);
+    // records handled RB at a time: their flags, then their rows and input
+    // indices, each step's loads issued together
+    constexpr int RB = D <= 2 ? 16 : D <= 4 ? 8 : 4;
+    const uint32_t l = lane_id();
+    for (uint32_t base = (blockIdx.x * kBlock + threadIdx.x) & ~(kWave - 1u); base < P.n;
+         base += gridDim.x * kBlock) {
+        const uint32_t p = base + l;
+        const bool noncore = p < P.n && !P.core[p];
+        const uint32_t nr = noncore ? P.nrec[p] : 0u;
+        const bool mine = noncore && nr <= (uint32_t)kRec;
+        // the others (records overflowed) are listed for the walk, one atomic
+        // per wave
+        const bool left = noncore && !mine;
+        const uint64_t m = __ballot(left);
+        if (m) {
+            uint32_t at = 0;
+            if (l == 0) at = atomicAdd(&P.ctr->n_blist, (uint32_t)__popcll(m));
+            at = __shfl(at, 0);
+            if (left) P.blist[at + __popcll(m & __lanemask_lt())] = p;
+        }
+        if (!__ballot(mine)) continue;
+        uint32_t q[kRec];
+        if (mine) {
+            const uint4 *rp = reinterpret_cast<const uint4 *>(P.rec + (uint64_t)p * kRec);
+#pragma unroll
+            for (int i = 0; i < kRec / 4; i++) {
+                const uint4 v = rp[i];
+                q[4 * i] = v.x;
+                q[4 * i + 1] = v.y;
+                q[4 * i + 2] = v.z;
+                q[4 * i + 3] = v.w;
+            }
+        }
+        const Pt<D> a = load_pt<D>(P.spts, mine ? p : 0u);
         int64_t bd = INT64_MAX;
         uint32_t bi = kNone, bq = kNone;
-        for (uint32_t r = 0, nr = P.nrec[p]; r < nr; r++) {
-            const uint32_t q = P.rec[(uint64_t)p * kRec + r];
-            if (!P.core[q]) continue;
-            const int64_t dd = dist2<D, WIDE>(a, load_pt<D>(P.spts, q));
-            const uint32_t qi = P.sidx[q];
-            if (dd < bd || (dd == bd && qi < bi)) { bd = dd; bi = qi; bq = q; }
+#pragma unroll
+        for (int r0 = 0; r0 < kRec; r0 += RB) {
+            bool c[RB];
+#pragma unroll
+            for (int k = 0; k < RB; k++) c[k] = mine && (uint32_t)(r0 + k) < nr && P.core[q[r0 + k]];
+            Pt<D> b[RB];
+            uint32_t qi[RB];
+#pragma unroll
+            for (int k = 0; k < RB; k++) {
+                if (c[k]) {
+                    b[k] = load_pt<D>(P.spts, q[r0 + k]);
+                    qi[k] = P.sidx[q[r0 + k]];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < RB; k++) {
+                if (!c[k]) continue;
+                const int64_t dd = dist2<D, WIDE>(a, b[k]);
+                if (dd < bd || (dd == bd && qi[k] < bi)) { bd = dd; bi = qi[k]; bq = q[r0 + k]; }
+            }
         }
-        finish_owner(P, p, bq);
+        if (mine) finish_owner(P, p, bq);
     }
 }
 
@@ -2867,8 +2927,7 @@ void launch_border(const Plan &P, int blocks, hipStream_t s)
 {
     if (P.rec) {
         const int cb = (int)std::min<uint64_t>((P.n + kBlock - 1) / kBlock, 2048);
-        HCA_DISPATCH_DW(k_border_rec, P, cb, s);
-        launch_border_list(P, s);
+        HCA_DISPATCH_DW(k_border_rec, P, cb, s);            // also lists the points it cannot decide
         HCA_DISPATCH_DW(k_border_walk_list, P, blocks, s);
         return;
     }
