@@ -230,9 +230,10 @@ hca_status hca_cluster_sets(hca_ctx *ctx, const int32_t *const *points, int32_t 
  * and tunes it on the first run otherwise; 2 always tunes on the first run.
  * The knobs are the representative mode (on/off), the core-marking mode (a
  * lane per point or a wave per cube), the enumeration mode (prefix-range
- * list scans or lookups), the persistent blocks of the neighbour phases, the
- * hash load factor, the radix digit width and the radix tile size; every
- * choice gives the same labels.  The cache is a JSON file (HCA_TUNE_CACHE,
+ * list scans or lookups), cube-mode neighbour lists (built once, or the
+ * stencil walked in every phase), the persistent blocks of the neighbour
+ * phases, the hash load factor, the radix digit width and the radix tile
+ * size; every choice gives the same labels.  The cache is a JSON file (HCA_TUNE_CACHE,
  * else $HOME/.cache/hca_tune.json) keyed by dimension, rows, cubes per axis
  * and data sets, in powers of two.
  * hca_batch_run clusters one batch of that shape: points[i] (DEVICE,
@@ -273,7 +274,7 @@ typedef struct {
     int32_t digit_cap;
     int32_t sort_items;
     int32_t tuned;            /* 1 tuned on this handle's first run, 2 from the cache, 0 default */
-    int32_t reserved;
+    int32_t lists;            /* 1 when the plan builds neighbour lists (tuned off: the stencil is walked) */
     double tuned_ms;
     double default_ms;
 } hca_batch_group;

@@ -467,8 +467,12 @@ struct Carver {
 // Neighbour lists in cube mode pay when the stencil is large (d >= 3): they
 // are built once and walked by core marking, merging and border assignment.
 // Returns 2R + 1 when they are used, else 0.
-uint32_t cube_list_width(int d, int32_t radius, uint32_t n_off)
+// HCA_CUBE_LISTS=0 (or a tuned lists = 0): every phase walks the stencil.
+uint32_t cube_list_width(int d, int32_t radius, uint32_t n_off, const Tune *t = nullptr)
 {
+    if (t && t->lists == 0) return 0u;
+    const char *e = std::getenv("HCA_CUBE_LISTS");
+    if ((!t || t->lists < 0) && e && !std::strcmp(e, "0")) return 0u;
     const uint32_t w = 2u * (uint32_t)radius + 1u;
     uint64_t half = 1;
     for (int k = 0; k < (d + 1) / 2; k++) half *= w;
@@ -1398,7 +1402,7 @@ void batch_plan(BatchGroup &g, char *db, const Tune *t)
     P.core_out = nullptr;
     int32_t rmax = 0;
     for (int32_t v : g.radius) rmax = std::max(rmax, v);
-    P.list_w = cube_list_width(d, rmax, P.n_off);
+    P.list_w = cube_list_width(d, rmax, P.n_off, t);
     plan_core_lanes(P, rmax, t);
     plan_sizes(P, P.key_bits, false, false, &g.Z, t);
     plan_prefix(P, P.key_bits, &g.Z, t);
@@ -1635,6 +1639,10 @@ hca_status tune_group(hca_batch *b, BatchGroup &g)
         Tune c = g.tune;
         c.prefix = 1 - c.prefix;
         st = try_all({c});
+        if (st) return st;
+        Tune e = g.tune;
+        e.lists = 0;                          // the stencil walked in every phase
+        st = try_all({e});
         if (st) return st;
     }
     {
@@ -2028,6 +2036,7 @@ hca_status hca_batch_stats(const hca_batch *b, hca_batch_info *info, hca_batch_g
         o.hash_load = g.tune.hash_load;
         o.digit_cap = g.tune.digit_cap;
         o.sort_items = g.tune.sort_items;
+        o.lists = g.P.list_w != 0;
         o.tuned = g.tuned ? 1 : g.from_cache ? 2 : 0;
         o.tuned_ms = g.tuned_ms;
         o.default_ms = g.default_ms;

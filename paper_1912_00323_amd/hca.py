@@ -33,7 +33,7 @@ class Geometry(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class Stats(ctypes.Structure):
@@ -132,11 +132,11 @@ class BatchGroupInfo(ctypes.Structure):
                 ("key_bits", ctypes.c_int32), ("sort_passes", ctypes.c_int32), ("wide", ctypes.c_int32),
                 ("reps", ctypes.c_int32), ("lanes", ctypes.c_int32), ("prefix", ctypes.c_int32),
                 ("wave_blocks", ctypes.c_int32), ("hash_load", ctypes.c_int32), ("digit_cap", ctypes.c_int32),
-                ("sort_items", ctypes.c_int32), ("tuned", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("sort_items", ctypes.c_int32), ("tuned", ctypes.c_int32), ("lists", ctypes.c_int32),
                 ("tuned_ms", ctypes.c_double), ("default_ms", ctypes.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class Batch:

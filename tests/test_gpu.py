@@ -88,6 +88,20 @@ def test_search_modes_agree(ctx, mode, reps, monkeypatch):
         check(ctx, pts, 0.05 * 2 ** 12, 5, f"mode={mode} reps={reps} d={d}")
 
 
+@pytest.mark.parametrize("lists", ["1", "0"])
+def test_cube_lists_on_off(ctx, lists, monkeypatch):
+    """Cube mode in three and four axes with neighbour lists built once, or
+    the stencil walked in every phase (the tuner's lists knob): the oracle's
+    labels either way."""
+    monkeypatch.setenv("HCA_SEARCH", "cube")
+    monkeypatch.setenv("HCA_CUBE_LISTS", lists)
+    for d in (3, 4):
+        rng = np.random.default_rng(17 * d)
+        pts = quantise(make_blobs(rng, 6000, d, 5, 0.03, 0.1), 12)
+        for eps, mp in ((0.03 * 2 ** 12, 4), (0.08 * 2 ** 12, 9)):
+            check(ctx, pts, eps, mp, f"cube lists={lists} d={d}")
+
+
 @pytest.mark.parametrize("slab", ["0", "16", "64"])
 def test_group_lists_fallback(ctx, slab, monkeypatch):
     """Group mode with no neighbour lists (stencil walk) and with slabs so small
