@@ -241,11 +241,12 @@ __global__ __launch_bounds__(kBlock) void k_init(uint32_t *zero, uint64_t zero_w
 }
 
 // ---------------------------------------------------------------------------
-// Group lookup table: direct index over the packed group key, or open
-// addressing with linear probing (64-bit keys, all-ones = empty).  The hash
-// uses a power of two >= 2^hash_load x the groups of this call (at least 1024
-// slots; hash_load is 1 unless tuned), so
-// that the slots probed stay few and cache-resident; only those start empty.
+// Group lookup table: direct index over the packed group key (written by
+// k_cells at each group's start), or open addressing with linear probing
+// (64-bit keys, all-ones = empty).  The hash uses a power of two >=
+// 2^hash_load x the groups of this call (at least 1024 slots; hash_load is 1
+// unless tuned), so that the slots probed stay few and cache-resident; only
+// those start empty.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_table_clear(Plan P)
 {
@@ -266,10 +267,6 @@ __global__ __launch_bounds__(kBlock) void k_table(Plan P)
     const uint64_t mask = P.ctr->hmask;
     for (uint32_t g = blockIdx.x * kBlock + threadIdx.x; g < ng; g += gridDim.x * kBlock) {
         const uint64_t key = P.group_key[g];
-        if (P.dense) {
-            P.table[key] = g;
-            continue;
-        }
         uint64_t h = mix64(key) & mask;
         while (true) {
             const uint64_t prev = atomicCAS((unsigned long long *)(P.hkeys + h), ~0ull, key);
@@ -2797,12 +2794,13 @@ void launch_init(uint32_t *zero, uint64_t zero_words, uint32_t *table, uint64_t 
     hipLaunchKernelGGL(k_init, dim3(blocks), dim3(kBlock), 0, s, zero, zero_words, table, tsize);
 }
 
+// The direct table is written by k_cells; the hash is sized to the groups
+// that scan found, cleared, then filled.
 void launch_table(const Plan &P, int blocks, hipStream_t s)
 {
-    if (!P.dense) {
-        const int cb = (int)std::min<uint64_t>((P.hash_mask + kBlock) / kBlock, 1024);
-        hipLaunchKernelGGL(k_table_clear, dim3(cb), dim3(kBlock), 0, s, P);
-    }
+    if (P.dense) return;
+    const int cb = (int)std::min<uint64_t>((P.hash_mask + kBlock) / kBlock, 1024);
+    hipLaunchKernelGGL(k_table_clear, dim3(cb), dim3(kBlock), 0, s, P);
     hipLaunchKernelGGL(k_table, dim3(blocks), dim3(kBlock), 0, s, P);
 }
 

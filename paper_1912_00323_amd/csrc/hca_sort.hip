@@ -479,9 +479,11 @@ __global__ __launch_bounds__(kCellsBlock) void k_cells(Plan P, uint64_t *__restr
         }
         if (v >> 31) {
             const uint32_t g = (uint32_t)(inc >> 31) - 1u;
+            const uint64_t gk = (uint64_t)kk[j] >> fb;
             P.group_start[g] = idx;
-            P.group_key[g] = (uint64_t)kk[j] >> fb;
+            P.group_key[g] = gk;
             P.group_cell[g] = cell;
+            if (P.dense) P.table[gk] = g;            // the direct lookup table (all ones before)
         }
         if (idx == n - 1) {
             const uint32_t nc = (uint32_t)(inc & lo_mask), ng = (uint32_t)(inc >> 31);
