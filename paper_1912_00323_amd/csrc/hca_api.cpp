@@ -719,8 +719,11 @@ void fill_stats(hca_ctx *ctx, const Plan &P, hca_stats *stats)
     int64_t pairs = 0;
     for (int r = 0; r < kWorkRegions; r++) pairs += hc->work_count[r * kCounterStride];
     stats->exact_pairs = pairs;
-    stats->n_core_points = hc->n_core;
-    stats->n_noise = hc->n_noise;
+    int64_t tally[2] = {0, 0};
+    for (int k = 0; k < 2; k++)
+        for (int r = 0; r < kWorkRegions; r++) tally[k] += hc->tally[k][r * kCounterStride];
+    stats->n_core_points = tally[0];
+    stats->n_noise = tally[1];
     stats->n_clusters = hc->n_clusters;
     int64_t *const dst[4] = {&stats->tests_core, &stats->tests_merge, &stats->tests_border,
                              &stats->tests_intra};

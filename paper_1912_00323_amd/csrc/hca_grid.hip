@@ -2746,7 +2746,7 @@ __global__ __launch_bounds__(kBlock) void k_label_write(Plan P)
         n_noise += label < 0;
     }
     if (!P.want_stats) return;
-    // one atomic per block and counter
+    // one atomic per block and counter, on one of kWorkRegions lines
     n_core = wave_sum(n_core);
     n_noise = wave_sum(n_noise);
     if (lane_id() == 0) {
@@ -2757,8 +2757,9 @@ __global__ __launch_bounds__(kBlock) void k_label_write(Plan P)
     if (threadIdx.x == 0) {
         uint32_t c = 0, z = 0;
         for (int i = 0; i < kWavesPerBlock; i++) { c += s_cnt[0][i]; z += s_cnt[1][i]; }
-        if (c) atomicAdd(&P.ctr->n_core, c);
-        if (z) atomicAdd(&P.ctr->n_noise, z);
+        const uint32_t r = (blockIdx.x % kWorkRegions) * kCounterStride;
+        if (c) atomicAdd(&P.ctr->tally[0][r], c);
+        if (z) atomicAdd(&P.ctr->tally[1][r], z);
     }
 }
 

@@ -75,8 +75,7 @@ struct Counters {
     uint32_t bbox_done;         // blocks of the bounding-box kernel finished
     uint32_t sort_tickets[8];   // tile tickets, one per radix pass
     uint32_t scan_tickets[4];   // tile tickets of the device-wide scans
-    uint32_t n_core;
-    uint32_t n_noise;
+    uint32_t pad_tally[2];      // (core and noise counts: see tally)
     uint32_t n_clusters;
     uint32_t n_tiles;           // intra-group point tiles
     uint32_t tile_ticket;
@@ -97,6 +96,10 @@ struct Counters {
     unsigned long long tests[4][kWorkRegions * 8];
     // work queues of the dynamically balanced kernels: [kernel][64 queues]
     uint32_t dyn[5][kWorkRegions * kCounterStride];
+    // core points and noise points (counted only on request), spread over
+    // kWorkRegions lines so that thousands of blocks do not all add to one
+    // address
+    uint32_t tally[2][kWorkRegions * kCounterStride];
 };
 
 enum { kTestsCore = 0, kTestsMerge = 1, kTestsBorder = 2, kTestsIntra = 3 };
