@@ -224,24 +224,26 @@ hca_status hca_cluster_sets(hca_ctx *ctx, const int32_t *const *points, int32_t 
 /* Batch handles: the batched form for batches of one fixed shape (the rows,
  * d, eps and minPts of every data set), as a serving loop or a pipeline
  * repeats them.  hca_batch_create checks the shape (as hca_cluster_batch;
- * nseg >= 1), uploads the offset tables and makes one stream per dimension.
+ * nseg >= 1), uploads the offset tables and makes the handle's stream.
  * tune: 0 keeps the default knobs; 1 takes each group's knobs (of the data
  * sets of one dimension) from the autotuner's cache when it knows the group
  * and tunes it on the first run otherwise; 2 always tunes on the first run.
  * The knobs are the representative mode (on/off), the core-marking mode (a
  * lane per point or a wave per cube), the enumeration mode (prefix-range
  * list scans or lookups), cube-mode neighbour lists (built once, or the
- * stencil walked in every phase), the persistent blocks of the neighbour
- * phases, the hash load factor, the radix digit width and the radix tile
- * size; every choice gives the same labels.  The cache is a JSON file (HCA_TUNE_CACHE,
- * else $HOME/.cache/hca_tune.json) keyed by dimension, rows, cubes per axis
- * and data sets, in powers of two.
+ * stencil walked in every phase), cube-mode merging in one launch or two
+ * (the nearest neighbours first, the forest flattened between), the
+ * persistent blocks of the neighbour phases, the hash load factor, the radix
+ * digit width and the radix tile size; every choice gives the same labels.
+ * The cache is a JSON file (HCA_TUNE_CACHE, else $HOME/.cache/hca_tune.json)
+ * keyed by dimension, rows, cubes per axis and data sets, in powers of two.
  * hca_batch_run clusters one batch of that shape: points[i] (DEVICE,
  * row-major int32[rows[i]][dims[i]], 4-byte aligned, never written) into
  * labels[i] (DEVICE int32[rows[i]]), HOST arrays of nseg pointers, on the
  * context's stream, blocking.  The first run plans on the host from the data
  * sets' bounding boxes, tunes, runs and captures the whole batch in one HIP
- * graph (every dimension on its own stream, in parallel); every later run is
+ * graph (the dimensions one after the other, or side by side on streams of
+ * their own when tuning finds that graph faster); every later run is
  * one graph launch with no host round trip before the final sync: the device
  * takes the boxes, writes the origins and checks that the data still fit the
  * captured key layout, and when they do not the run is planned and captured
@@ -257,7 +259,7 @@ typedef struct {
     int64_t graph_replays;
     int64_t plans;
     int32_t groups;
-    int32_t reserved;
+    int32_t side_by_side;     /* 1: the graph runs the groups side by side, 0: one after the other */
 } hca_batch_info;
 typedef struct {
     int32_t d;
@@ -275,6 +277,8 @@ typedef struct {
     int32_t sort_items;
     int32_t tuned;            /* 1 tuned on this handle's first run, 2 from the cache, 0 default */
     int32_t lists;            /* 1 when the plan builds neighbour lists (tuned off: the stencil is walked) */
+    int32_t merge_split;      /* nearest neighbours merged by a first launch (0: one merge launch) */
+    int32_t reserved;
     double tuned_ms;
     double default_ms;
 } hca_batch_group;

@@ -245,6 +245,20 @@ uint32_t sort_tile(uint32_t n, bool wide_keys)
     return n >= (8u << 20) ? 8192u : 0u;
 }
 
+// Cube-mode merging in two launches with a flattening between them: the two
+// nearest forward neighbours of every core cube first.  Large clusters then
+// hook into flat trees instead of building long chains (a 4-D set of 124k
+// points: merge 0.9 -> 0.18 ms).  On for three and four axes, and for one or
+// two from 2M points on, where clusters grow large; the autotuner or
+// HCA_MERGE_SPLIT=k (k neighbours first, 0: one launch) override.
+uint32_t merge_split(uint32_t n, uint32_t d, const Tune *t = nullptr)
+{
+    if (t && t->merge_split >= 0) return (uint32_t)std::min(64, t->merge_split);
+    const char *e = std::getenv("HCA_MERGE_SPLIT");
+    if (e) return (uint32_t)std::max(0, std::min(64, std::atoi(e)));
+    return d >= 3 || n >= (2u << 20) ? 2u : 0u;
+}
+
 // HCA_ORDER=reverse|permute: the wave-dealt units of the neighbour phases
 // taken in reverse or permuted order (tests: the result must not depend on
 // the schedule)
@@ -501,6 +515,7 @@ void plan_sizes(Plan &P, uint32_t gbits, bool count_work, bool want_stats, Sizes
     P.sort_items = t && t->sort_items == 16 ? 16u : 0u;
     P.sort_threads = sort_threads(Z->wide_keys);
     P.sort_tile = sort_tile(n, Z->wide_keys);
+    P.merge_split = merge_split(n, (uint32_t)P.d, t);
     Z->hcap = 1024;
     while (Z->hcap < ((uint64_t)n << P.hash_load)) Z->hcap <<= 1;
     P.hash_mask = Z->hcap - 1;
@@ -1505,7 +1520,7 @@ hca_status run_batch(hca_ctx *ctx, const int32_t *points, int32_t nseg, const in
 // A handle fixes the shape of a batch (rows, d, eps and minPts of every data
 // set).  Its first run plans on the host from the data sets' boxes (one sync),
 // tunes each group's knobs (or takes them from the cache) and captures the
-// whole batch, every group on its own stream, in one HIP graph.  Later runs
+// whole batch in one HIP graph (the groups side by side or in turn).  Later runs
 // are one graph launch: the device stages the rows, takes the boxes, writes
 // every data set's origin and checks that the data still fit the captured
 // key layout; the host reads that flag after the final sync and, when the
@@ -1524,10 +1539,11 @@ struct hca_batch {
     size_t pin_size = 0;
     size_t d_flag = 0, h_flag = 0;
     hipStream_t origin = nullptr;       // the handle's own stream (graphs cannot capture the null stream)
-    hipEvent_t ready = nullptr;         // the caller's stream up to the run
-    std::vector<hipStream_t> streams;
+    std::vector<hipStream_t> streams;   // one per group, for graphs with the groups side by side
     hipEvent_t fork = nullptr;
     std::vector<hipEvent_t> join;
+    bool parallel = false;              // the captured graph runs the groups side by side (else in turn)
+    hipEvent_t ready = nullptr;         // the caller's stream up to the run
     hipEvent_t t0 = nullptr, t1 = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1657,6 +1673,12 @@ hca_status tune_group(hca_batch *b, BatchGroup &g)
     }
     {
         Tune c = g.tune;
+        c.merge_split = merge_split(g.n, (uint32_t)g.d) ? 0 : 2;    // the other of one or two merge launches
+        st = try_all({c});
+        if (st) return st;
+    }
+    {
+        Tune c = g.tune;
         c.hash_load = 2;
         st = try_all({c});
         if (st) return st;
@@ -1680,7 +1702,8 @@ hca_status tune_group(hca_batch *b, BatchGroup &g)
 }
 
 // The graph of one run: the data-set tables from the pinned staging (the
-// callers' pointers of that run), then per group on its own stream: boxes,
+// callers' pointers of that run), then per group (side by side on streams of
+// their own, or in turn): boxes,
 // origins and the layout check, the launch sequence, the labels scattered
 // back; the flag comes back to the pinned staging last.
 hca_status batch_capture(hca_batch *b)
@@ -1696,12 +1719,14 @@ hca_status batch_capture(hca_batch *b)
     ctx->prof = -1;
     HCA_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
     launch_init((uint32_t *)(db + b->d_flag), 1, nullptr, 0, s);
-    (void)hipEventRecord(b->fork, s);
+    // side by side: every group on its own stream, forked from the origin and
+    // joined back; in turn: every group on the origin stream
+    if (b->parallel) (void)hipEventRecord(b->fork, s);
     for (size_t gi = 0; gi < b->groups.size(); gi++) {
         BatchGroup &g = b->groups[gi];
-        hipStream_t gs = b->streams[gi];
+        hipStream_t gs = b->parallel ? b->streams[gi] : s;
         const size_t ns = g.par.size();
-        (void)hipStreamWaitEvent(gs, b->fork, 0);
+        if (b->parallel) (void)hipStreamWaitEvent(gs, b->fork, 0);
         (void)hipMemcpyAsync(db + g.d_seg, hb + g.h_seg, ns * sizeof(SegParam), hipMemcpyHostToDevice, gs);
         launch_init((uint32_t *)(db + g.d_box), ns * 2 * g.d, nullptr, 0, gs);
         launch_seg_stage(g.d, (const SegParam *)(db + g.d_seg), (uint32_t)ns, (int32_t *)(db + g.d_pts),
@@ -1712,8 +1737,10 @@ hca_status batch_capture(hca_batch *b)
                           (uint32_t *)(db + b->d_flag), gs);
         launch_sequence(ctx, g.P, g.Z, (char *)b->ws + g.ws_off, gs);
         launch_seg_scatter(g.P.seg, g.P.seg_of, g.P.labels, g.n, gs);
-        (void)hipEventRecord(b->join[gi], gs);
-        (void)hipStreamWaitEvent(s, b->join[gi], 0);
+        if (b->parallel) {
+            (void)hipEventRecord(b->join[gi], gs);
+            (void)hipStreamWaitEvent(s, b->join[gi], 0);
+        }
     }
     (void)hipMemcpyAsync(hb + b->h_flag, db + b->d_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
     hipGraph_t graph = nullptr;
@@ -1722,6 +1749,25 @@ hca_status batch_capture(hca_batch *b)
     HCA_HIP(e, "end capture");
     b->graph = graph;
     HCA_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "graph instantiate");
+    return HCA_OK;
+}
+
+// Best of kTuneReps replays of the captured graph (after one), in ms.
+hca_status time_graph(hca_batch *b, double *ms)
+{
+    hca_ctx *ctx = b->ctx;
+    hipStream_t s = b->origin;
+    double best = 1e30;
+    for (int r = 0; r <= kTuneReps; r++) {
+        HCA_HIP(hipEventRecord(b->t0, s), "event");
+        HCA_HIP(hipGraphLaunch(b->exec, s), "graph launch");
+        HCA_HIP(hipEventRecord(b->t1, s), "event");
+        HCA_HIP(hipEventSynchronize(b->t1), "event sync");
+        float f = 0.f;
+        HCA_HIP(hipEventElapsedTime(&f, b->t0, b->t1), "event time");
+        if (r > 0) best = std::min(best, (double)f);
+    }
+    *ms = best;
     return HCA_OK;
 }
 
@@ -1762,7 +1808,24 @@ hca_status batch_plan_run(hca_batch *b)
     HCA_HIP(hipGetLastError(), "kernel launch");
     HCA_HIP(hipStreamSynchronize(s), "batch sync");
     b->plans++;
-    return batch_capture(b);
+    if (b->tune_mode == 0 || b->groups.size() < 2) {
+        b->parallel = false;
+        return batch_capture(b);
+    }
+    // tuned: the groups side by side or in turn, whichever graph replays
+    // faster (side by side, the persistent grids of large groups can get in
+    // each other's way: 2x slower for some knob choices; in turn is the
+    // default)
+    double t[2] = {0, 0};
+    for (int mode = 0; mode < 2; mode++) {
+        b->parallel = mode == 0;
+        st = batch_capture(b);
+        if (st) return st;
+        st = time_graph(b, &t[mode]);
+        if (st) return st;
+    }
+    b->parallel = t[0] <= t[1];
+    return b->parallel ? batch_capture(b) : HCA_OK;
 }
 
 }  // namespace
@@ -2022,6 +2085,7 @@ hca_status hca_batch_stats(const hca_batch *b, hca_batch_info *info, hca_batch_g
     info->graph_replays = b->replays;
     info->plans = b->plans;
     info->groups = (int32_t)b->groups.size();
+    info->side_by_side = b->parallel ? 1 : 0;
     for (int32_t i = 0; groups && i < max_groups && i < info->groups; i++) {
         const BatchGroup &g = b->groups[i];
         hca_batch_group &o = groups[i];
@@ -2040,6 +2104,7 @@ hca_status hca_batch_stats(const hca_batch *b, hca_batch_info *info, hca_batch_g
         o.digit_cap = g.tune.digit_cap;
         o.sort_items = g.tune.sort_items;
         o.lists = g.P.list_w != 0;
+        o.merge_split = (int32_t)g.P.merge_split;
         o.tuned = g.tuned ? 1 : g.from_cache ? 2 : 0;
         o.tuned_ms = g.tuned_ms;
         o.default_ms = g.default_ms;
@@ -2053,7 +2118,7 @@ void hca_batch_destroy(hca_batch *b)
     (void)hipSetDevice(b->ctx->device);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
+    for (hipStream_t gs : b->streams) (void)hipStreamDestroy(gs);
     if (b->origin) (void)hipStreamDestroy(b->origin);
     if (b->ready) (void)hipEventDestroy(b->ready);
     for (hipEvent_t e : b->join) (void)hipEventDestroy(e);

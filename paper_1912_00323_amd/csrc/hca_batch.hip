@@ -45,36 +45,64 @@ __global__ __launch_bounds__(kBlock) void k_seg_gather(const SegParam *seg, uint
 
 // Bounding box of every data set: order-preserving unsigned images of the
 // coordinates, the maximum of ~image for the minimum and of the image for the
-// maximum, so that a zeroed array is the neutral start.  One atomic per wave
-// and axis when the wave's rows share a data set.
+// maximum, so that a zeroed array is the neutral start.  Each wave takes a
+// contiguous run of rows (the data sets are staged one after the other) and
+// keeps lane-wise maxima while its rows stay in one data set; it folds them
+// over the wave and adds them with one atomic per axis when the data set
+// changes or the run ends.  A 64-row step that straddles two data sets goes
+// lane by lane.
 __device__ __forceinline__ uint32_t ord32(int32_t v) { return (uint32_t)v ^ 0x80000000u; }
+
+template <int D>
+__device__ __forceinline__ void seg_box_flush(uint32_t *box, uint32_t s, const uint32_t *lo, const uint32_t *hi)
+{
+#pragma unroll
+    for (int k = 0; k < D; k++) {
+        const uint32_t wlo = wave_max(lo[k]), whi = wave_max(hi[k]);
+        if (lane_id() == 0) {
+            atomicMax(box + (uint64_t)s * 2 * D + k, wlo);
+            atomicMax(box + (uint64_t)s * 2 * D + D + k, whi);
+        }
+    }
+}
 
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_seg_bbox(const int32_t *pts, const uint32_t *seg_of, uint32_t n,
                                                      uint32_t *box)
 {
-    for (uint32_t base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
-        const uint32_t r = base + threadIdx.x;
-        const bool in = r < n;
+    const uint32_t l = lane_id();
+    const uint32_t waves = gridDim.x * (kBlock / kWave), wid = blockIdx.x * (kBlock / kWave) + wave_in_block();
+    const uint32_t per = ((n + waves - 1) / waves + kWave - 1) & ~(uint32_t)(kWave - 1);
+    const uint64_t r0 = (uint64_t)wid * per, r1 = min((uint64_t)n, r0 + per);
+    uint32_t cur = kNone, lo[D], hi[D];
+#pragma unroll
+    for (int k = 0; k < D; k++) lo[k] = hi[k] = 0u;
+    for (uint64_t base = r0; base < r1; base += kWave) {
+        const uint32_t r = (uint32_t)base + l;
+        const bool in = r < r1;
         const uint32_t s = in ? seg_of[r] : kNone;
         const uint32_t s0 = __shfl(s, 0);
         const bool same = __ballot(in && s != s0) == 0;
-        const Pt<D> p = load_pt<D>(pts, in ? r : 0);
+        const Pt<D> p = load_pt<D>(pts, in ? r : (uint32_t)r0);
+        if (!same || s0 != cur) {
+            if (cur != kNone) seg_box_flush<D>(box, cur, lo, hi);
+#pragma unroll
+            for (int k = 0; k < D; k++) lo[k] = hi[k] = 0u;
+            cur = same ? s0 : kNone;
+        }
 #pragma unroll
         for (int k = 0; k < D; k++) {
-            const uint32_t lo = in ? ~ord32(p.x[k]) : 0u, hi = in ? ord32(p.x[k]) : 0u;
+            const uint32_t a = in ? ~ord32(p.x[k]) : 0u, b = in ? ord32(p.x[k]) : 0u;
             if (same) {
-                const uint32_t wlo = wave_max(lo), whi = wave_max(hi);
-                if (lane_id() == 0 && s0 != kNone) {
-                    atomicMax(box + (uint64_t)s0 * 2 * D + k, wlo);
-                    atomicMax(box + (uint64_t)s0 * 2 * D + D + k, whi);
-                }
+                lo[k] = max(lo[k], a);
+                hi[k] = max(hi[k], b);
             } else if (in) {
-                atomicMax(box + (uint64_t)s * 2 * D + k, lo);
-                atomicMax(box + (uint64_t)s * 2 * D + D + k, hi);
+                atomicMax(box + (uint64_t)s * 2 * D + k, a);
+                atomicMax(box + (uint64_t)s * 2 * D + D + k, b);
             }
         }
     }
+    if (cur != kNone) seg_box_flush<D>(box, cur, lo, hi);
 }
 
 // A batch plan replayed on new data (a captured graph): every data set's

@@ -1652,13 +1652,18 @@ __global__ __launch_bounds__(kBlock) void k_merge_rep(Plan P)
     if (!lists && flat_units <= 0xffffffffull) {
         // stencil: one (cube, offset) pair per lane, so the few forward
         // offsets of small d fill the wave
-        HCA_FOR_UNITS(wu, (uint32_t)flat_units) {
+        // offsets of this launch (nearest first): all, the first
+        // 2 merge_split (as many forward), or the others
+        const uint32_t cut = min(1u + 2u * P.merge_split, P.n_off);
+        const uint32_t j0 = P.merge_phase == 2 ? cut : 0u, nj = (P.merge_phase == 1 ? cut : P.n_off) - j0;
+        const uint64_t units = ((uint64_t)nc * nj + kWave - 1) / kWave;
+        HCA_FOR_UNITS(wu, (uint32_t)units) {
             const uint64_t u = (uint64_t)wu * kWave + l;
             uint32_t A = kNone, B = kNone, dfw = 0, dbw = 0;
             int64_t eps2 = 0;
-            if (u < (uint64_t)nc * P.n_off) {
-                A = (uint32_t)(u / P.n_off);
-                const uint32_t j = (uint32_t)(u - (uint64_t)A * P.n_off);
+            if (u < (uint64_t)nc * nj) {
+                A = (uint32_t)(u / nj);
+                const uint32_t j = j0 + (uint32_t)(u - (uint64_t)A * nj);
                 // cubes are numbered in key order: B > A exactly when the
                 // first non-zero component of the offset is positive
                 const int8_t *o = P.off + (uint64_t)j * D;
@@ -1683,9 +1688,13 @@ __global__ __launch_bounds__(kBlock) void k_merge_rep(Plan P)
             const uint64_t gkey = P.group_key[A];
             const int64_t eps2 = cube_geo<D>(P, gkey).eps2;
             const NbrSrc src = nbr_source(P, A);
-            // cubes B > A: the forward list, or the whole stencil
-            const uint32_t slots = src.lists ? 1 + src.fcount : src.slots;
-            for (uint32_t oc = 1; oc < slots; oc += kWave) {
+            // cubes B > A: the forward list, or the whole stencil; of this
+            // launch: all slots, the first merge_split, or the others
+            const uint32_t all_slots = src.lists ? 1 + src.fcount : src.slots;
+            const uint32_t cut = min(1u + (src.lists ? 1u : 2u) * P.merge_split, all_slots);
+            const uint32_t first = P.merge_phase == 2 ? cut : 1u;
+            const uint32_t slots = P.merge_phase == 1 ? cut : all_slots;
+            for (uint32_t oc = first; oc < slots; oc += kWave) {
                 const uint32_t j = oc + l;
                 uint32_t B = kNone, dfw = 0, dbw = 0;
                 if (j < slots) {
@@ -1728,7 +1737,12 @@ __global__ __launch_bounds__(kBlock) void k_merge_cubes(Plan P)
     const uint64_t fm = __ballot(fw);
     if (fw) s_fwd[w][__popcll(fm & __lanemask_lt())] = l;
     __builtin_amdgcn_wave_barrier();
-    const uint32_t nf = (uint32_t)__popcll(fm);
+    // the forward offsets of this launch (nearest first): all, the first
+    // merge_split, or the others
+    const uint32_t nfw = (uint32_t)__popcll(fm), cut = min(P.merge_split, nfw);
+    const uint32_t fa = P.merge_phase == 2 ? cut : 0u;
+    const uint32_t nf = (P.merge_phase == 1 ? cut : nfw) - fa;
+    if (nf == 0) return;
     const uint32_t ns = ld_agent32(&P.ctr->n_small), ncc = ns + ld_agent32(&P.ctr->n_big);
     const uint64_t pairs = (uint64_t)ncc * nf;
     uint32_t lt = 0;
@@ -1746,7 +1760,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_cubes(Plan P)
         if (u < pairs) {
             const uint32_t ci = (uint32_t)(u / nf), f = (uint32_t)(u - (uint64_t)ci * nf);
             A = ci < ns ? P.core_cubes[ci] : P.big_cubes[ci - ns];
-            const uint32_t j = s_fwd[w][f];
+            const uint32_t j = s_fwd[w][fa + f];
             const uint64_t gkey = P.group_key[A];
             if (P.n_dir) ra = ld_agent(P.rep + (uint64_t)A * P.n_dir + P.dir_fwd[j]);
             eps2 = cube_geo<D>(P, gkey).eps2;
@@ -2891,15 +2905,25 @@ void launch_merge_intra(const Plan &P, int blocks, hipStream_t s)
 void launch_merge(const Plan &P, int blocks, hipStream_t s)
 {
     if (P.m == 1) {
-        if (P.core_list) {
-            switch (P.d * 2 + (P.wide ? 1 : 0)) {
-            case 2: hipLaunchKernelGGL((k_merge_cubes<1, false>), dim3(blocks), dim3(kBlock), 0, s, P); break;
-            case 3: hipLaunchKernelGGL((k_merge_cubes<1, true>), dim3(blocks), dim3(kBlock), 0, s, P); break;
-            case 4: hipLaunchKernelGGL((k_merge_cubes<2, false>), dim3(blocks), dim3(kBlock), 0, s, P); break;
-            case 5: hipLaunchKernelGGL((k_merge_cubes<2, true>), dim3(blocks), dim3(kBlock), 0, s, P); break;
+        // with merge_split: the nearest forward neighbours first, then a
+        // flattening of the forest, then the others, whose finds then start
+        // from flat trees (hooking in key order alone builds long chains
+        // through large clusters)
+        const int launches = P.merge_split ? 2 : 1;
+        for (int r = 0; r < launches; r++) {
+            Plan Q = P;
+            Q.merge_phase = P.merge_split ? (uint32_t)r + 1u : 0u;
+            if (r) hipLaunchKernelGGL(k_flatten, dim3(1024), dim3(kBlock), 0, s, Q);
+            if (P.core_list) {
+                switch (P.d * 2 + (P.wide ? 1 : 0)) {
+                case 2: hipLaunchKernelGGL((k_merge_cubes<1, false>), dim3(blocks), dim3(kBlock), 0, s, Q); break;
+                case 3: hipLaunchKernelGGL((k_merge_cubes<1, true>), dim3(blocks), dim3(kBlock), 0, s, Q); break;
+                case 4: hipLaunchKernelGGL((k_merge_cubes<2, false>), dim3(blocks), dim3(kBlock), 0, s, Q); break;
+                case 5: hipLaunchKernelGGL((k_merge_cubes<2, true>), dim3(blocks), dim3(kBlock), 0, s, Q); break;
+                }
+            } else {
+                HCA_DISPATCH_DW(k_merge_rep, Q, blocks, s);
             }
-        } else {
-            HCA_DISPATCH_DW(k_merge_rep, P, blocks, s);
         }
         if (!P.rep_only) HCA_DISPATCH_DW(k_merge_exact, P, blocks, s);
     } else {

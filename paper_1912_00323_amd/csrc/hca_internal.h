@@ -17,6 +17,7 @@ struct Tune {
     int lanes = -1;         // core marking with a lane per point (d <= 2): 1, 0, -1
     int prefix = -1;        // neighbour lists from prefix-range scans (d >= 3): 1, 0, -1
     int lists = -1;         // cube-mode neighbour lists (d >= 3): 0 off, -1 as the plan and environment say
+    int merge_split = -1;   // cube-mode merge: nearest forward neighbours of a first launch (0: one launch; -1 the rule)
     int wave_blocks = 0;    // persistent blocks of the neighbour phases (0: the default)
     int hash_load = 1;      // hash slots in use >= groups << hash_load
     int digit_cap = 0;      // widest radix digit in bits (0: the key type's)

@@ -191,6 +191,8 @@ struct Plan {
     uint32_t hash_load;         // slots in use >= groups << hash_load (at least 1024)
     uint32_t sort_items;        // keys per thread of a radix tile (0: the key type's default)
     uint32_t sort_threads;      // threads that rank a radix tile (256, 512 or 1024; the tile size is the key type's)
+    uint32_t merge_split;       // cube-mode merge: forward neighbours of its first launch (0: one launch)
+    uint32_t merge_phase;       // of this launch: 0 all, 1 the first merge_split, 2 the others
     uint32_t sort_tile;         // keys per radix tile of 32-bit keys: 0 (4096) or 8192
 
     // buffers

@@ -71,6 +71,7 @@ void load_locked()
         if (field(obj, "lanes", &v)) e.t.lanes = (int)v;
         if (field(obj, "prefix", &v)) e.t.prefix = (int)v;
         if (field(obj, "lists", &v)) e.t.lists = (int)v;
+        if (field(obj, "merge_split", &v)) e.t.merge_split = (int)v;
         if (field(obj, "wave_blocks", &v)) e.t.wave_blocks = (int)v;
         if (field(obj, "hash_load", &v)) e.t.hash_load = (int)v;
         if (field(obj, "digit_cap", &v)) e.t.digit_cap = (int)v;
@@ -114,9 +115,10 @@ std::string tune_text(const Tune &t)
 {
     char buf[256];
     std::snprintf(buf, sizeof buf,
-                  "{\"reps\": %d, \"lanes\": %d, \"prefix\": %d, \"lists\": %d, \"wave_blocks\": %d, "
-                  "\"hash_load\": %d, \"digit_cap\": %d, \"sort_items\": %d}",
-                  t.reps, t.lanes, t.prefix, t.lists, t.wave_blocks, t.hash_load, t.digit_cap, t.sort_items);
+                  "{\"reps\": %d, \"lanes\": %d, \"prefix\": %d, \"lists\": %d, \"merge_split\": %d, "
+                  "\"wave_blocks\": %d, \"hash_load\": %d, \"digit_cap\": %d, \"sort_items\": %d}",
+                  t.reps, t.lanes, t.prefix, t.lists, t.merge_split, t.wave_blocks, t.hash_load, t.digit_cap,
+                  t.sort_items);
     return buf;
 }
 

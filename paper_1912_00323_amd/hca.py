@@ -33,7 +33,7 @@ class Geometry(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 class Stats(ctypes.Structure):
@@ -49,7 +49,7 @@ class Stats(ctypes.Structure):
                 ("core_rest", ctypes.c_int64)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 _lib = None
@@ -124,7 +124,7 @@ def load_library(path: str | Path | None = None) -> ctypes.CDLL:
 
 class BatchInfo(ctypes.Structure):
     _fields_ = [("runs", ctypes.c_int64), ("graph_replays", ctypes.c_int64), ("plans", ctypes.c_int64),
-                ("groups", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("groups", ctypes.c_int32), ("side_by_side", ctypes.c_int32)]
 
 
 class BatchGroupInfo(ctypes.Structure):
@@ -133,10 +133,11 @@ class BatchGroupInfo(ctypes.Structure):
                 ("reps", ctypes.c_int32), ("lanes", ctypes.c_int32), ("prefix", ctypes.c_int32),
                 ("wave_blocks", ctypes.c_int32), ("hash_load", ctypes.c_int32), ("digit_cap", ctypes.c_int32),
                 ("sort_items", ctypes.c_int32), ("tuned", ctypes.c_int32), ("lists", ctypes.c_int32),
+                ("merge_split", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("tuned_ms", ctypes.c_double), ("default_ms", ctypes.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 class Batch:
@@ -184,6 +185,7 @@ class Batch:
         groups = (BatchGroupInfo * 8)()
         self._ctx._check(self._lib.hca_batch_stats(self._h, ctypes.byref(info), groups, 8))
         return {"runs": info.runs, "graph_replays": info.graph_replays, "plans": info.plans,
+                "side_by_side": bool(info.side_by_side),
                 "groups": [groups[i].as_dict() for i in range(info.groups)]}
 
     def close(self):

@@ -88,6 +88,20 @@ def test_search_modes_agree(ctx, mode, reps, monkeypatch):
         check(ctx, pts, 0.05 * 2 ** 12, 5, f"mode={mode} reps={reps} d={d}")
 
 
+@pytest.mark.parametrize("split", ["0", "1", "2", "5"])
+def test_merge_split(ctx, split, monkeypatch):
+    """Cube-mode merging in one launch, or the nearest 1, 2 or 5 forward
+    neighbours first and the rest after a flattening of the forest: the
+    oracle's labels in one to four axes (lane path, stencil and lists)."""
+    monkeypatch.setenv("HCA_MERGE_SPLIT", split)
+    monkeypatch.setenv("HCA_SEARCH", "cube")
+    for d in (1, 2, 3, 4):
+        rng = np.random.default_rng(23 * d)
+        pts = quantise(make_blobs(rng, 8000, d, 4, 0.03, 0.1), 12)
+        for eps, mp in ((0.02 * 2 ** 12, 3), (0.06 * 2 ** 12, 8)):
+            check(ctx, pts, eps, mp, f"merge split={split} d={d}")
+
+
 @pytest.mark.parametrize("lists", ["1", "0"])
 def test_cube_lists_on_off(ctx, lists, monkeypatch):
     """Cube mode in three and four axes with neighbour lists built once, or
