@@ -436,7 +436,7 @@ def bench_batch(args) -> int:
         "data": "synthetic",
         "config": {"workload": "batch256_mixed", "jobs": len(jobs), "points": total,
                    "d": sorted(set(dims)), "parallelism": "single-gpu", "form": "batch handle, one graph launch"},
-        "graph": {"replays": st["graph_replays"], "plans": st["plans"], "side_by_side": st["side_by_side"], "first_run_ms": round(t_first * 1e3, 2),
+        "graph": {"replays": st["graph_replays"], "plans": st["plans"], "first_run_ms": round(t_first * 1e3, 2),
                   "groups": st["groups"]},
         "default_knobs": {"ms_per_batch": round(dt_default * 1e3, 3), "labels_identical": same_default},
         "tuned_vs_default": round(dt_default / dt, 3),

@@ -242,8 +242,7 @@ hca_status hca_cluster_sets(hca_ctx *ctx, const int32_t *const *points, int32_t 
  * labels[i] (DEVICE int32[rows[i]]), HOST arrays of nseg pointers, on the
  * context's stream, blocking.  The first run plans on the host from the data
  * sets' bounding boxes, tunes, runs and captures the whole batch in one HIP
- * graph (the dimensions one after the other, or side by side on streams of
- * their own when tuning finds that graph faster); every later run is
+ * graph (the dimensions one after the other); every later run is
  * one graph launch with no host round trip before the final sync: the device
  * takes the boxes, writes the origins and checks that the data still fit the
  * captured key layout, and when they do not the run is planned and captured
@@ -259,7 +258,7 @@ typedef struct {
     int64_t graph_replays;
     int64_t plans;
     int32_t groups;
-    int32_t side_by_side;     /* 1: the graph runs the groups side by side, 0: one after the other */
+    int32_t reserved;
 } hca_batch_info;
 typedef struct {
     int32_t d;

@@ -201,14 +201,22 @@ uint32_t env_core_budget()
     return (uint32_t)std::min<long>(std::max<long>(1, std::atol(e)), 1l << 30);
 }
 
-// Lane walk for core marking: cubes as search groups, no neighbour lists,
-// one or two axes, offsets within kColR.
+// Lane walk for core marking, cubes as search groups: over column ranges for
+// one or two axes with offsets within kColR (no neighbour lists), over the
+// cube neighbour lists for three and four axes.  A lane tests up to
+// core_budget candidates (64 over column ranges; 512 over lists, where a
+// sparse point's neighbourhood spans a few hundred cubes) before a wider
+// walk takes its point over.
 void plan_core_lanes(Plan &P, int32_t radius, const Tune *t = nullptr)
 {
     P.radius = (uint32_t)std::max(0, radius);
-    P.core_budget = env_core_budget();
     const bool want = t && t->lanes >= 0 ? t->lanes != 0 : env_core_lanes();
-    P.core_lanes = P.m == 1 && P.list_w == 0 && !P.hd && P.d <= 2 && radius <= kColR && want ? 1u : 0u;
+    P.core_lanes = 0;
+    if (P.m == 1 && !P.hd && want) {
+        if (P.list_w == 0 && P.d <= 2 && radius <= kColR) P.core_lanes = 1;
+        else if (P.list_w != 0 && P.d >= 3 && P.d <= 4) P.core_lanes = 2;
+    }
+    P.core_budget = std::getenv("HCA_CORE_BUDGET") || P.core_lanes != 2 ? env_core_budget() : 512u;
 }
 
 // Radix passes for a key of key_bits bits, digits no wider than the key
@@ -629,8 +637,8 @@ void carve_ws(Carver &cv, Plan &P, SortBuffers &B, const Sizes &Z, uint32_t **ze
     P.wrank = cv.take<uint32_t>(((size_t)n + 31) / 32);
     P.label_of = cv.take<int32_t>(n);
     // the lane path's core-cube lists, in arrays free until borders and labels
-    P.core_cubes = P.core_list ? P.owner : nullptr;
-    P.big_cubes = P.core_list ? (uint32_t *)P.label_of : nullptr;
+    P.core_cubes = P.core_list && P.core_lanes == 1 ? P.owner : nullptr;
+    P.big_cubes = P.core_list && P.core_lanes == 1 ? (uint32_t *)P.label_of : nullptr;
     // zeroed before every call: counters, histograms, look-back words
     const size_t zstart = cv.off;
     P.ctr = cv.take<Counters>(1);
@@ -1520,7 +1528,7 @@ hca_status run_batch(hca_ctx *ctx, const int32_t *points, int32_t nseg, const in
 // A handle fixes the shape of a batch (rows, d, eps and minPts of every data
 // set).  Its first run plans on the host from the data sets' boxes (one sync),
 // tunes each group's knobs (or takes them from the cache) and captures the
-// whole batch in one HIP graph (the groups side by side or in turn).  Later runs
+// whole batch in one HIP graph, group after group.  Later runs
 // are one graph launch: the device stages the rows, takes the boxes, writes
 // every data set's origin and checks that the data still fit the captured
 // key layout; the host reads that flag after the final sync and, when the
@@ -1539,10 +1547,6 @@ struct hca_batch {
     size_t pin_size = 0;
     size_t d_flag = 0, h_flag = 0;
     hipStream_t origin = nullptr;       // the handle's own stream (graphs cannot capture the null stream)
-    std::vector<hipStream_t> streams;   // one per group, for graphs with the groups side by side
-    hipEvent_t fork = nullptr;
-    std::vector<hipEvent_t> join;
-    bool parallel = false;              // the captured graph runs the groups side by side (else in turn)
     hipEvent_t ready = nullptr;         // the caller's stream up to the run
     hipEvent_t t0 = nullptr, t1 = nullptr;
     hipGraph_t graph = nullptr;
@@ -1648,9 +1652,9 @@ hca_status tune_group(hca_batch *b, BatchGroup &g)
         st = try_all({c});
         if (st) return st;
     }
-    if (g.d <= 2) {
+    {
         Tune c = g.tune;
-        c.lanes = 1 - c.lanes;
+        c.lanes = 1 - c.lanes;                // a lane per point or a wave per cube
         st = try_all({c});
         if (st) return st;
     }
@@ -1702,8 +1706,7 @@ hca_status tune_group(hca_batch *b, BatchGroup &g)
 }
 
 // The graph of one run: the data-set tables from the pinned staging (the
-// callers' pointers of that run), then per group (side by side on streams of
-// their own, or in turn): boxes,
+// callers' pointers of that run), then group after group: boxes,
 // origins and the layout check, the launch sequence, the labels scattered
 // back; the flag comes back to the pinned staging last.
 hca_status batch_capture(hca_batch *b)
@@ -1719,14 +1722,13 @@ hca_status batch_capture(hca_batch *b)
     ctx->prof = -1;
     HCA_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
     launch_init((uint32_t *)(db + b->d_flag), 1, nullptr, 0, s);
-    // side by side: every group on its own stream, forked from the origin and
-    // joined back; in turn: every group on the origin stream
-    if (b->parallel) (void)hipEventRecord(b->fork, s);
+    // the groups one after the other: each sequence fills the chip, and
+    // sequences side by side on streams of their own replayed erratically
+    // slower (up to 2x: their persistent grids competing for the same CUs)
     for (size_t gi = 0; gi < b->groups.size(); gi++) {
         BatchGroup &g = b->groups[gi];
-        hipStream_t gs = b->parallel ? b->streams[gi] : s;
+        hipStream_t gs = s;
         const size_t ns = g.par.size();
-        if (b->parallel) (void)hipStreamWaitEvent(gs, b->fork, 0);
         (void)hipMemcpyAsync(db + g.d_seg, hb + g.h_seg, ns * sizeof(SegParam), hipMemcpyHostToDevice, gs);
         launch_init((uint32_t *)(db + g.d_box), ns * 2 * g.d, nullptr, 0, gs);
         launch_seg_stage(g.d, (const SegParam *)(db + g.d_seg), (uint32_t)ns, (int32_t *)(db + g.d_pts),
@@ -1737,10 +1739,6 @@ hca_status batch_capture(hca_batch *b)
                           (uint32_t *)(db + b->d_flag), gs);
         launch_sequence(ctx, g.P, g.Z, (char *)b->ws + g.ws_off, gs);
         launch_seg_scatter(g.P.seg, g.P.seg_of, g.P.labels, g.n, gs);
-        if (b->parallel) {
-            (void)hipEventRecord(b->join[gi], gs);
-            (void)hipStreamWaitEvent(s, b->join[gi], 0);
-        }
     }
     (void)hipMemcpyAsync(hb + b->h_flag, db + b->d_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
     hipGraph_t graph = nullptr;
@@ -1749,25 +1747,6 @@ hca_status batch_capture(hca_batch *b)
     HCA_HIP(e, "end capture");
     b->graph = graph;
     HCA_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "graph instantiate");
-    return HCA_OK;
-}
-
-// Best of kTuneReps replays of the captured graph (after one), in ms.
-hca_status time_graph(hca_batch *b, double *ms)
-{
-    hca_ctx *ctx = b->ctx;
-    hipStream_t s = b->origin;
-    double best = 1e30;
-    for (int r = 0; r <= kTuneReps; r++) {
-        HCA_HIP(hipEventRecord(b->t0, s), "event");
-        HCA_HIP(hipGraphLaunch(b->exec, s), "graph launch");
-        HCA_HIP(hipEventRecord(b->t1, s), "event");
-        HCA_HIP(hipEventSynchronize(b->t1), "event sync");
-        float f = 0.f;
-        HCA_HIP(hipEventElapsedTime(&f, b->t0, b->t1), "event time");
-        if (r > 0) best = std::min(best, (double)f);
-    }
-    *ms = best;
     return HCA_OK;
 }
 
@@ -1808,24 +1787,7 @@ hca_status batch_plan_run(hca_batch *b)
     HCA_HIP(hipGetLastError(), "kernel launch");
     HCA_HIP(hipStreamSynchronize(s), "batch sync");
     b->plans++;
-    if (b->tune_mode == 0 || b->groups.size() < 2) {
-        b->parallel = false;
-        return batch_capture(b);
-    }
-    // tuned: the groups side by side or in turn, whichever graph replays
-    // faster (side by side, the persistent grids of large groups can get in
-    // each other's way: 2x slower for some knob choices; in turn is the
-    // default)
-    double t[2] = {0, 0};
-    for (int mode = 0; mode < 2; mode++) {
-        b->parallel = mode == 0;
-        st = batch_capture(b);
-        if (st) return st;
-        st = time_graph(b, &t[mode]);
-        if (st) return st;
-    }
-    b->parallel = t[0] <= t[1];
-    return b->parallel ? batch_capture(b) : HCA_OK;
+    return batch_capture(b);
 }
 
 }  // namespace
@@ -2017,18 +1979,7 @@ hca_status hca_batch_create(hca_ctx *ctx, int32_t nseg, const int64_t *rows, con
     st = batch_tables(ctx, b->groups, (char *)b->dev, (char *)b->pin, b->origin);
     if (st) return bail(st);
     if (hipStreamSynchronize(b->origin) != hipSuccess) return bail(fail(ctx, HCA_E_DEVICE, "table upload"));
-    for (size_t gi = 0; gi < b->groups.size(); gi++) {
-        hipStream_t gs = nullptr;
-        hipEvent_t e = nullptr;
-        if (hipStreamCreateWithFlags(&gs, hipStreamNonBlocking) != hipSuccess)
-            return bail(fail(ctx, HCA_E_DEVICE, "stream"));
-        b->streams.push_back(gs);
-        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
-            return bail(fail(ctx, HCA_E_DEVICE, "event"));
-        b->join.push_back(e);
-    }
-    if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess || hipEventCreate(&b->t0) != hipSuccess ||
-        hipEventCreate(&b->t1) != hipSuccess)
+    if (hipEventCreate(&b->t0) != hipSuccess || hipEventCreate(&b->t1) != hipSuccess)
         return bail(fail(ctx, HCA_E_DEVICE, "event"));
     *out = b;
     return HCA_OK;
@@ -2085,7 +2036,6 @@ hca_status hca_batch_stats(const hca_batch *b, hca_batch_info *info, hca_batch_g
     info->graph_replays = b->replays;
     info->plans = b->plans;
     info->groups = (int32_t)b->groups.size();
-    info->side_by_side = b->parallel ? 1 : 0;
     for (int32_t i = 0; groups && i < max_groups && i < info->groups; i++) {
         const BatchGroup &g = b->groups[i];
         hca_batch_group &o = groups[i];
@@ -2118,11 +2068,8 @@ void hca_batch_destroy(hca_batch *b)
     (void)hipSetDevice(b->ctx->device);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    for (hipStream_t gs : b->streams) (void)hipStreamDestroy(gs);
     if (b->origin) (void)hipStreamDestroy(b->origin);
     if (b->ready) (void)hipEventDestroy(b->ready);
-    for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
-    if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->t0) (void)hipEventDestroy(b->t0);
     if (b->t1) (void)hipEventDestroy(b->t1);
     if (b->dev) (void)hipFree(b->dev);

@@ -1283,6 +1283,146 @@ __global__ __launch_bounds__(kBlock) void k_core_deferred(Plan P)
     flush_tests(P, kTestsCore, lt);
 }
 
+// ---------------------------------------------------------------------------
+// Core marking in cube mode for three and four axes with neighbour lists,
+// one lane per point of a sparse cube.  Such cubes hold a point or two, and
+// a wave per cube would test 64 candidates against one point at a time.  A
+// lane counts its own cube whole (every pair in a cube is within eps), then
+// walks the cube's list kSlotBatch entries at a time: their point ranges are
+// looked up together, and their candidates are tested kLaneBatch at a time.
+// A point still short of minPts after P.core_budget candidates (or any
+// point, when a list overflowed) goes to a wave walk (k_core_list_deferred).
+// ---------------------------------------------------------------------------
+constexpr int kSlotBatch = 8;
+
+struct SlotRanges {
+    uint32_t pre[kSlotBatch + 1];                 // candidates before range r
+    uint32_t rb[kSlotBatch];                      // first sorted position of range r
+};
+
+__device__ __forceinline__ uint32_t slot_pos(const SlotRanges &sr, uint32_t v)
+{
+    uint32_t ps = 0;
+#pragma unroll
+    for (int r = 0; r < kSlotBatch; r++)
+        if (v >= sr.pre[r]) ps = sr.rb[r] + (v - sr.pre[r]);
+    return ps;
+}
+
+template <int D, bool WIDE>
+__global__ __launch_bounds__(kBlock) void k_core_list_lanes(Plan P)
+{
+    const uint32_t ns = ld_agent32(&P.ctr->n_sparse);
+    const bool lists = P.nbr_cap && P.ctr->nbr_overflow == 0;
+    const uint32_t stride = gridDim.x * kBlock;
+    const uint32_t l = lane_id();
+    uint32_t lt = 0;
+    // wave-uniform loop, so that the points a wave defers keep their order
+    for (uint32_t base = (blockIdx.x * kBlock + threadIdx.x) & ~(uint32_t)(kWave - 1); base < ns;
+         base += stride) {
+        const uint32_t i = base + l;
+        bool defer = false;
+        uint32_t q = kNone;
+        if (i < ns) {
+            q = P.core_list[i];
+            const uint32_t c = P.cell_of[q];
+            const Geo<D> geo = cube_geo<D>(P, P.group_key[c]);
+            const Pt<D> p = load_pt<D>(P.spts, q);
+            const uint32_t a0 = P.group_start[c], b0 = P.group_start[c + 1];
+            uint32_t cnt = b0 - a0;
+            if (P.rec)
+                for (uint32_t t = 0; t < cnt && t < (uint32_t)kRec; t++) P.rec[(uint64_t)q * kRec + t] = a0 + t;
+            const uint32_t minpts = geo.min_pts, budget = P.core_budget;
+            defer = !lists;
+            if (lists) {
+                const uint32_t fs = P.nbr_start[c], fc = P.nbr_count[c], bs = P.nbr_bstart[c];
+                const uint32_t nslots = fc + P.nbr_bcount[c];
+                uint32_t tested = 0, j = 0;
+                for (; j < nslots && cnt < minpts && tested < budget; j += kSlotBatch) {
+                    SlotRanges sr;
+                    uint32_t g[kSlotBatch];
+#pragma unroll
+                    for (int b = 0; b < kSlotBatch; b++) {
+                        const uint32_t k = j + (uint32_t)b;
+                        g[b] = k < nslots ? (k < fc ? P.nbr[fs + k] : P.nbr_back[bs + (k - fc)]) : kNone;
+                    }
+                    sr.pre[0] = 0;
+#pragma unroll
+                    for (int b = 0; b < kSlotBatch; b++) {
+                        const uint32_t lo = g[b] != kNone ? P.group_start[g[b]] : 0u;
+                        const uint32_t hi = g[b] != kNone ? P.group_start[g[b] + 1] : 0u;
+                        sr.rb[b] = lo;
+                        sr.pre[b + 1] = sr.pre[b] + (hi - lo);
+                    }
+                    const uint32_t total = sr.pre[kSlotBatch];
+                    for (uint32_t v = 0; v < total && cnt < minpts && tested < budget; v += kLaneBatch) {
+                        uint32_t pos[kLaneBatch];
+                        Pt<D> o[kLaneBatch];
+#pragma unroll
+                        for (int b = 0; b < kLaneBatch; b++) {
+                            pos[b] = slot_pos(sr, min(v + (uint32_t)b, total - 1u));
+                            o[b] = load_pt<D>(P.spts, pos[b]);
+                        }
+#pragma unroll
+                        for (int b = 0; b < kLaneBatch; b++) {
+                            if (v + (uint32_t)b >= total) break;
+                            lt++;
+                            tested++;
+                            if (within<D, WIDE>(p, o[b], geo.eps2)) {
+                                if (P.rec && cnt < (uint32_t)kRec) P.rec[(uint64_t)q * kRec + cnt] = pos[b];
+                                cnt++;
+                            }
+                        }
+                    }
+                }
+                // budget spent with candidates left: a wave decides this point
+                defer = cnt < minpts && tested >= budget;
+            }
+            if (!defer) core_result(P, q, c, cnt, minpts);
+        }
+        const uint64_t m = __ballot(defer);
+        if (m) {
+            const uint32_t lead = (uint32_t)__ffsll((unsigned long long)m) - 1u;
+            uint32_t at = 0;
+            if (l == lead) at = atomicAdd(&P.ctr->n_defer, (uint32_t)__popcll(m));
+            at = __shfl(at, lead);
+            if (defer) P.core_defer[at + __popcll(m & __lanemask_lt())] = q;
+        }
+    }
+    flush_tests(P, kTestsCore, lt);
+}
+
+// The deferred points of the list lane walk, one wave each: the count walk
+// of a one-point chunk over the cube's list (or the stencil), from zero.
+template <int D, bool WIDE>
+__global__ __launch_bounds__(kBlock) void k_core_list_deferred(Plan P)
+{
+    __shared__ uint32_t s_beg[kWavesPerBlock][kWave], s_pre[kWavesPerBlock][kWave];
+    const uint32_t w = wave_in_block();
+    const uint32_t nd = ld_agent32(&P.ctr->n_defer);
+    const uint32_t all = (1u << kPch) - 1u;
+    uint32_t lt = 0;
+    const WaveRange hca_wr_ = wave_range(P.order);
+    HCA_FOR_UNITS(i, nd) {
+        const uint32_t q = P.core_defer[i];
+        const uint32_t c = P.cell_of[q];
+        const uint64_t gkey = P.group_key[c];
+        const Geo<D> geo = cube_geo<D>(P, gkey);
+        Pt<D> pp[kPch];
+        uint32_t qpos[kPch], cnt[kPch];
+        const Pt<D> p = load_pt<D>(P.spts, q);
+#pragma unroll
+        for (int k = 0; k < kPch; k++) {
+            pp[k] = p;
+            qpos[k] = q;
+            cnt[k] = 0;
+        }
+        count_walk<D, WIDE>(P, c, gkey, pp, all & ~1u, cnt, s_beg[w], s_pre[w], lt, geo, kNone, qpos);
+        if (lane_id() == 0) core_result(P, q, c, cnt[0], geo.min_pts);
+    }
+    flush_tests(P, kTestsCore, lt);
+}
+
 // The core cubes of the lane path, for representatives and merging: cubes of
 // at most kRepLanePts points (a lane each) and the larger ones (a block each),
 // one atomic per list and block.
@@ -2847,6 +2987,21 @@ void launch_lists_back(const Plan &P, int blocks, hipStream_t s)
 // through core_list); otherwise one wave per cube or per chunk of points.
 void launch_core(const Plan &P, int blocks, hipStream_t s)
 {
+    if (P.m == 1 && P.core_list && P.core_lanes == 2) {
+        const int fb = (int)std::max<uint64_t>(1, (P.n + kFlatBlock - 1) / kFlatBlock);
+        switch (P.d * 2 + (P.wide ? 1 : 0)) {
+#define HCA_CORE_LIST_LANES(DD, WW)                                                            \
+    hipLaunchKernelGGL(k_core_flat<DD>, dim3(fb), dim3(kFlatBlock), 0, s, P);                  \
+    hipLaunchKernelGGL((k_core_list_lanes<DD, WW>), dim3(blocks), dim3(kBlock), 0, s, P);       \
+    hipLaunchKernelGGL((k_core_list_deferred<DD, WW>), dim3(blocks), dim3(kBlock), 0, s, P);
+        case 6: HCA_CORE_LIST_LANES(3, false) break;
+        case 7: HCA_CORE_LIST_LANES(3, true) break;
+        case 8: HCA_CORE_LIST_LANES(4, false) break;
+        case 9: HCA_CORE_LIST_LANES(4, true) break;
+#undef HCA_CORE_LIST_LANES
+        }
+        return;
+    }
     if (P.m == 1 && P.core_list) {
         const int fb = (int)std::max<uint64_t>(1, (P.n + kFlatBlock - 1) / kFlatBlock);
         switch (P.d * 2 + (P.wide ? 1 : 0)) {
@@ -2869,7 +3024,7 @@ void launch_core(const Plan &P, int blocks, hipStream_t s)
 
 void launch_reps(const Plan &P, int blocks, hipStream_t s)
 {
-    if (P.core_list) {
+    if (P.core_list && P.core_lanes == 1) {
         // per core cube (lane path): every slot of a core cube written once
         if (P.d == 1) {
             hipLaunchKernelGGL(k_reps_small<1>, dim3(blocks), dim3(kBlock), 0, s, P);
@@ -2914,7 +3069,7 @@ void launch_merge(const Plan &P, int blocks, hipStream_t s)
             Plan Q = P;
             Q.merge_phase = P.merge_split ? (uint32_t)r + 1u : 0u;
             if (r) hipLaunchKernelGGL(k_flatten, dim3(1024), dim3(kBlock), 0, s, Q);
-            if (P.core_list) {
+            if (P.core_list && P.core_lanes == 1) {
                 switch (P.d * 2 + (P.wide ? 1 : 0)) {
                 case 2: hipLaunchKernelGGL((k_merge_cubes<1, false>), dim3(blocks), dim3(kBlock), 0, s, Q); break;
                 case 3: hipLaunchKernelGGL((k_merge_cubes<1, true>), dim3(blocks), dim3(kBlock), 0, s, Q); break;

@@ -170,7 +170,7 @@ struct Plan {
     // it leaves the point to a wave-wide walk, and the two point lists
     // (carved from the worklist, which is free until merging)
     uint32_t radius;
-    uint32_t core_lanes;        // use the lane walk (carves core_list and core_defer)
+    uint32_t core_lanes;        // lane walk for core marking: 0 off, 1 column ranges (d <= 2), 2 neighbour lists (d 3..4)
     uint32_t core_budget;
     uint32_t *core_list;        // [n] sorted positions of points of sparse cubes
     uint32_t *core_defer;       // [n] the points left to the wave-wide walk

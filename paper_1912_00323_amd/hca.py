@@ -124,7 +124,7 @@ def load_library(path: str | Path | None = None) -> ctypes.CDLL:
 
 class BatchInfo(ctypes.Structure):
     _fields_ = [("runs", ctypes.c_int64), ("graph_replays", ctypes.c_int64), ("plans", ctypes.c_int64),
-                ("groups", ctypes.c_int32), ("side_by_side", ctypes.c_int32)]
+                ("groups", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class BatchGroupInfo(ctypes.Structure):
@@ -185,7 +185,6 @@ class Batch:
         groups = (BatchGroupInfo * 8)()
         self._ctx._check(self._lib.hca_batch_stats(self._h, ctypes.byref(info), groups, 8))
         return {"runs": info.runs, "graph_replays": info.graph_replays, "plans": info.plans,
-                "side_by_side": bool(info.side_by_side),
                 "groups": [groups[i].as_dict() for i in range(info.groups)]}
 
     def close(self):

@@ -272,6 +272,44 @@ def test_unaligned_rows(ctx):
             assert np.array_equal(got, oracle.dbscan(pts, eps, mp)), (d, off)
 
 
+@pytest.mark.parametrize("lanes,budget", [("1", "1"), ("1", "16"), ("1", ""), ("0", "")])
+def test_core_list_lane_walk(ctx, lanes, budget, monkeypatch):
+    """Cube-mode core marking for three and four axes over the cube
+    neighbour lists: one lane per point of a sparse cube (budgets so small
+    that most points go on to the wave walk, and the default), or a wave per
+    cube; the same labels and core flags as the oracle, also through the
+    batch path and with the lists overflowing into the stencil."""
+    monkeypatch.setenv("HCA_SEARCH", "cube")
+    monkeypatch.setenv("HCA_CORE_LANES", lanes)
+    if budget:
+        monkeypatch.setenv("HCA_CORE_BUDGET", budget)
+    for d in (3, 4):
+        rng = np.random.default_rng(190 + d)
+        pts = quantise(make_blobs(rng, 12000, d, 6, 0.02, 0.3), 12)
+        for f, mp in ((0.02, 4), (0.04, 9), (0.08, 20)):
+            eps = f * 2 ** 12
+            print(f"[case] list lanes={lanes} budget={budget} d={d} eps={eps} minPts={mp}", flush=True)
+            want, counts, _ = oracle.dbscan(pts, eps, mp, details=True)
+            got, core, st = gpu_labels(ctx, pts, eps, mp, core=True, stats=True)
+            assert np.array_equal(core.astype(bool), counts >= mp), (d, f, mp)
+            assert np.array_equal(got, want), (d, f, mp)
+            if lanes == "1" and budget == "1" and f == 0.04:
+                assert st["core_rest"] > 0, st
+    import torch
+    jobs = [make_mixed(1300 + k, 3000 + 2000 * k, 3 + k % 2) for k in range(4)]
+    flat = torch.from_numpy(np.concatenate([j.points.ravel() for j in jobs]).astype(np.int32)).cuda()
+    got = ctx.cluster_batch(flat, [j.n for j in jobs], [j.d for j in jobs], [j.eps for j in jobs],
+                            [j.min_pts for j in jobs]).cpu().numpy()
+    at = 0
+    for j in jobs:
+        assert np.array_equal(got[at:at + j.n], oracle.dbscan(j.points, j.eps, j.min_pts)), j.name
+        at += j.n
+    monkeypatch.setenv("HCA_LIST_SLAB", "16")
+    rng = np.random.default_rng(199)
+    pts = quantise(make_blobs(rng, 8000, 3, 4, 0.03, 0.2), 12)
+    check(ctx, pts, 0.05 * 2 ** 12, 6, f"list lanes={lanes} overflowing lists")
+
+
 @pytest.mark.parametrize("lanes,budget", [("1", "1"), ("1", "24"), ("1", "512"), ("0", "512")])
 def test_core_lane_walk(ctx, lanes, budget, monkeypatch):
     """Cube-mode core marking for one and two axes: one lane per point of a
