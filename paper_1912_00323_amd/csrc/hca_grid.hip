@@ -54,14 +54,14 @@ __device__ __forceinline__ Geo<D> cube_geo(const Plan &P, uint64_t key)
     return g;
 }
 
-template <int D>
+template <int D, int NP = kPch>
 __device__ __forceinline__ QBox<D> chunk_box(const Pt<D> *pp, uint32_t mask)
 {
     QBox<D> b;
 #pragma unroll
     for (int e = 0; e < D; e++) { b.lo[e] = INT32_MAX; b.hi[e] = INT32_MIN; }
 #pragma unroll
-    for (int k = 0; k < kPch; k++) {
+    for (int k = 0; k < NP; k++) {
         if (!(mask & (1u << k))) continue;
 #pragma unroll
         for (int e = 0; e < D; e++) {
@@ -213,11 +213,11 @@ __device__ __forceinline__ uint32_t load_neighbours(const Plan &P, uint32_t g, u
 
 
 // The chunk's own points [pc, pc + np) as wave-uniform registers.
-template <int D>
+template <int D, int NP = kPch>
 __device__ __forceinline__ void load_chunk(const Plan &P, uint32_t pc, uint32_t np, Pt<D> *pp)
 {
 #pragma unroll
-    for (int k = 0; k < kPch; k++) {
+    for (int k = 0; k < NP; k++) {
         const uint32_t q = pc + (k < (int)np ? k : 0);
         pp[k] = load_pt<D>(P.spts, q);
 #pragma unroll
@@ -782,7 +782,7 @@ __device__ __forceinline__ uint32_t candidate_pos(uint32_t c, uint32_t total, co
 // set).  Returns the updated mask.  With P.rec and a chunk position pc
 // (not kNone), the first kRec neighbours found of point pc + k are recorded
 // for merging; with qpos, those of point qpos[k] (wave-uniform).
-template <int D, bool WIDE>
+template <int D, bool WIDE, int NP = kPch>
 __device__ __forceinline__ uint32_t count_walk(const Plan &P, uint32_t g, uint64_t gkey, const Pt<D> *pp,
                                                uint32_t done, uint32_t *cnt, uint32_t *s_beg,
                                                uint32_t *s_pre, uint32_t &lt, const Geo<D> &geo,
@@ -791,8 +791,8 @@ __device__ __forceinline__ uint32_t count_walk(const Plan &P, uint32_t g, uint64
     const bool record = P.rec != nullptr && (pc != kNone || qpos != nullptr);
     const uint32_t l = lane_id();
     const uint32_t minpts = geo.min_pts;
-    const uint32_t all = (1u << kPch) - 1u;
-    const QBox<D> qb = chunk_box<D>(pp, ~done);
+    const uint32_t all = (1u << NP) - 1u;
+    const QBox<D> qb = chunk_box<D, NP>(pp, ~done);
     const NbrSrc src = nbr_source(P, g);
     for (uint32_t oc = 0; oc < src.slots && done != all; oc += kWave) {
         const uint32_t total = load_neighbours<D>(P, g, gkey, src, oc, 0, false, qb, s_beg, s_pre, geo);
@@ -809,7 +809,7 @@ __device__ __forceinline__ uint32_t count_walk(const Plan &P, uint32_t g, uint64
                 qn = load_pt<D>(P.spts, nxt);
             }
 #pragma unroll
-            for (int k = 0; k < kPch; k++) {
+            for (int k = 0; k < NP; k++) {
                 if (done & (1u << k)) continue;
                 lt += ok;
                 const bool hit = within<D, WIDE>(pp[k], q, geo.eps2) & ok;
@@ -939,11 +939,15 @@ __global__ __launch_bounds__(kBlock, 6) void k_core_chunks(Plan P)
     const uint32_t w = wave_in_block(), l = lane_id();
     const uint32_t n = P.n, minpts = (uint32_t)P.min_pts;
     const Geo<D> geo = call_geo<D>(P);
-    const uint32_t all = (1u << kPch) - 1u;
+    // chunks of NP points: four past four axes, so that the chunk's rows fit
+    // the scalar registers (eight rows of eight axes spilled them to vector
+    // lanes inside the candidate loop)
+    constexpr int NP = D > 4 ? 4 : kPch;
+    const uint32_t all = (1u << NP) - 1u;
     uint32_t lt = 0;
     const DynRange dr_ = dyn_range(P.ctr->dyn[kDynCore], P.order);
-    HCA_FOR_UNITS_DYN(u, (n + kPch - 1) / kPch, dr_) {
-        const uint32_t pc = u * kPch, np = min((uint32_t)kPch, n - pc);
+    HCA_FOR_UNITS_DYN(u, (n + NP - 1) / NP, dr_) {
+        const uint32_t pc = u * NP, np = min((uint32_t)NP, n - pc);
         // lane k < np: cube, group and density of point pc + k
         uint32_t cell = kNone, grp = kNone;
         bool dense = true;
@@ -953,25 +957,25 @@ __global__ __launch_bounds__(kBlock, 6) void k_core_chunks(Plan P)
             dense = P.cell_start[cell + 1] - P.cell_start[cell] >= minpts;
         }
         uint32_t done = (uint32_t)__ballot(dense) & all;
-        uint32_t cnt[kPch];
+        uint32_t cnt[NP];
 #pragma unroll
-        for (int k = 0; k < kPch; k++) cnt[k] = 0;
+        for (int k = 0; k < NP; k++) cnt[k] = 0;
         if (done != all) {
-            Pt<D> pp[kPch];
-            load_chunk<D>(P, pc, np, pp);
+            Pt<D> pp[NP];
+            load_chunk<D, NP>(P, pc, np, pp);
             uint32_t left = ~done & all;
             while (left) {
                 const uint32_t g = lane_value(grp, __ffs(left) - 1);
                 const uint32_t run = (uint32_t)__ballot(grp == g) & left;
                 left &= ~run;
-                const uint32_t got = count_walk<D, WIDE>(P, g, P.group_key[g], pp, ~run & all, cnt, s_beg[w],
+                const uint32_t got = count_walk<D, WIDE, NP>(P, g, P.group_key[g], pp, ~run & all, cnt, s_beg[w],
                                                          s_pre[w], lt, geo, pc);
                 done |= got & run;
             }
         }
         uint32_t mine = 0;
 #pragma unroll
-        for (int k = 0; k < kPch; k++)
+        for (int k = 0; k < NP; k++)
             if ((uint32_t)k == l) mine = cnt[k];
         const bool core = l < np && (dense || mine >= minpts);
         if (l < np) {
