@@ -383,16 +383,35 @@ __device__ __forceinline__ uint32_t ld_parent_cached(const uint32_t *p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Root of x.  Two ways of shortening the path: path splitting (each node on
+// the way points to its grandparent) or, with TOP, a plain walk after which
+// only x itself is pointed at the root found.  Either store names an ancestor
+// of the node written, so both are safe against concurrent unions.  TOP
+// stores once per call, which pays where many lanes walk the same deep chains
+// at once (cube merging over millions of points); the merging of search
+// groups is faster with path splitting.
+template <bool TOP = false>
 __device__ __forceinline__ uint32_t uf_find(uint32_t *parent, uint32_t x)
 {
-    uint32_t p = ld_parent_cached(parent + x);
-    while (p != x) {
-        const uint32_t gp = ld_parent_cached(parent + p);
-        if (gp != p) st_parent(parent + x, gp);   // path splitting; gp is an ancestor of x
-        x = p;
-        p = gp;
+    if constexpr (TOP) {
+        const uint32_t x0 = x, p0 = ld_parent_cached(parent + x);
+        uint32_t p = p0;
+        while (p != x) {
+            x = p;
+            p = ld_parent_cached(parent + x);
+        }
+        if (p0 != x) st_parent(parent + x0, x);
+        return x;
+    } else {
+        uint32_t p = ld_parent_cached(parent + x);
+        while (p != x) {
+            const uint32_t gp = ld_parent_cached(parent + p);
+            if (gp != p) st_parent(parent + x, gp);   // path splitting; gp is an ancestor of x
+            x = p;
+            p = gp;
+        }
+        return x;
     }
-    return x;
 }
 
 // Root of x without writing anything.  Used once no more unions can happen:
@@ -408,16 +427,17 @@ __device__ __forceinline__ uint32_t uf_root(const uint32_t *parent, uint32_t x)
     return x;
 }
 
+template <bool TOP = false>
 __device__ __forceinline__ void uf_union(uint32_t *parent, uint32_t a, uint32_t b)
 {
-    a = uf_find(parent, a);
-    b = uf_find(parent, b);
+    a = uf_find<TOP>(parent, a);
+    b = uf_find<TOP>(parent, b);
     while (a != b) {
         if (a < b) { uint32_t t = a; a = b; b = t; }     // hook larger root a under b
         uint32_t seen = cas_agent(parent + a, a, b);
         if (seen == a) return;
-        a = uf_find(parent, seen);
-        b = uf_find(parent, b);
+        a = uf_find<TOP>(parent, seen);
+        b = uf_find<TOP>(parent, b);
     }
 }
 

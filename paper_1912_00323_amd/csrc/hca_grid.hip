@@ -1748,10 +1748,10 @@ __device__ __forceinline__ bool rep_pair(const Plan &P, uint32_t A, uint32_t B, 
         if (ra != ~0ull && rb != ~0ull) {
             lt++;
             joined = within<D, WIDE>(load_pt<D>(P.spts, (uint32_t)ra), load_pt<D>(P.spts, (uint32_t)rb), eps2);
-            if (joined) uf_union(P.parent, A, B);
+            if (joined) uf_union<true>(P.parent, A, B);
         }
     }
-    if (todo && !joined && !P.rep_only) todo = uf_find(P.parent, A) != uf_find(P.parent, B);
+    if (todo && !joined && !P.rep_only) todo = uf_find<true>(P.parent, A) != uf_find<true>(P.parent, B);
     return todo && !joined && !P.rep_only;
 }
 
@@ -1921,9 +1921,9 @@ __global__ __launch_bounds__(kBlock) void k_merge_cubes(Plan P)
         if (todo && ra != ~0ull && rb != ~0ull) {
             lt++;
             joined = within<D, WIDE>(load_pt<D>(P.spts, (uint32_t)ra), load_pt<D>(P.spts, (uint32_t)rb), eps2);
-            if (joined) uf_union(P.parent, A, B);
+            if (joined) uf_union<true>(P.parent, A, B);
         }
-        if (todo && !joined && !P.rep_only) todo = uf_find(P.parent, A) != uf_find(P.parent, B);
+        if (todo && !joined && !P.rep_only) todo = uf_find<true>(P.parent, A) != uf_find<true>(P.parent, B);
         queue_exact<D, WIDE>(P, todo && !joined && !P.rep_only, A, B, lt);
     }
     flush_tests(P, kTestsMerge, lt);
@@ -1936,7 +1936,7 @@ template <int D, bool WIDE>
 __device__ void exact_pair(const Plan &P, uint32_t A, uint32_t B, uint32_t &lt)
 {
     const uint32_t l = lane_id();
-    if (uf_find(P.parent, A) == uf_find(P.parent, B)) return;
+    if (uf_find<true>(P.parent, A) == uf_find<true>(P.parent, B)) return;
     const int64_t eps2 = cube_geo<D>(P, P.group_key[A]).eps2;
     const uint32_t a0 = P.cell_start[A], na = P.cell_start[A + 1] - a0;
     const uint32_t b0 = P.cell_start[B], nb = P.cell_start[B + 1] - b0;
@@ -1955,9 +1955,9 @@ __device__ void exact_pair(const Plan &P, uint32_t A, uint32_t B, uint32_t &lt)
             }
         }
         if (__ballot(hit)) { found = true; break; }
-        if ((it & 63u) == 63u && uf_find(P.parent, A) == uf_find(P.parent, B)) return;
+        if ((it & 63u) == 63u && uf_find<true>(P.parent, A) == uf_find<true>(P.parent, B)) return;
     }
-    if (found && l == 0) uf_union(P.parent, A, B);
+    if (found && l == 0) uf_union<true>(P.parent, A, B);
 }
 
 template <int D, bool WIDE>
