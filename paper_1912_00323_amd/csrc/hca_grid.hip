@@ -373,26 +373,74 @@ __device__ __forceinline__ int64_t half_key_delta(const Plan &P, int first, uint
 // wave appends to its own slab; when a group does not fit, every group is
 // searched over the stencil instead.
 
-// Point box of every group, and the backward counters cleared.
+// Point box of every group, and the backward counters cleared.  A wave takes
+// eight groups at a time, eight lanes each: every lane folds every eighth
+// point of its group, three exchanges within the eight lanes combine them,
+// and lane e of the eight writes axis e.  Groups of more than kBoxOctet
+// points are then boxed one at a time by the whole wave.
+constexpr uint32_t kBoxOctet = 64;
+
+template <int D>
+__device__ __forceinline__ void store_gbox(const Plan &P, uint32_t g, const QBox<D> &b, uint32_t e_lane)
+{
+    int32_t lo = 0, hi = 0;
+#pragma unroll
+    for (int e = 0; e < D; e++)
+        if ((uint32_t)e == e_lane) { lo = b.lo[e]; hi = b.hi[e]; }
+    P.gbox[(uint64_t)g * 2 * D + e_lane] = lo;
+    P.gbox[(uint64_t)g * 2 * D + D + e_lane] = hi;
+}
+
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_group_box(Plan P)
 {
-    const uint32_t l = lane_id();
+    const uint32_t l = lane_id(), sub = l & 7u;
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
     const WaveRange hca_wr_ = wave_range(P.order);
-    HCA_FOR_UNITS(g, ng) {
-        const QBox<D> b = group_points_box<D>(P, P.group_start[g], P.group_start[g + 1]);
-        if (l < (uint32_t)D) {
-            int32_t lo = 0, hi = 0;
-#pragma unroll
-            for (int e = 0; e < D; e++)
-                if ((uint32_t)e == l) { lo = b.lo[e]; hi = b.hi[e]; }
-            P.gbox[(uint64_t)g * 2 * D + l] = lo;
-            P.gbox[(uint64_t)g * 2 * D + D + l] = hi;
+    HCA_FOR_UNITS(u, (ng + 7u) / 8u) {
+        const uint32_t g = u * 8u + (l >> 3);
+        uint32_t p0 = 0, p1 = 0;
+        if (g < ng) {
+            p0 = P.group_start[g];
+            p1 = P.group_start[g + 1];
         }
-        if (l == 0) {
+        const bool small = g < ng && p1 - p0 <= kBoxOctet;
+        QBox<D> b;
+#pragma unroll
+        for (int e = 0; e < D; e++) { b.lo[e] = INT32_MAX; b.hi[e] = INT32_MIN; }
+        if (small) {
+            // two rows per lane in flight; a lane past the end re-reads row p0
+            for (uint32_t q = p0 + sub; q < p1; q += 16u) {
+                const Pt<D> v0 = load_pt<D>(P.spts, q);
+                const Pt<D> v1 = load_pt<D>(P.spts, q + 8u < p1 ? q + 8u : p0);
+#pragma unroll
+                for (int e = 0; e < D; e++) {
+                    b.lo[e] = min(b.lo[e], min(v0.x[e], v1.x[e]));
+                    b.hi[e] = max(b.hi[e], max(v0.x[e], v1.x[e]));
+                }
+            }
+        }
+        // every lane takes part in the exchanges
+#pragma unroll
+        for (int e = 0; e < D; e++) {
+#pragma unroll
+            for (int o = 1; o < 8; o <<= 1) {
+                b.lo[e] = min(b.lo[e], __shfl_xor(b.lo[e], o));
+                b.hi[e] = max(b.hi[e], __shfl_xor(b.hi[e], o));
+            }
+        }
+        if (small && sub < (uint32_t)D) store_gbox<D>(P, g, b, sub);
+        if (g < ng && sub == 0) {
             st_agent32(P.nbr_bcount + g, 0u);
             st_agent32(P.nbr_bcursor + g, 0u);
+        }
+        uint64_t big = __ballot(g < ng && !small && sub == 0);
+        while (big) {
+            const uint32_t src = __ffsll((unsigned long long)big) - 1;
+            big &= big - 1;
+            const uint32_t gb = __shfl(g, src);
+            const QBox<D> bb = group_points_box<D>(P, P.group_start[gb], P.group_start[gb + 1]);
+            if (l < (uint32_t)D) store_gbox<D>(P, gb, bb, l);
         }
     }
 }
@@ -2446,13 +2494,9 @@ __global__ __launch_bounds__(kBlock, 4) void k_merge_inter(Plan P)
                     const uint32_t ti = t / nb_t, tj = t - ti * nb_t;
                     const bool mine = t < nt;
                     const uint32_t slot = first + t;
-                    if (mine && slot < cap) {
-                        uint32_t *e = P.work + 4ull * ((uint64_t)region * cap + slot);
-                        e[0] = GA;
-                        e[1] = gb;
-                        e[2] = whole ? kNone : ti;
-                        e[3] = tj;
-                    }
+                    if (mine && slot < cap)
+                        *(uint4 *)(P.work + 4ull * ((uint64_t)region * cap + slot)) =
+                            make_uint4(GA, gb, whole ? kNone : ti, tj);
                     // region full: link those tiles here
                     uint64_t sp = __ballot(mine && slot >= cap);
                     while (sp) {
@@ -2484,8 +2528,8 @@ __global__ __launch_bounds__(kBlock) void k_merge_pairs(Plan P)
     const WaveRange hca_wr_ = wave_range(P.order);
     HCA_FOR_UNITS(it, items) {
         const uint32_t r = candidate_lane(it, s_pre[w]);
-        const uint32_t *e = P.work + 4ull * ((uint64_t)r * cap + (it - s_pre[w][r]));
-        link_tile<D, WIDE>(P, e[0], e[1], e[2], e[3], s_pt[w], lt);
+        const uint4 e = *(const uint4 *)(P.work + 4ull * ((uint64_t)r * cap + (it - s_pre[w][r])));
+        link_tile<D, WIDE>(P, e.x, e.y, e.z, e.w, s_pt[w], lt);
     }
     flush_tests(P, kTestsMerge, lt);
 }
