@@ -46,26 +46,68 @@ __device__ __forceinline__ T wave_sum(T v)
     return v;
 }
 
+// 32-bit values: v as seen from the lane that the DPP control CTRL names
+// (within a row of 16 lanes), and lane `lane`'s value as a scalar.
+template <int CTRL, typename T>
+__device__ __forceinline__ T dpp_row(T v)
+{
+    static_assert(sizeof(T) == 4, "32-bit values only");
+    const int x = __builtin_bit_cast(int, v);
+    return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(x, x, CTRL, 0xF, 0xF, false));
+}
+template <typename T>
+__device__ __forceinline__ T lane_scalar(T v, int lane)
+{
+    static_assert(sizeof(T) == 4, "32-bit values only");
+    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+
+// Minimum / maximum over the wave, returned to every lane; every lane must
+// be active.  32-bit values stay in the vector unit: four DPP steps within
+// each row of 16 lanes (swap pairs, swap halves of quads, mirror the halves
+// of the row, mirror the row) leave every lane with its row's extreme, and
+// the four rows' values are read as scalars.  Wider values go through
+// lane exchanges.
 template <typename T>
 __device__ __forceinline__ T wave_min(T v)
 {
+    if constexpr (sizeof(T) == 4) {
+        T w = dpp_row<0xB1>(v); v = w < v ? w : v;       // quad_perm [1,0,3,2]
+        w = dpp_row<0x4E>(v); v = w < v ? w : v;         // quad_perm [2,3,0,1]
+        w = dpp_row<0x141>(v); v = w < v ? w : v;        // row_half_mirror
+        w = dpp_row<0x140>(v); v = w < v ? w : v;        // row_mirror
+        const T a = lane_scalar(v, 0), b = lane_scalar(v, 16), c = lane_scalar(v, 32), d = lane_scalar(v, 48);
+        const T ab = a < b ? a : b, cd = c < d ? c : d;
+        return ab < cd ? ab : cd;
+    } else {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        T w = __shfl_xor(v, o);
-        v = w < v ? w : v;
+        for (int o = 32; o > 0; o >>= 1) {
+            T w = __shfl_xor(v, o);
+            v = w < v ? w : v;
+        }
+        return v;
     }
-    return v;
 }
 
 template <typename T>
 __device__ __forceinline__ T wave_max(T v)
 {
+    if constexpr (sizeof(T) == 4) {
+        T w = dpp_row<0xB1>(v); v = w > v ? w : v;
+        w = dpp_row<0x4E>(v); v = w > v ? w : v;
+        w = dpp_row<0x141>(v); v = w > v ? w : v;
+        w = dpp_row<0x140>(v); v = w > v ? w : v;
+        const T a = lane_scalar(v, 0), b = lane_scalar(v, 16), c = lane_scalar(v, 32), d = lane_scalar(v, 48);
+        const T ab = a > b ? a : b, cd = c > d ? c : d;
+        return ab > cd ? ab : cd;
+    } else {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        T w = __shfl_xor(v, o);
-        v = w > v ? w : v;
+        for (int o = 32; o > 0; o >>= 1) {
+            T w = __shfl_xor(v, o);
+            v = w > v ? w : v;
+        }
+        return v;
     }
-    return v;
 }
 
 template <typename T>
