@@ -53,16 +53,23 @@ __global__ __launch_bounds__(kBlock) void k_seg_gather(const SegParam *seg, uint
 // lane by lane.
 __device__ __forceinline__ uint32_t ord32(int32_t v) { return (uint32_t)v ^ 0x80000000u; }
 
+// The words only grow, so a wave value not above the stored one needs no
+// atomic: a large data set then takes a few atomics per word instead of one
+// per wave, all on the same address.  Lane j < 2D handles word j.
 template <int D>
 __device__ __forceinline__ void seg_box_flush(uint32_t *box, uint32_t s, const uint32_t *lo, const uint32_t *hi)
 {
+    const uint32_t l = lane_id();
+    uint32_t mine = 0;
 #pragma unroll
     for (int k = 0; k < D; k++) {
         const uint32_t wlo = wave_max(lo[k]), whi = wave_max(hi[k]);
-        if (lane_id() == 0) {
-            atomicMax(box + (uint64_t)s * 2 * D + k, wlo);
-            atomicMax(box + (uint64_t)s * 2 * D + D + k, whi);
-        }
+        if (l == (uint32_t)k) mine = wlo;
+        if (l == (uint32_t)(D + k)) mine = whi;
+    }
+    if (l < (uint32_t)(2 * D)) {
+        uint32_t *word = box + (uint64_t)s * 2 * D + l;
+        if (mine > ld_agent32(word)) atomicMax(word, mine);
     }
 }
 
