@@ -343,6 +343,22 @@ double hca_clock(void);
  * or a NULL context. */
 hca_status hca_set_exact(hca_ctx *ctx, int32_t exact);
 
+/* Plan reuse for calls of up to eight axes (on = 1, the default; 0 off).
+ * The bounding box fixes a call's key layout (Algorithm 1's grid anchored at
+ * the data's minimum), and reading it back costs a device round trip before
+ * the rest of the call can be launched.  Once two calls in a row with the same
+ * n and d have had the same box, the next call of that shape is planned from
+ * that box and launched at once; its own box is still computed, and a kernel
+ * compares it with the one planned with.  When they differ, the results of
+ * that launch are discarded and the call is planned from its own box and run
+ * again, so results never depend on this setting.  Calls without allocation
+ * (hca_cluster_noalloc) always wait for their own box.  HCA_E_INVAL for other
+ * values or a NULL context.
+ * hca_plan_reuse_counts: calls of this context planned ahead so far, and how
+ * many of them ran again (HOST pointers owned by the caller). */
+hca_status hca_set_plan_reuse(hca_ctx *ctx, int32_t on);
+hca_status hca_plan_reuse_counts(const hca_ctx *ctx, int64_t *calls, int64_t *reruns);
+
 /* Phases of one call, in launch order, for hca_set_profiling / hca_phase_times:
  * origin shift (bounding box); cube keys and their radix sort with the gather
  * of points into cube order (methodology, pre-processing sort); cube and group

@@ -18,6 +18,12 @@ struct SortBuffers {
 
 void launch_bbox(int d, const int32_t *pts, uint32_t n, int32_t *partial, int blocks,
                  hipStream_t s);
+// The box a call was planned with (axes beyond d unused).
+struct BoxExpect {
+    int32_t mn[kMaxDim], mx[kMaxDim];
+};
+void launch_bbox_check(int d, const int32_t *partial, int blocks, const BoxExpect &e, uint32_t *flag,
+                       hipStream_t s);
 void launch_sort(const Plan &P, SortBuffers &B, bool wide_keys, hipStream_t s);
 void launch_cells(const Plan &P, bool wide_keys, uint64_t *status, uint32_t *ticket,
                   hipStream_t s);

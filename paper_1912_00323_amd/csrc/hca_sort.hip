@@ -104,8 +104,13 @@ __device__ __forceinline__ K cube_key(const Plan &P, const Pt<D> &p, uint32_t i)
     }
 #pragma unroll
     for (int k = 0; k < D; k++) {
-        const uint32_t u = (uint32_t)(p.x[k] - P.origin[k]);     // < 2^30 (host checked)
-        const uint32_t c = u / P.side;
+        // the cube coordinate is held to the key layout: a call planned from
+        // the previous call's box runs before its own box is checked (and is
+        // planned and run again when the box differs), and its keys must stay
+        // inside the tables meanwhile; data that fit the layout are unchanged
+        const int64_t dx = (int64_t)p.x[k] - P.origin[k];
+        const uint32_t u = (uint32_t)min(max(dx, (int64_t)0), (int64_t)INT32_MAX);
+        const uint32_t c = min(u / P.side, (P.gmax[k] + 1u) * P.m - 1u);
         const uint32_t g = c / P.m;
         const uint32_t f = c - g * P.m;
         key |= (uint64_t)g << (P.goff[k] + P.fine_bits);
@@ -506,6 +511,46 @@ __global__ __launch_bounds__(kCellsBlock) void k_cells(Plan P, uint64_t *__restr
     }
 }
 
+// A call planned from the previous call's bounding box: one block folds this
+// call's per-block partials and sets *flag (mapped host memory) to 1 when the
+// box differs from the one planned with, else to 0.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_bbox_check(const int32_t *__restrict__ partial, int blocks,
+                                                       BoxExpect e, uint32_t *flag)
+{
+    int32_t mn[D], mx[D];
+#pragma unroll
+    for (int k = 0; k < D; k++) { mn[k] = INT32_MAX; mx[k] = INT32_MIN; }
+    for (int b = threadIdx.x; b < blocks; b += kBlock) {
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+            mn[k] = min(mn[k], partial[b * 2 * D + k]);
+            mx[k] = max(mx[k], partial[b * 2 * D + D + k]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < D; k++) {
+        mn[k] = wave_min(mn[k]);
+        mx[k] = wave_max(mx[k]);
+    }
+    __shared__ int32_t s_mn[kBlock / kWave][D], s_mx[kBlock / kWave][D];
+    const uint32_t w = wave_in_block();
+    if (lane_id() == 0) {
+#pragma unroll
+        for (int k = 0; k < D; k++) { s_mn[w][k] = mn[k]; s_mx[w][k] = mx[k]; }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t f = 0;
+        for (int k = 0; k < D; k++) {
+            int32_t a = s_mn[0][k], z = s_mx[0][k];
+            for (int i = 1; i < kBlock / kWave; i++) { a = min(a, s_mn[i][k]); z = max(z, s_mx[i][k]); }
+            if (a != e.mn[k] || z != e.mx[k]) f = 1;
+        }
+        __hip_atomic_store(flag, f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
@@ -529,6 +574,18 @@ void launch_bbox(int d, const int32_t *pts, uint32_t n, int32_t *partial, int bl
     case 7: launch_bbox_d<7>(pts, n, partial, blocks, s); break;
     case 8: launch_bbox_d<8>(pts, n, partial, blocks, s); break;
     }
+}
+
+void launch_bbox_check(int d, const int32_t *partial, int blocks, const BoxExpect &e, uint32_t *flag,
+                       hipStream_t s)
+{
+#define HCA_BOX_CHECK(DD) \
+    case DD: hipLaunchKernelGGL(k_bbox_check<DD>, dim3(1), dim3(kBlock), 0, s, partial, blocks, e, flag); break;
+    switch (d) {
+        HCA_BOX_CHECK(1) HCA_BOX_CHECK(2) HCA_BOX_CHECK(3) HCA_BOX_CHECK(4)
+        HCA_BOX_CHECK(5) HCA_BOX_CHECK(6) HCA_BOX_CHECK(7) HCA_BOX_CHECK(8)
+    }
+#undef HCA_BOX_CHECK
 }
 
 template <int D, typename K, int ITEMS, int THREADS = kBlock>

@@ -77,6 +77,10 @@ def load_library(path: str | Path | None = None) -> ctypes.CDLL:
     lib.hca_last_error.restype = ctypes.c_char_p
     lib.hca_set_stream.argtypes = [vp, vp]
     lib.hca_set_stream.restype = ctypes.c_int
+    lib.hca_set_plan_reuse.argtypes = [vp, i32]
+    lib.hca_set_plan_reuse.restype = ctypes.c_int
+    lib.hca_plan_reuse_counts.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.hca_plan_reuse_counts.restype = ctypes.c_int
     lib.hca_cluster.argtypes = [vp, vp, i64, i32, dbl, i32, vp]
     lib.hca_cluster.restype = ctypes.c_int
     lib.hca_cluster_noalloc.argtypes = [vp, vp, i64, i32, dbl, i32, vp]
@@ -334,6 +338,18 @@ class Context:
         """True (default): exact DBSCAN.  False: the paper's merge on facing
         representatives alone (approximate; cubes as search groups, d <= 4)."""
         self._check(self._lib.hca_set_exact(self._ctx, 1 if exact else 0))
+
+    def set_plan_reuse(self, on: bool):
+        """True (default): a call whose shape and bounding box repeat those of
+        the previous calls is launched without waiting for its own box (which
+        is still checked on the device; a differing box runs the call again)."""
+        self._check(self._lib.hca_set_plan_reuse(self._ctx, 1 if on else 0))
+
+    def plan_reuse_counts(self) -> tuple:
+        """(calls planned ahead, of which ran again) on this context."""
+        calls, reruns = ctypes.c_int64(), ctypes.c_int64()
+        self._check(self._lib.hca_plan_reuse_counts(self._ctx, ctypes.byref(calls), ctypes.byref(reruns)))
+        return calls.value, reruns.value
 
     def set_profiling(self, phase: int | str | None):
         """Time later calls with HIP events: None = off, "all", or one phase."""

@@ -588,6 +588,53 @@ def test_repeatable(ctx):
     assert np.array_equal(first, oracle.dbscan(w.points, w.eps, w.min_pts))
 
 
+def test_plan_reuse(ctx):
+    """Calls planned ahead from the box of the previous calls: the same data
+    again (planned ahead, its box compared on the device), data of the same
+    shape with another box (the comparison fails and the call runs again from
+    its own box), a span past 2^30 once a plan is armed again (the error of the
+    call planned from its own box), and reuse switched off."""
+    import torch
+    from paper_1912_00323_amd import hca
+    ctx.set_plan_reuse(True)
+    for d in (2, 3, 5, 8):
+        rng = np.random.default_rng(300 + d)
+        pts = quantise(make_blobs(rng, 6000, d, 5, 0.04, 0.1), 10)
+        eps, mp = (0.06 + 0.01 * d) * 2 ** 10, 6
+        want = oracle.dbscan(pts, eps, mp)
+        t = torch.from_numpy(pts).cuda()
+        print(f"[case] plan reuse d={d} same box", flush=True)
+        c0, r0 = ctx.plan_reuse_counts()
+        for _ in range(4):
+            assert np.array_equal(ctx.cluster(t, eps, mp).cpu().numpy(), want)
+        c1, r1 = ctx.plan_reuse_counts()
+        assert c1 - c0 == 2 and r1 == r0, (d, c0, c1, r0, r1)
+        print(f"[case] plan reuse d={d} other box", flush=True)
+        other = pts.copy()
+        other[:, 0] += 1234
+        other[7] -= 3000
+        got = ctx.cluster(torch.from_numpy(other).cuda(), eps, mp).cpu().numpy()
+        assert np.array_equal(got, oracle.dbscan(other, eps, mp))
+        c2, r2 = ctx.plan_reuse_counts()
+        assert (c2, r2) == (c1 + 1, r1 + 1), (d, c1, c2, r1, r2)
+        print(f"[case] plan reuse d={d} span past 2^30", flush=True)
+        for _ in range(2):
+            ctx.cluster(t, eps, mp)
+        bad = pts.copy()
+        bad[0, 0] += 1 << 30
+        with pytest.raises(hca.HcaError) as e:
+            ctx.cluster(torch.from_numpy(bad).cuda(), eps, mp)
+        assert e.value.status == hca.HCA_E_RANGE
+        assert ctx.plan_reuse_counts() == (c2 + 1, r2 + 1)
+        assert np.array_equal(ctx.cluster(t, eps, mp).cpu().numpy(), want)
+    ctx.set_plan_reuse(False)
+    counts = ctx.plan_reuse_counts()
+    for _ in range(3):
+        assert np.array_equal(ctx.cluster(t, eps, mp).cpu().numpy(), want)
+    assert ctx.plan_reuse_counts() == counts
+    ctx.set_plan_reuse(True)
+
+
 def test_representative_only_mode(ctx):
     """The paper's merge as printed (facing representatives alone) against the
     oracle's representative-only mode, including the fixture where it splits a
