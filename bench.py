@@ -33,7 +33,7 @@ HBM_PHASES = ("bbox", "sort", "cells", "labels")
 ALU_PHASES = {"core": "tests_core", "intra": "tests_intra", "merge": "tests_merge",
               "border": "tests_border"}
 PHASE_KERNELS = {
-    "bbox": ["k_bbox"], "sort": ["k_keys_hist", "k_onesweep"], "cells": ["k_cells", "k_table_clear", "k_table"],
+    "bbox": ["k_bbox", "k_bbox_check"], "sort": ["k_keys_hist", "k_onesweep"], "cells": ["k_cells", "k_table_clear", "k_table"],
     "lists": ["k_group_box", "k_prefix_ranges", "k_nbr_lists", "k_nbr_bscan", "k_nbr_back"],
     "core": ["k_core", "k_core_chunks", "k_core_flat", "k_core_lanes", "k_core_deferred", "k_core_cubes"],
     "reps": ["k_reps_init", "k_reps", "k_reps_small", "k_reps_big"],
@@ -265,6 +265,7 @@ def measure(w, steps: int, warmup: int, merge: str, with_cpu: bool) -> dict:
     # dominant phase is bracketed by HIP events (two per call)
     ctx.set_profiling(dominant)
     dom_ms = []
+    reuse0 = ctx.plan_reuse_counts()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -272,7 +273,18 @@ def measure(w, steps: int, warmup: int, merge: str, with_cpu: bool) -> dict:
         dom_ms.append(ctx.phase_times()[dominant])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    reuse1 = ctx.plan_reuse_counts()
     ctx.set_profiling(None)
+    # for reference, outside the timed region: the same calls with plan reuse
+    # off, each waiting for its own bounding box before the rest is launched
+    ctx.set_plan_reuse(False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        ctx.cluster(pts, w.eps, w.min_pts, out=labels)
+    torch.cuda.synchronize()
+    dt_off = time.perf_counter() - t1
+    ctx.set_plan_reuse(True)
     ms_per_step = dt * 1e3 / steps
     dom = statistics.mean(dom_ms)
     key_bytes = 8 if stats["key_bits"] > 32 or w.d > 8 else 4
@@ -319,6 +331,11 @@ def measure(w, steps: int, warmup: int, merge: str, with_cpu: bool) -> dict:
         "roofline_binning_sort": hbm_roofline("sort", phase_ms["sort"]),
         "phase_ms": {p: round(v, 4) for p, v in phase_ms.items() if v > 0},
         "stats": stats,
+        "plan_reuse": {"timed_calls_planned_ahead": reuse1[0] - reuse0[0],
+                       "timed_calls_run_again": reuse1[1] - reuse0[1],
+                       "ms_per_step_without": round(dt_off * 1e3 / steps, 4),
+                       "note": "every call computes its bounding box; a call planned from the previous "
+                               "calls' box has it compared on the device and runs again if it differs"},
     }
     if approx is not None:
         out["approximate"] = approx
