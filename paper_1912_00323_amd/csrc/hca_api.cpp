@@ -240,9 +240,10 @@ uint32_t sort_threads(bool wide_keys)
     return wide_keys ? 512u : 1024u;
 }
 
-// Keys per radix tile of 32-bit keys: 8192 from 8M keys on (each tile's
-// runs per digit twice as long, with tiles enough to fill the chip), else
-// the default 4096; HCA_SORT_TILE=4096|8192 overrides.
+// Keys per radix tile of 32-bit keys: 8192 from 1.5M keys on (each tile's
+// runs per digit twice as long, with tiles enough to fill the chip: 2-D sort
+// at 2M 87 -> 73 us, 4M 145 -> 127, 8M 262 -> 229), else the default 4096
+// (at 1M 8192 is slower, 55 -> 61 us); HCA_SORT_TILE=4096|8192 overrides.
 uint32_t sort_tile(uint32_t n, bool wide_keys)
 {
     if (wide_keys) return 0u;
@@ -250,7 +251,7 @@ uint32_t sort_tile(uint32_t n, bool wide_keys)
     const int v = e ? std::atoi(e) : 0;
     if (v == 4096) return 0u;
     if (v == 8192) return 8192u;
-    return n >= (8u << 20) ? 8192u : 0u;
+    return n >= (3u << 19) ? 8192u : 0u;
 }
 
 // Cube-mode merging in two launches with a flattening between them: the two
