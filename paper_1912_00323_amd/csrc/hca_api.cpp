@@ -374,6 +374,7 @@ struct hca_ctx {
     int32_t box_d = 0;
     int32_t box_mn[kMaxDim] = {}, box_mx[kMaxDim] = {};
     uint32_t *check_host = nullptr, *check_dev = nullptr;   // the comparison's flag (mapped, coherent)
+    uint32_t *miss_dev = nullptr;     // the same flag in device memory, for the call's later kernels
     int64_t reuse_calls = 0, reuse_reruns = 0;
     void *io = nullptr;               // staging for hca_cluster_host
     size_t io_size = 0;
@@ -1073,8 +1074,8 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
     for (bool &u : ctx->ev_used) u = false;
     // planned from the box of the previous calls (checked on the device
     // below), or from this call's box, read back after a sync
-    const bool ahead = ctx->reuse && ctx->box_armed && ctx->check_dev && !ctx->fixed && ctx->box_n == n &&
-                       ctx->box_d == d;
+    const bool ahead = ctx->reuse && ctx->box_armed && ctx->check_dev && ctx->miss_dev && !ctx->fixed &&
+                       ctx->box_n == n && ctx->box_d == d;
     int64_t mn[kMaxDim], mx[kMaxDim];
     if (ahead) {
         for (int k = 0; k < d; k++) {
@@ -1173,9 +1174,13 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
         }
         mark(ctx, HCA_PHASE_BBOX, false);
         launch_bbox(d, points, n, partial, bb, s);
-        launch_bbox_check(d, partial, bb, e, ctx->check_dev, s);
+        launch_bbox_check(d, partial, bb, e, ctx->check_dev, ctx->miss_dev, s);
         mark(ctx, HCA_PHASE_BBOX, true);
         HCA_HIP(hipGetLastError(), "bbox launch");
+        // on a differing box every later kernel returns at once: the keys of
+        // such data are held to the layout, but the work of clustering them
+        // in it is not bounded (points piled into the edge cubes)
+        P.box_miss = ctx->miss_dev;
     }
     launch_sequence(ctx, P, Z);
     HCA_HIP(hipGetLastError(), "kernel launch");
@@ -1915,7 +1920,7 @@ hca_status hca_create(hca_ctx **out, int32_t device)
     }
     // the flag of plan reuse's box comparison, written by a kernel into host
     // memory; without it every call waits for its own box
-    void *fh = nullptr, *fd = nullptr;
+    void *fh = nullptr, *fd = nullptr, *md = nullptr;
     if (hipHostMalloc(&fh, 256, hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess) {
         if (hipHostGetDevicePointer(&fd, fh, 0) == hipSuccess) {
             ctx->check_host = (uint32_t *)fh;
@@ -1923,6 +1928,10 @@ hca_status hca_create(hca_ctx **out, int32_t device)
         } else {
             (void)hipHostFree(fh);
         }
+    }
+    if (hipMalloc(&md, 256) == hipSuccess) {
+        if (hipMemset(md, 0, 256) == hipSuccess) ctx->miss_dev = (uint32_t *)md;
+        else (void)hipFree(md);
     }
     (void)hipGetLastError();
     *out = ctx;
@@ -1940,6 +1949,7 @@ void hca_destroy(hca_ctx *ctx)
     if (ctx->bws) (void)hipFree(ctx->bws);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     if (ctx->check_host) (void)hipHostFree(ctx->check_host);
+    if (ctx->miss_dev) (void)hipFree(ctx->miss_dev);
     if (ctx->ev_made)
         for (auto &e : ctx->ev) (void)hipEventDestroy(e);
     delete ctx;

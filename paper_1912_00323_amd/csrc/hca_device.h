@@ -543,6 +543,14 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kPch = 8;           // points of the own group handled per sweep
 
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Whether this call was planned from a box that its own box turned out to
+// differ from (the same value in every thread of every kernel after the
+// comparison, so a kernel returning on it returns everywhere).
+__device__ __forceinline__ bool box_missed(const Plan &P)
+{
+    return P.box_miss != nullptr && *P.box_miss != 0;
+}
 __device__ __forceinline__ int32_t uniform_i(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 // Lane `src` of v, wave-uniform (src must be the same in every lane): one
 // readlane into a scalar register, so loops bounded by it stay scalar.

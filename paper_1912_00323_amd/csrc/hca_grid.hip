@@ -250,6 +250,7 @@ __global__ __launch_bounds__(kBlock) void k_init(uint32_t *zero, uint64_t zero_w
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_table_clear(Plan P)
 {
+    if (box_missed(P)) return;
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
     uint64_t cap = 1024;
     while (cap < ((uint64_t)ng << P.hash_load)) cap <<= 1;
@@ -263,6 +264,7 @@ __global__ __launch_bounds__(kBlock) void k_table_clear(Plan P)
 
 __global__ __launch_bounds__(kBlock) void k_table(Plan P)
 {
+    if (box_missed(P)) return;
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
     const uint64_t mask = P.ctr->hmask;
     for (uint32_t g = blockIdx.x * kBlock + threadIdx.x; g < ng; g += gridDim.x * kBlock) {
@@ -394,6 +396,7 @@ __device__ __forceinline__ void store_gbox(const Plan &P, uint32_t g, const QBox
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_group_box(Plan P)
 {
+    if (box_missed(P)) return;
     const uint32_t l = lane_id(), sub = l & 7u;
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
     const WaveRange hca_wr_ = wave_range(P.order);
@@ -451,6 +454,7 @@ __global__ __launch_bounds__(kBlock) void k_group_box(Plan P)
 // values, which the readers reject (the group at pstart has another prefix).
 __global__ __launch_bounds__(kBlock) void k_prefix_ranges(Plan P)
 {
+    if (box_missed(P)) return;
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
     for (uint32_t g = blockIdx.x * kBlock + threadIdx.x; g < ng; g += gridDim.x * kBlock) {
         const uint64_t p = P.group_key[g] >> P.pshift;
@@ -632,6 +636,7 @@ __device__ __forceinline__ bool list_by_prefix(const Plan &P, uint32_t g, uint64
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_nbr_lists(Plan P)
 {
+    if (box_missed(P)) return;
     constexpr int DA = D / 2, DB = D - DA;
     __shared__ int64_t s_sa[kWavesPerBlock][kListHalf], s_sb[kWavesPerBlock][kListHalf];
     __shared__ uint8_t s_ia[kWavesPerBlock][kListHalf], s_ib[kWavesPerBlock][kListHalf];
@@ -768,6 +773,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr_lists(Plan P)
 // Exclusive prefix of the backward counts over the groups.
 __global__ __launch_bounds__(kBlock) void k_nbr_bscan(Plan P)
 {
+    if (box_missed(P)) return;
     __shared__ uint32_t s_red[kBlock / kWave];
     __shared__ uint32_t s_tile, s_excl;
     const uint32_t t = threadIdx.x;
@@ -801,6 +807,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr_bscan(Plan P)
 // Backward entries: every forward pair (g, G) puts g into G's list.
 __global__ __launch_bounds__(kBlock) void k_nbr_back(Plan P)
 {
+    if (box_missed(P)) return;
     if (P.ctr->nbr_overflow) return;                     // lists unused
     const uint32_t l = lane_id();
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
@@ -887,6 +894,7 @@ __device__ __forceinline__ uint32_t count_walk(const Plan &P, uint32_t g, uint64
 template <int D, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_core(Plan P)
 {
+    if (box_missed(P)) return;
     __shared__ uint32_t s_beg[kWavesPerBlock][kWave], s_pre[kWavesPerBlock][kWave];
     const uint32_t w = wave_in_block(), l = lane_id();
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
@@ -983,6 +991,7 @@ __global__ __launch_bounds__(kBlock) void k_core(Plan P)
 template <int D, bool WIDE>
 __global__ __launch_bounds__(kBlock, 6) void k_core_chunks(Plan P)
 {
+    if (box_missed(P)) return;
     __shared__ uint32_t s_beg[kWavesPerBlock][kWave], s_pre[kWavesPerBlock][kWave];
     const uint32_t w = wave_in_block(), l = lane_id();
     const uint32_t n = P.n, minpts = (uint32_t)P.min_pts;
@@ -1078,6 +1087,7 @@ constexpr int kFlatBlock = 1024;
 template <int D>
 __global__ __launch_bounds__(kFlatBlock) void k_core_flat(Plan P)
 {
+    if (box_missed(P)) return;
     __shared__ uint32_t s_cnt[kFlatBlock / kWave];
     __shared__ uint32_t s_base;
     const uint32_t n = P.n, l = lane_id(), w = threadIdx.x / kWave;
@@ -1239,6 +1249,7 @@ __device__ __forceinline__ void core_result(const Plan &P, uint32_t q, uint32_t 
 template <int D, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_core_lanes(Plan P)
 {
+    if (box_missed(P)) return;
     static_assert(D <= 2, "lane walk for one or two axes");
     const uint32_t ns = ld_agent32(&P.ctr->n_sparse);
     const uint32_t stride = gridDim.x * kBlock;
@@ -1301,6 +1312,7 @@ __global__ __launch_bounds__(kBlock) void k_core_lanes(Plan P)
 template <int D, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_core_deferred(Plan P)
 {
+    if (box_missed(P)) return;
     __shared__ Nbhd<D> s_nb;
     __shared__ uint32_t s_cnt;
     const uint32_t nd = ld_agent32(&P.ctr->n_defer);
@@ -1364,6 +1376,7 @@ __device__ __forceinline__ uint32_t slot_pos(const SlotRanges &sr, uint32_t v)
 template <int D, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_core_list_lanes(Plan P)
 {
+    if (box_missed(P)) return;
     const uint32_t ns = ld_agent32(&P.ctr->n_sparse);
     const bool lists = P.nbr_cap && P.ctr->nbr_overflow == 0;
     const uint32_t stride = gridDim.x * kBlock;
@@ -1449,6 +1462,7 @@ __global__ __launch_bounds__(kBlock) void k_core_list_lanes(Plan P)
 template <int D, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_core_list_deferred(Plan P)
 {
+    if (box_missed(P)) return;
     __shared__ uint32_t s_beg[kWavesPerBlock][kWave], s_pre[kWavesPerBlock][kWave];
     const uint32_t w = wave_in_block();
     const uint32_t nd = ld_agent32(&P.ctr->n_defer);
@@ -1482,6 +1496,7 @@ __global__ __launch_bounds__(kBlock) void k_core_list_deferred(Plan P)
 // and its representative slots set to "none" for the chunks' atomic minima.
 __global__ __launch_bounds__(kFlatBlock) void k_core_cubes(Plan P)
 {
+    if (box_missed(P)) return;
     __shared__ uint32_t s_cnt[3][kFlatBlock / kWave];
     __shared__ uint32_t s_base[3];
     const uint32_t nc = ld_agent32(&P.ctr->n_cells), l = lane_id(), w = threadIdx.x / kWave;
@@ -1544,6 +1559,7 @@ __global__ __launch_bounds__(kFlatBlock) void k_core_cubes(Plan P)
 // Every representative slot to "none" (all ones) before the atomic minima.
 __global__ __launch_bounds__(kBlock) void k_reps_init(Plan P)
 {
+    if (box_missed(P)) return;
     const uint64_t total = (uint64_t)ld_agent32(&P.ctr->n_cells) * P.n_dir;
     for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (uint64_t)gridDim.x * kBlock)
         st_agent(P.rep + i, ~0ull);
@@ -1552,6 +1568,7 @@ __global__ __launch_bounds__(kBlock) void k_reps_init(Plan P)
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_reps(Plan P)
 {
+    if (box_missed(P)) return;
     const uint32_t l = lane_id();
     uint32_t zero = 0, mul = 1;
 #pragma unroll
@@ -1656,6 +1673,7 @@ constexpr int kRepPer = (int)kRepLanePts / kRepGroup;
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_reps_small(Plan P)
 {
+    if (box_missed(P)) return;
     constexpr int ND = rep_dirs<D>();
     const uint32_t ns = ld_agent32(&P.ctr->n_small);
     const uint32_t gl = threadIdx.x % kRepGroup;
@@ -1707,6 +1725,7 @@ __global__ __launch_bounds__(kBlock) void k_reps_small(Plan P)
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_reps_big(Plan P)
 {
+    if (box_missed(P)) return;
     constexpr int ND = rep_dirs<D>();
     const uint32_t nch = ld_agent32(&P.ctr->n_chunks), l = lane_id();
     const WaveRange hca_wr_ = wave_range(P.order);
@@ -1835,6 +1854,7 @@ __device__ __forceinline__ void queue_exact(const Plan &P, bool exact, uint32_t 
 template <int D, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_merge_rep(Plan P)
 {
+    if (box_missed(P)) return;
     const uint32_t l = lane_id();
     uint32_t lt = 0;
     const uint32_t nc = ld_agent32(&P.ctr->n_cells);
@@ -1913,6 +1933,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_rep(Plan P)
 template <int D, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_merge_cubes(Plan P)
 {
+    if (box_missed(P)) return;
     __shared__ uint32_t s_fwd[kWavesPerBlock][kWave];
     const uint32_t w = wave_in_block(), l = lane_id();
     // forward offsets: cubes are numbered in key order, so B > A exactly when
@@ -2011,6 +2032,7 @@ __device__ void exact_pair(const Plan &P, uint32_t A, uint32_t B, uint32_t &lt)
 template <int D, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_merge_exact(Plan P)
 {
+    if (box_missed(P)) return;
     __shared__ uint32_t s_pre[kWavesPerBlock][kWorkRegions];
     const uint32_t w = wave_in_block(), l = lane_id();
     // items per region (lane = region), laid out one region after the other
@@ -2071,6 +2093,7 @@ __device__ __forceinline__ uint32_t dealt_tiles(uint32_t nc)
 // counters.
 __global__ __launch_bounds__(kBlock) void k_tile_scan(Plan P, uint64_t *status, uint32_t *ticket)
 {
+    if (box_missed(P)) return;
     __shared__ uint32_t s_red[kBlock / kWave];
     __shared__ uint32_t s_tile, s_excl;
     const uint32_t t = threadIdx.x;
@@ -2164,6 +2187,7 @@ __device__ __forceinline__ void group_tile(const Plan &P, uint32_t a0, uint32_t 
 template <int D, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_merge_tiles(Plan P)
 {
+    if (box_missed(P)) return;
     __shared__ int32_t s_pt[kWavesPerBlock][kWave][D];
     const uint32_t w = wave_in_block();
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
@@ -2210,6 +2234,7 @@ __device__ __forceinline__ uint64_t sorted_key(const Plan &P, uint32_t i)
 template <int D, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_merge_big(Plan P)
 {
+    if (box_missed(P)) return;
     const uint32_t l = lane_id();
     if (ld_agent32(&P.ctr->n_big_groups) == 0) return;      // counted by k_tile_scan
     const uint32_t nc = ld_agent32(&P.ctr->n_cells);
@@ -2255,6 +2280,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_big(Plan P)
 template <int D, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_merge_unify(Plan P)
 {
+    if (box_missed(P)) return;
     const uint32_t l = lane_id();
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
     const WaveRange hca_wr_ = wave_range(P.order);
@@ -2396,6 +2422,7 @@ constexpr uint32_t kInlineTiles = 4;
 template <int D, bool WIDE>
 __global__ __launch_bounds__(kBlock, 4) void k_merge_inter(Plan P)
 {
+    if (box_missed(P)) return;
     __shared__ int32_t s_pt[kWavesPerBlock][kWave][D];
     const uint32_t w = wave_in_block(), l = lane_id();
     const uint32_t region = (blockIdx.x * kWavesPerBlock + w) % kWorkRegions;
@@ -2515,6 +2542,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_merge_inter(Plan P)
 template <int D, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_merge_pairs(Plan P)
 {
+    if (box_missed(P)) return;
     __shared__ uint32_t s_pre[kWavesPerBlock][kWorkRegions];
     __shared__ int32_t s_pt[kWavesPerBlock][kWave][D];
     const uint32_t w = wave_in_block(), l = lane_id();
@@ -2539,6 +2567,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_pairs(Plan P)
 // build long chains).  No union runs concurrently.
 __global__ __launch_bounds__(kBlock) void k_flatten(Plan P)
 {
+    if (box_missed(P)) return;
     const uint32_t nc = ld_agent32(&P.ctr->n_cells);
     for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < nc; c += gridDim.x * kBlock) {
         const uint32_t p = ld_parent(P.parent + c);
@@ -2556,6 +2585,7 @@ __global__ __launch_bounds__(kBlock) void k_flatten(Plan P)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_compress(Plan P)
 {
+    if (box_missed(P)) return;
     const uint32_t nc = ld_agent32(&P.ctr->n_cells);
     const uint32_t stride = gridDim.x * kBlock;
     for (uint32_t base = blockIdx.x * kBlock; base < nc; base += stride) {
@@ -2636,6 +2666,7 @@ __device__ __forceinline__ void border_walk(const Plan &P, uint32_t g, uint64_t 
 template <int D, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_border_rec(Plan P)
 {
+    if (box_missed(P)) return;
     // records handled RB at a time: their flags, then their rows and input
     // indices, each step's loads issued together
     constexpr int RB = D <= 2 ? 16 : D <= 4 ? 8 : 4;
@@ -2701,6 +2732,7 @@ __global__ __launch_bounds__(kBlock) void k_border_rec(Plan P)
 // positions, in runs of a wave) into P.blist.
 __global__ __launch_bounds__(kBlock) void k_border_list(Plan P)
 {
+    if (box_missed(P)) return;
     const uint32_t l = lane_id();
     for (uint32_t base = (blockIdx.x * kBlock + threadIdx.x) & ~(kWave - 1u); base < P.n;
          base += gridDim.x * kBlock) {
@@ -2721,6 +2753,7 @@ __global__ __launch_bounds__(kBlock) void k_border_list(Plan P)
 template <int D, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_border_walk_list(Plan P)
 {
+    if (box_missed(P)) return;
     __shared__ uint32_t s_beg[kWavesPerBlock][kWave], s_pre[kWavesPerBlock][kWave];
     const uint32_t w = wave_in_block(), l = lane_id();
     const uint32_t nl = ld_agent32(&P.ctr->n_blist);
@@ -2782,6 +2815,7 @@ __global__ __launch_bounds__(kBlock) void k_border_walk_list(Plan P)
 template <int D, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_border(Plan P)
 {
+    if (box_missed(P)) return;
     __shared__ uint32_t s_beg[kWavesPerBlock][kWave], s_pre[kWavesPerBlock][kWave];
     const uint32_t w = wave_in_block(), l = lane_id();
     uint32_t lt = 0;
@@ -2818,6 +2852,7 @@ __global__ __launch_bounds__(kBlock) void k_border(Plan P)
 template <int D, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_border_chunks(Plan P)
 {
+    if (box_missed(P)) return;
     __shared__ uint32_t s_beg[kWavesPerBlock][kWave], s_pre[kWavesPerBlock][kWave];
     const uint32_t w = wave_in_block(), l = lane_id();
     const uint32_t n = P.n;
@@ -2856,6 +2891,7 @@ __global__ __launch_bounds__(kBlock) void k_border_chunks(Plan P)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_label_marks(Plan P)
 {
+    if (box_missed(P)) return;
     const uint32_t nc = ld_agent32(&P.ctr->n_cells);
     for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < nc; c += gridDim.x * kBlock) {
         if (ld_parent(P.parent + c) != c) continue;
@@ -2866,6 +2902,7 @@ __global__ __launch_bounds__(kBlock) void k_label_marks(Plan P)
 
 __global__ __launch_bounds__(kBlock) void k_label_scan(Plan P, uint64_t *status, uint32_t *ticket)
 {
+    if (box_missed(P)) return;
     __shared__ uint32_t s_red[kBlock / kWave];
     __shared__ uint32_t s_tile, s_excl;
     const uint32_t t = threadIdx.x;
@@ -2902,6 +2939,7 @@ __global__ __launch_bounds__(kBlock) void k_label_scan(Plan P, uint64_t *status,
 // staged row.
 __global__ __launch_bounds__(kBlock) void k_seg_label_base(Plan P)
 {
+    if (box_missed(P)) return;
     for (uint32_t sg = blockIdx.x * kBlock + threadIdx.x; sg < P.nseg; sg += gridDim.x * kBlock) {
         const uint32_t r = P.seg[sg].vstart;
         uint32_t base = 0;
@@ -2916,6 +2954,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_label_base(Plan P)
 // Label of every cube's cluster (-1 for a cube without core points).
 __global__ __launch_bounds__(kBlock) void k_label_cubes(Plan P)
 {
+    if (box_missed(P)) return;
     const uint32_t nc = ld_agent32(&P.ctr->n_cells);
     for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < nc; c += gridDim.x * kBlock) {
         const uint32_t root = ld_parent(P.parent + c);
@@ -2935,6 +2974,7 @@ __global__ __launch_bounds__(kBlock) void k_label_cubes(Plan P)
 // Every point takes its cube's label (core) or its owner root's label (border).
 __global__ __launch_bounds__(kBlock) void k_label_write(Plan P)
 {
+    if (box_missed(P)) return;
     __shared__ uint32_t s_cnt[2][kWavesPerBlock];
     uint32_t n_core = 0, n_noise = 0;
     for (uint32_t a = blockIdx.x * kBlock + threadIdx.x; a < P.n; a += gridDim.x * kBlock) {

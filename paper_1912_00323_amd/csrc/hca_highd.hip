@@ -40,6 +40,7 @@ __device__ __forceinline__ int32_t sq_dot16(uint32_t a, uint32_t b, int32_t acc)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_hd_group_box(Plan P)
 {
+    if (box_missed(P)) return;
     const uint32_t l = lane_id(), sd = P.sd;
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
     const WaveRange hca_wr_ = wave_range(P.order);
@@ -161,6 +162,7 @@ constexpr int kHdHalf = 81;         // 3^4 offset combinations per half, at most
 template <int KD>
 __global__ __launch_bounds__(kBlock) void k_hd_lists(Plan P)
 {
+    if (box_missed(P)) return;
     constexpr int DA = KD / 2, DB = KD - DA;
     constexpr int NA = DA == 0 ? 1 : DA == 1 ? 3 : DA == 2 ? 9 : DA == 3 ? 27 : 81;
     constexpr int NB = DB == 1 ? 3 : DB == 2 ? 9 : DB == 3 ? 27 : 81;
@@ -562,6 +564,7 @@ __device__ __forceinline__ void hd_tally(const Plan &P, bool in, uint32_t cell, 
 template <int ROW>
 __global__ __launch_bounds__(kBlock, ROW == kRowPacked ? 5 : 1) void k_hd_core(Plan P)
 {
+    if (box_missed(P)) return;
     __shared__ __align__(16) int32_t s_own[kWavesPerBlock][kPch][kOwnStride];
     __shared__ int32_t s_qb[kWavesPerBlock][2 * kMaxDimHigh];
     __shared__ uint32_t s_beg[kWavesPerBlock][kWave], s_pre[kWavesPerBlock][kWave];
@@ -625,6 +628,7 @@ __global__ __launch_bounds__(kBlock, ROW == kRowPacked ? 5 : 1) void k_hd_core(P
 template <int ROW>
 __global__ __launch_bounds__(kBlock, ROW == kRowPacked ? 5 : 1) void k_hd_core_rest(Plan P)
 {
+    if (box_missed(P)) return;
     __shared__ __align__(16) int32_t s_own[kWavesPerBlock][kPch][kOwnStride];
     __shared__ int32_t s_qb[kWavesPerBlock][2 * kMaxDimHigh];
     __shared__ uint32_t s_beg[kWavesPerBlock][kWave], s_pre[kWavesPerBlock][kWave];
@@ -675,6 +679,7 @@ __global__ __launch_bounds__(kBlock, ROW == kRowPacked ? 5 : 1) void k_hd_core_r
 // First cube with a core point of every group (kNone: none).
 __global__ __launch_bounds__(kBlock) void k_hd_gcore(Plan P)
 {
+    if (box_missed(P)) return;
     const uint32_t nc = ld_agent32(&P.ctr->n_cells);
     for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c < nc; c += gridDim.x * kBlock)
         if (P.ncore[c]) atomicMin(P.gcube + P.group_of[c], c);
@@ -747,6 +752,7 @@ __device__ __forceinline__ void hd_link_walk(const Plan &P, uint32_t g, const in
 template <int ROW>
 __global__ __launch_bounds__(kBlock) void k_hd_merge(Plan P)
 {
+    if (box_missed(P)) return;
     __shared__ __align__(16) int32_t s_own[kWavesPerBlock][kPch][kOwnStride];
     __shared__ int32_t s_qb[kWavesPerBlock][2 * kMaxDimHigh];
     __shared__ uint32_t s_beg[kWavesPerBlock][kWave], s_pre[kWavesPerBlock][kWave];
@@ -784,6 +790,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_merge(Plan P)
 // one union to the next.
 __global__ __launch_bounds__(kBlock) void k_link_recorded(Plan P)
 {
+    if (box_missed(P)) return;
     for (uint32_t q = blockIdx.x * kBlock + threadIdx.x; q < P.n; q += gridDim.x * kBlock) {
         if (!P.core[q]) continue;
         const uint32_t c = P.cell_of[q], nr = min((uint32_t)P.nrec[q], (uint32_t)kRec);
@@ -829,6 +836,7 @@ __global__ __launch_bounds__(kBlock) void k_link_recorded(Plan P)
 // (one wave per group; the group's cubes are consecutive).
 __global__ __launch_bounds__(kBlock) void k_hd_unify(Plan P)
 {
+    if (box_missed(P)) return;
     const uint32_t l = lane_id();
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
     const WaveRange hca_wr_ = wave_range(P.order);
@@ -895,6 +903,7 @@ __device__ __forceinline__ void hd_border_walk(const Plan &P, uint32_t g, const 
 // among them (exact 64-bit distances over the int32 rows), one thread per point.
 __global__ __launch_bounds__(kBlock) void k_hd_border_rec(Plan P)
 {
+    if (box_missed(P)) return;
     const uint32_t sd = P.sd;
     for (uint32_t p = blockIdx.x * kBlock + threadIdx.x; p < P.n; p += gridDim.x * kBlock) {
         if (P.core[p] || !rec_complete(P, p)) continue;
@@ -923,6 +932,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_border_rec(Plan P)
 template <int ROW>
 __global__ __launch_bounds__(kBlock) void k_hd_border(Plan P)
 {
+    if (box_missed(P)) return;
     __shared__ __align__(16) int32_t s_own[kWavesPerBlock][kPch][kOwnStride];
     __shared__ int32_t s_qb[kWavesPerBlock][2 * kMaxDimHigh];
     __shared__ uint32_t s_beg[kWavesPerBlock][kWave], s_pre[kWavesPerBlock][kWave];

@@ -23,7 +23,7 @@ struct BoxExpect {
     int32_t mn[kMaxDim], mx[kMaxDim];
 };
 void launch_bbox_check(int d, const int32_t *partial, int blocks, const BoxExpect &e, uint32_t *flag,
-                       hipStream_t s);
+                       uint32_t *miss, hipStream_t s);
 void launch_sort(const Plan &P, SortBuffers &B, bool wide_keys, hipStream_t s);
 void launch_cells(const Plan &P, bool wide_keys, uint64_t *status, uint32_t *ticket,
                   hipStream_t s);

@@ -128,6 +128,7 @@ __global__ __launch_bounds__(kHistBlock) void k_keys_hist(Plan P, K *__restrict_
                                                           uint32_t *__restrict__ vals,
                                                           uint32_t *__restrict__ hist)
 {
+    if (box_missed(P)) return;
     __shared__ uint32_t s_hist[8 * kRadix];
     const uint32_t passes = P.passes, dmask = (1u << P.digit_bits) - 1u;
     for (uint32_t e = threadIdx.x; e < passes * kRadix; e += kHistBlock) s_hist[e] = 0;
@@ -165,6 +166,7 @@ __global__ __launch_bounds__(kHistBlock) void k_keys_hist(Plan P, K *__restrict_
 __global__ __launch_bounds__(kBlock) void k_hd_keys_hist(Plan P, uint64_t *__restrict__ keys,
                                                          uint32_t *__restrict__ vals, uint32_t *__restrict__ hist)
 {
+    if (box_missed(P)) return;
     __shared__ uint32_t s_hist[8 * kRadix];
     __shared__ int32_t s_org[kMaxDimHigh];
     const uint32_t passes = P.passes, d = (uint32_t)P.d, hb = P.fine_bits, dmask = (1u << P.digit_bits) - 1u;
@@ -202,6 +204,7 @@ __global__ __launch_bounds__(kBlock) void k_hd_keys_hist(Plan P, uint64_t *__res
 // of the rows t / sd, t / sd + rpb, ... (rpb = 256 / sd).
 __global__ __launch_bounds__(kBlock) void k_hd_gather(Plan P)
 {
+    if (box_missed(P)) return;
     const uint32_t d = (uint32_t)P.d, sd = P.sd, rpb = kBlock / sd;
     const uint32_t e = threadIdx.x % sd, r0 = threadIdx.x / sd;
     if (r0 >= rpb) return;
@@ -256,6 +259,7 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(Plan P, const K *__restric
                                                      uint64_t *__restrict__ status, uint32_t *ticket,
                                                      const int32_t *__restrict__ rin, int32_t *__restrict__ rout)
 {
+    if (box_missed(P)) return;
     constexpr int W = THREADS / kWave;
     constexpr int kItems = ITEMS;
     constexpr int kTile = THREADS * kItems;
@@ -408,6 +412,7 @@ template <typename K>
 __global__ __launch_bounds__(kCellsBlock) void k_cells(Plan P, uint64_t *__restrict__ status,
                                                   uint32_t *ticket)
 {
+    if (box_missed(P)) return;
     __shared__ uint64_t s_red[kCellsBlock / kWave];
     __shared__ uint32_t s_tile;
     __shared__ uint64_t s_excl;
@@ -516,7 +521,7 @@ __global__ __launch_bounds__(kCellsBlock) void k_cells(Plan P, uint64_t *__restr
 // box differs from the one planned with, else to 0.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_bbox_check(const int32_t *__restrict__ partial, int blocks,
-                                                       BoxExpect e, uint32_t *flag)
+                                                       BoxExpect e, uint32_t *flag, uint32_t *miss)
 {
     int32_t mn[D], mx[D];
 #pragma unroll
@@ -547,6 +552,7 @@ __global__ __launch_bounds__(kBlock) void k_bbox_check(const int32_t *__restrict
             for (int i = 1; i < kBlock / kWave; i++) { a = min(a, s_mn[i][k]); z = max(z, s_mx[i][k]); }
             if (a != e.mn[k] || z != e.mx[k]) f = 1;
         }
+        *miss = f;                                       // read by the kernels after this one
         __hip_atomic_store(flag, f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
@@ -577,10 +583,10 @@ void launch_bbox(int d, const int32_t *pts, uint32_t n, int32_t *partial, int bl
 }
 
 void launch_bbox_check(int d, const int32_t *partial, int blocks, const BoxExpect &e, uint32_t *flag,
-                       hipStream_t s)
+                       uint32_t *miss, hipStream_t s)
 {
 #define HCA_BOX_CHECK(DD) \
-    case DD: hipLaunchKernelGGL(k_bbox_check<DD>, dim3(1), dim3(kBlock), 0, s, partial, blocks, e, flag); break;
+    case DD: hipLaunchKernelGGL(k_bbox_check<DD>, dim3(1), dim3(kBlock), 0, s, partial, blocks, e, flag, miss); break;
     switch (d) {
         HCA_BOX_CHECK(1) HCA_BOX_CHECK(2) HCA_BOX_CHECK(3) HCA_BOX_CHECK(4)
         HCA_BOX_CHECK(5) HCA_BOX_CHECK(6) HCA_BOX_CHECK(7) HCA_BOX_CHECK(8)
