@@ -363,6 +363,16 @@ class Context:
         self._check(self._lib.hca_phase_times(self._ctx, buf, len(PHASES)))
         return {name: float(buf[i]) for i, name in enumerate(PHASES)}
 
+    def phase_time(self, index: int) -> float:
+        """Milliseconds of phase PHASES[index] in the last call (0 when not
+        timed), through a buffer kept by the context: cheap enough to call
+        after every call of a timed loop."""
+        buf = getattr(self, "_phase_buf", None)
+        if buf is None:
+            buf = self._phase_buf = (ctypes.c_float * len(PHASES))()
+        self._check(self._lib.hca_phase_times(self._ctx, buf, len(PHASES)))
+        return float(buf[index])
+
     def cluster(self, points, eps: float, min_pts: int, core: bool = False, stats: bool = False,
                 out=None):
         """Cluster a CUDA int32 tensor [n, d].  Returns an int32 tensor of labels
