@@ -403,6 +403,29 @@ class Context:
             res.append(st_obj.as_dict())
         return res[0] if len(res) == 1 else tuple(res)
 
+    def prepared(self, points, eps: float, min_pts: int, out):
+        """A repeated call on fixed tensors: the arguments are checked and
+        marshalled once, on the current torch stream, and the returned function
+        calls hca_cluster with them (blocking; raises HcaError on failure).  The
+        tensors must stay alive and in place while it is used."""
+        import torch
+        if not (isinstance(points, torch.Tensor) and points.is_cuda and points.is_contiguous()):
+            raise TypeError("points must be a contiguous CUDA (HIP) torch tensor")
+        if points.dtype != torch.int32 or points.dim() != 2:
+            raise TypeError("points must be int32 with shape [n, d]")
+        n, d = points.shape
+        check_labels(out, n, points.device)
+        self.set_stream(torch.cuda.current_stream(points.device).cuda_stream)
+        f, ctx = self._lib.hca_cluster, self._ctx
+        args = (ctx, ctypes.c_void_p(points.data_ptr()), n, d, float(eps), int(min_pts),
+                ctypes.c_void_p(out.data_ptr()))
+
+        def call():
+            st = f(*args)
+            if st != HCA_OK:
+                self._check(st)
+        return call
+
     def cluster_batch(self, points, rows, dims, eps, min_pts, out=None):
         """Cluster the data sets packed one after the other in the CUDA int32
         tensor ``points`` (flat, data set i being rows[i] x dims[i]).  Returns

@@ -588,6 +588,27 @@ def test_repeatable(ctx):
     assert np.array_equal(first, oracle.dbscan(w.points, w.eps, w.min_pts))
 
 
+def test_prepared_call(ctx):
+    """A call prepared once on fixed tensors and made repeatedly (the form the
+    benchmark times) against the oracle, including after the data change in
+    place."""
+    import torch
+    w = make_config(1)
+    pts = torch.from_numpy(w.points).cuda()
+    out = torch.empty(w.n, dtype=torch.int32, device="cuda")
+    call = ctx.prepared(pts, w.eps, w.min_pts, out)
+    want = oracle.dbscan(w.points, w.eps, w.min_pts)
+    for _ in range(3):
+        out.fill_(-7)
+        call()
+        assert np.array_equal(out.cpu().numpy(), want)
+    moved = w.points[::-1].copy()
+    moved[:, 1] += 77
+    pts.copy_(torch.from_numpy(moved))
+    call()
+    assert np.array_equal(out.cpu().numpy(), oracle.dbscan(moved, w.eps, w.min_pts))
+
+
 def test_plan_reuse(ctx):
     """Calls planned ahead from the box of the previous calls: the same data
     again (planned ahead, its box compared on the device), data of the same
