@@ -546,7 +546,9 @@ __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgc
 
 // Whether this call was planned from a box that its own box turned out to
 // differ from (the same value in every thread of every kernel after the
-// comparison, so a kernel returning on it returns everywhere).
+// comparison, so a kernel returning on it returns everywhere).  Read from
+// core marking on: the sort, the tables and the neighbour lists do bounded
+// work on any data, their keys held to the layout.
 __device__ __forceinline__ bool box_missed(const Plan &P)
 {
     return P.box_miss != nullptr && *P.box_miss != 0;

@@ -250,7 +250,6 @@ __global__ __launch_bounds__(kBlock) void k_init(uint32_t *zero, uint64_t zero_w
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_table_clear(Plan P)
 {
-    if (box_missed(P)) return;
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
     uint64_t cap = 1024;
     while (cap < ((uint64_t)ng << P.hash_load)) cap <<= 1;
@@ -264,7 +263,6 @@ __global__ __launch_bounds__(kBlock) void k_table_clear(Plan P)
 
 __global__ __launch_bounds__(kBlock) void k_table(Plan P)
 {
-    if (box_missed(P)) return;
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
     const uint64_t mask = P.ctr->hmask;
     for (uint32_t g = blockIdx.x * kBlock + threadIdx.x; g < ng; g += gridDim.x * kBlock) {
@@ -396,7 +394,6 @@ __device__ __forceinline__ void store_gbox(const Plan &P, uint32_t g, const QBox
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_group_box(Plan P)
 {
-    if (box_missed(P)) return;
     const uint32_t l = lane_id(), sub = l & 7u;
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
     const WaveRange hca_wr_ = wave_range(P.order);
@@ -454,7 +451,6 @@ __global__ __launch_bounds__(kBlock) void k_group_box(Plan P)
 // values, which the readers reject (the group at pstart has another prefix).
 __global__ __launch_bounds__(kBlock) void k_prefix_ranges(Plan P)
 {
-    if (box_missed(P)) return;
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);
     for (uint32_t g = blockIdx.x * kBlock + threadIdx.x; g < ng; g += gridDim.x * kBlock) {
         const uint64_t p = P.group_key[g] >> P.pshift;
@@ -636,7 +632,6 @@ __device__ __forceinline__ bool list_by_prefix(const Plan &P, uint32_t g, uint64
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_nbr_lists(Plan P)
 {
-    if (box_missed(P)) return;
     constexpr int DA = D / 2, DB = D - DA;
     __shared__ int64_t s_sa[kWavesPerBlock][kListHalf], s_sb[kWavesPerBlock][kListHalf];
     __shared__ uint8_t s_ia[kWavesPerBlock][kListHalf], s_ib[kWavesPerBlock][kListHalf];
@@ -773,7 +768,6 @@ __global__ __launch_bounds__(kBlock) void k_nbr_lists(Plan P)
 // Exclusive prefix of the backward counts over the groups.
 __global__ __launch_bounds__(kBlock) void k_nbr_bscan(Plan P)
 {
-    if (box_missed(P)) return;
     __shared__ uint32_t s_red[kBlock / kWave];
     __shared__ uint32_t s_tile, s_excl;
     const uint32_t t = threadIdx.x;
@@ -807,7 +801,6 @@ __global__ __launch_bounds__(kBlock) void k_nbr_bscan(Plan P)
 // Backward entries: every forward pair (g, G) puts g into G's list.
 __global__ __launch_bounds__(kBlock) void k_nbr_back(Plan P)
 {
-    if (box_missed(P)) return;
     if (P.ctr->nbr_overflow) return;                     // lists unused
     const uint32_t l = lane_id();
     const uint32_t ng = ld_agent32(&P.ctr->n_groups);

@@ -159,8 +159,8 @@ struct Plan {
     uint8_t kdim[kMaxDim];
     const int32_t *hd_origin;   // [d] origin of every axis (hd)
     // a call planned from the previous calls' box: the word its box
-    // comparison writes (1: the box differs, and every later kernel of the
-    // call returns at once); null otherwise
+    // comparison writes (1: the box differs, and every kernel from core
+    // marking on returns at once); null otherwise
     const uint32_t *box_miss;
     uint32_t *hd_list;          // [2n] sorted positions: undecided points, then non-core points (hd)
     uint32_t *rec;              // [n][kRec] first neighbours found by core marking (sorted positions), or null

@@ -128,7 +128,6 @@ __global__ __launch_bounds__(kHistBlock) void k_keys_hist(Plan P, K *__restrict_
                                                           uint32_t *__restrict__ vals,
                                                           uint32_t *__restrict__ hist)
 {
-    if (box_missed(P)) return;
     __shared__ uint32_t s_hist[8 * kRadix];
     const uint32_t passes = P.passes, dmask = (1u << P.digit_bits) - 1u;
     for (uint32_t e = threadIdx.x; e < passes * kRadix; e += kHistBlock) s_hist[e] = 0;
@@ -166,7 +165,6 @@ __global__ __launch_bounds__(kHistBlock) void k_keys_hist(Plan P, K *__restrict_
 __global__ __launch_bounds__(kBlock) void k_hd_keys_hist(Plan P, uint64_t *__restrict__ keys,
                                                          uint32_t *__restrict__ vals, uint32_t *__restrict__ hist)
 {
-    if (box_missed(P)) return;
     __shared__ uint32_t s_hist[8 * kRadix];
     __shared__ int32_t s_org[kMaxDimHigh];
     const uint32_t passes = P.passes, d = (uint32_t)P.d, hb = P.fine_bits, dmask = (1u << P.digit_bits) - 1u;
@@ -204,7 +202,6 @@ __global__ __launch_bounds__(kBlock) void k_hd_keys_hist(Plan P, uint64_t *__res
 // of the rows t / sd, t / sd + rpb, ... (rpb = 256 / sd).
 __global__ __launch_bounds__(kBlock) void k_hd_gather(Plan P)
 {
-    if (box_missed(P)) return;
     const uint32_t d = (uint32_t)P.d, sd = P.sd, rpb = kBlock / sd;
     const uint32_t e = threadIdx.x % sd, r0 = threadIdx.x / sd;
     if (r0 >= rpb) return;
@@ -259,7 +256,6 @@ __global__ __launch_bounds__(THREADS) void k_onesweep(Plan P, const K *__restric
                                                      uint64_t *__restrict__ status, uint32_t *ticket,
                                                      const int32_t *__restrict__ rin, int32_t *__restrict__ rout)
 {
-    if (box_missed(P)) return;
     constexpr int W = THREADS / kWave;
     constexpr int kItems = ITEMS;
     constexpr int kTile = THREADS * kItems;
@@ -412,7 +408,6 @@ template <typename K>
 __global__ __launch_bounds__(kCellsBlock) void k_cells(Plan P, uint64_t *__restrict__ status,
                                                   uint32_t *ticket)
 {
-    if (box_missed(P)) return;
     __shared__ uint64_t s_red[kCellsBlock / kWave];
     __shared__ uint32_t s_tile;
     __shared__ uint64_t s_excl;
