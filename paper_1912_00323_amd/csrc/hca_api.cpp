@@ -374,7 +374,7 @@ struct hca_ctx {
     int32_t box_d = 0;
     int32_t box_mn[kMaxDim] = {}, box_mx[kMaxDim] = {};
     uint32_t *check_host = nullptr, *check_dev = nullptr;   // the comparison's flag (mapped, coherent)
-    uint32_t *miss_dev = nullptr;     // the same flag in device memory, for the call's later kernels
+    uint32_t *miss_dev = nullptr;     // the same flag in device memory, for the kernels from core marking on
     int64_t reuse_calls = 0, reuse_reruns = 0;
     void *io = nullptr;               // staging for hca_cluster_host
     size_t io_size = 0;
@@ -1177,9 +1177,10 @@ hca_status run(hca_ctx *ctx, const int32_t *points, int64_t n64, int32_t d, doub
         launch_bbox_check(d, partial, bb, e, ctx->check_dev, ctx->miss_dev, s);
         mark(ctx, HCA_PHASE_BBOX, true);
         HCA_HIP(hipGetLastError(), "bbox launch");
-        // on a differing box every later kernel returns at once: the keys of
-        // such data are held to the layout, but the work of clustering them
-        // in it is not bounded (points piled into the edge cubes)
+        // on a differing box the kernels from core marking on return at
+        // once: the keys of such data are held to the layout, but the work
+        // of clustering them in it is not bounded (points piled into the
+        // edge cubes)
         P.box_miss = ctx->miss_dev;
     }
     launch_sequence(ctx, P, Z);
